@@ -1,0 +1,619 @@
+/*
+ * rod_oracle.c -- plain FP64 CPU oracle of the discrete Cosserat-rod step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the GPU library: every derived quantity is
+ * recomputed here from the raw material parameters, one rod at a time, in the
+ * most direct form, with the C library's sqrt/sin/cos/atan2.
+ *
+ * Model (Elastica++, Methods, "Cosserat rod dynamics"):
+ *   centreline r(s,t), row director matrix Q = {d1,d2,d3}^T, local vectors
+ *   vbar = Q v; strains sigma = Q(r' - d3), kappa = ax(Q dQ^T/ds),
+ *   omega = ax(Q dQ^T/dt); e = |r'|; B = diag(EI1, EI2, G(I1+I2)),
+ *   S = diag(alpha_c G A, alpha_c G A, E A), I = diag(I1, I2, I1+I2);
+ *   linear momentum  (Eq. 1a): rho A r_tt = d/ds(Q^T S sigma / e) + f
+ *   angular momentum (Eq. 1b): (rho I / e) omega_t = d/ds(B kappa / e^3)
+ *        + kappa x B kappa / e^3 + Q t x S sigma + (rho I omega / e) x omega
+ *        + (rho I omega / e^2) e_t + c.
+ * The paper defers its discretisation to a supplement that is not available;
+ * the discretisation below is the staggered one of the cited discrete model
+ * (nodes carry r, v; elements carry Q, omega; Voronoi points between adjacent
+ * elements carry kappa), with these readings:
+ *   - element i joins nodes i and i+1; rest length lh_i; Voronoi k joins
+ *     elements k and k+1 with rest length Dh_k = (lh_k + lh_{k+1})/2;
+ *   - sigma_i = Q_i (r_{i+1}-r_i)/lh_i - e3   (Q d3 = e3 for orthonormal Q);
+ *   - kappa_k = log(Q_k Q_{k+1}^T) / Dh_k, the rotation vector of the relative
+ *     rotation evaluated with atan2;
+ *   - difference operator: node j receives n_j - n_{j-1} (zero outside);
+ *     element i receives M_i - M_{i-1}; averaging operator: element i
+ *     receives (y_{i-1} + y_i)/2 (zero outside);
+ *   - solid circular section: A = pi r^2, I1 = I2 = pi r^4 / 4;
+ *   - lumped masses m_j = (rho A lh_{j-1} + rho A lh_j)/2;
+ *     element inertia J_i = rho I lh_i;
+ *   - Voronoi bending stiffness = rest-length weighted mean of the two
+ *     elements' B;
+ *   - rest strains: sigma0 = 0, kappa0 given or 0;
+ *   - linear damping: a -= gamma v, alpha -= gamma omega;
+ *   - velocity-dependent terms use the pre-kick velocities;
+ *   - time integration: position Verlet (Results, "Performance-oriented
+ *     software design": a multi-stage symplectic Verlet scheme whose every
+ *     stage re-imposes the kinematic constraints):
+ *       half drift (r += h/2 v, Q <- exp(-h/2 [omega]x) Q), constraints,
+ *       kick (v += h a, omega += h alpha) at t_n + h/2, constraints,
+ *       half drift, constraints;
+ *   - clamped end: node position and element director reset to their initial
+ *     values, node velocity and element angular velocity set to zero.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t n_rods;
+    const int32_t *n_elems;          /* [R] */
+    const double *density;           /* [R] rho */
+    const double *youngs;            /* [R] E */
+    const double *shear_modulus;     /* [R] G */
+    const double *radius;            /* [R] */
+    const double *shear_coeff;       /* [R] alpha_c */
+    const double *damping;           /* [R] gamma, 1/s */
+    const int32_t *bc_start;         /* [R] 1: clamped at s = 0 */
+    const int32_t *bc_end;           /* [R] 1: clamped at s = L */
+    const double *rest_length;       /* [N_e] */
+    const double *rest_kappa;        /* [N_v][3] or NULL */
+    const double *node_force;        /* [N_n][3] or NULL: constant external nodal force */
+    const double *couple_amp;        /* [N_e][3] or NULL: couple per unit length, material frame */
+    const double *couple_freq;       /* [R] Hz (used with couple_amp) */
+    const double *couple_phase;      /* [R] rad */
+    const double *pos0;              /* [N_n][3] initial positions (constraints, work of f) */
+    const double *dir0;              /* [N_e][9] initial directors (constraints) */
+    double dt;
+    double t0;                       /* time at step 0 */
+    int32_t drop_term;               /* 0 in normal use; k > 0 removes term k (mutation tests) */
+} orc_rods;
+
+/* ---------------------------------------------------------------- vectors */
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* y = Q x, Q row-major 3x3 */
+static void matvec(const double *Q, const double *x, double *y)
+{
+    for (int a = 0; a < 3; ++a)
+        y[a] = Q[3 * a + 0] * x[0] + Q[3 * a + 1] * x[1] + Q[3 * a + 2] * x[2];
+}
+
+/* y = Q^T x */
+static void matTvec(const double *Q, const double *x, double *y)
+{
+    for (int b = 0; b < 3; ++b)
+        y[b] = Q[0 + b] * x[0] + Q[3 + b] * x[1] + Q[6 + b] * x[2];
+}
+
+/* C = A B^T */
+static void mat_abt(const double *A, const double *B, double *C)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            C[3 * a + b] = A[3 * a + 0] * B[3 * b + 0] + A[3 * a + 1] * B[3 * b + 1]
+                         + A[3 * a + 2] * B[3 * b + 2];
+}
+
+/* C = A B */
+static void mat_ab(const double *A, const double *B, double *C)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            C[3 * a + b] = A[3 * a + 0] * B[0 + b] + A[3 * a + 1] * B[3 + b]
+                         + A[3 * a + 2] * B[6 + b];
+}
+
+/* Rotation exp([u]x) by the Rodrigues formula:
+ * I + sin(th) [k]x + (1 - cos(th)) [k]x^2 with th = |u|, k = u/th; exp(0) = I. */
+static void rodrigues(const double *u, double *E)
+{
+    double th = sqrt(dot3(u, u));
+    for (int i = 0; i < 9; ++i) E[i] = 0.0;
+    E[0] = E[4] = E[8] = 1.0;
+    if (th == 0.0) return;
+    double k[3] = {u[0] / th, u[1] / th, u[2] / th};
+    double K[9] = {0.0, -k[2], k[1],
+                   k[2], 0.0, -k[0],
+                   -k[1], k[0], 0.0};
+    double K2[9];
+    mat_ab(K, K, K2);
+    double s = sin(th), c1 = 1.0 - cos(th);
+    for (int i = 0; i < 9; ++i) E[i] += s * K[i] + c1 * K2[i];
+}
+
+/* Rotation vector u with exp([u]x) = R for a rotation matrix R:
+ * w = ax(R) = (R32 - R23, R13 - R31, R21 - R12)/2 = sin(th) k,
+ * c = (tr R - 1)/2 = cos(th), th = atan2(|w|, c), u = (th/|w|) w.
+ * For |w| -> 0 the ratio th/|w| tends to 1 + |w|^2/6. */
+static void logmap(const double *R, double *u)
+{
+    double w[3] = {0.5 * (R[7] - R[5]), 0.5 * (R[2] - R[6]), 0.5 * (R[3] - R[1])};
+    double sw = sqrt(dot3(w, w));
+    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    double f;
+    if (sw < 1e-7 && c > 0.0)
+        f = 1.0 + sw * sw / 6.0;   /* next term 3|w|^4/40 is below FP64 resolution */
+    else
+        f = atan2(sw, c) / sw;     /* a half-turn (w = 0, c = -1) has no unique axis */
+    u[0] = f * w[0];
+    u[1] = f * w[1];
+    u[2] = f * w[2];
+}
+
+/* ------------------------------------------------------------ one rod view */
+
+typedef struct {
+    int n;                       /* elements */
+    double rho, E, G, rad, alpha_c, gamma, freq, phase;
+    int clamp0, clamp1;
+    const double *lh;            /* [n] rest lengths */
+    const double *k0;            /* [n-1][3] or NULL */
+    const double *fext;          /* [n+1][3] or NULL */
+    const double *camp;          /* [n][3] or NULL */
+    const double *r0;            /* [n+1][3] */
+    const double *Q0;            /* [n][9] */
+    int drop;
+} rod_view;
+
+static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int64_t vo, rod_view *v)
+{
+    v->n = p->n_elems[r];
+    v->rho = p->density[r];
+    v->E = p->youngs[r];
+    v->G = p->shear_modulus[r];
+    v->rad = p->radius[r];
+    v->alpha_c = p->shear_coeff[r];
+    v->gamma = p->damping ? p->damping[r] : 0.0;
+    v->clamp0 = p->bc_start ? p->bc_start[r] : 0;
+    v->clamp1 = p->bc_end ? p->bc_end[r] : 0;
+    v->freq = p->couple_freq ? p->couple_freq[r] : 0.0;
+    v->phase = p->couple_phase ? p->couple_phase[r] : 0.0;
+    v->lh = p->rest_length + eo;
+    v->k0 = p->rest_kappa ? p->rest_kappa + 3 * vo : NULL;
+    v->fext = p->node_force ? p->node_force + 3 * no : NULL;
+    v->camp = p->couple_amp ? p->couple_amp + 3 * eo : NULL;
+    v->r0 = p->pos0 + 3 * no;
+    v->Q0 = p->dir0 + 9 * eo;
+    v->drop = p->drop_term;
+}
+
+/* Section and constitutive constants of one rod. */
+typedef struct {
+    double A, I1, I2, I3;        /* area, second moments */
+    double S[3];                 /* shear/stretch stiffness diag */
+    double B[3];                 /* bend/twist stiffness diag */
+} rod_consts;
+
+static void rod_consts_make(const rod_view *v, rod_consts *c)
+{
+    c->A = M_PI * v->rad * v->rad;
+    c->I1 = M_PI * pow(v->rad, 4) / 4.0;
+    c->I2 = c->I1;
+    c->I3 = c->I1 + c->I2;
+    c->S[0] = v->alpha_c * v->G * c->A;
+    c->S[1] = v->alpha_c * v->G * c->A;
+    c->S[2] = v->E * c->A;
+    c->B[0] = v->E * c->I1;
+    c->B[1] = v->E * c->I2;
+    c->B[2] = v->G * c->I3;
+}
+
+/* Workspace for one rod of up to nmax elements. */
+typedef struct {
+    double *l, *e, *t, *edot, *sig, *Ssig, *nint, *kap, *M, *y, *eps;
+} rod_work;
+
+static int work_alloc(rod_work *w, int nmax)
+{
+    size_t ne = (size_t)nmax;
+    w->l = malloc(ne * sizeof(double));
+    w->e = malloc(ne * sizeof(double));
+    w->t = malloc(3 * ne * sizeof(double));
+    w->edot = malloc(ne * sizeof(double));
+    w->sig = malloc(3 * ne * sizeof(double));
+    w->Ssig = malloc(3 * ne * sizeof(double));
+    w->nint = malloc(3 * ne * sizeof(double));
+    w->kap = malloc(3 * ne * sizeof(double));
+    w->M = malloc(3 * ne * sizeof(double));
+    w->y = malloc(3 * ne * sizeof(double));
+    w->eps = malloc(ne * sizeof(double));
+    return (w->l && w->e && w->t && w->edot && w->sig && w->Ssig && w->nint && w->kap && w->M
+            && w->y && w->eps) ? 0 : -1;
+}
+
+static void work_free(rod_work *w)
+{
+    free(w->l); free(w->e); free(w->t); free(w->edot); free(w->sig); free(w->Ssig);
+    free(w->nint); free(w->kap); free(w->M); free(w->y); free(w->eps);
+}
+
+/* Kinematics and strains of one rod at positions r, velocities v, directors Q:
+ * l, e, t, edot per element; sigma, S sigma, internal force n per element;
+ * eps, kappa per Voronoi point.  Returns nothing; fills w. */
+static void rod_kinematics(const rod_view *rv, const rod_consts *c, const double *r,
+                           const double *v, const double *Q, rod_work *w)
+{
+    const int n = rv->n;
+    for (int i = 0; i < n; ++i) {
+        double dr[3], dv[3];
+        for (int a = 0; a < 3; ++a) {
+            dr[a] = r[3 * (i + 1) + a] - r[3 * i + a];
+            dv[a] = v ? v[3 * (i + 1) + a] - v[3 * i + a] : 0.0;
+        }
+        double l = sqrt(dot3(dr, dr));
+        w->l[i] = l;
+        w->e[i] = l / rv->lh[i];
+        for (int a = 0; a < 3; ++a) w->t[3 * i + a] = dr[a] / l;
+        w->edot[i] = dot3(&w->t[3 * i], dv) / rv->lh[i];
+        /* sigma = Q dr / lh - e3 */
+        double qdr[3];
+        matvec(&Q[9 * i], dr, qdr);
+        w->sig[3 * i + 0] = qdr[0] / rv->lh[i];
+        w->sig[3 * i + 1] = qdr[1] / rv->lh[i];
+        w->sig[3 * i + 2] = qdr[2] / rv->lh[i] - 1.0;
+        for (int a = 0; a < 3; ++a) w->Ssig[3 * i + a] = c->S[a] * w->sig[3 * i + a];
+        /* n = Q^T S sigma / e (lab frame) */
+        double qs[3];
+        matTvec(&Q[9 * i], &w->Ssig[3 * i], qs);
+        for (int a = 0; a < 3; ++a) w->nint[3 * i + a] = qs[a] / w->e[i];
+    }
+    for (int k = 0; k + 1 < n; ++k) {
+        double Dh = 0.5 * (rv->lh[k] + rv->lh[k + 1]);
+        w->eps[k] = 0.5 * (w->l[k] + w->l[k + 1]) / Dh;
+        double R[9], u[3];
+        mat_abt(&Q[9 * k], &Q[9 * (k + 1)], R);
+        logmap(R, u);
+        for (int a = 0; a < 3; ++a) w->kap[3 * k + a] = u[a] / Dh;
+    }
+}
+
+/* Linear accelerations a[n+1][3] and angular accelerations alpha[n][3] of one
+ * rod (Eq. 1a and 1b) at state (r, v, Q, om) and time t. */
+static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, const double *v,
+                      const double *Q, const double *om, double t, rod_work *w,
+                      double *acc, double *alpha)
+{
+    const int n = rv->n;
+    rod_kinematics(rv, c, r, v, Q, w);
+
+    /* bending/twisting moments at Voronoi points */
+    for (int k = 0; k + 1 < n; ++k) {
+        double Dh = 0.5 * (rv->lh[k] + rv->lh[k + 1]);
+        double Bv[3];
+        for (int a = 0; a < 3; ++a)
+            Bv[a] = (c->B[a] * rv->lh[k] + c->B[a] * rv->lh[k + 1]) / (rv->lh[k] + rv->lh[k + 1]);
+        double e3 = w->eps[k] * w->eps[k] * w->eps[k];
+        double dk[3];
+        for (int a = 0; a < 3; ++a)
+            dk[a] = w->kap[3 * k + a] - (rv->k0 ? rv->k0[3 * k + a] : 0.0);
+        for (int a = 0; a < 3; ++a) w->M[3 * k + a] = Bv[a] * dk[a] / e3;
+        double kxM[3];
+        cross3(&w->kap[3 * k], &w->M[3 * k], kxM);
+        for (int a = 0; a < 3; ++a) w->y[3 * k + a] = kxM[a] * Dh;
+    }
+
+    /* nodes: Eq. 1a with the difference operator */
+    for (int j = 0; j <= n; ++j) {
+        double mass = 0.0;
+        if (j > 0) mass += 0.5 * rv->rho * c->A * rv->lh[j - 1];
+        if (j < n) mass += 0.5 * rv->rho * c->A * rv->lh[j];
+        for (int a = 0; a < 3; ++a) {
+            double F = 0.0;
+            if (j < n) F += w->nint[3 * j + a];
+            if (j > 0) F -= w->nint[3 * (j - 1) + a];
+            if (rv->fext) F += rv->fext[3 * j + a];
+            acc[3 * j + a] = F / mass - rv->gamma * v[3 * j + a];
+        }
+    }
+
+    /* elements: Eq. 1b */
+    double s_t = 0.0;
+    if (rv->camp) s_t = sin(2.0 * M_PI * rv->freq * t + rv->phase);
+    for (int i = 0; i < n; ++i) {
+        const double *Qi = &Q[9 * i];
+        const double *wi = &om[3 * i];
+        double lh = rv->lh[i], e = w->e[i];
+        double J[3] = {rv->rho * c->I1 * lh, rv->rho * c->I2 * lh, rv->rho * c->I3 * lh};
+        double tau[3] = {0.0, 0.0, 0.0};
+        /* d/ds(B kappa / e^3): difference of Voronoi moments */
+        if (rv->drop != 1)
+            for (int a = 0; a < 3; ++a) {
+                if (i < n - 1) tau[a] += w->M[3 * i + a];
+                if (i > 0) tau[a] -= w->M[3 * (i - 1) + a];
+            }
+        /* kappa x B kappa / e^3: average of the two adjacent Voronoi terms */
+        if (rv->drop != 2)
+            for (int a = 0; a < 3; ++a) {
+                double ysum = 0.0;
+                if (i > 0) ysum += w->y[3 * (i - 1) + a];
+                if (i < n - 1) ysum += w->y[3 * i + a];
+                tau[a] += 0.5 * ysum;
+            }
+        /* Q t x S sigma, per element (times the rest length) */
+        if (rv->drop != 3) {
+            double qt[3], sh[3];
+            matvec(Qi, &w->t[3 * i], qt);
+            cross3(qt, &w->Ssig[3 * i], sh);
+            for (int a = 0; a < 3; ++a) tau[a] += sh[a] * lh;
+        }
+        /* (rho I omega / e) x omega */
+        double Jw_e[3] = {J[0] * wi[0] / e, J[1] * wi[1] / e, J[2] * wi[2] / e};
+        if (rv->drop != 4) {
+            double lt[3];
+            cross3(Jw_e, wi, lt);
+            for (int a = 0; a < 3; ++a) tau[a] += lt[a];
+        }
+        /* (rho I omega / e^2) de/dt */
+        if (rv->drop != 5)
+            for (int a = 0; a < 3; ++a) tau[a] += Jw_e[a] / e * w->edot[i];
+        /* external couple per unit length */
+        if (rv->camp)
+            for (int a = 0; a < 3; ++a) tau[a] += rv->camp[3 * i + a] * s_t * lh;
+        for (int a = 0; a < 3; ++a)
+            alpha[3 * i + a] = e * tau[a] / J[a] - rv->gamma * wi[a];
+    }
+}
+
+static void rod_constraints(const rod_view *rv, double *r, double *v, double *Q, double *om)
+{
+    const int n = rv->n;
+    if (rv->clamp0) {
+        for (int a = 0; a < 3; ++a) { r[a] = rv->r0[a]; v[a] = 0.0; om[a] = 0.0; }
+        for (int a = 0; a < 9; ++a) Q[a] = rv->Q0[a];
+    }
+    if (rv->clamp1) {
+        for (int a = 0; a < 3; ++a) {
+            r[3 * n + a] = rv->r0[3 * n + a];
+            v[3 * n + a] = 0.0;
+            om[3 * (n - 1) + a] = 0.0;
+        }
+        for (int a = 0; a < 9; ++a) Q[9 * (n - 1) + a] = rv->Q0[9 * (n - 1) + a];
+    }
+}
+
+static void rod_half_drift(const rod_view *rv, double h, double *r, const double *v, double *Q,
+                           const double *om)
+{
+    const int n = rv->n;
+    for (int j = 0; j <= n; ++j)
+        for (int a = 0; a < 3; ++a) r[3 * j + a] += 0.5 * h * v[3 * j + a];
+    for (int i = 0; i < n; ++i) {
+        double u[3] = {-0.5 * h * om[3 * i + 0], -0.5 * h * om[3 * i + 1], -0.5 * h * om[3 * i + 2]};
+        double E[9], Qn[9];
+        rodrigues(u, E);
+        mat_ab(E, &Q[9 * i], Qn);
+        memcpy(&Q[9 * i], Qn, sizeof Qn);
+    }
+}
+
+static void rod_steps(const rod_view *rv, double h, double t0, int64_t step0, int64_t nsteps,
+                      double *r, double *v, double *Q, double *om, rod_work *w, double *acc,
+                      double *alpha)
+{
+    rod_consts c;
+    rod_consts_make(rv, &c);
+    const int n = rv->n;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double t_mid = t0 + ((double)(step0 + s) + 0.5) * h;
+        rod_half_drift(rv, h, r, v, Q, om);
+        rod_constraints(rv, r, v, Q, om);
+        rod_accel(rv, &c, r, v, Q, om, t_mid, w, acc, alpha);
+        for (int j = 0; j <= n; ++j)
+            for (int a = 0; a < 3; ++a) v[3 * j + a] += h * acc[3 * j + a];
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) om[3 * i + a] += h * alpha[3 * i + a];
+        rod_constraints(rv, r, v, Q, om);
+        rod_half_drift(rv, h, r, v, Q, om);
+        rod_constraints(rv, r, v, Q, om);
+    }
+}
+
+/* ------------------------------------------------------------------ API */
+
+static int max_elems(const orc_rods *p)
+{
+    int m = 0;
+    for (int r = 0; r < p->n_rods; ++r)
+        if (p->n_elems[r] > m) m = p->n_elems[r];
+    return m;
+}
+
+static void offsets(const orc_rods *p, int64_t *eo, int64_t *no, int64_t *vo)
+{
+    int64_t e = 0;
+    for (int r = 0; r < p->n_rods; ++r) {
+        eo[r] = e;
+        no[r] = e + r;
+        vo[r] = e - r;
+        e += p->n_elems[r];
+    }
+}
+
+/* Advance every rod by n_steps position-Verlet steps, starting at step index
+ * step0 (time t0 + step0*dt).  pos/vel [N_n][3], dir [N_e][9], omega [N_e][3]
+ * are updated in place.  n_threads <= 0 uses the OpenMP default. */
+int orc_step(const orc_rods *p, double *pos, double *vel, double *dir, double *omega,
+             int64_t step0, int64_t n_steps, int n_threads)
+{
+    const int R = p->n_rods;
+    int64_t *eo = malloc(3 * (size_t)R * sizeof(int64_t));
+    if (!eo) return -2;
+    int64_t *no = eo + R, *vo = eo + 2 * R;
+    offsets(p, eo, no, vo);
+    const int nmax = max_elems(p);
+    int fail = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel reduction(| : fail)
+#endif
+    {
+        rod_work w;
+        double *acc = malloc(3 * (size_t)(nmax + 1) * sizeof(double));
+        double *alpha = malloc(3 * (size_t)nmax * sizeof(double));
+        if (work_alloc(&w, nmax) != 0 || !acc || !alpha) {
+            fail = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int r = 0; r < R; ++r) {
+                rod_view rv;
+                rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
+                rod_steps(&rv, p->dt, p->t0, step0, n_steps, pos + 3 * no[r], vel + 3 * no[r],
+                          dir + 9 * eo[r], omega + 3 * eo[r], &w, acc, alpha);
+            }
+        }
+        work_free(&w);
+        free(acc);
+        free(alpha);
+    }
+    free(eo);
+    return fail ? -2 : 0;
+}
+
+/* Strains at a state: sigma [N_e][3], kappa [N_v][3], dilatation e [N_e]. */
+int orc_strains(const orc_rods *p, const double *pos, const double *dir, double *sigma,
+                double *kappa, double *dil)
+{
+    const int R = p->n_rods;
+    int64_t *eo = malloc(3 * (size_t)R * sizeof(int64_t));
+    if (!eo) return -2;
+    int64_t *no = eo + R, *vo = eo + 2 * R;
+    offsets(p, eo, no, vo);
+    rod_work w;
+    if (work_alloc(&w, max_elems(p)) != 0) { free(eo); return -2; }
+    for (int r = 0; r < R; ++r) {
+        rod_view rv;
+        rod_consts c;
+        rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
+        rod_consts_make(&rv, &c);
+        rod_kinematics(&rv, &c, pos + 3 * no[r], NULL, dir + 9 * eo[r], &w);
+        memcpy(sigma + 3 * eo[r], w.sig, 3 * (size_t)rv.n * sizeof(double));
+        memcpy(kappa + 3 * vo[r], w.kap, 3 * (size_t)(rv.n - 1) * sizeof(double));
+        if (dil) memcpy(dil + eo[r], w.e, (size_t)rv.n * sizeof(double));
+    }
+    work_free(&w);
+    free(eo);
+    return 0;
+}
+
+/* Accelerations at a state and time t: acc [N_n][3] (lab), alpha [N_e][3]
+ * (material frame), without constraints. */
+int orc_accel(const orc_rods *p, const double *pos, const double *vel, const double *dir,
+              const double *omega, double t, double *acc, double *alpha)
+{
+    const int R = p->n_rods;
+    int64_t *eo = malloc(3 * (size_t)R * sizeof(int64_t));
+    if (!eo) return -2;
+    int64_t *no = eo + R, *vo = eo + 2 * R;
+    offsets(p, eo, no, vo);
+    rod_work w;
+    if (work_alloc(&w, max_elems(p)) != 0) { free(eo); return -2; }
+    for (int r = 0; r < R; ++r) {
+        rod_view rv;
+        rod_consts c;
+        rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
+        rod_consts_make(&rv, &c);
+        rod_accel(&rv, &c, pos + 3 * no[r], vel + 3 * no[r], dir + 9 * eo[r], omega + 3 * eo[r],
+                  t, &w, acc + 3 * no[r], alpha + 3 * eo[r]);
+    }
+    work_free(&w);
+    free(eo);
+    return 0;
+}
+
+/* Energies per rod, out [R][5]:
+ *   T_lin   = 1/2 sum_j m_j |v_j|^2
+ *   T_rot   = 1/2 sum_i omega_i . J_i omega_i / e_i   (angular momentum density rho I omega / e)
+ *   U_shear = 1/2 sum_i sigma_i . S sigma_i lh_i
+ *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . Bv_k (kappa_k - kappa0_k) Dh_k
+ *   W_ext   = -sum_j f_j . (r_j - r_j(0))                (constant nodal forces) */
+int orc_energy(const orc_rods *p, const double *pos, const double *vel, const double *dir,
+               const double *omega, double *out)
+{
+    const int R = p->n_rods;
+    int64_t *eo = malloc(3 * (size_t)R * sizeof(int64_t));
+    if (!eo) return -2;
+    int64_t *no = eo + R, *vo = eo + 2 * R;
+    offsets(p, eo, no, vo);
+    rod_work w;
+    if (work_alloc(&w, max_elems(p)) != 0) { free(eo); return -2; }
+    for (int r = 0; r < R; ++r) {
+        rod_view rv;
+        rod_consts c;
+        rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
+        rod_consts_make(&rv, &c);
+        const int n = rv.n;
+        const double *x = pos + 3 * no[r], *v = vel + 3 * no[r], *om = omega + 3 * eo[r];
+        rod_kinematics(&rv, &c, x, v, dir + 9 * eo[r], &w);
+        double Tl = 0.0, Tr = 0.0, Us = 0.0, Ub = 0.0, Wx = 0.0;
+        for (int j = 0; j <= n; ++j) {
+            double mass = 0.0;
+            if (j > 0) mass += 0.5 * rv.rho * c.A * rv.lh[j - 1];
+            if (j < n) mass += 0.5 * rv.rho * c.A * rv.lh[j];
+            Tl += 0.5 * mass * dot3(&v[3 * j], &v[3 * j]);
+            if (rv.fext) {
+                double d[3] = {x[3 * j] - rv.r0[3 * j], x[3 * j + 1] - rv.r0[3 * j + 1],
+                               x[3 * j + 2] - rv.r0[3 * j + 2]};
+                Wx -= dot3(&rv.fext[3 * j], d);
+            }
+        }
+        for (int i = 0; i < n; ++i) {
+            double lh = rv.lh[i];
+            double J[3] = {rv.rho * c.I1 * lh, rv.rho * c.I2 * lh, rv.rho * c.I3 * lh};
+            for (int a = 0; a < 3; ++a) {
+                Tr += 0.5 * om[3 * i + a] * J[a] * om[3 * i + a] / w.e[i];
+                Us += 0.5 * w.sig[3 * i + a] * c.S[a] * w.sig[3 * i + a] * lh;
+            }
+        }
+        for (int k = 0; k + 1 < n; ++k) {
+            double Dh = 0.5 * (rv.lh[k] + rv.lh[k + 1]);
+            for (int a = 0; a < 3; ++a) {
+                double Bv = (c.B[a] * rv.lh[k] + c.B[a] * rv.lh[k + 1]) / (rv.lh[k] + rv.lh[k + 1]);
+                double dk = w.kap[3 * k + a] - (rv.k0 ? rv.k0[3 * k + a] : 0.0);
+                Ub += 0.5 * dk * Bv * dk * Dh;
+            }
+        }
+        out[5 * r + 0] = Tl;
+        out[5 * r + 1] = Tr;
+        out[5 * r + 2] = Us;
+        out[5 * r + 3] = Ub;
+        out[5 * r + 4] = Wx;
+    }
+    work_free(&w);
+    free(eo);
+    return 0;
+}
+
+/* The two rotation maps, exposed for direct checks. */
+void orc_rodrigues(const double *u, double *E) { rodrigues(u, E); }
+void orc_logmap(const double *R, double *u) { logmap(R, u); }
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,352 @@
+"""Seeded synthetic rod batches.
+
+This module only builds *inputs*: centrelines, director frames, material
+parameters, boundary flags and loads, as host FP64 numpy arrays in the layout
+of the C boundary (``include/rod.h``).  It contains none of the rod method's
+arithmetic (no strains, forces, couples or time stepping), so both the GPU path
+and the CPU oracle can consume the very same arrays.
+
+Workloads follow the problem statement of the Cosserat-rod model (Methods,
+"Cosserat rod dynamics": centreline r, row director matrix Q = {d1,d2,d3}^T,
+material parameters rho, E, G, alpha_c, cross-section) and the batch shapes
+listed for this build:
+
+* ``single_cantilever``  : 1 rod, 100 elements, 1 m, clamped at s=0, tip force.
+* ``ragged_batch``       : free-free rods of 16..256 elements, smooth random
+  3-mode Fourier centrelines with curvature <= 5/m, log-uniform E.
+* ``cilia_carpet``       : base-clamped vertical rods on a square grid, each
+  driven by a sinusoidal bending couple with a random phase.
+* ``surrogate_training`` : the carpet regime at 64 elements with random couple
+  amplitude and velocity noise (training data for the learned coarse step).
+
+Node j of rod r is row ``node_offset[r] + j`` of the node arrays, element i
+is row ``elem_offset[r] + i`` of the element arrays, Voronoi point k is row
+``elem_offset[r] - r + k``.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+SEED_BASE = 137660
+
+# shear modulus ratio and shear coefficient used by every workload here
+G_OVER_E = 1.0 / 1.5
+SHEAR_COEFF = 4.0 / 3.0
+DENSITY = 1000.0
+
+
+@dataclasses.dataclass
+class RodInputs:
+    """One batch of rods in the boundary's layout (all FP64 / int32, host)."""
+
+    n_elems: np.ndarray            # [R] int32
+    position: np.ndarray           # [N_n, 3]
+    velocity: np.ndarray           # [N_n, 3]
+    director: np.ndarray           # [N_e, 3, 3]  rows d1, d2, d3
+    omega: np.ndarray              # [N_e, 3]     material frame
+    density: np.ndarray            # [R]
+    youngs: np.ndarray             # [R]
+    shear_modulus: np.ndarray      # [R]
+    radius: np.ndarray             # [R]
+    shear_coeff: np.ndarray        # [R]
+    damping: np.ndarray            # [R]  1/s
+    bc_start: np.ndarray           # [R] int32, 1 = clamped at s=0
+    bc_end: np.ndarray             # [R] int32, 1 = clamped at s=L
+    dt: float
+    rest_length: Optional[np.ndarray] = None   # [N_e] or None -> from position
+    rest_kappa: Optional[np.ndarray] = None    # [N_v, 3] or None -> 0
+    end_force: Optional[np.ndarray] = None     # [R, 3] on the last node
+    couple_amp: Optional[np.ndarray] = None    # [R, 3] per unit length, material frame
+    couple_freq: Optional[np.ndarray] = None   # [R] Hz
+    couple_phase: Optional[np.ndarray] = None  # [R] rad
+    name: str = ""
+
+    # ------------------------------------------------------------------ sizes
+    @property
+    def n_rods(self) -> int:
+        return int(self.n_elems.shape[0])
+
+    @property
+    def n_elements(self) -> int:
+        return int(self.n_elems.sum())
+
+    @property
+    def elem_offset(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.n_elems)[:-1]]).astype(np.int64)
+
+    @property
+    def node_offset(self) -> np.ndarray:
+        return self.elem_offset + np.arange(self.n_rods, dtype=np.int64)
+
+    @property
+    def vor_offset(self) -> np.ndarray:
+        return self.elem_offset - np.arange(self.n_rods, dtype=np.int64)
+
+    def copy(self) -> "RodInputs":
+        kw = {}
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            kw[f.name] = v.copy() if isinstance(v, np.ndarray) else v
+        return RodInputs(**kw)
+
+    def subset(self, rods) -> "RodInputs":
+        """A new batch holding only the listed rods (in the given order)."""
+        rods = np.asarray(rods, dtype=np.int64)
+        eo, no, vo = self.elem_offset, self.node_offset, self.vor_offset
+        n = self.n_elems
+        e_idx = np.concatenate([np.arange(eo[r], eo[r] + n[r]) for r in rods])
+        n_idx = np.concatenate([np.arange(no[r], no[r] + n[r] + 1) for r in rods])
+        v_idx = np.concatenate([np.arange(vo[r], vo[r] + n[r] - 1) for r in rods])
+
+        def per_rod(a):
+            return None if a is None else a[rods].copy()
+
+        return RodInputs(
+            n_elems=n[rods].copy(),
+            position=self.position[n_idx].copy(),
+            velocity=self.velocity[n_idx].copy(),
+            director=self.director[e_idx].copy(),
+            omega=self.omega[e_idx].copy(),
+            density=per_rod(self.density), youngs=per_rod(self.youngs),
+            shear_modulus=per_rod(self.shear_modulus), radius=per_rod(self.radius),
+            shear_coeff=per_rod(self.shear_coeff), damping=per_rod(self.damping),
+            bc_start=per_rod(self.bc_start), bc_end=per_rod(self.bc_end),
+            dt=self.dt,
+            rest_length=None if self.rest_length is None else self.rest_length[e_idx].copy(),
+            rest_kappa=None if self.rest_kappa is None else self.rest_kappa[v_idx].copy(),
+            end_force=per_rod(self.end_force), couple_amp=per_rod(self.couple_amp),
+            couple_freq=per_rod(self.couple_freq), couple_phase=per_rod(self.couple_phase),
+            name=self.name + "[subset]",
+        )
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers (frames for given centrelines; no mechanics)
+# ---------------------------------------------------------------------------
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _any_perpendicular(d3):
+    a = np.array([1.0, 0.0, 0.0]) if abs(d3[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    d1 = a - np.dot(a, d3) * d3
+    return d1 / np.linalg.norm(d1)
+
+
+def _rotate_about(v, axis, angle):
+    """Rotate vector v about unit axis by angle (right hand)."""
+    c, s = np.cos(angle), np.sin(angle)
+    return v * c + np.cross(axis, v) * s + axis * np.dot(axis, v) * (1.0 - c)
+
+
+def frames_parallel_transport(nodes, d1_first=None):
+    """Director rows for the chords of a polyline, d1 carried by parallel transport.
+
+    d3_i is the unit chord of element i; d1 is transported from element to
+    element by the smallest rotation taking d3_i onto d3_{i+1}; d2 = d3 x d1.
+    Returns [n, 3, 3] with rows d1, d2, d3.
+    """
+    chords = np.diff(nodes, axis=0)
+    d3 = _unit(chords)
+    n = d3.shape[0]
+    Q = np.empty((n, 3, 3))
+    d1 = _any_perpendicular(d3[0]) if d1_first is None else np.asarray(d1_first, float)
+    for i in range(n):
+        if i > 0:
+            axis = np.cross(d3[i - 1], d3[i])
+            s = np.linalg.norm(axis)
+            if s > 1e-15:
+                ang = np.arctan2(s, np.dot(d3[i - 1], d3[i]))
+                d1 = _rotate_about(d1, axis / s, ang)
+            d1 = d1 - np.dot(d1, d3[i]) * d3[i]
+            d1 = d1 / np.linalg.norm(d1)
+        d2 = np.cross(d3[i], d1)
+        Q[i, 0], Q[i, 1], Q[i, 2] = d1, d2, d3[i]
+    return Q
+
+
+def _fourier_curve(rng, L, n, kappa_max):
+    """Nodes of a smooth 3-mode Fourier curve of arclength L, resampled to n equal chords.
+
+    r(s) = s*e + lam * sum_{m=1..3} (a_m sin(m pi s/L) + b_m (1 - cos(m pi s/L)));
+    lam is chosen by bisection so that the largest curvature of the dense curve
+    equals kappa_max.
+    """
+    e = _unit(rng.normal(size=3))
+    a = rng.normal(size=(3, 3))
+    b = rng.normal(size=(3, 3))
+    m = np.arange(1, 4)[:, None]
+    s = np.linspace(0.0, L, 4097)
+
+    def curve(lam):
+        ph = m * np.pi * s[None, :] / L            # [3, S]
+        pert = (a.T @ np.sin(ph) + b.T @ (1.0 - np.cos(ph))).T   # [S, 3]
+        return s[:, None] * e[None, :] + lam * pert
+
+    def max_curv(lam):
+        r = curve(lam)
+        d1 = np.gradient(r, s, axis=0)
+        d2 = np.gradient(d1, s, axis=0)
+        num = np.linalg.norm(np.cross(d1, d2), axis=1)
+        den = np.linalg.norm(d1, axis=1) ** 3
+        return float(np.max(num[2:-2] / den[2:-2]))
+
+    lo, hi = 0.0, 1.0
+    while max_curv(hi) < kappa_max:
+        hi *= 2.0
+        if hi > 1e6:
+            break
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        if max_curv(mid) < kappa_max:
+            lo = mid
+        else:
+            hi = mid
+    r = curve(lo)
+    seg = np.linalg.norm(np.diff(r, axis=0), axis=1)
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    # equal arclength resampling, then scale so that the total arclength is L
+    targ = np.linspace(0.0, arc[-1], n + 1)
+    nodes = np.stack([np.interp(targ, arc, r[:, k]) for k in range(3)], axis=1)
+    nodes = nodes * (L / arc[-1])
+    return nodes
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def _assemble(name, nodes_list, Q_list, dt, *, density, youngs, radius, damping,
+              bc_start, bc_end, velocity_list=None, omega_list=None,
+              end_force=None, couple_amp=None, couple_freq=None, couple_phase=None):
+    R = len(nodes_list)
+    n_elems = np.array([Q.shape[0] for Q in Q_list], dtype=np.int32)
+    position = np.concatenate(nodes_list, axis=0).astype(np.float64)
+    director = np.concatenate(Q_list, axis=0).astype(np.float64)
+    velocity = (np.zeros_like(position) if velocity_list is None
+                else np.concatenate(velocity_list, axis=0).astype(np.float64))
+    omega = (np.zeros((director.shape[0], 3)) if omega_list is None
+             else np.concatenate(omega_list, axis=0).astype(np.float64))
+    f = lambda x: np.array(np.broadcast_to(np.asarray(x, np.float64), (R,)))
+    return RodInputs(
+        n_elems=n_elems, position=np.ascontiguousarray(position),
+        velocity=np.ascontiguousarray(velocity),
+        director=np.ascontiguousarray(director), omega=np.ascontiguousarray(omega),
+        density=f(density), youngs=f(youngs), shear_modulus=f(np.asarray(youngs) * G_OVER_E),
+        radius=f(radius), shear_coeff=f(SHEAR_COEFF), damping=f(damping),
+        bc_start=np.array(np.broadcast_to(np.asarray(bc_start, np.int32), (R,))),
+        bc_end=np.array(np.broadcast_to(np.asarray(bc_end, np.int32), (R,))),
+        dt=float(dt), end_force=end_force, couple_amp=couple_amp,
+        couple_freq=couple_freq, couple_phase=couple_phase, name=name)
+
+
+def straight_rod(n, L, direction=(1.0, 0.0, 0.0), d1=(0.0, 1.0, 0.0), origin=(0.0, 0.0, 0.0)):
+    """Nodes and directors of a straight rod (d3 along `direction`)."""
+    d3 = _unit(np.asarray(direction, float))
+    d1 = np.asarray(d1, float)
+    d1 = _unit(d1 - np.dot(d1, d3) * d3)
+    d2 = np.cross(d3, d1)
+    s = np.linspace(0.0, L, n + 1)
+    nodes = np.asarray(origin, float)[None, :] + s[:, None] * d3[None, :]
+    Q = np.broadcast_to(np.stack([d1, d2, d3]), (n, 3, 3)).copy()
+    return nodes, Q
+
+
+def single_cantilever(n=100, L=1.0, radius=0.01, youngs=1e6, tip_force=(0.0, 0.0, -1e-3),
+                      noise=1e-6, dt=1e-5, seed=SEED_BASE + 1):
+    """One rod clamped at s=0 with a constant force on its last node.
+
+    Straight along +x with d1 = y, d2 = z, d3 = x; velocity noise N(0, noise^2)
+    on every free node; no damping.
+    """
+    rng = np.random.default_rng(seed)
+    nodes, Q = straight_rod(n, L)
+    vel = np.zeros_like(nodes)
+    if noise > 0:
+        vel[1:] = rng.normal(0.0, noise, size=(n, 3))
+    return _assemble("single_cantilever", [nodes], [Q], dt, density=DENSITY, youngs=youngs,
+                     radius=radius, damping=0.0, bc_start=1, bc_end=0, velocity_list=[vel],
+                     end_force=np.asarray(tip_force, float).reshape(1, 3).copy())
+
+
+def ragged_batch(n_rods=4096, n_min=16, n_max=256, ds=0.01, kappa_max=5.0, damping=0.1,
+                 dt=1e-5, seed=SEED_BASE + 2, box=5.0):
+    """Free-free rods with uneven element counts and curved centrelines.
+
+    Element count uniform in [n_min, n_max]; rod length n*ds; centrelines are
+    3-mode Fourier curves whose largest curvature is drawn in [0.2, 0.95] x
+    kappa_max; rest state straight and unstretched at the initial chord lengths;
+    E log-uniform in [1e5, 1e7] Pa; radius uniform in [0.005, 0.02] m.
+    """
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_min, n_max + 1, size=n_rods)
+    E = 10.0 ** rng.uniform(5.0, 7.0, size=n_rods)
+    rad = rng.uniform(0.005, 0.02, size=n_rods)
+    nodes_list, Q_list = [], []
+    for r in range(n_rods):
+        n = int(ns[r])
+        kap = kappa_max * rng.uniform(0.2, 0.95)
+        nodes = _fourier_curve(rng, n * ds, n, kap)
+        nodes = nodes + rng.uniform(-box, box, size=3)[None, :]
+        nodes_list.append(nodes)
+        Q_list.append(frames_parallel_transport(nodes))
+    return _assemble("ragged_batch", nodes_list, Q_list, dt, density=DENSITY, youngs=E,
+                     radius=rad, damping=damping, bc_start=0, bc_end=0)
+
+
+def cilia_carpet(grid=256, n=50, L=0.01, radius=2e-4, youngs=1e6, spacing=2.5e-3,
+                 amp=7.5e-6, freq=10.0, dt=1e-6, seed=SEED_BASE + 3, amp_range=None,
+                 noise=0.0, n_rods=None):
+    """Vertical rods clamped at their base on a grid x grid lattice.
+
+    Each rod carries a distributed couple amp*sin(2 pi freq t + phi) about its
+    material d1 axis, with phi uniform in [0, 2 pi).  d1 = x, d2 = y, d3 = z.
+    ``amp_range=(lo, hi)`` scales amp per rod by U[lo, hi]; ``noise`` adds
+    N(0, noise^2) velocity noise on free nodes; ``n_rods`` truncates the grid.
+    """
+    rng = np.random.default_rng(seed)
+    R = grid * grid if n_rods is None else int(n_rods)
+    ix, iy = np.divmod(np.arange(R), grid)
+    base = np.stack([ix * spacing, iy * spacing, np.zeros(R)], axis=1)
+    s = np.linspace(0.0, L, n + 1)
+    nodes = base[:, None, :] + s[None, :, None] * np.array([0.0, 0.0, 1.0])[None, None, :]
+    Q1 = np.stack([np.array([1.0, 0, 0]), np.array([0, 1.0, 0]), np.array([0, 0, 1.0])])
+    director = np.broadcast_to(Q1, (R * n, 3, 3)).copy()
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=R)
+    scale = np.ones(R) if amp_range is None else rng.uniform(amp_range[0], amp_range[1], size=R)
+    camp = np.zeros((R, 3))
+    camp[:, 0] = amp * scale
+    vel = np.zeros((R, n + 1, 3))
+    if noise > 0:
+        vel[:, 1:, :] = rng.normal(0.0, noise, size=(R, n, 3))
+    inp = RodInputs(
+        n_elems=np.full(R, n, dtype=np.int32),
+        position=np.ascontiguousarray(nodes.reshape(-1, 3)),
+        velocity=np.ascontiguousarray(vel.reshape(-1, 3)),
+        director=director, omega=np.zeros((R * n, 3)),
+        density=np.full(R, DENSITY), youngs=np.full(R, float(youngs)),
+        shear_modulus=np.full(R, youngs * G_OVER_E), radius=np.full(R, float(radius)),
+        shear_coeff=np.full(R, SHEAR_COEFF), damping=np.zeros(R),
+        bc_start=np.ones(R, dtype=np.int32), bc_end=np.zeros(R, dtype=np.int32),
+        dt=float(dt), couple_amp=camp, couple_freq=np.full(R, float(freq)),
+        couple_phase=phase, name="cilia_carpet")
+    return inp
+
+
+def surrogate_training(n_rods=16384, n=64, seed=SEED_BASE + 4, **kw):
+    """Training rods: the carpet regime at 64 elements, random couple amplitude in
+    [0.5, 1.5] x 7.5e-6 N m/m and N(0, 1e-6 m/s) velocity noise."""
+    grid = int(np.ceil(np.sqrt(n_rods)))
+    return cilia_carpet(grid=grid, n=n, seed=seed, amp_range=(0.5, 1.5), noise=1e-6,
+                        n_rods=n_rods, **kw)
+
+
+def surrogate_at_scale(n_rods=262144, n=64, seed=SEED_BASE + 5, **kw):
+    """Rods advanced by the learned coarse step: the carpet regime at 64 elements."""
+    grid = int(np.ceil(np.sqrt(n_rods)))
+    return cilia_carpet(grid=grid, n=n, seed=seed, amp_range=(0.5, 1.5), noise=1e-6,
+                        n_rods=n_rods, **kw)
