@@ -1,0 +1,170 @@
+/*
+ * rod.h -- C boundary of the MI355X (gfx950) discrete Cosserat-rod library.
+ *
+ * The library advances many independent elastic rods with the explicit
+ * position-Verlet step of the discrete Cosserat model (Elastica++, Methods,
+ * "Cosserat rod dynamics", Eq. 1a and 1b; time stepping as the multi-stage
+ * symplectic Verlet scheme of Results, "Performance-oriented software
+ * design").  Every step of the path runs in HIP kernels on the GPU; the host
+ * side only validates, packs and schedules.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: ROD_OK (0) or a negative ROD_E* code.  No C++ exception
+ *    crosses this boundary.  rod_last_error() returns a thread-local message
+ *    for the last non-zero return (and for warnings attached to ROD_OK).
+ *  - Layout of rod data (all FP64, C order):
+ *      rod r has n_r elements, n_r + 1 nodes and n_r - 1 Voronoi points;
+ *      node j of rod r is row  (sum_{q<r} (n_q + 1)) + j  of a node array,
+ *      element i is row         (sum_{q<r} n_q) + i       of an element array,
+ *      Voronoi point k is row   (sum_{q<r} (n_q - 1)) + k of a Voronoi array.
+ *      position, velocity: [N_nodes][3] lab frame (m, m/s)
+ *      director:           [N_elems][3][3], row a = director d_{a+1} in lab
+ *                          coordinates (the row matrix Q = {d1,d2,d3}^T)
+ *      omega:              [N_elems][3] angular velocity in the material
+ *                          frame, omega = ax(Q dQ^T/dt)
+ *  - Ownership: rod_batch_create copies everything it needs into device
+ *    memory it owns; the caller keeps its arrays.  Output buffers belong to
+ *    the caller.  A handle is valid until rod_batch_destroy.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  rod_step only enqueues work; rod_energy, rod_get_state,
+ *    rod_set_state and rod_get_flags synchronise the stream.
+ *  - Precision: inputs are always FP64.  ROD_F32 batches round them once at
+ *    creation (round to nearest even) and store node positions relative to a
+ *    per-rod FP64 origin (the rod's first node at creation).
+ *  - Not thread-safe per handle: calls on one handle must not overlap.
+ */
+#ifndef ROD_H
+#define ROD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ROD_OK = 0,
+    ROD_EINVAL = -1,        /* invalid argument (see rod_last_error) */
+    ROD_ENOMEM = -2,        /* device or host allocation failed */
+    ROD_EDEVICE = -3,       /* a HIP runtime call failed */
+    ROD_ENONFINITE = -4,    /* a rod's state became NaN/Inf (see rod_get_flags) */
+    ROD_EUNSUPPORTED = -5   /* valid but outside what this build supports */
+};
+
+enum { ROD_F64 = 0, ROD_F32 = 1 };
+enum { ROD_FREE = 0, ROD_CLAMPED = 1 };
+
+/* Longest rod (elements) one workgroup tile can hold. */
+#define ROD_MAX_ELEMS 512
+
+typedef struct rod_batch rod_batch;
+
+/*
+ * Problem description (Methods, "Cosserat rod dynamics": centreline r,
+ * directors Q, angular velocity omega, density rho, Young's and shear moduli
+ * E and G, shear coefficient alpha_c, cross-section; external force f and
+ * couple c; boundary conditions per property (4) of that section).
+ * The cross-section is a solid circle of the given radius:
+ *   A = pi r^2, I1 = I2 = pi r^4 / 4, I3 = I1 + I2,
+ *   S = diag(alpha_c G A, alpha_c G A, E A), B = diag(E I1, E I2, G I3).
+ */
+typedef struct {
+    int32_t n_rods;                  /* R >= 1 */
+    const int32_t *n_elems;          /* [R], each in [1, ROD_MAX_ELEMS] */
+    const double *position;          /* [N_nodes][3] required */
+    const double *velocity;          /* [N_nodes][3] required */
+    const double *director;          /* [N_elems][3][3] required, in SO(3) within 1e-8 */
+    const double *omega;             /* [N_elems][3] required */
+    const double *rest_length;       /* [N_elems] > 0, or NULL: chord lengths of `position` */
+    const double *rest_kappa;        /* [N_vor][3] rest curvature, or NULL: 0 */
+    const double *density;           /* [R] rho > 0 (kg/m^3) */
+    const double *youngs;            /* [R] E > 0 (Pa) */
+    const double *shear_modulus;     /* [R] G > 0 (Pa) */
+    const double *radius;            /* [R] > 0 (m) */
+    const double *shear_coeff;       /* [R] alpha_c > 0 */
+    const double *damping;           /* [R] gamma >= 0 (1/s): a -= gamma v, alpha -= gamma omega; or NULL: 0 */
+    const int32_t *bc_start;         /* [R] ROD_FREE / ROD_CLAMPED at s = 0, or NULL: free */
+    const int32_t *bc_end;           /* [R] ROD_FREE / ROD_CLAMPED at s = L, or NULL: free */
+    const double *end_force;         /* [R][3] constant lab-frame force on the last node (N), or NULL */
+    const double *couple_amp;        /* [R][3] distributed couple amplitude per unit length,
+                                        material frame (N m/m), or NULL */
+    const double *couple_freq;       /* [R] Hz (with couple_amp): c(t) = amp sin(2 pi f t + phase) */
+    const double *couple_phase;      /* [R] rad (with couple_amp) */
+    double dt;                       /* time step h > 0 (s) */
+    double t0;                       /* time of the initial state (s) */
+    int32_t precision;               /* ROD_F64 or ROD_F32 */
+    int32_t substeps;                /* steps per kernel launch; 0: all steps of a rod_step call */
+    int32_t tile_waves;              /* wave64s per workgroup tile (1, 2, 4, 8); 0: smallest that fits */
+    int32_t inputs_on_device;        /* 1: every pointer above is device memory; 0: host */
+} rod_batch_desc;
+
+/*
+ * Create a batch: validate, derive the per-element constants in FP64, pack
+ * the rods into workgroup tiles (whole rods per tile, best-fit decreasing),
+ * and upload.  Errors: ROD_EINVAL (n_elems outside [1, ROD_MAX_ELEMS], a
+ * NULL required array, dt <= 0, rho/E/G/radius/alpha_c <= 0, damping < 0,
+ * a director farther than 1e-8 from SO(3) or with det < 0, a zero-length
+ * element or rest length <= 0, couple_amp without freq/phase), ROD_ENOMEM,
+ * ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the longest rod).
+ * A time step above the explicit stability estimate is reported through
+ * rod_last_error with ROD_OK.
+ */
+int rod_batch_create(const rod_batch_desc *desc, void *stream, rod_batch **out);
+
+/*
+ * Advance every rod by n_steps >= 0 position-Verlet steps of size dt
+ * (Results, "Performance-oriented software design"): per step a half drift
+ * r += h/2 v, Q <- exp(-h/2 [omega]x) Q; the kick v += h a, omega += h alpha
+ * with a, alpha from Eq. 1a / 1b at time t_n + h/2; a second half drift; the
+ * clamped ends' kinematic constraints after every stage.  The steps run as
+ * ceil(n_steps / substeps) launches of one persistent kernel whose tiles
+ * keep the rods' state on chip across the substeps; the launch sequence is
+ * captured once per distinct n_steps into a HIP graph and replayed.
+ * Asynchronous on `stream`.  ROD_EINVAL for n_steps < 0 or a NULL handle.
+ */
+int rod_step(rod_batch *b, int64_t n_steps, void *stream);
+
+/*
+ * Per-rod energies, out[R][5] (host, FP64), synchronising `stream`:
+ *   T_lin   = 1/2 sum_j m_j |v_j|^2
+ *   T_rot   = 1/2 sum_i omega_i . J_i omega_i / e_i   (Eq. 1b's rho I omega / e)
+ *   U_shear = 1/2 sum_i sigma_i . S sigma_i lh_i
+ *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . B_k (kappa_k - kappa0_k) Dh_k
+ *   W_ext   = -sum f . (r_last - r_last(0))          (the constant end force)
+ * Returns ROD_ENONFINITE if any rod is flagged non-finite.
+ */
+int rod_energy(rod_batch *b, double *out, void *stream);
+
+/* Copy the state back into caller-owned host arrays in the layout above (any
+ * pointer may be NULL to skip it); *t receives the current time.
+ * Synchronises `stream`.  ROD_ENONFINITE if any rod is flagged. */
+int rod_get_state(rod_batch *b, double *position, double *velocity, double *director,
+                  double *omega, double *t, void *stream);
+
+/* Overwrite the state (host arrays, layout above; NULL keeps a field) and the
+ * time.  Constraints of clamped ends are re-imposed (their node and element
+ * keep the values captured at creation, with zero velocities).
+ * Synchronises `stream`.  Clears the non-finite flags. */
+int rod_set_state(rod_batch *b, const double *position, const double *velocity,
+                  const double *director, const double *omega, double t, void *stream);
+
+/* Per-rod non-finite flags (host int32 [R]: 1 = NaN/Inf seen at the end of a
+ * launch).  Synchronises `stream`. */
+int rod_get_flags(rod_batch *b, int32_t *nonfinite, void *stream);
+
+/* Sizes and the chosen launch shape: info[0] rods, [1] elements, [2] tiles,
+ * [3] tile_waves, [4] substeps per launch (0 = whole call), [5] precision,
+ * [6] slots (tiles * 64 * tile_waves), [7] steps taken so far. */
+int rod_batch_info(const rod_batch *b, int64_t *info);
+
+void rod_batch_destroy(rod_batch *b);
+
+/* Thread-local message for the last non-zero return or warning ("" if none). */
+const char *rod_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROD_H */

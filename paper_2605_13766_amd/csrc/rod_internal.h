@@ -1,0 +1,84 @@
+// Private declarations shared by the host runtime (rod_lib.cpp) and the HIP
+// kernels (rod_kernels.hip) of librod.so.  Not part of the public boundary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rodk {
+
+// Per-slot state fields.  A slot is one lane of a workgroup tile; slot s of a
+// rod holds its node s (r, v) and its element s (Q, omega).  The rod's last
+// node lives in the per-rod tail arrays.
+enum StateField {
+    RX, RY, RZ, VX, VY, VZ,
+    Q00, Q01, Q02, Q10, Q11, Q12, Q20, Q21, Q22,
+    WX, WY, WZ,
+    N_STATE
+};
+
+// Per-slot constants, derived in FP64 on the host.  Node quantities belong to
+// the slot's node, element quantities to its element, Voronoi quantities to
+// the Voronoi point between the slot's element and the next one.
+enum ParamField {
+    P_INV_M,    // node: 1 / lumped mass
+    P_LH,       // element: rest length
+    P_INV_LH,   // element: 1 / rest length
+    P_J1,       // element: rho I1 lh (= rho I2 lh; rho I3 lh = 2 P_J1)
+    P_S1,       // element: alpha_c G A (= S22)
+    P_S3,       // element: E A
+    P_DH,       // Voronoi: rest length (lh_k + lh_{k+1}) / 2
+    P_INV_DH,   // Voronoi: 1 / P_DH
+    P_B1,       // Voronoi: bending stiffness E I1 (= E I2), rest-length weighted
+    P_B3,       // Voronoi: twist stiffness G I3, rest-length weighted
+    P_K0X, P_K0Y, P_K0Z,   // Voronoi: rest curvature
+    N_PARAM
+};
+
+// Per-rod tail node (the rod's node n).
+enum TailField { TRX, TRY, TRZ, TVX, TVY, TVZ, N_TAIL };
+
+// Per-rod constants in the state precision.
+enum RodParam {
+    R_GAMMA,                  // linear damping
+    R_INV_M_TAIL,             // 1 / mass of node n
+    R_FX, R_FY, R_FZ,         // constant force on node n
+    R_CX, R_CY, R_CZ,         // couple amplitude per unit length (material frame)
+    R_T0X, R_T0Y, R_T0Z,      // position of node n at creation (work of the end force)
+    N_RODP
+};
+
+enum RodFlags { FLAG_CLAMP0 = 1, FLAG_CLAMP1 = 2, FLAG_COUPLE = 4 };
+
+template <typename T>
+struct DevBatch {
+    T *state;              // [N_STATE][n_slots]
+    T *param;              // [N_PARAM][n_slots]
+    T *tail;               // [N_TAIL][n_rods]
+    T *rodp;               // [N_RODP][n_rods]
+    double *rod_freq;      // [n_rods] Hz
+    double *rod_phase;     // [n_rods] rad
+    int32_t *slot_rod;     // [n_slots] rod of the slot, -1 for padding
+    int32_t *slot_idx;     // [n_slots] element index within the rod
+    int32_t *rod_n;        // [n_rods] elements
+    int32_t *rod_flags;    // [n_rods] RodFlags
+    int32_t *rod_slot;     // [n_rods] slot of element 0
+    int32_t *nonfinite;    // [n_rods] set to 1 when the state stops being finite
+    int64_t *step;         // global step counter (device)
+    int64_t n_slots;
+    int32_t n_rods;
+    int32_t n_tiles;
+    double dt;
+    double t0;
+};
+
+// Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
+hipError_t launch_step(const DevBatch<double> &b, int waves, int n_sub, int grid, hipStream_t s);
+hipError_t launch_step(const DevBatch<float> &b, int waves, int n_sub, int grid, hipStream_t s);
+hipError_t launch_advance(int64_t *step, int64_t n, hipStream_t s);
+hipError_t launch_energy(const DevBatch<double> &b, double *out, hipStream_t s);
+hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s);
+// Largest number of co-resident workgroups of the step kernel (occupancy x CUs).
+int step_resident_groups(int precision_f32, int waves);
+
+}  // namespace rodk

@@ -1,0 +1,766 @@
+// rod_lib.cpp -- host runtime behind include/rod.h: argument checks, the
+// derived per-element constants (FP64), packing of whole rods into
+// workgroup tiles, HIP-graph capture of the launch sequence, state I/O.
+//
+// Constitutive and inertial constants follow Elastica++, Methods, "Cosserat
+// rod dynamics": S = diag(alpha_c G A, alpha_c G A, E A),
+// B = diag(E I1, E I2, G (I1 + I2)), inertia rho I per unit length, for a
+// solid circular section A = pi r^2, I1 = I2 = pi r^4 / 4.
+#include "rod.h"
+#include "rod_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? ROD_ENOMEM : ROD_EDEVICE,                \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+struct HostInputs {
+    std::vector<int32_t> n;
+    std::vector<double> pos, vel, dir, om, lh, k0;
+    std::vector<double> rho, E, G, rad, ac, gam;
+    std::vector<int32_t> bc0, bc1;
+    std::vector<double> fend, camp, cfreq, cphase;
+    bool has_k0 = false, has_f = false, has_c = false;
+};
+
+template <typename X>
+int fetch(std::vector<X> &dst, const X *src, size_t count, bool on_device)
+{
+    dst.resize(count);
+    if (count == 0) return ROD_OK;
+    if (on_device) {
+        HIPCHK(hipMemcpy(dst.data(), src, count * sizeof(X), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(dst.data(), src, count * sizeof(X));
+    }
+    return ROD_OK;
+}
+
+}  // namespace
+
+struct rod_batch {
+    int precision = ROD_F64;
+    int waves = 1;
+    int substeps = 0;
+    int grid = 0;
+    int32_t R = 0;
+    int64_t Ne = 0, Nn = 0, n_slots = 0;
+    int n_tiles = 0;
+    double dt = 0, t0 = 0;
+    int64_t steps = 0;           // steps since t0 (mirrors the device counter)
+    std::vector<int32_t> n;
+    std::vector<int32_t> rod_slot;
+    std::vector<double> origin;  // [R][3]
+    // clamped ends: creation values of node 0 / element 0 and node n / element n-1
+    std::vector<int32_t> bc0, bc1;
+    std::vector<double> clamp_r0, clamp_q0, clamp_rn, clamp_qn;   // [R][3], [R][9]
+    // device
+    void *d_state = nullptr, *d_param = nullptr, *d_tail = nullptr, *d_rodp = nullptr;
+    double *d_freq = nullptr, *d_phase = nullptr, *d_energy = nullptr;
+    int32_t *d_ints = nullptr;   // slot_rod, slot_idx, rod_n, rod_flags, rod_slot, nonfinite
+    int64_t *d_step = nullptr;
+    rodk::DevBatch<double> b64{};
+    rodk::DevBatch<float> b32{};
+    hipStream_t capture_stream = nullptr;
+    std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    bool use_graphs = true;
+    // host staging of the packed layout
+    std::vector<int32_t> slot_rod, slot_idx;
+};
+
+namespace {
+
+size_t elem_bytes(const rod_batch *b) { return b->precision == ROD_F32 ? 4 : 8; }
+
+// Best-fit decreasing packing of whole rods into tiles of `cap` lanes.
+void pack_tiles(const std::vector<int32_t> &n, int cap, std::vector<int32_t> &rod_slot, int &n_tiles)
+{
+    const int R = (int)n.size();
+    std::vector<int32_t> order(R);
+    for (int r = 0; r < R; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    std::multiset<std::pair<int, int>> room;   // (free lanes, tile)
+    std::vector<int> used;
+    rod_slot.assign(R, 0);
+    for (int r : order) {
+        auto it = room.lower_bound({n[r], -1});
+        int tile;
+        if (it == room.end()) {
+            tile = (int)used.size();
+            used.push_back(0);
+        } else {
+            tile = it->second;
+            room.erase(it);
+        }
+        rod_slot[r] = tile * cap + used[tile];
+        used[tile] += n[r];
+        if (cap - used[tile] > 0) room.insert({cap - used[tile], tile});
+    }
+    n_tiles = (int)used.size();
+}
+
+int validate(const rod_batch_desc *d)
+{
+    if (!d) return fail(ROD_EINVAL, "desc is NULL");
+    if (d->n_rods < 1) return fail(ROD_EINVAL, "n_rods must be >= 1");
+    if (!d->n_elems || !d->position || !d->velocity || !d->director || !d->omega || !d->density
+        || !d->youngs || !d->shear_modulus || !d->radius || !d->shear_coeff)
+        return fail(ROD_EINVAL, "a required array is NULL");
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(ROD_EINVAL, "dt must be > 0");
+    if (!std::isfinite(d->t0)) return fail(ROD_EINVAL, "t0 must be finite");
+    if (d->precision != ROD_F64 && d->precision != ROD_F32) return fail(ROD_EINVAL, "precision must be ROD_F64 or ROD_F32");
+    if (d->substeps < 0) return fail(ROD_EINVAL, "substeps must be >= 0");
+    if (d->tile_waves != 0 && d->tile_waves != 1 && d->tile_waves != 2 && d->tile_waves != 4 && d->tile_waves != 8)
+        return fail(ROD_EINVAL, "tile_waves must be 0, 1, 2, 4 or 8");
+    if (d->couple_amp && (!d->couple_freq || !d->couple_phase))
+        return fail(ROD_EINVAL, "couple_amp needs couple_freq and couple_phase");
+    return ROD_OK;
+}
+
+int gather_inputs(const rod_batch_desc *d, HostInputs &h)
+{
+    const bool dev = d->inputs_on_device != 0;
+    const int R = d->n_rods;
+    int rc;
+    if ((rc = fetch(h.n, d->n_elems, R, dev))) return rc;
+    int64_t Ne = 0;
+    for (int r = 0; r < R; ++r) {
+        if (h.n[r] < 1 || h.n[r] > ROD_MAX_ELEMS)
+            return fail(ROD_EINVAL, "rod " + std::to_string(r) + ": n_elems " + std::to_string(h.n[r])
+                                        + " outside [1, " + std::to_string(ROD_MAX_ELEMS) + "]");
+        Ne += h.n[r];
+    }
+    const int64_t Nn = Ne + R, Nv = Ne - R;
+    if ((rc = fetch(h.pos, d->position, 3 * Nn, dev))) return rc;
+    if ((rc = fetch(h.vel, d->velocity, 3 * Nn, dev))) return rc;
+    if ((rc = fetch(h.dir, d->director, 9 * Ne, dev))) return rc;
+    if ((rc = fetch(h.om, d->omega, 3 * Ne, dev))) return rc;
+    if (d->rest_length) {
+        if ((rc = fetch(h.lh, d->rest_length, Ne, dev))) return rc;
+    }
+    if (d->rest_kappa) {
+        if ((rc = fetch(h.k0, d->rest_kappa, 3 * Nv, dev))) return rc;
+        h.has_k0 = true;
+    }
+    if ((rc = fetch(h.rho, d->density, R, dev))) return rc;
+    if ((rc = fetch(h.E, d->youngs, R, dev))) return rc;
+    if ((rc = fetch(h.G, d->shear_modulus, R, dev))) return rc;
+    if ((rc = fetch(h.rad, d->radius, R, dev))) return rc;
+    if ((rc = fetch(h.ac, d->shear_coeff, R, dev))) return rc;
+    if (d->damping) {
+        if ((rc = fetch(h.gam, d->damping, R, dev))) return rc;
+    } else {
+        h.gam.assign(R, 0.0);
+    }
+    if (d->bc_start) {
+        if ((rc = fetch(h.bc0, d->bc_start, R, dev))) return rc;
+    } else {
+        h.bc0.assign(R, 0);
+    }
+    if (d->bc_end) {
+        if ((rc = fetch(h.bc1, d->bc_end, R, dev))) return rc;
+    } else {
+        h.bc1.assign(R, 0);
+    }
+    if (d->end_force) {
+        if ((rc = fetch(h.fend, d->end_force, 3 * R, dev))) return rc;
+        h.has_f = true;
+    } else {
+        h.fend.assign(3 * R, 0.0);
+    }
+    if (d->couple_amp) {
+        if ((rc = fetch(h.camp, d->couple_amp, 3 * R, dev))) return rc;
+        if ((rc = fetch(h.cfreq, d->couple_freq, R, dev))) return rc;
+        if ((rc = fetch(h.cphase, d->couple_phase, R, dev))) return rc;
+        h.has_c = true;
+    } else {
+        h.camp.assign(3 * R, 0.0);
+        h.cfreq.assign(R, 0.0);
+        h.cphase.assign(R, 0.0);
+    }
+    return ROD_OK;
+}
+
+int check_values(HostInputs &h)
+{
+    const int R = (int)h.n.size();
+    for (int r = 0; r < R; ++r) {
+        const std::string tag = "rod " + std::to_string(r) + ": ";
+        if (!(h.rho[r] > 0) || !(h.E[r] > 0) || !(h.G[r] > 0) || !(h.rad[r] > 0) || !(h.ac[r] > 0))
+            return fail(ROD_EINVAL, tag + "density, youngs, shear_modulus, radius and shear_coeff must be > 0");
+        if (!(h.gam[r] >= 0) || !std::isfinite(h.gam[r])) return fail(ROD_EINVAL, tag + "damping must be >= 0");
+        if ((h.bc0[r] != 0 && h.bc0[r] != 1) || (h.bc1[r] != 0 && h.bc1[r] != 1))
+            return fail(ROD_EINVAL, tag + "bc flags must be ROD_FREE or ROD_CLAMPED");
+    }
+    for (double x : h.pos) if (!std::isfinite(x)) return fail(ROD_EINVAL, "position is not finite");
+    for (double x : h.vel) if (!std::isfinite(x)) return fail(ROD_EINVAL, "velocity is not finite");
+    for (double x : h.om) if (!std::isfinite(x)) return fail(ROD_EINVAL, "omega is not finite");
+    const int64_t Ne = (int64_t)h.dir.size() / 9;
+    for (int64_t i = 0; i < Ne; ++i) {
+        const double *q = &h.dir[9 * i];
+        double worst = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = q[3 * a] * q[3 * b] + q[3 * a + 1] * q[3 * b + 1] + q[3 * a + 2] * q[3 * b + 2];
+                worst = std::max(worst, std::fabs(s - (a == b ? 1.0 : 0.0)));
+            }
+        const double det = q[0] * (q[4] * q[8] - q[5] * q[7]) - q[1] * (q[3] * q[8] - q[5] * q[6])
+                         + q[2] * (q[3] * q[7] - q[4] * q[6]);
+        if (!(worst <= 1e-8) || !(det > 0))
+            return fail(ROD_EINVAL, "director of element " + std::to_string(i) + " is not in SO(3) within 1e-8");
+    }
+    // rest lengths: given or the initial chord lengths
+    const bool given = !h.lh.empty();
+    if (!given) h.lh.resize(Ne);
+    int64_t e = 0, nd = 0;
+    for (int r = 0; r < R; ++r) {
+        for (int i = 0; i < h.n[r]; ++i, ++e) {
+            const double *a = &h.pos[3 * (nd + i)], *b = &h.pos[3 * (nd + i + 1)];
+            const double l = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1])
+                                       + (b[2] - a[2]) * (b[2] - a[2]));
+            if (!(l > 0)) return fail(ROD_EINVAL, "element " + std::to_string(e) + " has zero length");
+            if (!given) h.lh[e] = l;
+            if (!(h.lh[e] > 0) || !std::isfinite(h.lh[e]))
+                return fail(ROD_EINVAL, "rest length of element " + std::to_string(e) + " must be > 0");
+        }
+        nd += h.n[r] + 1;
+    }
+    return ROD_OK;
+}
+
+// Crude explicit stability bound: 2 / (largest natural frequency) over the
+// axial, shear, bending, twisting and rotational-shear modes of one element.
+double stability_dt(const HostInputs &h)
+{
+    double dt = 1e300;
+    int64_t e = 0;
+    for (size_t r = 0; r < h.n.size(); ++r) {
+        double lmin = 1e300;
+        for (int i = 0; i < h.n[r]; ++i) lmin = std::min(lmin, h.lh[e + i]);
+        e += h.n[r];
+        const double A = M_PI * h.rad[r] * h.rad[r], I = M_PI * std::pow(h.rad[r], 4) / 4.0;
+        const double rho = h.rho[r];
+        double w = 0;
+        w = std::max(w, 2.0 / lmin * std::sqrt(h.E[r] / rho));                       // axial
+        w = std::max(w, 2.0 / lmin * std::sqrt(h.ac[r] * h.G[r] / rho));             // shear
+        w = std::max(w, 4.0 / (lmin * lmin) * std::sqrt(h.E[r] * I / (rho * A)));    // bending
+        w = std::max(w, 2.0 / lmin * std::sqrt(h.G[r] / rho));                       // twist
+        w = std::max(w, std::sqrt(2.0 * h.ac[r] * h.G[r] * A / (rho * I)));          // rotational shear
+        dt = std::min(dt, 2.0 / w);
+    }
+    return dt;
+}
+
+template <typename T>
+void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
+{
+    const int64_t NS = b->n_slots;
+    d.state = (T *)b->d_state;
+    d.param = (T *)b->d_param;
+    d.tail = (T *)b->d_tail;
+    d.rodp = (T *)b->d_rodp;
+    d.rod_freq = b->d_freq;
+    d.rod_phase = b->d_phase;
+    d.slot_rod = b->d_ints;
+    d.slot_idx = b->d_ints + NS;
+    d.rod_n = b->d_ints + 2 * NS;
+    d.rod_flags = d.rod_n + b->R;
+    d.rod_slot = d.rod_flags + b->R;
+    d.nonfinite = d.rod_slot + b->R;
+    d.step = b->d_step;
+    d.n_slots = NS;
+    d.n_rods = b->R;
+    d.n_tiles = b->n_tiles;
+    d.dt = b->dt;
+    d.t0 = b->t0;
+}
+
+// Pack the dynamic state into the slot layout, imposing the clamped ends'
+// constraints.  FP64 stores node positions; FP32 stores element edge vectors
+// r_{i+1} - r_i (differences taken in FP64) and node 0 relative to the rod
+// origin in the tail position fields.
+template <typename T>
+void pack_state(const rod_batch *b, const double *pos, const double *vel, const double *dir,
+                const double *om, std::vector<T> &state, std::vector<T> &tail)
+{
+    constexpr bool EDGE = sizeof(T) == 4;
+    const int64_t NS = b->n_slots;
+    const int R = b->R;
+    state.assign((size_t)rodk::N_STATE * NS, T(0));
+    tail.assign((size_t)rodk::N_TAIL * R, T(0));
+    for (int64_t s = 0; s < NS; ++s) {   // padding: identity frames, unit edges
+        state[rodk::Q00 * NS + s] = T(1);
+        state[rodk::Q11 * NS + s] = T(1);
+        state[rodk::Q22 * NS + s] = T(1);
+        if (EDGE) state[rodk::RZ * NS + s] = T(1);
+    }
+    std::vector<double> x;
+    int64_t e = 0, nd = 0;
+    for (int r = 0; r < R; ++r) {
+        const int n = b->n[r];
+        const double *o = &b->origin[3 * r];
+        // node positions with the clamped nodes at their creation values
+        x.assign(&pos[3 * nd], &pos[3 * (nd + n + 1)]);
+        if (b->bc0[r]) for (int a = 0; a < 3; ++a) x[a] = b->clamp_r0[3 * r + a];
+        if (b->bc1[r]) for (int a = 0; a < 3; ++a) x[3 * n + a] = b->clamp_rn[3 * r + a];
+        for (int i = 0; i < n; ++i) {
+            const int64_t s = b->rod_slot[r] + i;
+            const bool fixed_node = (i == 0 && b->bc0[r]);
+            const bool fixed_elem = (i == 0 && b->bc0[r]) || (i == n - 1 && b->bc1[r]);
+            for (int a = 0; a < 3; ++a) {
+                state[(rodk::RX + a) * NS + s] = EDGE ? T(x[3 * (i + 1) + a] - x[3 * i + a]) : T(x[3 * i + a] - o[a]);
+                state[(rodk::VX + a) * NS + s] = fixed_node ? T(0) : T(vel[3 * (nd + i) + a]);
+                state[(rodk::WX + a) * NS + s] = fixed_elem ? T(0) : T(om[3 * (e + i) + a]);
+            }
+            const double *q = (i == 0 && b->bc0[r]) ? &b->clamp_q0[9 * r]
+                            : (i == n - 1 && b->bc1[r]) ? &b->clamp_qn[9 * r] : &dir[9 * (e + i)];
+            for (int k = 0; k < 9; ++k) state[(rodk::Q00 + k) * NS + s] = T(q[k]);
+        }
+        for (int a = 0; a < 3; ++a) {
+            tail[(rodk::TRX + a) * R + r] = EDGE ? T(x[a] - o[a]) : T(x[3 * n + a] - o[a]);
+            tail[(rodk::TVX + a) * R + r] = b->bc1[r] ? T(0) : T(vel[3 * (nd + n) + a]);
+        }
+        e += n;
+        nd += n + 1;
+    }
+}
+
+template <typename T>
+int upload_state(rod_batch *b, const double *pos, const double *vel, const double *dir, const double *om)
+{
+    std::vector<T> state, tail;
+    pack_state<T>(b, pos, vel, dir, om, state, tail);
+    HIPCHK(hipMemcpy(b->d_state, state.data(), state.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_tail, tail.data(), tail.size() * sizeof(T), hipMemcpyHostToDevice));
+    return ROD_OK;
+}
+
+template <typename T>
+int build_device(rod_batch *b, const HostInputs &h)
+{
+    const int64_t NS = b->n_slots;
+    const int R = b->R;
+    // ---- per-slot constants (FP64 derivation, stored in T)
+    std::vector<T> param((size_t)rodk::N_PARAM * NS, T(0));
+    for (int64_t s = 0; s < NS; ++s) {   // padding: harmless values
+        param[rodk::P_INV_M * NS + s] = T(0);
+        param[rodk::P_LH * NS + s] = T(1);
+        param[rodk::P_INV_LH * NS + s] = T(1);
+        param[rodk::P_J1 * NS + s] = T(1);
+        param[rodk::P_DH * NS + s] = T(1);
+        param[rodk::P_INV_DH * NS + s] = T(1);
+    }
+    std::vector<T> rodp((size_t)rodk::N_RODP * R, T(0));
+    std::vector<double> freq(R), phase(R);
+    std::vector<int32_t> flags(R);
+    int64_t e = 0, v = 0, nd = 0;
+    for (int r = 0; r < R; ++r) {
+        const int n = h.n[r];
+        const double A = M_PI * h.rad[r] * h.rad[r];
+        const double I = M_PI * std::pow(h.rad[r], 4) / 4.0;
+        const double S1 = h.ac[r] * h.G[r] * A, S3 = h.E[r] * A;
+        const double B1 = h.E[r] * I, B3 = h.G[r] * 2.0 * I;
+        const double *lh = &h.lh[e];
+        for (int i = 0; i < n; ++i) {
+            const int64_t s = b->rod_slot[r] + i;
+            const double m = 0.5 * h.rho[r] * A * ((i > 0 ? lh[i - 1] : 0.0) + lh[i]);
+            param[rodk::P_INV_M * NS + s] = T(1.0 / m);
+            param[rodk::P_LH * NS + s] = T(lh[i]);
+            param[rodk::P_INV_LH * NS + s] = T(1.0 / lh[i]);
+            param[rodk::P_J1 * NS + s] = T(h.rho[r] * I * lh[i]);
+            param[rodk::P_S1 * NS + s] = T(S1);
+            param[rodk::P_S3 * NS + s] = T(S3);
+            if (i + 1 < n) {
+                const double Dh = 0.5 * (lh[i] + lh[i + 1]);
+                // rest-length weighted stiffness of the two elements (equal material here)
+                param[rodk::P_DH * NS + s] = T(Dh);
+                param[rodk::P_INV_DH * NS + s] = T(1.0 / Dh);
+                param[rodk::P_B1 * NS + s] = T((B1 * lh[i] + B1 * lh[i + 1]) / (lh[i] + lh[i + 1]));
+                param[rodk::P_B3 * NS + s] = T((B3 * lh[i] + B3 * lh[i + 1]) / (lh[i] + lh[i + 1]));
+                if (h.has_k0)
+                    for (int a = 0; a < 3; ++a) param[(rodk::P_K0X + a) * NS + s] = T(h.k0[3 * (v + i) + a]);
+            }
+        }
+        const double mt = 0.5 * h.rho[r] * A * lh[n - 1];
+        rodp[rodk::R_GAMMA * R + r] = T(h.gam[r]);
+        rodp[rodk::R_INV_M_TAIL * R + r] = T(1.0 / mt);
+        for (int a = 0; a < 3; ++a) {
+            rodp[(rodk::R_FX + a) * R + r] = T(h.fend[3 * r + a]);
+            rodp[(rodk::R_CX + a) * R + r] = T(h.camp[3 * r + a]);
+            rodp[(rodk::R_T0X + a) * R + r] = T(h.pos[3 * (nd + n) + a] - b->origin[3 * r + a]);
+        }
+        freq[r] = h.cfreq[r];
+        phase[r] = h.cphase[r];
+        flags[r] = (h.bc0[r] ? rodk::FLAG_CLAMP0 : 0) | (h.bc1[r] ? rodk::FLAG_CLAMP1 : 0)
+                 | ((h.has_c && (h.camp[3 * r] != 0 || h.camp[3 * r + 1] != 0 || h.camp[3 * r + 2] != 0))
+                        ? rodk::FLAG_COUPLE : 0);
+        e += n;
+        v += n - 1;
+        nd += n + 1;
+    }
+    // ---- integer tables
+    std::vector<int32_t> ints((size_t)2 * NS + 4 * R, 0);
+    std::copy(b->slot_rod.begin(), b->slot_rod.end(), ints.begin());
+    std::copy(b->slot_idx.begin(), b->slot_idx.end(), ints.begin() + NS);
+    std::copy(h.n.begin(), h.n.end(), ints.begin() + 2 * NS);
+    std::copy(flags.begin(), flags.end(), ints.begin() + 2 * NS + R);
+    std::copy(b->rod_slot.begin(), b->rod_slot.end(), ints.begin() + 2 * NS + 2 * R);
+    // ---- device allocations
+    const size_t es = sizeof(T);
+    HIPCHK(hipMalloc(&b->d_state, (size_t)rodk::N_STATE * NS * es));
+    HIPCHK(hipMalloc(&b->d_param, (size_t)rodk::N_PARAM * NS * es));
+    HIPCHK(hipMalloc(&b->d_tail, (size_t)rodk::N_TAIL * R * es));
+    HIPCHK(hipMalloc(&b->d_rodp, (size_t)rodk::N_RODP * R * es));
+    HIPCHK(hipMalloc((void **)&b->d_freq, (size_t)R * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&b->d_phase, (size_t)R * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&b->d_energy, (size_t)5 * R * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&b->d_ints, ints.size() * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&b->d_step, sizeof(int64_t)));
+    HIPCHK(hipMemcpy(b->d_param, param.data(), param.size() * es, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_rodp, rodp.data(), rodp.size() * es, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_freq, freq.data(), R * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_phase, phase.data(), R * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_ints, ints.data(), ints.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const int64_t zero = 0;
+    HIPCHK(hipMemcpy(b->d_step, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    int rc = upload_state<T>(b, h.pos.data(), h.vel.data(), h.dir.data(), h.om.data());
+    if (rc) return rc;
+    return ROD_OK;
+}
+
+void free_graphs(rod_batch *b)
+{
+    for (auto &kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    b->graphs.clear();
+}
+
+int enqueue_steps(rod_batch *b, int64_t n_steps, hipStream_t s)
+{
+    const int64_t S = b->substeps > 0 ? b->substeps : n_steps;
+    for (int64_t done = 0; done < n_steps; done += S) {
+        const int n_sub = (int)std::min<int64_t>(S, n_steps - done);
+        hipError_t e = b->precision == ROD_F32 ? rodk::launch_step(b->b32, b->waves, n_sub, b->grid, s)
+                                               : rodk::launch_step(b->b64, b->waves, n_sub, b->grid, s);
+        if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+        e = rodk::launch_advance(b->d_step, n_sub, s);
+        if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("advance launch: ") + hipGetErrorString(e));
+    }
+    return ROD_OK;
+}
+
+int check_flags(rod_batch *b, hipStream_t s, std::vector<int32_t> *out = nullptr)
+{
+    std::vector<int32_t> f(b->R);
+    int32_t *dflags = b->d_ints + 2 * b->n_slots + 3 * b->R;
+    HIPCHK(hipMemcpyAsync(f.data(), dflags, b->R * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (out) *out = f;
+    for (int r = 0; r < b->R; ++r)
+        if (f[r]) return fail(ROD_ENONFINITE, "rod " + std::to_string(r) + " has a non-finite state");
+    return ROD_OK;
+}
+
+template <typename T>
+int download_state(rod_batch *b, hipStream_t s, double *pos, double *vel, double *dir, double *om)
+{
+    constexpr bool EDGE = sizeof(T) == 4;
+    const int64_t NS = b->n_slots;
+    const int R = b->R;
+    std::vector<T> state((size_t)rodk::N_STATE * NS), tail((size_t)rodk::N_TAIL * R);
+    HIPCHK(hipMemcpyAsync(state.data(), b->d_state, state.size() * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(tail.data(), b->d_tail, tail.size() * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t e = 0, nd = 0;
+    for (int r = 0; r < R; ++r) {
+        const int n = b->n[r];
+        const double *o = &b->origin[3 * r];
+        double x[3];
+        if (EDGE)   // node 0, then accumulate the edges in FP64
+            for (int a = 0; a < 3; ++a) x[a] = (double)tail[(rodk::TRX + a) * R + r] + o[a];
+        for (int i = 0; i < n; ++i) {
+            const int64_t sl = b->rod_slot[r] + i;
+            for (int a = 0; a < 3; ++a) {
+                if (pos) {
+                    if (EDGE) {
+                        pos[3 * (nd + i) + a] = x[a];
+                        x[a] += (double)state[(rodk::RX + a) * NS + sl];
+                    } else {
+                        pos[3 * (nd + i) + a] = (double)state[(rodk::RX + a) * NS + sl] + o[a];
+                    }
+                }
+                if (vel) vel[3 * (nd + i) + a] = (double)state[(rodk::VX + a) * NS + sl];
+                if (om) om[3 * (e + i) + a] = (double)state[(rodk::WX + a) * NS + sl];
+            }
+            if (dir)
+                for (int k = 0; k < 9; ++k) dir[9 * (e + i) + k] = (double)state[(rodk::Q00 + k) * NS + sl];
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (pos) pos[3 * (nd + n) + a] = EDGE ? x[a] : (double)tail[(rodk::TRX + a) * R + r] + o[a];
+            if (vel) vel[3 * (nd + n) + a] = (double)tail[(rodk::TVX + a) * R + r];
+        }
+        e += n;
+        nd += n + 1;
+    }
+    return ROD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rod_last_error(void) { return g_err.c_str(); }
+
+int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
+{
+    g_err.clear();
+    if (!out) return fail(ROD_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(d);
+    if (rc) return rc;
+    HostInputs h;
+    if ((rc = gather_inputs(d, h))) return rc;
+    if ((rc = check_values(h))) return rc;
+    (void)stream;
+
+    auto *b = new (std::nothrow) rod_batch();
+    if (!b) return fail(ROD_ENOMEM, "host allocation failed");
+    b->precision = d->precision;
+    b->substeps = d->substeps;
+    b->R = d->n_rods;
+    b->n = h.n;
+    b->dt = d->dt;
+    b->t0 = d->t0;
+    b->use_graphs = std::getenv("ROD_NO_GRAPH") == nullptr;
+    int nmax = 0;
+    for (int r = 0; r < b->R; ++r) {
+        nmax = std::max(nmax, h.n[r]);
+        b->Ne += h.n[r];
+    }
+    b->Nn = b->Ne + b->R;
+    int waves = d->tile_waves;
+    const int need = (nmax + 63) / 64;
+    if (waves == 0) {
+        waves = 1;
+        while (waves < need) waves *= 2;
+    }
+    if (waves < need) {
+        delete b;
+        return fail(ROD_EUNSUPPORTED, "tile_waves " + std::to_string(waves) + " cannot hold a rod of "
+                                          + std::to_string(nmax) + " elements");
+    }
+    b->waves = waves;
+    pack_tiles(h.n, 64 * waves, b->rod_slot, b->n_tiles);
+    b->n_slots = (int64_t)b->n_tiles * 64 * waves;
+    b->slot_rod.assign(b->n_slots, -1);
+    b->slot_idx.assign(b->n_slots, 0);
+    for (int r = 0; r < b->R; ++r)
+        for (int i = 0; i < h.n[r]; ++i) {
+            b->slot_rod[b->rod_slot[r] + i] = r;
+            b->slot_idx[b->rod_slot[r] + i] = i;
+        }
+    // rod origins (FP32 keeps positions relative to the first node)
+    b->origin.assign(3 * b->R, 0.0);
+    b->bc0 = h.bc0;
+    b->bc1 = h.bc1;
+    b->clamp_r0.assign(3 * b->R, 0.0);
+    b->clamp_rn.assign(3 * b->R, 0.0);
+    b->clamp_q0.assign(9 * b->R, 0.0);
+    b->clamp_qn.assign(9 * b->R, 0.0);
+    {
+        int64_t e = 0, nd = 0;
+        for (int r = 0; r < b->R; ++r) {
+            const int n = h.n[r];
+            for (int a = 0; a < 3; ++a) {
+                if (b->precision == ROD_F32) b->origin[3 * r + a] = h.pos[3 * nd + a];
+                b->clamp_r0[3 * r + a] = h.pos[3 * nd + a];
+                b->clamp_rn[3 * r + a] = h.pos[3 * (nd + n) + a];
+            }
+            for (int k = 0; k < 9; ++k) {
+                b->clamp_q0[9 * r + k] = h.dir[9 * e + k];
+                b->clamp_qn[9 * r + k] = h.dir[9 * (e + n - 1) + k];
+            }
+            e += n;
+            nd += n + 1;
+        }
+    }
+    rc = b->precision == ROD_F32 ? build_device<float>(b, h) : build_device<double>(b, h);
+    if (rc) {
+        rod_batch_destroy(b);
+        return rc;
+    }
+    fill_dev(b->b64, b);
+    fill_dev(b->b32, b);
+    b->grid = b->n_tiles;
+    hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        rod_batch_destroy(b);
+        return fail(ROD_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    const double dts = stability_dt(h);
+    if (d->dt > dts) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "warning: dt %.3g exceeds the explicit stability estimate %.3g", d->dt, dts);
+        g_err = buf;
+    }
+    *out = b;
+    return ROD_OK;
+}
+
+int rod_step(rod_batch *b, int64_t n_steps, void *stream)
+{
+    if (!b) return fail(ROD_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(ROD_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return ROD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!b->use_graphs) {
+        int rc = enqueue_steps(b, n_steps, s);
+        if (rc) return rc;
+        b->steps += n_steps;
+        return ROD_OK;
+    }
+    auto it = b->graphs.find(n_steps);
+    if (it == b->graphs.end()) {
+        if (b->graphs.size() >= 16) free_graphs(b);
+        HIPCHK(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_steps(b, n_steps, b->capture_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(ROD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t x = nullptr;
+        ec = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (ec != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(ROD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+        }
+        it = b->graphs.emplace(n_steps, std::make_pair(g, x)).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second.second, s));
+    b->steps += n_steps;
+    return ROD_OK;
+}
+
+int rod_energy(rod_batch *b, double *out, void *stream)
+{
+    if (!b || !out) return fail(ROD_EINVAL, "handle or out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = b->precision == ROD_F32 ? rodk::launch_energy(b->b32, b->d_energy, s)
+                                           : rodk::launch_energy(b->b64, b->d_energy, s);
+    if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("energy launch: ") + hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(out, b->d_energy, (size_t)5 * b->R * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return check_flags(b, s);
+}
+
+int rod_get_state(rod_batch *b, double *pos, double *vel, double *dir, double *om, double *t, void *stream)
+{
+    if (!b) return fail(ROD_EINVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = b->precision == ROD_F32 ? download_state<float>(b, s, pos, vel, dir, om)
+                                     : download_state<double>(b, s, pos, vel, dir, om);
+    if (rc) return rc;
+    if (t) *t = b->t0 + (double)b->steps * b->dt;
+    return check_flags(b, s);
+}
+
+int rod_set_state(rod_batch *b, const double *pos, const double *vel, const double *dir, const double *om,
+                  double t, void *stream)
+{
+    if (!b) return fail(ROD_EINVAL, "handle is NULL");
+    if (!std::isfinite(t)) return fail(ROD_EINVAL, "t must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(s));
+    // fields left NULL keep their current values
+    std::vector<double> cp(3 * b->Nn), cv(3 * b->Nn), cd(9 * b->Ne), co(3 * b->Ne);
+    int rc = b->precision == ROD_F32 ? download_state<float>(b, s, cp.data(), cv.data(), cd.data(), co.data())
+                                     : download_state<double>(b, s, cp.data(), cv.data(), cd.data(), co.data());
+    if (rc) return rc;
+    const double *P = pos ? pos : cp.data(), *V = vel ? vel : cv.data();
+    const double *D = dir ? dir : cd.data(), *O = om ? om : co.data();
+    rc = b->precision == ROD_F32 ? upload_state<float>(b, P, V, D, O) : upload_state<double>(b, P, V, D, O);
+    if (rc) return rc;
+    int32_t *dflags = b->d_ints + 2 * b->n_slots + 3 * b->R;
+    HIPCHK(hipMemset(dflags, 0, b->R * sizeof(int32_t)));
+    const int64_t zero = 0;
+    HIPCHK(hipMemcpy(b->d_step, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    b->t0 = t;
+    b->steps = 0;
+    fill_dev(b->b64, b);
+    fill_dev(b->b32, b);
+    free_graphs(b);   // captured launches hold the old t0
+    return ROD_OK;
+}
+
+int rod_get_flags(rod_batch *b, int32_t *nonfinite, void *stream)
+{
+    if (!b || !nonfinite) return fail(ROD_EINVAL, "handle or out is NULL");
+    std::vector<int32_t> f;
+    int rc = check_flags(b, (hipStream_t)stream, &f);
+    if (rc && rc != ROD_ENONFINITE) return rc;
+    std::memcpy(nonfinite, f.data(), b->R * sizeof(int32_t));
+    return ROD_OK;
+}
+
+int rod_batch_info(const rod_batch *b, int64_t *info)
+{
+    if (!b || !info) return fail(ROD_EINVAL, "handle or info is NULL");
+    info[0] = b->R;
+    info[1] = b->Ne;
+    info[2] = b->n_tiles;
+    info[3] = b->waves;
+    info[4] = b->substeps;
+    info[5] = b->precision;
+    info[6] = b->n_slots;
+    info[7] = b->steps;
+    return ROD_OK;
+}
+
+void rod_batch_destroy(rod_batch *b)
+{
+    if (!b) return;
+    free_graphs(b);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    (void)hipFree(b->d_state);
+    (void)hipFree(b->d_param);
+    (void)hipFree(b->d_tail);
+    (void)hipFree(b->d_rodp);
+    (void)hipFree(b->d_freq);
+    (void)hipFree(b->d_phase);
+    (void)hipFree(b->d_energy);
+    (void)hipFree(b->d_ints);
+    (void)hipFree(b->d_step);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+"""ctypes binding of librod.so (include/rod.h), argument marshalling only.
+
+Every step of the rod path runs in the library's HIP kernels; this module
+converts numpy arrays and torch streams to the boundary's plain pointers.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librod.so")
+
+ROD_OK, ROD_EINVAL, ROD_ENOMEM, ROD_EDEVICE, ROD_ENONFINITE, ROD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+ROD_F64, ROD_F32 = 0, 1
+ROD_MAX_ELEMS = 512
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class RodBatchDesc(C.Structure):
+    _fields_ = [
+        ("n_rods", C.c_int32),
+        ("n_elems", _ip),
+        ("position", _dp), ("velocity", _dp), ("director", _dp), ("omega", _dp),
+        ("rest_length", _dp), ("rest_kappa", _dp),
+        ("density", _dp), ("youngs", _dp), ("shear_modulus", _dp), ("radius", _dp),
+        ("shear_coeff", _dp), ("damping", _dp),
+        ("bc_start", _ip), ("bc_end", _ip),
+        ("end_force", _dp), ("couple_amp", _dp), ("couple_freq", _dp), ("couple_phase", _dp),
+        ("dt", C.c_double), ("t0", C.c_double),
+        ("precision", C.c_int32), ("substeps", C.c_int32), ("tile_waves", C.c_int32),
+        ("inputs_on_device", C.c_int32),
+    ]
+
+
+class RodError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rod error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load librod.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2605_13766_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.rod_batch_create.argtypes = [C.POINTER(RodBatchDesc), vp, C.POINTER(vp)]
+        L.rod_step.argtypes = [vp, C.c_int64, vp]
+        L.rod_energy.argtypes = [vp, _dp, vp]
+        L.rod_get_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, vp]
+        L.rod_set_state.argtypes = [vp, _dp, _dp, _dp, _dp, C.c_double, vp]
+        L.rod_get_flags.argtypes = [vp, _ip, vp]
+        L.rod_batch_info.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.rod_batch_destroy.argtypes = [vp]
+        L.rod_batch_destroy.restype = None
+        L.rod_last_error.restype = C.c_char_p
+        for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_get_state", "rod_set_state",
+                  "rod_get_flags", "rod_batch_info"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().rod_last_error().decode()
+
+
+def _check(rc):
+    if rc != ROD_OK:
+        raise RodError(rc, last_error())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    """A torch.cuda.Stream, a raw integer handle or None (the null stream)."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _p(a, t=_dp):
+    return C.cast(a.ctypes.data, t) if a is not None else t()
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class RodBatch:
+    """A batch of rods resident on the GPU (owned by librod.so)."""
+
+    def __init__(self, inp, precision: str = "f64", substeps: int = 0, tile_waves: int = 0,
+                 t0: float = 0.0, stream=None):
+        self._h = None
+        prec = {"f64": ROD_F64, "f32": ROD_F32}[precision]
+        keep = {}
+
+        def arr(name, a, kind="d"):
+            if a is None:
+                return None
+            v = np.ascontiguousarray(a, dtype=np.float64 if kind == "d" else np.int32)
+            keep[name] = v
+            return v
+
+        d = RodBatchDesc()
+        n = arr("n", inp.n_elems, "i")
+        d.n_rods = int(n.shape[0])
+        d.n_elems = _p(n, _ip)
+        for name in ("position", "velocity", "director", "omega", "rest_length", "rest_kappa",
+                     "density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping",
+                     "end_force", "couple_amp", "couple_freq", "couple_phase"):
+            setattr(d, name, _p(arr(name, getattr(inp, name, None))))
+        for name in ("bc_start", "bc_end"):
+            setattr(d, name, _p(arr(name, getattr(inp, name, None), "i"), _ip))
+        d.dt = float(inp.dt)
+        d.t0 = float(t0)
+        d.precision = prec
+        d.substeps = int(substeps)
+        d.tile_waves = int(tile_waves)
+        d.inputs_on_device = 0
+        h = C.c_void_p()
+        _check(lib().rod_batch_create(C.byref(d), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self.warning = last_error()
+        self.precision = precision
+        self.n_elems = n.copy()
+        self.n_rods = d.n_rods
+        self.n_elements = int(n.sum())
+        self.n_nodes = self.n_elements + self.n_rods
+
+    # ------------------------------------------------------------ calls
+    def step(self, n_steps: int, stream=None):
+        _check(lib().rod_step(self._h, int(n_steps), _stream_ptr(stream)))
+
+    def energy(self, stream=None) -> np.ndarray:
+        out = np.empty((self.n_rods, 5))
+        _check(lib().rod_energy(self._h, _p(out), _stream_ptr(stream)))
+        return out
+
+    def get_state(self, stream=None):
+        pos = np.empty((self.n_nodes, 3))
+        vel = np.empty((self.n_nodes, 3))
+        dr = np.empty((self.n_elements, 3, 3))
+        om = np.empty((self.n_elements, 3))
+        t = C.c_double()
+        _check(lib().rod_get_state(self._h, _p(pos), _p(vel), _p(dr), _p(om), C.byref(t),
+                                   _stream_ptr(stream)))
+        return pos, vel, dr, om, t.value
+
+    def set_state(self, pos=None, vel=None, director=None, omega=None, t=0.0, stream=None):
+        arrs = [_f64(pos), _f64(vel), _f64(director), _f64(omega)]
+        _check(lib().rod_set_state(self._h, *[_p(a) for a in arrs], float(t), _stream_ptr(stream)))
+
+    def flags(self, stream=None) -> np.ndarray:
+        out = np.empty(self.n_rods, dtype=np.int32)
+        _check(lib().rod_get_flags(self._h, _p(out, _ip), _stream_ptr(stream)))
+        return out
+
+    def info(self) -> dict:
+        a = (C.c_int64 * 8)()
+        _check(lib().rod_batch_info(self._h, a))
+        keys = ("n_rods", "n_elements", "n_tiles", "tile_waves", "substeps", "precision", "n_slots",
+                "steps")
+        return dict(zip(keys, [int(x) for x in a]))
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.rod_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,95 @@
+"""The C boundary on the CPU: the library loads, exports every symbol that
+include/rod.h declares, and rejects invalid descriptors before touching the
+device (host-side validation only: no kernel runs here)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_13766_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rod_\w+)\s*\(", txt, flags=re.M))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_get_state", "rod_set_state",
+              "rod_get_flags", "rod_batch_destroy", "rod_last_error", "rod_batch_info"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2605_13766_amd import rod
+    L = rod.lib()
+    for name in sorted(declared_symbols()):
+        assert hasattr(L, name), name
+
+
+def _create(inp, **kw):
+    from paper_2605_13766_amd import rod
+    return rod.RodBatch(inp, **kw)
+
+
+def _expect(code, inp, **kw):
+    from paper_2605_13766_amd import rod
+    with pytest.raises(rod.RodError) as ei:
+        _create(inp, **kw)
+    assert ei.value.code == code, str(ei.value)
+    return str(ei.value)
+
+
+def test_invalid_descriptors_rejected():
+    from paper_2605_13766_amd import rod
+    base = W.ragged_batch(n_rods=3, n_min=16, n_max=20, seed=41)
+    bad = base.copy(); bad.n_elems = bad.n_elems.copy(); bad.n_elems[0] = 0
+    bad.position = bad.position[:-1]
+    _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.dt = 0.0
+    assert "dt" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.youngs[1] = -1.0
+    _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.damping[0] = -0.1
+    _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.director[5, 0, 0] += 1e-6
+    assert "SO(3)" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.director[2] = -bad.director[2]          # det = -1
+    assert "SO(3)" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.position[3] = bad.position[2]            # zero-length element
+    assert "zero length" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.rest_length = np.full(base.n_elements, 0.01); bad.rest_length[4] = 0.0
+    _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.couple_amp = np.ones((3, 3))              # no frequency / phase
+    _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.bc_start = np.array([0, 2, 0], np.int32)
+    _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.velocity[0, 0] = np.nan
+    _expect(rod.ROD_EINVAL, bad)
+    _expect(rod.ROD_EINVAL, base, tile_waves=3)
+    _expect(rod.ROD_EINVAL, base, substeps=-1)
+    long_rod = W.ragged_batch(n_rods=1, n_min=600, n_max=600, seed=43)
+    assert "outside" in _expect(rod.ROD_EINVAL, long_rod)
+
+
+def test_tile_too_small_unsupported():
+    from paper_2605_13766_amd import rod
+    inp = W.ragged_batch(n_rods=2, n_min=100, n_max=120, seed=45)
+    _expect(rod.ROD_EUNSUPPORTED, inp, tile_waves=1)
+
+
+def test_null_handle_calls():
+    from paper_2605_13766_amd import rod
+    L = rod.lib()
+    assert L.rod_step(None, 10, None) == rod.ROD_EINVAL
+    assert L.rod_batch_info(None, None) == rod.ROD_EINVAL
+    L.rod_batch_destroy(None)
