@@ -1,7 +1,8 @@
 """Build librod.so (HIP for gfx950) in-tree with hipcc.
 
 Every HIP translation unit is compiled with packed-FP32 instruction
-selection turned off.  Run as ``python -m paper_2605_13766_amd.build``.
+selection turned off and with FMA contraction limited to single source
+expressions.  Run as ``python -m paper_2605_13766_amd.build``.
 """
 from __future__ import annotations
 
@@ -20,6 +21,9 @@ ARCH = "gfx950"
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c only inside one source expression: the same FMAs in every
+    # tile-width instantiation, so results do not depend on the launch shape
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 
@@ -33,26 +37,27 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link librod.so; returns its path."""
+def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
+    """Compile every source and link librod.so (or `out`); returns its path.
+    `defines` are extra -D macros (tuning variants)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build", "x".join(defines).replace("=", "") or "default")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, "-x", "hip", "-I", INCLUDE, "-I", CSRC, "-c",
+        cmd = [hipcc(), *HIP_FLAGS, *[f"-D{d}" for d in defines], "-x", "hip", "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

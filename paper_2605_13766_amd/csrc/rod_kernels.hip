@@ -3,11 +3,13 @@
 // Mapping: one lane per element.  A workgroup of 64*W lanes owns a tile of
 // whole rods laid out on consecutive lanes; lane i of a rod holds node i
 // (v, and r in FP64) and element i (Q, omega, and the edge r_{i+1} - r_i in
-// FP32); the rod's last lane also holds node n.
-// Each launch loads its tiles' state once, runs `n_sub` position-Verlet
-// substeps with the state in registers, and stores it once.  The two-point
-// stencils of the difference and averaging operators read the neighbour
-// lane's values through LDS (three exchanges per substep, four in FP32).
+// FP32); the rod's last lane also holds node n.  Each launch loads its
+// tiles' state once, runs `n_sub` position-Verlet substeps with the state in
+// registers, and stores it once.  The two-point stencils of the difference
+// and averaging operators take the neighbour lane's values by DPP wave
+// shifts (wave_shl:1 / wave_shr:1, full-rate VALU moves); only values that
+// cross a wave boundary of a multi-wave tile go through LDS, behind one
+// barrier per exchange.
 //
 // Model: Elastica++, Methods, "Cosserat rod dynamics", Eq. 1a (linear
 // momentum) and Eq. 1b (angular momentum) on the staggered grid of nodes,
@@ -18,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <cstdint>
 
 namespace rodk {
 
@@ -42,6 +45,108 @@ __device__ inline float dcos(float x) { return cosf(x); }
 __device__ inline double datan2(double y, double x) { return atan2(y, x); }
 __device__ inline float datan2(float y, float x) { return atan2f(y, x); }
 
+// 1/sqrt(x) and 1/x from the hardware estimates (24 correct bits in both
+// precisions); FP64 adds two Newton steps (24 -> 48 -> full precision).
+__device__ inline double rsqrt_t(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    h = x * y;
+    return fma(0.5 * y, fma(-h, y, 1.0), y);
+}
+__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rcp_t(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ inline float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// DPP wave shifts: lane i reads lane i+1 (SHL) or lane i-1 (SHR) of its
+// wave; the wave's edge lane reads zero.
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ inline float dpp(float x)
+{
+    const int v = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ inline double dpp(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const uint32_t rlo = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
+    const uint32_t rhi = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)rhi << 32) | rlo);
+}
+
+// Neighbour exchange inside a tile of W waves.  `from_right` gives every
+// lane the values of lane + 1, `from_left` those of lane - 1.  Called by all
+// lanes (full EXEC).  For W > 1 the wave-edge values go through `lds`
+// ([W][N]) behind one barrier.
+template <int W, int N, typename T>
+__device__ __forceinline__ void from_right(const T (&v)[N], T (&out)[N], T *lds, int wave, int wl)
+{
+    if constexpr (W > 1) {
+        if (wl == 0) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) lds[wave * N + k] = v[k];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = dpp<DPP_WAVE_SHL1>(v[k]);
+    if constexpr (W > 1) {
+        if (wl == 63 && wave + 1 < W) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k] = lds[(wave + 1) * N + k];
+        }
+    }
+}
+
+template <int W, int N, typename T>
+__device__ __forceinline__ void from_left(const T (&v)[N], T (&out)[N], T *lds, int wave, int wl)
+{
+    if constexpr (W > 1) {
+        if (wl == 63) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) lds[wave * N + k] = v[k];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = dpp<DPP_WAVE_SHR1>(v[k]);
+    if constexpr (W > 1) {
+        if (wl == 0 && wave > 0) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k] = lds[(wave - 1) * N + k];
+        }
+    }
+}
+
+// Large-angle paths, kept out of line: they run only when a rod turns by more
+// than ~0.1 rad in half a step or bends by more than ~0.06 rad between two
+// elements, and inlining them would reserve their registers in the hot loop.
+template <typename T>
+__device__ __attribute__((noinline)) void rodrigues_coefs_general(T x, T &a, T &b)
+{
+    const T t = dsqrt(x);
+    a = dsin(t) / t;
+    b = (T(1) - dcos(t)) / x;
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) T log_factor_general(T s2, T c)
+{
+    const T s = dsqrt(s2);
+    return datan2(s, c) / s;
+}
+
 // q <- exp([u]x) q for a row-major director matrix q (rows d1, d2, d3).
 // exp([u]x) = I + a [u]x + b [u]x^2 with a = sin(t)/t, b = (1 - cos t)/t^2,
 // t = |u|; both are even series in t^2, used for small t.  [u]x acts on the
@@ -50,17 +155,11 @@ template <typename T>
 __device__ inline void rotate_left(T q[9], T ux, T uy, T uz)
 {
     const T x = ux * ux + uy * uy + uz * uz;
-    T a, b;
-    if (x < Coef<T>::rot_series_max) {
-        // sin(t)/t = 1 - x/3! + x^2/5! - x^3/7! + x^4/9!
-        a = T(1) + x * (T(-1.0 / 6) + x * (T(1.0 / 120) + x * (T(-1.0 / 5040) + x * T(1.0 / 362880))));
-        // (1-cos t)/t^2 = 1/2! - x/4! + x^2/6! - x^3/8! + x^4/10!
-        b = T(0.5) + x * (T(-1.0 / 24) + x * (T(1.0 / 720) + x * (T(-1.0 / 40320) + x * T(1.0 / 3628800))));
-    } else {
-        const T t = dsqrt(x);
-        a = dsin(t) / t;
-        b = (T(1) - dcos(t)) / x;
-    }
+    // sin(t)/t = 1 - x/3! + x^2/5! - x^3/7! + x^4/9!
+    T a = T(1) + x * (T(-1.0 / 6) + x * (T(1.0 / 120) + x * (T(-1.0 / 5040) + x * T(1.0 / 362880))));
+    // (1-cos t)/t^2 = 1/2! - x/4! + x^2/6! - x^3/8! + x^4/10!
+    T b = T(0.5) + x * (T(-1.0 / 24) + x * (T(1.0 / 720) + x * (T(-1.0 / 40320) + x * T(1.0 / 3628800))));
+    if (x >= Coef<T>::rot_series_max) rodrigues_coefs_general(x, a, b);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const T c0 = q[j], c1 = q[3 + j], c2 = q[6 + j];
@@ -78,30 +177,24 @@ __device__ inline void rotate_left(T q[9], T ux, T uy, T uz)
 
 // Rotation vector of R = qa qb^T (rows of qa against rows of qb):
 // w = ax(R) = sin(t) k, c = (tr R - 1)/2 = cos(t), result = (t / |w|) w.
-// t/|w| = asin(s)/s with s = |w| when c > 0, an even series in s^2.
+// t/|w| = asin(s)/s with s = |w| when c > 0, an even series in s^2.  Lanes
+// with `use` false (no Voronoi point) take the series value at s = 0, so an
+// unrelated neighbour frame never sends them down the large-angle path.
 template <typename T>
-__device__ inline void log_relative(const T qa[9], const T qb[9], T &u0, T &u1, T &u2)
+__device__ inline void log_relative(const T qa[9], const T qb[9], bool use, T &u0, T &u1, T &u2)
 {
-    T R[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            R[3 * a + b] = qa[3 * a] * qb[3 * b] + qa[3 * a + 1] * qb[3 * b + 1] + qa[3 * a + 2] * qb[3 * b + 2];
-    const T w0 = T(0.5) * (R[7] - R[5]);
-    const T w1 = T(0.5) * (R[2] - R[6]);
-    const T w2 = T(0.5) * (R[3] - R[1]);
-    const T c = T(0.5) * (R[0] + R[4] + R[8] - T(1));
-    const T s2 = w0 * w0 + w1 * w1 + w2 * w2;
-    T f;
-    if (c > T(0) && s2 < Coef<T>::log_series_max) {
-        // asin(s)/s = sum_k (2k)! / (4^k (k!)^2 (2k+1)) s^(2k)
-        f = T(1) + s2 * (T(1.0 / 6) + s2 * (T(3.0 / 40) + s2 * (T(5.0 / 112) + s2 * (T(35.0 / 1152)
-              + s2 * (T(63.0 / 2816) + s2 * (T(231.0 / 13312) + s2 * T(143.0 / 10240)))))));
-    } else {
-        const T s = dsqrt(s2);
-        f = datan2(s, c) / s;
-    }
+    auto dot = [&](int a, int b) {
+        return qa[3 * a] * qb[3 * b] + qa[3 * a + 1] * qb[3 * b + 1] + qa[3 * a + 2] * qb[3 * b + 2];
+    };
+    const T w0 = T(0.5) * (dot(2, 1) - dot(1, 2));
+    const T w1 = T(0.5) * (dot(0, 2) - dot(2, 0));
+    const T w2 = T(0.5) * (dot(1, 0) - dot(0, 1));
+    const T c = use ? T(0.5) * (dot(0, 0) + dot(1, 1) + dot(2, 2) - T(1)) : T(1);
+    const T s2 = use ? w0 * w0 + w1 * w1 + w2 * w2 : T(0);
+    // asin(s)/s = sum_k (2k)! / (4^k (k!)^2 (2k+1)) s^(2k)
+    T f = T(1) + s2 * (T(1.0 / 6) + s2 * (T(3.0 / 40) + s2 * (T(5.0 / 112) + s2 * (T(35.0 / 1152)
+            + s2 * (T(63.0 / 2816) + s2 * (T(231.0 / 13312) + s2 * T(143.0 / 10240)))))));
+    if (!(c > T(0) && s2 < Coef<T>::log_series_max)) f = log_factor_general(s2, c);
     u0 = f * w0;
     u1 = f * w1;
     u2 = f * w2;
@@ -123,23 +216,44 @@ __device__ inline bool finite3(T a, T b, T c)
 // which is the same update in exact arithmetic but keeps the strains at
 // FP32 relative precision (absolute FP32 positions would round each drift
 // increment against the rod's whole length).
+//
+// Inside a launch the closing half drift of one step and the opening half
+// drift of the next use the same velocities, so they run as one full drift
+// (exp(-h/2 W) exp(-h/2 W) = exp(-h W) for one axis): a launch of S steps is
+// half drift, S kicks separated by S-1 full drifts, half drift.
+#ifndef ROD_F64_WAVES_PER_SIMD
+#define ROD_F64_WAVES_PER_SIMD 2
+#endif
+#ifndef ROD_F32_WAVES_PER_SIMD
+#define ROD_F32_WAVES_PER_SIMD 4
+#endif
+
 template <typename T, int W>
-__global__ __launch_bounds__(64 * W) void rod_step_kernel(const DevBatch<T> B, int n_sub)
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? ROD_F64_WAVES_PER_SIMD : ROD_F32_WAVES_PER_SIMD)))
+void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
-    constexpr int TL = 64 * W;
     constexpr bool EDGE = sizeof(T) == 4;
-    constexpr int NX1 = EDGE ? 9 : 15;
-    __shared__ T xa[NX1][TL + 1];          // from the right: (r, v,) Q
-    __shared__ T xb[TL + 1];               // from the right: current length
-    __shared__ T xc[9][TL + 1];            // from the left: n, M, y
-    __shared__ T xd[EDGE ? 3 : 1][TL + 1]; // from the right: post-kick v (edge form)
+    constexpr int TL = 64 * W;
+    constexpr int NX1 = EDGE ? 9 : 15;     // from the right: Q (, r, v)
+    constexpr int NL = W > 1 ? W : 1;
+    __shared__ T lx1[NL * NX1];            // wave-edge values of the four exchanges
+    __shared__ T lx2[NL];
+    __shared__ T lx3[NL * 9];
+    __shared__ T lx4[NL * 3];
+    // lane-private constants (each lane reads back only its own column, so no
+    // barrier is needed): a register extension for values used once a substep
+    enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
+           C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, N_C };
+    __shared__ T cst[N_C * TL];
+    __shared__ double phs[2 * TL];   // couple phase increment: sin, cos
 
     const int lane = threadIdx.x;
+    const int wave = lane >> 6, wl = lane & 63;
     const int64_t NS = B.n_slots;
     const int64_t step0 = *B.step;
     const T h = T(B.dt);
     const T hh = T(0.5 * B.dt);
-    const int left = lane > 0 ? lane - 1 : 0;
 
     for (int tile = blockIdx.x; tile < B.n_tiles; tile += gridDim.x) {
         const int64_t s = (int64_t)tile * TL + lane;
@@ -154,6 +268,11 @@ __global__ __launch_bounds__(64 * W) void rod_step_kernel(const DevBatch<T> B, i
         const bool first = i == 0;
         const bool fix0 = first && (flags & FLAG_CLAMP0);
         const bool fix1 = last && (flags & FLAG_CLAMP1);
+        // kinematic constraints as kick factors: a clamped node or element
+        // starts at rest and never receives an increment
+        const T hv = fix0 ? T(0) : h;
+        const T hw = (fix0 || fix1) ? T(0) : h;
+        const T hu = fix1 ? T(0) : h;
 
         // ---- state: r0..2 is node i's position (FP64) or element i's edge (FP32);
         // t0..2 is node n's position (FP64, last lane) or node 0's (FP32, first lane)
@@ -171,85 +290,102 @@ __global__ __launch_bounds__(64 * W) void rod_step_kernel(const DevBatch<T> B, i
         if (last) {
             u0 = B.tail[TVX * B.n_rods + rr]; u1 = B.tail[TVY * B.n_rods + rr]; u2 = B.tail[TVZ * B.n_rods + rr];
         }
-        // ---- constants
+        // ---- constants: hot ones in registers, the rest in this lane's LDS column
         const T *pp = B.param + s;
         const T inv_m = pp[P_INV_M * NS], lh = pp[P_LH * NS], inv_lh = pp[P_INV_LH * NS];
-        const T J1 = pp[P_J1 * NS], S1 = pp[P_S1 * NS], S3 = pp[P_S3 * NS];
-        const T Dh = pp[P_DH * NS], inv_Dh = pp[P_INV_DH * NS], B1 = pp[P_B1 * NS], B3 = pp[P_B3 * NS];
-        const T k00 = pp[P_K0X * NS], k01 = pp[P_K0Y * NS], k02 = pp[P_K0Z * NS];
-        const T J3 = T(2) * J1;
-        const T inv_J1 = T(1) / J1, inv_J3 = T(1) / J3;
-        const T gamma = B.rodp[R_GAMMA * B.n_rods + rr];
-        T inv_mt = 0, f0 = 0, f1 = 0, f2 = 0;
-        if (last) {
-            inv_mt = B.rodp[R_INV_M_TAIL * B.n_rods + rr];
-            f0 = B.rodp[R_FX * B.n_rods + rr]; f1 = B.rodp[R_FY * B.n_rods + rr]; f2 = B.rodp[R_FZ * B.n_rods + rr];
-        }
-        // distributed couple amplitude times rest length; its time factor
-        // sin(2 pi f t + phi) at the substep midpoints by rotation recurrence
-        T c0 = 0, c1 = 0, c2 = 0;
-        double ps = 0.0, pc = 1.0, ds = 0.0, dc = 1.0;
-        if (valid && (flags & FLAG_COUPLE)) {
-            c0 = B.rodp[R_CX * B.n_rods + rr] * lh;
-            c1 = B.rodp[R_CY * B.n_rods + rr] * lh;
-            c2 = B.rodp[R_CZ * B.n_rods + rr] * lh;
-            const double fr = B.rod_freq[rr];
-            const double ph = 2.0 * M_PI * fr * (B.t0 + ((double)step0 + 0.5) * B.dt) + B.rod_phase[rr];
-            ps = sin(ph);
-            pc = cos(ph);
-            const double dp = 2.0 * M_PI * fr * B.dt;
-            ds = sin(dp);
-            dc = cos(dp);
+        const T S1 = pp[P_S1 * NS], S3 = pp[P_S3 * NS];
+        double ps = 0.0, pc = 1.0;
+        {
+            T *cw = cst + lane;
+            const T J1 = pp[P_J1 * NS];
+            cw[C_J1 * TL] = J1;
+            cw[C_INV_J1 * TL] = T(1) / J1;
+            cw[C_DH * TL] = pp[P_DH * NS];
+            cw[C_INV_DH * TL] = pp[P_INV_DH * NS];
+            // no Voronoi point on the last element: zero stiffness there
+            cw[C_B1 * TL] = hasv ? pp[P_B1 * NS] : T(0);
+            cw[C_B3 * TL] = hasv ? pp[P_B3 * NS] : T(0);
+            cw[C_K0X * TL] = pp[P_K0X * NS];
+            cw[C_K0Y * TL] = pp[P_K0Y * NS];
+            cw[C_K0Z * TL] = pp[P_K0Z * NS];
+            cw[C_GAMMA * TL] = B.rodp[R_GAMMA * B.n_rods + rr];
+            cw[C_INV_MT * TL] = last ? B.rodp[R_INV_M_TAIL * B.n_rods + rr] : T(0);
+            cw[C_FX * TL] = last ? B.rodp[R_FX * B.n_rods + rr] : T(0);
+            cw[C_FY * TL] = last ? B.rodp[R_FY * B.n_rods + rr] : T(0);
+            cw[C_FZ * TL] = last ? B.rodp[R_FZ * B.n_rods + rr] : T(0);
+            // distributed couple amplitude times rest length; its time factor
+            // sin(2 pi f t + phi) at the substep midpoints by rotation recurrence
+            T c0 = 0, c1 = 0, c2 = 0;
+            double ds = 0.0, dc = 1.0;
+            if (valid && (flags & FLAG_COUPLE)) {
+                c0 = B.rodp[R_CX * B.n_rods + rr] * lh;
+                c1 = B.rodp[R_CY * B.n_rods + rr] * lh;
+                c2 = B.rodp[R_CZ * B.n_rods + rr] * lh;
+                const double fr = B.rod_freq[rr];
+                const double ph = 2.0 * M_PI * fr * (B.t0 + ((double)step0 + 0.5) * B.dt) + B.rod_phase[rr];
+                ps = sin(ph);
+                pc = cos(ph);
+                const double dp = 2.0 * M_PI * fr * B.dt;
+                ds = sin(dp);
+                dc = cos(dp);
+            }
+            cw[C_CX * TL] = c0;
+            cw[C_CY * TL] = c1;
+            cw[C_CZ * TL] = c2;
+            phs[lane] = ds;
+            phs[TL + lane] = dc;
         }
 
         // edge form: velocity of node i+1 (refreshed after every kick)
         T vn0 = 0, vn1 = 0, vn2 = 0;
         if constexpr (EDGE) {
-            xd[0][lane] = v0; xd[1][lane] = v1; xd[2][lane] = v2;
-            __syncthreads();
-            if (last) { vn0 = u0; vn1 = u1; vn2 = u2; }
-            else { vn0 = xd[0][lane + 1]; vn1 = xd[1][lane + 1]; vn2 = xd[2][lane + 1]; }
+            const T a4[3] = {v0, v1, v2};
+            T b4[3];
+            from_right<W>(a4, b4, lx4, wave, wl);
+            vn0 = last ? u0 : b4[0]; vn1 = last ? u1 : b4[1]; vn2 = last ? u2 : b4[2];
         }
 
+        // ---- opening half drift (constraints hold: clamped v, omega are zero)
+        if constexpr (EDGE) {
+            r0 += hh * (vn0 - v0); r1 += hh * (vn1 - v1); r2 += hh * (vn2 - v2);
+            t0 += hh * v0; t1 += hh * v1; t2 += hh * v2;
+        } else {
+            r0 += hh * v0; r1 += hh * v1; r2 += hh * v2;
+            t0 += hh * u0; t1 += hh * u1; t2 += hh * u2;
+        }
+        rotate_left(q, -hh * w0, -hh * w1, -hh * w2);
+
         for (int sub = 0; sub < n_sub; ++sub) {
-            // ---- half drift (constraints hold: clamped v, omega are zero)
-            if constexpr (EDGE) {
-                r0 += hh * (vn0 - v0); r1 += hh * (vn1 - v1); r2 += hh * (vn2 - v2);
-                t0 += hh * v0; t1 += hh * v1; t2 += hh * v2;
-            } else {
-                r0 += hh * v0; r1 += hh * v1; r2 += hh * v2;
-                t0 += hh * u0; t1 += hh * u1; t2 += hh * u2;
-            }
-            rotate_left(q, -hh * w0, -hh * w1, -hh * w2);
+            // the lane-private constants are re-read every substep: an opaque
+            // address keeps the compiler from hoisting them into registers
+            int cofs = lane;
+            asm volatile("" : "+v"(cofs));
+            const T *cl = cst + cofs;
+            const double *phl = phs + cofs;
 
             // ---- exchange 1: neighbour element (and node)
-            if constexpr (!EDGE) {
-                xa[9][lane] = r0; xa[10][lane] = r1; xa[11][lane] = r2;
-                xa[12][lane] = v0; xa[13][lane] = v1; xa[14][lane] = v2;
-            }
+            T a1[NX1], qn[NX1];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) xa[k][lane] = q[k];
-            __syncthreads();
+            for (int k = 0; k < 9; ++k) a1[k] = q[k];
+            if constexpr (!EDGE) {
+                a1[9] = r0; a1[10] = r1; a1[11] = r2;
+                a1[12] = v0; a1[13] = v1; a1[14] = v2;
+            }
+            from_right<W>(a1, qn, lx1, wave, wl);
             T d0, d1, d2;
             if constexpr (EDGE) {
                 d0 = r0; d1 = r1; d2 = r2;
             } else {
-                if (last) {
-                    d0 = t0 - r0; d1 = t1 - r1; d2 = t2 - r2;
-                    vn0 = u0; vn1 = u1; vn2 = u2;
-                } else {
-                    d0 = xa[9][lane + 1] - r0; d1 = xa[10][lane + 1] - r1; d2 = xa[11][lane + 1] - r2;
-                    vn0 = xa[12][lane + 1]; vn1 = xa[13][lane + 1]; vn2 = xa[14][lane + 1];
-                }
+                d0 = (last ? t0 : qn[9]) - r0;
+                d1 = (last ? t1 : qn[10]) - r1;
+                d2 = (last ? t2 : qn[11]) - r2;
+                vn0 = last ? u0 : qn[12]; vn1 = last ? u1 : qn[13]; vn2 = last ? u2 : qn[14];
             }
-            T qn[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) qn[k] = xa[k][lane + 1];
 
             // ---- kinematics and shear/stretch strain of element i
             const T l2 = d0 * d0 + d1 * d1 + d2 * d2;
-            const T l = dsqrt(l2);
-            const T inv_l = T(1) / l;
+            const T inv_l = rsqrt_t(l2);
+            const T l = l2 * inv_l;
             const T e = l * inv_lh;
             const T inv_e = lh * inv_l;
             const T edot = ((d0 * (vn0 - v0) + d1 * (vn1 - v1) + d2 * (vn2 - v2)) * inv_l) * inv_lh;
@@ -264,91 +400,95 @@ __global__ __launch_bounds__(64 * W) void rod_step_kernel(const DevBatch<T> B, i
             const T nf2 = (q[2] * ss0 + q[5] * ss1 + q[8] * ss2) * inv_e;
 
             // ---- exchange 2: neighbour length
-            xb[lane] = l;
-            __syncthreads();
-            const T ln = xb[lane + 1];
+            const T a2[1] = {l};
+            T b2[1];
+            from_right<W>(a2, b2, lx2, wave, wl);
+            const T ln = hasv ? b2[0] : l;
 
             // ---- curvature, bending/twisting moment at Voronoi point i
-            T M0 = 0, M1 = 0, M2 = 0, y0 = 0, y1 = 0, y2 = 0;
-            if (hasv) {
-                T k0, k1, k2;
-                log_relative(q, qn, k0, k1, k2);
-                k0 *= inv_Dh; k1 *= inv_Dh; k2 *= inv_Dh;
-                const T eps = (l + ln) * (T(0.5) * inv_Dh);
-                const T ie3 = T(1) / (eps * eps * eps);
-                M0 = B1 * (k0 - k00) * ie3;
-                M1 = B1 * (k1 - k01) * ie3;
-                M2 = B3 * (k2 - k02) * ie3;
-                y0 = (k1 * M2 - k2 * M1) * Dh;
-                y1 = (k2 * M0 - k0 * M2) * Dh;
-                y2 = (k0 * M1 - k1 * M0) * Dh;
-            }
+            // (zero stiffness on lanes without one)
+            T k0, k1, k2;
+            log_relative(q, qn, hasv, k0, k1, k2);
+            const T inv_Dh = cl[C_INV_DH * TL], Dh = cl[C_DH * TL];
+            k0 *= inv_Dh; k1 *= inv_Dh; k2 *= inv_Dh;
+            const T eps = (l + ln) * (T(0.5) * inv_Dh);
+            const T ie3 = rcp_t(eps * eps * eps);
+            const T M0 = cl[C_B1 * TL] * (k0 - cl[C_K0X * TL]) * ie3;
+            const T M1 = cl[C_B1 * TL] * (k1 - cl[C_K0Y * TL]) * ie3;
+            const T M2 = cl[C_B3 * TL] * (k2 - cl[C_K0Z * TL]) * ie3;
+            const T y0 = (k1 * M2 - k2 * M1) * Dh;
+            const T y1 = (k2 * M0 - k0 * M2) * Dh;
+            const T y2 = (k0 * M1 - k1 * M0) * Dh;
 
-            // ---- exchange 3: left neighbour's force and moments
-            xc[0][lane] = nf0; xc[1][lane] = nf1; xc[2][lane] = nf2;
-            xc[3][lane] = M0; xc[4][lane] = M1; xc[5][lane] = M2;
-            xc[6][lane] = y0; xc[7][lane] = y1; xc[8][lane] = y2;
-            __syncthreads();
-            T np0 = 0, np1 = 0, np2 = 0, Mp0 = 0, Mp1 = 0, Mp2 = 0, yp0 = 0, yp1 = 0, yp2 = 0;
-            if (!first) {
-                np0 = xc[0][left]; np1 = xc[1][left]; np2 = xc[2][left];
-                Mp0 = xc[3][left]; Mp1 = xc[4][left]; Mp2 = xc[5][left];
-                yp0 = xc[6][left]; yp1 = xc[7][left]; yp2 = xc[8][left];
-            }
+            // ---- exchange 3: left neighbour's force and moments.  A rod's
+            // first lane sits next to the previous rod's last lane, whose
+            // moments vanish, or at the wave edge (zero); only its force is
+            // masked.
+            const T a3[9] = {nf0, nf1, nf2, M0, M1, M2, y0, y1, y2};
+            T b3[9];
+            from_left<W>(a3, b3, lx3, wave, wl);
+            const T np0 = first ? T(0) : b3[0], np1 = first ? T(0) : b3[1], np2 = first ? T(0) : b3[2];
 
             // ---- Eq. 1a at node i (and node n on the last lane)
+            const T gamma = cl[C_GAMMA * TL];
             const T a0 = (nf0 - np0) * inv_m - gamma * v0;
-            const T a1 = (nf1 - np1) * inv_m - gamma * v1;
-            const T a2 = (nf2 - np2) * inv_m - gamma * v2;
+            const T a1x = (nf1 - np1) * inv_m - gamma * v1;
+            const T a2x = (nf2 - np2) * inv_m - gamma * v2;
 
             // ---- Eq. 1b at element i
             // Q t = (sigma + e3) / e
             const T qt0 = sg0 * inv_e, qt1 = sg1 * inv_e, qt2 = (sg2 + T(1)) * inv_e;
-            const T jw0 = J1 * w0 * inv_e, jw1 = J1 * w1 * inv_e, jw2 = J3 * w2 * inv_e;
+            const T J1 = cl[C_J1 * TL];
+            const T jw0 = J1 * w0 * inv_e, jw1 = J1 * w1 * inv_e, jw2 = T(2) * J1 * w2 * inv_e;
             const T ede = edot * inv_e;
-            const T tq0 = (M0 - Mp0) + T(0.5) * (yp0 + y0) + (qt1 * ss2 - qt2 * ss1) * lh
-                        + (jw1 * w2 - jw2 * w1) + jw0 * ede + c0 * T(ps);
-            const T tq1 = (M1 - Mp1) + T(0.5) * (yp1 + y1) + (qt2 * ss0 - qt0 * ss2) * lh
-                        + (jw2 * w0 - jw0 * w2) + jw1 * ede + c1 * T(ps);
-            const T tq2 = (M2 - Mp2) + T(0.5) * (yp2 + y2) + (qt0 * ss1 - qt1 * ss0) * lh
-                        + (jw0 * w1 - jw1 * w0) + jw2 * ede + c2 * T(ps);
-            const T al0 = e * inv_J1 * tq0 - gamma * w0;
-            const T al1 = e * inv_J1 * tq1 - gamma * w1;
-            const T al2 = e * inv_J3 * tq2 - gamma * w2;
+            const T cs = T(ps);
+            const T tq0 = (M0 - b3[3]) + T(0.5) * (b3[6] + y0) + (qt1 * ss2 - qt2 * ss1) * lh
+                        + (jw1 * w2 - jw2 * w1) + jw0 * ede + cl[C_CX * TL] * cs;
+            const T tq1 = (M1 - b3[4]) + T(0.5) * (b3[7] + y1) + (qt2 * ss0 - qt0 * ss2) * lh
+                        + (jw2 * w0 - jw0 * w2) + jw1 * ede + cl[C_CY * TL] * cs;
+            const T tq2 = (M2 - b3[5]) + T(0.5) * (b3[8] + y2) + (qt0 * ss1 - qt1 * ss0) * lh
+                        + (jw0 * w1 - jw1 * w0) + jw2 * ede + cl[C_CZ * TL] * cs;
+            const T eJ = e * cl[C_INV_J1 * TL];
+            const T al0 = eJ * tq0 - gamma * w0;
+            const T al1 = eJ * tq1 - gamma * w1;
+            const T al2 = T(0.5) * eJ * tq2 - gamma * w2;
 
-            // ---- kick, then constraints
-            v0 += h * a0; v1 += h * a1; v2 += h * a2;
-            w0 += h * al0; w1 += h * al1; w2 += h * al2;
-            if (last) {
-                u0 += h * ((f0 - nf0) * inv_mt - gamma * u0);
-                u1 += h * ((f1 - nf1) * inv_mt - gamma * u1);
-                u2 += h * ((f2 - nf2) * inv_mt - gamma * u2);
+            // ---- kick (clamped nodes/elements have zero kick factors)
+            v0 += hv * a0; v1 += hv * a1x; v2 += hv * a2x;
+            w0 += hw * al0; w1 += hw * al1; w2 += hw * al2;
+            {
+                const T inv_mt = cl[C_INV_MT * TL];
+                u0 += hu * ((cl[C_FX * TL] - nf0) * inv_mt - gamma * u0);
+                u1 += hu * ((cl[C_FY * TL] - nf1) * inv_mt - gamma * u1);
+                u2 += hu * ((cl[C_FZ * TL] - nf2) * inv_mt - gamma * u2);
             }
-            if (fix0) { v0 = v1 = v2 = 0; w0 = w1 = w2 = 0; }
-            if (fix1) { u0 = u1 = u2 = 0; w0 = w1 = w2 = 0; }
 
             // ---- edge form: exchange 4, the post-kick velocity of node i+1
             if constexpr (EDGE) {
-                xd[0][lane] = v0; xd[1][lane] = v1; xd[2][lane] = v2;
-                __syncthreads();
-                if (last) { vn0 = u0; vn1 = u1; vn2 = u2; }
-                else { vn0 = xd[0][lane + 1]; vn1 = xd[1][lane + 1]; vn2 = xd[2][lane + 1]; }
+                const T a4[3] = {v0, v1, v2};
+                T b4[3];
+                from_right<W>(a4, b4, lx4, wave, wl);
+                vn0 = last ? u0 : b4[0]; vn1 = last ? u1 : b4[1]; vn2 = last ? u2 : b4[2];
             }
 
-            // ---- second half drift
+            // ---- drift: full between two kicks of this launch, half after the last
+            const T dd = sub + 1 < n_sub ? h : hh;
             if constexpr (EDGE) {
-                r0 += hh * (vn0 - v0); r1 += hh * (vn1 - v1); r2 += hh * (vn2 - v2);
-                t0 += hh * v0; t1 += hh * v1; t2 += hh * v2;
+                r0 += dd * (vn0 - v0); r1 += dd * (vn1 - v1); r2 += dd * (vn2 - v2);
+                t0 += dd * v0; t1 += dd * v1; t2 += dd * v2;
             } else {
-                r0 += hh * v0; r1 += hh * v1; r2 += hh * v2;
-                t0 += hh * u0; t1 += hh * u1; t2 += hh * u2;
+                r0 += dd * v0; r1 += dd * v1; r2 += dd * v2;
+                t0 += dd * u0; t1 += dd * u1; t2 += dd * u2;
             }
-            rotate_left(q, -hh * w0, -hh * w1, -hh * w2);
+            rotate_left(q, -dd * w0, -dd * w1, -dd * w2);
 
             // advance the couple's phase by one step
-            const double nps = ps * dc + pc * ds;
-            pc = pc * dc - ps * ds;
-            ps = nps;
+            {
+                const double ds = phl[0], dc = phl[TL];
+                const double nps = ps * dc + pc * ds;
+                pc = pc * dc - ps * ds;
+                ps = nps;
+            }
         }
 
         if (valid) {
@@ -370,7 +510,7 @@ __global__ __launch_bounds__(64 * W) void rod_step_kernel(const DevBatch<T> B, i
             }
             if (!ok) B.nonfinite[rr] = 1;
         }
-        __syncthreads();   // LDS reuse by the next tile
+        if constexpr (W > 1) __syncthreads();   // LDS reuse by the next tile
     }
 }
 
@@ -429,7 +569,7 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out)
         if (i > 0) {
             const int64_t sv = s - 1;   // Voronoi point i-1 lives on slot i-1
             double k0, k1, k2;
-            log_relative(qprev, q, k0, k1, k2);
+            log_relative(qprev, q, true, k0, k1, k2);
             const double iD = P(P_INV_DH, sv);
             k0 = k0 * iD - P(P_K0X, sv);
             k1 = k1 * iD - P(P_K0Y, sv);

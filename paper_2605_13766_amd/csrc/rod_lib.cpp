@@ -313,11 +313,15 @@ void pack_state(const rod_batch *b, const double *pos, const double *vel, const 
     const int R = b->R;
     state.assign((size_t)rodk::N_STATE * NS, T(0));
     tail.assign((size_t)rodk::N_TAIL * R, T(0));
-    for (int64_t s = 0; s < NS; ++s) {   // padding: identity frames, unit edges
+    // padding lanes: identity frames and unit-length elements (positions one
+    // apart along z, or unit edges), so they stay finite and at rest and never
+    // feed NaN/Inf to a neighbouring rod through the lane exchanges
+    const int TL = 64 * b->waves;
+    for (int64_t s = 0; s < NS; ++s) {
         state[rodk::Q00 * NS + s] = T(1);
         state[rodk::Q11 * NS + s] = T(1);
         state[rodk::Q22 * NS + s] = T(1);
-        if (EDGE) state[rodk::RZ * NS + s] = T(1);
+        state[rodk::RZ * NS + s] = EDGE ? T(1) : T(1 + s % TL);
     }
     std::vector<double> x;
     int64_t e = 0, nd = 0;
@@ -395,7 +399,11 @@ int build_device(rod_batch *b, const HostInputs &h)
             param[rodk::P_J1 * NS + s] = T(h.rho[r] * I * lh[i]);
             param[rodk::P_S1 * NS + s] = T(S1);
             param[rodk::P_S3 * NS + s] = T(S3);
-            if (i + 1 < n) {
+            if (i + 1 == n) {
+                // no Voronoi point here: finite placeholders (its stiffness is zero)
+                param[rodk::P_DH * NS + s] = T(lh[i]);
+                param[rodk::P_INV_DH * NS + s] = T(1.0 / lh[i]);
+            } else {
                 const double Dh = 0.5 * (lh[i] + lh[i + 1]);
                 // rest-length weighted stiffness of the two elements (equal material here)
                 param[rodk::P_DH * NS + s] = T(Dh);

@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librod.so")
+LIB_PATH = os.environ.get("ROD_LIBRARY") or os.path.join(HERE, "librod.so")
 
 ROD_OK, ROD_EINVAL, ROD_ENOMEM, ROD_EDEVICE, ROD_ENONFINITE, ROD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ROD_F64, ROD_F32 = 0, 1
