@@ -1,0 +1,35 @@
+// Private declarations of the surrogate MLP kernels (mlp_kernels.hip) used by
+// the host runtime (surrogate.cpp).  Not part of the public boundary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mlpk {
+
+enum Epilogue { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_DSILU = 3 };
+
+struct GemmArgs {
+    const void *A;          // see the launcher for layout and type
+    const void *B;
+    int64_t lda, ldb, ldc;
+    int M, N, K;
+    float *C;               // FP32 output (pre-activation, dZ or plain product)
+    const float *bias;      // [N] for EPI_BIAS / EPI_BIAS_SILU
+    __bf16 *act;            // [M][ldc] BF16 SiLU output for EPI_BIAS_SILU
+    const float *zsave;     // [M][ldc] pre-activation for EPI_DSILU
+};
+
+hipError_t gemm_forward(const GemmArgs &g, int epi, hipStream_t s);
+hipError_t gemm_backward_data(const GemmArgs &g, int epi, hipStream_t s);
+hipError_t gemm_backward_weight(const GemmArgs &g, hipStream_t s);
+hipError_t mse_grad(const float *Y, const float *T, const float *mask, float *dY, float *partial,
+                    int64_t M, int n_out, int ld, hipStream_t s);
+int mse_partials(int64_t M, int ld);
+hipError_t sum_partials(const float *partial, int n, float scale, float *out, hipStream_t s);
+hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, hipStream_t s);
+hipError_t adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
+                float eps, int64_t t, hipStream_t s);
+hipError_t to_bf16(const float *src, __bf16 *dst, int64_t n, hipStream_t s);
+
+}  // namespace mlpk

@@ -1,0 +1,295 @@
+// mlp_kernels.hip -- gfx950 kernels of the surrogate's per-element MLP:
+// a tiled BF16 MFMA GEMM (v_mfma_f32_16x16x32_bf16, FP32 accumulate) with
+// fused epilogues, the MSE gradient, bias-gradient column sums and Adam.
+//
+// Network: F_in -> 256 -> 256 -> 256 -> 12 (padded to 16 columns), SiLU after
+// the first three layers, BF16 weights and activations, FP32 bias, FP32
+// pre-activations kept for the backward pass.
+#include "mlp_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+
+namespace mlpk {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline float to_f(__bf16 x) { return (float)x; }
+__device__ inline float to_f(float x) { return x; }
+
+__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu_f(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+}  // namespace
+
+// C[M x N] = A[M x K] * B[K x N] with A stored [M][K] (or [K][M] when AT) and
+// B stored [K][N] (or [N][K] when BT); inputs of type TA / TB are rounded to
+// BF16 when staged in LDS.  One 256-thread workgroup computes a 64 x 64 tile,
+// each wave a 32 x 32 quarter as 2 x 2 MFMA blocks; K advances 32 per stage.
+// Edges in M, N and K are zero-filled on load and masked on store.
+template <bool AT, bool BT, typename TA, typename TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
+{
+    constexpr int BM = 64, BN = 64, BK = 32, PAD = 8;
+    __shared__ __bf16 As[BM][BK + PAD];   // [m][k]
+    __shared__ __bf16 Bs[BN][BK + PAD];   // [n][k]
+    const TA *A = (const TA *)g.A;
+    const TB *B = (const TB *)g.B;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        // ---- stage A (64 x 32); rows past M and columns past K read as zero
+        if (!AT) {
+            const int r = t >> 2, kc = (t & 3) * 8;
+            const int m = m0 + r;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k0 + kc + j;
+                As[r][kc + j] = (__bf16)(m < g.M && k < g.K ? to_f(A[(int64_t)m * g.lda + k]) : 0.f);
+            }
+        } else {
+            const int kr = t >> 3, mc = (t & 7) * 8;
+            const int k = k0 + kr;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int m = m0 + mc + j;
+                As[mc + j][kr] = (__bf16)(m < g.M && k < g.K ? to_f(A[(int64_t)k * g.lda + m]) : 0.f);
+            }
+        }
+        // ---- stage B (32 x 64), stored transposed as [n][k]
+        if (!BT) {
+            const int kr = t >> 3, nc = (t & 7) * 8;
+            const int k = k0 + kr;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int n = n0 + nc + j;
+                Bs[nc + j][kr] = (__bf16)(n < g.N && k < g.K ? to_f(B[(int64_t)k * g.ldb + n]) : 0.f);
+            }
+        } else {
+            const int r = t >> 2, kc = (t & 3) * 8;
+            const int n = n0 + r;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k0 + kc + j;
+                Bs[r][kc + j] = (__bf16)(n < g.N && k < g.K ? to_f(B[(int64_t)n * g.ldb + k]) : 0.f);
+            }
+        }
+        __syncthreads();
+        bf16x8 af[2], bfr[2];
+        const int q = lane >> 4, c = lane & 15;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                af[i][j] = As[wm + 16 * i + c][8 * q + j];
+                bfr[i][j] = Bs[wn + 16 * i + c][8 * q + j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+
+    // ---- epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each block
+    const int q = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + 4 * q + r;
+                const int n = n0 + wn + 16 * j + c;
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[i][j][r];
+                const int64_t o = (int64_t)m * g.ldc + n;
+                if (EPI == EPI_STORE) {
+                    g.C[o] = v;
+                } else if (EPI == EPI_BIAS) {
+                    g.C[o] = v + g.bias[n];
+                } else if (EPI == EPI_BIAS_SILU) {
+                    const float z = v + g.bias[n];
+                    g.C[o] = z;                          // pre-activation, for backward
+                    g.act[o] = (__bf16)silu_f(z);        // next layer's input
+                } else if (EPI == EPI_DSILU) {
+                    g.C[o] = v * dsilu_f(g.zsave[o]);    // dZ = dA * silu'(Z)
+                }
+            }
+}
+
+// dY = 2 * mask * (Y - T) / count for the first n_out columns (0 on padding),
+// and per-block partial sums of mask * (Y - T)^2.
+__global__ void mse_grad_kernel(const float *Y, const float *T, const float *mask, float *dY,
+                                float *partial, int64_t M, int n_out, int ld, float inv_count)
+{
+    __shared__ float red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float s = 0.f;
+    if (i < M * ld) {
+        const int64_t row = i / ld;
+        const int col = (int)(i % ld);
+        float d = 0.f;
+        if (col < n_out) {
+            const float mk = mask ? mask[row * n_out + col] : 1.f;
+            const float e = Y[i] - T[row * n_out + col];
+            d = 2.f * mk * e * inv_count;
+            s = mk * e * e;
+        }
+        dY[i] = d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out[0] = sum(partial[0..n)) * scale (one block).
+__global__ void sum_kernel(const float *partial, int n, float scale, float *out)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] * scale;
+}
+
+// db[n] = sum_m dZ[m][n], one block per column.
+__global__ void colsum_kernel(const float *dZ, int64_t M, int ld, float *db)
+{
+    __shared__ float red[256];
+    const int n = blockIdx.x;
+    float s = 0.f;
+    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) s += dZ[m * ld + n];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = red[0];
+}
+
+// Adam (Kingma & Ba): m, v, w in FP32; bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ void adam_kernel(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 copies of the FP32 master weights.
+__global__ void to_bf16_kernel(const float *src, __bf16 *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (__bf16)src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <bool AT, bool BT, typename TA, typename TB, int EPI>
+static hipError_t launch_t(const GemmArgs &g, hipStream_t s)
+{
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    hipLaunchKernelGGL((gemm_kernel<AT, BT, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t gemm_forward(const GemmArgs &g, int epi, hipStream_t s)
+{
+    // A = activations bf16 [M][K], B = W bf16 [K][N]
+    switch (epi) {
+    case EPI_BIAS_SILU: return launch_t<false, false, __bf16, __bf16, EPI_BIAS_SILU>(g, s);
+    case EPI_BIAS: return launch_t<false, false, __bf16, __bf16, EPI_BIAS>(g, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gemm_backward_data(const GemmArgs &g, int epi, hipStream_t s)
+{
+    // C[M][K_l] = dZ f32 [M][N_l] * W^T, W bf16 stored [K_l][N_l] = [N_gemm][K_gemm]
+    switch (epi) {
+    case EPI_DSILU: return launch_t<false, true, float, __bf16, EPI_DSILU>(g, s);
+    case EPI_STORE: return launch_t<false, true, float, __bf16, EPI_STORE>(g, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gemm_backward_weight(const GemmArgs &g, hipStream_t s)
+{
+    // C[K_l][N_l] = act^T * dZ: act bf16 stored [M][K_l] = [K_gemm][M_gemm], dZ f32 [M][N_l]
+    return launch_t<true, false, __bf16, float, EPI_STORE>(g, s);
+}
+
+hipError_t mse_grad(const float *Y, const float *T, const float *mask, float *dY, float *partial,
+                    int64_t M, int n_out, int ld, hipStream_t s)
+{
+    const int64_t n = M * ld;
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks), dim3(256), 0, s, Y, T, mask, dY, partial, M, n_out, ld,
+                       1.0f / (float)(M * n_out));
+    return hipGetLastError();
+}
+
+int mse_partials(int64_t M, int ld) { return (int)((M * ld + 255) / 256); }
+
+hipError_t sum_partials(const float *partial, int n, float scale, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, partial, n, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, hipStream_t s)
+{
+    hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, s, dZ, M, ld, db);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
+                float eps, int64_t t, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1,
+                       b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *src, __bf16 *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace mlpk

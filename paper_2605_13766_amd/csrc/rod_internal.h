@@ -4,8 +4,12 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <string>
 
 namespace rodk {
+
+// Record the message returned by rod_last_error() for this thread; returns code.
+int set_error(int code, const std::string &msg);
 
 // Per-slot state fields.  A slot is one lane of a workgroup tile; slot s of a
 // rod holds its node s (r, v) and its element s (Q, omega).  The rod's last

@@ -63,6 +63,12 @@ int fetch(std::vector<X> &dst, const X *src, size_t count, bool on_device)
 
 }  // namespace
 
+int rodk::set_error(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
 struct rod_batch {
     int precision = ROD_F64;
     int waves = 1;

@@ -39,6 +39,13 @@ class RodBatchDesc(C.Structure):
     ]
 
 
+class SurrogateDesc(C.Structure):
+    _fields_ = [("k_substeps", C.c_int32), ("seed", C.c_uint64), ("max_rows", C.c_int32)]
+
+
+SURROGATE_INPUTS, SURROGATE_OUTPUTS, SURROGATE_PARAMS = 96, 12, 159500
+
+
 class RodError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"rod error {code}: {msg}")
@@ -68,6 +75,18 @@ def lib():
         L.rod_last_error.restype = C.c_char_p
         for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_get_state", "rod_set_state",
                   "rod_get_flags", "rod_batch_info"):
+            getattr(L, f).restype = C.c_int
+        fp = C.POINTER(C.c_float)
+        L.rod_surrogate_create.argtypes = [C.POINTER(SurrogateDesc), C.POINTER(vp)]
+        L.rod_surrogate_destroy.argtypes = [vp]
+        L.rod_surrogate_destroy.restype = None
+        L.rod_surrogate_set_params.argtypes = [vp, fp]
+        L.rod_surrogate_get_params.argtypes = [vp, fp]
+        L.rod_surrogate_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.rod_surrogate_gradients.argtypes = [vp, vp, vp, vp, C.c_int64, fp, fp, vp]
+        L.rod_surrogate_train_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_float, fp, vp]
+        for f in ("rod_surrogate_create", "rod_surrogate_set_params", "rod_surrogate_get_params",
+                  "rod_surrogate_forward", "rod_surrogate_gradients", "rod_surrogate_train_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -179,6 +198,69 @@ class RodBatch:
     def close(self):
         if self._h is not None and _lib is not None:
             _lib.rod_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(int(t.data_ptr()))
+
+
+class Surrogate:
+    """The learned coarse step's network (owned by librod.so)."""
+
+    def __init__(self, k_substeps: int = 32, seed: int = 0, max_rows: int = 0):
+        d = SurrogateDesc(int(k_substeps), int(seed), int(max_rows))
+        h = C.c_void_p()
+        _check(lib().rod_surrogate_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.k = int(k_substeps)
+
+    def set_params(self, flat):
+        v = np.ascontiguousarray(flat, dtype=np.float32)
+        assert v.size == SURROGATE_PARAMS
+        _check(lib().rod_surrogate_set_params(self._h, v.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_params(self) -> np.ndarray:
+        v = np.empty(SURROGATE_PARAMS, dtype=np.float32)
+        _check(lib().rod_surrogate_get_params(self._h, v.ctypes.data_as(C.POINTER(C.c_float))))
+        return v
+
+    def forward(self, x_bf16, y_f32, stream=None):
+        """x: torch bfloat16 [M, 96] on the GPU; y: torch float32 [M, 12] on the GPU."""
+        _check(lib().rod_surrogate_forward(self._h, _dptr(x_bf16), int(x_bf16.shape[0]), _dptr(y_f32),
+                                           _stream_ptr(stream)))
+
+    def gradients(self, x_bf16, t_f32, mask_f32=None, stream=None):
+        g = np.empty(SURROGATE_PARAMS, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().rod_surrogate_gradients(self._h, _dptr(x_bf16), _dptr(t_f32), _dptr(mask_f32),
+                                             int(x_bf16.shape[0]), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                             C.byref(loss), _stream_ptr(stream)))
+        return g, loss.value
+
+    def train_step(self, x_bf16, t_f32, mask_f32=None, lr=1e-3, stream=None):
+        loss = C.c_float()
+        _check(lib().rod_surrogate_train_step(self._h, _dptr(x_bf16), _dptr(t_f32), _dptr(mask_f32),
+                                              int(x_bf16.shape[0]), float(lr), C.byref(loss),
+                                              _stream_ptr(stream)))
+        return loss.value
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.rod_surrogate_destroy(self._h)
         self._h = None
 
     def __del__(self):
