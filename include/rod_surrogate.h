@@ -66,6 +66,64 @@ int rod_surrogate_gradients(rod_surrogate *s, const void *x_bf16, const float *t
 int rod_surrogate_train_step(rod_surrogate *s, const void *x_bf16, const float *t, const float *mask,
                              int64_t M, float lr, float *loss, void *stream);
 
+/*
+ * Windows and the data path (FP32 batches only: ROD_EUNSUPPORTED otherwise).
+ * A rod of n elements has n + 1 windows, rod-major: window w < n is centred on
+ * element w and targets node w and element w; window n is centred on element
+ * n - 1 and targets node n.  With tau = k dt and lh_c the centre element's
+ * rest length, everything in the centre element's frame Q_c:
+ *   96 features = 5 stencil slots (elements c-2..c+2) x 16
+ *     [Q_c (x_j - x_c)/lh_c, Q_c (u_j - u_c) tau/lh_c, rows 0-1 of Q_j Q_c^T,
+ *      omega_j tau, 1]   (x midpoint, u mean node velocity; zeros off the rod)
+ *   + 16 globals [Q_c v_p tau/lh_c, Q_c (r_p - x_c)/lh_c, log10(E/1e6),
+ *      radius/lh_c, log10(tau/T_b) with T_b = lh_c^2 sqrt(rho A/(E I)),
+ *      alpha_c, clamped-base flag, c/n, end flag, couple amplitude / 1e-5,
+ *      sin and cos of the couple phase];
+ *   12 targets = [Q_c dr_p/lh_c, Q_c dv_p tau/lh_c, theta with
+ *      Q_c(t+tau) = exp(-[theta]x) Q_c(t), d omega_c tau]; the element part of
+ *   window n is masked.
+ */
+
+/* Raw FP32 features [W][96] of the batch's current state (device buffer). */
+int rod_surrogate_features(rod_surrogate *s, rod_batch *b, float *features, void *stream);
+
+/* Training sample at the current state: features [W][96], then k plain steps
+ * of the batch (rod_step), then targets [W][12] and the loss mask [W][12]
+ * (device buffers). */
+int rod_surrogate_collect(rod_surrogate *s, rod_batch *b, float *features, float *targets, float *mask,
+                          void *stream);
+
+/* Apply raw deltas [W][12] (device) to the batch as one coarse step and
+ * advance its clock by k steps.  Clamped ends are left unchanged. */
+int rod_surrogate_apply(rod_surrogate *s, rod_batch *b, const float *deltas, void *stream);
+
+/* Standardisation of inputs and outputs (host arrays: 96, 96, 12, 12 values;
+ * standard deviations > 0): the network sees (x - mu_x)/sd_x and predicts
+ * (t - mu_t)/sd_t. */
+int rod_surrogate_set_normalization(rod_surrogate *s, const float *mu_x, const float *sd_x, const float *mu_t,
+                                    const float *sd_t);
+int rod_surrogate_get_normalization(rod_surrogate *s, float *mu_x, float *sd_x, float *mu_t, float *sd_t);
+
+typedef struct {
+    int32_t warmup_steps;    /* plain steps before the first sample */
+    int32_t n_samples;       /* collect() calls; all windows of the batch each time */
+    int32_t sample_stride;   /* plain steps from one sample's start to the next (>= k) */
+    int32_t epochs;
+    int32_t batch_rows;      /* minibatch rows: a multiple of 64, <= max_rows */
+    float lr;                /* peak learning rate, cosine decay to lr_min over all steps */
+    float lr_min;
+    float val_fraction;      /* share of windows held out for validation */
+    uint64_t seed;           /* shuffling */
+} rod_train_desc;
+
+/* Generate trajectories with the plain integrator on `b` (advancing it),
+ * standardise, and train the network with Adam on minibatches.  Host
+ * outputs: epoch_loss[epochs] (mean training loss per epoch, may be NULL) and
+ * *val_loss (loss on the held-out windows after training, may be NULL).
+ * Synchronises `stream`. */
+int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d, float *epoch_loss,
+                        float *val_loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

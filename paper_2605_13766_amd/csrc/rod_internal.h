@@ -6,6 +6,9 @@
 #include <cstdint>
 #include <string>
 
+struct rod_batch;
+typedef struct rod_batch rod_batch_opaque;
+
 namespace rodk {
 
 // Record the message returned by rod_last_error() for this thread; returns code.
@@ -84,5 +87,24 @@ hipError_t launch_energy(const DevBatch<double> &b, double *out, hipStream_t s);
 hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s);
 // Largest number of co-resident workgroups of the step kernel (occupancy x CUs).
 int step_resident_groups(int precision_f32, int waves);
+
+// Read access to a batch for the surrogate runtime (rod_lib.cpp).
+struct BatchView {
+    int precision;
+    int waves;
+    int32_t n_rods;
+    int64_t n_elems, n_slots;
+    const int32_t *n;          // host [R]
+    const int32_t *rod_slot;   // host [R]
+    const double *youngs, *shear_modulus, *density, *radius, *shear_coeff;   // host [R]
+    const double *couple_amp, *couple_freq, *couple_phase;                    // host [R][3], [R], [R]
+    const int32_t *bc_start, *bc_end;                                         // host [R]
+    double dt, time;           // step and current time
+    DevBatch<float> f32;       // device pointers (FP32 batches)
+    size_t state_bytes, tail_bytes;
+};
+int batch_view(const rod_batch_opaque *b, BatchView *v);
+// Advance the batch's clock by n steps without stepping (the learned coarse step).
+int batch_advance_clock(rod_batch_opaque *b, int64_t n, hipStream_t s);
 
 }  // namespace rodk

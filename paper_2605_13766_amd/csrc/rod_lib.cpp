@@ -85,6 +85,7 @@ struct rod_batch {
     // clamped ends: creation values of node 0 / element 0 and node n / element n-1
     std::vector<int32_t> bc0, bc1;
     std::vector<double> clamp_r0, clamp_q0, clamp_rn, clamp_qn;   // [R][3], [R][9]
+    std::vector<double> E, G, rho, rad, ac, camp, cfreq, cphase;  // per-rod inputs kept for the surrogate
     // device
     void *d_state = nullptr, *d_param = nullptr, *d_tail = nullptr, *d_rodp = nullptr;
     double *d_freq = nullptr, *d_phase = nullptr, *d_energy = nullptr;
@@ -548,6 +549,42 @@ int download_state(rod_batch *b, hipStream_t s, double *pos, double *vel, double
 
 }  // namespace
 
+int rodk::batch_view(const rod_batch *b, BatchView *v)
+{
+    if (!b || !v) return fail(ROD_EINVAL, "batch is NULL");
+    v->precision = b->precision;
+    v->waves = b->waves;
+    v->n_rods = b->R;
+    v->n_elems = b->Ne;
+    v->n_slots = b->n_slots;
+    v->n = b->n.data();
+    v->rod_slot = b->rod_slot.data();
+    v->youngs = b->E.data();
+    v->shear_modulus = b->G.data();
+    v->density = b->rho.data();
+    v->radius = b->rad.data();
+    v->shear_coeff = b->ac.data();
+    v->couple_amp = b->camp.data();
+    v->couple_freq = b->cfreq.data();
+    v->couple_phase = b->cphase.data();
+    v->bc_start = b->bc0.data();
+    v->bc_end = b->bc1.data();
+    v->dt = b->dt;
+    v->time = b->t0 + (double)b->steps * b->dt;
+    v->f32 = b->b32;
+    v->state_bytes = (size_t)rodk::N_STATE * b->n_slots * elem_bytes(b);
+    v->tail_bytes = (size_t)rodk::N_TAIL * b->R * elem_bytes(b);
+    return ROD_OK;
+}
+
+int rodk::batch_advance_clock(rod_batch *b, int64_t n, hipStream_t s)
+{
+    hipError_t e = rodk::launch_advance(b->d_step, n, s);
+    if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("advance: ") + hipGetErrorString(e));
+    b->steps += n;
+    return ROD_OK;
+}
+
 extern "C" {
 
 const char *rod_last_error(void) { return g_err.c_str(); }
@@ -604,6 +641,14 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->origin.assign(3 * b->R, 0.0);
     b->bc0 = h.bc0;
     b->bc1 = h.bc1;
+    b->E = h.E;
+    b->G = h.G;
+    b->rho = h.rho;
+    b->rad = h.rad;
+    b->ac = h.ac;
+    b->camp = h.camp;
+    b->cfreq = h.cfreq;
+    b->cphase = h.cphase;
     b->clamp_r0.assign(3 * b->R, 0.0);
     b->clamp_rn.assign(3 * b->R, 0.0);
     b->clamp_q0.assign(9 * b->R, 0.0);

@@ -46,6 +46,12 @@ class SurrogateDesc(C.Structure):
 SURROGATE_INPUTS, SURROGATE_OUTPUTS, SURROGATE_PARAMS = 96, 12, 159500
 
 
+class TrainDesc(C.Structure):
+    _fields_ = [("warmup_steps", C.c_int32), ("n_samples", C.c_int32), ("sample_stride", C.c_int32),
+                ("epochs", C.c_int32), ("batch_rows", C.c_int32), ("lr", C.c_float), ("lr_min", C.c_float),
+                ("val_fraction", C.c_float), ("seed", C.c_uint64)]
+
+
 class RodError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"rod error {code}: {msg}")
@@ -85,8 +91,17 @@ def lib():
         L.rod_surrogate_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.rod_surrogate_gradients.argtypes = [vp, vp, vp, vp, C.c_int64, fp, fp, vp]
         L.rod_surrogate_train_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_float, fp, vp]
+        L.rod_surrogate_features.argtypes = [vp, vp, vp, vp]
+        L.rod_surrogate_collect.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.rod_surrogate_apply.argtypes = [vp, vp, vp, vp]
+        L.rod_surrogate_set_normalization.argtypes = [vp, fp, fp, fp, fp]
+        L.rod_surrogate_get_normalization.argtypes = [vp, fp, fp, fp, fp]
+        L.rod_surrogate_train.argtypes = [vp, vp, C.POINTER(TrainDesc), fp, fp, vp]
         for f in ("rod_surrogate_create", "rod_surrogate_set_params", "rod_surrogate_get_params",
-                  "rod_surrogate_forward", "rod_surrogate_gradients", "rod_surrogate_train_step"):
+                  "rod_surrogate_forward", "rod_surrogate_gradients", "rod_surrogate_train_step",
+                  "rod_surrogate_features", "rod_surrogate_collect", "rod_surrogate_apply",
+                  "rod_surrogate_set_normalization", "rod_surrogate_get_normalization",
+                  "rod_surrogate_train"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -257,6 +272,40 @@ class Surrogate:
                                               int(x_bf16.shape[0]), float(lr), C.byref(loss),
                                               _stream_ptr(stream)))
         return loss.value
+
+    # ---------------------------------------------------------- data path
+    @staticmethod
+    def n_windows(batch) -> int:
+        return int(batch.n_elements + batch.n_rods)
+
+    def features(self, batch, out_f32, stream=None):
+        _check(lib().rod_surrogate_features(self._h, batch._h, _dptr(out_f32), _stream_ptr(stream)))
+
+    def collect(self, batch, feat, targ, mask, stream=None):
+        _check(lib().rod_surrogate_collect(self._h, batch._h, _dptr(feat), _dptr(targ), _dptr(mask),
+                                           _stream_ptr(stream)))
+
+    def apply(self, batch, deltas, stream=None):
+        _check(lib().rod_surrogate_apply(self._h, batch._h, _dptr(deltas), _stream_ptr(stream)))
+
+    def set_normalization(self, mu_x, sd_x, mu_t, sd_t):
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (mu_x, sd_x, mu_t, sd_t)]
+        _check(lib().rod_surrogate_set_normalization(self._h, *[x.ctypes.data_as(C.POINTER(C.c_float)) for x in a]))
+
+    def get_normalization(self):
+        a = [np.empty(n, dtype=np.float32) for n in (96, 96, 12, 12)]
+        _check(lib().rod_surrogate_get_normalization(self._h, *[x.ctypes.data_as(C.POINTER(C.c_float)) for x in a]))
+        return a
+
+    def train(self, batch, warmup_steps=0, n_samples=2, sample_stride=None, epochs=2, batch_rows=4096,
+              lr=1e-3, lr_min=1e-5, val_fraction=0.1, seed=0, stream=None):
+        d = TrainDesc(int(warmup_steps), int(n_samples), int(sample_stride or self.k), int(epochs),
+                      int(batch_rows), float(lr), float(lr_min), float(val_fraction), int(seed))
+        ep = np.empty(int(epochs), dtype=np.float32)
+        vl = C.c_float()
+        _check(lib().rod_surrogate_train(self._h, batch._h, C.byref(d), ep.ctypes.data_as(C.POINTER(C.c_float)),
+                                         C.byref(vl), _stream_ptr(stream)))
+        return ep, vl.value
 
     def close(self):
         if self._h is not None and _lib is not None:
