@@ -79,9 +79,11 @@ int rod_surrogate_train_step(rod_surrogate *s, const void *x_bf16, const float *
  *      radius/lh_c, log10(tau/T_b) with T_b = lh_c^2 sqrt(rho A/(E I)),
  *      alpha_c, clamped-base flag, c/n, end flag, couple amplitude / 1e-5,
  *      sin and cos of the couple phase];
- *   12 targets = [Q_c dr_p/lh_c, Q_c dv_p tau/lh_c, theta with
- *      Q_c(t+tau) = exp(-[theta]x) Q_c(t), d omega_c tau]; the element part of
- *   window n is masked.
+ *   12 targets, the departures from free flight over tau (constant node
+ *      velocity and element angular velocity) = [Q_c (dr_p - v_p tau)/lh_c,
+ *      Q_c dv_p tau/lh_c, theta - omega_c tau with Q_c(t+tau) =
+ *      exp(-[theta]x) Q_c(t), d omega_c tau]; the element part of window n is
+ *      masked.  Applying deltas adds the free flight back.
  */
 
 /* Raw FP32 features [W][96] of the batch's current state (device buffer). */
@@ -94,7 +96,9 @@ int rod_surrogate_collect(rod_surrogate *s, rod_batch *b, float *features, float
                           void *stream);
 
 /* Apply raw deltas [W][12] (device) to the batch as one coarse step and
- * advance its clock by k steps.  Clamped ends are left unchanged. */
+ * advance its clock by k steps: free flight plus the deltas, then each
+ * rotated director frame is moved to its nearest rotation (one Newton-Schulz
+ * polar step).  Clamped ends are left unchanged. */
 int rod_surrogate_apply(rod_surrogate *s, rod_batch *b, const float *deltas, void *stream);
 
 /* Standardisation of inputs and outputs (host arrays: 96, 96, 12, 12 values;
@@ -123,6 +127,51 @@ typedef struct {
  * Synchronises `stream`. */
 int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d, float *epoch_loss,
                         float *val_loss, void *stream);
+
+/*
+ * The learned coarse step with the plain integrator as judge and fallback.
+ * Each coarse step: features of every window, the network, and the predicted
+ * deltas applied to every rod not on the plain step (the clock advances by
+ * k steps); rods on the plain step take k plain steps instead.  Every
+ * judge_every coarse steps a seeded sample of judge_fraction of the rods
+ * (at least one) that are still on the coarse step is re-run by the plain
+ * integrator from the state saved at the start of the window; a sampled rod
+ * whose max_j |r_j - r_j(plain)| / L exceeds max_pos_error, or whose
+ * max |Q Q^T - I| exceeds max_orth_error, takes the plain state and stays on
+ * the plain step.  Requires an FP32 batch whose rods all have the same
+ * element count (ROD_EUNSUPPORTED otherwise).
+ */
+typedef struct {
+    int32_t judge_every;     /* coarse steps per judge window (> 0) */
+    float judge_fraction;    /* in (0, 1] */
+    float max_pos_error;     /* relative to the rod's rest length */
+    float max_orth_error;
+    uint64_t seed;
+} rod_judge_desc;
+
+typedef struct {
+    int64_t coarse_steps;    /* taken by this call */
+    int64_t judge_windows;
+    int64_t rods_judged;
+    int64_t rods_failed;     /* sent to the plain step by this call */
+    int64_t rods_plain;      /* on the plain step after the call */
+    double max_pos_error;    /* largest judged errors of this call */
+    double max_orth_error;
+} rod_surrogate_stats;
+
+int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const rod_judge_desc *j,
+                       rod_surrogate_stats *stats, void *stream);
+
+/* Write the network (FP32 parameters, normalisation, k) to a file, or read
+ * one back (resets Adam).  ROD_EINVAL when the file cannot be opened, is not
+ * a file of this network, or was written for another k.  Synchronous. */
+int rod_surrogate_save(rod_surrogate *s, const char *path);
+int rod_surrogate_load(rod_surrogate *s, const char *path);
+
+/* Per-rod fallback flags of the batch (host int32 [R], 1 = on the plain
+ * step); reset puts every rod back on the coarse step. */
+int rod_surrogate_fallback_flags(rod_surrogate *s, rod_batch *b, int32_t *flags);
+int rod_surrogate_reset_fallback(rod_surrogate *s, rod_batch *b);
 
 #ifdef __cplusplus
 }

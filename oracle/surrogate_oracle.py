@@ -18,9 +18,11 @@ T_b = lh_c^2 sqrt(rho A / (E I)); alpha_c; clamped-base flag; c / n; end flag;
 couple amplitude (material x) / 1e-5 N m/m; sin and cos of the couple phase
 2 pi f t + phi.
 
-Targets (12): Q_c (r_p(t+tau) - r_p(t)) / lh_c; Q_c (v_p(t+tau) - v_p(t)) tau / lh_c;
-theta = log(Q_c(t) Q_c(t+tau)^T) (so Q_c(t+tau) = exp(-[theta]x) Q_c(t));
-(omega_c(t+tau) - omega_c(t)) tau.
+Targets (12) are the departures from free flight over tau (constant node
+velocity, constant element angular velocity), which the apply step adds back:
+Q_c (r_p(t+tau) - r_p(t) - v_p(t) tau) / lh_c; Q_c (v_p(t+tau) - v_p(t)) tau / lh_c;
+theta - omega_c(t) tau with theta = log(Q_c(t) Q_c(t+tau)^T) (so
+Q_c(t+tau) = exp(-[theta]x) Q_c(t)); (omega_c(t+tau) - omega_c(t)) tau.
 """
 from __future__ import annotations
 
@@ -52,6 +54,13 @@ def _expmap(u):
     s = np.sin(th)[..., None, None]
     c1 = (1.0 - np.cos(th))[..., None, None]
     return np.eye(3) + s * K + c1 * (K @ K)
+
+
+def _nearest_rotation(A):
+    """Orthogonal polar factor U V^T of A = U S V^T: the rotation closest to A
+    in the Frobenius norm (A near a rotation, so det > 0)."""
+    U, _, Vt = np.linalg.svd(A)
+    return U @ Vt
 
 
 def rod_views(inp):
@@ -139,10 +148,10 @@ def window_targets(inp, s0, s1, k):
             p = wi if wi < n else n
             Qc = Q0[es][c]
             L = lh[c]
-            tgt[wi, 0:3] = Qc @ (p1[ns][p] - p0[ns][p]) / L
+            tgt[wi, 0:3] = Qc @ (p1[ns][p] - p0[ns][p] - v0[ns][p] * tau) / L
             tgt[wi, 3:6] = Qc @ (v1[ns][p] - v0[ns][p]) * tau / L
             if wi < n:
-                tgt[wi, 6:9] = _logvec(Qc @ Q1[es][c].T)
+                tgt[wi, 6:9] = _logvec(Qc @ Q1[es][c].T) - w0[es][c] * tau
                 tgt[wi, 9:12] = (w1[es][c] - w0[es][c]) * tau
             else:
                 msk[wi, 6:] = 0.0
@@ -153,8 +162,10 @@ def window_targets(inp, s0, s1, k):
 
 def apply_deltas(inp, state, d, k):
     """State after one coarse step with raw predicted deltas d [sum(n+1), 12]:
-    r_p += Q_c^T d[0:3] lh_c, v_p += Q_c^T d[3:6] lh_c / tau, Q_c <- exp(-[d[6:9]]x) Q_c,
-    omega_c += d[9:12] / tau (frames taken before the update); clamped ends are
+    r_p += v_p tau + Q_c^T d[0:3] lh_c, v_p += Q_c^T d[3:6] lh_c / tau,
+    Q_c <- P(exp(-[omega_c tau + d[6:9]]x) Q_c), omega_c += d[9:12] / tau (frames,
+    velocities and angular velocities taken before the update), where P is the
+    nearest rotation (orthogonal polar factor, from the SVD); clamped ends are
     left unchanged."""
     pos, vel, Q, om = (a.copy() for a in state)
     tau = k * inp.dt
@@ -165,6 +176,7 @@ def apply_deltas(inp, state, d, k):
     for r, (ns, es) in enumerate(rod_views(inp)):
         n = int(inp.n_elems[r])
         Qr = state[2][es]
+        v0, w0 = state[1][ns], state[3][es]
         x, v, q, w = pos[ns], vel[ns], Q[es], om[es]
         lh = lh_all[es]
         for wi in range(n + 1):
@@ -174,12 +186,12 @@ def apply_deltas(inp, state, d, k):
             Qc = Qr[c]
             fixed_node = (p == 0 and inp.bc_start[r]) or (p == n and inp.bc_end[r])
             if not fixed_node:
-                x[p] += Qc.T @ dd[0:3] * lh[c]
+                x[p] += v0[p] * tau + Qc.T @ dd[0:3] * lh[c]
                 v[p] += Qc.T @ dd[3:6] * lh[c] / tau
             if wi < n:
                 fixed_elem = (c == 0 and inp.bc_start[r]) or (c == n - 1 and inp.bc_end[r])
                 if not fixed_elem:
-                    q[c] = _expmap(-dd[6:9]) @ Qr[c]
+                    q[c] = _nearest_rotation(_expmap(-(w0[c] * tau + dd[6:9])) @ Qr[c])
                     w[c] += dd[9:12] / tau
         pos[ns], vel[ns], Q[es], om[es] = x, v, q, w
         row += n + 1

@@ -72,6 +72,7 @@ struct DevBatch {
     int32_t *rod_slot;     // [n_rods] slot of element 0
     int32_t *nonfinite;    // [n_rods] set to 1 when the state stops being finite
     int64_t *step;         // global step counter (device)
+    const int32_t *active; // [n_rods] or NULL: rods with active[r] == 0 keep their state
     int64_t n_slots;
     int32_t n_rods;
     int32_t n_tiles;
@@ -106,5 +107,10 @@ struct BatchView {
 int batch_view(const rod_batch_opaque *b, BatchView *v);
 // Advance the batch's clock by n steps without stepping (the learned coarse step).
 int batch_advance_clock(rod_batch_opaque *b, int64_t n, hipStream_t s);
+// n plain steps of the rods with active[r] != 0 (device [R]), direct launches.
+int batch_step_masked(rod_batch_opaque *b, int64_t n, const int32_t *active, hipStream_t s);
+// Set the batch's clock to time t with its step counter at 0 (direct launches afterwards).
+int batch_set_time(rod_batch_opaque *b, double t, hipStream_t s);
+hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t s);
 
 }  // namespace rodk

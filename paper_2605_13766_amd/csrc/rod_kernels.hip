@@ -268,6 +268,10 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         const bool first = i == 0;
         const bool fix0 = first && (flags & FLAG_CLAMP0);
         const bool fix1 = last && (flags & FLAG_CLAMP1);
+        // rods switched off by the caller keep their state; a tile with none
+        // active is skipped (uniform across the workgroup)
+        const bool act = valid && (!B.active || B.active[rr]);
+        if (!__syncthreads_or(act)) continue;
         // kinematic constraints as kick factors: a clamped node or element
         // starts at rest and never receives an increment
         const T hv = fix0 ? T(0) : h;
@@ -491,7 +495,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             }
         }
 
-        if (valid) {
+        if (act) {
             T *so = B.state + s;
             so[RX * NS] = r0; so[RY * NS] = r1; so[RZ * NS] = r2;
             so[VX * NS] = v0; so[VY * NS] = v1; so[VZ * NS] = v2;
@@ -517,6 +521,11 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
 __global__ void advance_kernel(int64_t *step, int64_t n)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *step += n;
+}
+
+__global__ void set_step_kernel(int64_t *step, int64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step = v;
 }
 
 // Per-rod energies, one thread per rod walking its slots (off the step path).
@@ -618,6 +627,12 @@ hipError_t launch_step(const DevBatch<double> &b, int waves, int n_sub, int grid
 hipError_t launch_step(const DevBatch<float> &b, int waves, int n_sub, int grid, hipStream_t s)
 {
     return launch_t<float>(b, waves, n_sub, grid, s);
+}
+
+hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, s, step, value);
+    return hipGetLastError();
 }
 
 hipError_t launch_advance(int64_t *step, int64_t n, hipStream_t s)

@@ -585,6 +585,31 @@ int rodk::batch_advance_clock(rod_batch *b, int64_t n, hipStream_t s)
     return ROD_OK;
 }
 
+int rodk::batch_step_masked(rod_batch *b, int64_t n, const int32_t *active, hipStream_t s)
+{
+    b->b32.active = active;
+    b->b64.active = active;
+    const int rc = enqueue_steps(b, n, s);
+    b->b32.active = nullptr;
+    b->b64.active = nullptr;
+    if (rc) return rc;
+    b->steps += n;
+    return ROD_OK;
+}
+
+int rodk::batch_set_time(rod_batch *b, double t, hipStream_t s)
+{
+    hipError_t e = rodk::launch_set_step(b->d_step, 0, s);
+    if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("set step: ") + hipGetErrorString(e));
+    b->t0 = t;
+    b->steps = 0;
+    fill_dev(b->b64, b);
+    fill_dev(b->b32, b);
+    free_graphs(b);
+    b->use_graphs = false;
+    return ROD_OK;
+}
+
 extern "C" {
 
 const char *rod_last_error(void) { return g_err.c_str(); }

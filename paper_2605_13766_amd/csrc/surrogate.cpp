@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <random>
@@ -77,6 +78,16 @@ struct rod_surrogate {
     float *rodf = nullptr, *disp = nullptr;
     void *saved = nullptr;                   // state copy for targets / the judge
     size_t saved_bytes = 0;
+    // coarse stepping
+    int32_t *plain = nullptr;                // device [R]: 1 = rod on the plain step
+    std::vector<int32_t> plain_h;
+    __bf16 *xall = nullptr;                  // [W][96] standardised features
+    float *yall = nullptr;                   // [W][16] network outputs
+    rod_batch *judge = nullptr;              // plain re-runs of the sampled rods
+    int judge_rods = 0;
+    int32_t *jmap = nullptr, *jsel = nullptr;
+    float *jerr = nullptr;
+    int64_t judge_windows_total = 0;
 };
 
 namespace {
@@ -88,8 +99,9 @@ int refresh_bf16(rod_surrogate *s, hipStream_t st)
     return ROD_OK;
 }
 
-// Forward over rows [0, M) of x (M <= max_rows), keeping Z and BF16 activations.
-int forward_chunk(rod_surrogate *s, const __bf16 *x, int M, hipStream_t st)
+// Forward over rows [0, M) of x (M <= max_rows), keeping Z and BF16 activations;
+// the output rows ([M][16]) go to yout, or to the workspace when NULL.
+int forward_chunk(rod_surrogate *s, const __bf16 *x, int M, hipStream_t st, float *yout = nullptr)
 {
     const __bf16 *in = x;
     for (int l = 0; l < NL; ++l) {
@@ -110,7 +122,7 @@ int forward_chunk(rod_surrogate *s, const __bf16 *x, int M, hipStream_t st)
             e = mlpk::gemm_forward(a, mlpk::EPI_BIAS_SILU, st);
             in = s->Ab[l];
         } else {
-            a.C = s->Y;
+            a.C = yout ? yout : s->Y;
             a.ldc = NOUT_LD;
             e = mlpk::gemm_forward(a, mlpk::EPI_BIAS, st);
         }
@@ -184,6 +196,21 @@ void free_ctx(rod_surrogate *s)
     (void)hipFree(s->rodf);
     (void)hipFree(s->disp);
     (void)hipFree(s->saved);
+    (void)hipFree(s->plain);
+    (void)hipFree(s->xall);
+    (void)hipFree(s->yall);
+    (void)hipFree(s->jmap);
+    (void)hipFree(s->jsel);
+    (void)hipFree(s->jerr);
+    if (s->judge) rod_batch_destroy(s->judge);
+    s->judge = nullptr;
+    s->judge_rods = 0;
+    s->plain = nullptr;
+    s->xall = nullptr;
+    s->yall = nullptr;
+    s->jmap = s->jsel = nullptr;
+    s->jerr = nullptr;
+    s->plain_h.clear();
     s->win_rod = s->elem_rod = nullptr;
     s->win_first = s->elem_first = nullptr;
     s->rodf = s->disp = nullptr;
@@ -240,6 +267,8 @@ int ensure_ctx(rod_surrogate *s, rod_batch *b, rodk::BatchView &v)
     up((void **)&s->disp, nullptr, (size_t)w * 3 * 4);
     s->saved_bytes = v.state_bytes + v.tail_bytes;
     up(&s->saved, nullptr, s->saved_bytes);
+    s->plain_h.assign(R, 0);
+    up((void **)&s->plain, s->plain_h.data(), (size_t)R * 4);
     if (err != hipSuccess) {
         free_ctx(s);
         return sfail(err == hipErrorOutOfMemory ? ROD_ENOMEM : ROD_EDEVICE, std::string("window context: ") + hipGetErrorString(err));
@@ -294,6 +323,78 @@ int loss_chunk(rod_surrogate *s, const __bf16 *x, const float *t, const float *m
 int upload_norm(rod_surrogate *s)
 {
     SHIPCHK(hipMemcpy(s->norm, s->norm_h.data(), s->norm_h.size() * 4, hipMemcpyHostToDevice));
+    return ROD_OK;
+}
+
+
+// A batch of `m` placeholder rods of n elements (straight, unit material) in
+// the main batch's tile width: the judge copies real rods into it.
+int make_judge(rod_surrogate *s, const rodk::BatchView &v, int m, int n)
+{
+    if (s->judge && s->judge_rods == m) return ROD_OK;
+    if (s->judge) rod_batch_destroy(s->judge);
+    s->judge = nullptr;
+    (void)hipFree(s->jmap);
+    (void)hipFree(s->jsel);
+    (void)hipFree(s->jerr);
+    s->jmap = s->jsel = nullptr;
+    s->jerr = nullptr;
+    const int64_t Ne = (int64_t)m * n, Nn = Ne + m;
+    std::vector<int32_t> ne(m, n), zero(m, 0);
+    std::vector<double> pos(3 * Nn, 0.0), vel(3 * Nn, 0.0), dir(9 * Ne, 0.0), om(3 * Ne, 0.0), one(m, 1.0);
+    for (int64_t i = 0, nd = 0; i < m; ++i)
+        for (int j = 0; j <= n; ++j, ++nd) pos[3 * nd + 2] = j;
+    for (int64_t e = 0; e < Ne; ++e) dir[9 * e] = dir[9 * e + 4] = dir[9 * e + 8] = 1.0;
+    rod_batch_desc d{};
+    d.n_rods = m;
+    d.n_elems = ne.data();
+    d.position = pos.data();
+    d.velocity = vel.data();
+    d.director = dir.data();
+    d.omega = om.data();
+    d.density = d.youngs = d.shear_modulus = d.radius = d.shear_coeff = one.data();
+    d.bc_start = d.bc_end = zero.data();
+    d.dt = v.dt;
+    d.precision = ROD_F32;
+    d.tile_waves = v.waves;
+    int rc = rod_batch_create(&d, nullptr, &s->judge);
+    if (rc) return rc;
+    SHIPCHK(hipMalloc((void **)&s->jmap, (size_t)m * 4));
+    SHIPCHK(hipMalloc((void **)&s->jsel, (size_t)m * 4));
+    SHIPCHK(hipMalloc((void **)&s->jerr, (size_t)m * 8));
+    s->judge_rods = m;
+    return ROD_OK;
+}
+
+int ensure_step_buffers(rod_surrogate *s)
+{
+    if (s->xall) return ROD_OK;
+    SHIPCHK(hipMalloc((void **)&s->xall, (size_t)s->n_windows * ROD_SURROGATE_INPUTS * 2));
+    SHIPCHK(hipMalloc((void **)&s->yall, (size_t)s->n_windows * NOUT_LD * 4));
+    return ROD_OK;
+}
+
+// features -> network -> deltas applied to the rods off the plain step; the
+// plain ones take k plain steps.  Advances the clock by k.
+int coarse_step(rod_surrogate *s, rod_batch *b, const rodk::BatchView &v, int n_plain, hipStream_t st)
+{
+    const float *mux = s->norm, *sdx = s->norm + ROD_SURROGATE_INPUTS;
+    const float *mut = s->norm + 2 * ROD_SURROGATE_INPUTS, *sdt = mut + ROD_SURROGATE_OUTPUTS;
+    hipError_t e = surk::features(win_args(s, v), nullptr, s->xall, mux, sdx, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("features: ") + hipGetErrorString(e));
+    for (int64_t r0 = 0; r0 < s->n_windows; r0 += s->max_rows) {
+        const int rows = (int)std::min<int64_t>(s->max_rows, s->n_windows - r0);
+        int rc = forward_chunk(s, s->xall + r0 * ROD_SURROGATE_INPUTS, rows, st, s->yall + r0 * NOUT_LD);
+        if (rc) return rc;
+    }
+    int rc;
+    if (n_plain > 0) {
+        if ((rc = rodk::batch_step_masked(b, s->k, s->plain, st))) return rc;
+    }
+    e = surk::apply(win_args(s, v), s->yall, NOUT_LD, mut, sdt, n_plain > 0 ? s->plain : nullptr, s->disp, s->elem_rod,
+                    s->elem_first, s->n_elems, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("apply: ") + hipGetErrorString(e));
+    if (n_plain == 0 && (rc = rodk::batch_advance_clock(b, s->k, st))) return rc;
     return ROD_OK;
 }
 
@@ -639,7 +740,9 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
         const double m = c > 0 ? sm / c : 0.0;
         const double var = c > 0 ? std::max(0.0, sq / c - m * m) : 0.0;
         double sdv = std::sqrt(var);
-        if (!(sdv > 1e-6 * std::max(1.0, std::fabs(m)))) sdv = 1.0;   // constant column
+        // constant column (a flag, or variation below FP32 resolution of its mean): unit scale.
+        // Targets keep tiny scales: departures from free flight are small by construction.
+        if (!(sdv > 1e-6 * std::fabs(m)) || !(sdv > 0)) sdv = 1.0;
         mu[j] = (float)m;
         sd[j] = (float)sdv;
     }
@@ -698,6 +801,171 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
 #undef TRYH
     cleanup();
     return ROD_OK;
+}
+
+int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const rod_judge_desc *j,
+                       rod_surrogate_stats *stats, void *stream)
+{
+    if (!s || !b || !j) return sfail(ROD_EINVAL, "NULL argument");
+    if (n_coarse < 0 || j->judge_every <= 0 || !(j->judge_fraction > 0 && j->judge_fraction <= 1)
+        || !(j->max_pos_error >= 0) || !(j->max_orth_error >= 0))
+        return sfail(ROD_EINVAL, "invalid judge descriptor");
+    rodk::BatchView v;
+    int rc = ensure_ctx(s, b, v);
+    if (rc) return rc;
+    const int n = v.n[0];
+    for (int r = 1; r < v.n_rods; ++r)
+        if (v.n[r] != n) return sfail(ROD_EUNSUPPORTED, "the coarse step needs rods of equal element count");
+    if ((rc = ensure_step_buffers(s))) return rc;
+    const int m = std::max(1, (int)std::lround(j->judge_fraction * v.n_rods));
+    if ((rc = make_judge(s, v, m, n))) return rc;
+    rodk::BatchView jv;
+    if ((rc = rodk::batch_view(s->judge, &jv))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rod_surrogate_stats out{};
+    int n_plain = 0;
+    for (int32_t f : s->plain_h) n_plain += f != 0;
+    std::vector<int32_t> map;
+    std::vector<float> err;
+    int64_t c = 0;
+    while (c < n_coarse) {
+        // ---- open a judge window: sample rods still on the coarse step
+        std::vector<int32_t> cand;
+        for (int r = 0; r < v.n_rods; ++r)
+            if (!s->plain_h[r]) cand.push_back(r);
+        const int mw = std::min<int>(m, (int)cand.size());
+        if (mw > 0) {
+            std::mt19937_64 rng(j->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s->judge_windows_total + 1));
+            std::shuffle(cand.begin(), cand.end(), rng);
+            map.assign(cand.begin(), cand.begin() + mw);
+            std::sort(map.begin(), map.end());
+            map.resize(m, map.back());   // unused tail of the judge batch repeats the last rod
+            std::vector<int32_t> sel(m, 0);
+            std::fill(sel.begin(), sel.begin() + mw, 1);
+            SHIPCHK(hipMemcpyAsync(s->jmap, map.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+            SHIPCHK(hipMemcpyAsync(s->jsel, sel.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+            rodk::BatchView cv;
+            if ((rc = rodk::batch_view(b, &cv))) return rc;
+            hipError_t e = surk::copy_rods(jv.f32, cv.f32, s->jmap, nullptr, m, n, false, false, st);
+            if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("judge copy: ") + hipGetErrorString(e));
+            if ((rc = rodk::batch_set_time(s->judge, cv.time, st))) return rc;
+            SHIPCHK(hipStreamSynchronize(st));   // the host map and selection buffers are reused
+        }
+        const int64_t steps = std::min<int64_t>(j->judge_every, n_coarse - c);
+        for (int64_t i = 0; i < steps; ++i) {
+            rodk::BatchView cv;
+            if ((rc = rodk::batch_view(b, &cv))) return rc;
+            if ((rc = coarse_step(s, b, cv, n_plain, st))) return rc;
+        }
+        c += steps;
+        out.coarse_steps += steps;
+        if (mw == 0) continue;
+        // ---- close the window: plain re-run of the sample, compare, fall back
+        if ((rc = rod_step(s->judge, steps * s->k, stream))) return rc;
+        rodk::BatchView cv, jv2;
+        if ((rc = rodk::batch_view(b, &cv)) || (rc = rodk::batch_view(s->judge, &jv2))) return rc;
+        hipError_t e = surk::judge_errors(cv.f32, jv2.f32, s->jmap, m, s->jerr, st);
+        if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("judge errors: ") + hipGetErrorString(e));
+        err.resize(2 * (size_t)m);
+        SHIPCHK(hipMemcpyAsync(err.data(), s->jerr, err.size() * 4, hipMemcpyDeviceToHost, st));
+        SHIPCHK(hipStreamSynchronize(st));
+        std::vector<int32_t> fail_sel(m, 0);
+        int nf = 0;
+        for (int k = 0; k < mw; ++k) {
+            const double pe = err[2 * k], oe = err[2 * k + 1];
+            out.max_pos_error = std::max(out.max_pos_error, std::isfinite(pe) ? pe : INFINITY);
+            out.max_orth_error = std::max(out.max_orth_error, std::isfinite(oe) ? oe : INFINITY);
+            if (!(pe <= j->max_pos_error) || !(oe <= j->max_orth_error)) {
+                fail_sel[k] = 1;
+                s->plain_h[map[k]] = 1;
+                ++nf;
+            }
+        }
+        out.judge_windows += 1;
+        out.rods_judged += mw;
+        s->judge_windows_total += 1;
+        if (nf > 0) {
+            SHIPCHK(hipMemcpyAsync(s->jsel, fail_sel.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+            e = surk::copy_rods(jv2.f32, cv.f32, s->jmap, s->jsel, m, n, true, true, st);
+            if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("fallback copy: ") + hipGetErrorString(e));
+            SHIPCHK(hipMemcpyAsync(s->plain, s->plain_h.data(), s->plain_h.size() * 4, hipMemcpyHostToDevice, st));
+            SHIPCHK(hipStreamSynchronize(st));
+            out.rods_failed += nf;
+            n_plain += nf;
+        }
+    }
+    out.rods_plain = n_plain;
+    if (stats) *stats = out;
+    return ROD_OK;
+}
+
+int rod_surrogate_fallback_flags(rod_surrogate *s, rod_batch *b, int32_t *flags)
+{
+    if (!s || !b || !flags) return sfail(ROD_EINVAL, "NULL argument");
+    rodk::BatchView v;
+    int rc = ensure_ctx(s, b, v);
+    if (rc) return rc;
+    std::copy(s->plain_h.begin(), s->plain_h.end(), flags);
+    return ROD_OK;
+}
+
+int rod_surrogate_reset_fallback(rod_surrogate *s, rod_batch *b)
+{
+    if (!s || !b) return sfail(ROD_EINVAL, "NULL argument");
+    rodk::BatchView v;
+    int rc = ensure_ctx(s, b, v);
+    if (rc) return rc;
+    std::fill(s->plain_h.begin(), s->plain_h.end(), 0);
+    SHIPCHK(hipMemcpy(s->plain, s->plain_h.data(), s->plain_h.size() * 4, hipMemcpyHostToDevice));
+    return ROD_OK;
+}
+
+// File: 8-byte magic "RODSURR1", int32 k, int32 parameter count, int32
+// normalisation count, int32 zero, then the FP32 parameters (external layout)
+// and the normalisation vector (mu_x, sd_x, mu_t, sd_t), little-endian.
+static const char kMagic[8] = {'R', 'O', 'D', 'S', 'U', 'R', 'R', '1'};
+
+int rod_surrogate_save(rod_surrogate *s, const char *path)
+{
+    if (!s || !path) return sfail(ROD_EINVAL, "NULL argument");
+    std::vector<float> p(ROD_SURROGATE_PARAMS);
+    int rc = rod_surrogate_get_params(s, p.data());
+    if (rc) return rc;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return sfail(ROD_EINVAL, std::string("cannot open ") + path + " for writing");
+    const int32_t hdr[4] = {s->k, ROD_SURROGATE_PARAMS, (int32_t)s->norm_h.size(), 0};
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4
+              && std::fwrite(p.data(), 4, p.size(), f) == p.size()
+              && std::fwrite(s->norm_h.data(), 4, s->norm_h.size(), f) == s->norm_h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return sfail(ROD_EINVAL, std::string("write failed: ") + path);
+    return ROD_OK;
+}
+
+int rod_surrogate_load(rod_surrogate *s, const char *path)
+{
+    if (!s || !path) return sfail(ROD_EINVAL, "NULL argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return sfail(ROD_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t hdr[4];
+    std::vector<float> p(ROD_SURROGATE_PARAMS), nm(s->norm_h.size());
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 && std::fread(hdr, 4, 4, f) == 4
+              && hdr[1] == ROD_SURROGATE_PARAMS && hdr[2] == (int32_t)nm.size()
+              && std::fread(p.data(), 4, p.size(), f) == p.size() && std::fread(nm.data(), 4, nm.size(), f) == nm.size();
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;
+    std::fclose(f);
+    if (!ok) return sfail(ROD_EINVAL, std::string("not a surrogate file of this network: ") + path);
+    if (hdr[0] != s->k)
+        return sfail(ROD_EINVAL, "file was trained for k = " + std::to_string(hdr[0]) + ", handle has k = " + std::to_string(s->k));
+    for (float x : p)
+        if (!std::isfinite(x)) return sfail(ROD_EINVAL, "non-finite parameter in file");
+    const float *n = nm.data();
+    int rc = rod_surrogate_set_normalization(s, n, n + ROD_SURROGATE_INPUTS, n + 2 * ROD_SURROGATE_INPUTS,
+                                             n + 2 * ROD_SURROGATE_INPUTS + ROD_SURROGATE_OUTPUTS);
+    if (rc) return rc;
+    return rod_surrogate_set_params(s, p.data());
 }
 
 }  // extern "C"

@@ -33,8 +33,9 @@ hipError_t apply(const WinArgs &A, const float *y, int ldy, const float *mu, con
 hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, const int64_t *idx, int64_t rows,
                        const float *mu_x, const float *sd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
                        float *m, hipStream_t s);
-hipError_t copy_rods(const rodk::DevBatch<float> &dst, const rodk::DevBatch<float> &src, const int32_t *map, int n_map,
-                     int n, bool state_only, bool to_src, hipStream_t s);
+// dst rod k <-> src rod map[k] (to_src: copy back into src); sel[k] == 0 skips k
+hipError_t copy_rods(const rodk::DevBatch<float> &dst, const rodk::DevBatch<float> &src, const int32_t *map,
+                     const int32_t *sel, int n_map, int n, bool state_only, bool to_src, hipStream_t s);
 hipError_t colstats(const float *a, const float *mask, int64_t rows, int cols, double *out, hipStream_t s);
 hipError_t judge_errors(const rodk::DevBatch<float> &main, const rodk::DevBatch<float> &ref, const int32_t *map,
                         int n_map, float *err, hipStream_t s);

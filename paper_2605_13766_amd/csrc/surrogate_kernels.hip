@@ -203,16 +203,18 @@ __global__ void targets_kernel(const WinArgs A, const DevBatch<float> S0, float 
     // node p displacement: anchor plus the edges before p
     V3 dr = R1.anchor() - R0.anchor();
     for (int m = 0; m < p; ++m) dr = dr + (R1.edge(m) - R0.edge(m));
-    const V3 a = matvec(q0, dr);
-    const V3 b = matvec(q0, R1.node_v(p) - R0.node_v(p));
+    const V3 v0 = R0.node_v(p);
+    const V3 a = matvec(q0, dr - A.tau * v0);
+    const V3 b = matvec(q0, R1.node_v(p) - v0);
     float *t = tgt + g * N_OUT;
     float *mk = mask + g * N_OUT;
     t[0] = a.x * iL; t[1] = a.y * iL; t[2] = a.z * iL;
     t[3] = b.x * A.tau * iL; t[4] = b.y * A.tau * iL; t[5] = b.z * A.tau * iL;
     for (int k = 0; k < 6; ++k) mk[k] = 1.f;
     if (w < n) {
-        const V3 th = log_rel(q0, q1);
-        const V3 dw = R1.omega(c) - R0.omega(c);
+        const V3 w0 = R0.omega(c);
+        const V3 th = log_rel(q0, q1) - A.tau * w0;
+        const V3 dw = R1.omega(c) - w0;
         t[6] = th.x; t[7] = th.y; t[8] = th.z;
         t[9] = dw.x * A.tau; t[10] = dw.y * A.tau; t[11] = dw.z * A.tau;
         for (int k = 6; k < 12; ++k) mk[k] = 1.f;
@@ -225,6 +227,24 @@ __global__ void targets_kernel(const WinArgs A, const DevBatch<float> S0, float 
 // deltas y [window][ldy]: raw = y * sd + mu (sd = NULL: y is raw already).
 // Phase 1 (one thread per window): lab displacement of the target node into
 // disp [window][3], node velocity update.  Skips rods with skip[r] != 0.
+// One Newton-Schulz step towards the orthogonal polar factor, Q <- Q (3I - Q^T Q) / 2:
+// an orthonormality error e becomes O(e^2), so FP32 round-off drift carried in
+// by the plain step (about 1e-8 per step) is removed at every coarse step.
+__device__ inline void polar_step(float q[9])
+{
+    float g[9];   // Q^T Q
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) g[3 * a + b] = q[a] * q[b] + q[3 + a] * q[3 + b] + q[6 + a] * q[6 + b];
+    float o[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            float acc = 0.f;
+            for (int c = 0; c < 3; ++c) acc += q[3 * a + c] * ((c == b ? 3.f : 0.f) - g[3 * c + b]);
+            o[3 * a + b] = 0.5f * acc;
+        }
+    for (int k = 0; k < 9; ++k) q[k] = o[k];
+}
+
 __global__ void apply_nodes_kernel(const WinArgs A, const float *y, int ldy, const float *mu, const float *sd,
                                    const int32_t *skip, float *disp)
 {
@@ -247,11 +267,11 @@ __global__ void apply_nodes_kernel(const WinArgs A, const float *y, int ldy, con
     float qc[9];
     R.dirs(c, qc);
     const float L = R.lh(c);
-    const V3 dr = matTvec(qc, V3{d[0], d[1], d[2]});
+    const V3 dr = L * matTvec(qc, V3{d[0], d[1], d[2]}) + A.tau * R.node_v(p);   // free flight + learned part
     const V3 dv = matTvec(qc, V3{d[3], d[4], d[5]});
-    disp[g * 3] = dr.x * L;
-    disp[g * 3 + 1] = dr.y * L;
-    disp[g * 3 + 2] = dr.z * L;
+    disp[g * 3] = dr.x;
+    disp[g * 3 + 1] = dr.y;
+    disp[g * 3 + 2] = dr.z;
     const float s = L / A.tau;
     float *st = A.B.state;
     const int64_t NS = A.B.n_slots;
@@ -297,7 +317,9 @@ __global__ void apply_elems_kernel(const WinArgs A, const float *y, int ldy, con
     for (int k = 0; k < 6; ++k) d[k] = sd ? y[g * ldy + 6 + k] * sd[6 + k] + mu[6 + k] : y[g * ldy + 6 + k];
     float q[9];
     R.dirs(c, q);
-    rotate_left(q, V3{-d[0], -d[1], -d[2]});
+    const V3 w0 = R.omega(c);
+    rotate_left(q, V3{-(d[0] + w0.x * A.tau), -(d[1] + w0.y * A.tau), -(d[2] + w0.z * A.tau)});
+    polar_step(q);
     for (int k = 0; k < 9; ++k) st[(rodk::Q00 + k) * NS + sl] = q[k];
     const float it = 1.f / A.tau;
     st[rodk::WX * NS + sl] += d[3] * it;
@@ -352,12 +374,13 @@ __global__ void colstats_kernel(const float *a, const float *mask, int64_t rows,
 // ---------------------------------------------------------------- judge
 // Copy rods between two FP32 batches of equal per-rod layout: dst rod k <- src rod map[k]
 // (state, constants, tail, per-rod tables).  One thread per (k, element).
-__global__ void copy_rods_kernel(DevBatch<float> dst, DevBatch<float> src, const int32_t *map, int n_map,
-                                 int n, bool state_only, bool to_src)
+__global__ void copy_rods_kernel(DevBatch<float> dst, DevBatch<float> src, const int32_t *map, const int32_t *sel,
+                                 int n_map, int n, bool state_only, bool to_src)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n_map * n) return;
     const int k = (int)(t / n), i = (int)(t % n);
+    if (sel && !sel[k]) return;
     const int rs = map[k];
     // to_src: write the dst batch's rod k back into src rod map[k]
     const DevBatch<float> &from = to_src ? dst : src;
@@ -444,10 +467,10 @@ hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, 
     return hipGetLastError();
 }
 
-hipError_t copy_rods(const DevBatch<float> &dst, const DevBatch<float> &src, const int32_t *map, int n_map, int n,
-                     bool state_only, bool to_src, hipStream_t s)
+hipError_t copy_rods(const DevBatch<float> &dst, const DevBatch<float> &src, const int32_t *map, const int32_t *sel,
+                     int n_map, int n, bool state_only, bool to_src, hipStream_t s)
 {
-    hipLaunchKernelGGL(copy_rods_kernel, blocks((int64_t)n_map * n), dim3(256), 0, s, dst, src, map, n_map, n,
+    hipLaunchKernelGGL(copy_rods_kernel, blocks((int64_t)n_map * n), dim3(256), 0, s, dst, src, map, sel, n_map, n,
                        state_only, to_src);
     return hipGetLastError();
 }

@@ -52,6 +52,20 @@ class TrainDesc(C.Structure):
                 ("val_fraction", C.c_float), ("seed", C.c_uint64)]
 
 
+class JudgeDesc(C.Structure):
+    _fields_ = [("judge_every", C.c_int32), ("judge_fraction", C.c_float), ("max_pos_error", C.c_float),
+                ("max_orth_error", C.c_float), ("seed", C.c_uint64)]
+
+
+class SurrogateStats(C.Structure):
+    _fields_ = [("coarse_steps", C.c_int64), ("judge_windows", C.c_int64), ("rods_judged", C.c_int64),
+                ("rods_failed", C.c_int64), ("rods_plain", C.c_int64), ("max_pos_error", C.c_double),
+                ("max_orth_error", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class RodError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"rod error {code}: {msg}")
@@ -97,11 +111,17 @@ def lib():
         L.rod_surrogate_set_normalization.argtypes = [vp, fp, fp, fp, fp]
         L.rod_surrogate_get_normalization.argtypes = [vp, fp, fp, fp, fp]
         L.rod_surrogate_train.argtypes = [vp, vp, C.POINTER(TrainDesc), fp, fp, vp]
+        L.rod_surrogate_step.argtypes = [vp, vp, C.c_int64, C.POINTER(JudgeDesc), C.POINTER(SurrogateStats), vp]
+        L.rod_surrogate_fallback_flags.argtypes = [vp, vp, _ip]
+        L.rod_surrogate_reset_fallback.argtypes = [vp, vp]
+        L.rod_surrogate_save.argtypes = [vp, C.c_char_p]
+        L.rod_surrogate_load.argtypes = [vp, C.c_char_p]
         for f in ("rod_surrogate_create", "rod_surrogate_set_params", "rod_surrogate_get_params",
                   "rod_surrogate_forward", "rod_surrogate_gradients", "rod_surrogate_train_step",
                   "rod_surrogate_features", "rod_surrogate_collect", "rod_surrogate_apply",
                   "rod_surrogate_set_normalization", "rod_surrogate_get_normalization",
-                  "rod_surrogate_train"):
+                  "rod_surrogate_train", "rod_surrogate_step", "rod_surrogate_fallback_flags",
+                  "rod_surrogate_reset_fallback", "rod_surrogate_save", "rod_surrogate_load"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -306,6 +326,30 @@ class Surrogate:
         _check(lib().rod_surrogate_train(self._h, batch._h, C.byref(d), ep.ctypes.data_as(C.POINTER(C.c_float)),
                                          C.byref(vl), _stream_ptr(stream)))
         return ep, vl.value
+
+    def step(self, batch, n_coarse, judge_every=8, judge_fraction=0.01, max_pos_error=1e-3,
+             max_orth_error=1e-5, seed=0, stream=None) -> dict:
+        """n_coarse learned coarse steps (k plain steps each) with the plain
+        integrator judging a sample of rods every judge_every steps."""
+        j = JudgeDesc(int(judge_every), float(judge_fraction), float(max_pos_error), float(max_orth_error), int(seed))
+        st = SurrogateStats()
+        _check(lib().rod_surrogate_step(self._h, batch._h, int(n_coarse), C.byref(j), C.byref(st),
+                                        _stream_ptr(stream)))
+        return st.as_dict()
+
+    def fallback_flags(self, batch) -> np.ndarray:
+        f = np.empty(batch.n_rods, dtype=np.int32)
+        _check(lib().rod_surrogate_fallback_flags(self._h, batch._h, _p(f, _ip)))
+        return f
+
+    def reset_fallback(self, batch):
+        _check(lib().rod_surrogate_reset_fallback(self._h, batch._h))
+
+    def save(self, path):
+        _check(lib().rod_surrogate_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        _check(lib().rod_surrogate_load(self._h, os.fsencode(path)))
 
     def close(self):
         if self._h is not None and _lib is not None:

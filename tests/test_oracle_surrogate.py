@@ -72,6 +72,10 @@ def test_straight_rest_features_closed_form():
 
 
 def test_targets_rigid_translation_and_spin():
+    """Targets are departures from free flight: a rigid translation at constant
+    velocity and a spin at constant angular velocity give zero; an extra
+    displacement delta gives Q delta / lh, an extra turn phi about d3 gives
+    (0, 0, phi) (sign and frame of the rotation target)."""
     n = 6
     nodes, Q = W.straight_rod(n, 0.06, direction=(0, 0, 1), d1=(1, 0, 0))
     lh = np.full(n, 0.01)
@@ -81,13 +85,17 @@ def test_targets_rigid_translation_and_spin():
     s1 = (nodes + v * tau, np.tile(v, (n + 1, 1)), Q, np.zeros((n, 3)))
     inp = RC.single(nodes, Q, rest_length=lh)
     T, M = S.window_targets(inp, s0, s1, 32)
-    assert np.allclose(T[:, 0:3], (Q[0] @ v) * tau / 0.01, atol=1e-12)
-    assert np.allclose(T[:, 3:], 0, atol=1e-12)
+    assert np.allclose(T, 0, atol=1e-12)
     assert M[n, 6:].sum() == 0 and M[:n].min() == 1
-    # spin about d3 at rate w: Q(t + tau) = exp(-tau [w e3]x) Q(t), theta = (0, 0, w tau)
-    w = 3.0
-    E = S._expmap(np.array([0, 0, -w * tau]))
+    delta = np.array([2e-4, -1e-4, 3e-4])
+    s1b = (nodes + v * tau + delta, np.tile(v, (n + 1, 1)), Q, np.zeros((n, 3)))
+    Tb, _ = S.window_targets(inp, s0, s1b, 32)
+    assert np.allclose(Tb[:, 0:3], (Q[0] @ delta) / 0.01, atol=1e-12)
+    # spin about d3 at rate w: Q(t + tau) = exp(-tau [w e3]x) Q(t) is free flight
+    w, phi = 3.0, 0.02
     s2 = (nodes, np.zeros_like(nodes), Q @ np.eye(3), np.tile([0, 0, w], (n, 1)))
-    s3 = (nodes, np.zeros_like(nodes), np.einsum("ab,ibc->iac", E, Q), np.tile([0, 0, w], (n, 1)))
-    T2, _ = S.window_targets(inp, s2, s3, 32)
-    assert np.allclose(T2[:n, 6:9], [0, 0, w * tau], atol=1e-13)
+    for extra, want in ((0.0, 0.0), (phi, phi)):
+        E = S._expmap(np.array([0, 0, -(w * tau + extra)]))
+        s3 = (nodes, np.zeros_like(nodes), np.einsum("ab,ibc->iac", E, Q), np.tile([0, 0, w], (n, 1)))
+        T2, _ = S.window_targets(inp, s2, s3, 32)
+        assert np.allclose(T2[:n, 6:9], [0, 0, want], atol=1e-13)
