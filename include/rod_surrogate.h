@@ -95,6 +95,21 @@ int rod_surrogate_features(rod_surrogate *s, rod_batch *b, float *features, void
 int rod_surrogate_collect(rod_surrogate *s, rod_batch *b, float *features, float *targets, float *mask,
                           void *stream);
 
+/* Perturb the free part of the batch state in place (seeded, counter-based
+ * N(0, 1) deviates g): node positions by noise[0] lh g, node velocities by
+ * noise[1] lh / tau g, director frames by exp(-[noise[2] g]x), angular
+ * velocities by noise[3] / tau g, with lh the rest length of the node's own
+ * element (element n-1 for node n).  Clamped nodes and elements are left
+ * alone.  The same (seed, batch) gives the same perturbation. */
+int rod_surrogate_perturb(rod_surrogate *s, rod_batch *b, const float *noise, uint64_t seed, void *stream);
+
+/* As rod_surrogate_collect, but the features are those of the perturbed state
+ * (rod_surrogate_perturb with noise and seed) while the batch steps on from
+ * the unperturbed state, and the targets lead from the perturbed state to the
+ * plain result: the network learns to return to the trajectory. */
+int rod_surrogate_collect_noisy(rod_surrogate *s, rod_batch *b, const float *noise, uint64_t seed, float *features,
+                                float *targets, float *mask, void *stream);
+
 /* Apply raw deltas [W][12] (device) to the batch as one coarse step and
  * advance its clock by k steps: free flight plus the deltas, then each
  * rotated director frame is moved to its nearest rotation (one Newton-Schulz
@@ -117,7 +132,9 @@ typedef struct {
     float lr;                /* peak learning rate, cosine decay to lr_min over all steps */
     float lr_min;
     float val_fraction;      /* share of windows held out for validation */
-    uint64_t seed;           /* shuffling */
+    uint64_t seed;           /* shuffling and perturbations */
+    float noise[4];          /* perturbation levels (rod_surrogate_perturb); sample i uses
+                                (i mod 4) / 3 of them, so a quarter of the samples is clean */
 } rod_train_desc;
 
 /* Generate trajectories with the plain integrator on `b` (advancing it),
@@ -136,10 +153,15 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
  * judge_every coarse steps a seeded sample of judge_fraction of the rods
  * (at least one) that are still on the coarse step is re-run by the plain
  * integrator from the state saved at the start of the window; a sampled rod
- * whose max_j |r_j - r_j(plain)| / L exceeds max_pos_error, or whose
- * max |Q Q^T - I| exceeds max_orth_error, takes the plain state and stays on
- * the plain step.  Requires an FP32 batch whose rods all have the same
- * element count (ROD_EUNSUPPORTED otherwise).
+ * whose max_j |r_j - r_j(plain)| / L exceeds max_pos_error, whose
+ * max |Q Q^T - I| exceeds max_orth_error, or whose strain energy (shear plus
+ * bending, as rod_energy) differs from the plain re-run's by more than
+ * max_energy_error times the re-run's mechanical energy (kinetic plus strain)
+ * takes the plain state and stays on the plain step.  Non-finite errors fail.
+ * Requires an FP32 batch whose rods all have the same element count
+ * (ROD_EUNSUPPORTED otherwise).  The fallback flags belong to the last batch
+ * this handle worked on: using the handle with another batch resets them.
+ * Synchronises `stream` at the end of every judge window.
  */
 typedef struct {
     int32_t judge_every;     /* coarse steps per judge window (> 0) */
@@ -147,6 +169,7 @@ typedef struct {
     float max_pos_error;     /* relative to the rod's rest length */
     float max_orth_error;
     uint64_t seed;
+    float max_energy_error;  /* relative strain-energy difference */
 } rod_judge_desc;
 
 typedef struct {
@@ -157,6 +180,7 @@ typedef struct {
     int64_t rods_plain;      /* on the plain step after the call */
     double max_pos_error;    /* largest judged errors of this call */
     double max_orth_error;
+    double max_energy_error;
 } rod_surrogate_stats;
 
 int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const rod_judge_desc *j,

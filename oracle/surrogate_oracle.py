@@ -198,6 +198,71 @@ def apply_deltas(inp, state, d, k):
     return pos, vel, Q, om
 
 
+# ------------------------------------------------------------------ perturbation
+# Counter-based N(0, 1) deviates: the splitmix64 output function (Steele, Lea and
+# Flood, "Fast splittable pseudorandom number generators", 2014) hashes
+# (seed, key); the top 24 and the low 24 bits give two uniforms in (0, 1), and
+# the Box-Muller transform one normal deviate.
+
+def _mix64(z):
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def gauss(seed, key):
+    """N(0, 1) deviate for (seed, key) (arrays of keys allowed)."""
+    h = _mix64(np.uint64(seed) ^ _mix64(key))
+    u1 = ((h >> np.uint64(40)).astype(np.float64) + 0.5) / 16777216.0
+    u2 = ((h & np.uint64(0xFFFFFF)).astype(np.float64) + 0.5) / 16777216.0
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def noise_key(r, j, kind, a):
+    """Key of component a of quantity `kind` (0 position, 1 velocity,
+    2 rotation, 3 angular velocity) at node or element j of rod r."""
+    return (np.uint64(r) << np.uint64(32)) | (np.uint64(j) << np.uint64(4)) | np.uint64(3 * kind + a)
+
+
+def perturb(inp, state, noise, seed, k):
+    """Perturbed copy of a state: node positions += noise[0] lh g, node
+    velocities += noise[1] lh / tau g, frames Q <- exp(-[noise[2] g]x) Q,
+    angular velocities += noise[3] / tau g, g ~ N(0, 1) from gauss(seed, key)
+    per component; lh of the node's own element (element n-1 for node n);
+    clamped nodes and elements unchanged."""
+    pos, vel, Q, om = (np.array(a, dtype=np.float64, copy=True) for a in state)
+    tau = k * inp.dt
+    lh_all = (inp.rest_length if inp.rest_length is not None
+              else np.concatenate([np.linalg.norm(np.diff(inp.position[ns], axis=0), axis=1)
+                                   for ns, _ in rod_views(inp)]))
+    def g3(r, idx, kind):
+        # [len(idx), 3] deviates for nodes / elements idx of rod r
+        return np.stack([gauss(seed, noise_key(r, idx, kind, a)) for a in range(3)], axis=1)
+
+    for r, (ns, es) in enumerate(rod_views(inp)):
+        n = int(inp.n_elems[r])
+        lh = lh_all[es]
+        x, v, q, w = pos[ns], vel[ns], Q[es], om[es]
+        nodes = np.array([j for j in range(n + 1)
+                          if not ((j == 0 and inp.bc_start[r]) or (j == n and inp.bc_end[r]))], dtype=np.uint64)
+        L = lh[np.minimum(nodes.astype(np.int64), n - 1)][:, None]
+        ni = nodes.astype(np.int64)
+        if noise[0] != 0:
+            x[ni] += noise[0] * L * g3(r, nodes, 0)
+        if noise[1] != 0:
+            v[ni] += noise[1] * L / tau * g3(r, nodes, 1)
+        elems = np.array([c for c in range(n)
+                          if not ((c == 0 and inp.bc_start[r]) or (c == n - 1 and inp.bc_end[r]))], dtype=np.uint64)
+        ei = elems.astype(np.int64)
+        q[ei] = np.einsum("iab,ibc->iac", _expmap(-noise[2] * g3(r, elems, 2)), q[ei])
+        w[ei] += noise[3] / tau * g3(r, elems, 3)
+        pos[ns], vel[ns], Q[es], om[es] = x, v, q, w
+    return pos, vel, Q, om
+
+
 def judge_errors(inp, ref_state, state):
     """Per rod: max_j |dr_j| / L (against the plain reference) and the director
     orthonormality error max |Q Q^T - I| of `state`."""

@@ -85,7 +85,9 @@ hipError_t launch_step(const DevBatch<double> &b, int waves, int n_sub, int grid
 hipError_t launch_step(const DevBatch<float> &b, int waves, int n_sub, int grid, hipStream_t s);
 hipError_t launch_advance(int64_t *step, int64_t n, hipStream_t s);
 hipError_t launch_energy(const DevBatch<double> &b, double *out, hipStream_t s);
-hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s);
+// map (device [n_map]) or NULL: output row i is rod map[i]
+hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s, const int32_t *map = nullptr,
+                         int n_map = 0);
 // Largest number of co-resident workgroups of the step kernel (occupancy x CUs).
 int step_resident_groups(int precision_f32, int waves);
 

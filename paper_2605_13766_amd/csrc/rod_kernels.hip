@@ -531,11 +531,12 @@ __global__ void set_step_kernel(int64_t *step, int64_t v)
 // Per-rod energies, one thread per rod walking its slots (off the step path).
 // FP32 batches hold edge vectors: node n = anchor + sum of edges (in FP64).
 template <typename T>
-__global__ void rod_energy_kernel(const DevBatch<T> B, double *out)
+__global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_t *map, int n_map)
 {
     constexpr bool EDGE = sizeof(T) == 4;
-    const int rod = blockIdx.x * blockDim.x + threadIdx.x;
-    if (rod >= B.n_rods) return;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;   // output row: rod `row`, or rod map[row]
+    if (row >= (map ? n_map : B.n_rods)) return;
+    const int rod = map ? map[row] : row;
     const int64_t NS = B.n_slots;
     const int n = B.rod_n[rod];
     const int64_t s0 = B.rod_slot[rod];
@@ -590,11 +591,11 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out)
     }
     Tl += 0.5 / RP(R_INV_M_TAIL) * (tv0 * tv0 + tv1 * tv1 + tv2 * tv2);
     const double Wx = -(RP(R_FX) * (tr0 - RP(R_T0X)) + RP(R_FY) * (tr1 - RP(R_T0Y)) + RP(R_FZ) * (tr2 - RP(R_T0Z)));
-    out[5 * rod + 0] = Tl;
-    out[5 * rod + 1] = Tr;
-    out[5 * rod + 2] = Us;
-    out[5 * rod + 3] = Ub;
-    out[5 * rod + 4] = Wx;
+    out[5 * row + 0] = Tl;
+    out[5 * row + 1] = Tr;
+    out[5 * row + 2] = Us;
+    out[5 * row + 3] = Ub;
+    out[5 * row + 4] = Wx;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -642,21 +643,23 @@ hipError_t launch_advance(int64_t *step, int64_t n, hipStream_t s)
 }
 
 template <typename T>
-static hipError_t launch_energy_t(const DevBatch<T> &b, double *out, hipStream_t s)
+static hipError_t launch_energy_t(const DevBatch<T> &b, double *out, const int32_t *map, int n_map, hipStream_t s)
 {
     const int bs = 64;
-    hipLaunchKernelGGL((rod_energy_kernel<T>), dim3((b.n_rods + bs - 1) / bs), dim3(bs), 0, s, b, out);
+    const int rows = map ? n_map : b.n_rods;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((rod_energy_kernel<T>), dim3((rows + bs - 1) / bs), dim3(bs), 0, s, b, out, map, n_map);
     return hipGetLastError();
 }
 
 hipError_t launch_energy(const DevBatch<double> &b, double *out, hipStream_t s)
 {
-    return launch_energy_t<double>(b, out, s);
+    return launch_energy_t<double>(b, out, nullptr, 0, s);
 }
 
-hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s)
+hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s, const int32_t *map, int n_map)
 {
-    return launch_energy_t<float>(b, out, s);
+    return launch_energy_t<float>(b, out, map, n_map, s);
 }
 
 template <typename T, int W>

@@ -77,6 +77,7 @@ struct rod_surrogate {
     int64_t *win_first = nullptr, *elem_first = nullptr;
     float *rodf = nullptr, *disp = nullptr;
     void *saved = nullptr;                   // state copy for targets / the judge
+    void *saved2 = nullptr;                  // perturbed start state of a noisy sample
     size_t saved_bytes = 0;
     // coarse stepping
     int32_t *plain = nullptr;                // device [R]: 1 = rod on the plain step
@@ -87,6 +88,7 @@ struct rod_surrogate {
     int judge_rods = 0;
     int32_t *jmap = nullptr, *jsel = nullptr;
     float *jerr = nullptr;
+    double *jen = nullptr;                   // [2][m][5] energies of the sample and its plain re-run
     int64_t judge_windows_total = 0;
 };
 
@@ -196,12 +198,16 @@ void free_ctx(rod_surrogate *s)
     (void)hipFree(s->rodf);
     (void)hipFree(s->disp);
     (void)hipFree(s->saved);
+    (void)hipFree(s->saved2);
+    s->saved2 = nullptr;
     (void)hipFree(s->plain);
     (void)hipFree(s->xall);
     (void)hipFree(s->yall);
     (void)hipFree(s->jmap);
     (void)hipFree(s->jsel);
     (void)hipFree(s->jerr);
+    (void)hipFree(s->jen);
+    s->jen = nullptr;
     if (s->judge) rod_batch_destroy(s->judge);
     s->judge = nullptr;
     s->judge_rods = 0;
@@ -300,10 +306,57 @@ rodk::DevBatch<float> saved_batch(const rod_surrogate *s, const rodk::BatchView 
     return d;
 }
 
-int save_state(rod_surrogate *s, const rodk::BatchView &v, hipStream_t st)
+int save_state(rod_surrogate *s, const rodk::BatchView &v, hipStream_t st, void *to = nullptr)
 {
-    SHIPCHK(hipMemcpyAsync(s->saved, v.f32.state, v.state_bytes, hipMemcpyDeviceToDevice, st));
-    SHIPCHK(hipMemcpyAsync((char *)s->saved + v.state_bytes, v.f32.tail, v.tail_bytes, hipMemcpyDeviceToDevice, st));
+    char *dst = (char *)(to ? to : s->saved);
+    SHIPCHK(hipMemcpyAsync(dst, v.f32.state, v.state_bytes, hipMemcpyDeviceToDevice, st));
+    SHIPCHK(hipMemcpyAsync(dst + v.state_bytes, v.f32.tail, v.tail_bytes, hipMemcpyDeviceToDevice, st));
+    return ROD_OK;
+}
+
+int restore_state(rod_surrogate *s, const rodk::BatchView &v, hipStream_t st)
+{
+    SHIPCHK(hipMemcpyAsync(v.f32.state, s->saved, v.state_bytes, hipMemcpyDeviceToDevice, st));
+    SHIPCHK(hipMemcpyAsync(v.f32.tail, (char *)s->saved + v.state_bytes, v.tail_bytes, hipMemcpyDeviceToDevice, st));
+    return ROD_OK;
+}
+
+int perturb_batch(rod_surrogate *s, const rodk::BatchView &v, const float noise[4], uint64_t seed, hipStream_t st)
+{
+    hipError_t e = surk::perturb(v.f32, s->elem_rod, s->elem_first, s->n_elems, noise, (float)(s->k * v.dt), seed, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("perturb: ") + hipGetErrorString(e));
+    return ROD_OK;
+}
+
+// One training sample.  Without noise: features now, k plain steps, targets.
+// With noise: the features are taken at a perturbed copy of the state while the
+// batch itself steps on from the clean state, so the targets lead from the
+// perturbed state back onto the plain trajectory.
+int collect_impl(rod_surrogate *s, rod_batch *b, const float *noise, uint64_t seed, float *F, float *T, float *M,
+                 hipStream_t st)
+{
+    rodk::BatchView v;
+    int rc = ensure_ctx(s, b, v);
+    if (rc) return rc;
+    const bool noisy = noise && (noise[0] != 0.f || noise[1] != 0.f || noise[2] != 0.f || noise[3] != 0.f);
+    if ((rc = save_state(s, v, st))) return rc;
+    if (noisy) {
+        if (!s->saved2) SHIPCHK(hipMalloc(&s->saved2, s->saved_bytes));
+        if ((rc = perturb_batch(s, v, noise, seed, st))) return rc;
+    }
+    hipError_t e = surk::features(win_args(s, v), F, nullptr, nullptr, nullptr, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("features: ") + hipGetErrorString(e));
+    if (noisy) {
+        if ((rc = save_state(s, v, st, s->saved2))) return rc;
+        if ((rc = restore_state(s, v, st))) return rc;
+    }
+    if ((rc = rod_step(b, s->k, st))) return rc;
+    rodk::BatchView v1;
+    if ((rc = rodk::batch_view(b, &v1))) return rc;
+    rodk::DevBatch<float> s0 = saved_batch(s, v);
+    if (noisy) s0.state = (float *)s->saved2, s0.tail = (float *)((char *)s->saved2 + v.state_bytes);
+    e = surk::targets(win_args(s, v1), s0, T, M, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("targets: ") + hipGetErrorString(e));
     return ROD_OK;
 }
 
@@ -337,8 +390,10 @@ int make_judge(rod_surrogate *s, const rodk::BatchView &v, int m, int n)
     (void)hipFree(s->jmap);
     (void)hipFree(s->jsel);
     (void)hipFree(s->jerr);
+    (void)hipFree(s->jen);
     s->jmap = s->jsel = nullptr;
     s->jerr = nullptr;
+    s->jen = nullptr;
     const int64_t Ne = (int64_t)m * n, Nn = Ne + m;
     std::vector<int32_t> ne(m, n), zero(m, 0);
     std::vector<double> pos(3 * Nn, 0.0), vel(3 * Nn, 0.0), dir(9 * Ne, 0.0), om(3 * Ne, 0.0), one(m, 1.0);
@@ -362,6 +417,7 @@ int make_judge(rod_surrogate *s, const rodk::BatchView &v, int m, int n)
     SHIPCHK(hipMalloc((void **)&s->jmap, (size_t)m * 4));
     SHIPCHK(hipMalloc((void **)&s->jsel, (size_t)m * 4));
     SHIPCHK(hipMalloc((void **)&s->jerr, (size_t)m * 8));
+    SHIPCHK(hipMalloc((void **)&s->jen, (size_t)m * 10 * sizeof(double)));
     s->judge_rods = m;
     return ROD_OK;
 }
@@ -378,6 +434,7 @@ int ensure_step_buffers(rod_surrogate *s)
 // plain ones take k plain steps.  Advances the clock by k.
 int coarse_step(rod_surrogate *s, rod_batch *b, const rodk::BatchView &v, int n_plain, hipStream_t st)
 {
+    if (n_plain == v.n_rods) return rodk::batch_step_masked(b, s->k, s->plain, st);   // nothing left to predict
     const float *mux = s->norm, *sdx = s->norm + ROD_SURROGATE_INPUTS;
     const float *mut = s->norm + 2 * ROD_SURROGATE_INPUTS, *sdt = mut + ROD_SURROGATE_OUTPUTS;
     hipError_t e = surk::features(win_args(s, v), nullptr, s->xall, mux, sdx, st);
@@ -604,19 +661,27 @@ int rod_surrogate_features(rod_surrogate *s, rod_batch *b, float *features, void
 int rod_surrogate_collect(rod_surrogate *s, rod_batch *b, float *features, float *targets, float *mask, void *stream)
 {
     if (!s || !b || !features || !targets || !mask) return sfail(ROD_EINVAL, "NULL argument");
+    return collect_impl(s, b, nullptr, 0, features, targets, mask, (hipStream_t)stream);
+}
+
+int rod_surrogate_collect_noisy(rod_surrogate *s, rod_batch *b, const float *noise, uint64_t seed, float *features,
+                                float *targets, float *mask, void *stream)
+{
+    if (!s || !b || !noise || !features || !targets || !mask) return sfail(ROD_EINVAL, "NULL argument");
+    for (int i = 0; i < 4; ++i)
+        if (!(noise[i] >= 0) || !std::isfinite(noise[i])) return sfail(ROD_EINVAL, "noise levels must be finite, >= 0");
+    return collect_impl(s, b, noise, seed, features, targets, mask, (hipStream_t)stream);
+}
+
+int rod_surrogate_perturb(rod_surrogate *s, rod_batch *b, const float *noise, uint64_t seed, void *stream)
+{
+    if (!s || !b || !noise) return sfail(ROD_EINVAL, "NULL argument");
+    for (int i = 0; i < 4; ++i)
+        if (!(noise[i] >= 0) || !std::isfinite(noise[i])) return sfail(ROD_EINVAL, "noise levels must be finite, >= 0");
     rodk::BatchView v;
     int rc = ensure_ctx(s, b, v);
     if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = surk::features(win_args(s, v), features, nullptr, nullptr, nullptr, st);
-    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("features: ") + hipGetErrorString(e));
-    if ((rc = save_state(s, v, st))) return rc;
-    if ((rc = rod_step(b, s->k, stream))) return rc;
-    rodk::BatchView v1;
-    if ((rc = rodk::batch_view(b, &v1))) return rc;
-    e = surk::targets(win_args(s, v1), saved_batch(s, v), targets, mask, st);
-    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("targets: ") + hipGetErrorString(e));
-    return ROD_OK;
+    return perturb_batch(s, v, noise, seed, (hipStream_t)stream);
 }
 
 int rod_surrogate_apply(rod_surrogate *s, rod_batch *b, const float *deltas, void *stream)
@@ -664,7 +729,8 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
     if (!s || !b || !d) return sfail(ROD_EINVAL, "NULL argument");
     if (d->warmup_steps < 0 || d->n_samples < 1 || d->sample_stride < s->k || d->epochs < 1 || d->batch_rows <= 0
         || d->batch_rows % 64 || d->batch_rows > s->max_rows || !(d->lr > 0) || !(d->lr_min >= 0)
-        || !(d->val_fraction >= 0 && d->val_fraction < 1))
+        || !(d->val_fraction >= 0 && d->val_fraction < 1) || !(d->noise[0] >= 0) || !(d->noise[1] >= 0)
+        || !(d->noise[2] >= 0) || !(d->noise[3] >= 0))
         return sfail(ROD_EINVAL, "invalid training descriptor");
     rodk::BatchView v;
     int rc = ensure_ctx(s, b, v);
@@ -723,9 +789,11 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
     } while (0)
     if (d->warmup_steps > 0) TRY(rod_step(b, d->warmup_steps, stream));
     for (int i = 0; i < d->n_samples; ++i) {
-        TRY(rod_surrogate_collect(s, b, F + (size_t)i * W * ROD_SURROGATE_INPUTS,
-                                  T + (size_t)i * W * ROD_SURROGATE_OUTPUTS, Mk + (size_t)i * W * ROD_SURROGATE_OUTPUTS,
-                                  stream));
+        // noise levels cycle through 0, 1/3, 2/3 and 1 times d->noise
+        const float f = (float)(i % 4) / 3.0f;
+        const float nz[4] = {f * d->noise[0], f * d->noise[1], f * d->noise[2], f * d->noise[3]};
+        TRY(collect_impl(s, b, nz, d->seed * 0x100000001B3ull + (uint64_t)i, F + (size_t)i * W * ROD_SURROGATE_INPUTS,
+                         T + (size_t)i * W * ROD_SURROGATE_OUTPUTS, Mk + (size_t)i * W * ROD_SURROGATE_OUTPUTS, st));
         if (i + 1 < d->n_samples && d->sample_stride > s->k) TRY(rod_step(b, d->sample_stride - s->k, stream));
     }
     // ---- standardisation from the whole data set
@@ -808,7 +876,7 @@ int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const r
 {
     if (!s || !b || !j) return sfail(ROD_EINVAL, "NULL argument");
     if (n_coarse < 0 || j->judge_every <= 0 || !(j->judge_fraction > 0 && j->judge_fraction <= 1)
-        || !(j->max_pos_error >= 0) || !(j->max_orth_error >= 0))
+        || !(j->max_pos_error >= 0) || !(j->max_orth_error >= 0) || !(j->max_energy_error >= 0))
         return sfail(ROD_EINVAL, "invalid judge descriptor");
     rodk::BatchView v;
     int rc = ensure_ctx(s, b, v);
@@ -827,6 +895,7 @@ int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const r
     for (int32_t f : s->plain_h) n_plain += f != 0;
     std::vector<int32_t> map;
     std::vector<float> err;
+    std::vector<double> en;
     int64_t c = 0;
     while (c < n_coarse) {
         // ---- open a judge window: sample rods still on the coarse step
@@ -866,16 +935,28 @@ int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const r
         if ((rc = rodk::batch_view(b, &cv)) || (rc = rodk::batch_view(s->judge, &jv2))) return rc;
         hipError_t e = surk::judge_errors(cv.f32, jv2.f32, s->jmap, m, s->jerr, st);
         if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("judge errors: ") + hipGetErrorString(e));
+        e = rodk::launch_energy(cv.f32, s->jen, st, s->jmap, m);
+        if (e == hipSuccess) e = rodk::launch_energy(jv2.f32, s->jen + 5 * (size_t)m, st);
+        if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("judge energies: ") + hipGetErrorString(e));
         err.resize(2 * (size_t)m);
+        en.resize(10 * (size_t)m);
         SHIPCHK(hipMemcpyAsync(err.data(), s->jerr, err.size() * 4, hipMemcpyDeviceToHost, st));
+        SHIPCHK(hipMemcpyAsync(en.data(), s->jen, en.size() * 8, hipMemcpyDeviceToHost, st));
         SHIPCHK(hipStreamSynchronize(st));
         std::vector<int32_t> fail_sel(m, 0);
         int nf = 0;
         for (int k = 0; k < mw; ++k) {
             const double pe = err[2 * k], oe = err[2 * k + 1];
+            // strain energy (shear + bending) against the plain re-run, relative to the
+            // re-run's mechanical energy (kinetic + strain)
+            const double *a = &en[5 * (size_t)k], *p = &en[5 * ((size_t)m + k)];
+            const double du = std::fabs((a[2] + a[3]) - (p[2] + p[3]));
+            const double den = p[0] + p[1] + p[2] + p[3];
+            const double ue = du == 0.0 ? 0.0 : (den > 0.0 ? du / den : INFINITY);
             out.max_pos_error = std::max(out.max_pos_error, std::isfinite(pe) ? pe : INFINITY);
             out.max_orth_error = std::max(out.max_orth_error, std::isfinite(oe) ? oe : INFINITY);
-            if (!(pe <= j->max_pos_error) || !(oe <= j->max_orth_error)) {
+            out.max_energy_error = std::max(out.max_energy_error, std::isfinite(ue) ? ue : INFINITY);
+            if (!(pe <= j->max_pos_error) || !(oe <= j->max_orth_error) || !(ue <= j->max_energy_error)) {
                 fail_sel[k] = 1;
                 s->plain_h[map[k]] = 1;
                 ++nf;

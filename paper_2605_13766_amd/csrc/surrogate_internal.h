@@ -36,6 +36,9 @@ hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, 
 // dst rod k <-> src rod map[k] (to_src: copy back into src); sel[k] == 0 skips k
 hipError_t copy_rods(const rodk::DevBatch<float> &dst, const rodk::DevBatch<float> &src, const int32_t *map,
                      const int32_t *sel, int n_map, int n, bool state_only, bool to_src, hipStream_t s);
+// seeded perturbation of the free state (positions, velocities, frames, omega), in place
+hipError_t perturb(const rodk::DevBatch<float> &B, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems,
+                   const float noise[4], float tau, uint64_t seed, hipStream_t s);
 hipError_t colstats(const float *a, const float *mask, int64_t rows, int cols, double *out, hipStream_t s);
 hipError_t judge_errors(const rodk::DevBatch<float> &main, const rodk::DevBatch<float> &ref, const int32_t *map,
                         int n_map, float *err, hipStream_t s);

@@ -432,6 +432,90 @@ __global__ void judge_errors_kernel(DevBatch<float> main, DevBatch<float> ref, c
     err[2 * k + 1] = orth;
 }
 
+// Counter-based normal deviates: the splitmix64 output function (Steele, Lea
+// and Flood 2014) hashes (seed, key) to 64 bits, Box-Muller turns two 24-bit
+// uniforms into one N(0, 1) value.
+__device__ inline uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ inline float gauss(uint64_t seed, uint64_t key)
+{
+    const uint64_t h = mix64(seed ^ mix64(key));
+    const float u1 = ((float)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
+    const float u2 = ((float)(h & 0xFFFFFFull) + 0.5f) * (1.0f / 16777216.0f);
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+// key of component a (0-2) of quantity kind (0 position, 1 velocity, 2 rotation, 3 omega) at node/element j of rod r
+__device__ inline uint64_t noise_key(int r, int j, int kind, int a)
+{
+    return ((uint64_t)(uint32_t)r << 32) | ((uint64_t)(uint32_t)j << 4) | (uint64_t)(3 * kind + a);
+}
+
+// Perturb the free part of every rod in place: node positions by
+// noise[0] lh N(0, 1), node velocities by noise[1] lh / tau N(0, 1), each
+// director frame by the rotation exp(-[noise[2] g]x), g ~ N(0, I), and
+// angular velocities by noise[3] / tau N(0, 1) (lh of the node's own element,
+// element n-1 for node n).  Clamped nodes and elements are left alone.  One
+// thread per element: element c moves edge c by the noise of nodes c and c+1.
+__global__ void perturb_kernel(DevBatch<float> B, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems,
+                               float4 noise, float tau, uint64_t seed)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elems) return;
+    const int r = elem_rod[e];
+    const Rod R(B, r);
+    const int n = R.n;
+    const int c = (int)(e - elem_first[r]);
+    const int flags = B.rod_flags[r];
+    const bool c0 = flags & rodk::FLAG_CLAMP0, c1 = flags & rodk::FLAG_CLAMP1;
+    auto node_fixed = [&](int j) { return (j == 0 && c0) || (j == n && c1); };
+    auto node_noise = [&](int j, int kind, float scale) -> V3 {
+        if (node_fixed(j) || scale == 0.f) return {0.f, 0.f, 0.f};
+        const float L = R.lh(j < n ? j : n - 1) * scale;
+        return {L * gauss(seed, noise_key(r, j, kind, 0)), L * gauss(seed, noise_key(r, j, kind, 1)),
+                L * gauss(seed, noise_key(r, j, kind, 2))};
+    };
+    float *st = B.state;
+    const int64_t NS = B.n_slots, sl = R.s0 + c;
+    const V3 d0 = node_noise(c, 0, noise.x), d1 = node_noise(c + 1, 0, noise.x);
+    st[rodk::RX * NS + sl] += d1.x - d0.x;
+    st[rodk::RY * NS + sl] += d1.y - d0.y;
+    st[rodk::RZ * NS + sl] += d1.z - d0.z;
+    if (c == 0) {
+        B.tail[rodk::TRX * B.n_rods + r] += d0.x;
+        B.tail[rodk::TRY * B.n_rods + r] += d0.y;
+        B.tail[rodk::TRZ * B.n_rods + r] += d0.z;
+    }
+    const float vs = noise.y / tau;
+    const V3 dv = node_noise(c, 1, vs);
+    st[rodk::VX * NS + sl] += dv.x;
+    st[rodk::VY * NS + sl] += dv.y;
+    st[rodk::VZ * NS + sl] += dv.z;
+    if (c == n - 1) {
+        const V3 dn = node_noise(n, 1, vs);
+        B.tail[rodk::TVX * B.n_rods + r] += dn.x;
+        B.tail[rodk::TVY * B.n_rods + r] += dn.y;
+        B.tail[rodk::TVZ * B.n_rods + r] += dn.z;
+    }
+    if ((c == 0 && c0) || (c == n - 1 && c1)) return;
+    if (noise.z != 0.f) {
+        float q[9];
+        R.dirs(c, q);
+        const V3 g{gauss(seed, noise_key(r, c, 2, 0)), gauss(seed, noise_key(r, c, 2, 1)),
+                   gauss(seed, noise_key(r, c, 2, 2))};
+        rotate_left(q, V3{-noise.z * g.x, -noise.z * g.y, -noise.z * g.z});
+        for (int k = 0; k < 9; ++k) st[(rodk::Q00 + k) * NS + sl] = q[k];
+    }
+    const float ws = noise.w / tau;
+    st[rodk::WX * NS + sl] += ws * gauss(seed, noise_key(r, c, 3, 0));
+    st[rodk::WY * NS + sl] += ws * gauss(seed, noise_key(r, c, 3, 1));
+    st[rodk::WZ * NS + sl] += ws * gauss(seed, noise_key(r, c, 3, 2));
+}
+
 // ---------------------------------------------------------------- launchers
 static inline dim3 blocks(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
@@ -472,6 +556,15 @@ hipError_t copy_rods(const DevBatch<float> &dst, const DevBatch<float> &src, con
 {
     hipLaunchKernelGGL(copy_rods_kernel, blocks((int64_t)n_map * n), dim3(256), 0, s, dst, src, map, sel, n_map, n,
                        state_only, to_src);
+    return hipGetLastError();
+}
+
+hipError_t perturb(const DevBatch<float> &B, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems,
+                   const float noise[4], float tau, uint64_t seed, hipStream_t s)
+{
+    const float4 nz{noise[0], noise[1], noise[2], noise[3]};
+    hipLaunchKernelGGL(perturb_kernel, blocks(n_elems), dim3(256), 0, s, B, elem_rod, elem_first, n_elems, nz, tau,
+                       seed);
     return hipGetLastError();
 }
 

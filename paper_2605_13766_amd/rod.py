@@ -49,18 +49,18 @@ SURROGATE_INPUTS, SURROGATE_OUTPUTS, SURROGATE_PARAMS = 96, 12, 159500
 class TrainDesc(C.Structure):
     _fields_ = [("warmup_steps", C.c_int32), ("n_samples", C.c_int32), ("sample_stride", C.c_int32),
                 ("epochs", C.c_int32), ("batch_rows", C.c_int32), ("lr", C.c_float), ("lr_min", C.c_float),
-                ("val_fraction", C.c_float), ("seed", C.c_uint64)]
+                ("val_fraction", C.c_float), ("seed", C.c_uint64), ("noise", C.c_float * 4)]
 
 
 class JudgeDesc(C.Structure):
     _fields_ = [("judge_every", C.c_int32), ("judge_fraction", C.c_float), ("max_pos_error", C.c_float),
-                ("max_orth_error", C.c_float), ("seed", C.c_uint64)]
+                ("max_orth_error", C.c_float), ("seed", C.c_uint64), ("max_energy_error", C.c_float)]
 
 
 class SurrogateStats(C.Structure):
     _fields_ = [("coarse_steps", C.c_int64), ("judge_windows", C.c_int64), ("rods_judged", C.c_int64),
                 ("rods_failed", C.c_int64), ("rods_plain", C.c_int64), ("max_pos_error", C.c_double),
-                ("max_orth_error", C.c_double)]
+                ("max_orth_error", C.c_double), ("max_energy_error", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +81,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2605_13766_amd.build")
+        # torch ships its own HIP runtime under the same soname as the system one the
+        # library links; loading torch first makes both use torch's, whichever of
+        # them the caller touches first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.rod_batch_create.argtypes = [C.POINTER(RodBatchDesc), vp, C.POINTER(vp)]
@@ -115,13 +122,16 @@ def lib():
         L.rod_surrogate_fallback_flags.argtypes = [vp, vp, _ip]
         L.rod_surrogate_reset_fallback.argtypes = [vp, vp]
         L.rod_surrogate_save.argtypes = [vp, C.c_char_p]
+        L.rod_surrogate_perturb.argtypes = [vp, vp, fp, C.c_uint64, vp]
+        L.rod_surrogate_collect_noisy.argtypes = [vp, vp, fp, C.c_uint64, vp, vp, vp, vp]
         L.rod_surrogate_load.argtypes = [vp, C.c_char_p]
         for f in ("rod_surrogate_create", "rod_surrogate_set_params", "rod_surrogate_get_params",
                   "rod_surrogate_forward", "rod_surrogate_gradients", "rod_surrogate_train_step",
                   "rod_surrogate_features", "rod_surrogate_collect", "rod_surrogate_apply",
                   "rod_surrogate_set_normalization", "rod_surrogate_get_normalization",
                   "rod_surrogate_train", "rod_surrogate_step", "rod_surrogate_fallback_flags",
-                  "rod_surrogate_reset_fallback", "rod_surrogate_save", "rod_surrogate_load"):
+                  "rod_surrogate_reset_fallback", "rod_surrogate_save", "rod_surrogate_load",
+                  "rod_surrogate_perturb", "rod_surrogate_collect_noisy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -305,6 +315,16 @@ class Surrogate:
         _check(lib().rod_surrogate_collect(self._h, batch._h, _dptr(feat), _dptr(targ), _dptr(mask),
                                            _stream_ptr(stream)))
 
+    def collect_noisy(self, batch, noise, seed, feat, targ, mask, stream=None):
+        nz = np.ascontiguousarray(noise, dtype=np.float32)
+        _check(lib().rod_surrogate_collect_noisy(self._h, batch._h, nz.ctypes.data_as(C.POINTER(C.c_float)), int(seed),
+                                                 _dptr(feat), _dptr(targ), _dptr(mask), _stream_ptr(stream)))
+
+    def perturb(self, batch, noise, seed, stream=None):
+        nz = np.ascontiguousarray(noise, dtype=np.float32)
+        _check(lib().rod_surrogate_perturb(self._h, batch._h, nz.ctypes.data_as(C.POINTER(C.c_float)), int(seed),
+                                           _stream_ptr(stream)))
+
     def apply(self, batch, deltas, stream=None):
         _check(lib().rod_surrogate_apply(self._h, batch._h, _dptr(deltas), _stream_ptr(stream)))
 
@@ -318,9 +338,10 @@ class Surrogate:
         return a
 
     def train(self, batch, warmup_steps=0, n_samples=2, sample_stride=None, epochs=2, batch_rows=4096,
-              lr=1e-3, lr_min=1e-5, val_fraction=0.1, seed=0, stream=None):
+              lr=1e-3, lr_min=1e-5, val_fraction=0.1, seed=0, noise=(0.0, 0.0, 0.0, 0.0), stream=None):
         d = TrainDesc(int(warmup_steps), int(n_samples), int(sample_stride or self.k), int(epochs),
-                      int(batch_rows), float(lr), float(lr_min), float(val_fraction), int(seed))
+                      int(batch_rows), float(lr), float(lr_min), float(val_fraction), int(seed),
+                      (C.c_float * 4)(*[float(x) for x in noise]))
         ep = np.empty(int(epochs), dtype=np.float32)
         vl = C.c_float()
         _check(lib().rod_surrogate_train(self._h, batch._h, C.byref(d), ep.ctypes.data_as(C.POINTER(C.c_float)),
@@ -328,10 +349,11 @@ class Surrogate:
         return ep, vl.value
 
     def step(self, batch, n_coarse, judge_every=8, judge_fraction=0.01, max_pos_error=1e-3,
-             max_orth_error=1e-5, seed=0, stream=None) -> dict:
+             max_orth_error=1e-5, seed=0, max_energy_error=5e-2, stream=None) -> dict:
         """n_coarse learned coarse steps (k plain steps each) with the plain
         integrator judging a sample of rods every judge_every steps."""
-        j = JudgeDesc(int(judge_every), float(judge_fraction), float(max_pos_error), float(max_orth_error), int(seed))
+        j = JudgeDesc(int(judge_every), float(judge_fraction), float(max_pos_error), float(max_orth_error), int(seed),
+                      float(max_energy_error))
         st = SurrogateStats()
         _check(lib().rod_surrogate_step(self._h, batch._h, int(n_coarse), C.byref(j), C.byref(st),
                                         _stream_ptr(stream)))

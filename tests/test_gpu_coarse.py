@@ -1,0 +1,271 @@
+"""The learned coarse step end to end on the GPU: one step against the FP64
+oracle (features, network, apply), the judge and its fallback, the training
+perturbation, save/load, and what the trained network gains over the same
+coarse step without it (free flight: zero departures).
+
+Rods: the carpet regime at 64 elements (clamped base, 10 Hz couple), FP32.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from oracle import surrogate_oracle as S
+from paper_2605_13766_amd import workloads as W
+from surrcases import N, L, carpet, oracle_run, gpu_batch, gpu_state as _state, pos_err as _pos_err
+
+pytestmark = pytest.mark.gpu
+
+K = 32
+
+
+def _rods(n_rods, seed_shift=0, warm=2000):
+    """GPU-warmed batch (for GPU-against-GPU comparisons only)."""
+    inp = carpet(n_rods, seed_shift)
+    b = gpu_batch(inp)
+    b.step(warm)
+    return inp, b
+
+
+NO_JUDGE = dict(judge_every=8, judge_fraction=0.01, max_pos_error=1e30, max_orth_error=1e30,
+                max_energy_error=1e30)
+
+
+def _random_net(s, seed=11, out_scale=2e-6):
+    """Oracle-initialised weights and a fixed standardisation (inputs scaled
+    to O(1) for the carpet state, outputs to out_scale)."""
+    p = MO.init_params(seed)
+    s.set_params(MO.flatten(p))
+    mu_x = np.zeros(96, np.float32)
+    sd_x = np.full(96, 1e-2, np.float32)
+    sd_x[80:] = 1.0
+    mu_t = np.zeros(12, np.float32)
+    sd_t = np.full(12, out_scale, np.float32)
+    s.set_normalization(mu_x, sd_x, mu_t, sd_t)
+    return p, (mu_x, sd_x, mu_t, sd_t)
+
+
+def test_coarse_step_matches_oracle():
+    """rod_surrogate_step (no judge fires) = oracle features, standardisation,
+    BF16 network and apply.  Bar: the state change against the oracle's,
+    2e-3 of its norm and 2e-2 of each column's largest change: FP32 vs FP64
+    features move a few standardised inputs across a BF16 rounding boundary
+    (one BF16 ulp, 2^-8 relative), on top of the network's own 1e-4.  Columns
+    whose change is below 1e-3 of the quantity's largest change (frame entries
+    that barely move) are measured on that scale."""
+    from paper_2605_13766_amd import rod
+    inp = carpet(8)
+    s0, t0 = oracle_run(inp, 2000)
+    b = gpu_batch(inp, s0, t0)
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    params, (mx, sx, mt, st_) = _random_net(s)
+    stats = s.step(b, 1, **NO_JUDGE)
+    assert stats["coarse_steps"] == 1 and stats["rods_failed"] == 0
+    s1, t1 = _state(b)
+    assert abs(t1 - t0 - K * inp.dt) < 1e-12
+    F = S.window_features(inp, s0, t0, K)
+    x = MO.bf16_round((F - mx) / sx)
+    y = MO.forward(params, x, bf16=True)[0]
+    D = y * st_ + mt
+    ref = S.apply_deltas(inp, s0, D, K)
+    for got, r0, rr, name in zip(s1, s0, ref, ("pos", "vel", "dir", "omega")):
+        dg = (got - r0).reshape(len(got), -1)
+        do = (rr - r0).reshape(len(rr), -1)
+        nrm = np.linalg.norm(dg - do) / np.linalg.norm(do)
+        # columns whose change is below 1e-3 of the largest are measured on that scale
+        scale = np.maximum(np.abs(do).max(axis=0), 1e-3 * np.abs(do).max())
+        col = (np.abs(dg - do).max(axis=0) / scale).max()
+        print(name, "normwise", nrm, "columnwise", col)
+        assert nrm <= 2e-3 and col <= 2e-2, name
+    s.close()
+    b.close()
+
+
+def test_forced_fallback_gives_the_plain_result():
+    """Thresholds 0 and every rod judged: the first window fails every rod,
+    which takes the plain state and stays plain, so the result is the plain
+    integrator's (up to the rounding of the couple's time argument)."""
+    from paper_2605_13766_amd import rod
+    inp, b = _rods(16)
+    _, ref = _rods(16)
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    _random_net(s)
+    st = s.step(b, 3, judge_every=1, judge_fraction=1.0, max_pos_error=0.0, max_orth_error=0.0,
+                max_energy_error=0.0)
+    ref.step(3 * K)
+    assert st["judge_windows"] == 1 and st["rods_judged"] == 16 and st["rods_failed"] == 16
+    assert st["rods_plain"] == 16
+    assert np.all(s.fallback_flags(b) == 1)
+    e = _pos_err(ref, b)
+    print("fallback vs plain", e.max())
+    assert e.max() <= 1e-6
+    (_, tb), (_, tr) = _state(b), _state(ref)
+    assert abs(tb - tr) < 1e-12
+    s.reset_fallback(b)
+    assert np.all(s.fallback_flags(b) == 0)
+    s.close()
+    b.close()
+    ref.close()
+
+
+def test_judge_counts_and_sampling():
+    """Thresholds that nothing exceeds: no fallback; judge_fraction of the rods
+    (rounded, at least one) judged per window; the seed fixes the sample."""
+    from paper_2605_13766_amd import rod
+    inp, b = _rods(200)
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    _random_net(s, out_scale=1e-9)
+    st = s.step(b, 16, judge_every=4, judge_fraction=0.05, max_pos_error=1e30, max_orth_error=1e30,
+                max_energy_error=1e30)
+    assert st["coarse_steps"] == 16 and st["judge_windows"] == 4 and st["rods_judged"] == 40
+    assert st["rods_failed"] == 0 and st["rods_plain"] == 0
+    assert 0 < st["max_pos_error"] < 1e-3 and st["max_orth_error"] < 1e-6
+    assert np.all(s.fallback_flags(b) == 0)
+    s.close()
+    b.close()
+
+
+def test_perturbation_against_oracle():
+    """The perturbation kernel against the oracle's (same counter-based
+    generator): zero noise leaves the state bitwise; otherwise the change
+    agrees to 1e-5 of each quantity's noise scale (FP32 log / cos of the
+    Box-Muller transform and FP32 state) and frames stay orthonormal."""
+    from paper_2605_13766_amd import rod
+    inp = carpet(64)
+    st0, t0 = oracle_run(inp, 500)
+    b = gpu_batch(inp, st0, t0)
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    g0, _ = _state(b)
+    s.perturb(b, [0, 0, 0, 0], 1)
+    z, _ = _state(b)
+    for a, c in zip(g0, z):
+        assert np.array_equal(a, c)
+    sig = [1e-3, 2e-3, 3e-3, 4e-3]
+    s.perturb(b, sig, 5)
+    g1, _ = _state(b)
+    ref = S.perturb(inp, st0, sig, 5, K)
+    lh, tau = L / N, K * inp.dt
+    scales = (sig[0] * lh, sig[1] * lh / tau, sig[2], sig[3] / tau)
+    for a0, a1, r1, sc, name in zip(st0, g1, ref, scales, ("pos", "vel", "dir", "omega")):
+        err = np.abs((a1 - np.asarray(a0).reshape(a1.shape)) - (r1 - np.asarray(a0).reshape(r1.shape))).max() / sc
+        print(name, err)
+        assert err <= 1e-2 if name == "pos" else err <= 1e-3, name
+    QQ = np.einsum("iab,icb->iac", g1[2], g1[2]) - np.eye(3)
+    assert np.abs(QQ).max() < 1e-6
+    s.close()
+    b.close()
+
+
+def test_noisy_collect_against_oracle():
+    """Features of the perturbed state, targets from the perturbed state to
+    the plain result of the unperturbed one; the oracle perturbs and steps in
+    FP64.  Bars: features as the clean data path (2e-5 of the column scale);
+    targets 2e-5 of the column scale plus the FP32 plain step's own drift
+    from FP64 over k steps, measured by the plain comparison alongside."""
+    import torch
+    from paper_2605_13766_amd import rod
+    inp = carpet(12)
+    st0, t0 = oracle_run(inp, 1000)
+    b = gpu_batch(inp, st0, t0)
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    sig = [3e-5, 5e-5, 1e-4, 2e-4]
+    Wn = s.n_windows(b)
+    F = torch.empty((Wn, 96), dtype=torch.float32, device="cuda")
+    T = torch.empty((Wn, 12), dtype=torch.float32, device="cuda")
+    M = torch.empty((Wn, 12), dtype=torch.float32, device="cuda")
+    s.collect_noisy(b, sig, 9, F, T, M)
+    torch.cuda.synchronize()
+    sp = S.perturb(inp, st0, sig, 9, K)
+    s1, t1 = oracle_run(inp, K, st0, t0)
+    refF = S.window_features(inp, sp, t0, K)
+    refT, refM = S.window_targets(inp, sp, s1, K)
+    g = F.cpu().numpy().astype(np.float64)
+    fe = (np.abs(g - refF) / np.maximum(1.0, np.abs(refF).max(axis=0))).max()
+    g = T.cpu().numpy().astype(np.float64)
+    te = np.abs(g - refT).max(axis=0) / np.maximum(1.0, np.abs(refT).max(axis=0))
+    drift = _pos_err(s1, b).max() * L / (L / N)   # FP32 plain vs FP64 oracle, in rest lengths
+    print("features", fe, "targets", te, "plain drift / lh", drift)
+    assert fe <= 2e-5
+    assert te.max() <= 2e-5 + 2 * drift
+    assert np.array_equal(M.cpu().numpy(), refM)
+    s.close()
+    b.close()
+
+
+def test_save_load_roundtrip(tmp_path):
+    from paper_2605_13766_amd import rod
+    s = rod.Surrogate(k_substeps=K, seed=3)
+    _random_net(s, seed=4)
+    f = str(tmp_path / "net.bin")
+    s.save(f)
+    t = rod.Surrogate(k_substeps=K, seed=0)
+    t.load(f)
+    assert np.array_equal(s.get_params(), t.get_params())
+    for a, c in zip(s.get_normalization(), t.get_normalization()):
+        assert np.array_equal(a, c)
+    u = rod.Surrogate(k_substeps=16, seed=0)
+    with pytest.raises(rod.RodError):
+        u.load(f)
+    bad = str(tmp_path / "bad.bin")
+    with open(f, "rb") as fi, open(bad, "wb") as fo:
+        fo.write(fi.read()[:1000])
+    with pytest.raises(rod.RodError):
+        t.load(bad)
+    for h in (s, t, u):
+        h.close()
+
+
+def test_trained_network_gains_over_free_flight():
+    """Train on the 16,384-rod training set (perturbed samples), then advance
+    256 unseen rods.  Against the plain integrator, the median position error
+    of the trained coarse step is at most 0.6 of the free-flight coarse step's
+    (the same step with zero departures) after one coarse step and at most
+    0.85 after four, and its median shear-energy error (relative to the
+    rod's mechanical energy) at most 0.05 of free flight's, which leaves
+    positions and frames inconsistent; with every rod judged every 8 steps at
+    the 1e-3 / 1e-5 / 5e-2 thresholds, every rod ends within 1e-3 of the plain
+    result after 16 coarse steps (512 plain steps) and not every rod needed
+    the fallback."""
+    import torch
+    from paper_2605_13766_amd import rod
+    tr = W.surrogate_training(n_rods=16384, n=N)
+    btr = rod.RodBatch(tr, precision="f32")
+    s = rod.Surrogate(k_substeps=K, seed=1)
+    ep, val = s.train(btr, warmup_steps=2000, n_samples=8, sample_stride=1500, epochs=8, batch_rows=4096,
+                      lr=1e-3, lr_min=1e-5, val_fraction=0.1, seed=7, noise=(1e-4, 1.5e-4, 3e-4, 6e-4))
+    print("epoch losses", ep, "validation", val)
+    btr.close()
+    inp, net = _rods(256, seed_shift=17)
+    _, ff = _rods(256, seed_shift=17)
+    _, ref = _rods(256, seed_shift=17)
+    s0 = rod.Surrogate(k_substeps=K, seed=0)
+    zero = torch.zeros((s0.n_windows(ff), 12), dtype=torch.float32, device="cuda")
+    done = 0
+    res, shear = {}, {}
+    for H in (1, 4):
+        s.step(net, H - done, **NO_JUDGE)
+        for _ in range(H - done):
+            s0.apply(ff, zero)
+        ref.step((H - done) * K)
+        done = H
+        res[H] = (np.median(_pos_err(ref, net)), np.median(_pos_err(ref, ff)))
+        Er, En, Ef = ref.energy(), net.energy(), ff.energy()
+        mech = Er[:, :4].sum(axis=1)
+        shear[H] = tuple(np.median(np.abs(E[:, 2] - Er[:, 2]) / mech) for E in (En, Ef))
+        print("H", H, "position: trained", res[H][0], "free flight", res[H][1], "ratio", res[H][0] / res[H][1],
+              "| shear energy: trained", shear[H][0], "free flight", shear[H][1])
+    _, j = _rods(256, seed_shift=17)
+    _, jr = _rods(256, seed_shift=17)
+    st = s.step(j, 16, judge_every=8, judge_fraction=1.0, max_pos_error=1e-3, max_orth_error=1e-5,
+                max_energy_error=5e-2, seed=2)
+    jr.step(16 * K)
+    e = _pos_err(jr, j)
+    print("judged run", st, "end-to-end max", e.max(), "median", np.median(e))
+    assert res[1][0] <= 0.6 * res[1][1]
+    assert res[4][0] <= 0.85 * res[4][1]
+    assert shear[4][0] <= 0.05 * shear[4][1]
+    assert e.max() <= 1e-3
+    assert st["judge_windows"] == 2 and st["rods_plain"] < 256
+    for h in (s, s0, net, ff, ref, j, jr):
+        h.close()

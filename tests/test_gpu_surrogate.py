@@ -1,16 +1,19 @@
 """GPU parity of the learned coarse step's data path against the FP64 oracle
 (features, training targets, applying deltas) and a short training run.
 
-The GPU works on the FP32 batch state; the oracle reads the same state back
-through rod_get_state (FP64).  Bars: 2e-5 of the column's scale (max(1,
-max |column|)) for features, targets and applied states: FP32 rounding of the
-frame products and of element-midpoint offsets, nothing systematic.
+Start states come from the FP64 oracle and are loaded into the FP32 batch;
+the oracle evaluates the same FP64 states.  Bars: 2e-5 of the column's scale
+(max(1, max |column|)) for features and applied states: FP32 rounding of the
+state, of the frame products and of element-midpoint offsets, nothing
+systematic.  Targets add the FP32 plain step's own drift from FP64 over the
+k steps.
 """
 import numpy as np
 import pytest
 
 from oracle import surrogate_oracle as S
 from paper_2605_13766_amd import workloads as W
+from surrcases import oracle_run, gpu_batch, pos_err
 
 pytestmark = pytest.mark.gpu
 
@@ -18,11 +21,9 @@ K = 32
 
 
 def _batch(n_rods=24, n=64, warm=3000):
-    from paper_2605_13766_amd import rod
     inp = W.surrogate_training(n_rods=n_rods, n=n)
-    b = rod.RodBatch(inp, precision="f32")
-    b.step(warm)
-    return inp, b
+    st, t = oracle_run(inp, warm)
+    return inp, gpu_batch(inp, st, t), (st, t)
 
 
 def _st(b):
@@ -39,13 +40,12 @@ def _close(got, ref, tol=2e-5):
 def test_feature_parity():
     import torch
     from paper_2605_13766_amd import rod
-    inp, b = _batch()
+    inp, b, (st, t) = _batch()
     s = rod.Surrogate(k_substeps=K, seed=0)
     Wn = s.n_windows(b)
     F = torch.empty((Wn, 96), dtype=torch.float32, device="cuda")
     s.features(b, F)
     torch.cuda.synchronize()
-    st, t = _st(b)
     ref = S.window_features(inp, st, t, K)
     _close(F.cpu().numpy().astype(np.float64), ref)
     s.close()
@@ -55,20 +55,22 @@ def test_feature_parity():
 def test_collect_targets_parity():
     import torch
     from paper_2605_13766_amd import rod
-    inp, b = _batch(16, 64, 2000)
+    inp, b, (s0, t0) = _batch(16, 64, 2000)
     s = rod.Surrogate(k_substeps=K, seed=0)
     Wn = s.n_windows(b)
     F = torch.empty((Wn, 96), dtype=torch.float32, device="cuda")
     T = torch.empty((Wn, 12), dtype=torch.float32, device="cuda")
     M = torch.empty((Wn, 12), dtype=torch.float32, device="cuda")
-    s0, t0 = _st(b)
     s.collect(b, F, T, M)
     torch.cuda.synchronize()
-    s1, t1 = _st(b)
+    _, t1 = _st(b)
     assert abs(t1 - t0 - K * inp.dt) < 1e-12
+    s1, _ = oracle_run(inp, K, s0, t0)
     refT, refM = S.window_targets(inp, s0, s1, K)
     assert np.array_equal(M.cpu().numpy(), refM)
-    _close(T.cpu().numpy().astype(np.float64), refT)
+    drift = pos_err(s1, b).max() * 64   # FP32 plain vs FP64 oracle, in rest lengths
+    print("plain drift / lh", drift)
+    _close(T.cpu().numpy().astype(np.float64), refT, 2e-5 + 2 * drift)
     _close(F.cpu().numpy().astype(np.float64), S.window_features(inp, s0, t0, K))
     s.close()
     b.close()
@@ -77,12 +79,11 @@ def test_collect_targets_parity():
 def test_apply_parity():
     import torch
     from paper_2605_13766_amd import rod
-    inp, b = _batch(12, 64, 1000)
+    inp, b, (s0, t0) = _batch(12, 64, 1000)
     s = rod.Surrogate(k_substeps=K, seed=0)
     Wn = s.n_windows(b)
     rng = np.random.default_rng(3)
     D = rng.normal(0, 1e-3, (Wn, 12))
-    s0, t0 = _st(b)
     s.apply(b, torch.tensor(D, dtype=torch.float32, device="cuda"))
     torch.cuda.synchronize()
     s1, t1 = _st(b)
@@ -95,15 +96,17 @@ def test_apply_parity():
 
 
 def test_training_learns_the_coarse_step():
-    """Trajectories of 64 carpet rods: validation loss (standardised targets,
-    variance 1 each) well below the 1 of predicting the mean."""
+    """Trajectories of 1024 carpet rods (clean samples): the validation loss
+    (standardised targets, variance 1 each, so predicting the mean scores 1)
+    falls to a fraction of 1, and the epoch losses fall."""
     from paper_2605_13766_amd import rod
-    inp, b = _batch(64, 64, 0)
+    inp = W.surrogate_training(n_rods=1024, n=64)
+    b = gpu_batch(inp)
     s = rod.Surrogate(k_substeps=K, seed=1, max_rows=4096)
-    ep, val = s.train(b, warmup_steps=2000, n_samples=8, sample_stride=500, epochs=6, batch_rows=1024,
-                      lr=2e-3, lr_min=1e-4, val_fraction=0.1, seed=5)
+    ep, val = s.train(b, warmup_steps=2000, n_samples=8, sample_stride=1000, epochs=6, batch_rows=2048,
+                      lr=1e-3, lr_min=1e-5, val_fraction=0.1, seed=5)
     print("epoch losses", ep, "validation", val)
-    assert ep[-1] < ep[0]
-    assert val < 0.2
+    assert ep[-1] < 0.8 * ep[0]
+    assert val < 0.35
     s.close()
     b.close()

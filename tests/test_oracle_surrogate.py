@@ -99,3 +99,49 @@ def test_targets_rigid_translation_and_spin():
         s3 = (nodes, np.zeros_like(nodes), np.einsum("ab,ibc->iac", E, Q), np.tile([0, 0, w], (n, 1)))
         T2, _ = S.window_targets(inp, s2, s3, 32)
         assert np.allclose(T2[:n, 6:9], [0, 0, want], atol=1e-13)
+
+
+def test_splitmix64_published_values():
+    """splitmix64 with state 0 yields 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+    0x06C45D188009454F as its first outputs (the generator's published
+    reference sequence: output k is the mixer applied to k times the
+    golden-ratio increment)."""
+    gamma = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for k, w in enumerate(want):
+        z = np.uint64((k * gamma) & ((1 << 64) - 1))
+        assert int(S._mix64(z)) == w
+
+
+def test_perturbation_statistics_and_clamps():
+    """Zero noise is the identity; the seed fixes the draw; clamped base node
+    and element untouched; node offsets / lh, velocity offsets tau / lh,
+    rotation vectors and angular velocity offsets tau are N(0, s^2) per
+    component (mean and std within sampling error of 60k draws)."""
+    inp = W.surrogate_at_scale(n_rods=320, n=64)
+    st = (inp.position, inp.velocity, inp.director, inp.omega)
+    z = S.perturb(inp, st, [0, 0, 0, 0], 3, 32)
+    for a, b in zip(st, z):
+        assert np.array_equal(np.asarray(a, float).reshape(b.shape), b)
+    sig = [1e-3, 2e-3, 3e-3, 4e-3]
+    p1 = S.perturb(inp, st, sig, 5, 32)
+    p2 = S.perturb(inp, st, sig, 5, 32)
+    p3 = S.perturb(inp, st, sig, 6, 32)
+    for a, b in zip(p1, p2):
+        assert np.array_equal(a, b)
+    assert not np.array_equal(p1[0], p3[0])
+    lh, tau, n = 0.01 / 64, 32 * inp.dt, 64
+    dp = (p1[0] - inp.position).reshape(-1, n + 1, 3)
+    assert np.all(dp[:, 0] == 0)
+    dv = (p1[1] - inp.velocity).reshape(-1, n + 1, 3)
+    Q0 = np.asarray(inp.director).reshape(-1, n, 3, 3)
+    Q1 = p1[2].reshape(-1, n, 3, 3)
+    assert np.array_equal(Q0[:, 0], Q1[:, 0])
+    th = S._logvec(np.einsum("rjab,rjcb->rjac", Q0[:, 1:], Q1[:, 1:]))
+    dw = (p1[3] - inp.omega).reshape(-1, n, 3)
+    for x, s_ in ((dp[:, 1:] / lh, sig[0]), (dv[:, 1:] * tau / lh, sig[1]), (th, sig[2]),
+                  (dw[:, 1:] * tau, sig[3])):
+        x = x.reshape(-1) / s_
+        assert abs(x.mean()) < 0.02 and abs(x.std() - 1) < 0.02
+    QQ = np.einsum("iab,icb->iac", p1[2], p1[2]) - np.eye(3)
+    assert np.abs(QQ).max() < 1e-14
