@@ -6,7 +6,17 @@ rod_step call of 1000 position-Verlet steps (one persistent kernel launch
 replayed from a HIP graph).  The headline value is FP64 element-steps/s; the
 FP32 figure rides along in the same JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate]
+
+The learned coarse step rides along as the "surrogate" object: the network is
+trained on 16,384 carpet rods (64 elements, 2.1e6 windows from plain
+trajectories, perturbed samples), then 262,144 carpet rods advance by
+SURR_COARSE coarse steps of k = 32 with the plain integrator judging 1% of
+them every 8 coarse steps; the same rods advance by the same simulated time
+with the plain FP32 step.  Both rates are simulated seconds per wall second
+for all rods (judge and fallback included); the end-to-end position error is
+against the plain run.  The MLP's roofline is its fused inference kernel
+timed alone on the same number of rows, against the BF16 dense MFMA peak.
 
 Roofline: the step is plain ALU arithmetic once the rods' state stays on
 chip for the 1000 substeps of a launch (1147 FLOP per byte of HBM traffic
@@ -36,6 +46,10 @@ ALGO_FLOP = 459                                  # per element-step (breakdown i
 ALGO_BYTES = {"f64": 400, "f32": 204}            # HBM bytes per element per launch
 PEAK = {"f64": 78.6, "f32": 157.3}               # TFLOP/s, MI355X vector peaks
 STEPS_PER_LAUNCH = 1000
+SURR_K = 32
+SURR_COARSE = 16                                 # two judge windows
+MLP_FLOP = 2 * (96 * 256 + 256 * 256 * 2 + 256 * 12)   # per window
+BF16_PEAK = 2500.0                               # TFLOP/s, dense MFMA
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_13766_amd", "csrc", "rod_kernels.hip")
 
 
@@ -130,6 +144,93 @@ def cpu_baseline(inp, target_s=10.0):
     }
 
 
+def time_surrogate():
+    """Train, then the coarse step with judge against the plain step on the
+    262,144-rod carpet (see the module docstring)."""
+    import torch
+    from paper_2605_13766_amd import rod
+    from paper_2605_13766_amd import workloads as W
+
+    out = {}
+    t0 = time.perf_counter()
+    tr = W.surrogate_training(n_rods=16384, n=64)
+    btr = rod.RodBatch(tr, precision="f32")
+    s = rod.Surrogate(k_substeps=SURR_K, seed=1)
+    tdesc = dict(warmup_steps=2000, n_samples=2, sample_stride=6000, epochs=24, batch_rows=4096, lr=1e-3,
+                 lr_min=1e-5, val_fraction=0.1, seed=7, noise=(1e-4, 1.5e-4, 3e-4, 6e-4))
+    ep, val = s.train(btr, **tdesc)
+    torch.cuda.synchronize()
+    out["train"] = {"rods": tr.n_rods, "windows": int(2 * (tr.n_elements + tr.n_rods)), "epochs": tdesc["epochs"],
+                    "val_loss": float(val), "first_epoch_loss": float(ep[0]), "last_epoch_loss": float(ep[-1]),
+                    "seconds": time.perf_counter() - t0}
+    btr.close()
+    del tr
+    print("surrogate trained", out["train"], file=sys.stderr, flush=True)
+
+    inp = W.surrogate_at_scale(n_rods=262144, n=64)
+    judge = dict(judge_every=8, judge_fraction=0.01, max_pos_error=1e-3, max_orth_error=1e-5,
+                 max_energy_error=5e-2, seed=11)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sb = rod.RodBatch(inp, precision="f32", stream=stream)
+        pb = rod.RodBatch(inp, precision="f32", stream=stream)
+        sb.step(2000, stream=stream)
+        pb.step(2000 + SURR_K, stream=stream)
+        s.step(sb, 1, stream=stream, **judge)        # allocations; both batches now at 2000 + k steps
+        torch.cuda.synchronize()
+        sim = SURR_COARSE * SURR_K * inp.dt
+        t = time.perf_counter()
+        st = s.step(sb, SURR_COARSE, stream=stream, **judge)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        t = time.perf_counter()
+        pb.step(SURR_COARSE * SURR_K, stream=stream)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        ps = pb.get_state(stream=stream)[0].reshape(-1, 65, 3)
+        ss = sb.get_state(stream=stream)[0].reshape(-1, 65, 3)
+        err = np.linalg.norm(ss - ps, axis=2).max(axis=1) / 0.01
+        rng = np.random.default_rng(3)
+        sample = rng.choice(inp.n_rods, size=64, replace=False)
+        # the fused MLP kernel alone, on as many rows as the batch has windows
+        rows = int(inp.n_elements + inp.n_rods)
+        x = torch.randn((rows, 96), device="cuda").to(torch.bfloat16)
+        y = torch.empty((rows, 12), device="cuda")
+        s.forward(x, y, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            s.forward(x, y, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mlp_ms = e0.elapsed_time(e1) / 3
+        flags = sb.flags(stream=stream)
+        sb.close()
+        pb.close()
+    s.close()
+    if flags.any():
+        raise RuntimeError(f"{int(flags.sum())} rods became non-finite under the coarse step")
+    achieved = MLP_FLOP * rows / (mlp_ms * 1e-3) / 1e12
+    out.update({
+        "value": sim / ts,
+        "unit": "simulated-s/s",
+        "plain_value": sim / tp,
+        "speedup": tp / ts,
+        "workload": f"cilia carpet: {inp.n_rods} base-clamped rods x 64 elements, dt 1e-6 s, k = {SURR_K}, "
+                    f"{SURR_COARSE} coarse steps ({SURR_COARSE * SURR_K} plain steps), judge every 8 on 1%, "
+                    "thresholds 1e-3 position / 1e-5 orthonormality / 5e-2 strain energy",
+        "ms_per_coarse_step": ts / SURR_COARSE * 1e3,
+        "plain_ms_per_k_steps": tp / SURR_COARSE * 1e3,
+        "error": {"max": float(err.max()), "median": float(np.median(err)),
+                  "frac_within_1e-3": float(np.mean(err <= 1e-3)),
+                  "sample64_max": float(err[sample].max())},
+        "judge": st,
+        "mlp_roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK, "unit": "TFLOP/s",
+                         "frac": achieved / BF16_PEAK, "rows": rows, "launch_ms": mlp_ms},
+    })
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +238,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="f64,f32")
+    ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -188,6 +290,9 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         print("timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inp)
+    if not args.no_surrogate:
+        print("training and timing the learned coarse step", file=sys.stderr, flush=True)
+        line["surrogate"] = time_surrogate()
     print(json.dumps(line), flush=True)
     return 0
 

@@ -32,4 +32,23 @@ hipError_t adam(float *w, float *m, float *v, const float *g, int64_t n, float l
                 float eps, int64_t t, hipStream_t s);
 hipError_t to_bf16(const float *src, __bf16 *dst, int64_t n, hipStream_t s);
 
+// Fused inference (mlp_infer.hip).  Weights are first packed from the BF16
+// internal layout (layer l at w_offset[l], [K][ld[l]] row-major) into MFMA
+// fragments (infer_fragments_bytes() bytes, 16-byte aligned).
+struct PackArgs {
+    int64_t w_offset[4];
+    int ld[4];
+};
+struct InferArgs {
+    const __bf16 *x;        // [M][96] standardised inputs, rows 16-byte aligned
+    int64_t M;
+    const __bf16 *frag;     // packed fragments
+    const float *bias[4];   // FP32 biases (256, 256, 256, 16 values)
+    float *y;               // [M][ldy] outputs, ldy 16 (all 16 columns) or 12
+    int ldy;
+};
+int infer_fragments_bytes();
+hipError_t pack_fragments(const __bf16 *wb, const PackArgs &p, __bf16 *frags, hipStream_t s);
+hipError_t mlp_infer(const InferArgs &a, hipStream_t s);
+
 }  // namespace mlpk

@@ -60,6 +60,7 @@ struct rod_surrogate {
     Layout lay{};
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;   // FP32, internal layout
     __bf16 *wb = nullptr;                                           // BF16 weights (internal layout)
+    __bf16 *frag = nullptr;                                         // BF16 weights as inference fragments
     int64_t adam_t = 0;
     // workspace (max_rows rows)
     float *Z[3] = {nullptr, nullptr, nullptr};
@@ -98,6 +99,28 @@ int refresh_bf16(rod_surrogate *s, hipStream_t st)
 {
     hipError_t e = mlpk::to_bf16(s->w, s->wb, s->lay.total, st);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("to_bf16: ") + hipGetErrorString(e));
+    mlpk::PackArgs p{};
+    for (int l = 0; l < NL; ++l) {
+        p.w_offset[l] = s->lay.w[l];
+        p.ld[l] = NPAD[l];
+    }
+    e = mlpk::pack_fragments(s->wb, p, s->frag, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("pack: ") + hipGetErrorString(e));
+    return ROD_OK;
+}
+
+// Fused inference over M rows of standardised BF16 inputs into y ([M][ldy], ldy 16 or 12).
+int infer(rod_surrogate *s, const __bf16 *x, int64_t M, float *y, int ldy, hipStream_t st)
+{
+    mlpk::InferArgs a{};
+    a.x = x;
+    a.M = M;
+    a.frag = s->frag;
+    for (int l = 0; l < NL; ++l) a.bias[l] = s->w + s->lay.b[l];
+    a.y = y;
+    a.ldy = ldy;
+    hipError_t e = mlpk::mlp_infer(a, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("inference: ") + hipGetErrorString(e));
     return ROD_OK;
 }
 
@@ -439,12 +462,8 @@ int coarse_step(rod_surrogate *s, rod_batch *b, const rodk::BatchView &v, int n_
     const float *mut = s->norm + 2 * ROD_SURROGATE_INPUTS, *sdt = mut + ROD_SURROGATE_OUTPUTS;
     hipError_t e = surk::features(win_args(s, v), nullptr, s->xall, mux, sdx, st);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("features: ") + hipGetErrorString(e));
-    for (int64_t r0 = 0; r0 < s->n_windows; r0 += s->max_rows) {
-        const int rows = (int)std::min<int64_t>(s->max_rows, s->n_windows - r0);
-        int rc = forward_chunk(s, s->xall + r0 * ROD_SURROGATE_INPUTS, rows, st, s->yall + r0 * NOUT_LD);
-        if (rc) return rc;
-    }
-    int rc;
+    int rc = infer(s, s->xall, s->n_windows, s->yall, NOUT_LD, st);
+    if (rc) return rc;
     if (n_plain > 0) {
         if ((rc = rodk::batch_step_masked(b, s->k, s->plain, st))) return rc;
     }
@@ -502,6 +521,7 @@ int rod_surrogate_create(const rod_surrogate_desc *d, rod_surrogate **out)
     alloc((void **)&s->v, P * 4);
     alloc((void **)&s->g, P * 4);
     alloc((void **)&s->wb, P * 2);
+    alloc((void **)&s->frag, (size_t)mlpk::infer_fragments_bytes());
     for (int l = 0; l < 3; ++l) {
         alloc((void **)&s->Z[l], R * 256 * 4);
         alloc((void **)&s->Ab[l], R * 256 * 2);
@@ -551,6 +571,7 @@ void rod_surrogate_destroy(rod_surrogate *s)
     (void)hipFree(s->v);
     (void)hipFree(s->g);
     (void)hipFree(s->wb);
+    (void)hipFree(s->frag);
     for (int l = 0; l < 3; ++l) {
         (void)hipFree(s->Z[l]);
         (void)hipFree(s->Ab[l]);
@@ -596,15 +617,8 @@ int rod_surrogate_forward(rod_surrogate *s, const void *x, int64_t M, float *y, 
 {
     if (!s || !x || !y) return sfail(ROD_EINVAL, "NULL argument");
     if (M < 0) return sfail(ROD_EINVAL, "M must be >= 0");
-    hipStream_t st = (hipStream_t)stream;
-    for (int64_t r0 = 0; r0 < M; r0 += s->max_rows) {
-        const int rows = (int)std::min<int64_t>(s->max_rows, M - r0);
-        int rc = forward_chunk(s, (const __bf16 *)x + r0 * ROD_SURROGATE_INPUTS, rows, st);
-        if (rc) return rc;
-        SHIPCHK(hipMemcpy2DAsync(y + r0 * ROD_SURROGATE_OUTPUTS, ROD_SURROGATE_OUTPUTS * 4, s->Y, NOUT_LD * 4,
-                                 ROD_SURROGATE_OUTPUTS * 4, rows, hipMemcpyDeviceToDevice, st));
-    }
-    return ROD_OK;
+    if ((uintptr_t)x % 16 || (uintptr_t)y % 4) return sfail(ROD_EINVAL, "x must be 16-byte aligned, y 4-byte aligned");
+    return infer(s, (const __bf16 *)x, M, y, ROD_SURROGATE_OUTPUTS, (hipStream_t)stream);
 }
 
 int rod_surrogate_gradients(rod_surrogate *s, const void *x, const float *t, const float *mask, int64_t M,
