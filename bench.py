@@ -2,8 +2,9 @@
 
 Workload: the ragged batch of 4096 free-free rods (16..256 elements,
 556,994 elements in all), dt = 1e-5 s, damping 0.1; one bench step is one
-rod_step call of 1000 position-Verlet steps (one persistent kernel launch
-replayed from a HIP graph).  The headline value is FP64 element-steps/s; the
+rod_step call of 1000 position-Verlet steps (ceil(1000 / S) launches of the
+persistent kernel replayed from a HIP graph, with the tile width and the
+substeps per launch S chosen by the library's autotuner).  The headline value is FP64 element-steps/s; the
 FP32 figure rides along in the same JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate]
@@ -77,8 +78,9 @@ def time_gpu(inp, precision, steps, warmup):
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        b = rod.RodBatch(inp, precision=precision, stream=stream)
+        b = rod.RodBatch(inp, precision=precision, stream=stream, autotune=True)
         info = b.info()
+        info["tuning"] = b.tuning()
         for _ in range(warmup):
             b.step(STEPS_PER_LAUNCH, stream=stream)
         torch.cuda.synchronize()
@@ -172,8 +174,10 @@ def time_surrogate():
                  max_energy_error=5e-2, seed=11)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sb = rod.RodBatch(inp, precision="f32", stream=stream)
-        pb = rod.RodBatch(inp, precision="f32", stream=stream)
+        pb = rod.RodBatch(inp, precision="f32", stream=stream, autotune=True)
+        pinfo = pb.info()
+        sb = rod.RodBatch(inp, precision="f32", stream=stream, tile_waves=pinfo["tile_waves"],
+                          substeps=pinfo["substeps"])
         sb.step(2000, stream=stream)
         pb.step(2000 + SURR_K, stream=stream)
         s.step(sb, 1, stream=stream, **judge)        # allocations; both batches now at 2000 + k steps
@@ -220,6 +224,8 @@ def time_surrogate():
                     f"{SURR_COARSE} coarse steps ({SURR_COARSE * SURR_K} plain steps), judge every 8 on 1%, "
                     "thresholds 1e-3 position / 1e-5 orthonormality / 5e-2 strain energy",
         "ms_per_coarse_step": ts / SURR_COARSE * 1e3,
+        "plain_tile_waves": pinfo["tile_waves"],
+        "plain_substeps_per_launch": pinfo["substeps"],
         "plain_ms_per_k_steps": tp / SURR_COARSE * 1e3,
         "error": {"max": float(err.max()), "median": float(np.median(err)),
                   "frac_within_1e-3": float(np.mean(err <= 1e-3)),
@@ -278,7 +284,9 @@ def main(argv=None):
             "n_elements": inp.n_elements,
             "steps_per_launch": STEPS_PER_LAUNCH,
             "tile_waves": head["info"]["tile_waves"],
+            "substeps_per_launch": head["info"]["substeps"],
             "n_tiles": head["info"]["n_tiles"],
+            "autotuner_trials": head["info"]["tuning"],
         },
         "roofline": head["roofline"],
         "launch_ms": head["launch_ms"],
@@ -286,7 +294,8 @@ def main(argv=None):
     for p in precs[1:]:
         line[p] = {"value": res[p]["value"], "unit": "element-steps/s",
                    "ms_per_step": res[p]["ms_per_step"], "launch_ms": res[p]["launch_ms"],
-                   "roofline": res[p]["roofline"]}
+                   "roofline": res[p]["roofline"], "tile_waves": res[p]["info"]["tile_waves"],
+                   "substeps_per_launch": res[p]["info"]["substeps"]}
     if not args.no_cpu_baseline:
         print("timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inp)

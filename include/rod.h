@@ -94,10 +94,22 @@ typedef struct {
     double dt;                       /* time step h > 0 (s) */
     double t0;                       /* time of the initial state (s) */
     int32_t precision;               /* ROD_F64 or ROD_F32 */
-    int32_t substeps;                /* steps per kernel launch; 0: all steps of a rod_step call */
-    int32_t tile_waves;              /* wave64s per workgroup tile (1, 2, 4, 8); 0: smallest that fits */
+    int32_t substeps;                /* steps per kernel launch; 0: all steps of a rod_step call
+                                        (autotune: 0 = tuned) */
+    int32_t tile_waves;              /* wave64s per workgroup tile (1, 2, 4, 8); 0: smallest that fits
+                                        (autotune: 0 = tuned) */
     int32_t inputs_on_device;        /* 1: every pointer above is device memory; 0: host */
+    int32_t autotune;                /* 1: choose every tile parameter given as 0 by timing (below) */
 } rod_batch_desc;
+
+/* One timed candidate of the autotuner. */
+typedef struct {
+    int32_t tile_waves;
+    int32_t substeps;
+    double ns_per_element_step;      /* device time per element-step of the trial */
+} rod_tune_trial;
+
+#define ROD_MAX_TUNE_TRIALS 12
 
 /*
  * Create a batch: validate, derive the per-element constants in FP64, pack
@@ -111,6 +123,19 @@ typedef struct {
  * rod_last_error with ROD_OK.
  */
 int rod_batch_create(const rod_batch_desc *desc, void *stream, rod_batch **out);
+
+/*
+ * The autotuner (desc->autotune = 1).  Candidates: tile_waves in {1, 2, 4, 8}
+ * that hold the longest rod (when tile_waves = 0) times substeps in
+ * {50, 200, 1000} (when substeps = 0).  Each tile width is packed into a
+ * scratch batch of the same rods; each candidate runs one warm-up launch and
+ * then 1000 timed steps (HIP events on a private stream; the scratch state is
+ * discarded), and the fastest per element-step is kept.  Tile width does not
+ * change results; substeps per launch change them at round-off (the half
+ * drifts of consecutive steps are fused inside a launch).  rod_batch_tuning
+ * returns the trials (n_trials = 0 without autotuning).
+ */
+int rod_batch_tuning(const rod_batch *b, rod_tune_trial *trials, int32_t max_trials, int32_t *n_trials);
 
 /*
  * Advance every rod by n_steps >= 0 position-Verlet steps of size dt

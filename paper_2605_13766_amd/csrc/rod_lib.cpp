@@ -96,6 +96,7 @@ struct rod_batch {
     hipStream_t capture_stream = nullptr;
     std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     bool use_graphs = true;
+    std::vector<rod_tune_trial> tune_log;   // autotuner trials (empty without autotuning)
     // host staging of the packed layout
     std::vector<int32_t> slot_rod, slot_idx;
 };
@@ -144,6 +145,7 @@ int validate(const rod_batch_desc *d)
     if (d->substeps < 0) return fail(ROD_EINVAL, "substeps must be >= 0");
     if (d->tile_waves != 0 && d->tile_waves != 1 && d->tile_waves != 2 && d->tile_waves != 4 && d->tile_waves != 8)
         return fail(ROD_EINVAL, "tile_waves must be 0, 1, 2, 4 or 8");
+    if (d->autotune != 0 && d->autotune != 1) return fail(ROD_EINVAL, "autotune must be 0 or 1");
     if (d->couple_amp && (!d->couple_freq || !d->couple_phase))
         return fail(ROD_EINVAL, "couple_amp needs couple_freq and couple_phase");
     return ROD_OK;
@@ -610,9 +612,89 @@ int rodk::batch_set_time(rod_batch *b, double t, hipStream_t s)
     return ROD_OK;
 }
 
+namespace {
+
+// Time every candidate (tile width x substeps per launch) on scratch batches
+// of the same rods and return the fastest in `best` (autotune cleared).
+int autotune(const rod_batch_desc *d, std::vector<rod_tune_trial> &log, rod_batch_desc &best)
+{
+    constexpr int TRIAL_STEPS = 1000;
+    const std::vector<int> widths = d->tile_waves ? std::vector<int>{d->tile_waves} : std::vector<int>{1, 2, 4, 8};
+    const std::vector<int> subs = d->substeps ? std::vector<int>{d->substeps} : std::vector<int>{50, 200, 1000};
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    hipError_t he = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        release();
+        return fail(ROD_EDEVICE, std::string("autotune set-up: ") + hipGetErrorString(he));
+    }
+    best = *d;
+    best.autotune = 0;
+    double best_ns = INFINITY;
+    for (int w : widths) {
+        rod_batch_desc c = *d;
+        c.autotune = 0;
+        c.tile_waves = w;
+        c.substeps = subs[0];
+        rod_batch *tb = nullptr;
+        int rc = rod_batch_create(&c, nullptr, &tb);
+        if (rc == ROD_EUNSUPPORTED) continue;   // this width cannot hold the longest rod
+        if (rc) {
+            release();
+            return rc;
+        }
+        tb->use_graphs = false;
+        for (int sub : subs) {
+            tb->substeps = sub;
+            rc = enqueue_steps(tb, sub, st);   // warm-up launch
+            if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = fail(ROD_EDEVICE, "autotune: event record");
+            if (!rc) rc = enqueue_steps(tb, TRIAL_STEPS, st);
+            if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(ROD_EDEVICE, "autotune: event record");
+            float ms = 0.f;
+            if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(ROD_EDEVICE, "autotune: event timing");
+            if (rc) {
+                rod_batch_destroy(tb);
+                release();
+                return rc;
+            }
+            const double ns = (double)ms * 1e6 / ((double)tb->Ne * TRIAL_STEPS);
+            log.push_back(rod_tune_trial{w, sub, ns});
+            if (ns < best_ns) {
+                best_ns = ns;
+                best.tile_waves = w;
+                best.substeps = sub;
+            }
+        }
+        rod_batch_destroy(tb);
+    }
+    release();
+    if (log.empty()) return fail(ROD_EUNSUPPORTED, "autotune: no tile width holds the longest rod");
+    return ROD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *rod_last_error(void) { return g_err.c_str(); }
+
+int rod_batch_tuning(const rod_batch *b, rod_tune_trial *trials, int32_t max_trials, int32_t *n_trials)
+{
+    if (!b || !n_trials || (max_trials > 0 && !trials) || max_trials < 0)
+        return fail(ROD_EINVAL, "NULL handle or output, or max_trials < 0");
+    const int32_t n = (int32_t)std::min<size_t>(b->tune_log.size(), (size_t)max_trials);
+    for (int32_t i = 0; i < n; ++i) trials[i] = b->tune_log[i];
+    *n_trials = (int32_t)b->tune_log.size();
+    return ROD_OK;
+}
 
 int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
 {
@@ -621,6 +703,14 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     *out = nullptr;
     int rc = validate(d);
     if (rc) return rc;
+    if (d->autotune && (d->tile_waves == 0 || d->substeps == 0)) {
+        std::vector<rod_tune_trial> log;
+        rod_batch_desc best;
+        if ((rc = autotune(d, log, best))) return rc;
+        if ((rc = rod_batch_create(&best, stream, out))) return rc;
+        (*out)->tune_log = std::move(log);
+        return ROD_OK;
+    }
     HostInputs h;
     if ((rc = gather_inputs(d, h))) return rc;
     if ((rc = check_values(h))) return rc;

@@ -178,10 +178,19 @@ __global__ void features_kernel(const WinArgs A, float *raw, __bf16 *xn, const f
     const double ph = 2.0 * M_PI * (double)rf[RF_FREQ] * A.time + (double)rf[RF_PHASE];
     gl[14] = (float)sin(ph);
     gl[15] = (float)cos(ph);
-    if (raw)
-        for (int k = 0; k < N_FEAT; ++k) raw[g * N_FEAT + k] = f[k];
-    if (xn)
-        for (int k = 0; k < N_FEAT; ++k) xn[g * N_FEAT + k] = (__bf16)((f[k] - mu[k]) / sd[k]);
+    // 16-byte stores: a window's row is 384 bytes of FP32 or 192 bytes of BF16
+    if (raw) {
+        float4 *o = reinterpret_cast<float4 *>(raw + g * N_FEAT);
+        for (int k = 0; k < N_FEAT / 4; ++k) o[k] = float4{f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
+    }
+    if (xn) {
+        uint4 *o = reinterpret_cast<uint4 *>(xn + g * N_FEAT);
+        for (int k = 0; k < N_FEAT / 8; ++k) {
+            __bf16 v[8];
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)((f[8 * k + j] - mu[8 * k + j]) / sd[8 * k + j]);
+            o[k] = __builtin_bit_cast(uint4, v);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- targets

@@ -35,8 +35,12 @@ class RodBatchDesc(C.Structure):
         ("end_force", _dp), ("couple_amp", _dp), ("couple_freq", _dp), ("couple_phase", _dp),
         ("dt", C.c_double), ("t0", C.c_double),
         ("precision", C.c_int32), ("substeps", C.c_int32), ("tile_waves", C.c_int32),
-        ("inputs_on_device", C.c_int32),
+        ("inputs_on_device", C.c_int32), ("autotune", C.c_int32),
     ]
+
+
+class TuneTrial(C.Structure):
+    _fields_ = [("tile_waves", C.c_int32), ("substeps", C.c_int32), ("ns_per_element_step", C.c_double)]
 
 
 class SurrogateDesc(C.Structure):
@@ -98,6 +102,8 @@ def lib():
         L.rod_get_flags.argtypes = [vp, _ip, vp]
         L.rod_batch_info.argtypes = [vp, C.POINTER(C.c_int64)]
         L.rod_batch_destroy.argtypes = [vp]
+        L.rod_batch_tuning.argtypes = [vp, C.POINTER(TuneTrial), C.c_int32, C.POINTER(C.c_int32)]
+        L.rod_batch_tuning.restype = C.c_int
         L.rod_batch_destroy.restype = None
         L.rod_last_error.restype = C.c_char_p
         for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_get_state", "rod_set_state",
@@ -167,7 +173,7 @@ class RodBatch:
     """A batch of rods resident on the GPU (owned by librod.so)."""
 
     def __init__(self, inp, precision: str = "f64", substeps: int = 0, tile_waves: int = 0,
-                 t0: float = 0.0, stream=None):
+                 t0: float = 0.0, stream=None, autotune: bool = False):
         self._h = None
         prec = {"f64": ROD_F64, "f32": ROD_F32}[precision]
         keep = {}
@@ -195,6 +201,7 @@ class RodBatch:
         d.substeps = int(substeps)
         d.tile_waves = int(tile_waves)
         d.inputs_on_device = 0
+        d.autotune = int(autotune)
         h = C.c_void_p()
         _check(lib().rod_batch_create(C.byref(d), _stream_ptr(stream), C.byref(h)))
         self._h = h
@@ -227,6 +234,14 @@ class RodBatch:
     def set_state(self, pos=None, vel=None, director=None, omega=None, t=0.0, stream=None):
         arrs = [_f64(pos), _f64(vel), _f64(director), _f64(omega)]
         _check(lib().rod_set_state(self._h, *[_p(a) for a in arrs], float(t), _stream_ptr(stream)))
+
+    def tuning(self) -> list:
+        """The autotuner's trials (empty unless created with autotune)."""
+        buf = (TuneTrial * 12)()
+        n = C.c_int32()
+        _check(lib().rod_batch_tuning(self._h, buf, 12, C.byref(n)))
+        return [{"tile_waves": t.tile_waves, "substeps": t.substeps, "ns_per_element_step": t.ns_per_element_step}
+                for t in buf[:min(n.value, 12)]]
 
     def flags(self, stream=None) -> np.ndarray:
         out = np.empty(self.n_rods, dtype=np.int32)

@@ -77,6 +77,7 @@ def test_invalid_descriptors_rejected():
     _expect(rod.ROD_EINVAL, bad)
     _expect(rod.ROD_EINVAL, base, tile_waves=3)
     _expect(rod.ROD_EINVAL, base, substeps=-1)
+    assert "autotune" in _expect(rod.ROD_EINVAL, base, autotune=2)
     long_rod = W.ragged_batch(n_rods=1, n_min=600, n_max=600, seed=43)
     assert "outside" in _expect(rod.ROD_EINVAL, long_rod)
 

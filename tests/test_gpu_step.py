@@ -112,6 +112,34 @@ def test_tile_layout_bitwise_invariant():
             assert np.array_equal(a, b)
 
 
+def test_autotuner_keeps_the_fastest_and_the_results():
+    """autotune: every fitting tile width (rods of up to 100 elements: 2, 4
+    and 8 waves) times substeps 50 / 200 / 1000 is timed; the batch uses the
+    fastest; its results equal those of a batch created with that choice by
+    hand, bit for bit, and of the same substeps at another tile width."""
+    R = _rod()
+    inp = W.ragged_batch(n_rods=512, n_min=16, n_max=100, seed=37)
+    with R.RodBatch(inp, autotune=True) as b:
+        trials = b.tuning()
+        info = b.info()
+        print(trials, info)
+        assert sorted((t["tile_waves"], t["substeps"]) for t in trials) == \
+            [(w, s) for w in (2, 4, 8) for s in (50, 200, 1000)]
+        assert all(t["ns_per_element_step"] > 0 for t in trials)
+        best = min(trials, key=lambda t: t["ns_per_element_step"])
+        assert (info["tile_waves"], info["substeps"]) == (best["tile_waves"], best["substeps"])
+        b.step(600)
+        got = b.get_state()
+    other = 2 if info["tile_waves"] != 2 else 4
+    for w in (info["tile_waves"], other):
+        with R.RodBatch(inp, tile_waves=w, substeps=info["substeps"]) as c:
+            assert c.tuning() == []
+            c.step(600)
+            ref = c.get_state()
+        for a, r in zip(got[:4], ref[:4]):
+            assert np.array_equal(a, r)
+
+
 def test_resume_bitwise_and_launch_split_roundoff():
     """Checkpoint/resume at a launch boundary is bitwise: 500 steps, get_state,
     a fresh batch set_state, 500 steps == 500 + 500 steps in one batch.  A
