@@ -72,13 +72,15 @@ def traffic_from_profile(precision: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_gpu(inp, precision, steps, warmup):
+def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0):
     import torch
     from paper_2605_13766_amd import rod
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        b = rod.RodBatch(inp, precision=precision, stream=stream, autotune=True)
+        tuned = tile_waves == 0 or substeps == 0
+        b = rod.RodBatch(inp, precision=precision, stream=stream, autotune=tuned, tile_waves=tile_waves,
+                         substeps=substeps)
         info = b.info()
         info["tuning"] = b.tuning()
         for _ in range(warmup):
@@ -245,6 +247,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--tile-waves", type=int, default=0, help="fix the tile width (0: autotune)")
+    ap.add_argument("--substeps", type=int, default=0, help="fix the substeps per launch (0: autotune)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (for scaling HBM counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -256,13 +262,22 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20)
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return 0
     print("generating the ragged 4096-rod batch", file=sys.stderr, flush=True)
     inp = W.ragged_batch(n_rods=4096)
     precs = args.precisions.split(",")
     res = {}
     for p in precs:
         print(f"timing {p}", file=sys.stderr, flush=True)
-        res[p] = time_gpu(inp, p, args.steps, args.warmup)
+        res[p] = time_gpu(inp, p, args.steps, args.warmup, args.tile_waves, args.substeps)
     head = res[precs[0]]
     line = {
         "metric": METRIC,
