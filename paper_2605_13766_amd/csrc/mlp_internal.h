@@ -18,11 +18,14 @@ struct GemmArgs {
     const float *bias;      // [N] for EPI_BIAS / EPI_BIAS_SILU
     __bf16 *act;            // [M][ldc] BF16 SiLU output for EPI_BIAS_SILU
     const float *zsave;     // [M][ldc] pre-activation for EPI_DSILU
+    int kchunk = 0;         // split reduction: K per z-slice (0: one slice)
+    int64_t zstride = 0;    // offset between the slices' outputs
 };
 
 hipError_t gemm_forward(const GemmArgs &g, int epi, hipStream_t s);
 hipError_t gemm_backward_data(const GemmArgs &g, int epi, hipStream_t s);
-hipError_t gemm_backward_weight(const GemmArgs &g, hipStream_t s);
+// work: scratch of work_floats floats for the split reduction (NULL: no split)
+hipError_t gemm_backward_weight(const GemmArgs &g, float *work, int64_t work_floats, hipStream_t s);
 hipError_t mse_grad(const float *Y, const float *T, const float *mask, float *dY, float *partial,
                     int64_t M, int n_out, int ld, hipStream_t s);
 int mse_partials(int64_t M, int ld);

@@ -8,6 +8,7 @@
 #include "mlp_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -46,6 +47,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // split reduction: z-slice blockIdx.z covers k in [kb, ke) and writes its own partial C
+    const int kb = g.kchunk > 0 ? blockIdx.z * g.kchunk : 0;
+    const int ke = g.kchunk > 0 ? min(g.K, kb + g.kchunk) : g.K;
+    float *const Cz = g.C + (int64_t)blockIdx.z * g.zstride;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     f32x4 acc[2][2];
 #pragma unroll
@@ -53,7 +58,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         // ---- stage A (64 x 32); rows past M and columns past K read as zero
         if (!AT) {
             const int r = t >> 2, kc = (t & 3) * 8;
@@ -61,7 +66,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = k0 + kc + j;
-                As[r][kc + j] = (__bf16)(m < g.M && k < g.K ? to_f(A[(int64_t)m * g.lda + k]) : 0.f);
+                As[r][kc + j] = (__bf16)(m < g.M && k < ke ? to_f(A[(int64_t)m * g.lda + k]) : 0.f);
             }
         } else {
             const int kr = t >> 3, mc = (t & 7) * 8;
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int m = m0 + mc + j;
-                As[mc + j][kr] = (__bf16)(m < g.M && k < g.K ? to_f(A[(int64_t)k * g.lda + m]) : 0.f);
+                As[mc + j][kr] = (__bf16)(m < g.M && k < ke ? to_f(A[(int64_t)k * g.lda + m]) : 0.f);
             }
         }
         // ---- stage B (32 x 64), stored transposed as [n][k]
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int n = n0 + nc + j;
-                Bs[nc + j][kr] = (__bf16)(n < g.N && k < g.K ? to_f(B[(int64_t)k * g.ldb + n]) : 0.f);
+                Bs[nc + j][kr] = (__bf16)(n < g.N && k < ke ? to_f(B[(int64_t)k * g.ldb + n]) : 0.f);
             }
         } else {
             const int r = t >> 2, kc = (t & 3) * 8;
@@ -87,7 +92,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = k0 + kc + j;
-                Bs[r][kc + j] = (__bf16)(n < g.N && k < g.K ? to_f(B[(int64_t)n * g.ldb + k]) : 0.f);
+                Bs[r][kc + j] = (__bf16)(n < g.N && k < ke ? to_f(B[(int64_t)n * g.ldb + k]) : 0.f);
             }
         }
         __syncthreads();
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
                 const float v = acc[i][j][r];
                 const int64_t o = (int64_t)m * g.ldc + n;
                 if (EPI == EPI_STORE) {
-                    g.C[o] = v;
+                    Cz[o] = v;
                 } else if (EPI == EPI_BIAS) {
                     g.C[o] = v + g.bias[n];
                 } else if (EPI == EPI_BIAS_SILU) {
@@ -220,11 +225,21 @@ __global__ void to_bf16_kernel(const float *src, __bf16 *dst, int64_t n)
 // ------------------------------------------------------------------ launchers
 
 template <bool AT, bool BT, typename TA, typename TB, int EPI>
-static hipError_t launch_t(const GemmArgs &g, hipStream_t s)
+static hipError_t launch_t(const GemmArgs &g, hipStream_t s, int splits = 1)
 {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
     hipLaunchKernelGGL((gemm_kernel<AT, BT, TA, TB, EPI>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
+}
+
+// out[i] = sum over z of part[z * stride + i], z ascending (deterministic)
+__global__ void sum_splits_kernel(const float *part, int splits, int64_t stride, int64_t n, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float acc = 0.f;
+    for (int z = 0; z < splits; ++z) acc += part[z * stride + i];
+    out[i] = acc;
 }
 
 hipError_t gemm_forward(const GemmArgs &g, int epi, hipStream_t s)
@@ -247,10 +262,27 @@ hipError_t gemm_backward_data(const GemmArgs &g, int epi, hipStream_t s)
     }
 }
 
-hipError_t gemm_backward_weight(const GemmArgs &g, hipStream_t s)
+hipError_t gemm_backward_weight(const GemmArgs &g, float *work, int64_t work_floats, hipStream_t s)
 {
-    // C[K_l][N_l] = act^T * dZ: act bf16 stored [M][K_l] = [K_gemm][M_gemm], dZ f32 [M][N_l]
-    return launch_t<true, false, __bf16, float, EPI_STORE>(g, s);
+    // C[K_l][N_l] = act^T * dZ: act bf16 stored [M][K_l] = [K_gemm][M_gemm], dZ f32 [M][N_l].
+    // The output has few 64 x 64 tiles, so the long reduction (the minibatch) is split
+    // into z-slices of whole 32-row stages, about 512 workgroups in all; the slices'
+    // partial products go to `work` and are summed in slice order.
+    const int64_t tiles = (int64_t)((g.N + 63) / 64) * ((g.M + 63) / 64);
+    const int64_t out_floats = (int64_t)g.M * g.ldc;
+    int splits = (int)std::min<int64_t>({(512 + tiles - 1) / tiles, (g.K + 31) / 32,
+                                         work ? work_floats / std::max<int64_t>(out_floats, 1) : 1});
+    if (splits <= 1) return launch_t<true, false, __bf16, float, EPI_STORE>(g, s);
+    GemmArgs a = g;
+    a.kchunk = (int)((((int64_t)g.K + splits - 1) / splits + 31) / 32 * 32);
+    splits = (int)(((int64_t)g.K + a.kchunk - 1) / a.kchunk);
+    a.C = work;
+    a.zstride = out_floats;
+    hipError_t e = launch_t<true, false, __bf16, float, EPI_STORE>(a, s, splits);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_splits_kernel, dim3((unsigned)((out_floats + 255) / 256)), dim3(256), 0, s, work, splits,
+                       out_floats, out_floats, g.C);
+    return hipGetLastError();
 }
 
 hipError_t mse_grad(const float *Y, const float *T, const float *mask, float *dY, float *partial,

@@ -33,6 +33,7 @@ constexpr int KDIM[NL] = {ROD_SURROGATE_INPUTS, 256, 256, 256};
 constexpr int NDIM[NL] = {256, 256, 256, ROD_SURROGATE_OUTPUTS};   // external
 constexpr int NPAD[NL] = {256, 256, 256, 16};                        // internal
 constexpr int NOUT_LD = 16;
+constexpr int64_t SPLIT_FLOATS = 512 * 64 * 64 + 256 * 256;   // split-reduction partials of the dW GEMMs
 
 struct Layout {
     int64_t w[NL], b[NL], total;
@@ -67,6 +68,7 @@ struct rod_surrogate {
     __bf16 *Ab[3] = {nullptr, nullptr, nullptr};
     float *Y = nullptr, *dY = nullptr, *dZa = nullptr, *dZb = nullptr;
     float *partial = nullptr, *loss = nullptr;
+    float *splitw = nullptr;                 // dW split-reduction partials
     // standardisation (device and host copies)
     float *norm = nullptr;                   // mu_x[96] sd_x[96] mu_t[12] sd_t[12]
     std::vector<float> norm_h;
@@ -183,7 +185,7 @@ int gradient_chunk(rod_surrogate *s, const __bf16 *x, const float *t, const floa
         a.K = M;
         a.C = s->g + s->lay.w[l];
         a.ldc = NPAD[l];
-        e = mlpk::gemm_backward_weight(a, st);
+        e = mlpk::gemm_backward_weight(a, s->splitw, SPLIT_FLOATS, st);
         if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("dW gemm: ") + hipGetErrorString(e));
         e = mlpk::colsum(dZ, M, NPAD[l], ldz, s->g + s->lay.b[l], st);
         if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("db: ") + hipGetErrorString(e));
@@ -532,6 +534,7 @@ int rod_surrogate_create(const rod_surrogate_desc *d, rod_surrogate **out)
     alloc((void **)&s->dZb, R * 256 * 4);
     alloc((void **)&s->partial, (size_t)mlpk::mse_partials(s->max_rows, NOUT_LD) * 4);
     alloc((void **)&s->loss, 4);
+    alloc((void **)&s->splitw, SPLIT_FLOATS * 4);
     alloc((void **)&s->norm, (2 * ROD_SURROGATE_INPUTS + 2 * ROD_SURROGATE_OUTPUTS) * 4);
     if (e != hipSuccess) {
         rod_surrogate_destroy(s);
@@ -572,6 +575,7 @@ void rod_surrogate_destroy(rod_surrogate *s)
     (void)hipFree(s->g);
     (void)hipFree(s->wb);
     (void)hipFree(s->frag);
+    (void)hipFree(s->splitw);
     for (int l = 0; l < 3; ++l) {
         (void)hipFree(s->Z[l]);
         (void)hipFree(s->Ab[l]);
