@@ -221,16 +221,22 @@ __device__ inline bool finite3(T a, T b, T c)
 // drift of the next use the same velocities, so they run as one full drift
 // (exp(-h/2 W) exp(-h/2 W) = exp(-h W) for one axis): a launch of S steps is
 // half drift, S kicks separated by S-1 full drifts, half drift.
+// Waves per SIMD: at 3 (FP64, 168 VGPRs) and 5 (FP32, 96 VGPRs) the compiler
+// keeps the substep loop free of spill traffic (what it spills are the state
+// addresses used once after the loop); measured 8.57 ms vs 9.47 ms (FP64) and
+// 4.60 vs 4.82 ms (FP32) per 1000-step launch on the ragged 4096-rod batch
+// against 2 and 4 waves; 4 FP64 waves spill inside the loop and run 2.2x slower.
+// FP64 tiles of 8 waves stay at 2: their LDS (90 KB) admits one workgroup per CU.
 #ifndef ROD_F64_WAVES_PER_SIMD
-#define ROD_F64_WAVES_PER_SIMD 2
+#define ROD_F64_WAVES_PER_SIMD 3
 #endif
 #ifndef ROD_F32_WAVES_PER_SIMD
-#define ROD_F32_WAVES_PER_SIMD 4
+#define ROD_F32_WAVES_PER_SIMD 5
 #endif
 
 template <typename T, int W>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? ROD_F64_WAVES_PER_SIMD : ROD_F32_WAVES_PER_SIMD)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (W == 8 ? 2 : ROD_F64_WAVES_PER_SIMD) : ROD_F32_WAVES_PER_SIMD)))
 void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
     constexpr bool EDGE = sizeof(T) == 4;
@@ -244,7 +250,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     // lane-private constants (each lane reads back only its own column, so no
     // barrier is needed): a register extension for values used once a substep
     enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
-           C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, N_C };
+           C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3, N_C };
     __shared__ T cst[N_C * TL];
     __shared__ double phs[2 * TL];   // couple phase increment: sin, cos
 
@@ -294,13 +300,18 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         if (last) {
             u0 = B.tail[TVX * B.n_rods + rr]; u1 = B.tail[TVY * B.n_rods + rr]; u2 = B.tail[TVZ * B.n_rods + rr];
         }
-        // ---- constants: hot ones in registers, the rest in this lane's LDS column
+        // ---- constants: all in this lane's LDS column (registers hold the state
+        // and the substep's temporaries, which leaves room for three waves per SIMD)
         const T *pp = B.param + s;
-        const T inv_m = pp[P_INV_M * NS], lh = pp[P_LH * NS], inv_lh = pp[P_INV_LH * NS];
-        const T S1 = pp[P_S1 * NS], S3 = pp[P_S3 * NS];
+        const T lh = pp[P_LH * NS];
         double ps = 0.0, pc = 1.0;
         {
             T *cw = cst + lane;
+            cw[C_INV_M * TL] = pp[P_INV_M * NS];
+            cw[C_LH * TL] = lh;
+            cw[C_INV_LH * TL] = pp[P_INV_LH * NS];
+            cw[C_S1 * TL] = pp[P_S1 * NS];
+            cw[C_S3 * TL] = pp[P_S3 * NS];
             const T J1 = pp[P_J1 * NS];
             cw[C_J1 * TL] = J1;
             cw[C_INV_J1 * TL] = T(1) / J1;
@@ -376,6 +387,10 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 a1[12] = v0; a1[13] = v1; a1[14] = v2;
             }
             from_right<W>(a1, qn, lx1, wave, wl);
+            // curvature at Voronoi point i first: the neighbour frame dies here
+            // (zero stiffness on lanes without a Voronoi point)
+            T k0, k1, k2;
+            log_relative(q, qn, hasv, k0, k1, k2);
             T d0, d1, d2;
             if constexpr (EDGE) {
                 d0 = r0; d1 = r1; d2 = r2;
@@ -387,6 +402,8 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             }
 
             // ---- kinematics and shear/stretch strain of element i
+            const T lh = cl[C_LH * TL], inv_lh = cl[C_INV_LH * TL];
+            const T S1 = cl[C_S1 * TL], S3 = cl[C_S3 * TL];
             const T l2 = d0 * d0 + d1 * d1 + d2 * d2;
             const T inv_l = rsqrt_t(l2);
             const T l = l2 * inv_l;
@@ -409,10 +426,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             from_right<W>(a2, b2, lx2, wave, wl);
             const T ln = hasv ? b2[0] : l;
 
-            // ---- curvature, bending/twisting moment at Voronoi point i
-            // (zero stiffness on lanes without one)
-            T k0, k1, k2;
-            log_relative(q, qn, hasv, k0, k1, k2);
+            // ---- bending/twisting moment at Voronoi point i
             const T inv_Dh = cl[C_INV_DH * TL], Dh = cl[C_DH * TL];
             k0 *= inv_Dh; k1 *= inv_Dh; k2 *= inv_Dh;
             const T eps = (l + ln) * (T(0.5) * inv_Dh);
@@ -435,6 +449,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
 
             // ---- Eq. 1a at node i (and node n on the last lane)
             const T gamma = cl[C_GAMMA * TL];
+            const T inv_m = cl[C_INV_M * TL];
             const T a0 = (nf0 - np0) * inv_m - gamma * v0;
             const T a1x = (nf1 - np1) * inv_m - gamma * v1;
             const T a2x = (nf2 - np2) * inv_m - gamma * v2;
