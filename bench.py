@@ -164,9 +164,17 @@ def time_surrogate():
                  lr_min=1e-5, val_fraction=0.1, seed=7, noise=(1e-4, 1.5e-4, 3e-4, 6e-4))
     ep, val = s.train(btr, **tdesc)
     torch.cuda.synchronize()
-    out["train"] = {"rods": tr.n_rods, "windows": int(2 * (tr.n_elements + tr.n_rods)), "epochs": tdesc["epochs"],
+    t_train = time.perf_counter() - t0
+    windows = int(2 * (tr.n_elements + tr.n_rods))
+    # minibatch rows processed: whole 4096-row batches of the 90% training share, every epoch;
+    # forward + backward = 3 x the forward's FLOP per row (dA and dW each match the forward)
+    rows = (int(0.9 * windows) // tdesc["batch_rows"]) * tdesc["batch_rows"] * tdesc["epochs"]
+    out["train"] = {"rods": tr.n_rods, "windows": windows, "epochs": tdesc["epochs"],
                     "val_loss": float(val), "first_epoch_loss": float(ep[0]), "last_epoch_loss": float(ep[-1]),
-                    "seconds": time.perf_counter() - t0}
+                    "seconds": t_train,
+                    "mlp_tflops": 3 * MLP_FLOP * rows / t_train / 1e12,
+                    "note": "seconds include generating the trajectories; mlp_tflops divides the minibatch "
+                            "MLP work by that whole time"}
     btr.close()
     del tr
     print("surrogate trained", out["train"], file=sys.stderr, flush=True)

@@ -73,6 +73,8 @@ struct DevBatch {
     int32_t *nonfinite;    // [n_rods] set to 1 when the state stops being finite
     int64_t *step;         // global step counter (device)
     const int32_t *active; // [n_rods] or NULL: rods with active[r] == 0 keep their state
+    const int32_t *tile_list;  // [n_list] or NULL: visit only these tiles (all tiles when NULL)
+    int n_list;
     int64_t n_slots;
     int32_t n_rods;
     int32_t n_tiles;
@@ -109,8 +111,10 @@ struct BatchView {
 int batch_view(const rod_batch_opaque *b, BatchView *v);
 // Advance the batch's clock by n steps without stepping (the learned coarse step).
 int batch_advance_clock(rod_batch_opaque *b, int64_t n, hipStream_t s);
-// n plain steps of the rods with active[r] != 0 (device [R]), direct launches.
-int batch_step_masked(rod_batch_opaque *b, int64_t n, const int32_t *active, hipStream_t s);
+// n plain steps of the rods with active[r] != 0 (device [R]), direct launches
+// over the n_list tiles of tile_list (device) that hold those rods.
+int batch_step_masked(rod_batch_opaque *b, int64_t n, const int32_t *active, const int32_t *tile_list, int n_list,
+                      hipStream_t s);
 // Set the batch's clock to time t with its step counter at 0 (direct launches afterwards).
 int batch_set_time(rod_batch_opaque *b, double t, hipStream_t s);
 hipError_t launch_set_step(int64_t *step, int64_t value, hipStream_t s);

@@ -261,7 +261,9 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     const T h = T(B.dt);
     const T hh = T(0.5 * B.dt);
 
-    for (int tile = blockIdx.x; tile < B.n_tiles; tile += gridDim.x) {
+    const int n_work = B.tile_list ? B.n_list : B.n_tiles;
+    for (int it = blockIdx.x; it < n_work; it += gridDim.x) {
+        const int tile = B.tile_list ? B.tile_list[it] : it;
         const int64_t s = (int64_t)tile * TL + lane;
         const int rod = B.slot_rod[s];
         const bool valid = rod >= 0;

@@ -587,13 +587,20 @@ int rodk::batch_advance_clock(rod_batch *b, int64_t n, hipStream_t s)
     return ROD_OK;
 }
 
-int rodk::batch_step_masked(rod_batch *b, int64_t n, const int32_t *active, hipStream_t s)
+int rodk::batch_step_masked(rod_batch *b, int64_t n, const int32_t *active, const int32_t *tile_list, int n_list,
+                            hipStream_t s)
 {
-    b->b32.active = active;
-    b->b64.active = active;
+    if (n_list <= 0 || !tile_list) return fail(ROD_EINVAL, "masked step needs a non-empty tile list");
+    b->b32.active = b->b64.active = active;
+    b->b32.tile_list = b->b64.tile_list = tile_list;
+    b->b32.n_list = b->b64.n_list = n_list;
+    const int grid = b->grid;
+    b->grid = std::min(grid, n_list);
     const int rc = enqueue_steps(b, n, s);
-    b->b32.active = nullptr;
-    b->b64.active = nullptr;
+    b->grid = grid;
+    b->b32.active = b->b64.active = nullptr;
+    b->b32.tile_list = b->b64.tile_list = nullptr;
+    b->b32.n_list = b->b64.n_list = 0;
     if (rc) return rc;
     b->steps += n;
     return ROD_OK;

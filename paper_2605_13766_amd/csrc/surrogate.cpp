@@ -79,12 +79,15 @@ struct rod_surrogate {
     int32_t *win_rod = nullptr, *elem_rod = nullptr;
     int64_t *win_first = nullptr, *elem_first = nullptr;
     float *rodf = nullptr, *disp = nullptr;
+    float2 *phase = nullptr;                 // [R] couple phase sin / cos
     void *saved = nullptr;                   // state copy for targets / the judge
     void *saved2 = nullptr;                  // perturbed start state of a noisy sample
     size_t saved_bytes = 0;
     // coarse stepping
     int32_t *plain = nullptr;                // device [R]: 1 = rod on the plain step
     std::vector<int32_t> plain_h;
+    int32_t *plain_tiles = nullptr;          // device: tiles holding plain rods
+    int n_plain_tiles = 0;
     __bf16 *xall = nullptr;                  // [W][96] standardised features
     float *yall = nullptr;                   // [W][16] network outputs
     rod_batch *judge = nullptr;              // plain re-runs of the sampled rods
@@ -221,11 +224,16 @@ void free_ctx(rod_surrogate *s)
     (void)hipFree(s->win_first);
     (void)hipFree(s->elem_first);
     (void)hipFree(s->rodf);
+    (void)hipFree(s->phase);
+    s->phase = nullptr;
     (void)hipFree(s->disp);
     (void)hipFree(s->saved);
     (void)hipFree(s->saved2);
     s->saved2 = nullptr;
     (void)hipFree(s->plain);
+    (void)hipFree(s->plain_tiles);
+    s->plain_tiles = nullptr;
+    s->n_plain_tiles = 0;
     (void)hipFree(s->xall);
     (void)hipFree(s->yall);
     (void)hipFree(s->jmap);
@@ -296,6 +304,7 @@ int ensure_ctx(rod_surrogate *s, rod_batch *b, rodk::BatchView &v)
     up((void **)&s->elem_first, ef.data(), ef.size() * 8);
     up((void **)&s->rodf, rf.data(), rf.size() * 4);
     up((void **)&s->disp, nullptr, (size_t)w * 3 * 4);
+    up((void **)&s->phase, nullptr, (size_t)R * sizeof(float2));
     s->saved_bytes = v.state_bytes + v.tail_bytes;
     up(&s->saved, nullptr, s->saved_bytes);
     s->plain_h.assign(R, 0);
@@ -319,6 +328,7 @@ surk::WinArgs win_args(const rod_surrogate *s, const rodk::BatchView &v)
     a.n_windows = s->n_windows;
     a.tau = (float)(s->k * v.dt);
     a.time = v.time;
+    a.phase = s->phase;
     return a;
 }
 
@@ -400,7 +410,10 @@ int loss_chunk(rod_surrogate *s, const __bf16 *x, const float *t, const float *m
 
 int upload_norm(rod_surrogate *s)
 {
-    SHIPCHK(hipMemcpy(s->norm, s->norm_h.data(), s->norm_h.size() * 4, hipMemcpyHostToDevice));
+    // device copy: mu_x, sd_x, mu_t, sd_t, then 1 / sd_x (inputs are standardised by multiplication)
+    std::vector<float> d(s->norm_h);
+    for (int i = 0; i < ROD_SURROGATE_INPUTS; ++i) d.push_back(1.0f / s->norm_h[ROD_SURROGATE_INPUTS + i]);
+    SHIPCHK(hipMemcpy(s->norm, d.data(), d.size() * 4, hipMemcpyHostToDevice));
     return ROD_OK;
 }
 
@@ -455,19 +468,42 @@ int ensure_step_buffers(rod_surrogate *s)
     return ROD_OK;
 }
 
+// Upload the fallback flags and the sorted list of tiles that hold plain rods.
+int upload_plain(rod_surrogate *s, const rodk::BatchView &v, hipStream_t st)
+{
+    const int TL = 64 * v.waves;
+    std::vector<int32_t> tiles;
+    for (int r = 0; r < v.n_rods; ++r)
+        if (s->plain_h[r]) tiles.push_back((int32_t)(v.rod_slot[r] / TL));
+    std::sort(tiles.begin(), tiles.end());
+    tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
+    if ((int)tiles.size() > s->n_plain_tiles || !s->plain_tiles) {
+        (void)hipFree(s->plain_tiles);
+        s->plain_tiles = nullptr;
+        SHIPCHK(hipMalloc((void **)&s->plain_tiles, std::max<size_t>(tiles.size(), 1) * 4));
+    }
+    s->n_plain_tiles = (int)tiles.size();
+    if (!tiles.empty())
+        SHIPCHK(hipMemcpyAsync(s->plain_tiles, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, st));
+    SHIPCHK(hipMemcpyAsync(s->plain, s->plain_h.data(), s->plain_h.size() * 4, hipMemcpyHostToDevice, st));
+    SHIPCHK(hipStreamSynchronize(st));   // the host vectors are reused
+    return ROD_OK;
+}
+
 // features -> network -> deltas applied to the rods off the plain step; the
 // plain ones take k plain steps.  Advances the clock by k.
 int coarse_step(rod_surrogate *s, rod_batch *b, const rodk::BatchView &v, int n_plain, hipStream_t st)
 {
-    if (n_plain == v.n_rods) return rodk::batch_step_masked(b, s->k, s->plain, st);   // nothing left to predict
-    const float *mux = s->norm, *sdx = s->norm + ROD_SURROGATE_INPUTS;
+    if (n_plain == v.n_rods)   // nothing left to predict
+        return rodk::batch_step_masked(b, s->k, s->plain, s->plain_tiles, s->n_plain_tiles, st);
+    const float *mux = s->norm, *isdx = s->norm + 2 * ROD_SURROGATE_INPUTS + 2 * ROD_SURROGATE_OUTPUTS;
     const float *mut = s->norm + 2 * ROD_SURROGATE_INPUTS, *sdt = mut + ROD_SURROGATE_OUTPUTS;
-    hipError_t e = surk::features(win_args(s, v), nullptr, s->xall, mux, sdx, st);
+    hipError_t e = surk::features(win_args(s, v), nullptr, s->xall, mux, isdx, st);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("features: ") + hipGetErrorString(e));
     int rc = infer(s, s->xall, s->n_windows, s->yall, NOUT_LD, st);
     if (rc) return rc;
     if (n_plain > 0) {
-        if ((rc = rodk::batch_step_masked(b, s->k, s->plain, st))) return rc;
+        if ((rc = rodk::batch_step_masked(b, s->k, s->plain, s->plain_tiles, s->n_plain_tiles, st))) return rc;
     }
     e = surk::apply(win_args(s, v), s->yall, NOUT_LD, mut, sdt, n_plain > 0 ? s->plain : nullptr, s->disp, s->elem_rod,
                     s->elem_first, s->n_elems, st);
@@ -535,7 +571,7 @@ int rod_surrogate_create(const rod_surrogate_desc *d, rod_surrogate **out)
     alloc((void **)&s->partial, (size_t)mlpk::mse_partials(s->max_rows, NOUT_LD) * 4);
     alloc((void **)&s->loss, 4);
     alloc((void **)&s->splitw, SPLIT_FLOATS * 4);
-    alloc((void **)&s->norm, (2 * ROD_SURROGATE_INPUTS + 2 * ROD_SURROGATE_OUTPUTS) * 4);
+    alloc((void **)&s->norm, (3 * ROD_SURROGATE_INPUTS + 2 * ROD_SURROGATE_OUTPUTS) * 4);
     if (e != hipSuccess) {
         rod_surrogate_destroy(s);
         return sfail(e == hipErrorOutOfMemory ? ROD_ENOMEM : ROD_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -834,7 +870,7 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
     }
     TRY(rod_surrogate_set_normalization(s, mu.data(), sd.data(), mu.data() + ROD_SURROGATE_INPUTS,
                                         sd.data() + ROD_SURROGATE_INPUTS));
-    const float *mux = s->norm, *sdx = s->norm + ROD_SURROGATE_INPUTS;
+    const float *mux = s->norm, *isdx = s->norm + 2 * ROD_SURROGATE_INPUTS + 2 * ROD_SURROGATE_OUTPUTS;
     const float *mut = s->norm + 2 * ROD_SURROGATE_INPUTS, *sdt = mut + ROD_SURROGATE_OUTPUTS;
     // ---- split and train
     std::mt19937_64 rng(d->seed);
@@ -847,7 +883,7 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
         std::shuffle(tr.begin(), tr.end(), rng);
         TRYH(hipMemcpyAsync(idx, tr.data(), n_tr * 8, hipMemcpyHostToDevice, st));
         for (int64_t bi = 0; bi < steps_per_epoch; ++bi, ++step) {
-            TRYH(surk::gather_rows(F, T, Mk, idx + bi * B, B, mux, sdx, mut, sdt, xb, tb, mb, st));
+            TRYH(surk::gather_rows(F, T, Mk, idx + bi * B, B, mux, isdx, mut, sdt, xb, tb, mb, st));
             TRY(gradient_chunk(s, xb, tb, mb, B, st));
             const double ph = total_steps > 1 ? (double)step / (double)(total_steps - 1) : 1.0;
             const float lr = (float)(d->lr_min + 0.5 * (d->lr - d->lr_min) * (1.0 + std::cos(M_PI * ph)));
@@ -866,7 +902,7 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
     if (n_val >= B) {
         TRYH(hipMemcpyAsync(idx, val.data(), n_val * 8, hipMemcpyHostToDevice, st));
         for (int64_t v0 = 0; v0 + B <= n_val; v0 += B) {
-            TRYH(surk::gather_rows(F, T, Mk, idx + v0, B, mux, sdx, mut, sdt, xb, tb, mb, st));
+            TRYH(surk::gather_rows(F, T, Mk, idx + v0, B, mux, isdx, mut, sdt, xb, tb, mb, st));
             TRY(loss_chunk(s, xb, tb, mb, B, st));
             float l = 0;
             TRYH(hipMemcpyAsync(&l, s->loss, 4, hipMemcpyDeviceToHost, st));
@@ -987,8 +1023,8 @@ int rod_surrogate_step(rod_surrogate *s, rod_batch *b, int64_t n_coarse, const r
             SHIPCHK(hipMemcpyAsync(s->jsel, fail_sel.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
             e = surk::copy_rods(jv2.f32, cv.f32, s->jmap, s->jsel, m, n, true, true, st);
             if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("fallback copy: ") + hipGetErrorString(e));
-            SHIPCHK(hipMemcpyAsync(s->plain, s->plain_h.data(), s->plain_h.size() * 4, hipMemcpyHostToDevice, st));
-            SHIPCHK(hipStreamSynchronize(st));
+            rodk::BatchView pv;
+            if ((rc = rodk::batch_view(b, &pv)) || (rc = upload_plain(s, pv, st))) return rc;
             out.rods_failed += nf;
             n_plain += nf;
         }
@@ -1015,8 +1051,7 @@ int rod_surrogate_reset_fallback(rod_surrogate *s, rod_batch *b)
     int rc = ensure_ctx(s, b, v);
     if (rc) return rc;
     std::fill(s->plain_h.begin(), s->plain_h.end(), 0);
-    SHIPCHK(hipMemcpy(s->plain, s->plain_h.data(), s->plain_h.size() * 4, hipMemcpyHostToDevice));
-    return ROD_OK;
+    return upload_plain(s, v, nullptr);
 }
 
 // File: 8-byte magic "RODSURR1", int32 k, int32 parameter count, int32

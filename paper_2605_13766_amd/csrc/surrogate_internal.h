@@ -24,14 +24,16 @@ struct WinArgs {
     int64_t n_windows;
     float tau;                   // k dt
     double time;
+    float2 *phase;               // [R] scratch: sin and cos of each rod's couple phase at `time`
 };
 
-hipError_t features(const WinArgs &A, float *raw, __bf16 *xn, const float *mu, const float *sd, hipStream_t s);
+// raw FP32 rows and/or BF16 rows (x - mu) * isd (isd = 1 / sd per column)
+hipError_t features(const WinArgs &A, float *raw, __bf16 *xn, const float *mu, const float *isd, hipStream_t s);
 hipError_t targets(const WinArgs &A, const rodk::DevBatch<float> &S0, float *tgt, float *mask, hipStream_t s);
 hipError_t apply(const WinArgs &A, const float *y, int ldy, const float *mu, const float *sd, const int32_t *skip,
                  float *disp, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems, hipStream_t s);
 hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, const int64_t *idx, int64_t rows,
-                       const float *mu_x, const float *sd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
+                       const float *mu_x, const float *isd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
                        float *m, hipStream_t s);
 // dst rod k <-> src rod map[k] (to_src: copy back into src); sel[k] == 0 skips k
 hipError_t copy_rods(const rodk::DevBatch<float> &dst, const rodk::DevBatch<float> &src, const int32_t *map,

@@ -124,10 +124,90 @@ __device__ inline void rotate_left(float q[9], V3 u)
 }  // namespace
 
 // ---------------------------------------------------------------- features
-__global__ void features_kernel(const WinArgs A, float *raw, __bf16 *xn, const float *mu, const float *sd)
+// sin and cos of each rod's couple phase 2 pi f t + phi, once per rod (FP64)
+__global__ void phase_kernel(const float *rodf, int n_rods, double time, float2 *out)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= A.n_windows) return;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rods) return;
+    const float *rf = rodf + (int64_t)r * NRF;
+    const double ph = 2.0 * M_PI * (double)rf[RF_FREQ] * time + (double)rf[RF_PHASE];
+    out[r] = float2{(float)sin(ph), (float)cos(ph)};
+}
+
+// midpoint of element c + D minus midpoint of element c (D = -2..2), from the
+// edges, in the order of mid_offset
+template <int D>
+__device__ inline V3 mid_off(const Rod &R, int c)
+{
+    if constexpr (D == 0) {
+        return {0.f, 0.f, 0.f};
+    } else if constexpr (D > 0) {
+        V3 s = 0.5f * R.edge(c);
+        if constexpr (D == 2) s = s + R.edge(c + 1);
+        return s + 0.5f * R.edge(c + D);
+    } else {
+        V3 s = 0.5f * R.edge(c);
+        if constexpr (D == -2) s = s + R.edge(c - 1);
+        s = s + 0.5f * R.edge(c + D);
+        return {-s.x, -s.y, -s.z};
+    }
+}
+
+// Write 16 feature values at columns col0..col0+15 of window g: FP32 rows
+// and/or BF16 rows standardised as (x - mu) * (1 / sd), as 16-byte stores.
+__device__ inline void emit16(const float (&v)[16], int col0, int64_t g, float *raw, __bf16 *xn, const float *mu,
+                              const float *isd)
+{
+    if (raw) {
+        float4 *o = reinterpret_cast<float4 *>(raw + g * N_FEAT + col0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = float4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+    }
+    if (xn) {
+        // xn points at this thread's BF16 row (in LDS: the wave's staging tile)
+        uint4 *o = reinterpret_cast<uint4 *>(xn + col0);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            __bf16 b[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = (__bf16)((v[8 * k + j] - mu[col0 + 8 * k + j]) * isd[col0 + 8 * k + j]);
+            o[k] = __builtin_bit_cast(uint4, b);
+        }
+    }
+}
+
+// stencil slot D (element c + D) of window g
+template <int D>
+__device__ inline void emit_slot(const Rod &R, int c, int n, const float (&qc)[9], V3 uc, float iL, float tau,
+                                 int64_t g, float *raw, __bf16 *xn, const float *mu, const float *isd)
+{
+    float o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o[k] = 0.f;
+    const int j = c + D;
+    if (j >= 0 && j < n) {
+        const V3 d = matvec(qc, mid_off<D>(R, c));
+        o[0] = d.x * iL; o[1] = d.y * iL; o[2] = d.z * iL;
+        const V3 uj = 0.5f * (R.node_v(j) + R.node_v(j + 1));
+        const V3 du = matvec(qc, uj - uc);
+        o[3] = du.x * tau * iL; o[4] = du.y * tau * iL; o[5] = du.z * tau * iL;
+        float qj[9];
+        R.dirs(j, qj);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                o[6 + 3 * a + b] = qj[3 * a] * qc[3 * b] + qj[3 * a + 1] * qc[3 * b + 1] + qj[3 * a + 2] * qc[3 * b + 2];
+        const V3 wj = R.omega(j);
+        o[12] = wj.x * tau; o[13] = wj.y * tau; o[14] = wj.z * tau;
+        o[15] = 1.f;
+    }
+    emit16(o, 16 * (D + 2), g, raw, xn, mu, isd);
+}
+
+__device__ inline void window_features(const WinArgs &A, int64_t g, float *raw, __bf16 *xn, const float *mu,
+                                const float *isd)
+{
     const int r = A.win_rod[g];
     const Rod R(A.B, r);
     const int n = R.n;
@@ -141,27 +221,12 @@ __global__ void features_kernel(const WinArgs A, float *raw, __bf16 *xn, const f
     const float iL = 1.f / L;
     const float tau = A.tau;
     const V3 uc = 0.5f * (R.node_v(c) + R.node_v(c + 1));
-    float f[N_FEAT];
-    for (int k = 0; k < N_FEAT; ++k) f[k] = 0.f;
-    for (int si = 0; si < 5; ++si) {
-        const int j = c + si - 2;
-        if (j < 0 || j >= n) continue;
-        float* o = f + 16 * si;
-        const V3 d = matvec(qc, mid_offset(R, c, j));
-        o[0] = d.x * iL; o[1] = d.y * iL; o[2] = d.z * iL;
-        const V3 uj = 0.5f * (R.node_v(j) + R.node_v(j + 1));
-        const V3 du = matvec(qc, uj - uc);
-        o[3] = du.x * tau * iL; o[4] = du.y * tau * iL; o[5] = du.z * tau * iL;
-        float qj[9];
-        R.dirs(j, qj);
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 3; ++b)
-                o[6 + 3 * a + b] = qj[3 * a] * qc[3 * b] + qj[3 * a + 1] * qc[3 * b + 1] + qj[3 * a + 2] * qc[3 * b + 2];
-        const V3 wj = R.omega(j);
-        o[12] = wj.x * tau; o[13] = wj.y * tau; o[14] = wj.z * tau;
-        o[15] = 1.f;
-    }
-    float *gl = f + 80;
+    emit_slot<-2>(R, c, n, qc, uc, iL, tau, g, raw, xn, mu, isd);
+    emit_slot<-1>(R, c, n, qc, uc, iL, tau, g, raw, xn, mu, isd);
+    emit_slot<0>(R, c, n, qc, uc, iL, tau, g, raw, xn, mu, isd);
+    emit_slot<1>(R, c, n, qc, uc, iL, tau, g, raw, xn, mu, isd);
+    emit_slot<2>(R, c, n, qc, uc, iL, tau, g, raw, xn, mu, isd);
+    float gl[16];
     const V3 vp = matvec(qc, R.node_v(p));
     gl[0] = vp.x * tau * iL; gl[1] = vp.y * tau * iL; gl[2] = vp.z * tau * iL;
     const V3 ec = R.edge(c);
@@ -175,23 +240,34 @@ __global__ void features_kernel(const WinArgs A, float *raw, __bf16 *xn, const f
     gl[11] = (float)c / (float)n;
     gl[12] = w == n ? 1.f : 0.f;
     gl[13] = rf[RF_AMP];
-    const double ph = 2.0 * M_PI * (double)rf[RF_FREQ] * A.time + (double)rf[RF_PHASE];
-    gl[14] = (float)sin(ph);
-    gl[15] = (float)cos(ph);
-    // 16-byte stores: a window's row is 384 bytes of FP32 or 192 bytes of BF16
-    if (raw) {
-        float4 *o = reinterpret_cast<float4 *>(raw + g * N_FEAT);
-        for (int k = 0; k < N_FEAT / 4; ++k) o[k] = float4{f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
-    }
-    if (xn) {
-        uint4 *o = reinterpret_cast<uint4 *>(xn + g * N_FEAT);
-        for (int k = 0; k < N_FEAT / 8; ++k) {
-            __bf16 v[8];
-            for (int j = 0; j < 8; ++j) v[j] = (__bf16)((f[8 * k + j] - mu[8 * k + j]) / sd[8 * k + j]);
-            o[k] = __builtin_bit_cast(uint4, v);
-        }
-    }
+    const float2 sc = A.phase[r];
+    gl[14] = sc.x;
+    gl[15] = sc.y;
+    emit16(gl, 80, g, raw, xn, mu, isd);
 }
+
+// One wave per workgroup.  BF16 rows are staged in LDS (64 rows x 192 bytes)
+// and written out as lane-contiguous 16-byte chunks, so every store
+// instruction covers 1 KB of consecutive memory.
+constexpr int FEAT_BLOCK = 64;
+constexpr int ROW_BF16 = N_FEAT;   // 192 bytes
+
+__global__ __launch_bounds__(FEAT_BLOCK) void features_kernel(const WinArgs A, float *raw, __bf16 *xn, const float *mu,
+                                                             const float *isd)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 rows[FEAT_BLOCK * ROW_BF16];
+    const int64_t g0 = (int64_t)blockIdx.x * FEAT_BLOCK;
+    const int64_t g = g0 + threadIdx.x;
+    if (g < A.n_windows) window_features(A, g, raw, xn ? rows + threadIdx.x * ROW_BF16 : nullptr, mu, isd);
+    if (!xn) return;
+    __syncthreads();
+    const int64_t nrows = A.n_windows - g0 < FEAT_BLOCK ? A.n_windows - g0 : FEAT_BLOCK;
+    const int chunks = (int)nrows * (ROW_BF16 * 2 / 16);
+    const uint4 *src = reinterpret_cast<const uint4 *>(rows);
+    uint4 *dst = reinterpret_cast<uint4 *>(xn + g0 * N_FEAT);
+    for (int k = threadIdx.x; k < chunks; k += FEAT_BLOCK) dst[k] = src[k];
+}
+
 
 // ---------------------------------------------------------------- targets
 // S0 is the state at t, A.B the state at t + tau (same layout)
@@ -338,13 +414,13 @@ __global__ void apply_elems_kernel(const WinArgs A, const float *y, int ldy, con
 
 // ---------------------------------------------------------------- training rows
 __global__ void gather_rows_kernel(const float *fraw, const float *traw, const float *mraw, const int64_t *idx,
-                                   int64_t rows, const float *mu_x, const float *sd_x, const float *mu_t,
+                                   int64_t rows, const float *mu_x, const float *isd_x, const float *mu_t,
                                    const float *sd_t, __bf16 *x, float *t, float *m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows) return;
     const int64_t s = idx[i];
-    for (int k = 0; k < N_FEAT; ++k) x[i * N_FEAT + k] = (__bf16)((fraw[s * N_FEAT + k] - mu_x[k]) / sd_x[k]);
+    for (int k = 0; k < N_FEAT; ++k) x[i * N_FEAT + k] = (__bf16)((fraw[s * N_FEAT + k] - mu_x[k]) * isd_x[k]);
     for (int k = 0; k < N_OUT; ++k) {
         t[i * N_OUT + k] = (traw[s * N_OUT + k] - mu_t[k]) / sd_t[k];
         m[i * N_OUT + k] = mraw[s * N_OUT + k];
@@ -528,9 +604,11 @@ __global__ void perturb_kernel(DevBatch<float> B, const int32_t *elem_rod, const
 // ---------------------------------------------------------------- launchers
 static inline dim3 blocks(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
-hipError_t features(const WinArgs &A, float *raw, __bf16 *xn, const float *mu, const float *sd, hipStream_t s)
+hipError_t features(const WinArgs &A, float *raw, __bf16 *xn, const float *mu, const float *isd, hipStream_t s)
 {
-    hipLaunchKernelGGL(features_kernel, blocks(A.n_windows, 128), dim3(128), 0, s, A, raw, xn, mu, sd);
+    hipLaunchKernelGGL(phase_kernel, blocks(A.B.n_rods), dim3(256), 0, s, A.rodf, A.B.n_rods, A.time, A.phase);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    hipLaunchKernelGGL(features_kernel, blocks(A.n_windows, FEAT_BLOCK), dim3(FEAT_BLOCK), 0, s, A, raw, xn, mu, isd);
     return hipGetLastError();
 }
 
@@ -552,10 +630,10 @@ hipError_t apply(const WinArgs &A, const float *y, int ldy, const float *mu, con
 }
 
 hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, const int64_t *idx, int64_t rows,
-                       const float *mu_x, const float *sd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
+                       const float *mu_x, const float *isd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
                        float *m, hipStream_t s)
 {
-    hipLaunchKernelGGL(gather_rows_kernel, blocks(rows), dim3(256), 0, s, fraw, traw, mraw, idx, rows, mu_x, sd_x, mu_t,
+    hipLaunchKernelGGL(gather_rows_kernel, blocks(rows), dim3(256), 0, s, fraw, traw, mraw, idx, rows, mu_x, isd_x, mu_t,
                        sd_t, x, t, m);
     return hipGetLastError();
 }
