@@ -513,7 +513,11 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         }
 
         if (act) {
-            T *so = B.state + s;
+            // an opaque slot index: the store addresses are recomputed here rather
+            // than kept (and spilled) across the substep loop
+            int64_t s_out = s;
+            asm volatile("" : "+v"(s_out));
+            T *so = B.state + s_out;
             so[RX * NS] = r0; so[RY * NS] = r1; so[RZ * NS] = r2;
             so[VX * NS] = v0; so[VY * NS] = v1; so[VZ * NS] = v2;
 #pragma unroll
