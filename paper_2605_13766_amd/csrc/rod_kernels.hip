@@ -243,16 +243,25 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     constexpr int TL = 64 * W;
     constexpr int NX1 = EDGE ? 9 : 15;     // from the right: Q (, r, v)
     constexpr int NL = W > 1 ? W : 1;
-    __shared__ T lx1[NL * NX1];            // wave-edge values of the four exchanges
-    __shared__ T lx2[NL];
-    __shared__ T lx3[NL * 9];
-    __shared__ T lx4[NL * 3];
     // lane-private constants (each lane reads back only its own column, so no
     // barrier is needed): a register extension for values used once a substep
     enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
            C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3, N_C };
-    __shared__ T cst[N_C * TL];
-    __shared__ double phs[2 * TL];   // couple phase increment: sin, cos
+    // One LDS block in a fixed order: the small wave-edge exchange buffers first,
+    // so their addresses fit the 8-bit offsets of ds_write2/ds_read2 and need no
+    // per-access address arithmetic, then the constant columns.
+    struct Shared {
+        T lx1[NL * NX1];           // wave-edge values of the four exchanges
+        T lx2[NL];
+        T lx3[NL * 9];
+        T lx4[NL * 3];
+        double phs[2 * TL];        // couple phase increment: sin, cos
+        T cst[N_C * TL];
+    };
+    __shared__ Shared sh;
+    T *const lx1 = sh.lx1, *const lx2 = sh.lx2, *const lx3 = sh.lx3, *const lx4 = sh.lx4;
+    T *const cst = sh.cst;
+    double *const phs = sh.phs;
 
     const int lane = threadIdx.x;
     const int wave = lane >> 6, wl = lane & 63;
