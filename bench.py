@@ -261,7 +261,7 @@ def main(argv=None):
                     help="only run a plain device-to-device copy of MIB MiB three times (for scaling HBM counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         return 2
 

@@ -49,7 +49,7 @@ enum {
     ROD_ENOMEM = -2,        /* device or host allocation failed */
     ROD_EDEVICE = -3,       /* a HIP runtime call failed */
     ROD_ENONFINITE = -4,    /* a rod's state became NaN/Inf (see rod_get_flags) */
-    ROD_EUNSUPPORTED = -5   /* valid but outside what this build supports */
+    ROD_EUNSUPPORTED = -5   /* valid but outside what the library supports */
 };
 
 enum { ROD_F64 = 0, ROD_F32 = 1 };

@@ -1,7 +1,7 @@
 /*
  * rod_surrogate.h -- C boundary of the learned coarse step.
  *
- * The surrogate is this build's addition to the discrete Cosserat-rod step
+ * The surrogate is this library's addition to the discrete Cosserat-rod step
  * (the paper, Elastica++, only motivates learning-oriented workflows in its
  * introduction): a per-element MLP that maps a 5-element stencil window of a
  * rod, expressed in the centre element's material frame, to the change of

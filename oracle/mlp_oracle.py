@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg use it; the GPU library never does.
 
 The network is not from the paper (which only motivates learning-oriented
-workflows); it is the learned coarse step of this build: 4 linear layers
+workflows); it is the library's learned coarse step: 4 linear layers
 F_in -> 256 -> 256 -> 256 -> 12, SiLU x*sigmoid(x) after the first three,
 BF16 weights and BF16 activations between layers (round to nearest even at
 each layer input), sums of products in FP64 here (FP32 accumulation on the

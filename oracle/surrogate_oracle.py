@@ -1,8 +1,8 @@
 """FP64 CPU oracle of the learned coarse step's data path: window features,
 training targets, applying predicted deltas, and the judge's error measures.
 
-TEST INFRASTRUCTURE ONLY (tests, smoke, CPU baseline).  Definitions (this
-build's own; the paper has no surrogate): for a rod with n elements there are
+TEST INFRASTRUCTURE ONLY (tests, smoke, CPU baseline).  Definitions (the
+library's own; the paper has no surrogate): for a rod with n elements there are
 n + 1 windows; window w < n is centred on element c = w and targets node c and
 element c, window n is centred on element n - 1 and targets node n (its
 element outputs are masked).  tau = k * dt is the coarse step; lh_c is the

@@ -1,5 +1,5 @@
 // surrogate.cpp -- host runtime of the learned coarse step (rod_surrogate.h):
-// parameter layout, MLP workspace, forward / gradient / Adam drivers.
+// parameter layout, MLP workspace, forward / gradient / Adam routines, training, the coarse step and its judge.
 #include "rod_surrogate.h"
 #include "mlp_internal.h"
 #include "rod_internal.h"

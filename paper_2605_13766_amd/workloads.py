@@ -8,8 +8,8 @@ and the CPU oracle can consume the very same arrays.
 
 Workloads follow the problem statement of the Cosserat-rod model (Methods,
 "Cosserat rod dynamics": centreline r, row director matrix Q = {d1,d2,d3}^T,
-material parameters rho, E, G, alpha_c, cross-section) and the batch shapes
-listed for this build:
+material parameters rho, E, G, alpha_c, cross-section) and these batch
+shapes:
 
 * ``single_cantilever``  : 1 rod, 100 elements, 1 m, clamped at s=0, tip force.
 * ``ragged_batch``       : free-free rods of 16..256 elements, smooth random
