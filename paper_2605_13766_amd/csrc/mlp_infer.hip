@@ -29,16 +29,15 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// 2 row blocks (32 rows) per wave at 2 waves per SIMD measured 618 TFLOP/s on
-// 17M rows, against 504 for 4 row blocks at 1 wave per SIMD: the second wave
-// hides the SiLU epilogue (two transcendentals per element, which at about
-// 0.8 SIMD cycles per output outweigh the 0.5 cycles of its MFMA work) and the
-// fragment latency.
+// Row blocks per wave and waves per SIMD, measured on 17M rows once the SiLU
+// uses the hardware reciprocal: 4 blocks (64 rows) at 1 wave per SIMD 6.04 ms,
+// 3 at 1 wave 6.25 ms, 2 at 2 waves 6.51 ms, 1 at 4 waves 15.3 ms.  With the
+// lighter epilogue the weight reuse of 64 rows per fragment wins.
 #ifndef ROD_MLP_ROW_BLOCKS
-#define ROD_MLP_ROW_BLOCKS 2
+#define ROD_MLP_ROW_BLOCKS 4
 #endif
 #ifndef ROD_MLP_WAVES_PER_SIMD
-#define ROD_MLP_WAVES_PER_SIMD 2
+#define ROD_MLP_WAVES_PER_SIMD 1
 #endif
 constexpr int IR = ROD_MLP_ROW_BLOCKS;                 // 16-row blocks per wave
 constexpr int ROWS_PER_WAVE = 16 * IR;
@@ -48,7 +47,9 @@ constexpr int WAVES = 4;
 constexpr int F_BASE[4] = {0, 48, 176, 304};
 constexpr int N_FRAG = 312;
 
-__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU z sigma(z) with the hardware reciprocal (1 ulp) instead of an IEEE
+// division: the result is rounded to BF16 right after
+__device__ inline float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 __device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
 
@@ -66,11 +67,14 @@ __device__ __forceinline__ void load_tile(uint4 (&w)[CI], const uint4 *__restric
     for (int c = 0; c < CI; ++c) w[c] = frag[(t * CI + c) * 64 + lane];
 }
 
+// acc = bias + W^T hin for one output tile (the accumulators start at the bias)
 template <int CI>
-__device__ __forceinline__ void mma_tile(f32x4 (&acc)[IR], const uint4 (&w)[CI], const bf16x8 (&hin)[IR][CI])
+__device__ __forceinline__ void mma_tile(f32x4 (&acc)[IR], const uint4 (&w)[CI], const bf16x8 (&hin)[IR][CI],
+                                         const float *__restrict__ bias, int t, int g)
 {
+    const float4 b = *reinterpret_cast<const float4 *>(bias + 16 * t + 4 * g);
 #pragma unroll
-    for (int q = 0; q < IR; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < IR; ++q) acc[q] = f32x4{b.x, b.y, b.z, b.w};
 #pragma unroll
     for (int c = 0; c < CI; ++c) {
         const bf16x8 a = as_bf16x8(w[c]);
@@ -80,15 +84,12 @@ __device__ __forceinline__ void mma_tile(f32x4 (&acc)[IR], const uint4 (&w)[CI],
 }
 
 template <int TO>
-__device__ __forceinline__ void epilogue(const f32x4 (&acc)[IR], bf16x8 (&hout)[IR][TO / 2], int t,
-                                         const float *__restrict__ bias, int g)
+__device__ __forceinline__ void epilogue(const f32x4 (&acc)[IR], bf16x8 (&hout)[IR][TO / 2], int t)
 {
-    const float4 b = *reinterpret_cast<const float4 *>(bias + 16 * t + 4 * g);
-    const float bb[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
     for (int q = 0; q < IR; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hout[q][t >> 1][(t & 1) * 4 + r] = (__bf16)silu_f(acc[q][r] + bb[r]);
+        for (int r = 0; r < 4; ++r) hout[q][t >> 1][(t & 1) * 4 + r] = (__bf16)silu_f(acc[q][r]);
 }
 
 // One hidden layer: hout = bf16(silu(W^T hin + b)) for the wave's IR row blocks,
@@ -104,16 +105,16 @@ __device__ __forceinline__ void dense_silu(const bf16x8 (&hin)[IR][CI], bf16x8 (
     f32x4 acc0[IR], acc1[IR];
     load_tile<CI>(w0, frag, 0, lane);
     load_tile<CI>(w1, frag, 1, lane);
-    mma_tile<CI>(acc0, w0, hin);
+    mma_tile<CI>(acc0, w0, hin, bias, 0, g);
 #pragma unroll
     for (int t = 0; t < TO; t += 2) {
         // acc0 holds tile t; w1 holds tile t + 1
         if (t + 2 < TO) load_tile<CI>(w0, frag, t + 2, lane);
-        mma_tile<CI>(acc1, w1, hin);
-        epilogue<TO>(acc0, hout, t, bias, g);
+        mma_tile<CI>(acc1, w1, hin, bias, t + 1, g);
+        epilogue<TO>(acc0, hout, t);
         if (t + 3 < TO) load_tile<CI>(w1, frag, t + 3, lane);
-        if (t + 2 < TO) mma_tile<CI>(acc0, w0, hin);
-        epilogue<TO>(acc1, hout, t + 1, bias, g);
+        if (t + 2 < TO) mma_tile<CI>(acc0, w0, hin, bias, t + 2, g);
+        epilogue<TO>(acc1, hout, t + 1);
     }
 }
 
@@ -141,21 +142,21 @@ void mlp_infer_kernel(const InferArgs a)
     dense_silu<8, 16>(h1, h2, frag + F_BASE[1] * 64, a.bias[1], lane);
     dense_silu<8, 16>(h2, h1, frag + F_BASE[2] * 64, a.bias[2], lane);
     // output layer: one 16-wide tile (12 outputs and 4 zero columns), no activation
+    const float4 b = *reinterpret_cast<const float4 *>(a.bias[3] + 4 * g);
     f32x4 acc[IR];
 #pragma unroll
-    for (int q = 0; q < IR; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < IR; ++q) acc[q] = f32x4{b.x, b.y, b.z, b.w};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const bf16x8 w = as_bf16x8(frag[(F_BASE[3] + c) * 64 + lane]);
 #pragma unroll
         for (int q = 0; q < IR; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h1[q][c], acc[q], 0, 0, 0);
     }
-    const float4 b = *reinterpret_cast<const float4 *>(a.bias[3] + 4 * g);
 #pragma unroll
     for (int q = 0; q < IR; ++q) {
         const int64_t row = m0 + 16 * q + i;
         if (row >= a.M) continue;
-        const float4 o{acc[q][0] + b.x, acc[q][1] + b.y, acc[q][2] + b.z, acc[q][3] + b.w};
+        const float4 o{acc[q][0], acc[q][1], acc[q][2], acc[q][3]};
         if (a.ldy == 16) {
             *reinterpret_cast<float4 *>(a.y + row * 16 + 4 * g) = o;
         } else if (g < 3) {

@@ -22,7 +22,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ inline float to_f(__bf16 x) { return (float)x; }
 __device__ inline float to_f(float x) { return x; }
 
-__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU z sigma(z) with the hardware reciprocal (1 ulp) instead of an IEEE
+// division: the result is rounded to BF16 right after
+__device__ inline float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ inline float dsilu_f(float z)
 {
     const float s = 1.0f / (1.0f + __expf(-z));
