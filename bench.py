@@ -218,6 +218,18 @@ def time_surrogate():
         e1.record(stream)
         torch.cuda.synchronize()
         mlp_ms = e0.elapsed_time(e1) / 3
+        # one training step (forward keeping activations, backward, Adam) on the largest
+        # workspace chunk, timed alone: the backward path's own throughput
+        trows = 65536
+        xt = x[:trows].contiguous()
+        tt = torch.randn((trows, 12), device="cuda")
+        s.train_step(xt, tt, lr=0.0, stream=stream, return_loss=False)
+        e0.record(stream)
+        for _ in range(5):
+            s.train_step(xt, tt, lr=0.0, stream=stream, return_loss=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        train_ms = e0.elapsed_time(e1) / 5
         flags = sb.flags(stream=stream)
         sb.close()
         pb.close()
@@ -243,6 +255,13 @@ def time_surrogate():
         "judge": st,
         "mlp_roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK, "unit": "TFLOP/s",
                          "frac": achieved / BF16_PEAK, "rows": rows, "launch_ms": mlp_ms},
+        "train_step_roofline": {"bound": "mfma", "achieved": 3 * MLP_FLOP * trows / (train_ms * 1e-3) / 1e12,
+                                "peak": BF16_PEAK, "unit": "TFLOP/s",
+                                "frac": 3 * MLP_FLOP * trows / (train_ms * 1e-3) / 1e12 / BF16_PEAK,
+                                "rows": trows, "ms": train_ms,
+                                "work": "forward with saved activations, backward (dA, split-reduction dW, bias "
+                                        "sums), MSE gradient, Adam, BF16 refresh and fragment repack; "
+                                        "3 x the forward's FLOP per row"},
     })
     return out
 

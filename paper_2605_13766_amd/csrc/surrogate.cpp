@@ -76,6 +76,7 @@ struct rod_surrogate {
     const rod_batch *ctx_batch = nullptr;
     int64_t ctx_rods = -1;
     int64_t n_windows = 0, n_elems = 0;
+    int n_max = 0;                           // longest rod of the context
     int32_t *win_rod = nullptr, *elem_rod = nullptr;
     int64_t *win_first = nullptr, *elem_first = nullptr;
     float *rodf = nullptr, *disp = nullptr;
@@ -293,6 +294,8 @@ int ensure_ctx(rod_surrogate *s, rod_batch *b, rodk::BatchView &v)
     }
     s->n_windows = w;
     s->n_elems = e;
+    s->n_max = 0;
+    for (int r = 0; r < R; ++r) s->n_max = std::max(s->n_max, (int)v.n[r]);
     hipError_t err = hipSuccess;
     auto up = [&](void **p, const void *src, size_t bytes) {
         if (err == hipSuccess) err = hipMalloc(p, bytes);
@@ -506,7 +509,7 @@ int coarse_step(rod_surrogate *s, rod_batch *b, const rodk::BatchView &v, int n_
         if ((rc = rodk::batch_step_masked(b, s->k, s->plain, s->plain_tiles, s->n_plain_tiles, st))) return rc;
     }
     e = surk::apply(win_args(s, v), s->yall, NOUT_LD, mut, sdt, n_plain > 0 ? s->plain : nullptr, s->disp, s->elem_rod,
-                    s->elem_first, s->n_elems, st);
+                    s->elem_first, s->n_elems, st, s->n_max);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("apply: ") + hipGetErrorString(e));
     if (n_plain == 0 && (rc = rodk::batch_advance_clock(b, s->k, st))) return rc;
     return ROD_OK;
@@ -746,7 +749,7 @@ int rod_surrogate_apply(rod_surrogate *s, rod_batch *b, const float *deltas, voi
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = surk::apply(win_args(s, v), deltas, ROD_SURROGATE_OUTPUTS, nullptr, nullptr, nullptr, s->disp,
-                               s->elem_rod, s->elem_first, s->n_elems, st);
+                               s->elem_rod, s->elem_first, s->n_elems, st, s->n_max);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("apply: ") + hipGetErrorString(e));
     return rodk::batch_advance_clock(b, s->k, st);
 }

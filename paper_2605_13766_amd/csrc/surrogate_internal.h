@@ -30,8 +30,10 @@ struct WinArgs {
 // raw FP32 rows and/or BF16 rows (x - mu) * isd (isd = 1 / sd per column)
 hipError_t features(const WinArgs &A, float *raw, __bf16 *xn, const float *mu, const float *isd, hipStream_t s);
 hipError_t targets(const WinArgs &A, const rodk::DevBatch<float> &S0, float *tgt, float *mask, hipStream_t s);
+// n_max: the longest rod (<= 512: one workgroup per rod; else two passes)
 hipError_t apply(const WinArgs &A, const float *y, int ldy, const float *mu, const float *sd, const int32_t *skip,
-                 float *disp, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems, hipStream_t s);
+                 float *disp, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems, hipStream_t s,
+                 int n_max = 0);
 hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, const int64_t *idx, int64_t rows,
                        const float *mu_x, const float *isd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
                        float *m, hipStream_t s);

@@ -457,6 +457,85 @@ __global__ void colstats_kernel(const float *a, const float *mask, int64_t rows,
 }
 
 // ---------------------------------------------------------------- judge
+// The apply step in one pass: one workgroup per rod, one thread per element
+// (the last one also takes window n).  Every thread reads what it needs of the
+// pre-step state and the outputs, publishes its node displacement in LDS, and
+// after one barrier writes its edge, velocity, frame and angular velocity:
+// the same arithmetic as apply_nodes_kernel and apply_elems_kernel.
+constexpr int APPLY_MAX_THREADS = 512;
+
+__global__ __launch_bounds__(APPLY_MAX_THREADS) void apply_rod_kernel(const WinArgs A, const float *y, int ldy,
+                                                                      const float *mu, const float *sd,
+                                                                      const int32_t *skip)
+{
+    __shared__ V3 sdisp[APPLY_MAX_THREADS + 1];
+    const int r = blockIdx.x;
+    if (skip && skip[r]) return;   // uniform over the workgroup
+    const Rod R(A.B, r);
+    const int n = R.n;
+    const int c = threadIdx.x;
+    const bool on = c < n;
+    const int flags = A.B.rod_flags[r];
+    const int64_t g = A.win_first[r] + c;
+    auto out = [&](int64_t row, int k) { return sd ? y[row * ldy + k] * sd[k] + mu[k] : y[row * ldy + k]; };
+    float qc[9];
+    float L = 0.f;
+    V3 dv{0.f, 0.f, 0.f}, dvn{0.f, 0.f, 0.f};
+    if (on) {
+        R.dirs(c, qc);
+        L = R.lh(c);
+        const bool fixed = (c == 0 && (flags & rodk::FLAG_CLAMP0));
+        V3 dr{0.f, 0.f, 0.f};
+        if (!fixed) {
+            dr = L * matTvec(qc, V3{out(g, 0), out(g, 1), out(g, 2)}) + A.tau * R.node_v(c);
+            dv = (L / A.tau) * matTvec(qc, V3{out(g, 3), out(g, 4), out(g, 5)});
+        }
+        sdisp[c] = dr;
+        if (c == n - 1) {   // window n: node n, centred on element n - 1
+            V3 drn{0.f, 0.f, 0.f};
+            if (!(flags & rodk::FLAG_CLAMP1)) {
+                drn = L * matTvec(qc, V3{out(g + 1, 0), out(g + 1, 1), out(g + 1, 2)}) + A.tau * R.node_v(n);
+                dvn = (L / A.tau) * matTvec(qc, V3{out(g + 1, 3), out(g + 1, 4), out(g + 1, 5)});
+            }
+            sdisp[n] = drn;
+        }
+    }
+    __syncthreads();
+    if (!on) return;
+    float *st = A.B.state;
+    const int64_t NS = A.B.n_slots;
+    const int64_t sl = R.s0 + c;
+    const V3 d0 = sdisp[c], d1 = sdisp[c + 1];
+    st[rodk::RX * NS + sl] += d1.x - d0.x;
+    st[rodk::RY * NS + sl] += d1.y - d0.y;
+    st[rodk::RZ * NS + sl] += d1.z - d0.z;
+    if (c == 0) {
+        A.B.tail[rodk::TRX * A.B.n_rods + r] += d0.x;
+        A.B.tail[rodk::TRY * A.B.n_rods + r] += d0.y;
+        A.B.tail[rodk::TRZ * A.B.n_rods + r] += d0.z;
+    }
+    st[rodk::VX * NS + sl] += dv.x;
+    st[rodk::VY * NS + sl] += dv.y;
+    st[rodk::VZ * NS + sl] += dv.z;
+    if (c == n - 1) {
+        A.B.tail[rodk::TVX * A.B.n_rods + r] += dvn.x;
+        A.B.tail[rodk::TVY * A.B.n_rods + r] += dvn.y;
+        A.B.tail[rodk::TVZ * A.B.n_rods + r] += dvn.z;
+    }
+    const bool fixed_e = (c == 0 && (flags & rodk::FLAG_CLAMP0)) || (c == n - 1 && (flags & rodk::FLAG_CLAMP1));
+    if (fixed_e) return;
+    float d[6];
+    for (int k = 0; k < 6; ++k) d[k] = out(g, 6 + k);
+    const V3 w0 = R.omega(c);
+    rotate_left(qc, V3{-(d[0] + w0.x * A.tau), -(d[1] + w0.y * A.tau), -(d[2] + w0.z * A.tau)});
+    polar_step(qc);
+    for (int k = 0; k < 9; ++k) st[(rodk::Q00 + k) * NS + sl] = qc[k];
+    const float it = 1.f / A.tau;
+    st[rodk::WX * NS + sl] += d[3] * it;
+    st[rodk::WY * NS + sl] += d[4] * it;
+    st[rodk::WZ * NS + sl] += d[5] * it;
+}
+
 // Copy rods between two FP32 batches of equal per-rod layout: dst rod k <- src rod map[k]
 // (state, constants, tail, per-rod tables).  One thread per (k, element).
 __global__ void copy_rods_kernel(DevBatch<float> dst, DevBatch<float> src, const int32_t *map, const int32_t *sel,
@@ -619,8 +698,14 @@ hipError_t targets(const WinArgs &A, const DevBatch<float> &S0, float *tgt, floa
 }
 
 hipError_t apply(const WinArgs &A, const float *y, int ldy, const float *mu, const float *sd, const int32_t *skip,
-                 float *disp, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems, hipStream_t s)
+                 float *disp, const int32_t *elem_rod, const int64_t *elem_first, int64_t n_elems, hipStream_t s,
+                 int n_max)
 {
+    if (n_max > 0 && n_max <= APPLY_MAX_THREADS) {
+        const int threads = (n_max + 63) / 64 * 64;
+        hipLaunchKernelGGL(apply_rod_kernel, dim3(A.B.n_rods), dim3(threads), 0, s, A, y, ldy, mu, sd, skip);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(apply_nodes_kernel, blocks(A.n_windows), dim3(256), 0, s, A, y, ldy, mu, sd, skip, disp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

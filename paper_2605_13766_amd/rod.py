@@ -311,12 +311,13 @@ class Surrogate:
                                              C.byref(loss), _stream_ptr(stream)))
         return g, loss.value
 
-    def train_step(self, x_bf16, t_f32, mask_f32=None, lr=1e-3, stream=None):
+    def train_step(self, x_bf16, t_f32, mask_f32=None, lr=1e-3, stream=None, return_loss=True):
+        """One Adam step; returns the loss (synchronising) unless return_loss is False."""
         loss = C.c_float()
         _check(lib().rod_surrogate_train_step(self._h, _dptr(x_bf16), _dptr(t_f32), _dptr(mask_f32),
-                                              int(x_bf16.shape[0]), float(lr), C.byref(loss),
-                                              _stream_ptr(stream)))
-        return loss.value
+                                              int(x_bf16.shape[0]), float(lr),
+                                              C.byref(loss) if return_loss else None, _stream_ptr(stream)))
+        return loss.value if return_loss else None
 
     # ---------------------------------------------------------- data path
     @staticmethod
