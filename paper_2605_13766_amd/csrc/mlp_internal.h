@@ -30,7 +30,9 @@ hipError_t mse_grad(const float *Y, const float *T, const float *mask, float *dY
                     int64_t M, int n_out, int ld, hipStream_t s);
 int mse_partials(int64_t M, int ld);
 hipError_t sum_partials(const float *partial, int n, float scale, float *out, hipStream_t s);
-hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, hipStream_t s);
+// db[n] = sum_m dZ[m][n]; N must divide 256; work: ceil(M / 64) * N floats of scratch
+hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, float *work, int64_t work_floats,
+                  hipStream_t s);
 hipError_t adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
                 float eps, int64_t t, hipStream_t s);
 hipError_t to_bf16(const float *src, __bf16 *dst, int64_t n, hipStream_t s);

@@ -33,17 +33,72 @@ __device__ inline float dsilu_f(float z)
 
 }  // namespace
 
+// Stage a 64 (rows) x 64 (k) operand tile into S[row][k] as BF16.  The source
+// is src[row][k] (k contiguous) or, when TRANS, src[k][row] (rows contiguous);
+// each thread moves one 16-element run with 16-byte loads (two for BF16, four
+// for FP32 sources), written to LDS as two 16-byte stores (k contiguous) or
+// sixteen 2-byte stores (transposing).  Rows >= nrows and k outside [k0, ke)
+// read as zero.
+template <bool TRANS, typename TS, int LDK>
+__device__ inline void stage_tile(__bf16 (*S)[LDK], const TS *src, int64_t ld, int row0, int nrows, int k0, int ke,
+                                  int t)
+{
+    __bf16 v[16];
+    const int a = t >> 2, b = (t & 3) * 16;   // direct: a = row, b = k offset; transposed: a = k, b = row offset
+    const int row = TRANS ? row0 + b : row0 + a;
+    const int k = TRANS ? k0 + a : k0 + b;
+    const bool full = TRANS ? (k < ke && row + 16 <= nrows) : (row < nrows && k + 16 <= ke);
+    if (full) {
+        const TS *p = TRANS ? src + (int64_t)k * ld + row : src + (int64_t)row * ld + k;
+        if constexpr (sizeof(TS) == 2) {
+            const uint4 u0 = reinterpret_cast<const uint4 *>(p)[0], u1 = reinterpret_cast<const uint4 *>(p)[1];
+            const bf16x8 h0 = __builtin_bit_cast(bf16x8, u0), h1 = __builtin_bit_cast(bf16x8, u1);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                v[j] = h0[j];
+                v[8 + j] = h1[j];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 f = reinterpret_cast<const float4 *>(p)[q];
+                v[4 * q] = (__bf16)f.x;
+                v[4 * q + 1] = (__bf16)f.y;
+                v[4 * q + 2] = (__bf16)f.z;
+                v[4 * q + 3] = (__bf16)f.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int rj = TRANS ? row + j : row, kj = TRANS ? k : k + j;
+            v[j] = (__bf16)(rj < nrows && kj >= k0 && kj < ke ? to_f(src[TRANS ? (int64_t)kj * ld + rj : (int64_t)rj * ld + kj])
+                                                              : 0.f);
+        }
+    }
+    if constexpr (TRANS) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) S[b + j][a] = v[j];
+    } else {
+        uint4 *o = reinterpret_cast<uint4 *>(&S[a][b]);
+        o[0] = __builtin_bit_cast(uint4, *reinterpret_cast<const bf16x8 *>(&v[0]));
+        o[1] = __builtin_bit_cast(uint4, *reinterpret_cast<const bf16x8 *>(&v[8]));
+    }
+}
+
 // C[M x N] = A[M x K] * B[K x N] with A stored [M][K] (or [K][M] when AT) and
 // B stored [K][N] (or [N][K] when BT); inputs of type TA / TB are rounded to
 // BF16 when staged in LDS.  One 256-thread workgroup computes a 64 x 64 tile,
-// each wave a 32 x 32 quarter as 2 x 2 MFMA blocks; K advances 32 per stage.
-// Edges in M, N and K are zero-filled on load and masked on store.
+// each wave a 32 x 32 quarter as 2 x 2 MFMA blocks; K advances 64 per stage
+// (two MFMA k-steps).  Edges in M, N and K are zero-filled on load and masked
+// on store.  Leading dimensions and base pointers must allow 16-byte loads of
+// 16-element runs (multiples of 8 elements for BF16, 4 for FP32).
 template <bool AT, bool BT, typename TA, typename TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 {
-    constexpr int BM = 64, BN = 64, BK = 32, PAD = 8;
-    __shared__ __bf16 As[BM][BK + PAD];   // [m][k]
-    __shared__ __bf16 Bs[BN][BK + PAD];   // [n][k]
+    constexpr int BM = 64, BN = 64, BK = 64, LDK = BK + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 As[BM][LDK];   // [m][k]
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][LDK];   // [n][k]
     const TA *A = (const TA *)g.A;
     const TB *B = (const TB *)g.B;
     const int t = threadIdx.x;
@@ -60,64 +115,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    const int q = lane >> 4, c = lane & 15;
     for (int k0 = kb; k0 < ke; k0 += BK) {
-        // ---- stage A (64 x 32); rows past M and columns past K read as zero
-        if (!AT) {
-            const int r = t >> 2, kc = (t & 3) * 8;
-            const int m = m0 + r;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = k0 + kc + j;
-                As[r][kc + j] = (__bf16)(m < g.M && k < ke ? to_f(A[(int64_t)m * g.lda + k]) : 0.f);
-            }
-        } else {
-            const int kr = t >> 3, mc = (t & 7) * 8;
-            const int k = k0 + kr;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int m = m0 + mc + j;
-                As[mc + j][kr] = (__bf16)(m < g.M && k < ke ? to_f(A[(int64_t)k * g.lda + m]) : 0.f);
-            }
-        }
-        // ---- stage B (32 x 64), stored transposed as [n][k]
-        if (!BT) {
-            const int kr = t >> 3, nc = (t & 7) * 8;
-            const int k = k0 + kr;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int n = n0 + nc + j;
-                Bs[nc + j][kr] = (__bf16)(n < g.N && k < ke ? to_f(B[(int64_t)k * g.ldb + n]) : 0.f);
-            }
-        } else {
-            const int r = t >> 2, kc = (t & 3) * 8;
-            const int n = n0 + r;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = k0 + kc + j;
-                Bs[r][kc + j] = (__bf16)(n < g.N && k < ke ? to_f(B[(int64_t)n * g.ldb + k]) : 0.f);
-            }
-        }
+        // A: rows m, stored [M][K] (k contiguous) or [K][M] (m contiguous)
+        stage_tile<AT, TA, LDK>(As, A, g.lda, m0, g.M, k0, ke, t);
+        // B: rows n, stored [N][K] (k contiguous) when BT, else [K][N] (n contiguous)
+        stage_tile<!BT, TB, LDK>(Bs, B, g.ldb, n0, g.N, k0, ke, t);
         __syncthreads();
-        bf16x8 af[2], bfr[2];
-        const int q = lane >> 4, c = lane & 15;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int kk = 0; kk < BK; kk += 32) {
+            bf16x8 af[2], bfr[2];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                af[i][j] = As[wm + 16 * i + c][8 * q + j];
-                bfr[i][j] = Bs[wn + 16 * i + c][8 * q + j];
+            for (int i = 0; i < 2; ++i) {
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + c][kk + 8 * q]);
+                bfr[i] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * i + c][kk + 8 * q]);
             }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
 
     // ---- epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each block
-    const int q = lane >> 4, c = lane & 15;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -188,12 +210,38 @@ __global__ void sum_kernel(const float *partial, int n, float scale, float *out)
 }
 
 // db[n] = sum_m dZ[m][n], one block per column.
-__global__ void colsum_kernel(const float *dZ, int64_t M, int ld, float *db)
+// Column sums db[n] = sum_m dZ[m][n], first pass: workgroup b sums rows
+// [b * CS_ROWS, (b + 1) * CS_ROWS) of every column; its 256 threads are
+// 256 / N row groups of N consecutive columns (N divides 256), so every load
+// instruction reads consecutive columns.  Partials go to part[b][N].  Short
+// chunks give many workgroups (1024 for 65,536 rows).
+constexpr int CS_ROWS = 64;
+
+__global__ void colsum_partial_kernel(const float *dZ, int64_t M, int N, int ld, float *part)
+{
+    __shared__ float red[256];
+    const int groups = 256 / N;
+    const int n = threadIdx.x % N, grp = threadIdx.x / N;
+    const int64_t r0 = (int64_t)blockIdx.x * CS_ROWS;
+    const int64_t r1 = r0 + CS_ROWS < M ? r0 + CS_ROWS : M;
+    float s = 0.f;
+    for (int64_t m = r0 + grp; m < r1; m += groups) s += dZ[m * ld + n];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (grp == 0) {
+        for (int k = 1; k < groups; ++k) s += red[k * N + n];
+        part[(int64_t)blockIdx.x * N + n] = s;
+    }
+}
+
+// Second pass, one workgroup per column: thread t sums part[b][n] over
+// b = t, t + 256, ..., then a fixed-order tree over the 256 threads.
+__global__ void colsum_final_kernel(const float *part, int nb, int N, float *db)
 {
     __shared__ float red[256];
     const int n = blockIdx.x;
     float s = 0.f;
-    for (int64_t m = threadIdx.x; m < M; m += blockDim.x) s += dZ[m * ld + n];
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(int64_t)b * N + n];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -305,9 +353,19 @@ hipError_t sum_partials(const float *partial, int n, float scale, float *out, hi
     return hipGetLastError();
 }
 
-hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, hipStream_t s)
+hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, float *work, int64_t work_floats,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, s, dZ, M, ld, db);
+    const int64_t nb = (M + CS_ROWS - 1) / CS_ROWS;
+    if (256 % N != 0 || nb * N > work_floats) return hipErrorInvalidValue;
+    if (nb == 0) {
+        hipLaunchKernelGGL(colsum_final_kernel, dim3(N), dim3(256), 0, s, work, 0, N, db);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, dZ, M, N, ld, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(N), dim3(256), 0, s, work, (int)nb, N, db);
     return hipGetLastError();
 }
 

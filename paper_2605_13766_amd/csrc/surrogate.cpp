@@ -191,7 +191,7 @@ int gradient_chunk(rod_surrogate *s, const __bf16 *x, const float *t, const floa
         a.ldc = NPAD[l];
         e = mlpk::gemm_backward_weight(a, s->splitw, SPLIT_FLOATS, st);
         if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("dW gemm: ") + hipGetErrorString(e));
-        e = mlpk::colsum(dZ, M, NPAD[l], ldz, s->g + s->lay.b[l], st);
+        e = mlpk::colsum(dZ, M, NPAD[l], ldz, s->g + s->lay.b[l], s->splitw, SPLIT_FLOATS, st);
         if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("db: ") + hipGetErrorString(e));
         if (l == 0) break;
         // dZ_{l-1} = (dZ_l W_l^T) * silu'(Z_{l-1})
