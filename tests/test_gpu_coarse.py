@@ -307,3 +307,26 @@ def test_judge_errors_match_the_oracle():
     assert abs(st["max_orth_error"] - errs[:, 1].max()) < 1e-6
     s.close()
     b.close()
+
+
+def test_coarse_step_rejects_unsupported_batches():
+    """The learned coarse step needs an FP32 batch of equal element counts:
+    a ragged batch and an FP64 batch are refused with ROD_EUNSUPPORTED, and a
+    malformed judge descriptor with ROD_EINVAL, before anything runs."""
+    from paper_2605_13766_amd import rod
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    ragged = gpu_batch(W.ragged_batch(n_rods=8, n_min=16, n_max=40, seed=3))
+    with pytest.raises(rod.RodError) as ei:
+        s.step(ragged, 1)
+    assert ei.value.code == rod.ROD_EUNSUPPORTED
+    f64 = rod.RodBatch(carpet(4), precision="f64")
+    with pytest.raises(rod.RodError) as ei:
+        s.step(f64, 1)
+    assert ei.value.code == rod.ROD_EUNSUPPORTED
+    _, b = _rods(4, warm=0)
+    for bad in (dict(judge_every=0), dict(judge_fraction=0.0), dict(judge_fraction=1.5), dict(max_pos_error=-1.0)):
+        with pytest.raises(rod.RodError) as ei:
+            s.step(b, 1, **bad)
+        assert ei.value.code == rod.ROD_EINVAL
+    for h in (s, ragged, f64, b):
+        h.close()
