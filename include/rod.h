@@ -30,8 +30,9 @@
  *    stream).  rod_step only enqueues work; rod_energy, rod_get_state,
  *    rod_set_state and rod_get_flags synchronise the stream.
  *  - Precision: inputs are always FP64.  ROD_F32 batches round them once at
- *    creation (round to nearest even) and store node positions relative to a
- *    per-rod FP64 origin (the rod's first node at creation).
+ *    creation (round to nearest even) and store, per element, the edge
+ *    vector r_{i+1} - r_i and, per rod, the first node relative to an FP64
+ *    origin (that node at creation); rod_get_state sums the edges in FP64.
  *  - Not thread-safe per handle: calls on one handle must not overlap.
  */
 #ifndef ROD_H

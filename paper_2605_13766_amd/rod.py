@@ -173,7 +173,9 @@ class RodBatch:
     """A batch of rods resident on the GPU (owned by librod.so)."""
 
     def __init__(self, inp, precision: str = "f64", substeps: int = 0, tile_waves: int = 0,
-                 t0: float = 0.0, stream=None, autotune: bool = False):
+                 t0: float = 0.0, stream=None, autotune: bool = False, device_inputs: bool = False):
+        """device_inputs: hand the library device copies (torch tensors) of every
+        input array instead of host arrays (inputs_on_device = 1)."""
         self._h = None
         prec = {"f64": ROD_F64, "f32": ROD_F32}[precision]
         keep = {}
@@ -182,26 +184,42 @@ class RodBatch:
             if a is None:
                 return None
             v = np.ascontiguousarray(a, dtype=np.float64 if kind == "d" else np.int32)
-            keep[name] = v
+            if device_inputs:
+                import torch
+                keep[name] = torch.from_numpy(v).to("cuda")
+            else:
+                keep[name] = v
             return v
+
+        def ptr(name, t):
+            if name not in keep:
+                return None
+            if device_inputs:
+                return C.cast(C.c_void_p(keep[name].data_ptr()), t)
+            return keep[name].ctypes.data_as(t)
 
         d = RodBatchDesc()
         n = arr("n", inp.n_elems, "i")
         d.n_rods = int(n.shape[0])
-        d.n_elems = _p(n, _ip)
+        d.n_elems = ptr("n", _ip)
         for name in ("position", "velocity", "director", "omega", "rest_length", "rest_kappa",
                      "density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping",
                      "end_force", "couple_amp", "couple_freq", "couple_phase"):
-            setattr(d, name, _p(arr(name, getattr(inp, name, None))))
+            arr(name, getattr(inp, name, None))
+            setattr(d, name, ptr(name, _dp))
         for name in ("bc_start", "bc_end"):
-            setattr(d, name, _p(arr(name, getattr(inp, name, None), "i"), _ip))
+            arr(name, getattr(inp, name, None), "i")
+            setattr(d, name, ptr(name, _ip))
         d.dt = float(inp.dt)
         d.t0 = float(t0)
         d.precision = prec
         d.substeps = int(substeps)
         d.tile_waves = int(tile_waves)
-        d.inputs_on_device = 0
+        d.inputs_on_device = 1 if device_inputs else 0
         d.autotune = int(autotune)
+        if device_inputs:
+            import torch
+            torch.cuda.synchronize()
         h = C.c_void_p()
         _check(lib().rod_batch_create(C.byref(d), _stream_ptr(stream), C.byref(h)))
         self._h = h

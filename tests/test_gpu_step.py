@@ -233,3 +233,18 @@ def test_f32_parity():
         print(f"case: {name}, FP32, 1000 steps", flush=True)
         norms, _ = run_both(inp, 1000, precision="f32")
         assert_norms(norms, 1e-4, keys=("pos", "dir"))
+
+
+def test_device_inputs_give_the_same_batch():
+    """inputs_on_device = 1 (every input a device array) builds the same batch
+    as host inputs: identical state after creation and after 100 steps."""
+    R = _rod()
+    inp = W.ragged_batch(n_rods=24, n_min=16, n_max=120, seed=43)
+    for prec in ("f64", "f32"):
+        with R.RodBatch(inp, precision=prec) as a, R.RodBatch(inp, precision=prec, device_inputs=True) as b:
+            for x, y in zip(a.get_state()[:4], b.get_state()[:4]):
+                assert np.array_equal(x, y)
+            a.step(100)
+            b.step(100)
+            for x, y in zip(a.get_state()[:4], b.get_state()[:4]):
+                assert np.array_equal(x, y)
