@@ -43,7 +43,11 @@
  *       kick (v += h a, omega += h alpha) at t_n + h/2, constraints,
  *       half drift, constraints;
  *   - clamped end: node position and element director reset to their initial
- *     values, node velocity and element angular velocity set to zero.
+ *     values, node velocity and element angular velocity set to zero;
+ *   - magnetic couple (Methods, "Magnetized filaments", Eq. 2): element i
+ *     carries a magnetization m_i per unit length in its material frame; a
+ *     homogeneous lab field b(t) = b0 + bc cos(2 pi f t) + bs sin(2 pi f t),
+ *     evaluated at the kick time, adds m_i x (Q_i b) to the couple c.
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,6 +79,9 @@ typedef struct {
     double dt;
     double t0;                       /* time at step 0 */
     int32_t drop_term;               /* 0 in normal use; k > 0 removes term k (mutation tests) */
+    const double *magnetization;     /* [N_e][3] or NULL: magnetization per unit length, material frame */
+    double field[9];                 /* b(t) = field[0:3] + field[3:6] cos(2 pi f t) + field[6:9] sin(2 pi f t) */
+    double field_freq;               /* f, Hz */
 } orc_rods;
 
 /* ---------------------------------------------------------------- vectors */
@@ -172,6 +179,9 @@ typedef struct {
     const double *camp;          /* [n][3] or NULL */
     const double *r0;            /* [n+1][3] */
     const double *Q0;            /* [n][9] */
+    const double *mag;           /* [n][3] or NULL */
+    const double *field;         /* [9] */
+    double field_freq;
     int drop;
 } rod_view;
 
@@ -194,6 +204,9 @@ static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int6
     v->camp = p->couple_amp ? p->couple_amp + 3 * eo : NULL;
     v->r0 = p->pos0 + 3 * no;
     v->Q0 = p->dir0 + 9 * eo;
+    v->mag = p->magnetization ? p->magnetization + 3 * eo : NULL;
+    v->field = p->field;
+    v->field_freq = p->field_freq;
     v->drop = p->drop_term;
 }
 
@@ -329,6 +342,12 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
     /* elements: Eq. 1b */
     double s_t = 0.0;
     if (rv->camp) s_t = sin(2.0 * M_PI * rv->freq * t + rv->phase);
+    /* homogeneous lab field at time t (Methods, "Magnetized filaments") */
+    double bfield[3] = {0.0, 0.0, 0.0};
+    if (rv->mag) {
+        const double cb = cos(2.0 * M_PI * rv->field_freq * t), sb = sin(2.0 * M_PI * rv->field_freq * t);
+        for (int a = 0; a < 3; ++a) bfield[a] = rv->field[a] + rv->field[3 + a] * cb + rv->field[6 + a] * sb;
+    }
     for (int i = 0; i < n; ++i) {
         const double *Qi = &Q[9 * i];
         const double *wi = &om[3 * i];
@@ -369,6 +388,13 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
         /* external couple per unit length */
         if (rv->camp)
             for (int a = 0; a < 3; ++a) tau[a] += rv->camp[3 * i + a] * s_t * lh;
+        /* magnetic couple per unit length, m x (Q b(t)), in the material frame */
+        if (rv->mag) {
+            double qb[3], cm[3];
+            matvec(Qi, bfield, qb);
+            cross3(&rv->mag[3 * i], qb, cm);
+            for (int a = 0; a < 3; ++a) tau[a] += cm[a] * lh;
+        }
         for (int a = 0; a < 3; ++a)
             alpha[3 * i + a] = e * tau[a] / J[a] - rv->gamma * wi[a];
     }

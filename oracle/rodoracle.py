@@ -33,6 +33,7 @@ class _OrcRods(C.Structure):
         ("rest_length", _dp), ("rest_kappa", _dp), ("node_force", _dp), ("couple_amp", _dp),
         ("couple_freq", _dp), ("couple_phase", _dp), ("pos0", _dp), ("dir0", _dp),
         ("dt", C.c_double), ("t0", C.c_double), ("drop_term", C.c_int32),
+        ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
     ]
 
 
@@ -125,6 +126,11 @@ class Oracle:
         cp = getattr(inp, "couple_phase", None)
         self.couple_freq = _d(cf if cf is not None else np.zeros(R))
         self.couple_phase = _d(cp if cp is not None else np.full(R, np.pi / 2))
+        mg = getattr(inp, "magnetization", None)
+        self.magnetization = _d(np.asarray(mg, float).reshape(Ne, 3)) if mg is not None else None
+        fl = getattr(inp, "field", None)
+        self.field = np.zeros(9) if fl is None else np.asarray(fl, float).reshape(9).copy()
+        self.field_freq = float(getattr(inp, "field_freq", 0.0) or 0.0)
         self.mat = {k: _d(getattr(inp, k)) for k in
                     ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping")}
         self.bc_start = np.ascontiguousarray(inp.bc_start, dtype=np.int32)
@@ -154,6 +160,9 @@ class Oracle:
         s.dt = self.dt
         s.t0 = self.t0
         s.drop_term = self.drop_term
+        s.magnetization = _ptr(self.magnetization)
+        s.field = (C.c_double * 9)(*[float(x) for x in self.field])
+        s.field_freq = self.field_freq
         self._s = s
 
     @property

@@ -62,6 +62,9 @@ class RodInputs:
     couple_amp: Optional[np.ndarray] = None    # [R, 3] per unit length, material frame
     couple_freq: Optional[np.ndarray] = None   # [R] Hz
     couple_phase: Optional[np.ndarray] = None  # [R] rad
+    magnetization: Optional[np.ndarray] = None  # [N_e, 3] per unit length, material frame (A m)
+    field: Optional[np.ndarray] = None          # [9]: b(t) = f[0:3] + f[3:6] cos(2 pi ff t) + f[6:9] sin(...), T
+    field_freq: float = 0.0                     # ff, Hz
     name: str = ""
 
     # ------------------------------------------------------------------ sizes
@@ -119,6 +122,9 @@ class RodInputs:
             rest_kappa=None if self.rest_kappa is None else self.rest_kappa[v_idx].copy(),
             end_force=per_rod(self.end_force), couple_amp=per_rod(self.couple_amp),
             couple_freq=per_rod(self.couple_freq), couple_phase=per_rod(self.couple_phase),
+            magnetization=None if self.magnetization is None else self.magnetization[e_idx].copy(),
+            field=None if self.field is None else np.array(self.field, float).copy(),
+            field_freq=self.field_freq,
             name=self.name + "[subset]",
         )
 
