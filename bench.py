@@ -7,7 +7,12 @@ persistent kernel replayed from a HIP graph, with the tile width and the
 substeps per launch S chosen by the library's autotuner).  The headline value is FP64 element-steps/s; the
 FP32 figure rides along in the same JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate] [--no-magnetic]
+
+The magnetic carpet rides along as the "magnetic" object: 65,536 base-clamped
+rods x 50 elements (FP32) turned by a rotating homogeneous field through their
+programmed magnetization, timed like the headline and next to the same carpet
+driven by its distributed couple.
 
 The learned coarse step rides along as the "surrogate" object: the network is
 trained on 16,384 carpet rods (64 elements, 2.1e6 windows from plain
@@ -44,6 +49,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rod element-steps/s (plain) and surrogate simulated-s/s at ≤1e-3 error"
 ALGO_FLOP = 459                                  # per element-step (breakdown in the design notes)
+ALGO_FLOP_MAG = 459 - 6 + 27                     # the external couple's 6 replaced by m x (Q b): 27
 ALGO_BYTES = {"f64": 400, "f32": 204}            # HBM bytes per element per launch
 PEAK = {"f64": 78.6, "f32": 157.3}               # TFLOP/s, MI355X vector peaks
 STEPS_PER_LAUNCH = 1000
@@ -72,7 +78,7 @@ def traffic_from_profile(precision: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0):
+def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=ALGO_FLOP, traffic_key=True):
     import torch
     from paper_2605_13766_amd import rod
 
@@ -102,8 +108,8 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0):
         raise RuntimeError(f"{int(flags.sum())} rods became non-finite")
     el_steps = inp.n_elements * STEPS_PER_LAUNCH
     value = el_steps * steps / wall
-    achieved = ALGO_FLOP * el_steps / (launch_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(precision)
+    achieved = algo_flop * el_steps / (launch_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile(precision) if traffic_key else None
     return {
         "value": value,
         "ms_per_step": wall / steps * 1e3,
@@ -118,6 +124,26 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0):
             "traffic": traffic,
             "algorithmic_bytes_per_launch": ALGO_BYTES[precision] * inp.n_elements,
         },
+    }
+
+
+def time_magnetic(steps, warmup):
+    """The cilia carpet (65,536 base-clamped rods x 50 elements, FP32, dt 1e-6 s,
+    autotuned) driven by the rotating magnetic field, next to the same carpet
+    driven by its distributed couple: the cost of the magnetic couple."""
+    from paper_2605_13766_amd import workloads as W
+    mag = time_gpu(W.magnetic_carpet(), "f32", steps, warmup, algo_flop=ALGO_FLOP_MAG, traffic_key=False)
+    drv = time_gpu(W.cilia_carpet(), "f32", steps, warmup, traffic_key=False)
+    return {
+        "workload": "magnetic_carpet: 65,536 rods x 50 elements on a 256 x 256 grid, FP32, dt 1e-6 s, "
+                    "field 10 mT rotating at 10 Hz, programmed magnetization 1.5e-3 A m, "
+                    f"{STEPS_PER_LAUNCH} steps per launch",
+        "value": mag["value"], "unit": "element-steps/s", "ms_per_step": mag["ms_per_step"],
+        "launch_ms": mag["launch_ms"], "roofline": mag["roofline"],
+        "tile_waves": mag["info"]["tile_waves"], "substeps_per_launch": mag["info"]["substeps"],
+        "driven_carpet": {"value": drv["value"], "launch_ms": drv["launch_ms"],
+                          "tile_waves": drv["info"]["tile_waves"], "substeps_per_launch": drv["info"]["substeps"]},
+        "magnetic_over_driven_time": mag["launch_ms"] / drv["launch_ms"],
     }
 
 
@@ -274,6 +300,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-magnetic", action="store_true")
     ap.add_argument("--tile-waves", type=int, default=0, help="fix the tile width (0: autotune)")
     ap.add_argument("--substeps", type=int, default=0, help="fix the substeps per launch (0: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -338,6 +365,9 @@ def main(argv=None):
                    "ms_per_step": res[p]["ms_per_step"], "launch_ms": res[p]["launch_ms"],
                    "roofline": res[p]["roofline"], "tile_waves": res[p]["info"]["tile_waves"],
                    "substeps_per_launch": res[p]["info"]["substeps"]}
+    if not args.no_magnetic:
+        print("timing the magnetic carpet", file=sys.stderr, flush=True)
+        line["magnetic"] = time_magnetic(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         print("timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inp)

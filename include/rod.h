@@ -101,6 +101,16 @@ typedef struct {
                                         (autotune: 0 = tuned) */
     int32_t inputs_on_device;        /* 1: every pointer above is device memory; 0: host */
     int32_t autotune;                /* 1: choose every tile parameter given as 0 by timing (below) */
+    /* Magnetic couple (Methods, "Magnetized filaments", Eq. 2): element i of
+     * the batch carries a magnetization m_i per unit length in its material
+     * frame, and every rod sits in one homogeneous lab-frame field
+     *   b(t) = field[0:3] + field[3:6] cos(2 pi field_freq t) + field[6:9] sin(2 pi field_freq t)  (T),
+     * evaluated at the time of each kick; the couple per unit length
+     * m_i x (Q_i b(t)) joins c.  NULL magnetization: no magnetic couple (the
+     * step then runs the kernel without the term, and field is ignored). */
+    const double *magnetization;     /* [N_elems][3] (A m), or NULL */
+    double field[9];                 /* b0, bc, bs (lab frame) */
+    double field_freq;               /* Hz */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -118,7 +128,8 @@ typedef struct {
  * and upload.  Errors: ROD_EINVAL (n_elems outside [1, ROD_MAX_ELEMS], a
  * NULL required array, dt <= 0, rho/E/G/radius/alpha_c <= 0, damping < 0,
  * a director farther than 1e-8 from SO(3) or with det < 0, a zero-length
- * element or rest length <= 0, couple_amp without freq/phase), ROD_ENOMEM,
+ * element or rest length <= 0, couple_amp without freq/phase, a magnetization,
+ * field or field_freq that is not finite), ROD_ENOMEM,
  * ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the longest rod).
  * A time step above the explicit stability estimate is reported through
  * rod_last_error with ROD_OK.
@@ -158,7 +169,7 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream);
  *   U_shear = 1/2 sum_i sigma_i . S sigma_i lh_i
  *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . B_k (kappa_k - kappa0_k) Dh_k
  *   W_ext   = -sum f . (r_last - r_last(0))          (the constant end force)
- * Returns ROD_ENONFINITE if any rod is flagged non-finite.
+ * The distributed and magnetic couples have no energy column.  Returns ROD_ENONFINITE if any rod is flagged non-finite.
  */
 int rod_energy(rod_batch *b, double *out, void *stream);
 

@@ -80,6 +80,13 @@ struct DevBatch {
     int32_t n_tiles;
     double dt;
     double t0;
+    // magnetic couple: [3][n_slots] magnetization times rest length (material
+    // frame), NULL for batches without one; the lab field
+    // b(t) = field[0:3] + field[3:6] cos(2 pi field_freq t) + field[6:9] sin(...)
+    const T *mag;
+    T field[9];
+    double field_freq;
+    double field_ds, field_dc;   // sin, cos of 2 pi field_freq dt
 };
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
@@ -97,6 +104,7 @@ int step_resident_groups(int precision_f32, int waves);
 struct BatchView {
     int precision;
     int waves;
+    bool magnetic;             // the batch carries a magnetic couple
     int32_t n_rods;
     int64_t n_elems, n_slots;
     const int32_t *n;          // host [R]

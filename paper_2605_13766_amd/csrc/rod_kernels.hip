@@ -234,9 +234,19 @@ __device__ inline bool finite3(T a, T b, T c)
 #define ROD_F32_WAVES_PER_SIMD 5
 #endif
 
-template <typename T, int W>
+// MAG: the batch carries a magnetic couple (a separate instantiation, so the
+// plain step keeps its registers and LDS).  Its FP64 4-wave and FP32 8-wave
+// tiles need one wave per SIMD less than the plain step's.
+template <typename T, int W, bool MAG>
+constexpr int step_waves_per_simd()
+{
+    return sizeof(T) == 8 ? ((W == 8 || (MAG && W == 4)) ? 2 : ROD_F64_WAVES_PER_SIMD)
+                          : ((MAG && W == 8) ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
+}
+
+template <typename T, int W, bool MAG>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (W == 8 ? 2 : ROD_F64_WAVES_PER_SIMD) : ROD_F32_WAVES_PER_SIMD)))
+__attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, MAG>())))
 void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
     constexpr bool EDGE = sizeof(T) == 4;
@@ -246,7 +256,9 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     // lane-private constants (each lane reads back only its own column, so no
     // barrier is needed): a register extension for values used once a substep
     enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
-           C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3, N_C };
+           C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3,
+           C_MX, C_MY, C_MZ };   // magnetization times rest length (MAG only)
+    constexpr int N_C = MAG ? C_MZ + 1 : C_MX;
     // One LDS block in a fixed order: the small wave-edge exchange buffers first,
     // so their addresses fit the 8-bit offsets of ds_write2/ds_read2 and need no
     // per-access address arithmetic, then the constant columns.
@@ -360,6 +372,19 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             cw[C_CZ * TL] = c2;
             phs[lane] = ds;
             phs[TL + lane] = dc;
+            if constexpr (MAG) {
+                cw[C_MX * TL] = B.mag[s];
+                cw[C_MY * TL] = B.mag[NS + s];
+                cw[C_MZ * TL] = B.mag[2 * NS + s];
+            }
+        }
+        // magnetic field phase 2 pi f t at the substep midpoints (the same
+        // for every lane), advanced by the rotation recurrence
+        double fs = 0.0, fc = 1.0;
+        if constexpr (MAG) {
+            const double ph = 2.0 * M_PI * B.field_freq * (B.t0 + ((double)step0 + 0.5) * B.dt);
+            fs = sin(ph);
+            fc = cos(ph);
         }
 
         // edge form: velocity of node i+1 (refreshed after every kick)
@@ -478,10 +503,25 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                         + (jw2 * w0 - jw0 * w2) + jw1 * ede + cl[C_CY * TL] * cs;
             const T tq2 = (M2 - b3[5]) + T(0.5) * (b3[8] + y2) + (qt0 * ss1 - qt1 * ss0) * lh
                         + (jw0 * w1 - jw1 * w0) + jw2 * ede + cl[C_CZ * TL] * cs;
+            T mc0 = 0, mc1 = 0, mc2 = 0;
+            if constexpr (MAG) {
+                // magnetic couple (m lh) x (Q b(t)), material frame
+                const T cb = T(fc), sb = T(fs);
+                const T b0 = B.field[0] + B.field[3] * cb + B.field[6] * sb;
+                const T b1 = B.field[1] + B.field[4] * cb + B.field[7] * sb;
+                const T b2 = B.field[2] + B.field[5] * cb + B.field[8] * sb;
+                const T qb0 = q[0] * b0 + q[1] * b1 + q[2] * b2;
+                const T qb1 = q[3] * b0 + q[4] * b1 + q[5] * b2;
+                const T qb2 = q[6] * b0 + q[7] * b1 + q[8] * b2;
+                const T m0 = cl[C_MX * TL], m1 = cl[C_MY * TL], m2 = cl[C_MZ * TL];
+                mc0 = m1 * qb2 - m2 * qb1;
+                mc1 = m2 * qb0 - m0 * qb2;
+                mc2 = m0 * qb1 - m1 * qb0;
+            }
             const T eJ = e * cl[C_INV_J1 * TL];
-            const T al0 = eJ * tq0 - gamma * w0;
-            const T al1 = eJ * tq1 - gamma * w1;
-            const T al2 = T(0.5) * eJ * tq2 - gamma * w2;
+            const T al0 = eJ * (tq0 + mc0) - gamma * w0;
+            const T al1 = eJ * (tq1 + mc1) - gamma * w1;
+            const T al2 = T(0.5) * eJ * (tq2 + mc2) - gamma * w2;
 
             // ---- kick (clamped nodes/elements have zero kick factors)
             v0 += hv * a0; v1 += hv * a1x; v2 += hv * a2x;
@@ -518,6 +558,11 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 const double nps = ps * dc + pc * ds;
                 pc = pc * dc - ps * ds;
                 ps = nps;
+            }
+            if constexpr (MAG) {
+                const double nfs = fs * B.field_dc + fc * B.field_ds;
+                fc = fc * B.field_dc - fs * B.field_ds;
+                fs = nfs;
             }
         }
 
@@ -634,7 +679,10 @@ template <typename T, int W>
 static hipError_t launch_w(const DevBatch<T> &b, int n_sub, int grid, hipStream_t s)
 {
     if (grid <= 0) grid = b.n_tiles;
-    hipLaunchKernelGGL((rod_step_kernel<T, W>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
+    if (b.mag)
+        hipLaunchKernelGGL((rod_step_kernel<T, W, true>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
+    else
+        hipLaunchKernelGGL((rod_step_kernel<T, W, false>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
     return hipGetLastError();
 }
 
@@ -696,7 +744,7 @@ template <typename T, int W>
 static int resident_w()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rod_step_kernel<T, W>, 64 * W, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rod_step_kernel<T, W, false>, 64 * W, 0) != hipSuccess)
         return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;

@@ -45,6 +45,7 @@ struct HostInputs {
     std::vector<double> rho, E, G, rad, ac, gam;
     std::vector<int32_t> bc0, bc1;
     std::vector<double> fend, camp, cfreq, cphase;
+    std::vector<double> mag;     // [N_e][3] magnetization per unit length (empty: none)
     bool has_k0 = false, has_f = false, has_c = false;
 };
 
@@ -86,8 +87,11 @@ struct rod_batch {
     std::vector<int32_t> bc0, bc1;
     std::vector<double> clamp_r0, clamp_q0, clamp_rn, clamp_qn;   // [R][3], [R][9]
     std::vector<double> E, G, rho, rad, ac, camp, cfreq, cphase;  // per-rod inputs kept for the surrogate
+    bool magnetic = false;
+    double field[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, field_freq = 0;
     // device
     void *d_state = nullptr, *d_param = nullptr, *d_tail = nullptr, *d_rodp = nullptr;
+    void *d_mag = nullptr;       // [3][n_slots] magnetization times rest length (magnetic batches)
     double *d_freq = nullptr, *d_phase = nullptr, *d_energy = nullptr;
     int32_t *d_ints = nullptr;   // slot_rod, slot_idx, rod_n, rod_flags, rod_slot, nonfinite
     int64_t *d_step = nullptr;
@@ -148,6 +152,11 @@ int validate(const rod_batch_desc *d)
     if (d->autotune != 0 && d->autotune != 1) return fail(ROD_EINVAL, "autotune must be 0 or 1");
     if (d->couple_amp && (!d->couple_freq || !d->couple_phase))
         return fail(ROD_EINVAL, "couple_amp needs couple_freq and couple_phase");
+    if (d->magnetization) {
+        for (int k = 0; k < 9; ++k)
+            if (!std::isfinite(d->field[k])) return fail(ROD_EINVAL, "field is not finite");
+        if (!std::isfinite(d->field_freq)) return fail(ROD_EINVAL, "field_freq is not finite");
+    }
     return ROD_OK;
 }
 
@@ -212,6 +221,9 @@ int gather_inputs(const rod_batch_desc *d, HostInputs &h)
         h.cfreq.assign(R, 0.0);
         h.cphase.assign(R, 0.0);
     }
+    if (d->magnetization) {
+        if ((rc = fetch(h.mag, d->magnetization, 3 * Ne, dev))) return rc;
+    }
     return ROD_OK;
 }
 
@@ -229,6 +241,7 @@ int check_values(HostInputs &h)
     for (double x : h.pos) if (!std::isfinite(x)) return fail(ROD_EINVAL, "position is not finite");
     for (double x : h.vel) if (!std::isfinite(x)) return fail(ROD_EINVAL, "velocity is not finite");
     for (double x : h.om) if (!std::isfinite(x)) return fail(ROD_EINVAL, "omega is not finite");
+    for (double x : h.mag) if (!std::isfinite(x)) return fail(ROD_EINVAL, "magnetization is not finite");
     const int64_t Ne = (int64_t)h.dir.size() / 9;
     for (int64_t i = 0; i < Ne; ++i) {
         const double *q = &h.dir[9 * i];
@@ -264,13 +277,24 @@ int check_values(HostInputs &h)
 
 // Crude explicit stability bound: 2 / (largest natural frequency) over the
 // axial, shear, bending, twisting and rotational-shear modes of one element.
-double stability_dt(const HostInputs &h)
+double stability_dt(const HostInputs &h, const double *field)
 {
     double dt = 1e300;
+    double bmax = 0;   // bound on |b(t)|
+    if (!h.mag.empty())
+        for (int c = 0; c < 3; ++c)
+            bmax += std::sqrt(field[3 * c] * field[3 * c] + field[3 * c + 1] * field[3 * c + 1]
+                              + field[3 * c + 2] * field[3 * c + 2]);
     int64_t e = 0;
     for (size_t r = 0; r < h.n.size(); ++r) {
-        double lmin = 1e300;
-        for (int i = 0; i < h.n[r]; ++i) lmin = std::min(lmin, h.lh[e + i]);
+        double lmin = 1e300, mmax = 0;
+        for (int i = 0; i < h.n[r]; ++i) {
+            lmin = std::min(lmin, h.lh[e + i]);
+            if (!h.mag.empty())
+                mmax = std::max(mmax, std::sqrt(h.mag[3 * (e + i)] * h.mag[3 * (e + i)]
+                                                + h.mag[3 * (e + i) + 1] * h.mag[3 * (e + i) + 1]
+                                                + h.mag[3 * (e + i) + 2] * h.mag[3 * (e + i) + 2]));
+        }
         e += h.n[r];
         const double A = M_PI * h.rad[r] * h.rad[r], I = M_PI * std::pow(h.rad[r], 4) / 4.0;
         const double rho = h.rho[r];
@@ -280,6 +304,7 @@ double stability_dt(const HostInputs &h)
         w = std::max(w, 4.0 / (lmin * lmin) * std::sqrt(h.E[r] * I / (rho * A)));    // bending
         w = std::max(w, 2.0 / lmin * std::sqrt(h.G[r] / rho));                       // twist
         w = std::max(w, std::sqrt(2.0 * h.ac[r] * h.G[r] * A / (rho * I)));          // rotational shear
+        w = std::max(w, std::sqrt(mmax * bmax / (rho * I)));                         // magnetic restoring couple
         dt = std::min(dt, 2.0 / w);
     }
     return dt;
@@ -307,6 +332,11 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.n_tiles = b->n_tiles;
     d.dt = b->dt;
     d.t0 = b->t0;
+    d.mag = (T *)b->d_mag;
+    for (int k = 0; k < 9; ++k) d.field[k] = T(b->field[k]);
+    d.field_freq = b->field_freq;
+    d.field_ds = std::sin(2.0 * M_PI * b->field_freq * b->dt);
+    d.field_dc = std::cos(2.0 * M_PI * b->field_freq * b->dt);
 }
 
 // Pack the dynamic state into the slot layout, imposing the clamped ends'
@@ -465,6 +495,19 @@ int build_device(rod_batch *b, const HostInputs &h)
     HIPCHK(hipMemcpy(b->d_ints, ints.data(), ints.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     const int64_t zero = 0;
     HIPCHK(hipMemcpy(b->d_step, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    if (b->magnetic) {
+        // magnetization times rest length per slot (zero on padding lanes)
+        std::vector<T> mag((size_t)3 * NS, T(0));
+        int64_t ee = 0;
+        for (int r = 0; r < R; ++r) {
+            for (int i = 0; i < h.n[r]; ++i)
+                for (int a = 0; a < 3; ++a)
+                    mag[a * NS + b->rod_slot[r] + i] = T(h.mag[3 * (ee + i) + a] * h.lh[ee + i]);
+            ee += h.n[r];
+        }
+        HIPCHK(hipMalloc(&b->d_mag, mag.size() * es));
+        HIPCHK(hipMemcpy(b->d_mag, mag.data(), mag.size() * es, hipMemcpyHostToDevice));
+    }
     int rc = upload_state<T>(b, h.pos.data(), h.vel.data(), h.dir.data(), h.om.data());
     if (rc) return rc;
     return ROD_OK;
@@ -556,6 +599,7 @@ int rodk::batch_view(const rod_batch *b, BatchView *v)
     if (!b || !v) return fail(ROD_EINVAL, "batch is NULL");
     v->precision = b->precision;
     v->waves = b->waves;
+    v->magnetic = b->magnetic;
     v->n_rods = b->R;
     v->n_elems = b->Ne;
     v->n_slots = b->n_slots;
@@ -771,6 +815,11 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->camp = h.camp;
     b->cfreq = h.cfreq;
     b->cphase = h.cphase;
+    b->magnetic = d->magnetization != nullptr;
+    if (b->magnetic) {
+        for (int k = 0; k < 9; ++k) b->field[k] = d->field[k];
+        b->field_freq = d->field_freq;
+    }
     b->clamp_r0.assign(3 * b->R, 0.0);
     b->clamp_rn.assign(3 * b->R, 0.0);
     b->clamp_q0.assign(9 * b->R, 0.0);
@@ -805,7 +854,7 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
         rod_batch_destroy(b);
         return fail(ROD_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
-    const double dts = stability_dt(h);
+    const double dts = stability_dt(h, d->field);
     if (d->dt > dts) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "warning: dt %.3g exceeds the explicit stability estimate %.3g", d->dt, dts);
@@ -936,6 +985,7 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->d_param);
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);
+    (void)hipFree(b->d_mag);
     (void)hipFree(b->d_freq);
     (void)hipFree(b->d_phase);
     (void)hipFree(b->d_energy);

@@ -36,6 +36,7 @@ class RodBatchDesc(C.Structure):
         ("dt", C.c_double), ("t0", C.c_double),
         ("precision", C.c_int32), ("substeps", C.c_int32), ("tile_waves", C.c_int32),
         ("inputs_on_device", C.c_int32), ("autotune", C.c_int32),
+        ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
     ]
 
 
@@ -204,7 +205,7 @@ class RodBatch:
         d.n_elems = ptr("n", _ip)
         for name in ("position", "velocity", "director", "omega", "rest_length", "rest_kappa",
                      "density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping",
-                     "end_force", "couple_amp", "couple_freq", "couple_phase"):
+                     "end_force", "couple_amp", "couple_freq", "couple_phase", "magnetization"):
             arr(name, getattr(inp, name, None))
             setattr(d, name, ptr(name, _dp))
         for name in ("bc_start", "bc_end"):
@@ -217,6 +218,11 @@ class RodBatch:
         d.tile_waves = int(tile_waves)
         d.inputs_on_device = 1 if device_inputs else 0
         d.autotune = int(autotune)
+        if getattr(inp, "magnetization", None) is not None:
+            fl = getattr(inp, "field", None)
+            fl = np.zeros(9) if fl is None else np.asarray(fl, dtype=np.float64).reshape(9)
+            d.field = (C.c_double * 9)(*[float(x) for x in fl])
+            d.field_freq = float(getattr(inp, "field_freq", 0.0) or 0.0)
         if device_inputs:
             import torch
             torch.cuda.synchronize()

@@ -94,3 +94,40 @@ def test_null_handle_calls():
     assert L.rod_step(None, 10, None) == rod.ROD_EINVAL
     assert L.rod_batch_info(None, None) == rod.ROD_EINVAL
     L.rod_batch_destroy(None)
+
+
+def test_descriptor_layouts_match_the_headers(tmp_path):
+    """Every struct of the boundary has the same size and member offsets in the
+    C headers (compiled here with gcc) as in the Python binding's ctypes."""
+    import ctypes
+    import subprocess
+    from paper_2605_13766_amd import rod
+    pairs = [("rod_batch_desc", rod.RodBatchDesc), ("rod_tune_trial", rod.TuneTrial),
+             ("rod_surrogate_desc", rod.SurrogateDesc), ("rod_train_desc", rod.TrainDesc),
+             ("rod_judge_desc", rod.JudgeDesc), ("rod_surrogate_stats", rod.SurrogateStats)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "rod_surrogate.h"', "int main(void) {"]
+    want = []
+    for cname, py in pairs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(py))
+        for f in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f[0]}));')
+            want.append(getattr(py, f[0]).offset)
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == want
+
+
+def test_magnetic_descriptor_rejected_when_not_finite():
+    from paper_2605_13766_amd import rod
+    base = W.magnetic_carpet(grid=2, n=8)
+    bad = base.copy(); bad.field = base.field.copy(); bad.field[4] = np.inf
+    assert "field" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.field_freq = np.nan
+    assert "field_freq" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.magnetization = base.magnetization.copy(); bad.magnetization[3, 1] = np.nan
+    assert "magnetization" in _expect(rod.ROD_EINVAL, bad)
