@@ -111,6 +111,23 @@ typedef struct {
     const double *magnetization;     /* [N_elems][3] (A m), or NULL */
     double field[9];                 /* b0, bc, bs (lab frame) */
     double field_freq;               /* Hz */
+    /* Gravity (Results, "Active matter": the rods
+     * settle under gravity): a uniform lab-frame acceleration g adds m_j g to
+     * the force on every node (Eq. 1a's f); its work joins W_ext. */
+    double gravity[3];               /* g (m/s^2); zero: none */
+    /* Muscle torques (same section: internal, net-zero torques prescribed as a
+     * travelling wave after the snake-locomotion model it cites).  An active
+     * moment at Voronoi point k of rod r,
+     *   m_k(t) = beta_k sin(2 pi f_r t - q_r s_k + phi_r) axis_r   (material frame),
+     * with s_k the rest arc length from the rod's first node to the Voronoi
+     * point, adds to the internal moment B kappa / e^3 of Eq. 1b (so it enters
+     * both d/ds(.) and kappa x (.), and sums to zero over a rod).  Evaluated
+     * at the time of each kick. */
+    const double *muscle_amp;        /* [N_vor] beta_k (N m), or NULL: no muscle torque */
+    const double *muscle_axis;       /* [R][3] material-frame axis (with muscle_amp; its length scales beta) */
+    const double *muscle_freq;       /* [R] f = 1 / period (Hz) */
+    const double *muscle_wavenumber; /* [R] q = 2 pi / wavelength (rad/m) */
+    const double *muscle_phase;      /* [R] phi (rad) */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -128,8 +145,9 @@ typedef struct {
  * and upload.  Errors: ROD_EINVAL (n_elems outside [1, ROD_MAX_ELEMS], a
  * NULL required array, dt <= 0, rho/E/G/radius/alpha_c <= 0, damping < 0,
  * a director farther than 1e-8 from SO(3) or with det < 0, a zero-length
- * element or rest length <= 0, couple_amp without freq/phase, a magnetization,
- * field or field_freq that is not finite), ROD_ENOMEM,
+ * element or rest length <= 0, couple_amp without freq/phase, muscle_amp
+ * without axis/freq/wavenumber/phase, a magnetization, field, field_freq,
+ * gravity or muscle input that is not finite), ROD_ENOMEM,
  * ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the longest rod).
  * A time step above the explicit stability estimate is reported through
  * rod_last_error with ROD_OK.
@@ -168,8 +186,9 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream);
  *   T_rot   = 1/2 sum_i omega_i . J_i omega_i / e_i   (Eq. 1b's rho I omega / e)
  *   U_shear = 1/2 sum_i sigma_i . S sigma_i lh_i
  *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . B_k (kappa_k - kappa0_k) Dh_k
- *   W_ext   = -sum f . (r_last - r_last(0))          (the constant end force)
- * The distributed and magnetic couples have no energy column.  Returns ROD_ENONFINITE if any rod is flagged non-finite.
+ *   W_ext   = -sum f . (r_last - r_last(0)) - sum_j m_j g . (r_j - r_j(0))
+ *                                                    (the end force and gravity)
+ * The distributed, magnetic and muscle couples have no energy column.  Returns ROD_ENONFINITE if any rod is flagged non-finite.
  */
 int rod_energy(rod_batch *b, double *out, void *stream);
 

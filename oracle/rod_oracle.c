@@ -47,7 +47,13 @@
  *   - magnetic couple (Methods, "Magnetized filaments", Eq. 2): element i
  *     carries a magnetization m_i per unit length in its material frame; a
  *     homogeneous lab field b(t) = b0 + bc cos(2 pi f t) + bs sin(2 pi f t),
- *     evaluated at the kick time, adds m_i x (Q_i b) to the couple c.
+ *     evaluated at the kick time, adds m_i x (Q_i b) to the couple c;
+ *   - gravity (Results, "Active matter"): nodal force m_j g;
+ *   - muscle torques (same section; a travelling wave of internal, net-zero
+ *     torques): an active moment beta_k sin(2 pi f t - q s_k + phi) axis at
+ *     Voronoi point k, s_k its rest arc length from the first node, added to
+ *     the internal moment B kappa / e^3 (so it enters both the difference
+ *     and the kappa x M terms), evaluated at the kick time.
  */
 #include <math.h>
 #include <stdint.h>
@@ -82,6 +88,12 @@ typedef struct {
     const double *magnetization;     /* [N_e][3] or NULL: magnetization per unit length, material frame */
     double field[9];                 /* b(t) = field[0:3] + field[3:6] cos(2 pi f t) + field[6:9] sin(2 pi f t) */
     double field_freq;               /* f, Hz */
+    double gravity[3];               /* g, m/s^2: nodal force m_j g */
+    const double *muscle_amp;        /* [N_v] or NULL: active moment amplitude beta_k */
+    const double *muscle_axis;       /* [R][3] material-frame axis */
+    const double *muscle_freq;       /* [R] Hz */
+    const double *muscle_wavenumber; /* [R] rad/m */
+    const double *muscle_phase;      /* [R] rad */
 } orc_rods;
 
 /* ---------------------------------------------------------------- vectors */
@@ -182,6 +194,10 @@ typedef struct {
     const double *mag;           /* [n][3] or NULL */
     const double *field;         /* [9] */
     double field_freq;
+    const double *grav;          /* [3] */
+    const double *mamp;          /* [n-1] or NULL */
+    const double *maxis;         /* [3] */
+    double mfreq, mwave, mphase;
     int drop;
 } rod_view;
 
@@ -207,6 +223,12 @@ static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int6
     v->mag = p->magnetization ? p->magnetization + 3 * eo : NULL;
     v->field = p->field;
     v->field_freq = p->field_freq;
+    v->grav = p->gravity;
+    v->mamp = p->muscle_amp ? p->muscle_amp + vo : NULL;
+    v->maxis = p->muscle_amp ? p->muscle_axis + 3 * r : NULL;
+    v->mfreq = p->muscle_amp ? p->muscle_freq[r] : 0.0;
+    v->mwave = p->muscle_amp ? p->muscle_wavenumber[r] : 0.0;
+    v->mphase = p->muscle_amp ? p->muscle_phase[r] : 0.0;
     v->drop = p->drop_term;
 }
 
@@ -320,6 +342,14 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
         for (int a = 0; a < 3; ++a)
             dk[a] = w->kap[3 * k + a] - (rv->k0 ? rv->k0[3 * k + a] : 0.0);
         for (int a = 0; a < 3; ++a) w->M[3 * k + a] = Bv[a] * dk[a] / e3;
+        /* active muscle moment at Voronoi k (travelling wave in the rest arc
+         * length s_k of the point), part of the internal moment */
+        if (rv->mamp) {
+            double sk = 0.0;
+            for (int i = 0; i <= k; ++i) sk += rv->lh[i];
+            const double act = rv->mamp[k] * sin(2.0 * M_PI * rv->mfreq * t - rv->mwave * sk + rv->mphase);
+            for (int a = 0; a < 3; ++a) w->M[3 * k + a] += act * rv->maxis[a];
+        }
         double kxM[3];
         cross3(&w->kap[3 * k], &w->M[3 * k], kxM);
         for (int a = 0; a < 3; ++a) w->y[3 * k + a] = kxM[a] * Dh;
@@ -335,6 +365,7 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
             if (j < n) F += w->nint[3 * j + a];
             if (j > 0) F -= w->nint[3 * (j - 1) + a];
             if (rv->fext) F += rv->fext[3 * j + a];
+            F += mass * rv->grav[a];
             acc[3 * j + a] = F / mass - rv->gamma * v[3 * j + a];
         }
     }
@@ -573,7 +604,7 @@ int orc_accel(const orc_rods *p, const double *pos, const double *vel, const dou
  *   T_rot   = 1/2 sum_i omega_i . J_i omega_i / e_i   (angular momentum density rho I omega / e)
  *   U_shear = 1/2 sum_i sigma_i . S sigma_i lh_i
  *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . Bv_k (kappa_k - kappa0_k) Dh_k
- *   W_ext   = -sum_j f_j . (r_j - r_j(0))                (constant nodal forces) */
+ *   W_ext   = -sum_j (f_j + m_j g) . (r_j - r_j(0))      (constant nodal forces, gravity) */
 int orc_energy(const orc_rods *p, const double *pos, const double *vel, const double *dir,
                const double *omega, double *out)
 {
@@ -598,11 +629,10 @@ int orc_energy(const orc_rods *p, const double *pos, const double *vel, const do
             if (j > 0) mass += 0.5 * rv.rho * c.A * rv.lh[j - 1];
             if (j < n) mass += 0.5 * rv.rho * c.A * rv.lh[j];
             Tl += 0.5 * mass * dot3(&v[3 * j], &v[3 * j]);
-            if (rv.fext) {
-                double d[3] = {x[3 * j] - rv.r0[3 * j], x[3 * j + 1] - rv.r0[3 * j + 1],
-                               x[3 * j + 2] - rv.r0[3 * j + 2]};
-                Wx -= dot3(&rv.fext[3 * j], d);
-            }
+            double d[3] = {x[3 * j] - rv.r0[3 * j], x[3 * j + 1] - rv.r0[3 * j + 1],
+                           x[3 * j + 2] - rv.r0[3 * j + 2]};
+            if (rv.fext) Wx -= dot3(&rv.fext[3 * j], d);
+            Wx -= mass * dot3(rv.grav, d);
         }
         for (int i = 0; i < n; ++i) {
             double lh = rv.lh[i];

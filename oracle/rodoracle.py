@@ -34,6 +34,8 @@ class _OrcRods(C.Structure):
         ("couple_freq", _dp), ("couple_phase", _dp), ("pos0", _dp), ("dir0", _dp),
         ("dt", C.c_double), ("t0", C.c_double), ("drop_term", C.c_int32),
         ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
+        ("gravity", C.c_double * 3), ("muscle_amp", _dp), ("muscle_axis", _dp), ("muscle_freq", _dp),
+        ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
     ]
 
 
@@ -131,6 +133,14 @@ class Oracle:
         fl = getattr(inp, "field", None)
         self.field = np.zeros(9) if fl is None else np.asarray(fl, float).reshape(9).copy()
         self.field_freq = float(getattr(inp, "field_freq", 0.0) or 0.0)
+        g = getattr(inp, "gravity", None)
+        self.gravity = np.zeros(3) if g is None else np.asarray(g, float).reshape(3).copy()
+        ma = getattr(inp, "muscle_amp", None)
+        self.muscle = None
+        if ma is not None:
+            self.muscle = [_d(np.asarray(ma, float).reshape(-1))] + [
+                _d(np.asarray(getattr(inp, k), float).reshape(-1))
+                for k in ("muscle_axis", "muscle_freq", "muscle_wavenumber", "muscle_phase")]
         self.mat = {k: _d(getattr(inp, k)) for k in
                     ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping")}
         self.bc_start = np.ascontiguousarray(inp.bc_start, dtype=np.int32)
@@ -163,6 +173,10 @@ class Oracle:
         s.magnetization = _ptr(self.magnetization)
         s.field = (C.c_double * 9)(*[float(x) for x in self.field])
         s.field_freq = self.field_freq
+        s.gravity = (C.c_double * 3)(*[float(x) for x in self.gravity])
+        if self.muscle is not None:
+            s.muscle_amp, s.muscle_axis, s.muscle_freq, s.muscle_wavenumber, s.muscle_phase = \
+                [_ptr(a) for a in self.muscle]
         self._s = s
 
     @property

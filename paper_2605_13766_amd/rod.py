@@ -37,6 +37,8 @@ class RodBatchDesc(C.Structure):
         ("precision", C.c_int32), ("substeps", C.c_int32), ("tile_waves", C.c_int32),
         ("inputs_on_device", C.c_int32), ("autotune", C.c_int32),
         ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
+        ("gravity", C.c_double * 3), ("muscle_amp", _dp), ("muscle_axis", _dp), ("muscle_freq", _dp),
+        ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
     ]
 
 
@@ -205,7 +207,8 @@ class RodBatch:
         d.n_elems = ptr("n", _ip)
         for name in ("position", "velocity", "director", "omega", "rest_length", "rest_kappa",
                      "density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping",
-                     "end_force", "couple_amp", "couple_freq", "couple_phase", "magnetization"):
+                     "end_force", "couple_amp", "couple_freq", "couple_phase", "magnetization",
+                     "muscle_amp", "muscle_axis", "muscle_freq", "muscle_wavenumber", "muscle_phase"):
             arr(name, getattr(inp, name, None))
             setattr(d, name, ptr(name, _dp))
         for name in ("bc_start", "bc_end"):
@@ -223,6 +226,9 @@ class RodBatch:
             fl = np.zeros(9) if fl is None else np.asarray(fl, dtype=np.float64).reshape(9)
             d.field = (C.c_double * 9)(*[float(x) for x in fl])
             d.field_freq = float(getattr(inp, "field_freq", 0.0) or 0.0)
+        g = getattr(inp, "gravity", None)
+        if g is not None:
+            d.gravity = (C.c_double * 3)(*[float(x) for x in np.asarray(g, dtype=np.float64).reshape(3)])
         if device_inputs:
             import torch
             torch.cuda.synchronize()

@@ -68,6 +68,12 @@ class RodInputs:
     magnetization: Optional[np.ndarray] = None  # [N_e, 3] per unit length, material frame (A m)
     field: Optional[np.ndarray] = None          # [9]: b(t) = f[0:3] + f[3:6] cos(2 pi ff t) + f[6:9] sin(...), T
     field_freq: float = 0.0                     # ff, Hz
+    gravity: Optional[np.ndarray] = None        # [3] m/s^2, lab frame
+    muscle_amp: Optional[np.ndarray] = None     # [N_v] N m: beta_k at Voronoi point k
+    muscle_axis: Optional[np.ndarray] = None    # [R, 3] material frame
+    muscle_freq: Optional[np.ndarray] = None    # [R] Hz
+    muscle_wavenumber: Optional[np.ndarray] = None  # [R] rad/m
+    muscle_phase: Optional[np.ndarray] = None   # [R] rad
     name: str = ""
 
     # ------------------------------------------------------------------ sizes
@@ -128,6 +134,10 @@ class RodInputs:
             magnetization=None if self.magnetization is None else self.magnetization[e_idx].copy(),
             field=None if self.field is None else np.array(self.field, float).copy(),
             field_freq=self.field_freq,
+            gravity=None if self.gravity is None else np.array(self.gravity, float).copy(),
+            muscle_amp=None if self.muscle_amp is None else self.muscle_amp[v_idx].copy(),
+            muscle_axis=per_rod(self.muscle_axis), muscle_freq=per_rod(self.muscle_freq),
+            muscle_wavenumber=per_rod(self.muscle_wavenumber), muscle_phase=per_rod(self.muscle_phase),
             name=self.name + "[subset]",
         )
 
