@@ -8,11 +8,14 @@ substeps per launch S chosen by the library's autotuner).  The headline value is
 FP32 figure rides along in the same JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate] [--no-magnetic]
+                  [--no-active]
 
 The magnetic carpet rides along as the "magnetic" object: 65,536 base-clamped
 rods x 50 elements (FP32) turned by a rotating homogeneous field through their
 programmed magnetization, timed like the headline and next to the same carpet
-driven by its distributed couple.
+driven by its distributed couple.  The "active" object times 16,384 free
+filaments x 50 elements under gravity and travelling-wave muscle moments in
+both precisions.
 
 The learned coarse step rides along as the "surrogate" object: the network is
 trained on 16,384 carpet rods (64 elements, 2.1e6 windows from plain
@@ -50,7 +53,10 @@ sys.path.insert(0, ROOT)
 METRIC = "rod element-steps/s (plain) and surrogate simulated-s/s at ≤1e-3 error"
 ALGO_FLOP = 459                                  # per element-step (breakdown in the design notes)
 ALGO_FLOP_MAG = 459 - 6 + 27                     # the external couple's 6 replaced by m x (Q b): 27
+ALGO_FLOP_ACTIVE = 459 - 6 + 3 + 9               # no external couple; gravity 3; muscle moment 9
 ALGO_BYTES = {"f64": 400, "f32": 204}            # HBM bytes per element per launch
+MAG_BYTES = 12                                   # FP32 magnetization x rest length, read once per launch
+MUSCLE_BYTES = {"f64": 32, "f32": 20}            # muscle amplitude x axis (T) and phase offset (FP64)
 PEAK = {"f64": 78.6, "f32": 157.3}               # TFLOP/s, MI355X vector peaks
 STEPS_PER_LAUNCH = 1000
 SURR_K = 32
@@ -65,10 +71,11 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(precision: str):
+def traffic_from_profile(tag: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"rod_step_{precision}_ragged4096_traffic.json")
+    taken on the current kernel source (else None).  tag: f64_ragged4096,
+    f32_ragged4096 or f32_magnetic65536."""
+    path = os.path.join(ROOT, "profiles", f"rod_step_{tag}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -78,7 +85,8 @@ def traffic_from_profile(precision: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=ALGO_FLOP, traffic_key=True):
+def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=ALGO_FLOP, extra_bytes=0,
+             traffic_tag=None):
     import torch
     from paper_2605_13766_amd import rod
 
@@ -109,7 +117,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
     el_steps = inp.n_elements * STEPS_PER_LAUNCH
     value = el_steps * steps / wall
     achieved = algo_flop * el_steps / (launch_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(precision) if traffic_key else None
+    traffic = traffic_from_profile(traffic_tag or f"{precision}_ragged4096")
     return {
         "value": value,
         "ms_per_step": wall / steps * 1e3,
@@ -122,18 +130,19 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
             "unit": "TFLOP/s",
             "frac": achieved / PEAK[precision],
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": ALGO_BYTES[precision] * inp.n_elements,
+            "algorithmic_bytes_per_launch": (ALGO_BYTES[precision] + extra_bytes) * inp.n_elements,
         },
     }
 
 
-def time_magnetic(steps, warmup):
+def time_magnetic(steps, warmup, tile_waves=0, substeps=0):
     """The cilia carpet (65,536 base-clamped rods x 50 elements, FP32, dt 1e-6 s,
     autotuned) driven by the rotating magnetic field, next to the same carpet
     driven by its distributed couple: the cost of the magnetic couple."""
     from paper_2605_13766_amd import workloads as W
-    mag = time_gpu(W.magnetic_carpet(), "f32", steps, warmup, algo_flop=ALGO_FLOP_MAG, traffic_key=False)
-    drv = time_gpu(W.cilia_carpet(), "f32", steps, warmup, traffic_key=False)
+    mag = time_gpu(W.magnetic_carpet(), "f32", steps, warmup, tile_waves, substeps, algo_flop=ALGO_FLOP_MAG,
+                   extra_bytes=MAG_BYTES, traffic_tag="f32_magnetic65536")
+    drv = time_gpu(W.cilia_carpet(), "f32", steps, warmup, tile_waves, substeps, traffic_tag="none")
     return {
         "workload": "magnetic_carpet: 65,536 rods x 50 elements on a 256 x 256 grid, FP32, dt 1e-6 s, "
                     "field 10 mT rotating at 10 Hz, programmed magnetization 1.5e-3 A m, "
@@ -145,6 +154,23 @@ def time_magnetic(steps, warmup):
                           "tile_waves": drv["info"]["tile_waves"], "substeps_per_launch": drv["info"]["substeps"]},
         "magnetic_over_driven_time": mag["launch_ms"] / drv["launch_ms"],
     }
+
+
+def time_active(steps, warmup, tile_waves=0, substeps=0):
+    """Active filaments (16,384 free rods x 50 elements under gravity, driven by
+    travelling muscle waves, dt 5e-5 s), both precisions, autotuned."""
+    from paper_2605_13766_amd import workloads as W
+    inp = W.active_filaments()
+    out = {"workload": "active_filaments: 16,384 free rods x 50 elements, 1 m, gravity, travelling muscle "
+                       f"moments (1 s period, wavelength 1 m), dt 5e-5 s, {STEPS_PER_LAUNCH} steps per launch",
+           "unit": "element-steps/s"}
+    for p in ("f64", "f32"):
+        r = time_gpu(inp, p, steps, warmup, tile_waves, substeps, algo_flop=ALGO_FLOP_ACTIVE,
+                     extra_bytes=MUSCLE_BYTES[p], traffic_tag=f"{p}_active16384")
+        out[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms": r["launch_ms"],
+                  "roofline": r["roofline"], "tile_waves": r["info"]["tile_waves"],
+                  "substeps_per_launch": r["info"]["substeps"]}
+    return out
 
 
 def cpu_baseline(inp, target_s=10.0):
@@ -301,6 +327,7 @@ def main(argv=None):
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-magnetic", action="store_true")
+    ap.add_argument("--no-active", action="store_true")
     ap.add_argument("--tile-waves", type=int, default=0, help="fix the tile width (0: autotune)")
     ap.add_argument("--substeps", type=int, default=0, help="fix the substeps per launch (0: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -367,7 +394,10 @@ def main(argv=None):
                    "substeps_per_launch": res[p]["info"]["substeps"]}
     if not args.no_magnetic:
         print("timing the magnetic carpet", file=sys.stderr, flush=True)
-        line["magnetic"] = time_magnetic(args.steps, args.warmup)
+        line["magnetic"] = time_magnetic(args.steps, args.warmup, args.tile_waves, args.substeps)
+    if not args.no_active:
+        print("timing the active filaments", file=sys.stderr, flush=True)
+        line["active"] = time_active(args.steps, args.warmup, args.tile_waves, args.substeps)
     if not args.no_cpu_baseline:
         print("timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inp)

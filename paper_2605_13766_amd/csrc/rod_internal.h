@@ -87,6 +87,17 @@ struct DevBatch {
     T field[9];
     double field_freq;
     double field_ds, field_dc;   // sin, cos of 2 pi field_freq dt
+    // extended step (magnetic couple, gravity, muscle torques): when false the
+    // plain kernel runs and the fields below are unused
+    bool ext;
+    T grav[3];                 // gravity, lab frame
+    const T *mus;              // [3][n_slots] muscle amplitude x axis at the slot's Voronoi point, or NULL
+    const double *mus_ofs;     // [n_slots] phi - q s_k
+    const double *mus_freq;    // [n_rods] Hz
+    // creation positions relative to the rod origin (work of gravity), FP64:
+    // [3][n_slots + n_rods], the slot's node, then each rod's node n; NULL
+    // without gravity
+    const double *grav_r0;
 };
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
@@ -104,7 +115,7 @@ int step_resident_groups(int precision_f32, int waves);
 struct BatchView {
     int precision;
     int waves;
-    bool magnetic;             // the batch carries a magnetic couple
+    bool extended;             // the batch carries a magnetic couple, gravity or muscle torques
     int32_t n_rods;
     int64_t n_elems, n_slots;
     const int32_t *n;          // host [R]

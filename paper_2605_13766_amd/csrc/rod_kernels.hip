@@ -234,19 +234,22 @@ __device__ inline bool finite3(T a, T b, T c)
 #define ROD_F32_WAVES_PER_SIMD 5
 #endif
 
-// MAG: the batch carries a magnetic couple (a separate instantiation, so the
-// plain step keeps its registers and LDS).  Its FP64 4-wave and FP32 8-wave
-// tiles need one wave per SIMD less than the plain step's.
-template <typename T, int W, bool MAG>
+// EXT: the extended step, for batches with a magnetic couple, gravity or
+// muscle torques (a separate instantiation, so the plain step keeps its
+// registers and LDS).  Each extension a batch lacks contributes an exact zero
+// (zero magnetization, amplitude or gravity), so the extended kernel reproduces
+// the plain one bit for bit on a plain batch.  Its multi-wave FP64 tiles and
+// all its FP32 tiles run one wave per SIMD fewer than the plain step's.
+template <typename T, int W, bool EXT>
 constexpr int step_waves_per_simd()
 {
-    return sizeof(T) == 8 ? ((W == 8 || (MAG && W == 4)) ? 2 : ROD_F64_WAVES_PER_SIMD)
-                          : ((MAG && W == 8) ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
+    return sizeof(T) == 8 ? ((W == 8 || (EXT && W > 1)) ? 2 : ROD_F64_WAVES_PER_SIMD)
+                          : (EXT ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
 }
 
-template <typename T, int W, bool MAG>
+template <typename T, int W, bool EXT>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, MAG>())))
+__attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, EXT>())))
 void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
     constexpr bool EDGE = sizeof(T) == 4;
@@ -257,8 +260,9 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     // barrier is needed): a register extension for values used once a substep
     enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
            C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3,
-           C_MX, C_MY, C_MZ };   // magnetization times rest length (MAG only)
-    constexpr int N_C = MAG ? C_MZ + 1 : C_MX;
+           C_MX, C_MY, C_MZ,     // magnetization times rest length (EXT only)
+           C_AX, C_AY, C_AZ };   // muscle amplitude times axis (EXT only)
+    constexpr int N_C = EXT ? C_AZ + 1 : C_MX;
     // One LDS block in a fixed order: the small wave-edge exchange buffers first,
     // so their addresses fit the 8-bit offsets of ds_write2/ds_read2 and need no
     // per-access address arithmetic, then the constant columns.
@@ -268,6 +272,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         T lx3[NL * 9];
         T lx4[NL * 3];
         double phs[2 * TL];        // couple phase increment: sin, cos
+        double mph[EXT ? 2 * TL : 1];   // muscle phase increment: sin, cos (EXT only)
         T cst[N_C * TL];
     };
     __shared__ Shared sh;
@@ -372,19 +377,39 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             cw[C_CZ * TL] = c2;
             phs[lane] = ds;
             phs[TL + lane] = dc;
-            if constexpr (MAG) {
-                cw[C_MX * TL] = B.mag[s];
-                cw[C_MY * TL] = B.mag[NS + s];
-                cw[C_MZ * TL] = B.mag[2 * NS + s];
-            }
         }
-        // magnetic field phase 2 pi f t at the substep midpoints (the same
-        // for every lane), advanced by the rotation recurrence
-        double fs = 0.0, fc = 1.0;
-        if constexpr (MAG) {
-            const double ph = 2.0 * M_PI * B.field_freq * (B.t0 + ((double)step0 + 0.5) * B.dt);
-            fs = sin(ph);
-            fc = cos(ph);
+        // extended step: magnetization and muscle amplitude columns; the
+        // field's phase 2 pi f t (the same for every lane) and the muscle
+        // wave's phase 2 pi f_r t - q_r s_k + phi_r at the substep midpoints,
+        // both advanced by rotation recurrences
+        double fs = 0.0, fc = 1.0, ms = 0.0, mc = 1.0;
+        if constexpr (EXT) {
+            T *cw = cst + lane;
+            const bool hm = B.mag != nullptr, ha = B.mus != nullptr && valid;
+            cw[C_MX * TL] = hm ? B.mag[s] : T(0);
+            cw[C_MY * TL] = hm ? B.mag[NS + s] : T(0);
+            cw[C_MZ * TL] = hm ? B.mag[2 * NS + s] : T(0);
+            cw[C_AX * TL] = ha ? B.mus[s] : T(0);
+            cw[C_AY * TL] = ha ? B.mus[NS + s] : T(0);
+            cw[C_AZ * TL] = ha ? B.mus[2 * NS + s] : T(0);
+            const double tm = B.t0 + ((double)step0 + 0.5) * B.dt;
+            if (hm) {
+                const double ph = 2.0 * M_PI * B.field_freq * tm;
+                fs = sin(ph);
+                fc = cos(ph);
+            }
+            double mds = 0.0, mdc = 1.0;
+            if (ha) {
+                const double fr = B.mus_freq[rr];
+                const double ph = 2.0 * M_PI * fr * tm + B.mus_ofs[s];
+                ms = sin(ph);
+                mc = cos(ph);
+                const double dp = 2.0 * M_PI * fr * B.dt;
+                mds = sin(dp);
+                mdc = cos(dp);
+            }
+            sh.mph[lane] = mds;
+            sh.mph[TL + lane] = mdc;
         }
 
         // edge form: velocity of node i+1 (refreshed after every kick)
@@ -467,9 +492,16 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             k0 *= inv_Dh; k1 *= inv_Dh; k2 *= inv_Dh;
             const T eps = (l + ln) * (T(0.5) * inv_Dh);
             const T ie3 = rcp_t(eps * eps * eps);
-            const T M0 = cl[C_B1 * TL] * (k0 - cl[C_K0X * TL]) * ie3;
-            const T M1 = cl[C_B1 * TL] * (k1 - cl[C_K0Y * TL]) * ie3;
-            const T M2 = cl[C_B3 * TL] * (k2 - cl[C_K0Z * TL]) * ie3;
+            T M0 = cl[C_B1 * TL] * (k0 - cl[C_K0X * TL]) * ie3;
+            T M1 = cl[C_B1 * TL] * (k1 - cl[C_K0Y * TL]) * ie3;
+            T M2 = cl[C_B3 * TL] * (k2 - cl[C_K0Z * TL]) * ie3;
+            if constexpr (EXT) {
+                // active muscle moment, part of the internal moment
+                const T sa = T(ms);
+                M0 += cl[C_AX * TL] * sa;
+                M1 += cl[C_AY * TL] * sa;
+                M2 += cl[C_AZ * TL] * sa;
+            }
             const T y0 = (k1 * M2 - k2 * M1) * Dh;
             const T y1 = (k2 * M0 - k0 * M2) * Dh;
             const T y2 = (k0 * M1 - k1 * M0) * Dh;
@@ -486,9 +518,14 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             // ---- Eq. 1a at node i (and node n on the last lane)
             const T gamma = cl[C_GAMMA * TL];
             const T inv_m = cl[C_INV_M * TL];
-            const T a0 = (nf0 - np0) * inv_m - gamma * v0;
-            const T a1x = (nf1 - np1) * inv_m - gamma * v1;
-            const T a2x = (nf2 - np2) * inv_m - gamma * v2;
+            T a0 = (nf0 - np0) * inv_m - gamma * v0;
+            T a1x = (nf1 - np1) * inv_m - gamma * v1;
+            T a2x = (nf2 - np2) * inv_m - gamma * v2;
+            if constexpr (EXT) {
+                a0 += B.grav[0];
+                a1x += B.grav[1];
+                a2x += B.grav[2];
+            }
 
             // ---- Eq. 1b at element i
             // Q t = (sigma + e3) / e
@@ -504,7 +541,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T tq2 = (M2 - b3[5]) + T(0.5) * (b3[8] + y2) + (qt0 * ss1 - qt1 * ss0) * lh
                         + (jw0 * w1 - jw1 * w0) + jw2 * ede + cl[C_CZ * TL] * cs;
             T mc0 = 0, mc1 = 0, mc2 = 0;
-            if constexpr (MAG) {
+            if constexpr (EXT) {
                 // magnetic couple (m lh) x (Q b(t)), material frame
                 const T cb = T(fc), sb = T(fs);
                 const T b0 = B.field[0] + B.field[3] * cb + B.field[6] * sb;
@@ -528,9 +565,17 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             w0 += hw * al0; w1 += hw * al1; w2 += hw * al2;
             {
                 const T inv_mt = cl[C_INV_MT * TL];
-                u0 += hu * ((cl[C_FX * TL] - nf0) * inv_mt - gamma * u0);
-                u1 += hu * ((cl[C_FY * TL] - nf1) * inv_mt - gamma * u1);
-                u2 += hu * ((cl[C_FZ * TL] - nf2) * inv_mt - gamma * u2);
+                T b0 = (cl[C_FX * TL] - nf0) * inv_mt - gamma * u0;
+                T b1 = (cl[C_FY * TL] - nf1) * inv_mt - gamma * u1;
+                T b2 = (cl[C_FZ * TL] - nf2) * inv_mt - gamma * u2;
+                if constexpr (EXT) {
+                    b0 += B.grav[0];
+                    b1 += B.grav[1];
+                    b2 += B.grav[2];
+                }
+                u0 += hu * b0;
+                u1 += hu * b1;
+                u2 += hu * b2;
             }
 
             // ---- edge form: exchange 4, the post-kick velocity of node i+1
@@ -559,10 +604,14 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 pc = pc * dc - ps * ds;
                 ps = nps;
             }
-            if constexpr (MAG) {
+            if constexpr (EXT) {
                 const double nfs = fs * B.field_dc + fc * B.field_ds;
                 fc = fc * B.field_dc - fs * B.field_ds;
                 fs = nfs;
+                const double mds = sh.mph[cofs], mdc = sh.mph[TL + cofs];
+                const double nms = ms * mdc + mc * mds;
+                mc = mc * mdc - ms * mds;
+                ms = nms;
             }
         }
 
@@ -626,10 +675,20 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
     const double tv1 = (double)B.tail[TVY * B.n_rods + rod];
     const double tv2 = (double)B.tail[TVZ * B.n_rods + rod];
     double qprev[9];
+    const double g0 = (double)B.grav[0], g1 = (double)B.grav[1], g2 = (double)B.grav[2];
+    const bool grav = B.ext && B.grav_r0;
+    const int64_t NT = NS + B.n_rods;
+    double Wg = 0;   // g . sum_j m_j (r_j - r_j(0))
     for (int i = 0; i < n; ++i) {
         const int64_t s = s0 + i;
         const double v0 = S(VX, s), v1 = S(VY, s), v2 = S(VZ, s);
         Tl += 0.5 / P(P_INV_M, s) * (v0 * v0 + v1 * v1 + v2 * v2);
+        if (grav) {
+            const double x0 = (EDGE ? tr0 : S(RX, s)) - B.grav_r0[s];
+            const double x1 = (EDGE ? tr1 : S(RY, s)) - B.grav_r0[NT + s];
+            const double x2 = (EDGE ? tr2 : S(RZ, s)) - B.grav_r0[2 * NT + s];
+            Wg += (g0 * x0 + g1 * x1 + g2 * x2) / P(P_INV_M, s);
+        }
         double d0, d1, d2;
         if (EDGE) {
             d0 = S(RX, s); d1 = S(RY, s); d2 = S(RZ, s);
@@ -665,7 +724,13 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
         if (EDGE) { tr0 += d0; tr1 += d1; tr2 += d2; }   // anchor + edges -> node n
     }
     Tl += 0.5 / RP(R_INV_M_TAIL) * (tv0 * tv0 + tv1 * tv1 + tv2 * tv2);
-    const double Wx = -(RP(R_FX) * (tr0 - RP(R_T0X)) + RP(R_FY) * (tr1 - RP(R_T0Y)) + RP(R_FZ) * (tr2 - RP(R_T0Z)));
+    double Wx = -(RP(R_FX) * (tr0 - RP(R_T0X)) + RP(R_FY) * (tr1 - RP(R_T0Y)) + RP(R_FZ) * (tr2 - RP(R_T0Z)));
+    if (grav) {
+        const int64_t c = NS + rod;
+        Wg += (g0 * (tr0 - B.grav_r0[c]) + g1 * (tr1 - B.grav_r0[NT + c]) + g2 * (tr2 - B.grav_r0[2 * NT + c]))
+            / RP(R_INV_M_TAIL);
+        Wx -= Wg;
+    }
     out[5 * row + 0] = Tl;
     out[5 * row + 1] = Tr;
     out[5 * row + 2] = Us;
@@ -679,7 +744,7 @@ template <typename T, int W>
 static hipError_t launch_w(const DevBatch<T> &b, int n_sub, int grid, hipStream_t s)
 {
     if (grid <= 0) grid = b.n_tiles;
-    if (b.mag)
+    if (b.ext)
         hipLaunchKernelGGL((rod_step_kernel<T, W, true>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
     else
         hipLaunchKernelGGL((rod_step_kernel<T, W, false>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);

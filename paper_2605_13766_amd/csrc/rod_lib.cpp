@@ -46,6 +46,7 @@ struct HostInputs {
     std::vector<int32_t> bc0, bc1;
     std::vector<double> fend, camp, cfreq, cphase;
     std::vector<double> mag;     // [N_e][3] magnetization per unit length (empty: none)
+    std::vector<double> mamp, maxis, mfreq, mwave, mphase;   // muscle torques (empty: none)
     bool has_k0 = false, has_f = false, has_c = false;
 };
 
@@ -87,11 +88,17 @@ struct rod_batch {
     std::vector<int32_t> bc0, bc1;
     std::vector<double> clamp_r0, clamp_q0, clamp_rn, clamp_qn;   // [R][3], [R][9]
     std::vector<double> E, G, rho, rad, ac, camp, cfreq, cphase;  // per-rod inputs kept for the surrogate
-    bool magnetic = false;
+    bool magnetic = false, muscle = false;
+    bool ext = false;            // magnetic, gravity or muscle: the step runs the extended kernel
     double field[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, field_freq = 0;
+    double grav[3] = {0, 0, 0};
     // device
     void *d_state = nullptr, *d_param = nullptr, *d_tail = nullptr, *d_rodp = nullptr;
     void *d_mag = nullptr;       // [3][n_slots] magnetization times rest length (magnetic batches)
+    void *d_mus = nullptr;       // [3][n_slots] muscle amplitude times axis at the slot's Voronoi point
+    double *d_mus_ofs = nullptr; // [n_slots] muscle phase offset phi - q s_k
+    double *d_mus_freq = nullptr;   // [R] muscle frequency
+    double *d_grav_r0 = nullptr;    // [3][n_slots + R] creation positions (batches with gravity)
     double *d_freq = nullptr, *d_phase = nullptr, *d_energy = nullptr;
     int32_t *d_ints = nullptr;   // slot_rod, slot_idx, rod_n, rod_flags, rod_slot, nonfinite
     int64_t *d_step = nullptr;
@@ -157,6 +164,10 @@ int validate(const rod_batch_desc *d)
             if (!std::isfinite(d->field[k])) return fail(ROD_EINVAL, "field is not finite");
         if (!std::isfinite(d->field_freq)) return fail(ROD_EINVAL, "field_freq is not finite");
     }
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d->gravity[k])) return fail(ROD_EINVAL, "gravity is not finite");
+    if (d->muscle_amp && (!d->muscle_axis || !d->muscle_freq || !d->muscle_wavenumber || !d->muscle_phase))
+        return fail(ROD_EINVAL, "muscle_amp needs muscle_axis, muscle_freq, muscle_wavenumber and muscle_phase");
     return ROD_OK;
 }
 
@@ -224,6 +235,13 @@ int gather_inputs(const rod_batch_desc *d, HostInputs &h)
     if (d->magnetization) {
         if ((rc = fetch(h.mag, d->magnetization, 3 * Ne, dev))) return rc;
     }
+    if (d->muscle_amp) {
+        if ((rc = fetch(h.mamp, d->muscle_amp, Nv, dev))) return rc;
+        if ((rc = fetch(h.maxis, d->muscle_axis, 3 * R, dev))) return rc;
+        if ((rc = fetch(h.mfreq, d->muscle_freq, R, dev))) return rc;
+        if ((rc = fetch(h.mwave, d->muscle_wavenumber, R, dev))) return rc;
+        if ((rc = fetch(h.mphase, d->muscle_phase, R, dev))) return rc;
+    }
     return ROD_OK;
 }
 
@@ -242,6 +260,8 @@ int check_values(HostInputs &h)
     for (double x : h.vel) if (!std::isfinite(x)) return fail(ROD_EINVAL, "velocity is not finite");
     for (double x : h.om) if (!std::isfinite(x)) return fail(ROD_EINVAL, "omega is not finite");
     for (double x : h.mag) if (!std::isfinite(x)) return fail(ROD_EINVAL, "magnetization is not finite");
+    for (const auto *vec : {&h.mamp, &h.maxis, &h.mfreq, &h.mwave, &h.mphase})
+        for (double x : *vec) if (!std::isfinite(x)) return fail(ROD_EINVAL, "a muscle input is not finite");
     const int64_t Ne = (int64_t)h.dir.size() / 9;
     for (int64_t i = 0; i < Ne; ++i) {
         const double *q = &h.dir[9 * i];
@@ -337,6 +357,12 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.field_freq = b->field_freq;
     d.field_ds = std::sin(2.0 * M_PI * b->field_freq * b->dt);
     d.field_dc = std::cos(2.0 * M_PI * b->field_freq * b->dt);
+    d.ext = b->ext;
+    for (int a = 0; a < 3; ++a) d.grav[a] = T(b->grav[a]);
+    d.mus = (T *)b->d_mus;
+    d.mus_ofs = b->d_mus_ofs;
+    d.mus_freq = b->d_mus_freq;
+    d.grav_r0 = b->d_grav_r0;
 }
 
 // Pack the dynamic state into the slot layout, imposing the clamped ends'
@@ -508,6 +534,45 @@ int build_device(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc(&b->d_mag, mag.size() * es));
         HIPCHK(hipMemcpy(b->d_mag, mag.data(), mag.size() * es, hipMemcpyHostToDevice));
     }
+    if (b->grav[0] != 0 || b->grav[1] != 0 || b->grav[2] != 0) {
+        // creation positions relative to the rod origin, for the work of gravity
+        const int64_t NT = NS + R;
+        std::vector<double> r0((size_t)3 * NT, 0.0);
+        int64_t nn = 0;
+        for (int r = 0; r < R; ++r) {
+            for (int j = 0; j <= h.n[r]; ++j) {
+                const int64_t col = j < h.n[r] ? b->rod_slot[r] + j : NS + r;
+                for (int a = 0; a < 3; ++a) r0[a * NT + col] = h.pos[3 * (nn + j) + a] - b->origin[3 * r + a];
+            }
+            nn += h.n[r] + 1;
+        }
+        HIPCHK(hipMalloc((void **)&b->d_grav_r0, r0.size() * sizeof(double)));
+        HIPCHK(hipMemcpy(b->d_grav_r0, r0.data(), r0.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (b->muscle) {
+        // amplitude times axis and the phase offset phi - q s_k at the Voronoi
+        // point of each slot (zero amplitude on a rod's last element and padding)
+        std::vector<T> mus((size_t)3 * NS, T(0));
+        std::vector<double> ofs((size_t)NS, 0.0);
+        int64_t ee = 0, vv = 0;
+        for (int r = 0; r < R; ++r) {
+            double sk = 0.0;
+            for (int i = 0; i + 1 < h.n[r]; ++i) {
+                sk += h.lh[ee + i];
+                const int64_t sl = b->rod_slot[r] + i;
+                for (int a = 0; a < 3; ++a) mus[a * NS + sl] = T(h.mamp[vv + i] * h.maxis[3 * r + a]);
+                ofs[sl] = h.mphase[r] - h.mwave[r] * sk;
+            }
+            ee += h.n[r];
+            vv += h.n[r] - 1;
+        }
+        HIPCHK(hipMalloc(&b->d_mus, mus.size() * es));
+        HIPCHK(hipMalloc((void **)&b->d_mus_ofs, ofs.size() * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&b->d_mus_freq, (size_t)R * sizeof(double)));
+        HIPCHK(hipMemcpy(b->d_mus, mus.data(), mus.size() * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_mus_ofs, ofs.data(), ofs.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_mus_freq, h.mfreq.data(), (size_t)R * sizeof(double), hipMemcpyHostToDevice));
+    }
     int rc = upload_state<T>(b, h.pos.data(), h.vel.data(), h.dir.data(), h.om.data());
     if (rc) return rc;
     return ROD_OK;
@@ -599,7 +664,7 @@ int rodk::batch_view(const rod_batch *b, BatchView *v)
     if (!b || !v) return fail(ROD_EINVAL, "batch is NULL");
     v->precision = b->precision;
     v->waves = b->waves;
-    v->magnetic = b->magnetic;
+    v->extended = b->ext;
     v->n_rods = b->R;
     v->n_elems = b->Ne;
     v->n_slots = b->n_slots;
@@ -820,6 +885,9 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
         for (int k = 0; k < 9; ++k) b->field[k] = d->field[k];
         b->field_freq = d->field_freq;
     }
+    b->muscle = d->muscle_amp != nullptr;
+    for (int a = 0; a < 3; ++a) b->grav[a] = d->gravity[a];
+    b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0;
     b->clamp_r0.assign(3 * b->R, 0.0);
     b->clamp_rn.assign(3 * b->R, 0.0);
     b->clamp_q0.assign(9 * b->R, 0.0);
@@ -986,6 +1054,10 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);
     (void)hipFree(b->d_mag);
+    (void)hipFree(b->d_mus);
+    (void)hipFree(b->d_mus_ofs);
+    (void)hipFree(b->d_mus_freq);
+    (void)hipFree(b->d_grav_r0);
     (void)hipFree(b->d_freq);
     (void)hipFree(b->d_phase);
     (void)hipFree(b->d_energy);

@@ -266,7 +266,8 @@ int ensure_ctx(rod_surrogate *s, rod_batch *b, rodk::BatchView &v)
     int rc = rodk::batch_view(b, &v);
     if (rc) return rc;
     if (v.precision != ROD_F32) return sfail(ROD_EUNSUPPORTED, "the learned coarse step runs on FP32 batches");
-    if (v.magnetic) return sfail(ROD_EUNSUPPORTED, "the learned coarse step has no magnetic-couple features");
+    if (v.extended)
+        return sfail(ROD_EUNSUPPORTED, "the learned coarse step has no features for a magnetic couple, gravity or muscle torques");
     if (s->ctx_batch == b && s->ctx_rods == v.n_rods) return ROD_OK;
     free_ctx(s);
     const int R = v.n_rods;

@@ -21,6 +21,8 @@ shapes:
 * ``magnetic_carpet``    : the carpet driven instead by a rotating homogeneous
   magnetic field acting on a programmed per-rod magnetization (Methods,
   "Magnetized filaments"; Results, "Magnetized filament assemblies").
+* ``active_filaments``   : free rods scattered in a box, under gravity and
+  driven by travelling-wave muscle moments (Results, "Active matter").
 
 Node j of rod r is row ``node_offset[r] + j`` of the node arrays, element i
 is row ``elem_offset[r] + i`` of the element arrays, Voronoi point k is row
@@ -441,4 +443,40 @@ def magnetic_carpet(grid=256, n=50, L=0.01, radius=2e-4, youngs=1e6, spacing=2.5
     inp.field_freq = float(freq)
     inp.couple_amp = inp.couple_freq = inp.couple_phase = None
     inp.name = "magnetic_carpet"
+    return inp
+
+
+def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period=1.0,
+                     wavelength=None, curvature_amp=3.0, g=9.81, damping=0.5, dt=5e-5,
+                     seed=SEED_BASE + 7):
+    """Free straight filaments at random positions and orientations in a cube of
+    side 2L, under gravity (-z) and each driven by a travelling muscle wave.
+
+    The muscle moment at Voronoi point k is beta_k sin(2 pi t / period - 2 pi
+    s_k / wavelength + phi_r) about the material d1 axis, with
+    beta_k = curvature_amp E I sin(pi s_k / L) (the curvature it would hold
+    statically, tapered to zero at both ends) and a random phase phi_r per rod;
+    wavelength defaults to L.  Defaults follow a snake-sized rod (1 m, radius
+    25 mm, E = 1e7 Pa, one wave per second).
+    """
+    rng = np.random.default_rng(seed)
+    wavelength = L if wavelength is None else wavelength
+    base = rng.uniform(0.0, 2.0 * L, size=(n_rods, 3))
+    d3 = _unit(rng.normal(size=(n_rods, 3)))
+    s = np.linspace(0.0, L, n + 1)
+    nodes = base[:, None, :] + (s - 0.5 * L)[None, :, None] * d3[:, None, :]
+    a = np.where(np.abs(d3[:, :1]) < 0.9, np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 1.0, 0.0]]))
+    d1 = _unit(a - np.sum(a * d3, axis=1, keepdims=True) * d3)
+    d2 = np.cross(d3, d1)
+    Q = np.repeat(np.stack([d1, d2, d3], axis=1), n, axis=0)
+    inp = _assemble("active_filaments", list(nodes), list(Q.reshape(n_rods, n, 3, 3)), dt,
+                    density=DENSITY, youngs=youngs, radius=radius, damping=damping, bc_start=0, bc_end=0)
+    EI = youngs * np.pi * radius ** 4 / 4.0
+    sk = np.arange(1, n) * (L / n)
+    inp.gravity = np.array([0.0, 0.0, -g])
+    inp.muscle_amp = np.tile(curvature_amp * EI * np.sin(np.pi * sk / L), n_rods)
+    inp.muscle_axis = np.tile([1.0, 0.0, 0.0], (n_rods, 1))
+    inp.muscle_freq = np.full(n_rods, 1.0 / period)
+    inp.muscle_wavenumber = np.full(n_rods, 2.0 * np.pi / wavelength)
+    inp.muscle_phase = rng.uniform(0.0, 2.0 * np.pi, size=n_rods)
     return inp

@@ -131,3 +131,14 @@ def test_magnetic_descriptor_rejected_when_not_finite():
     assert "field_freq" in _expect(rod.ROD_EINVAL, bad)
     bad = base.copy(); bad.magnetization = base.magnetization.copy(); bad.magnetization[3, 1] = np.nan
     assert "magnetization" in _expect(rod.ROD_EINVAL, bad)
+
+
+def test_muscle_descriptor_rejected_when_incomplete_or_not_finite():
+    from paper_2605_13766_amd import rod
+    base = W.active_filaments(n_rods=3, n=8)
+    bad = base.copy(); bad.muscle_phase = None
+    assert "muscle_amp needs" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.muscle_amp = base.muscle_amp.copy(); bad.muscle_amp[2] = np.nan
+    assert "muscle" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.gravity = np.array([0.0, np.inf, 0.0])
+    assert "gravity" in _expect(rod.ROD_EINVAL, bad)
