@@ -15,8 +15,11 @@ namespace rodk {
 int set_error(int code, const std::string &msg);
 
 // Per-slot state fields.  A slot is one lane of a workgroup tile; slot s of a
-// rod holds its node s (r, v) and its element s (Q, omega).  The rod's last
-// node lives in the per-rod tail arrays.
+// rod holds its node s's position (FP64) or its element s's edge vector
+// r_{s+1} - r_s (FP32) in RX..RZ, its node s's velocity and its element s's
+// frame and angular velocity.  The per-rod tail arrays hold node n's position
+// (FP64) or node 0's position relative to the rod origin (FP32), and node n's
+// velocity.
 enum StateField {
     RX, RY, RZ, VX, VY, VZ,
     Q00, Q01, Q02, Q10, Q11, Q12, Q20, Q21, Q22,
@@ -26,7 +29,8 @@ enum StateField {
 
 // Per-slot constants, derived in FP64 on the host.  Node quantities belong to
 // the slot's node, element quantities to its element, Voronoi quantities to
-// the Voronoi point between the slot's element and the next one.
+// the Voronoi point between the previous element and the slot's element
+// (placeholders with zero stiffness on a rod's first slot).
 enum ParamField {
     P_INV_M,    // node: 1 / lumped mass
     P_LH,       // element: rest length
@@ -42,7 +46,8 @@ enum ParamField {
     N_PARAM
 };
 
-// Per-rod tail node (the rod's node n).
+// Per-rod tail: node n's position (FP64) or node 0's relative to the rod
+// origin (FP32, the anchor), and node n's velocity.
 enum TailField { TRX, TRY, TRZ, TVX, TVY, TVZ, N_TAIL };
 
 // Per-rod constants in the state precision.

@@ -210,23 +210,29 @@ __device__ inline bool finite3(T a, T b, T c)
 
 // One launch: n_sub position-Verlet substeps for every tile (grid-stride).
 //
-// FP64 keeps node positions.  FP32 keeps, per element, the edge vector
-// e_i = r_{i+1} - r_i and, per rod, the position of node 0 (the anchor): the
-// drift r_j += h/2 v_j becomes e_i += h/2 (v_{i+1} - v_i), anchor += h/2 v_0,
-// which is the same update in exact arithmetic but keeps the strains at
-// FP32 relative precision (absolute FP32 positions would round each drift
-// increment against the rod's whole length).
+// State per lane, in registers: the edge vector d_i = r_{i+1} - r_i, node i's
+// velocity, element i's frame and angular velocity; per rod, node 0's
+// position (the anchor, first lane) and node n's velocity (last lane).  The
+// drift r_j += h v_j becomes d_i += h (v_{i+1} - v_i), anchor += h v_0: the
+// same update in exact arithmetic, with the strains kept at the state
+// precision's relative accuracy.  FP32 batches keep this form in memory too
+// (absolute FP32 positions would round each drift increment against the rod's
+// whole length); FP64 batches keep node positions in memory, turned into edges
+// at the start of a launch and back, by a prefix sum along the rod, at its end.
+//
+// Voronoi point k (between elements k and k+1) belongs to lane k+1, so a
+// substep needs two neighbour exchanges, each one barrier in a multi-wave
+// tile: from the left, element i-1's frame, length and internal force (the
+// curvature, moment and y of Voronoi point i-1, and node i's force and kick);
+// from the right, Voronoi point i's moment and y and node i+1's kicked
+// velocity (element i's couple and kick, and the next drift).
 //
 // Inside a launch the closing half drift of one step and the opening half
 // drift of the next use the same velocities, so they run as one full drift
 // (exp(-h/2 W) exp(-h/2 W) = exp(-h W) for one axis): a launch of S steps is
 // half drift, S kicks separated by S-1 full drifts, half drift.
-// Waves per SIMD: at 3 (FP64, 168 VGPRs) and 5 (FP32, 96 VGPRs) the compiler
-// keeps the substep loop free of spill traffic (what it spills are the state
-// addresses used once after the loop); measured 8.57 ms vs 9.47 ms (FP64) and
-// 4.60 vs 4.82 ms (FP32) per 1000-step launch on the ragged 4096-rod batch
-// against 2 and 4 waves; 4 FP64 waves spill inside the loop and run 2.2x slower.
-// FP64 tiles of 8 waves stay at 2: their LDS (90 KB) admits one workgroup per CU.
+// Waves per SIMD: 3 (FP64, 168 VGPRs) and 5 (FP32, 96 VGPRs); FP64 tiles of 8
+// waves stay at 2: their LDS admits one workgroup per CU.
 #ifndef ROD_F64_WAVES_PER_SIMD
 #define ROD_F64_WAVES_PER_SIMD 3
 #endif
@@ -252,12 +258,14 @@ __global__ __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, EXT>())))
 void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
-    constexpr bool EDGE = sizeof(T) == 4;
+    constexpr bool POS = sizeof(T) == 8;   // node positions in memory
     constexpr int TL = 64 * W;
-    constexpr int NX1 = EDGE ? 9 : 15;     // from the right: Q (, r, v)
+    constexpr int NA = 13;     // from the left: frame (9), length, internal force (3)
+    constexpr int NB = 9;      // from the right: Voronoi moment (3), y (3), node velocity (3)
     constexpr int NL = W > 1 ? W : 1;
     // lane-private constants (each lane reads back only its own column, so no
-    // barrier is needed): a register extension for values used once a substep
+    // barrier is needed): a register extension for values used once a substep.
+    // The Voronoi quantities of a lane are those of the point on its left.
     enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
            C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3,
            C_MX, C_MY, C_MZ,     // magnetization times rest length (EXT only)
@@ -267,16 +275,14 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     // so their addresses fit the 8-bit offsets of ds_write2/ds_read2 and need no
     // per-access address arithmetic, then the constant columns.
     struct Shared {
-        T lx1[NL * NX1];           // wave-edge values of the four exchanges
-        T lx2[NL];
-        T lx3[NL * 9];
-        T lx4[NL * 3];
+        T lxa[NL * NA];            // wave-edge values of the two exchanges
+        T lxb[NL * NB];
         double phs[2 * TL];        // couple phase increment: sin, cos
         double mph[EXT ? 2 * TL : 1];   // muscle phase increment: sin, cos (EXT only)
         T cst[N_C * TL];
     };
     __shared__ Shared sh;
-    T *const lx1 = sh.lx1, *const lx2 = sh.lx2, *const lx3 = sh.lx3, *const lx4 = sh.lx4;
+    T *const lxa = sh.lxa, *const lxb = sh.lxb;
     T *const cst = sh.cst;
     double *const phs = sh.phs;
 
@@ -298,8 +304,8 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         const int n = valid ? B.rod_n[rr] : 1;
         const int flags = valid ? B.rod_flags[rr] : 0;
         const bool last = valid && (i == n - 1);
-        const bool hasv = valid && (i < n - 1);
         const bool first = i == 0;
+        const bool hasl = valid && i > 0;    // Voronoi point i-1 exists
         const bool fix0 = first && (flags & FLAG_CLAMP0);
         const bool fix1 = last && (flags & FLAG_CLAMP1);
         // rods switched off by the caller keep their state; a tile with none
@@ -312,29 +318,30 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         const T hw = (fix0 || fix1) ? T(0) : h;
         const T hu = fix1 ? T(0) : h;
 
-        // ---- state: r0..2 is node i's position (FP64) or element i's edge (FP32);
-        // t0..2 is node n's position (FP64, last lane) or node 0's (FP32, first lane)
+        // ---- state: d = edge i (FP64: node i's position until the first
+        // exchange), v = node i, t = anchor (first lane; FP64: node n's position
+        // on the last lane until the first exchange), u = node n (last lane)
         const T *st = B.state + s;
-        T r0 = st[RX * NS], r1 = st[RY * NS], r2 = st[RZ * NS];
+        T d0 = st[RX * NS], d1 = st[RY * NS], d2 = st[RZ * NS];
         T v0 = st[VX * NS], v1 = st[VY * NS], v2 = st[VZ * NS];
         T q[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) q[k] = st[(Q00 + k) * NS];
         T w0 = st[WX * NS], w1 = st[WY * NS], w2 = st[WZ * NS];
-        T t0 = 0, t1 = 0, t2 = 0, u0 = 0, u1 = 0, u2 = 0;   // tail position, node n velocity
-        if (EDGE ? (valid && first) : last) {
+        T t0 = 0, t1 = 0, t2 = 0, u0 = 0, u1 = 0, u2 = 0;
+        if (POS ? last : (valid && first)) {
             t0 = B.tail[TRX * B.n_rods + rr]; t1 = B.tail[TRY * B.n_rods + rr]; t2 = B.tail[TRZ * B.n_rods + rr];
         }
         if (last) {
             u0 = B.tail[TVX * B.n_rods + rr]; u1 = B.tail[TVY * B.n_rods + rr]; u2 = B.tail[TVZ * B.n_rods + rr];
         }
         // ---- constants: all in this lane's LDS column (registers hold the state
-        // and the substep's temporaries, which leaves room for three waves per SIMD)
+        // and the substep's temporaries)
         const T *pp = B.param + s;
-        const T lh = pp[P_LH * NS];
         double ps = 0.0, pc = 1.0;
         {
             T *cw = cst + lane;
+            const T lh = pp[P_LH * NS];
             cw[C_INV_M * TL] = pp[P_INV_M * NS];
             cw[C_LH * TL] = lh;
             cw[C_INV_LH * TL] = pp[P_INV_LH * NS];
@@ -345,9 +352,9 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             cw[C_INV_J1 * TL] = T(1) / J1;
             cw[C_DH * TL] = pp[P_DH * NS];
             cw[C_INV_DH * TL] = pp[P_INV_DH * NS];
-            // no Voronoi point on the last element: zero stiffness there
-            cw[C_B1 * TL] = hasv ? pp[P_B1 * NS] : T(0);
-            cw[C_B3 * TL] = hasv ? pp[P_B3 * NS] : T(0);
+            // no Voronoi point left of a rod's first element: zero stiffness there
+            cw[C_B1 * TL] = hasl ? pp[P_B1 * NS] : T(0);
+            cw[C_B3 * TL] = hasl ? pp[P_B3 * NS] : T(0);
             cw[C_K0X * TL] = pp[P_K0X * NS];
             cw[C_K0Y * TL] = pp[P_K0Y * NS];
             cw[C_K0Z * TL] = pp[P_K0Z * NS];
@@ -412,23 +419,27 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             sh.mph[TL + lane] = mdc;
         }
 
-        // edge form: velocity of node i+1 (refreshed after every kick)
-        T vn0 = 0, vn1 = 0, vn2 = 0;
-        if constexpr (EDGE) {
-            const T a4[3] = {v0, v1, v2};
-            T b4[3];
-            from_right<W>(a4, b4, lx4, wave, wl);
-            vn0 = last ? u0 : b4[0]; vn1 = last ? u1 : b4[1]; vn2 = last ? u2 : b4[2];
+        // velocity of node i+1 (refreshed by every kick's exchange)
+        T vn0, vn1, vn2;
+        if constexpr (POS) {
+            // and node i+1's position: edge i, with node i's position as the anchor
+            const T a0[6] = {v0, v1, v2, d0, d1, d2};
+            T b0[6];
+            from_right<W>(a0, b0, lxb, wave, wl);
+            vn0 = last ? u0 : b0[0]; vn1 = last ? u1 : b0[1]; vn2 = last ? u2 : b0[2];
+            const T rn0 = last ? t0 : b0[3], rn1 = last ? t1 : b0[4], rn2 = last ? t2 : b0[5];
+            t0 = d0; t1 = d1; t2 = d2;
+            d0 = rn0 - t0; d1 = rn1 - t1; d2 = rn2 - t2;
+        } else {
+            const T a0[3] = {v0, v1, v2};
+            T b0[3];
+            from_right<W>(a0, b0, lxb, wave, wl);
+            vn0 = last ? u0 : b0[0]; vn1 = last ? u1 : b0[1]; vn2 = last ? u2 : b0[2];
         }
 
         // ---- opening half drift (constraints hold: clamped v, omega are zero)
-        if constexpr (EDGE) {
-            r0 += hh * (vn0 - v0); r1 += hh * (vn1 - v1); r2 += hh * (vn2 - v2);
-            t0 += hh * v0; t1 += hh * v1; t2 += hh * v2;
-        } else {
-            r0 += hh * v0; r1 += hh * v1; r2 += hh * v2;
-            t0 += hh * u0; t1 += hh * u1; t2 += hh * u2;
-        }
+        d0 += hh * (vn0 - v0); d1 += hh * (vn1 - v1); d2 += hh * (vn2 - v2);
+        t0 += hh * v0; t1 += hh * v1; t2 += hh * v2;
         rotate_left(q, -hh * w0, -hh * w1, -hh * w2);
 
         for (int sub = 0; sub < n_sub; ++sub) {
@@ -439,30 +450,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T *cl = cst + cofs;
             const double *phl = phs + cofs;
 
-            // ---- exchange 1: neighbour element (and node)
-            T a1[NX1], qn[NX1];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) a1[k] = q[k];
-            if constexpr (!EDGE) {
-                a1[9] = r0; a1[10] = r1; a1[11] = r2;
-                a1[12] = v0; a1[13] = v1; a1[14] = v2;
-            }
-            from_right<W>(a1, qn, lx1, wave, wl);
-            // curvature at Voronoi point i first: the neighbour frame dies here
-            // (zero stiffness on lanes without a Voronoi point)
-            T k0, k1, k2;
-            log_relative(q, qn, hasv, k0, k1, k2);
-            T d0, d1, d2;
-            if constexpr (EDGE) {
-                d0 = r0; d1 = r1; d2 = r2;
-            } else {
-                d0 = (last ? t0 : qn[9]) - r0;
-                d1 = (last ? t1 : qn[10]) - r1;
-                d2 = (last ? t2 : qn[11]) - r2;
-                vn0 = last ? u0 : qn[12]; vn1 = last ? u1 : qn[13]; vn2 = last ? u2 : qn[14];
-            }
-
-            // ---- kinematics and shear/stretch strain of element i
+            // ---- kinematics, shear/stretch strain and internal force of element i
             const T lh = cl[C_LH * TL], inv_lh = cl[C_INV_LH * TL];
             const T S1 = cl[C_S1 * TL], S3 = cl[C_S3 * TL];
             const T l2 = d0 * d0 + d1 * d1 + d2 * d2;
@@ -471,7 +459,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T e = l * inv_lh;
             const T inv_e = lh * inv_l;
             const T edot = ((d0 * (vn0 - v0) + d1 * (vn1 - v1) + d2 * (vn2 - v2)) * inv_l) * inv_lh;
-            // sigma = Q dr / lh - e3
+            // sigma = Q d / lh - e3
             const T sg0 = (q[0] * d0 + q[1] * d1 + q[2] * d2) * inv_lh;
             const T sg1 = (q[3] * d0 + q[4] * d1 + q[5] * d2) * inv_lh;
             const T sg2 = (q[6] * d0 + q[7] * d1 + q[8] * d2) * inv_lh - T(1);
@@ -481,64 +469,82 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T nf1 = (q[1] * ss0 + q[4] * ss1 + q[7] * ss2) * inv_e;
             const T nf2 = (q[2] * ss0 + q[5] * ss1 + q[8] * ss2) * inv_e;
 
-            // ---- exchange 2: neighbour length
-            const T a2[1] = {l};
-            T b2[1];
-            from_right<W>(a2, b2, lx2, wave, wl);
-            const T ln = hasv ? b2[0] : l;
-
-            // ---- bending/twisting moment at Voronoi point i
-            const T inv_Dh = cl[C_INV_DH * TL], Dh = cl[C_DH * TL];
-            k0 *= inv_Dh; k1 *= inv_Dh; k2 *= inv_Dh;
-            const T eps = (l + ln) * (T(0.5) * inv_Dh);
-            const T ie3 = rcp_t(eps * eps * eps);
-            T M0 = cl[C_B1 * TL] * (k0 - cl[C_K0X * TL]) * ie3;
-            T M1 = cl[C_B1 * TL] * (k1 - cl[C_K0Y * TL]) * ie3;
-            T M2 = cl[C_B3 * TL] * (k2 - cl[C_K0Z * TL]) * ie3;
-            if constexpr (EXT) {
-                // active muscle moment, part of the internal moment
-                const T sa = T(ms);
-                M0 += cl[C_AX * TL] * sa;
-                M1 += cl[C_AY * TL] * sa;
-                M2 += cl[C_AZ * TL] * sa;
+            // ---- exchange A: element i-1's frame, length and internal force.
+            // A rod's first lane sits next to the previous rod's last lane or
+            // at the tile edge (zeros): its Voronoi stiffness is zero and its
+            // left force is masked.
+            T M0, M1, M2, y0, y1, y2, np0, np1, np2;
+            {
+                const T aa[NA] = {q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], l, nf0, nf1, nf2};
+                T ba[NA];
+                from_left<W>(aa, ba, lxa, wave, wl);
+                // curvature of Voronoi point i-1: log(Q_{i-1} Q_i^T) / Dh
+                T k0, k1, k2;
+                log_relative(ba, q, hasl, k0, k1, k2);
+                const T inv_Dh = cl[C_INV_DH * TL], Dh = cl[C_DH * TL];
+                k0 *= inv_Dh; k1 *= inv_Dh; k2 *= inv_Dh;
+                const T eps = (ba[9] + l) * (T(0.5) * inv_Dh);
+                const T ie3 = rcp_t(eps * eps * eps);
+                M0 = cl[C_B1 * TL] * (k0 - cl[C_K0X * TL]) * ie3;
+                M1 = cl[C_B1 * TL] * (k1 - cl[C_K0Y * TL]) * ie3;
+                M2 = cl[C_B3 * TL] * (k2 - cl[C_K0Z * TL]) * ie3;
+                if constexpr (EXT) {
+                    // active muscle moment, part of the internal moment
+                    const T sa = T(ms);
+                    M0 += cl[C_AX * TL] * sa;
+                    M1 += cl[C_AY * TL] * sa;
+                    M2 += cl[C_AZ * TL] * sa;
+                }
+                y0 = (k1 * M2 - k2 * M1) * Dh;
+                y1 = (k2 * M0 - k0 * M2) * Dh;
+                y2 = (k0 * M1 - k1 * M0) * Dh;
+                np0 = first ? T(0) : ba[10];
+                np1 = first ? T(0) : ba[11];
+                np2 = first ? T(0) : ba[12];
             }
-            const T y0 = (k1 * M2 - k2 * M1) * Dh;
-            const T y1 = (k2 * M0 - k0 * M2) * Dh;
-            const T y2 = (k0 * M1 - k1 * M0) * Dh;
 
-            // ---- exchange 3: left neighbour's force and moments.  A rod's
-            // first lane sits next to the previous rod's last lane, whose
-            // moments vanish, or at the wave edge (zero); only its force is
-            // masked.
-            const T a3[9] = {nf0, nf1, nf2, M0, M1, M2, y0, y1, y2};
-            T b3[9];
-            from_left<W>(a3, b3, lx3, wave, wl);
-            const T np0 = first ? T(0) : b3[0], np1 = first ? T(0) : b3[1], np2 = first ? T(0) : b3[2];
-
-            // ---- Eq. 1a at node i (and node n on the last lane)
+            // ---- Eq. 1a at node i (and node n on the last lane); kick
             const T gamma = cl[C_GAMMA * TL];
-            const T inv_m = cl[C_INV_M * TL];
-            T a0 = (nf0 - np0) * inv_m - gamma * v0;
-            T a1x = (nf1 - np1) * inv_m - gamma * v1;
-            T a2x = (nf2 - np2) * inv_m - gamma * v2;
-            if constexpr (EXT) {
-                a0 += B.grav[0];
-                a1x += B.grav[1];
-                a2x += B.grav[2];
+            {
+                const T inv_m = cl[C_INV_M * TL];
+                T a0 = (nf0 - np0) * inv_m - gamma * v0;
+                T a1 = (nf1 - np1) * inv_m - gamma * v1;
+                T a2 = (nf2 - np2) * inv_m - gamma * v2;
+                const T inv_mt = cl[C_INV_MT * TL];
+                T b0 = (cl[C_FX * TL] - nf0) * inv_mt - gamma * u0;
+                T b1 = (cl[C_FY * TL] - nf1) * inv_mt - gamma * u1;
+                T b2 = (cl[C_FZ * TL] - nf2) * inv_mt - gamma * u2;
+                if constexpr (EXT) {
+                    a0 += B.grav[0]; a1 += B.grav[1]; a2 += B.grav[2];
+                    b0 += B.grav[0]; b1 += B.grav[1]; b2 += B.grav[2];
+                }
+                v0 += hv * a0; v1 += hv * a1; v2 += hv * a2;
+                u0 += hu * b0; u1 += hu * b1; u2 += hu * b2;
             }
 
-            // ---- Eq. 1b at element i
+            // ---- exchange B: Voronoi point i's moment and y, node i+1's kicked velocity
+            T mr0, mr1, mr2, yr0, yr1, yr2;
+            {
+                const T ab[NB] = {M0, M1, M2, y0, y1, y2, v0, v1, v2};
+                T bb[NB];
+                from_right<W>(ab, bb, lxb, wave, wl);
+                mr0 = bb[0]; mr1 = bb[1]; mr2 = bb[2];
+                yr0 = bb[3]; yr1 = bb[4]; yr2 = bb[5];
+                vn0 = last ? u0 : bb[6]; vn1 = last ? u1 : bb[7]; vn2 = last ? u2 : bb[8];
+            }
+
+            // ---- Eq. 1b at element i (pre-kick omega, e and edot)
             // Q t = (sigma + e3) / e
             const T qt0 = sg0 * inv_e, qt1 = sg1 * inv_e, qt2 = (sg2 + T(1)) * inv_e;
             const T J1 = cl[C_J1 * TL];
             const T jw0 = J1 * w0 * inv_e, jw1 = J1 * w1 * inv_e, jw2 = T(2) * J1 * w2 * inv_e;
             const T ede = edot * inv_e;
             const T cs = T(ps);
-            const T tq0 = (M0 - b3[3]) + T(0.5) * (b3[6] + y0) + (qt1 * ss2 - qt2 * ss1) * lh
+            const T tq0 = (mr0 - M0) + T(0.5) * (y0 + yr0) + (qt1 * ss2 - qt2 * ss1) * lh
                         + (jw1 * w2 - jw2 * w1) + jw0 * ede + cl[C_CX * TL] * cs;
-            const T tq1 = (M1 - b3[4]) + T(0.5) * (b3[7] + y1) + (qt2 * ss0 - qt0 * ss2) * lh
+            const T tq1 = (mr1 - M1) + T(0.5) * (y1 + yr1) + (qt2 * ss0 - qt0 * ss2) * lh
                         + (jw2 * w0 - jw0 * w2) + jw1 * ede + cl[C_CY * TL] * cs;
-            const T tq2 = (M2 - b3[5]) + T(0.5) * (b3[8] + y2) + (qt0 * ss1 - qt1 * ss0) * lh
+            const T tq2 = (mr2 - M2) + T(0.5) * (y2 + yr2) + (qt0 * ss1 - qt1 * ss0) * lh
                         + (jw0 * w1 - jw1 * w0) + jw2 * ede + cl[C_CZ * TL] * cs;
             T mc0 = 0, mc1 = 0, mc2 = 0;
             if constexpr (EXT) {
@@ -559,42 +565,12 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T al0 = eJ * (tq0 + mc0) - gamma * w0;
             const T al1 = eJ * (tq1 + mc1) - gamma * w1;
             const T al2 = T(0.5) * eJ * (tq2 + mc2) - gamma * w2;
-
-            // ---- kick (clamped nodes/elements have zero kick factors)
-            v0 += hv * a0; v1 += hv * a1x; v2 += hv * a2x;
             w0 += hw * al0; w1 += hw * al1; w2 += hw * al2;
-            {
-                const T inv_mt = cl[C_INV_MT * TL];
-                T b0 = (cl[C_FX * TL] - nf0) * inv_mt - gamma * u0;
-                T b1 = (cl[C_FY * TL] - nf1) * inv_mt - gamma * u1;
-                T b2 = (cl[C_FZ * TL] - nf2) * inv_mt - gamma * u2;
-                if constexpr (EXT) {
-                    b0 += B.grav[0];
-                    b1 += B.grav[1];
-                    b2 += B.grav[2];
-                }
-                u0 += hu * b0;
-                u1 += hu * b1;
-                u2 += hu * b2;
-            }
-
-            // ---- edge form: exchange 4, the post-kick velocity of node i+1
-            if constexpr (EDGE) {
-                const T a4[3] = {v0, v1, v2};
-                T b4[3];
-                from_right<W>(a4, b4, lx4, wave, wl);
-                vn0 = last ? u0 : b4[0]; vn1 = last ? u1 : b4[1]; vn2 = last ? u2 : b4[2];
-            }
 
             // ---- drift: full between two kicks of this launch, half after the last
             const T dd = sub + 1 < n_sub ? h : hh;
-            if constexpr (EDGE) {
-                r0 += dd * (vn0 - v0); r1 += dd * (vn1 - v1); r2 += dd * (vn2 - v2);
-                t0 += dd * v0; t1 += dd * v1; t2 += dd * v2;
-            } else {
-                r0 += dd * v0; r1 += dd * v1; r2 += dd * v2;
-                t0 += dd * u0; t1 += dd * u1; t2 += dd * u2;
-            }
+            d0 += dd * (vn0 - v0); d1 += dd * (vn1 - v1); d2 += dd * (vn2 - v2);
+            t0 += dd * v0; t1 += dd * v1; t2 += dd * v2;
             rotate_left(q, -dd * w0, -dd * w1, -dd * w2);
 
             // advance the couple's phase by one step
@@ -615,20 +591,43 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             }
         }
 
+        if constexpr (POS) {
+            // node positions from the edges, r_i = anchor + d_0 + ... + d_{i-1}:
+            // a prefix sum along the rod (Kogge-Stone over the tile's lanes in
+            // LDS, restarted at each rod's first lane; its additions depend only
+            // on the element index, so every tile width gives the same bits).
+            // Afterwards d holds node i's position and t node n's (last lane).
+            const T e3[3] = {d0, d1, d2};
+            T lf[3];
+            from_left<W>(e3, lf, lxa, wave, wl);
+            T p0 = first ? t0 : lf[0], p1 = first ? t1 : lf[1], p2 = first ? t2 : lf[2];
+            T *const sc = cst;   // the constant columns are not read any more
+            for (int k = 1; k < TL; k <<= 1) {
+                __syncthreads();
+                sc[lane] = p0; sc[TL + lane] = p1; sc[2 * TL + lane] = p2;
+                __syncthreads();
+                if (i >= k) {
+                    p0 += sc[lane - k]; p1 += sc[TL + lane - k]; p2 += sc[2 * TL + lane - k];
+                }
+            }
+            t0 = p0 + d0; t1 = p1 + d1; t2 = p2 + d2;
+            d0 = p0; d1 = p1; d2 = p2;
+        }
+
         if (act) {
             // an opaque slot index: the store addresses are recomputed here rather
             // than kept (and spilled) across the substep loop
             int64_t s_out = s;
             asm volatile("" : "+v"(s_out));
             T *so = B.state + s_out;
-            so[RX * NS] = r0; so[RY * NS] = r1; so[RZ * NS] = r2;
+            so[RX * NS] = d0; so[RY * NS] = d1; so[RZ * NS] = d2;
             so[VX * NS] = v0; so[VY * NS] = v1; so[VZ * NS] = v2;
 #pragma unroll
             for (int k = 0; k < 9; ++k) so[(Q00 + k) * NS] = q[k];
             so[WX * NS] = w0; so[WY * NS] = w1; so[WZ * NS] = w2;
-            bool ok = finite3(r0, r1, r2) && finite3(v0, v1, v2) && finite3(w0, w1, w2)
+            bool ok = finite3(d0, d1, d2) && finite3(v0, v1, v2) && finite3(w0, w1, w2)
                     && finite3(q[0], q[1], q[2]) && finite3(q[3], q[4], q[5]) && finite3(q[6], q[7], q[8]);
-            if (EDGE ? first : last) {
+            if (POS ? last : first) {
                 B.tail[TRX * B.n_rods + rr] = t0; B.tail[TRY * B.n_rods + rr] = t1; B.tail[TRZ * B.n_rods + rr] = t2;
                 ok = ok && finite3(t0, t1, t2);
             }
@@ -711,7 +710,7 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
         const double sg2 = (q[6] * d0 + q[7] * d1 + q[8] * d2) / lh - 1.0;
         Us += 0.5 * (P(P_S1, s) * (sg0 * sg0 + sg1 * sg1) + P(P_S3, s) * sg2 * sg2) * lh;
         if (i > 0) {
-            const int64_t sv = s - 1;   // Voronoi point i-1 lives on slot i-1
+            const int64_t sv = s;       // Voronoi point i-1 lives on slot i
             double k0, k1, k2;
             log_relative(qprev, q, true, k0, k1, k2);
             const double iD = P(P_INV_DH, sv);
@@ -721,7 +720,7 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
             Ub += 0.5 * (P(P_B1, sv) * (k0 * k0 + k1 * k1) + P(P_B3, sv) * k2 * k2) * P(P_DH, sv);
         }
         for (int k = 0; k < 9; ++k) qprev[k] = q[k];
-        if (EDGE) { tr0 += d0; tr1 += d1; tr2 += d2; }   // anchor + edges -> node n
+        if (EDGE) { tr0 += d0; tr1 += d1; tr2 += d2; }   // anchor + edges -> node i+1
     }
     Tl += 0.5 / RP(R_INV_M_TAIL) * (tv0 * tv0 + tv1 * tv1 + tv2 * tv2);
     double Wx = -(RP(R_FX) * (tr0 - RP(R_T0X)) + RP(R_FY) * (tr1 - RP(R_T0Y)) + RP(R_FZ) * (tr2 - RP(R_T0Z)));

@@ -379,8 +379,8 @@ void pack_state(const rod_batch *b, const double *pos, const double *vel, const 
     state.assign((size_t)rodk::N_STATE * NS, T(0));
     tail.assign((size_t)rodk::N_TAIL * R, T(0));
     // padding lanes: identity frames and unit-length elements (positions one
-    // apart along z, or unit edges), so they stay finite and at rest and never
-    // feed NaN/Inf to a neighbouring rod through the lane exchanges
+    // apart along z, or unit edges), so they stay finite and never feed
+    // NaN/Inf to a neighbouring rod through the lane exchanges
     const int TL = 64 * b->waves;
     for (int64_t s = 0; s < NS; ++s) {
         state[rodk::Q00 * NS + s] = T(1);
@@ -464,19 +464,21 @@ int build_device(rod_batch *b, const HostInputs &h)
             param[rodk::P_J1 * NS + s] = T(h.rho[r] * I * lh[i]);
             param[rodk::P_S1 * NS + s] = T(S1);
             param[rodk::P_S3 * NS + s] = T(S3);
-            if (i + 1 == n) {
-                // no Voronoi point here: finite placeholders (its stiffness is zero)
-                param[rodk::P_DH * NS + s] = T(lh[i]);
-                param[rodk::P_INV_DH * NS + s] = T(1.0 / lh[i]);
+            if (i == 0) {
+                // no Voronoi point left of the first element: finite placeholders
+                // (its stiffness is zero)
+                param[rodk::P_DH * NS + s] = T(lh[0]);
+                param[rodk::P_INV_DH * NS + s] = T(1.0 / lh[0]);
             } else {
-                const double Dh = 0.5 * (lh[i] + lh[i + 1]);
+                // Voronoi point i-1, between elements i-1 and i, lives on slot i;
                 // rest-length weighted stiffness of the two elements (equal material here)
+                const double Dh = 0.5 * (lh[i - 1] + lh[i]);
                 param[rodk::P_DH * NS + s] = T(Dh);
                 param[rodk::P_INV_DH * NS + s] = T(1.0 / Dh);
-                param[rodk::P_B1 * NS + s] = T((B1 * lh[i] + B1 * lh[i + 1]) / (lh[i] + lh[i + 1]));
-                param[rodk::P_B3 * NS + s] = T((B3 * lh[i] + B3 * lh[i + 1]) / (lh[i] + lh[i + 1]));
+                param[rodk::P_B1 * NS + s] = T((B1 * lh[i - 1] + B1 * lh[i]) / (lh[i - 1] + lh[i]));
+                param[rodk::P_B3 * NS + s] = T((B3 * lh[i - 1] + B3 * lh[i]) / (lh[i - 1] + lh[i]));
                 if (h.has_k0)
-                    for (int a = 0; a < 3; ++a) param[(rodk::P_K0X + a) * NS + s] = T(h.k0[3 * (v + i) + a]);
+                    for (int a = 0; a < 3; ++a) param[(rodk::P_K0X + a) * NS + s] = T(h.k0[3 * (v + i - 1) + a]);
             }
         }
         const double mt = 0.5 * h.rho[r] * A * lh[n - 1];
@@ -551,7 +553,7 @@ int build_device(rod_batch *b, const HostInputs &h)
     }
     if (b->muscle) {
         // amplitude times axis and the phase offset phi - q s_k at the Voronoi
-        // point of each slot (zero amplitude on a rod's last element and padding)
+        // point of each slot (zero amplitude on a rod's first element and padding)
         std::vector<T> mus((size_t)3 * NS, T(0));
         std::vector<double> ofs((size_t)NS, 0.0);
         int64_t ee = 0, vv = 0;
@@ -559,7 +561,7 @@ int build_device(rod_batch *b, const HostInputs &h)
             double sk = 0.0;
             for (int i = 0; i + 1 < h.n[r]; ++i) {
                 sk += h.lh[ee + i];
-                const int64_t sl = b->rod_slot[r] + i;
+                const int64_t sl = b->rod_slot[r] + i + 1;   // Voronoi point i lives on slot i+1
                 for (int a = 0; a < 3; ++a) mus[a * NS + sl] = T(h.mamp[vv + i] * h.maxis[3 * r + a]);
                 ofs[sl] = h.mphase[r] - h.mwave[r] * sk;
             }
