@@ -156,7 +156,7 @@ def time_magnetic(steps, warmup, tile_waves=0, substeps=0):
     }
 
 
-def time_active(steps, warmup, tile_waves=0, substeps=0):
+def time_active(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32")):
     """Active filaments (16,384 free rods x 50 elements under gravity, driven by
     travelling muscle waves, dt 5e-5 s), both precisions, autotuned."""
     from paper_2605_13766_amd import workloads as W
@@ -164,7 +164,7 @@ def time_active(steps, warmup, tile_waves=0, substeps=0):
     out = {"workload": "active_filaments: 16,384 free rods x 50 elements, 1 m, gravity, travelling muscle "
                        f"moments (1 s period, wavelength 1 m), dt 5e-5 s, {STEPS_PER_LAUNCH} steps per launch",
            "unit": "element-steps/s"}
-    for p in ("f64", "f32"):
+    for p in precisions:
         r = time_gpu(inp, p, steps, warmup, tile_waves, substeps, algo_flop=ALGO_FLOP_ACTIVE,
                      extra_bytes=MUSCLE_BYTES[p], traffic_tag=f"{p}_active16384")
         out[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms": r["launch_ms"],
@@ -328,6 +328,8 @@ def main(argv=None):
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-magnetic", action="store_true")
     ap.add_argument("--no-active", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the headline batch (profiling runs of the other workloads; value is then null)")
     ap.add_argument("--tile-waves", type=int, default=0, help="fix the tile width (0: autotune)")
     ap.add_argument("--substeps", type=int, default=0, help="fix the substeps per launch (0: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -356,10 +358,16 @@ def main(argv=None):
     inp = W.ragged_batch(n_rods=4096)
     precs = args.precisions.split(",")
     res = {}
-    for p in precs:
+    for p in precs if not args.no_ragged else ():
         print(f"timing {p}", file=sys.stderr, flush=True)
         res[p] = time_gpu(inp, p, args.steps, args.warmup, args.tile_waves, args.substeps)
-    head = res[precs[0]]
+    if args.no_ragged:
+        head = {"value": None, "ms_per_step": None, "info": {"tile_waves": None, "substeps": None, "n_tiles": None,
+                                                              "tuning": []},
+                "roofline": None, "launch_ms": None}
+        precs = precs[:1]
+    else:
+        head = res[precs[0]]
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -397,7 +405,8 @@ def main(argv=None):
         line["magnetic"] = time_magnetic(args.steps, args.warmup, args.tile_waves, args.substeps)
     if not args.no_active:
         print("timing the active filaments", file=sys.stderr, flush=True)
-        line["active"] = time_active(args.steps, args.warmup, args.tile_waves, args.substeps)
+        line["active"] = time_active(args.steps, args.warmup, args.tile_waves, args.substeps,
+                                     precisions=args.precisions.split(","))
     if not args.no_cpu_baseline:
         print("timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inp)

@@ -318,25 +318,9 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         const T hw = (fix0 || fix1) ? T(0) : h;
         const T hu = fix1 ? T(0) : h;
 
-        // ---- state: d = edge i (FP64: node i's position until the first
-        // exchange), v = node i, t = anchor (first lane; FP64: node n's position
-        // on the last lane until the first exchange), u = node n (last lane)
-        const T *st = B.state + s;
-        T d0 = st[RX * NS], d1 = st[RY * NS], d2 = st[RZ * NS];
-        T v0 = st[VX * NS], v1 = st[VY * NS], v2 = st[VZ * NS];
-        T q[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) q[k] = st[(Q00 + k) * NS];
-        T w0 = st[WX * NS], w1 = st[WY * NS], w2 = st[WZ * NS];
-        T t0 = 0, t1 = 0, t2 = 0, u0 = 0, u1 = 0, u2 = 0;
-        if (POS ? last : (valid && first)) {
-            t0 = B.tail[TRX * B.n_rods + rr]; t1 = B.tail[TRY * B.n_rods + rr]; t2 = B.tail[TRZ * B.n_rods + rr];
-        }
-        if (last) {
-            u0 = B.tail[TVX * B.n_rods + rr]; u1 = B.tail[TVY * B.n_rods + rr]; u2 = B.tail[TVZ * B.n_rods + rr];
-        }
         // ---- constants: all in this lane's LDS column (registers hold the state
-        // and the substep's temporaries)
+        // and the substep's temporaries); set up before the state is loaded, so
+        // the phase computations have the registers to themselves
         const T *pp = B.param + s;
         double ps = 0.0, pc = 1.0;
         {
@@ -419,6 +403,23 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             sh.mph[TL + lane] = mdc;
         }
 
+        // ---- state: d = edge i (FP64: node i's position until the first
+        // exchange), v = node i, t = anchor (first lane; FP64: node n's position
+        // on the last lane until the first exchange), u = node n (last lane)
+        const T *st = B.state + s;
+        T d0 = st[RX * NS], d1 = st[RY * NS], d2 = st[RZ * NS];
+        T v0 = st[VX * NS], v1 = st[VY * NS], v2 = st[VZ * NS];
+        T q[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) q[k] = st[(Q00 + k) * NS];
+        T w0 = st[WX * NS], w1 = st[WY * NS], w2 = st[WZ * NS];
+        T t0 = 0, t1 = 0, t2 = 0, u0 = 0, u1 = 0, u2 = 0;
+        if (POS ? last : (valid && first)) {
+            t0 = B.tail[TRX * B.n_rods + rr]; t1 = B.tail[TRY * B.n_rods + rr]; t2 = B.tail[TRZ * B.n_rods + rr];
+        }
+        if (last) {
+            u0 = B.tail[TVX * B.n_rods + rr]; u1 = B.tail[TVY * B.n_rods + rr]; u2 = B.tail[TVZ * B.n_rods + rr];
+        }
         // velocity of node i+1 (refreshed by every kick's exchange)
         T vn0, vn1, vn2;
         if constexpr (POS) {
@@ -591,6 +592,17 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             }
         }
 
+        // per-slot facts re-read through an opaque slot index instead of being
+        // kept (and spilled) across the substep loop
+        int64_t s_out = s;
+        asm volatile("" : "+v"(s_out));
+        const int rod_o = B.slot_rod[s_out];
+        const bool valid_o = rod_o >= 0;
+        const int rr_o = valid_o ? rod_o : 0;
+        const int i_o = B.slot_idx[s_out];
+        const bool first_o = i_o == 0;
+        const bool last_o = valid_o && i_o == B.rod_n[rr_o] - 1;
+        const bool act_o = valid_o && (!B.active || B.active[rr_o]);
         if constexpr (POS) {
             // node positions from the edges, r_i = anchor + d_0 + ... + d_{i-1}:
             // a prefix sum along the rod (Kogge-Stone over the tile's lanes in
@@ -600,13 +612,13 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T e3[3] = {d0, d1, d2};
             T lf[3];
             from_left<W>(e3, lf, lxa, wave, wl);
-            T p0 = first ? t0 : lf[0], p1 = first ? t1 : lf[1], p2 = first ? t2 : lf[2];
+            T p0 = first_o ? t0 : lf[0], p1 = first_o ? t1 : lf[1], p2 = first_o ? t2 : lf[2];
             T *const sc = cst;   // the constant columns are not read any more
             for (int k = 1; k < TL; k <<= 1) {
                 __syncthreads();
                 sc[lane] = p0; sc[TL + lane] = p1; sc[2 * TL + lane] = p2;
                 __syncthreads();
-                if (i >= k) {
+                if (i_o >= k) {
                     p0 += sc[lane - k]; p1 += sc[TL + lane - k]; p2 += sc[2 * TL + lane - k];
                 }
             }
@@ -614,11 +626,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             d0 = p0; d1 = p1; d2 = p2;
         }
 
-        if (act) {
-            // an opaque slot index: the store addresses are recomputed here rather
-            // than kept (and spilled) across the substep loop
-            int64_t s_out = s;
-            asm volatile("" : "+v"(s_out));
+        if (act_o) {
             T *so = B.state + s_out;
             so[RX * NS] = d0; so[RY * NS] = d1; so[RZ * NS] = d2;
             so[VX * NS] = v0; so[VY * NS] = v1; so[VZ * NS] = v2;
@@ -627,15 +635,15 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             so[WX * NS] = w0; so[WY * NS] = w1; so[WZ * NS] = w2;
             bool ok = finite3(d0, d1, d2) && finite3(v0, v1, v2) && finite3(w0, w1, w2)
                     && finite3(q[0], q[1], q[2]) && finite3(q[3], q[4], q[5]) && finite3(q[6], q[7], q[8]);
-            if (POS ? last : first) {
-                B.tail[TRX * B.n_rods + rr] = t0; B.tail[TRY * B.n_rods + rr] = t1; B.tail[TRZ * B.n_rods + rr] = t2;
+            if (POS ? last_o : first_o) {
+                B.tail[TRX * B.n_rods + rr_o] = t0; B.tail[TRY * B.n_rods + rr_o] = t1; B.tail[TRZ * B.n_rods + rr_o] = t2;
                 ok = ok && finite3(t0, t1, t2);
             }
-            if (last) {
-                B.tail[TVX * B.n_rods + rr] = u0; B.tail[TVY * B.n_rods + rr] = u1; B.tail[TVZ * B.n_rods + rr] = u2;
+            if (last_o) {
+                B.tail[TVX * B.n_rods + rr_o] = u0; B.tail[TVY * B.n_rods + rr_o] = u1; B.tail[TVZ * B.n_rods + rr_o] = u2;
                 ok = ok && finite3(u0, u1, u2);
             }
-            if (!ok) B.nonfinite[rr] = 1;
+            if (!ok) B.nonfinite[rr_o] = 1;
         }
         if constexpr (W > 1) __syncthreads();   // LDS reuse by the next tile
     }
