@@ -71,18 +71,19 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(tag: str):
+def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None).  tag: f64_ragged4096,
-    f32_ragged4096 or f32_magnetic65536."""
-    path = os.path.join(ROOT, "profiles", f"rod_step_{tag}_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    if d.get("kernel_sha256_16") != kernel_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
+    taken on the current kernel source in the same launch shape (else None).
+    tag: f64_ragged4096, f32_ragged4096, f32_magnetic65536, f64_active16384 or
+    f32_active16384."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"rod_step_{tag}*_traffic.json"))):
+        with open(path) as f:
+            d = json.load(f)
+        if (d.get("kernel_sha256_16") == kernel_hash()
+                and (d.get("tile_waves"), d.get("substeps")) == (tile_waves, substeps)):
+            return d.get("hbm_bytes_per_launch")
+    return None
 
 
 def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=ALGO_FLOP, extra_bytes=0,
@@ -117,7 +118,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
     el_steps = inp.n_elements * STEPS_PER_LAUNCH
     value = el_steps * steps / wall
     achieved = algo_flop * el_steps / (launch_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(traffic_tag or f"{precision}_ragged4096")
+    traffic = traffic_from_profile(traffic_tag or f"{precision}_ragged4096", info["tile_waves"], info["substeps"])
     return {
         "value": value,
         "ms_per_step": wall / steps * 1e3,
