@@ -53,7 +53,15 @@
  *     torques): an active moment beta_k sin(2 pi f t - q s_k + phi) axis at
  *     Voronoi point k, s_k its rest arc length from the first node, added to
  *     the internal moment B kappa / e^3 (so it enters both the difference
- *     and the kappa x M terms), evaluated at the kick time.
+ *     and the kappa x M terms), evaluated at the kick time;
+ *   - connections (Results, "Magnetized filament assemblies": components joined
+ *     point-wise and by distributed lateral connections): a central
+ *     spring-dashpot between two nodes, force on the first
+ *     [k (l - l0) + c dl/dt] (x_b - x_a)/l, the opposite on the second,
+ *     with pre-kick velocities; its potential 1/2 k (l - l0)^2 is split evenly
+ *     between the two rods' W_ext.
+ * Rods joined by connections are advanced together (one batch step), the
+ * connection forces from the state of all rods at the kick time.
  */
 #include <math.h>
 #include <stdint.h>
@@ -94,6 +102,11 @@ typedef struct {
     const double *muscle_freq;       /* [R] Hz */
     const double *muscle_wavenumber; /* [R] rad/m */
     const double *muscle_phase;      /* [R] rad */
+    int32_t n_conn;                  /* node-pair connections */
+    const int32_t *conn_node;        /* [C][2] global node indices (rows of the node arrays) */
+    const double *conn_k;            /* [C] spring stiffness (N/m) */
+    const double *conn_c;            /* [C] dashpot coefficient (N s/m) */
+    const double *conn_rest;         /* [C] rest distance (m) */
 } orc_rods;
 
 /* ---------------------------------------------------------------- vectors */
@@ -195,6 +208,7 @@ typedef struct {
     const double *field;         /* [9] */
     double field_freq;
     const double *grav;          /* [3] */
+    const double *fconn;         /* [n+1][3] or NULL: connection forces at this kick */
     const double *mamp;          /* [n-1] or NULL */
     const double *maxis;         /* [3] */
     double mfreq, mwave, mphase;
@@ -224,6 +238,7 @@ static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int6
     v->field = p->field;
     v->field_freq = p->field_freq;
     v->grav = p->gravity;
+    v->fconn = NULL;
     v->mamp = p->muscle_amp ? p->muscle_amp + vo : NULL;
     v->maxis = p->muscle_amp ? p->muscle_axis + 3 * r : NULL;
     v->mfreq = p->muscle_amp ? p->muscle_freq[r] : 0.0;
@@ -365,6 +380,7 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
             if (j < n) F += w->nint[3 * j + a];
             if (j > 0) F -= w->nint[3 * (j - 1) + a];
             if (rv->fext) F += rv->fext[3 * j + a];
+            if (rv->fconn) F += rv->fconn[3 * j + a];
             F += mass * rv->grav[a];
             acc[3 * j + a] = F / mass - rv->gamma * v[3 * j + a];
         }
@@ -506,6 +522,78 @@ static void offsets(const orc_rods *p, int64_t *eo, int64_t *no, int64_t *vo)
     }
 }
 
+/* Connection forces at the current state: fc [N_n][3] (zeroed here). */
+static void conn_forces(const orc_rods *p, const double *pos, const double *vel, double *fc, int64_t Nn)
+{
+    memset(fc, 0, 3 * (size_t)Nn * sizeof(double));
+    for (int32_t c = 0; c < p->n_conn; ++c) {
+        const int64_t a = p->conn_node[2 * c], b = p->conn_node[2 * c + 1];
+        double d[3], dv[3];
+        for (int k = 0; k < 3; ++k) {
+            d[k] = pos[3 * b + k] - pos[3 * a + k];
+            dv[k] = vel[3 * b + k] - vel[3 * a + k];
+        }
+        const double l = sqrt(dot3(d, d));
+        double e[3] = {d[0] / l, d[1] / l, d[2] / l};
+        const double mag = p->conn_k[c] * (l - p->conn_rest[c]) + p->conn_c[c] * dot3(e, dv);
+        for (int k = 0; k < 3; ++k) {
+            fc[3 * a + k] += mag * e[k];
+            fc[3 * b + k] -= mag * e[k];
+        }
+    }
+}
+
+/* All rods together, one step at a time (rods joined by connections). */
+static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double *dir, double *omega,
+                            int64_t step0, int64_t n_steps, const int64_t *eo, const int64_t *no,
+                            const int64_t *vo)
+{
+    const int R = p->n_rods;
+    const int64_t Nn = no[R - 1] + p->n_elems[R - 1] + 1;
+    const int nmax = max_elems(p);
+    double *fc = malloc(3 * (size_t)Nn * sizeof(double));
+    double *acc = malloc(3 * (size_t)(nmax + 1) * sizeof(double));
+    double *alpha = malloc(3 * (size_t)nmax * sizeof(double));
+    rod_work w;
+    int fail = (!fc || !acc || !alpha || work_alloc(&w, nmax) != 0);
+    if (!fail) {
+        const double h = p->dt;
+        for (int64_t s = 0; s < n_steps; ++s) {
+            const double t_mid = p->t0 + ((double)(step0 + s) + 0.5) * h;
+            for (int r = 0; r < R; ++r) {
+                rod_view rv;
+                rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
+                double *x = pos + 3 * no[r], *v = vel + 3 * no[r], *Q = dir + 9 * eo[r], *om = omega + 3 * eo[r];
+                rod_half_drift(&rv, h, x, v, Q, om);
+                rod_constraints(&rv, x, v, Q, om);
+            }
+            conn_forces(p, pos, vel, fc, Nn);
+            for (int r = 0; r < R; ++r) {
+                rod_view rv;
+                rod_consts c;
+                rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
+                rod_consts_make(&rv, &c);
+                rv.fconn = fc + 3 * no[r];
+                const int n = rv.n;
+                double *x = pos + 3 * no[r], *v = vel + 3 * no[r], *Q = dir + 9 * eo[r], *om = omega + 3 * eo[r];
+                rod_accel(&rv, &c, x, v, Q, om, t_mid, &w, acc, alpha);
+                for (int j = 0; j <= n; ++j)
+                    for (int a = 0; a < 3; ++a) v[3 * j + a] += h * acc[3 * j + a];
+                for (int i = 0; i < n; ++i)
+                    for (int a = 0; a < 3; ++a) om[3 * i + a] += h * alpha[3 * i + a];
+                rod_constraints(&rv, x, v, Q, om);
+                rod_half_drift(&rv, h, x, v, Q, om);
+                rod_constraints(&rv, x, v, Q, om);
+            }
+        }
+    }
+    if (fc && acc && alpha) work_free(&w);
+    free(fc);
+    free(acc);
+    free(alpha);
+    return fail ? -2 : 0;
+}
+
 /* Advance every rod by n_steps position-Verlet steps, starting at step index
  * step0 (time t0 + step0*dt).  pos/vel [N_n][3], dir [N_e][9], omega [N_e][3]
  * are updated in place.  n_threads <= 0 uses the OpenMP default. */
@@ -517,6 +605,11 @@ int orc_step(const orc_rods *p, double *pos, double *vel, double *dir, double *o
     if (!eo) return -2;
     int64_t *no = eo + R, *vo = eo + 2 * R;
     offsets(p, eo, no, vo);
+    if (p->n_conn > 0) {
+        const int rc = orc_step_coupled(p, pos, vel, dir, omega, step0, n_steps, eo, no, vo);
+        free(eo);
+        return rc;
+    }
     const int nmax = max_elems(p);
     int fail = 0;
 #ifdef _OPENMP
@@ -655,6 +748,19 @@ int orc_energy(const orc_rods *p, const double *pos, const double *vel, const do
         out[5 * r + 2] = Us;
         out[5 * r + 3] = Ub;
         out[5 * r + 4] = Wx;
+    }
+    /* connection springs: half of each potential to each of the two rods */
+    for (int32_t c = 0; c < p->n_conn; ++c) {
+        const int64_t a = p->conn_node[2 * c], b = p->conn_node[2 * c + 1];
+        double d[3] = {pos[3 * b] - pos[3 * a], pos[3 * b + 1] - pos[3 * a + 1], pos[3 * b + 2] - pos[3 * a + 2]};
+        const double ext = sqrt(dot3(d, d)) - p->conn_rest[c];
+        const double half = 0.25 * p->conn_k[c] * ext * ext;
+        for (int end = 0; end < 2; ++end) {
+            const int64_t node = p->conn_node[2 * c + end];
+            int r = 0;
+            while (r + 1 < R && no[r + 1] <= node) ++r;
+            out[5 * r + 4] += half;
+        }
     }
     work_free(&w);
     free(eo);

@@ -36,6 +36,7 @@ class _OrcRods(C.Structure):
         ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
         ("gravity", C.c_double * 3), ("muscle_amp", _dp), ("muscle_axis", _dp), ("muscle_freq", _dp),
         ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
+        ("n_conn", C.c_int32), ("conn_node", _ip), ("conn_k", _dp), ("conn_c", _dp), ("conn_rest", _dp),
     ]
 
 
@@ -141,6 +142,14 @@ class Oracle:
             self.muscle = [_d(np.asarray(ma, float).reshape(-1))] + [
                 _d(np.asarray(getattr(inp, k), float).reshape(-1))
                 for k in ("muscle_axis", "muscle_freq", "muscle_wavenumber", "muscle_phase")]
+        cr = getattr(inp, "conn_rod", None)
+        self.conn = None
+        if cr is not None and len(cr) > 0:
+            no = np.concatenate([[0], np.cumsum(np.asarray(inp.n_elems) + 1)])
+            nodes = no[np.asarray(cr, dtype=np.int64)] + np.asarray(inp.conn_node, dtype=np.int64)
+            self.conn = (np.ascontiguousarray(nodes, dtype=np.int32),
+                         _d(np.asarray(inp.conn_k, float)), _d(np.asarray(inp.conn_c, float)),
+                         _d(np.asarray(inp.conn_rest, float)))
         self.mat = {k: _d(getattr(inp, k)) for k in
                     ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping")}
         self.bc_start = np.ascontiguousarray(inp.bc_start, dtype=np.int32)
@@ -177,6 +186,10 @@ class Oracle:
         if self.muscle is not None:
             s.muscle_amp, s.muscle_axis, s.muscle_freq, s.muscle_wavenumber, s.muscle_phase = \
                 [_ptr(a) for a in self.muscle]
+        if self.conn is not None:
+            s.n_conn = int(self.conn[0].shape[0])
+            s.conn_node = self.conn[0].ctypes.data_as(_ip)
+            s.conn_k, s.conn_c, s.conn_rest = [_ptr(a) for a in self.conn[1:]]
         self._s = s
 
     @property

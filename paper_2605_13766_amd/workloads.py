@@ -76,6 +76,11 @@ class RodInputs:
     muscle_freq: Optional[np.ndarray] = None    # [R] Hz
     muscle_wavenumber: Optional[np.ndarray] = None  # [R] rad/m
     muscle_phase: Optional[np.ndarray] = None   # [R] rad
+    conn_rod: Optional[np.ndarray] = None       # [C, 2] int32: rods of the two connected nodes
+    conn_node: Optional[np.ndarray] = None      # [C, 2] int32: node index within each rod (0..n)
+    conn_k: Optional[np.ndarray] = None         # [C] N/m
+    conn_c: Optional[np.ndarray] = None         # [C] N s/m
+    conn_rest: Optional[np.ndarray] = None      # [C] m
     name: str = ""
 
     # ------------------------------------------------------------------ sizes
@@ -140,8 +145,22 @@ class RodInputs:
             muscle_amp=None if self.muscle_amp is None else self.muscle_amp[v_idx].copy(),
             muscle_axis=per_rod(self.muscle_axis), muscle_freq=per_rod(self.muscle_freq),
             muscle_wavenumber=per_rod(self.muscle_wavenumber), muscle_phase=per_rod(self.muscle_phase),
+            **self._subset_connections(rods),
             name=self.name + "[subset]",
         )
+
+    def _subset_connections(self, rods):
+        """Connections whose two rods are both in `rods`, renumbered."""
+        if self.conn_rod is None:
+            return {}
+        where = {int(r): k for k, r in enumerate(rods)}
+        keep = [c for c in range(len(self.conn_rod))
+                if int(self.conn_rod[c, 0]) in where and int(self.conn_rod[c, 1]) in where]
+        if not keep:
+            return {}
+        cr = np.array([[where[int(self.conn_rod[c, 0])], where[int(self.conn_rod[c, 1])]] for c in keep], np.int32)
+        return dict(conn_rod=cr, conn_node=self.conn_node[keep].copy(), conn_k=self.conn_k[keep].copy(),
+                    conn_c=self.conn_c[keep].copy(), conn_rest=self.conn_rest[keep].copy())
 
 
 # ---------------------------------------------------------------------------
