@@ -128,6 +128,24 @@ typedef struct {
     const double *muscle_freq;       /* [R] f = 1 / period (Hz) */
     const double *muscle_wavenumber; /* [R] q = 2 pi / wavelength (rad/m) */
     const double *muscle_phase;      /* [R] phi (rad) */
+    /* Rod-rod connections (Results, "Magnetized filament assemblies": components
+     * joined point-wise, backbones by distributed lateral connections).  Each
+     * connection is a central spring-dashpot between node conn_node[c][0] of rod
+     * conn_rod[c][0] and node conn_node[c][1] of rod conn_rod[c][1] (node indices
+     * 0..n of their rods): with l the distance between the two nodes and e the
+     * unit vector from the first to the second, the first node receives
+     *   [k (l - l0) + c dl/dt] e   (pre-kick velocities, at the kick time)
+     * and the second the opposite; half of its potential 1/2 k (l - l0)^2 joins
+     * each rod's W_ext.  Rods joined directly or through other rods are packed
+     * into one workgroup tile, so a connected group must fit a tile (at most
+     * 512 elements; ROD_EUNSUPPORTED otherwise, or when tile_waves is too small
+     * for it). */
+    int32_t n_connections;           /* C >= 0 */
+    const int32_t *conn_rod;         /* [C][2] rod indices */
+    const int32_t *conn_node;        /* [C][2] node indices within the rods */
+    const double *conn_k;            /* [C] spring stiffness >= 0 (N/m) */
+    const double *conn_c;            /* [C] dashpot coefficient >= 0 (N s/m) */
+    const double *conn_rest;         /* [C] rest distance >= 0 (m) */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -147,8 +165,10 @@ typedef struct {
  * a director farther than 1e-8 from SO(3) or with det < 0, a zero-length
  * element or rest length <= 0, couple_amp without freq/phase, muscle_amp
  * without axis/freq/wavenumber/phase, a magnetization, field, field_freq,
- * gravity or muscle input that is not finite), ROD_ENOMEM,
- * ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the longest rod).
+ * gravity or muscle input that is not finite, a connection naming a rod or
+ * node outside the batch, joining a node to itself, or with k, c or l0
+ * negative or not finite), ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED
+ * (tile_waves too small for the longest rod or connected group).
  * A time step above the explicit stability estimate is reported through
  * rod_last_error with ROD_OK.
  */
@@ -187,7 +207,8 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream);
  *   U_shear = 1/2 sum_i sigma_i . S sigma_i lh_i
  *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . B_k (kappa_k - kappa0_k) Dh_k
  *   W_ext   = -sum f . (r_last - r_last(0)) - sum_j m_j g . (r_j - r_j(0))
- *                                                    (the end force and gravity)
+ *             + half of 1/2 k (l - l0)^2 of every connection at the rod
+ *                                         (the end force, gravity, connections)
  * The distributed, magnetic and muscle couples have no energy column.  Returns ROD_ENONFINITE if any rod is flagged non-finite.
  */
 int rod_energy(rod_batch *b, double *out, void *stream);

@@ -103,6 +103,18 @@ struct DevBatch {
     // [3][n_slots + n_rods], the slot's node, then each rod's node n; NULL
     // without gravity
     const double *grav_r0;
+    // connections (NULL conn_idx: none).  A connected node has a compact index
+    // within its tile; the kernel keeps its position and velocity in a
+    // dynamic-LDS table of conn_nodes rows per tile.
+    const int32_t *conn_idx;       // [2][n_slots]: the slot's node i, and node n on a rod's last slot; -1: none
+    const int32_t *conn_tbase;     // [n_tiles] first global compact index of each tile
+    const int32_t *conn_off;       // [total + 1] CSR offsets over global compact indices
+    const int32_t *conn_partner;   // [2C] partner's compact index within the tile
+    const int32_t *conn_key;       // [total] slot * 2 + (0: node i, 1: node n) of each compact index
+    const T *conn_par;             // [3][2C] k, c, rest
+    const T *conn_org;             // [3][n_rods] rod origin relative to the first rod of its tile
+    int conn_nodes;                // table rows per tile
+    int64_t conn_entries;          // 2C
 };
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.

@@ -19,6 +19,7 @@
 #include "rod_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -206,6 +207,51 @@ __device__ inline bool finite3(T a, T b, T c)
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// Inclusive prefix sum of (p0, p1, p2) along each rod's lanes of a tile:
+// Kogge-Stone through LDS (`sc`, 3 * 64W values), restarted where the element
+// index `idx` is 0.  Its additions depend only on the element index, so every
+// tile width gives the same bits.  Called by all lanes (full EXEC).
+template <int W, typename T>
+__device__ __forceinline__ void rod_prefix(T &p0, T &p1, T &p2, int idx, T *sc, int lane)
+{
+    constexpr int TL = 64 * W;
+    for (int k = 1; k < TL; k <<= 1) {
+        __syncthreads();
+        sc[lane] = p0; sc[TL + lane] = p1; sc[2 * TL + lane] = p2;
+        __syncthreads();
+        if (idx >= k) {
+            p0 += sc[lane - k]; p1 += sc[TL + lane - k]; p2 += sc[2 * TL + lane - k];
+        }
+    }
+}
+
+// Force on connected node `me` (compact index in the tile, global index g)
+// from its connections: sum over them, in connection order, of
+// [k (l - l0) + c dl/dt] e, e the unit vector to the partner.  `tab` holds
+// rows x0 x1 x2 v0 v1 v2 of `rows` entries.  Coincident nodes exert nothing
+// (the direction is undefined there).
+template <typename T>
+__device__ inline void connection_force(const DevBatch<T> &B, const T *tab, int rows, int me, int g, T &f0, T &f1,
+                                        T &f2)
+{
+    const int64_t E = B.conn_entries;
+    const T x0 = tab[me], x1 = tab[rows + me], x2 = tab[2 * rows + me];
+    const T u0 = tab[3 * rows + me], u1 = tab[4 * rows + me], u2 = tab[5 * rows + me];
+    for (int e = B.conn_off[g]; e < B.conn_off[g + 1]; ++e) {
+        const int p = B.conn_partner[e];
+        const T dx = tab[p] - x0, dy = tab[rows + p] - x1, dz = tab[2 * rows + p] - x2;
+        const T l2 = dx * dx + dy * dy + dz * dz;
+        if (l2 > T(0)) {
+            const T il = rsqrt_t(l2);
+            const T l = l2 * il;
+            const T ex = dx * il, ey = dy * il, ez = dz * il;
+            const T ldot = ex * (tab[3 * rows + p] - u0) + ey * (tab[4 * rows + p] - u1) + ez * (tab[5 * rows + p] - u2);
+            const T mag = B.conn_par[e] * (l - B.conn_par[2 * E + e]) + B.conn_par[E + e] * ldot;
+            f0 += mag * ex; f1 += mag * ey; f2 += mag * ez;
+        }
+    }
+}
+
 }  // namespace
 
 // One launch: n_sub position-Verlet substeps for every tile (grid-stride).
@@ -240,24 +286,27 @@ __device__ inline bool finite3(T a, T b, T c)
 #define ROD_F32_WAVES_PER_SIMD 5
 #endif
 
-// EXT: the extended step, for batches with a magnetic couple, gravity or
-// muscle torques (a separate instantiation, so the plain step keeps its
-// registers and LDS).  Each extension a batch lacks contributes an exact zero
+// KIND 0: the plain step.  KIND 1: the extended step, for batches with a
+// magnetic couple, gravity or muscle torques.  KIND 2: the extended step with
+// rod-rod connections.  Separate instantiations, so the plain step keeps its
+// registers and LDS.  Each extension a batch lacks contributes an exact zero
 // (zero magnetization, amplitude or gravity), so the extended kernel reproduces
 // the plain one bit for bit on a plain batch.  Its multi-wave FP64 tiles and
 // all its FP32 tiles run one wave per SIMD fewer than the plain step's.
-template <typename T, int W, bool EXT>
+template <typename T, int W, int KIND>
 constexpr int step_waves_per_simd()
 {
-    return sizeof(T) == 8 ? ((W == 8 || (EXT && W > 1)) ? 2 : ROD_F64_WAVES_PER_SIMD)
-                          : (EXT ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
+    return sizeof(T) == 8 ? ((W == 8 || (KIND > 0 && W > 1)) ? 2 : ROD_F64_WAVES_PER_SIMD)
+                          : (KIND > 0 ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
 }
 
-template <typename T, int W, bool EXT>
+template <typename T, int W, int KIND>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, EXT>())))
+__attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, KIND>())))
 void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
+    constexpr bool EXT = KIND > 0;     // magnetic couple, gravity, muscle torques
+    constexpr bool CONN = KIND == 2;   // and rod-rod connections
     constexpr bool POS = sizeof(T) == 8;   // node positions in memory
     constexpr int TL = 64 * W;
     constexpr int NA = 13;     // from the left: frame (9), length, internal force (3)
@@ -282,6 +331,10 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         T cst[N_C * TL];
     };
     __shared__ Shared sh;
+    // connections: rows x0 x1 x2 v0 v1 v2 of the tile's connected nodes (and,
+    // for FP32, scratch of a prefix sum at the tile's start); sized at launch
+    extern __shared__ __align__(16) unsigned char conn_lds[];
+    T *const tab = reinterpret_cast<T *>(conn_lds);
     T *const lxa = sh.lxa, *const lxb = sh.lxb;
     T *const cst = sh.cst;
     double *const phs = sh.phs;
@@ -438,6 +491,36 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             vn0 = last ? u0 : b0[0]; vn1 = last ? u1 : b0[1]; vn2 = last ? u2 : b0[2];
         }
 
+        // connections: the connected nodes' positions (the frame of the tile's
+        // first rod) into the table
+        int ci = -1, cn = -1, cbase = 0;
+        if constexpr (CONN) {
+            {
+                const int rows = B.conn_nodes;
+                ci = B.conn_idx[s];
+                cn = last ? B.conn_idx[NS + s] : -1;
+                cbase = B.conn_tbase[tile];
+                T x0, x1, x2;
+                if constexpr (POS) {
+                    x0 = t0; x1 = t1; x2 = t2;   // node i's position
+                } else {
+                    // rod origin + anchor + the edges before node i
+                    const T e3[3] = {d0, d1, d2};
+                    T lf[3];
+                    from_left<W>(e3, lf, lxa, wave, wl);
+                    x0 = first ? B.conn_org[rr] + t0 : lf[0];
+                    x1 = first ? B.conn_org[B.n_rods + rr] + t1 : lf[1];
+                    x2 = first ? B.conn_org[2 * B.n_rods + rr] + t2 : lf[2];
+                    rod_prefix<W>(x0, x1, x2, i, tab, lane);
+                    __syncthreads();
+                }
+                if (ci >= 0) { tab[ci] = x0 + hh * v0; tab[rows + ci] = x1 + hh * v1; tab[2 * rows + ci] = x2 + hh * v2; }
+                if (cn >= 0) {
+                    tab[cn] = x0 + d0 + hh * u0; tab[rows + cn] = x1 + d1 + hh * u1; tab[2 * rows + cn] = x2 + d2 + hh * u2;
+                }
+            }
+        }
+
         // ---- opening half drift (constraints hold: clamped v, omega are zero)
         d0 += hh * (vn0 - v0); d1 += hh * (vn1 - v1); d2 += hh * (vn2 - v2);
         t0 += hh * v0; t1 += hh * v1; t2 += hh * v2;
@@ -504,6 +587,19 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 np2 = first ? T(0) : ba[12];
             }
 
+            // ---- connection forces on node i and node n (pre-kick velocities)
+            T fc0 = 0, fc1 = 0, fc2 = 0, gc0 = 0, gc1 = 0, gc2 = 0;
+            if constexpr (CONN) {
+                {
+                    const int rows = B.conn_nodes;
+                    if (ci >= 0) { tab[3 * rows + ci] = v0; tab[4 * rows + ci] = v1; tab[5 * rows + ci] = v2; }
+                    if (cn >= 0) { tab[3 * rows + cn] = u0; tab[4 * rows + cn] = u1; tab[5 * rows + cn] = u2; }
+                    __syncthreads();
+                    if (ci >= 0) connection_force(B, tab, rows, ci, cbase + ci, fc0, fc1, fc2);
+                    if (cn >= 0) connection_force(B, tab, rows, cn, cbase + cn, gc0, gc1, gc2);
+                }
+            }
+
             // ---- Eq. 1a at node i (and node n on the last lane); kick
             const T gamma = cl[C_GAMMA * TL];
             {
@@ -516,8 +612,8 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 T b1 = (cl[C_FY * TL] - nf1) * inv_mt - gamma * u1;
                 T b2 = (cl[C_FZ * TL] - nf2) * inv_mt - gamma * u2;
                 if constexpr (EXT) {
-                    a0 += B.grav[0]; a1 += B.grav[1]; a2 += B.grav[2];
-                    b0 += B.grav[0]; b1 += B.grav[1]; b2 += B.grav[2];
+                    a0 += B.grav[0] + fc0 * inv_m; a1 += B.grav[1] + fc1 * inv_m; a2 += B.grav[2] + fc2 * inv_m;
+                    b0 += B.grav[0] + gc0 * inv_mt; b1 += B.grav[1] + gc1 * inv_mt; b2 += B.grav[2] + gc2 * inv_mt;
                 }
                 v0 += hv * a0; v1 += hv * a1; v2 += hv * a2;
                 u0 += hu * b0; u1 += hu * b1; u2 += hu * b2;
@@ -572,6 +668,13 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T dd = sub + 1 < n_sub ? h : hh;
             d0 += dd * (vn0 - v0); d1 += dd * (vn1 - v1); d2 += dd * (vn2 - v2);
             t0 += dd * v0; t1 += dd * v1; t2 += dd * v2;
+            if constexpr (CONN) {
+                {
+                    const int rows = B.conn_nodes;
+                    if (ci >= 0) { tab[ci] += dd * v0; tab[rows + ci] += dd * v1; tab[2 * rows + ci] += dd * v2; }
+                    if (cn >= 0) { tab[cn] += dd * u0; tab[rows + cn] += dd * u1; tab[2 * rows + cn] += dd * u2; }
+                }
+            }
             rotate_left(q, -dd * w0, -dd * w1, -dd * w2);
 
             // advance the couple's phase by one step
@@ -659,6 +762,29 @@ __global__ void set_step_kernel(int64_t *step, int64_t v)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step = v;
 }
 
+// Position of a connected node in the frame of its tile's first rod (FP64:
+// the stored positions; FP32: rod origin + anchor + the edges before it, in
+// FP64).  col 0: the slot's node i; col 1: node n of the rod ending there.
+template <typename T>
+__device__ void conn_node_position(const DevBatch<T> &B, int64_t slot, int col, double x[3])
+{
+    constexpr bool EDGE = sizeof(T) == 4;
+    const int64_t NS = B.n_slots;
+    const int rod = B.slot_rod[slot];
+    if (!EDGE) {
+        for (int a = 0; a < 3; ++a)
+            x[a] = col == 0 ? (double)B.state[(RX + a) * NS + slot] : (double)B.tail[(TRX + a) * B.n_rods + rod];
+        return;
+    }
+    const int j = B.slot_idx[slot] + col;
+    const int64_t s0 = B.rod_slot[rod];
+    for (int a = 0; a < 3; ++a) {
+        double v = (double)B.conn_org[a * B.n_rods + rod] + (double)B.tail[(TRX + a) * B.n_rods + rod];
+        for (int k = 0; k < j; ++k) v += (double)B.state[(RX + a) * NS + s0 + k];
+        x[a] = v;
+    }
+}
+
 // Per-rod energies, one thread per rod walking its slots (off the step path).
 // FP32 batches hold edge vectors: node n = anchor + sum of edges (in FP64).
 template <typename T>
@@ -738,6 +864,29 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
             / RP(R_INV_M_TAIL);
         Wx -= Wg;
     }
+    if (B.ext && B.conn_idx) {
+        // half of the potential 1/2 k (l - l0)^2 of every connection at this rod's nodes
+        const int64_t TLn = NS / B.n_tiles;
+        const int64_t E = B.conn_entries;
+        for (int j = 0; j <= n; ++j) {
+            const int col = j < n ? 0 : 1;
+            const int64_t slot = s0 + (j < n ? j : n - 1);
+            const int me = B.conn_idx[col * NS + slot];
+            if (me < 0) continue;
+            const int tb = B.conn_tbase[slot / TLn];
+            double x[3];
+            conn_node_position(B, slot, col, x);
+            for (int e = B.conn_off[tb + me]; e < B.conn_off[tb + me + 1]; ++e) {
+                const int key = B.conn_key[tb + B.conn_partner[e]];
+                double xp[3];
+                conn_node_position(B, key / 2, key % 2, xp);
+                const double l = sqrt((xp[0] - x[0]) * (xp[0] - x[0]) + (xp[1] - x[1]) * (xp[1] - x[1])
+                                      + (xp[2] - x[2]) * (xp[2] - x[2]));
+                const double ext = l - (double)B.conn_par[2 * E + e];
+                Wx += 0.25 * (double)B.conn_par[e] * ext * ext;
+            }
+        }
+    }
     out[5 * row + 0] = Tl;
     out[5 * row + 1] = Tr;
     out[5 * row + 2] = Us;
@@ -751,10 +900,16 @@ template <typename T, int W>
 static hipError_t launch_w(const DevBatch<T> &b, int n_sub, int grid, hipStream_t s)
 {
     if (grid <= 0) grid = b.n_tiles;
-    if (b.ext)
-        hipLaunchKernelGGL((rod_step_kernel<T, W, true>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
-    else
-        hipLaunchKernelGGL((rod_step_kernel<T, W, false>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
+    if (b.ext && b.conn_idx) {
+        // connections: the table (6 rows per connected node), and for FP32 the
+        // scratch of the starting prefix sum (3 per lane)
+        const size_t lds = sizeof(T) * (size_t)std::max(6 * b.conn_nodes, sizeof(T) == 4 ? 3 * 64 * W : 0);
+        hipLaunchKernelGGL((rod_step_kernel<T, W, 2>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
+    } else if (b.ext) {
+        hipLaunchKernelGGL((rod_step_kernel<T, W, 1>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
+    } else {
+        hipLaunchKernelGGL((rod_step_kernel<T, W, 0>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
+    }
     return hipGetLastError();
 }
 
@@ -816,7 +971,7 @@ template <typename T, int W>
 static int resident_w()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rod_step_kernel<T, W, false>, 64 * W, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rod_step_kernel<T, W, 0>, 64 * W, 0) != hipSuccess)
         return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;

@@ -47,6 +47,8 @@ struct HostInputs {
     std::vector<double> fend, camp, cfreq, cphase;
     std::vector<double> mag;     // [N_e][3] magnetization per unit length (empty: none)
     std::vector<double> mamp, maxis, mfreq, mwave, mphase;   // muscle torques (empty: none)
+    std::vector<int32_t> crod, cnode;                        // connections [C][2] (empty: none)
+    std::vector<double> ck, cc, crest;
     bool has_k0 = false, has_f = false, has_c = false;
 };
 
@@ -99,6 +101,16 @@ struct rod_batch {
     double *d_mus_ofs = nullptr; // [n_slots] muscle phase offset phi - q s_k
     double *d_mus_freq = nullptr;   // [R] muscle frequency
     double *d_grav_r0 = nullptr;    // [3][n_slots + R] creation positions (batches with gravity)
+    // connections: per-slot compact node indices, CSR over them, spring parameters, rod offsets
+    int32_t *d_conn_idx = nullptr;  // [2][n_slots]
+    int32_t *d_conn_off = nullptr;  // [total + 1]
+    int32_t *d_conn_tbase = nullptr;   // [n_tiles] first compact index of each tile
+    int32_t *d_conn_partner = nullptr; // [2C] partner's compact index within its tile
+    int32_t *d_conn_key = nullptr;     // [total] slot * 2 + column of each compact index
+    void *d_conn_par = nullptr;        // [3][2C] k, c, rest (state precision)
+    void *d_conn_org = nullptr;        // [3][R] rod origin relative to its tile's first rod
+    int conn_max_nodes = 0;            // most connected nodes in one tile
+    int n_conn = 0;
     double *d_freq = nullptr, *d_phase = nullptr, *d_energy = nullptr;
     int32_t *d_ints = nullptr;   // slot_rod, slot_idx, rod_n, rod_flags, rod_slot, nonfinite
     int64_t *d_step = nullptr;
@@ -116,18 +128,50 @@ namespace {
 
 size_t elem_bytes(const rod_batch *b) { return b->precision == ROD_F32 ? 4 : 8; }
 
-// Best-fit decreasing packing of whole rods into tiles of `cap` lanes.
-void pack_tiles(const std::vector<int32_t> &n, int cap, std::vector<int32_t> &rod_slot, int &n_tiles)
+// Groups of rods joined (directly or through other rods) by connections; a
+// rod without connections is a group of its own.  Members in rod order.
+std::vector<std::vector<int32_t>> connected_groups(int R, const std::vector<int32_t> &crod)
 {
-    const int R = (int)n.size();
-    std::vector<int32_t> order(R);
-    for (int r = 0; r < R; ++r) order[r] = r;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    std::vector<int32_t> parent(R);
+    for (int r = 0; r < R; ++r) parent[r] = r;
+    auto root = [&](int32_t x) {
+        while (parent[x] != x) x = parent[x] = parent[parent[x]];
+        return x;
+    };
+    for (size_t c = 0; c + 1 < crod.size(); c += 2) {
+        const int32_t a = root(crod[c]), b = root(crod[c + 1]);
+        if (a != b) parent[std::max(a, b)] = std::min(a, b);
+    }
+    std::vector<int32_t> gid(R, -1);
+    std::vector<std::vector<int32_t>> groups;
+    for (int r = 0; r < R; ++r) {
+        const int32_t g = root(r);
+        if (gid[g] < 0) {
+            gid[g] = (int32_t)groups.size();
+            groups.emplace_back();
+        }
+        groups[gid[g]].push_back(r);
+    }
+    return groups;
+}
+
+// Best-fit decreasing packing of whole groups into tiles of `cap` lanes; the
+// rods of a group sit on consecutive lanes of one tile.
+void pack_tiles(const std::vector<int32_t> &n, const std::vector<std::vector<int32_t>> &groups, int cap,
+                std::vector<int32_t> &rod_slot, int &n_tiles)
+{
+    const int G = (int)groups.size();
+    std::vector<int> size(G, 0);
+    for (int g = 0; g < G; ++g)
+        for (int32_t r : groups[g]) size[g] += n[r];
+    std::vector<int32_t> order(G);
+    for (int g = 0; g < G; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size[a] > size[b]; });
     std::multiset<std::pair<int, int>> room;   // (free lanes, tile)
     std::vector<int> used;
-    rod_slot.assign(R, 0);
-    for (int r : order) {
-        auto it = room.lower_bound({n[r], -1});
+    rod_slot.assign(n.size(), 0);
+    for (int g : order) {
+        auto it = room.lower_bound({size[g], -1});
         int tile;
         if (it == room.end()) {
             tile = (int)used.size();
@@ -136,8 +180,10 @@ void pack_tiles(const std::vector<int32_t> &n, int cap, std::vector<int32_t> &ro
             tile = it->second;
             room.erase(it);
         }
-        rod_slot[r] = tile * cap + used[tile];
-        used[tile] += n[r];
+        for (int32_t r : groups[g]) {
+            rod_slot[r] = tile * cap + used[tile];
+            used[tile] += n[r];
+        }
         if (cap - used[tile] > 0) room.insert({cap - used[tile], tile});
     }
     n_tiles = (int)used.size();
@@ -168,6 +214,9 @@ int validate(const rod_batch_desc *d)
         if (!std::isfinite(d->gravity[k])) return fail(ROD_EINVAL, "gravity is not finite");
     if (d->muscle_amp && (!d->muscle_axis || !d->muscle_freq || !d->muscle_wavenumber || !d->muscle_phase))
         return fail(ROD_EINVAL, "muscle_amp needs muscle_axis, muscle_freq, muscle_wavenumber and muscle_phase");
+    if (d->n_connections < 0) return fail(ROD_EINVAL, "n_connections must be >= 0");
+    if (d->n_connections > 0 && (!d->conn_rod || !d->conn_node || !d->conn_k || !d->conn_c || !d->conn_rest))
+        return fail(ROD_EINVAL, "connections need conn_rod, conn_node, conn_k, conn_c and conn_rest");
     return ROD_OK;
 }
 
@@ -235,6 +284,14 @@ int gather_inputs(const rod_batch_desc *d, HostInputs &h)
     if (d->magnetization) {
         if ((rc = fetch(h.mag, d->magnetization, 3 * Ne, dev))) return rc;
     }
+    if (d->n_connections > 0) {
+        const size_t C = (size_t)d->n_connections;
+        if ((rc = fetch(h.crod, d->conn_rod, 2 * C, dev))) return rc;
+        if ((rc = fetch(h.cnode, d->conn_node, 2 * C, dev))) return rc;
+        if ((rc = fetch(h.ck, d->conn_k, C, dev))) return rc;
+        if ((rc = fetch(h.cc, d->conn_c, C, dev))) return rc;
+        if ((rc = fetch(h.crest, d->conn_rest, C, dev))) return rc;
+    }
     if (d->muscle_amp) {
         if ((rc = fetch(h.mamp, d->muscle_amp, Nv, dev))) return rc;
         if ((rc = fetch(h.maxis, d->muscle_axis, 3 * R, dev))) return rc;
@@ -262,6 +319,19 @@ int check_values(HostInputs &h)
     for (double x : h.mag) if (!std::isfinite(x)) return fail(ROD_EINVAL, "magnetization is not finite");
     for (const auto *vec : {&h.mamp, &h.maxis, &h.mfreq, &h.mwave, &h.mphase})
         for (double x : *vec) if (!std::isfinite(x)) return fail(ROD_EINVAL, "a muscle input is not finite");
+    for (size_t c = 0; c < h.ck.size(); ++c) {
+        const std::string tag = "connection " + std::to_string(c) + ": ";
+        for (int end = 0; end < 2; ++end) {
+            const int32_t r = h.crod[2 * c + end], j = h.cnode[2 * c + end];
+            if (r < 0 || r >= R) return fail(ROD_EINVAL, tag + "rod outside the batch");
+            if (j < 0 || j > h.n[r]) return fail(ROD_EINVAL, tag + "node outside its rod");
+        }
+        if (h.crod[2 * c] == h.crod[2 * c + 1] && h.cnode[2 * c] == h.cnode[2 * c + 1])
+            return fail(ROD_EINVAL, tag + "joins a node to itself");
+        if (!(h.ck[c] >= 0) || !(h.cc[c] >= 0) || !(h.crest[c] >= 0) || !std::isfinite(h.ck[c])
+            || !std::isfinite(h.cc[c]) || !std::isfinite(h.crest[c]))
+            return fail(ROD_EINVAL, tag + "k, c and l0 must be finite and >= 0");
+    }
     const int64_t Ne = (int64_t)h.dir.size() / 9;
     for (int64_t i = 0; i < Ne; ++i) {
         const double *q = &h.dir[9 * i];
@@ -363,6 +433,15 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.mus_ofs = b->d_mus_ofs;
     d.mus_freq = b->d_mus_freq;
     d.grav_r0 = b->d_grav_r0;
+    d.conn_idx = b->d_conn_idx;
+    d.conn_tbase = b->d_conn_tbase;
+    d.conn_off = b->d_conn_off;
+    d.conn_partner = b->d_conn_partner;
+    d.conn_key = b->d_conn_key;
+    d.conn_par = (const T *)b->d_conn_par;
+    d.conn_org = (const T *)b->d_conn_org;
+    d.conn_nodes = b->conn_max_nodes;
+    d.conn_entries = 2 * (int64_t)b->n_conn;
 }
 
 // Pack the dynamic state into the slot layout, imposing the clamped ends'
@@ -550,6 +629,90 @@ int build_device(rod_batch *b, const HostInputs &h)
         }
         HIPCHK(hipMalloc((void **)&b->d_grav_r0, r0.size() * sizeof(double)));
         HIPCHK(hipMemcpy(b->d_grav_r0, r0.data(), r0.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (!h.ck.empty()) {
+        // connections: compact indices of the connected nodes per tile (node j < n of
+        // rod r is column 0 of slot rod_slot[r] + j, node n column 1 of the rod's
+        // last slot), CSR over them in connection order, spring parameters, and
+        // each rod's origin relative to the first rod of its tile
+        const int TL = 64 * b->waves;
+        const int C = (int)h.ck.size();
+        auto key_of = [&](int32_t r, int32_t j) -> int64_t {
+            const int n = h.n[r];
+            return j < n ? 2 * ((int64_t)b->rod_slot[r] + j) : 2 * ((int64_t)b->rod_slot[r] + n - 1) + 1;
+        };
+        std::vector<int64_t> keys;
+        keys.reserve(2 * C);
+        for (int c = 0; c < C; ++c)
+            for (int end = 0; end < 2; ++end) keys.push_back(key_of(h.crod[2 * c + end], h.cnode[2 * c + end]));
+        std::vector<int64_t> ukeys(keys);
+        std::sort(ukeys.begin(), ukeys.end());
+        ukeys.erase(std::unique(ukeys.begin(), ukeys.end()), ukeys.end());
+        std::vector<int32_t> idx((size_t)2 * NS, -1), count(b->n_tiles, 0), tbase(b->n_tiles, 0);
+        std::vector<int32_t> gidx(ukeys.size());
+        for (size_t u = 0; u < ukeys.size(); ++u) {
+            const int64_t slot = ukeys[u] / 2;
+            const int tile = (int)(slot / TL);
+            idx[(ukeys[u] % 2) * NS + slot] = count[tile]++;
+        }
+        int32_t total = 0;
+        for (int t = 0; t < b->n_tiles; ++t) {
+            tbase[t] = total;
+            total += count[t];
+            b->conn_max_nodes = std::max(b->conn_max_nodes, count[t]);
+        }
+        auto global_of = [&](int64_t key) {
+            const int64_t slot = key / 2;
+            return tbase[slot / TL] + idx[(key % 2) * NS + slot];
+        };
+        std::vector<int32_t> ckey(total);
+        for (int64_t key : ukeys) ckey[global_of(key)] = (int32_t)key;
+        std::vector<int32_t> off(total + 1, 0), partner(2 * C);
+        std::vector<T> par((size_t)3 * 2 * C);
+        for (int c = 0; c < C; ++c) {
+            ++off[global_of(keys[2 * c]) + 1];
+            ++off[global_of(keys[2 * c + 1]) + 1];
+        }
+        for (int32_t g = 0; g < total; ++g) off[g + 1] += off[g];
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (int c = 0; c < C; ++c)
+            for (int end = 0; end < 2; ++end) {
+                const int64_t me = keys[2 * c + end], other = keys[2 * c + 1 - end];
+                if ((me / 2) / TL != (other / 2) / TL)
+                    return fail(ROD_EDEVICE, "connection " + std::to_string(c) + " spans two tiles");
+                const int32_t e = fill[global_of(me)]++;
+                partner[e] = idx[(other % 2) * NS + other / 2];
+                par[e] = T(h.ck[c]);
+                par[2 * C + e] = T(h.cc[c]);
+                par[4 * C + e] = T(h.crest[c]);
+            }
+        std::vector<T> org((size_t)3 * R, T(0));
+        {
+            std::vector<int32_t> first_rod(b->n_tiles, -1);
+            for (int r = 0; r < R; ++r) {
+                const int tile = b->rod_slot[r] / TL;
+                if (first_rod[tile] < 0 || b->rod_slot[r] < b->rod_slot[first_rod[tile]]) first_rod[tile] = r;
+            }
+            for (int r = 0; r < R; ++r) {
+                const int ref = first_rod[b->rod_slot[r] / TL];
+                for (int a = 0; a < 3; ++a) org[a * R + r] = T(b->origin[3 * r + a] - b->origin[3 * ref + a]);
+            }
+        }
+        b->n_conn = C;
+        HIPCHK(hipMalloc((void **)&b->d_conn_idx, idx.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&b->d_conn_tbase, tbase.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&b->d_conn_off, off.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&b->d_conn_partner, partner.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&b->d_conn_key, std::max<size_t>(ckey.size(), 1) * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&b->d_conn_par, par.size() * es));
+        HIPCHK(hipMalloc(&b->d_conn_org, org.size() * es));
+        HIPCHK(hipMemcpy(b->d_conn_idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_tbase, tbase.data(), tbase.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_partner, partner.data(), partner.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_key, ckey.data(), ckey.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_par, par.data(), par.size() * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_org, org.data(), org.size() * es, hipMemcpyHostToDevice));
     }
     if (b->muscle) {
         // amplitude times axis and the phase offset phi - q s_k at the Voronoi
@@ -843,11 +1006,14 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->dt = d->dt;
     b->t0 = d->t0;
     b->use_graphs = std::getenv("ROD_NO_GRAPH") == nullptr;
-    int nmax = 0;
-    for (int r = 0; r < b->R; ++r) {
-        nmax = std::max(nmax, h.n[r]);
-        b->Ne += h.n[r];
+    const auto groups = connected_groups(b->R, h.crod);
+    int nmax = 0;   // the largest group (a rod, or rods joined by connections)
+    for (const auto &g : groups) {
+        int sz = 0;
+        for (int32_t r : g) sz += h.n[r];
+        nmax = std::max(nmax, sz);
     }
+    for (int r = 0; r < b->R; ++r) b->Ne += h.n[r];
     b->Nn = b->Ne + b->R;
     int waves = d->tile_waves;
     const int need = (nmax + 63) / 64;
@@ -857,11 +1023,15 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     }
     if (waves < need) {
         delete b;
-        return fail(ROD_EUNSUPPORTED, "tile_waves " + std::to_string(waves) + " cannot hold a rod of "
+        return fail(ROD_EUNSUPPORTED, "tile_waves " + std::to_string(waves) + " cannot hold a rod or connected group of "
                                           + std::to_string(nmax) + " elements");
     }
     b->waves = waves;
-    pack_tiles(h.n, 64 * waves, b->rod_slot, b->n_tiles);
+    if (nmax > 64 * 8) {
+        delete b;
+        return fail(ROD_EUNSUPPORTED, "a connected group of " + std::to_string(nmax) + " elements exceeds a tile (512)");
+    }
+    pack_tiles(h.n, groups, 64 * waves, b->rod_slot, b->n_tiles);
     b->n_slots = (int64_t)b->n_tiles * 64 * waves;
     b->slot_rod.assign(b->n_slots, -1);
     b->slot_idx.assign(b->n_slots, 0);
@@ -889,7 +1059,8 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     }
     b->muscle = d->muscle_amp != nullptr;
     for (int a = 0; a < 3; ++a) b->grav[a] = d->gravity[a];
-    b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0;
+    b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0
+           || d->n_connections > 0;
     b->clamp_r0.assign(3 * b->R, 0.0);
     b->clamp_rn.assign(3 * b->R, 0.0);
     b->clamp_q0.assign(9 * b->R, 0.0);
@@ -1060,6 +1231,13 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->d_mus_ofs);
     (void)hipFree(b->d_mus_freq);
     (void)hipFree(b->d_grav_r0);
+    (void)hipFree(b->d_conn_idx);
+    (void)hipFree(b->d_conn_tbase);
+    (void)hipFree(b->d_conn_off);
+    (void)hipFree(b->d_conn_partner);
+    (void)hipFree(b->d_conn_key);
+    (void)hipFree(b->d_conn_par);
+    (void)hipFree(b->d_conn_org);
     (void)hipFree(b->d_freq);
     (void)hipFree(b->d_phase);
     (void)hipFree(b->d_energy);

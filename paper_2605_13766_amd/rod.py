@@ -39,6 +39,8 @@ class RodBatchDesc(C.Structure):
         ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
         ("gravity", C.c_double * 3), ("muscle_amp", _dp), ("muscle_axis", _dp), ("muscle_freq", _dp),
         ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
+        ("n_connections", C.c_int32), ("conn_rod", _ip), ("conn_node", _ip), ("conn_k", _dp), ("conn_c", _dp),
+        ("conn_rest", _dp),
     ]
 
 
@@ -211,9 +213,14 @@ class RodBatch:
                      "muscle_amp", "muscle_axis", "muscle_freq", "muscle_wavenumber", "muscle_phase"):
             arr(name, getattr(inp, name, None))
             setattr(d, name, ptr(name, _dp))
-        for name in ("bc_start", "bc_end"):
+        for name in ("bc_start", "bc_end", "conn_rod", "conn_node"):
             arr(name, getattr(inp, name, None), "i")
             setattr(d, name, ptr(name, _ip))
+        for name in ("conn_k", "conn_c", "conn_rest"):
+            arr(name, getattr(inp, name, None))
+            setattr(d, name, ptr(name, _dp))
+        cr = getattr(inp, "conn_rod", None)
+        d.n_connections = 0 if cr is None else int(np.asarray(cr).shape[0])
         d.dt = float(inp.dt)
         d.t0 = float(t0)
         d.precision = prec

@@ -499,3 +499,58 @@ def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period
     inp.muscle_wavenumber = np.full(n_rods, 2.0 * np.pi / wavelength)
     inp.muscle_phase = rng.uniform(0.0, 2.0 * np.pi, size=n_rods)
     return inp
+
+
+def millipede_swarm(n_bots=224, legs_per_side=12, n_back=20, n_leg=8, back_length=0.02, leg_length=0.004,
+                    back_radius=2.5e-4, leg_radius=2e-4, width=2e-3, youngs=1e6, k_lateral=1.0, k_leg=1.0,
+                    c_conn=1e-5, m0=1e-4, b0=0.01, freq=5.0, spacing=0.03, dt=1e-6, seed=SEED_BASE + 8):
+    """Millipede-like bots of connected rods (Results, "Magnetized filament
+    assemblies"): per bot two parallel backbone rods along x, `width` apart,
+    joined node by node by lateral connections (distributed connection, rest
+    length `width`), and `legs_per_side` legs per backbone, each attached
+    point-wise (rest length 0) by its first node to a backbone node and
+    pointing outward and down.  The legs carry a magnetization m0 along their
+    axis whose sign alternates along the bot; the field rotates in the x-z
+    plane.  Bots sit on a square grid `spacing` apart; each bot is one
+    connected group (2 * n_back + 2 * legs_per_side * n_leg elements).
+    """
+    rng = np.random.default_rng(seed)
+    g = int(np.ceil(np.sqrt(n_bots)))
+    nodes_list, Q_list, radius, rods = [], [], [], []
+    conn_rod, conn_node, conn_k, conn_rest = [], [], [], []
+    mag = []
+    for bot in range(n_bots):
+        ox, oy = (bot % g) * spacing, (bot // g) * spacing
+        base = np.array([ox, oy, 0.0]) + rng.normal(0, 1e-5, 3)
+        first = len(nodes_list)
+        for side in (0, 1):
+            nodes, Q = straight_rod(n_back, back_length, direction=(1, 0, 0), d1=(0, 0, 1),
+                                    origin=base + np.array([0.0, side * width, 0.0]))
+            nodes_list.append(nodes); Q_list.append(Q); radius.append(back_radius)
+            mag.append(np.zeros((n_back, 3)))
+        for j in range(n_back + 1):      # lateral connections, node by node
+            conn_rod.append([first, first + 1]); conn_node.append([j, j]); conn_k.append(k_lateral)
+            conn_rest.append(width)
+        at = np.linspace(1, n_back - 1, legs_per_side).round().astype(int)
+        for side in (0, 1):
+            out = -1.0 if side == 0 else 1.0
+            for li, j in enumerate(at):
+                root = nodes_list[first + side][j]
+                direction = np.array([0.0, out * np.cos(np.pi / 4), -np.sin(np.pi / 4)])
+                nodes, Q = straight_rod(n_leg, leg_length, direction=direction, d1=(1, 0, 0), origin=root)
+                nodes_list.append(nodes); Q_list.append(Q); radius.append(leg_radius)
+                sign = 1.0 if li % 2 == 0 else -1.0
+                mag.append(np.tile([0.0, 0.0, sign * m0], (n_leg, 1)))
+                conn_rod.append([first + side, len(nodes_list) - 1]); conn_node.append([int(j), 0])
+                conn_k.append(k_leg); conn_rest.append(0.0)
+    inp = _assemble("millipede_swarm", nodes_list, Q_list, dt, density=DENSITY, youngs=youngs,
+                    radius=np.array(radius), damping=0.0, bc_start=0, bc_end=0)
+    inp.conn_rod = np.array(conn_rod, np.int32)
+    inp.conn_node = np.array(conn_node, np.int32)
+    inp.conn_k = np.array(conn_k, float)
+    inp.conn_c = np.full(len(conn_k), float(c_conn))
+    inp.conn_rest = np.array(conn_rest, float)
+    inp.magnetization = np.ascontiguousarray(np.concatenate(mag))
+    inp.field = np.array([0.0, 0.0, 0.0, 0.0, 0.0, b0, b0, 0.0, 0.0])
+    inp.field_freq = float(freq)
+    return inp

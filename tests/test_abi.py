@@ -142,3 +142,19 @@ def test_muscle_descriptor_rejected_when_incomplete_or_not_finite():
     assert "muscle" in _expect(rod.ROD_EINVAL, bad)
     bad = base.copy(); bad.gravity = np.array([0.0, np.inf, 0.0])
     assert "gravity" in _expect(rod.ROD_EINVAL, bad)
+
+
+def test_connection_descriptor_rejected_when_invalid():
+    from paper_2605_13766_amd import rod
+    base = W.millipede_swarm(n_bots=1)
+    bad = base.copy(); bad.conn_rod = base.conn_rod.copy(); bad.conn_rod[3, 1] = base.n_rods
+    assert "rod outside" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.conn_node = base.conn_node.copy(); bad.conn_node[0, 0] = 999
+    assert "node outside" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.conn_rod = base.conn_rod.copy(); bad.conn_node = base.conn_node.copy()
+    bad.conn_rod[0] = [0, 0]; bad.conn_node[0] = [2, 2]
+    assert "itself" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.conn_k = base.conn_k.copy(); bad.conn_k[1] = -1.0
+    assert ">= 0" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.conn_rest = None
+    assert "conn_rest" in _expect(rod.ROD_EINVAL, bad)
