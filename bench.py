@@ -8,14 +8,16 @@ substeps per launch S chosen by the library's autotuner).  The headline value is
 FP32 figure rides along in the same JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate] [--no-magnetic]
-                  [--no-active]
+                  [--no-active] [--no-connected]
 
 The magnetic carpet rides along as the "magnetic" object: 65,536 base-clamped
 rods x 50 elements (FP32) turned by a rotating homogeneous field through their
 programmed magnetization, timed like the headline and next to the same carpet
 driven by its distributed couple.  The "active" object times 16,384 free
 filaments x 50 elements under gravity and travelling-wave muscle moments in
-both precisions.
+both precisions; the "connected" object times millipede-like bots of rods
+joined by point-wise and lateral spring-dashpot connections (224 bots, and
+4096 to fill the GPU).
 
 The learned coarse step rides along as the "surrogate" object: the network is
 trained on 16,384 carpet rods (64 elements, 2.1e6 windows from plain
@@ -57,6 +59,7 @@ ALGO_FLOP_ACTIVE = 459 - 6 + 3 + 9               # no external couple; gravity 3
 ALGO_BYTES = {"f64": 400, "f32": 204}            # HBM bytes per element per launch
 MAG_BYTES = 12                                   # FP32 magnetization x rest length, read once per launch
 MUSCLE_BYTES = {"f64": 32, "f32": 20}            # muscle amplitude x axis (T) and phase offset (FP64)
+CONN_FLOP = 30                                   # one spring-dashpot force per connection and step
 PEAK = {"f64": 78.6, "f32": 157.3}               # TFLOP/s, MI355X vector peaks
 STEPS_PER_LAUNCH = 1000
 SURR_K = 32
@@ -171,6 +174,45 @@ def time_active(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32
         out[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms": r["launch_ms"],
                   "roofline": r["roofline"], "tile_waves": r["info"]["tile_waves"],
                   "substeps_per_launch": r["info"]["substeps"]}
+    return out
+
+
+def connected_costs(inp, precision):
+    """Algorithmic FLOP per element-step and extra bytes per element per launch of
+    the millipede swarm: the plain step without the distributed couple, the
+    magnetic couple on magnetized elements, one force per connection and step;
+    bytes for the magnetization, the per-slot connection indices and the
+    connection table (offsets, partners, k, c, l0)."""
+    es = 8 if precision == "f64" else 4
+    ne = inp.n_elements
+    C = len(inp.conn_k)
+    mag_frac = float(np.mean(np.any(inp.magnetization != 0, axis=1)))
+    nodes = len({(int(r), int(j)) for pair_r, pair_j in zip(inp.conn_rod, inp.conn_node)
+                 for r, j in zip(pair_r, pair_j)})
+    flop = (ALGO_FLOP - 6 + 27 * mag_frac) + CONN_FLOP * C / ne
+    extra = 3 * es + 8 + (4 * nodes + 2 * C * (4 + 3 * es)) / ne
+    return flop, extra
+
+
+def time_connected(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32"), bots_list=(224, 4096)):
+    """The millipede swarm (rods joined by point-wise and lateral connections,
+    magnetized legs in a rotating field): the paper's 224 bots, and 4096 bots
+    that fill the GPU."""
+    from paper_2605_13766_amd import workloads as W
+    out = {"unit": "element-steps/s"}
+    for bots in bots_list:
+        inp = W.millipede_swarm(n_bots=bots)
+        row = {"workload": f"millipede_swarm: {bots} bots of 26 rods (2 backbones x 20 + 24 legs x 8 elements, "
+                           f"{inp.n_elements} elements), {len(inp.conn_k)} connections, rotating field, dt 1e-6 s, "
+                           f"{STEPS_PER_LAUNCH} steps per launch"}
+        for p in precisions:
+            flop, extra = connected_costs(inp, p)
+            r = time_gpu(inp, p, steps, warmup, tile_waves, substeps, algo_flop=flop, extra_bytes=extra,
+                         traffic_tag=f"{p}_millipede{bots}")
+            row[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms": r["launch_ms"],
+                      "roofline": r["roofline"], "tile_waves": r["info"]["tile_waves"],
+                      "substeps_per_launch": r["info"]["substeps"], "algorithmic_flop_per_element_step": flop}
+        out[f"bots{bots}"] = row
     return out
 
 
@@ -329,6 +371,8 @@ def main(argv=None):
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-magnetic", action="store_true")
     ap.add_argument("--no-active", action="store_true")
+    ap.add_argument("--no-connected", action="store_true")
+    ap.add_argument("--connected-bots", default="224,4096", help="swarm sizes of the connected workload")
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the headline batch (profiling runs of the other workloads; value is then null)")
     ap.add_argument("--tile-waves", type=int, default=0, help="fix the tile width (0: autotune)")
@@ -408,6 +452,11 @@ def main(argv=None):
         print("timing the active filaments", file=sys.stderr, flush=True)
         line["active"] = time_active(args.steps, args.warmup, args.tile_waves, args.substeps,
                                      precisions=args.precisions.split(","))
+    if not args.no_connected:
+        print("timing the millipede swarm", file=sys.stderr, flush=True)
+        line["connected"] = time_connected(args.steps, args.warmup, args.tile_waves, args.substeps,
+                                           precisions=args.precisions.split(","),
+                                           bots_list=[int(x) for x in args.connected_bots.split(",")])
     if not args.no_cpu_baseline:
         print("timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inp)
