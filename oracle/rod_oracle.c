@@ -58,8 +58,16 @@
  *     point-wise and by distributed lateral connections): a central
  *     spring-dashpot between two nodes, force on the first
  *     [k (l - l0) + c dl/dt] (x_b - x_a)/l, the opposite on the second,
- *     with pre-kick velocities; its potential 1/2 k (l - l0)^2 is split evenly
- *     between the two rods' W_ext.
+ *     with pre-kick velocities (nothing while the two nodes coincide); its
+ *     potential 1/2 k (l - l0)^2 is split evenly between the two rods' W_ext.
+ *   - planar walls (Results, "Active matter" and "Fibrous granular materials":
+ *     filaments confined by and in frictional contact with boundaries; the
+ *     contact model itself is in the supplement, which is not available): each
+ *     node is a sphere of the rod's radius; penalty normal force
+ *     k delta - c v_n while it penetrates a wall by delta and that force is
+ *     positive, Coulomb friction mu f_n against the tangential velocity,
+ *     regularised as viscous below a slip speed; the penalty potential
+ *     1/2 k delta^2 joins W_ext.
  * Rods joined by connections are advanced together (one batch step), the
  * connection forces from the state of all rods at the kick time.
  */
@@ -107,6 +115,9 @@ typedef struct {
     const double *conn_k;            /* [C] spring stiffness (N/m) */
     const double *conn_c;            /* [C] dashpot coefficient (N s/m) */
     const double *conn_rest;         /* [C] rest distance (m) */
+    int32_t n_walls;                 /* planar boundaries */
+    const double *wall;              /* [n_walls][4]: unit normal nx ny nz, offset d (the wall is n.x = d) */
+    double wall_k, wall_c, wall_mu, wall_vslip;   /* contact stiffness, damping, friction, slip speed */
 } orc_rods;
 
 /* ---------------------------------------------------------------- vectors */
@@ -209,6 +220,9 @@ typedef struct {
     double field_freq;
     const double *grav;          /* [3] */
     const double *fconn;         /* [n+1][3] or NULL: connection forces at this kick */
+    int32_t n_walls;
+    const double *wall;
+    double wall_k, wall_c, wall_mu, wall_vslip;
     const double *mamp;          /* [n-1] or NULL */
     const double *maxis;         /* [3] */
     double mfreq, mwave, mphase;
@@ -239,6 +253,12 @@ static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int6
     v->field_freq = p->field_freq;
     v->grav = p->gravity;
     v->fconn = NULL;
+    v->n_walls = p->n_walls;
+    v->wall = p->wall;
+    v->wall_k = p->wall_k;
+    v->wall_c = p->wall_c;
+    v->wall_mu = p->wall_mu;
+    v->wall_vslip = p->wall_vslip;
     v->mamp = p->muscle_amp ? p->muscle_amp + vo : NULL;
     v->maxis = p->muscle_amp ? p->muscle_axis + 3 * r : NULL;
     v->mfreq = p->muscle_amp ? p->muscle_freq[r] : 0.0;
@@ -337,6 +357,31 @@ static void rod_kinematics(const rod_view *rv, const rod_consts *c, const double
     }
 }
 
+/* Contact of a node (sphere of the rod's radius) with the planar walls: a
+ * penalty normal force k delta - c v_n along the wall normal while the node
+ * penetrates by delta = radius - (n.x - d) and the normal force is positive,
+ * and Coulomb friction -mu f_n v_t / max(|v_t|, v_slip) against the tangential
+ * velocity (viscous below the slip speed).  Adds to f; returns the penalty
+ * potential 1/2 k delta^2 of the contacts. */
+static double wall_force(const rod_view *rv, const double *x, const double *v, double *f)
+{
+    double pot = 0.0;
+    for (int w = 0; w < rv->n_walls; ++w) {
+        const double *nw = &rv->wall[4 * w];
+        const double delta = rv->rad - (dot3(nw, x) - nw[3]);
+        if (!(delta > 0.0)) continue;
+        pot += 0.5 * rv->wall_k * delta * delta;
+        const double vn = dot3(nw, v);
+        const double fn = rv->wall_k * delta - rv->wall_c * vn;
+        if (!(fn > 0.0)) continue;
+        double vt[3] = {v[0] - vn * nw[0], v[1] - vn * nw[1], v[2] - vn * nw[2]};
+        const double speed = sqrt(dot3(vt, vt));
+        const double g = rv->wall_mu * fn / (speed > rv->wall_vslip ? speed : rv->wall_vslip);
+        for (int a = 0; a < 3; ++a) f[a] += fn * nw[a] - g * vt[a];
+    }
+    return pot;
+}
+
 /* Linear accelerations a[n+1][3] and angular accelerations alpha[n][3] of one
  * rod (Eq. 1a and 1b) at state (r, v, Q, om) and time t. */
 static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, const double *v,
@@ -375,12 +420,15 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
         double mass = 0.0;
         if (j > 0) mass += 0.5 * rv->rho * c->A * rv->lh[j - 1];
         if (j < n) mass += 0.5 * rv->rho * c->A * rv->lh[j];
+        double fw[3] = {0.0, 0.0, 0.0};
+        if (rv->n_walls) wall_force(rv, &r[3 * j], &v[3 * j], fw);
         for (int a = 0; a < 3; ++a) {
             double F = 0.0;
             if (j < n) F += w->nint[3 * j + a];
             if (j > 0) F -= w->nint[3 * (j - 1) + a];
             if (rv->fext) F += rv->fext[3 * j + a];
             if (rv->fconn) F += rv->fconn[3 * j + a];
+            F += fw[a];
             F += mass * rv->grav[a];
             acc[3 * j + a] = F / mass - rv->gamma * v[3 * j + a];
         }
@@ -534,6 +582,7 @@ static void conn_forces(const orc_rods *p, const double *pos, const double *vel,
             dv[k] = vel[3 * b + k] - vel[3 * a + k];
         }
         const double l = sqrt(dot3(d, d));
+        if (!(l > 0.0)) continue;   /* coincident nodes: no direction, no force */
         double e[3] = {d[0] / l, d[1] / l, d[2] / l};
         const double mag = p->conn_k[c] * (l - p->conn_rest[c]) + p->conn_c[c] * dot3(e, dv);
         for (int k = 0; k < 3; ++k) {
@@ -726,6 +775,10 @@ int orc_energy(const orc_rods *p, const double *pos, const double *vel, const do
                            x[3 * j + 2] - rv.r0[3 * j + 2]};
             if (rv.fext) Wx -= dot3(&rv.fext[3 * j], d);
             Wx -= mass * dot3(rv.grav, d);
+            if (rv.n_walls) {
+                double fw[3] = {0.0, 0.0, 0.0};
+                Wx += wall_force(&rv, &x[3 * j], &v[3 * j], fw);
+            }
         }
         for (int i = 0; i < n; ++i) {
             double lh = rv.lh[i];

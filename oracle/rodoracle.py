@@ -37,6 +37,8 @@ class _OrcRods(C.Structure):
         ("gravity", C.c_double * 3), ("muscle_amp", _dp), ("muscle_axis", _dp), ("muscle_freq", _dp),
         ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
         ("n_conn", C.c_int32), ("conn_node", _ip), ("conn_k", _dp), ("conn_c", _dp), ("conn_rest", _dp),
+        ("n_walls", C.c_int32), ("wall", _dp), ("wall_k", C.c_double), ("wall_c", C.c_double),
+        ("wall_mu", C.c_double), ("wall_vslip", C.c_double),
     ]
 
 
@@ -150,6 +152,9 @@ class Oracle:
             self.conn = (np.ascontiguousarray(nodes, dtype=np.int32),
                          _d(np.asarray(inp.conn_k, float)), _d(np.asarray(inp.conn_c, float)),
                          _d(np.asarray(inp.conn_rest, float)))
+        wl = getattr(inp, "walls", None)
+        self.walls = None if wl is None or len(wl) == 0 else _d(np.asarray(wl, float).reshape(-1, 4))
+        self.wall_par = [float(getattr(inp, k, 0.0) or 0.0) for k in ("wall_k", "wall_c", "wall_mu", "wall_vslip")]
         self.mat = {k: _d(getattr(inp, k)) for k in
                     ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping")}
         self.bc_start = np.ascontiguousarray(inp.bc_start, dtype=np.int32)
@@ -186,6 +191,10 @@ class Oracle:
         if self.muscle is not None:
             s.muscle_amp, s.muscle_axis, s.muscle_freq, s.muscle_wavenumber, s.muscle_phase = \
                 [_ptr(a) for a in self.muscle]
+        if self.walls is not None:
+            s.n_walls = int(self.walls.shape[0])
+            s.wall = _ptr(self.walls)
+            s.wall_k, s.wall_c, s.wall_mu, s.wall_vslip = self.wall_par
         if self.conn is not None:
             s.n_conn = int(self.conn[0].shape[0])
             s.conn_node = self.conn[0].ctypes.data_as(_ip)

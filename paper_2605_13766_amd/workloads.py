@@ -81,6 +81,11 @@ class RodInputs:
     conn_k: Optional[np.ndarray] = None         # [C] N/m
     conn_c: Optional[np.ndarray] = None         # [C] N s/m
     conn_rest: Optional[np.ndarray] = None      # [C] m
+    walls: Optional[np.ndarray] = None          # [n_walls, 4]: unit normal, offset (wall n.x = d)
+    wall_k: float = 0.0                         # N/m
+    wall_c: float = 0.0                         # N s/m
+    wall_mu: float = 0.0
+    wall_vslip: float = 1e-4                    # m/s
     name: str = ""
 
     # ------------------------------------------------------------------ sizes
@@ -146,6 +151,8 @@ class RodInputs:
             muscle_axis=per_rod(self.muscle_axis), muscle_freq=per_rod(self.muscle_freq),
             muscle_wavenumber=per_rod(self.muscle_wavenumber), muscle_phase=per_rod(self.muscle_phase),
             **self._subset_connections(rods),
+            walls=None if self.walls is None else np.array(self.walls, float).copy(),
+            wall_k=self.wall_k, wall_c=self.wall_c, wall_mu=self.wall_mu, wall_vslip=self.wall_vslip,
             name=self.name + "[subset]",
         )
 
