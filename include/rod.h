@@ -58,6 +58,7 @@ enum { ROD_FREE = 0, ROD_CLAMPED = 1 };
 
 /* Longest rod (elements) one workgroup tile can hold. */
 #define ROD_MAX_ELEMS 512
+#define ROD_MAX_WALLS 8
 
 typedef struct rod_batch rod_batch;
 
@@ -146,6 +147,28 @@ typedef struct {
     const double *conn_k;            /* [C] spring stiffness >= 0 (N/m) */
     const double *conn_c;            /* [C] dashpot coefficient >= 0 (N s/m) */
     const double *conn_rest;         /* [C] rest distance >= 0 (m) */
+    /* Planar walls (Results, "Active matter" and "Fibrous granular materials":
+     * filaments confined by boundaries and in frictional contact with them).
+     * Wall w is the solid half-space n.x < d (walls[w] = {nx, ny, nz, d}, n a
+     * unit normal); every node is a sphere of its rod's radius.  While a node
+     * penetrates a wall by delta = radius - (n.x - d) > 0 it receives the
+     * normal force f_n n, f_n = delta (wall_k - wall_c (n.v)) (damping grows
+     * with the penetration, so the force is continuous at contact onset),
+     * when f_n > 0, and
+     * the friction -wall_mu f_n v_t / max(|v_t|, wall_vslip) against its
+     * tangential velocity v_t (Coulomb, viscous below the slip speed), with
+     * pre-kick velocities at the kick time.  The penalty potential
+     * 1/2 wall_k delta^2 joins W_ext.  Below the slip speed the friction is a
+     * damper of coefficient wall_mu f_n / wall_vslip: the explicit step needs
+     * wall_mu f_n h / (m wall_vslip) well below 2 for node masses m (the
+     * contact frequency sqrt(wall_k / m) enters the stability warning).
+     * Rod-rod contact is not modelled. */
+    int32_t n_walls;                 /* 0..ROD_MAX_WALLS */
+    const double *walls;             /* [n_walls][4], host memory always */
+    double wall_k;                   /* N/m >= 0 */
+    double wall_c;                   /* N s/m^2 >= 0 */
+    double wall_mu;                  /* >= 0 */
+    double wall_vslip;               /* m/s > 0 (with walls) */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -167,7 +190,9 @@ typedef struct {
  * without axis/freq/wavenumber/phase, a magnetization, field, field_freq,
  * gravity or muscle input that is not finite, a connection naming a rod or
  * node outside the batch, joining a node to itself, or with k, c or l0
- * negative or not finite), ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED
+ * negative or not finite; n_walls outside [0, ROD_MAX_WALLS], a wall normal
+ * not of unit length within 1e-9, wall_k, wall_c or wall_mu negative,
+ * wall_vslip <= 0), ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED
  * (tile_waves too small for the longest rod or connected group).
  * A time step above the explicit stability estimate is reported through
  * rod_last_error with ROD_OK.
@@ -208,7 +233,8 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream);
  *   U_bend  = 1/2 sum_k (kappa_k - kappa0_k) . B_k (kappa_k - kappa0_k) Dh_k
  *   W_ext   = -sum f . (r_last - r_last(0)) - sum_j m_j g . (r_j - r_j(0))
  *             + half of 1/2 k (l - l0)^2 of every connection at the rod
- *                                         (the end force, gravity, connections)
+ *             + 1/2 wall_k delta^2 of every node in contact with a wall
+ *                                  (the end force, gravity, connections, walls)
  * The distributed, magnetic and muscle couples have no energy column.  Returns ROD_ENONFINITE if any rod is flagged non-finite.
  */
 int rod_energy(rod_batch *b, double *out, void *stream);

@@ -64,8 +64,9 @@
  *     filaments confined by and in frictional contact with boundaries; the
  *     contact model itself is in the supplement, which is not available): each
  *     node is a sphere of the rod's radius; penalty normal force
- *     k delta - c v_n while it penetrates a wall by delta and that force is
- *     positive, Coulomb friction mu f_n against the tangential velocity,
+ *     delta (k - c v_n) while it penetrates a wall by delta and that force is
+ *     positive (damping grows with the penetration, so the force is continuous
+ *     at contact onset), Coulomb friction mu f_n against the tangential velocity,
  *     regularised as viscous below a slip speed; the penalty potential
  *     1/2 k delta^2 joins W_ext.
  * Rods joined by connections are advanced together (one batch step), the
@@ -358,8 +359,10 @@ static void rod_kinematics(const rod_view *rv, const rod_consts *c, const double
 }
 
 /* Contact of a node (sphere of the rod's radius) with the planar walls: a
- * penalty normal force k delta - c v_n along the wall normal while the node
- * penetrates by delta = radius - (n.x - d) and the normal force is positive,
+ * penalty normal force delta (k - c v_n) along the wall normal (linear spring
+ * with damping proportional to the penetration, which keeps the force
+ * continuous at contact onset) while the node penetrates by
+ * delta = radius - (n.x - d) and the normal force is positive,
  * and Coulomb friction -mu f_n v_t / max(|v_t|, v_slip) against the tangential
  * velocity (viscous below the slip speed).  Adds to f; returns the penalty
  * potential 1/2 k delta^2 of the contacts. */
@@ -372,7 +375,7 @@ static double wall_force(const rod_view *rv, const double *x, const double *v, d
         if (!(delta > 0.0)) continue;
         pot += 0.5 * rv->wall_k * delta * delta;
         const double vn = dot3(nw, v);
-        const double fn = rv->wall_k * delta - rv->wall_c * vn;
+        const double fn = delta * (rv->wall_k - rv->wall_c * vn);
         if (!(fn > 0.0)) continue;
         double vt[3] = {v[0] - vn * nw[0], v[1] - vn * nw[1], v[2] - vn * nw[2]};
         const double speed = sqrt(dot3(vt, vt));

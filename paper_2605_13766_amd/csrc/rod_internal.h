@@ -112,9 +112,16 @@ struct DevBatch {
     const int32_t *conn_partner;   // [2C] partner's compact index within the tile
     const int32_t *conn_key;       // [total] slot * 2 + (0: node i, 1: node n) of each compact index
     const T *conn_par;             // [3][2C] k, c, rest
-    const T *conn_org;             // [3][n_rods] rod origin relative to the first rod of its tile
+    const T *rod_org;              // [3][n_rods] rod origin relative to its tile's first rod (connections or walls)
+    const double *rod_rad;         // [n_rods] rod radius (connections or walls)
+    const T *wall_off;             // [n_tiles][8] wall offsets d in each tile's frame
     int conn_nodes;                // table rows per tile
     int64_t conn_entries;          // 2C
+    // planar walls: n.x = d with the solid on the side n.x < d (d in the lab
+    // frame; the kernels use wall_off)
+    int n_walls;
+    T wall[8][4];
+    T wall_k, wall_c, wall_mu, wall_vslip;
 };
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
@@ -127,6 +134,10 @@ hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s, c
                          int n_map = 0);
 // Largest number of co-resident workgroups of the step kernel (occupancy x CUs).
 int step_resident_groups(int precision_f32, int waves);
+// LDS bytes per workgroup of the step kernel: static, plus the dynamic table of
+// the node-interaction kinds (2: connections, 3: walls) with conn_nodes
+// connected nodes per tile.
+size_t step_lds_bytes(int precision_f32, int waves, int kind, int conn_nodes);
 
 // Read access to a batch for the surrogate runtime (rod_lib.cpp).
 struct BatchView {

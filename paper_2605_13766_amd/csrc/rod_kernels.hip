@@ -252,6 +252,32 @@ __device__ inline void connection_force(const DevBatch<T> &B, const T *tab, int 
     }
 }
 
+// Contact of a node (a sphere of radius `rad` at x, velocity v) with the
+// batch's planar walls: penalty normal force delta (k - c v_n) while it
+// penetrates by delta = rad - (n.x - d) and that force is positive, Coulomb
+// friction -mu f_n v_t / max(|v_t|, v_slip) against the tangential velocity.
+template <typename T>
+__device__ inline void wall_force(const DevBatch<T> &B, const T *woff, T rad, T x0, T x1, T x2, T v0, T v1, T v2,
+                                  T &f0, T &f1, T &f2)
+{
+    for (int w = 0; w < B.n_walls; ++w) {
+        const T n0 = B.wall[w][0], n1 = B.wall[w][1], n2 = B.wall[w][2];
+        const T delta = rad - ((n0 * x0 + n1 * x1 + n2 * x2) - woff[w]);
+        if (delta > T(0)) {
+            const T vn = n0 * v0 + n1 * v1 + n2 * v2;
+            const T fn = delta * (B.wall_k - B.wall_c * vn);
+            if (fn > T(0)) {
+                const T t0 = v0 - vn * n0, t1 = v1 - vn * n1, t2 = v2 - vn * n2;
+                const T sp = dsqrt(t0 * t0 + t1 * t1 + t2 * t2);
+                const T g = B.wall_mu * fn / (sp > B.wall_vslip ? sp : B.wall_vslip);
+                f0 += fn * n0 - g * t0;
+                f1 += fn * n1 - g * t1;
+                f2 += fn * n2 - g * t2;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // One launch: n_sub position-Verlet substeps for every tile (grid-stride).
@@ -288,8 +314,12 @@ __device__ inline void connection_force(const DevBatch<T> &B, const T *tab, int 
 
 // KIND 0: the plain step.  KIND 1: the extended step, for batches with a
 // magnetic couple, gravity or muscle torques.  KIND 2: the extended step with
-// rod-rod connections.  Separate instantiations, so the plain step keeps its
-// registers and LDS.  Each extension a batch lacks contributes an exact zero
+// rod-rod connections (connected node positions in an LDS table).  KIND 3: the
+// extended step with planar walls, with or without connections, which needs
+// every node's position in every substep (FP32: three more LDS columns).
+// Separate instantiations, so each kernel keeps the registers and LDS of what
+// it computes.  FP32 wall tiles run 3 waves per SIMD (2 at 8 waves a tile:
+// their LDS admits one workgroup per CU).  Each extension a batch lacks contributes an exact zero
 // (zero magnetization, amplitude or gravity), so the extended kernel reproduces
 // the plain one bit for bit on a plain batch.  Its multi-wave FP64 tiles and
 // all its FP32 tiles run one wave per SIMD fewer than the plain step's.
@@ -297,7 +327,8 @@ template <typename T, int W, int KIND>
 constexpr int step_waves_per_simd()
 {
     return sizeof(T) == 8 ? ((W == 8 || (KIND > 0 && W > 1)) ? 2 : ROD_F64_WAVES_PER_SIMD)
-                          : (KIND > 0 ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
+                          : (KIND == 3 ? (W == 8 ? 2 : ROD_F32_WAVES_PER_SIMD - 2)
+                                       : KIND > 0 ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
 }
 
 template <typename T, int W, int KIND>
@@ -306,7 +337,8 @@ __attribute__((amdgpu_waves_per_eu(step_waves_per_simd<T, W, KIND>())))
 void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
     constexpr bool EXT = KIND > 0;     // magnetic couple, gravity, muscle torques
-    constexpr bool CONN = KIND == 2;   // and rod-rod connections
+    constexpr bool NODE = KIND >= 2;   // and node interactions (connections, walls)
+    constexpr bool WALL = KIND == 3;   // planar walls: every node's position
     constexpr bool POS = sizeof(T) == 8;   // node positions in memory
     constexpr int TL = 64 * W;
     constexpr int NA = 13;     // from the left: frame (9), length, internal force (3)
@@ -318,8 +350,10 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
     enum { C_J1, C_INV_J1, C_DH, C_INV_DH, C_B1, C_B3, C_K0X, C_K0Y, C_K0Z, C_GAMMA,
            C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3,
            C_MX, C_MY, C_MZ,     // magnetization times rest length (EXT only)
-           C_AX, C_AY, C_AZ };   // muscle amplitude times axis (EXT only)
-    constexpr int N_C = EXT ? C_AZ + 1 : C_MX;
+           C_AX, C_AY, C_AZ,     // muscle amplitude times axis (EXT only)
+           C_RAD,                // rod radius (KIND 3)
+           C_PX, C_PY, C_PZ };   // node i's position (KIND 3, FP32; FP64 has it in registers)
+    constexpr int N_C = WALL ? (POS ? C_RAD + 1 : C_PZ + 1) : (EXT ? C_AZ + 1 : C_MX);
     // One LDS block in a fixed order: the small wave-edge exchange buffers first,
     // so their addresses fit the 8-bit offsets of ds_write2/ds_read2 and need no
     // per-access address arithmetic, then the constant columns.
@@ -491,29 +525,38 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             vn0 = last ? u0 : b0[0]; vn1 = last ? u1 : b0[1]; vn2 = last ? u2 : b0[2];
         }
 
-        // connections: the connected nodes' positions (the frame of the tile's
-        // first rod) into the table
+        // node interactions: node positions (in the frame of the tile's first
+        // rod) into this lane's LDS columns, and the connected nodes' into the
+        // connection table
         int ci = -1, cn = -1, cbase = 0;
-        if constexpr (CONN) {
-            {
+        if constexpr (NODE) {
+            T x0, x1, x2;
+            if constexpr (POS) {
+                x0 = t0; x1 = t1; x2 = t2;   // node i's position
+            } else {
+                // rod origin + anchor + the edges before node i (a prefix sum along the rod)
+                const T e3[3] = {d0, d1, d2};
+                T lf[3];
+                from_left<W>(e3, lf, lxa, wave, wl);
+                x0 = first ? B.rod_org[rr] + t0 : lf[0];
+                x1 = first ? B.rod_org[B.n_rods + rr] + t1 : lf[1];
+                x2 = first ? B.rod_org[2 * B.n_rods + rr] + t2 : lf[2];
+                rod_prefix<W>(x0, x1, x2, i, tab, lane);
+                __syncthreads();
+            }
+            // positions after the opening half drift
+            if constexpr (WALL) {
+                T *cw = cst + lane;
+                cw[C_RAD * TL] = valid ? T(B.rod_rad[rr]) : T(0);
+                if constexpr (!POS) {
+                    cw[C_PX * TL] = x0 + hh * v0; cw[C_PY * TL] = x1 + hh * v1; cw[C_PZ * TL] = x2 + hh * v2;
+                }
+            }
+            if (B.conn_idx) {
                 const int rows = B.conn_nodes;
                 ci = B.conn_idx[s];
                 cn = last ? B.conn_idx[NS + s] : -1;
                 cbase = B.conn_tbase[tile];
-                T x0, x1, x2;
-                if constexpr (POS) {
-                    x0 = t0; x1 = t1; x2 = t2;   // node i's position
-                } else {
-                    // rod origin + anchor + the edges before node i
-                    const T e3[3] = {d0, d1, d2};
-                    T lf[3];
-                    from_left<W>(e3, lf, lxa, wave, wl);
-                    x0 = first ? B.conn_org[rr] + t0 : lf[0];
-                    x1 = first ? B.conn_org[B.n_rods + rr] + t1 : lf[1];
-                    x2 = first ? B.conn_org[2 * B.n_rods + rr] + t2 : lf[2];
-                    rod_prefix<W>(x0, x1, x2, i, tab, lane);
-                    __syncthreads();
-                }
                 if (ci >= 0) { tab[ci] = x0 + hh * v0; tab[rows + ci] = x1 + hh * v1; tab[2 * rows + ci] = x2 + hh * v2; }
                 if (cn >= 0) {
                     tab[cn] = x0 + d0 + hh * u0; tab[rows + cn] = x1 + d1 + hh * u1; tab[2 * rows + cn] = x2 + d2 + hh * u2;
@@ -589,14 +632,27 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
 
             // ---- connection forces on node i and node n (pre-kick velocities)
             T fc0 = 0, fc1 = 0, fc2 = 0, gc0 = 0, gc1 = 0, gc2 = 0;
-            if constexpr (CONN) {
-                {
+            if constexpr (NODE) {
+                if (B.conn_idx) {
                     const int rows = B.conn_nodes;
                     if (ci >= 0) { tab[3 * rows + ci] = v0; tab[4 * rows + ci] = v1; tab[5 * rows + ci] = v2; }
                     if (cn >= 0) { tab[3 * rows + cn] = u0; tab[4 * rows + cn] = u1; tab[5 * rows + cn] = u2; }
                     __syncthreads();
                     if (ci >= 0) connection_force(B, tab, rows, ci, cbase + ci, fc0, fc1, fc2);
                     if (cn >= 0) connection_force(B, tab, rows, cn, cbase + cn, gc0, gc1, gc2);
+                }
+                if constexpr (WALL) {
+                    // node i at x, node n (last lane) at x + the edge
+                    const T rad = cl[C_RAD * TL];
+                    const T *woff = B.wall_off + 8 * (int64_t)tile;
+                    T x0, x1, x2;
+                    if constexpr (POS) {
+                        x0 = t0; x1 = t1; x2 = t2;
+                    } else {
+                        x0 = cl[C_PX * TL]; x1 = cl[C_PY * TL]; x2 = cl[C_PZ * TL];
+                    }
+                    wall_force(B, woff, rad, x0, x1, x2, v0, v1, v2, fc0, fc1, fc2);
+                    if (last) wall_force(B, woff, rad, x0 + d0, x1 + d1, x2 + d2, u0, u1, u2, gc0, gc1, gc2);
                 }
             }
 
@@ -668,8 +724,12 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             const T dd = sub + 1 < n_sub ? h : hh;
             d0 += dd * (vn0 - v0); d1 += dd * (vn1 - v1); d2 += dd * (vn2 - v2);
             t0 += dd * v0; t1 += dd * v1; t2 += dd * v2;
-            if constexpr (CONN) {
-                {
+            if constexpr (NODE) {
+                if constexpr (WALL && !POS) {
+                    T *cw = cst + cofs;
+                    cw[C_PX * TL] += dd * v0; cw[C_PY * TL] += dd * v1; cw[C_PZ * TL] += dd * v2;
+                }
+                if (B.conn_idx) {
                     const int rows = B.conn_nodes;
                     if (ci >= 0) { tab[ci] += dd * v0; tab[rows + ci] += dd * v1; tab[2 * rows + ci] += dd * v2; }
                     if (cn >= 0) { tab[cn] += dd * u0; tab[rows + cn] += dd * u1; tab[2 * rows + cn] += dd * u2; }
@@ -779,7 +839,7 @@ __device__ void conn_node_position(const DevBatch<T> &B, int64_t slot, int col, 
     const int j = B.slot_idx[slot] + col;
     const int64_t s0 = B.rod_slot[rod];
     for (int a = 0; a < 3; ++a) {
-        double v = (double)B.conn_org[a * B.n_rods + rod] + (double)B.tail[(TRX + a) * B.n_rods + rod];
+        double v = (double)B.rod_org[a * B.n_rods + rod] + (double)B.tail[(TRX + a) * B.n_rods + rod];
         for (int k = 0; k < j; ++k) v += (double)B.state[(RX + a) * NS + s0 + k];
         x[a] = v;
     }
@@ -864,6 +924,21 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
             / RP(R_INV_M_TAIL);
         Wx -= Wg;
     }
+    if (B.ext && B.n_walls) {
+        // penalty potential 1/2 k delta^2 of every node in contact with a wall
+        const double rad = (double)B.rod_rad[rod];
+        const T *woff = B.wall_off + 8 * (s0 / (NS / B.n_tiles));
+        for (int j = 0; j <= n; ++j) {
+            double x[3];
+            const int64_t slot = s0 + (j < n ? j : n - 1);
+            conn_node_position(B, slot, j < n ? 0 : 1, x);
+            for (int w = 0; w < B.n_walls; ++w) {
+                const double delta = rad - ((double)B.wall[w][0] * x[0] + (double)B.wall[w][1] * x[1]
+                                            + (double)B.wall[w][2] * x[2] - (double)woff[w]);
+                if (delta > 0) Wx += 0.5 * (double)B.wall_k * delta * delta;
+            }
+        }
+    }
     if (B.ext && B.conn_idx) {
         // half of the potential 1/2 k (l - l0)^2 of every connection at this rod's nodes
         const int64_t TLn = NS / B.n_tiles;
@@ -900,11 +975,15 @@ template <typename T, int W>
 static hipError_t launch_w(const DevBatch<T> &b, int n_sub, int grid, hipStream_t s)
 {
     if (grid <= 0) grid = b.n_tiles;
-    if (b.ext && b.conn_idx) {
-        // connections: the table (6 rows per connected node), and for FP32 the
-        // scratch of the starting prefix sum (3 per lane)
-        const size_t lds = sizeof(T) * (size_t)std::max(6 * b.conn_nodes, sizeof(T) == 4 ? 3 * 64 * W : 0);
-        hipLaunchKernelGGL((rod_step_kernel<T, W, 2>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
+    if (b.ext && (b.conn_idx || b.n_walls)) {
+        // node interactions: the connection table (6 rows per connected node),
+        // and for FP32 the scratch of the starting prefix sum (3 per lane)
+        const size_t lds = sizeof(T) * (size_t)std::max(b.conn_idx ? 6 * b.conn_nodes : 0,
+                                                        sizeof(T) == 4 ? 3 * 64 * W : 0);
+        if (b.n_walls)
+            hipLaunchKernelGGL((rod_step_kernel<T, W, 3>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
+        else
+            hipLaunchKernelGGL((rod_step_kernel<T, W, 2>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
     } else if (b.ext) {
         hipLaunchKernelGGL((rod_step_kernel<T, W, 1>), dim3(grid), dim3(64 * W), 0, s, b, n_sub);
     } else {
@@ -997,6 +1076,41 @@ int step_resident_groups(int precision_f32, int waves)
         }
     }
     return 0;
+}
+
+template <typename T, int W, int KIND>
+static size_t static_lds_w()
+{
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(rod_step_kernel<T, W, KIND>)) != hipSuccess) return 0;
+    return a.sharedSizeBytes;
+}
+
+template <typename T, int KIND>
+static size_t static_lds_t(int waves)
+{
+    switch (waves) {
+    case 1: return static_lds_w<T, 1, KIND>();
+    case 2: return static_lds_w<T, 2, KIND>();
+    case 4: return static_lds_w<T, 4, KIND>();
+    case 8: return static_lds_w<T, 8, KIND>();
+    }
+    return 0;
+}
+
+size_t step_lds_bytes(int precision_f32, int waves, int kind, int conn_nodes)
+{
+    size_t st = 0, dyn = 0;
+    if (precision_f32) {
+        st = kind == 3 ? static_lds_t<float, 3>(waves) : kind == 2 ? static_lds_t<float, 2>(waves)
+           : kind == 1 ? static_lds_t<float, 1>(waves) : static_lds_t<float, 0>(waves);
+        if (kind >= 2) dyn = sizeof(float) * (size_t)std::max(6 * conn_nodes, 3 * 64 * waves);
+    } else {
+        st = kind == 3 ? static_lds_t<double, 3>(waves) : kind == 2 ? static_lds_t<double, 2>(waves)
+           : kind == 1 ? static_lds_t<double, 1>(waves) : static_lds_t<double, 0>(waves);
+        if (kind >= 2) dyn = sizeof(double) * (size_t)(6 * conn_nodes);
+    }
+    return st + dyn;
 }
 
 }  // namespace rodk

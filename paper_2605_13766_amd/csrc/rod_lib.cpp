@@ -108,7 +108,12 @@ struct rod_batch {
     int32_t *d_conn_partner = nullptr; // [2C] partner's compact index within its tile
     int32_t *d_conn_key = nullptr;     // [total] slot * 2 + column of each compact index
     void *d_conn_par = nullptr;        // [3][2C] k, c, rest (state precision)
-    void *d_conn_org = nullptr;        // [3][R] rod origin relative to its tile's first rod
+    void *d_rod_org = nullptr;         // [3][R] rod origins (connections or walls)
+    double *d_rod_rad = nullptr;       // [R] rod radii (walls)
+    void *d_wall_off = nullptr;        // [n_tiles][8] wall offsets in each tile's frame
+    int n_walls = 0;
+    double walls[ROD_MAX_WALLS][4] = {};
+    double wall_k = 0, wall_c = 0, wall_mu = 0, wall_vslip = 0;
     int conn_max_nodes = 0;            // most connected nodes in one tile
     int n_conn = 0;
     double *d_freq = nullptr, *d_phase = nullptr, *d_energy = nullptr;
@@ -125,6 +130,8 @@ struct rod_batch {
 };
 
 namespace {
+
+static_assert(ROD_MAX_WALLS == 8, "DevBatch holds eight walls");
 
 size_t elem_bytes(const rod_batch *b) { return b->precision == ROD_F32 ? 4 : 8; }
 
@@ -217,6 +224,22 @@ int validate(const rod_batch_desc *d)
     if (d->n_connections < 0) return fail(ROD_EINVAL, "n_connections must be >= 0");
     if (d->n_connections > 0 && (!d->conn_rod || !d->conn_node || !d->conn_k || !d->conn_c || !d->conn_rest))
         return fail(ROD_EINVAL, "connections need conn_rod, conn_node, conn_k, conn_c and conn_rest");
+    if (d->n_walls < 0 || d->n_walls > ROD_MAX_WALLS)
+        return fail(ROD_EINVAL, "n_walls must be in [0, " + std::to_string(ROD_MAX_WALLS) + "]");
+    if (d->n_walls > 0) {
+        if (!d->walls) return fail(ROD_EINVAL, "walls is NULL");
+        for (int w = 0; w < d->n_walls; ++w) {
+            const double *n = &d->walls[4 * w];
+            for (int k = 0; k < 4; ++k)
+                if (!std::isfinite(n[k])) return fail(ROD_EINVAL, "wall " + std::to_string(w) + " is not finite");
+            if (std::fabs(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] - 1.0) > 1e-9)
+                return fail(ROD_EINVAL, "wall " + std::to_string(w) + ": the normal must be a unit vector");
+        }
+        if (!(d->wall_k >= 0) || !(d->wall_c >= 0) || !(d->wall_mu >= 0) || !std::isfinite(d->wall_k)
+            || !std::isfinite(d->wall_c) || !std::isfinite(d->wall_mu))
+            return fail(ROD_EINVAL, "wall_k, wall_c and wall_mu must be finite and >= 0");
+        if (!(d->wall_vslip > 0) || !std::isfinite(d->wall_vslip)) return fail(ROD_EINVAL, "wall_vslip must be > 0");
+    }
     return ROD_OK;
 }
 
@@ -367,7 +390,7 @@ int check_values(HostInputs &h)
 
 // Crude explicit stability bound: 2 / (largest natural frequency) over the
 // axial, shear, bending, twisting and rotational-shear modes of one element.
-double stability_dt(const HostInputs &h, const double *field)
+double stability_dt(const HostInputs &h, const double *field, double wall_k = 0.0)
 {
     double dt = 1e300;
     double bmax = 0;   // bound on |b(t)|
@@ -395,6 +418,7 @@ double stability_dt(const HostInputs &h, const double *field)
         w = std::max(w, 2.0 / lmin * std::sqrt(h.G[r] / rho));                       // twist
         w = std::max(w, std::sqrt(2.0 * h.ac[r] * h.G[r] * A / (rho * I)));          // rotational shear
         w = std::max(w, std::sqrt(mmax * bmax / (rho * I)));                         // magnetic restoring couple
+        w = std::max(w, std::sqrt(wall_k / (0.5 * rho * A * lmin)));                // wall contact of an end node
         dt = std::min(dt, 2.0 / w);
     }
     return dt;
@@ -439,7 +463,16 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.conn_partner = b->d_conn_partner;
     d.conn_key = b->d_conn_key;
     d.conn_par = (const T *)b->d_conn_par;
-    d.conn_org = (const T *)b->d_conn_org;
+    d.rod_org = (const T *)b->d_rod_org;
+    d.rod_rad = b->d_rod_rad;
+    d.wall_off = (const T *)b->d_wall_off;
+    d.n_walls = b->n_walls;
+    for (int w = 0; w < 8; ++w)
+        for (int k = 0; k < 4; ++k) d.wall[w][k] = T(w < b->n_walls ? b->walls[w][k] : 0.0);
+    d.wall_k = T(b->wall_k);
+    d.wall_c = T(b->wall_c);
+    d.wall_mu = T(b->wall_mu);
+    d.wall_vslip = T(b->wall_vslip);
     d.conn_nodes = b->conn_max_nodes;
     d.conn_entries = 2 * (int64_t)b->n_conn;
 }
@@ -686,18 +719,6 @@ int build_device(rod_batch *b, const HostInputs &h)
                 par[2 * C + e] = T(h.cc[c]);
                 par[4 * C + e] = T(h.crest[c]);
             }
-        std::vector<T> org((size_t)3 * R, T(0));
-        {
-            std::vector<int32_t> first_rod(b->n_tiles, -1);
-            for (int r = 0; r < R; ++r) {
-                const int tile = b->rod_slot[r] / TL;
-                if (first_rod[tile] < 0 || b->rod_slot[r] < b->rod_slot[first_rod[tile]]) first_rod[tile] = r;
-            }
-            for (int r = 0; r < R; ++r) {
-                const int ref = first_rod[b->rod_slot[r] / TL];
-                for (int a = 0; a < 3; ++a) org[a * R + r] = T(b->origin[3 * r + a] - b->origin[3 * ref + a]);
-            }
-        }
         b->n_conn = C;
         HIPCHK(hipMalloc((void **)&b->d_conn_idx, idx.size() * sizeof(int32_t)));
         HIPCHK(hipMalloc((void **)&b->d_conn_tbase, tbase.size() * sizeof(int32_t)));
@@ -705,14 +726,45 @@ int build_device(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc((void **)&b->d_conn_partner, partner.size() * sizeof(int32_t)));
         HIPCHK(hipMalloc((void **)&b->d_conn_key, std::max<size_t>(ckey.size(), 1) * sizeof(int32_t)));
         HIPCHK(hipMalloc(&b->d_conn_par, par.size() * es));
-        HIPCHK(hipMalloc(&b->d_conn_org, org.size() * es));
+
         HIPCHK(hipMemcpy(b->d_conn_idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_tbase, tbase.data(), tbase.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_partner, partner.data(), partner.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_key, ckey.data(), ckey.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_par, par.data(), par.size() * es, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->d_conn_org, org.data(), org.size() * es, hipMemcpyHostToDevice));
+    }
+    if (!h.ck.empty() || b->n_walls > 0) {
+        // FP32 node interactions work in the frame of each tile's first rod
+        // (small coordinates): rod origins relative to it, and the walls'
+        // offsets d - n . (its origin) per tile. FP64 keeps lab-frame node
+        // positions, so there the reference is the lab origin.
+        const bool rel = sizeof(T) == 4;
+        const int TL = 64 * b->waves;
+        std::vector<int32_t> first_rod(b->n_tiles, -1);
+        for (int r = 0; r < R; ++r) {
+            const int tile = b->rod_slot[r] / TL;
+            if (first_rod[tile] < 0 || b->rod_slot[r] < b->rod_slot[first_rod[tile]]) first_rod[tile] = r;
+        }
+        std::vector<T> org((size_t)3 * R, T(0));
+        for (int r = 0; r < R; ++r) {
+            const int ref = first_rod[b->rod_slot[r] / TL];
+            for (int a = 0; a < 3; ++a)
+                org[a * R + r] = rel ? T(b->origin[3 * r + a] - b->origin[3 * ref + a]) : T(0);
+        }
+        std::vector<T> woff((size_t)8 * b->n_tiles, T(0));
+        for (int t = 0; t < b->n_tiles; ++t)
+            for (int w = 0; w < b->n_walls; ++w) {
+                const double *o = rel && first_rod[t] >= 0 ? &b->origin[3 * first_rod[t]] : nullptr;
+                const double shift = o ? b->walls[w][0] * o[0] + b->walls[w][1] * o[1] + b->walls[w][2] * o[2] : 0.0;
+                woff[(size_t)8 * t + w] = T(b->walls[w][3] - shift);
+            }
+        HIPCHK(hipMalloc(&b->d_wall_off, woff.size() * es));
+        HIPCHK(hipMemcpy(b->d_wall_off, woff.data(), woff.size() * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc(&b->d_rod_org, org.size() * es));
+        HIPCHK(hipMemcpy(b->d_rod_org, org.data(), org.size() * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc((void **)&b->d_rod_rad, (size_t)R * sizeof(double)));
+        HIPCHK(hipMemcpy(b->d_rod_rad, h.rad.data(), (size_t)R * sizeof(double), hipMemcpyHostToDevice));
     }
     if (b->muscle) {
         // amplitude times axis and the phase offset phi - q s_k at the Voronoi
@@ -1059,8 +1111,15 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     }
     b->muscle = d->muscle_amp != nullptr;
     for (int a = 0; a < 3; ++a) b->grav[a] = d->gravity[a];
+    b->n_walls = d->n_walls;
+    for (int w = 0; w < d->n_walls; ++w)
+        for (int k = 0; k < 4; ++k) b->walls[w][k] = d->walls[4 * w + k];
+    b->wall_k = d->wall_k;
+    b->wall_c = d->wall_c;
+    b->wall_mu = d->wall_mu;
+    b->wall_vslip = d->wall_vslip;
     b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0
-           || d->n_connections > 0;
+           || d->n_connections > 0 || d->n_walls > 0;
     b->clamp_r0.assign(3 * b->R, 0.0);
     b->clamp_rn.assign(3 * b->R, 0.0);
     b->clamp_q0.assign(9 * b->R, 0.0);
@@ -1090,12 +1149,26 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     fill_dev(b->b64, b);
     fill_dev(b->b32, b);
     b->grid = b->n_tiles;
+    {
+        // the kernel this batch runs must fit the workgroup's LDS
+        const int kind = !b->ext ? 0 : b->n_walls > 0 ? 3 : b->n_conn > 0 ? 2 : 1;
+        int dev = 0, limit = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) limit = 65536;
+        const size_t need = rodk::step_lds_bytes(b->precision == ROD_F32, b->waves, kind, b->conn_max_nodes);
+        if (need > (size_t)limit) {
+            rod_batch_destroy(b);
+            return fail(ROD_EUNSUPPORTED, "tiles of " + std::to_string(waves) + " waves need " + std::to_string(need)
+                                              + " bytes of LDS for this batch (the device allows "
+                                              + std::to_string(limit) + "); use narrower tiles");
+        }
+    }
     hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         rod_batch_destroy(b);
         return fail(ROD_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
-    const double dts = stability_dt(h, d->field);
+    const double dts = stability_dt(h, d->field, d->n_walls > 0 ? d->wall_k : 0.0);
     if (d->dt > dts) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "warning: dt %.3g exceeds the explicit stability estimate %.3g", d->dt, dts);
@@ -1237,7 +1310,9 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->d_conn_partner);
     (void)hipFree(b->d_conn_key);
     (void)hipFree(b->d_conn_par);
-    (void)hipFree(b->d_conn_org);
+    (void)hipFree(b->d_rod_org);
+    (void)hipFree(b->d_rod_rad);
+    (void)hipFree(b->d_wall_off);
     (void)hipFree(b->d_freq);
     (void)hipFree(b->d_phase);
     (void)hipFree(b->d_energy);

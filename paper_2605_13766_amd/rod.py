@@ -41,6 +41,8 @@ class RodBatchDesc(C.Structure):
         ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
         ("n_connections", C.c_int32), ("conn_rod", _ip), ("conn_node", _ip), ("conn_k", _dp), ("conn_c", _dp),
         ("conn_rest", _dp),
+        ("n_walls", C.c_int32), ("walls", _dp), ("wall_k", C.c_double), ("wall_c", C.c_double),
+        ("wall_mu", C.c_double), ("wall_vslip", C.c_double),
     ]
 
 
@@ -221,6 +223,13 @@ class RodBatch:
             setattr(d, name, ptr(name, _dp))
         cr = getattr(inp, "conn_rod", None)
         d.n_connections = 0 if cr is None else int(np.asarray(cr).shape[0])
+        wl = getattr(inp, "walls", None)
+        if wl is not None and len(wl) > 0:
+            keep["walls"] = np.ascontiguousarray(np.asarray(wl, dtype=np.float64).reshape(-1, 4))   # host always
+            d.n_walls = int(keep["walls"].shape[0])
+            d.walls = keep["walls"].ctypes.data_as(_dp)
+            d.wall_k, d.wall_c = float(inp.wall_k), float(inp.wall_c)
+            d.wall_mu, d.wall_vslip = float(inp.wall_mu), float(inp.wall_vslip)
         d.dt = float(inp.dt)
         d.t0 = float(t0)
         d.precision = prec

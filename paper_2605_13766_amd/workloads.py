@@ -83,7 +83,7 @@ class RodInputs:
     conn_rest: Optional[np.ndarray] = None      # [C] m
     walls: Optional[np.ndarray] = None          # [n_walls, 4]: unit normal, offset (wall n.x = d)
     wall_k: float = 0.0                         # N/m
-    wall_c: float = 0.0                         # N s/m
+    wall_c: float = 0.0                         # N s/m^2 (damping per unit penetration)
     wall_mu: float = 0.0
     wall_vslip: float = 1e-4                    # m/s
     name: str = ""
@@ -474,7 +474,7 @@ def magnetic_carpet(grid=256, n=50, L=0.01, radius=2e-4, youngs=1e6, spacing=2.5
 
 def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period=1.0,
                      wavelength=None, curvature_amp=3.0, g=9.81, damping=0.5, dt=5e-5,
-                     seed=SEED_BASE + 7):
+                     seed=SEED_BASE + 7, box=False, wall_k=1e4, wall_c=2e4, wall_mu=0.3, wall_vslip=1e-3):
     """Free straight filaments at random positions and orientations in a cube of
     side 2L, under gravity (-z) and each driven by a travelling muscle wave.
 
@@ -487,7 +487,8 @@ def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period
     """
     rng = np.random.default_rng(seed)
     wavelength = L if wavelength is None else wavelength
-    base = rng.uniform(0.0, 2.0 * L, size=(n_rods, 3))
+    # with box=True, centres stay within [L/2, 3L/2] so every node starts inside the 2L box
+    base = rng.uniform(0.5 * L, 1.5 * L, size=(n_rods, 3)) if box else rng.uniform(0.0, 2.0 * L, size=(n_rods, 3))
     d3 = _unit(rng.normal(size=(n_rods, 3)))
     s = np.linspace(0.0, L, n + 1)
     nodes = base[:, None, :] + (s - 0.5 * L)[None, :, None] * d3[:, None, :]
@@ -505,6 +506,12 @@ def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period
     inp.muscle_freq = np.full(n_rods, 1.0 / period)
     inp.muscle_wavenumber = np.full(n_rods, 2.0 * np.pi / wavelength)
     inp.muscle_phase = rng.uniform(0.0, 2.0 * np.pi, size=n_rods)
+    if box:
+        # the paper's cuboidal box of side 2L: floor, ceiling and four side walls
+        inp.walls = np.array([[0, 0, 1, 0], [0, 0, -1, -2 * L], [1, 0, 0, 0], [-1, 0, 0, -2 * L],
+                              [0, 1, 0, 0], [0, -1, 0, -2 * L]], float)
+        inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = wall_k, wall_c, wall_mu, wall_vslip
+        inp.name = "active_box"
     return inp
 
 

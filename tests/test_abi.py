@@ -158,3 +158,16 @@ def test_connection_descriptor_rejected_when_invalid():
     assert ">= 0" in _expect(rod.ROD_EINVAL, bad)
     bad = base.copy(); bad.conn_rest = None
     assert "conn_rest" in _expect(rod.ROD_EINVAL, bad)
+
+
+def test_wall_descriptor_rejected_when_invalid():
+    from paper_2605_13766_amd import rod
+    base = W.active_filaments(n_rods=3, n=8, box=True)
+    bad = base.copy(); bad.walls = base.walls.copy(); bad.walls[0, :3] = [0.0, 0.0, 2.0]
+    assert "unit vector" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.walls = np.tile(base.walls, (2, 1))
+    assert "n_walls" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.wall_mu = -0.1
+    assert ">= 0" in _expect(rod.ROD_EINVAL, bad)
+    bad = base.copy(); bad.wall_vslip = 0.0
+    assert "wall_vslip" in _expect(rod.ROD_EINVAL, bad)

@@ -2,7 +2,7 @@
 granular materials": filaments confined by boundaries and in frictional
 contact with them; the contact model is in the unavailable supplement, so the
 reading is a penalty contact per node, a sphere of the rod's radius, with
-normal damping and regularised Coulomb friction):
+damping proportional to the penetration and regularised Coulomb friction):
 
 * a straight rod lying on the floor under gravity settles with every node
   sunk by its own weight over the stiffness, delta_j = m_j g / k;
@@ -45,7 +45,7 @@ def test_resting_rod_sinks_by_its_weight():
     a one-element rod, whose two nodes carry equal loads, sinks uniformly by
     exactly m g / k."""
     k = 100.0
-    o = ro.Oracle(_rod(RAD, k=k, c=0.05, damping=5.0))
+    o = ro.Oracle(_rod(RAD, k=k, c=500.0, damping=5.0))
     o.step(100000)
     M = _masses().sum()
     carried = k * np.sum(RAD - o.pos[:, 2])
@@ -55,7 +55,7 @@ def test_resting_rod_sinks_by_its_weight():
     one = RC.single(nodes, Q, E=1e6, radius=RAD, damping=5.0, dt=1e-5)
     one.gravity = np.array([0.0, 0.0, -9.81])
     one.walls = FLOOR.copy()
-    one.wall_k, one.wall_c, one.wall_mu = k, 0.05, 0.0
+    one.wall_k, one.wall_c, one.wall_mu = k, 500.0, 0.0
     o1 = ro.Oracle(one)
     o1.step(100000)
     m = 0.5 * 1000.0 * np.pi * RAD ** 2 * 0.01
@@ -65,7 +65,7 @@ def test_resting_rod_sinks_by_its_weight():
 def test_sliding_rod_decelerates_at_mu_g():
     k, mu, v0 = 100.0, 0.3, 0.5
     z0 = RAD - _masses() * 9.81 / k          # start at the resting penetration
-    inp = _rod(RAD, k=k, c=0.05, mu=mu, vel=np.tile([v0, 0.0, 0.0], (N + 1, 1)))
+    inp = _rod(RAD, k=k, c=500.0, mu=mu, vel=np.tile([v0, 0.0, 0.0], (N + 1, 1)))
     inp.position[:, 2] = z0
     o = ro.Oracle(inp)
     for _ in range(5):
