@@ -8,16 +8,17 @@ substeps per launch S chosen by the library's autotuner).  The headline value is
 FP32 figure rides along in the same JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate] [--no-magnetic]
-                  [--no-active] [--no-connected]
+                  [--no-active] [--no-walls] [--no-connected]
 
 The magnetic carpet rides along as the "magnetic" object: 65,536 base-clamped
 rods x 50 elements (FP32) turned by a rotating homogeneous field through their
 programmed magnetization, timed like the headline and next to the same carpet
 driven by its distributed couple.  The "active" object times 16,384 free
 filaments x 50 elements under gravity and travelling-wave muscle moments in
-both precisions; the "connected" object times millipede-like bots of rods
-joined by point-wise and lateral spring-dashpot connections (224 bots, and
-4096 to fill the GPU).
+both precisions, and the "walls" object the same filaments confined in a box
+of six planar walls (penalty contact with Coulomb friction); the "connected"
+object times millipede-like bots of rods joined by point-wise and lateral
+spring-dashpot connections (224 bots, and 4096 to fill the GPU).
 
 The learned coarse step rides along as the "surrogate" object: the network is
 trained on 16,384 carpet rods (64 elements, 2.1e6 windows from plain
@@ -60,6 +61,8 @@ ALGO_BYTES = {"f64": 400, "f32": 204}            # HBM bytes per element per lau
 MAG_BYTES = 12                                   # FP32 magnetization x rest length, read once per launch
 MUSCLE_BYTES = {"f64": 32, "f32": 20}            # muscle amplitude x axis (T) and phase offset (FP64)
 CONN_FLOP = 30                                   # one spring-dashpot force per connection and step
+WALL_TEST_FLOP = 7                               # one node against one wall: n.x (5), minus offset and radius (2)
+CONTACT_FLOP = 35                                # one node-wall contact: normal force 8, friction 15, sum 12
 PEAK = {"f64": 78.6, "f32": 157.3}               # TFLOP/s, MI355X vector peaks
 STEPS_PER_LAUNCH = 1000
 SURR_K = 32
@@ -77,8 +80,8 @@ def kernel_hash() -> str:
 def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source in the same launch shape (else None).
-    tag: f64_ragged4096, f32_ragged4096, f32_magnetic65536, f64_active16384 or
-    f32_active16384."""
+    tag: {f64,f32}_ragged4096, f32_magnetic65536, {f64,f32}_active16384,
+    {f64,f32}_activebox16384 or {f64,f32}_millipede{224,4096}."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"rod_step_{tag}*_traffic.json"))):
         with open(path) as f:
@@ -90,7 +93,10 @@ def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
 
 
 def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=ALGO_FLOP, extra_bytes=0,
-             traffic_tag=None):
+             traffic_tag=None, probe=None):
+    """Times `steps` bench steps after `warmup`.  algo_flop: FLOP per
+    element-step, or a function of (probe before, probe after) when probe(batch)
+    measures state the work depends on (outside the timed region)."""
     import torch
     from paper_2605_13766_amd import rod
 
@@ -104,6 +110,8 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         for _ in range(warmup):
             b.step(STEPS_PER_LAUNCH, stream=stream)
         torch.cuda.synchronize()
+        before = probe(b, stream) if probe else None
+        torch.cuda.synchronize()
         starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
         ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
         t0 = time.perf_counter()
@@ -114,12 +122,15 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         launch_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+        after = probe(b, stream) if probe else None
         flags = b.flags(stream=stream)
         b.close()
     if flags.any():
         raise RuntimeError(f"{int(flags.sum())} rods became non-finite")
     el_steps = inp.n_elements * STEPS_PER_LAUNCH
     value = el_steps * steps / wall
+    if probe:
+        algo_flop = algo_flop(before, after)
     achieved = algo_flop * el_steps / (launch_ms * 1e-3) / 1e12
     traffic = traffic_from_profile(traffic_tag or f"{precision}_ragged4096", info["tile_waves"], info["substeps"])
     return {
@@ -127,6 +138,8 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         "ms_per_step": wall / steps * 1e3,
         "launch_ms": launch_ms,
         "info": info,
+        "algo_flop": algo_flop,
+        "probe": (before, after) if probe else None,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
@@ -174,6 +187,56 @@ def time_active(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32
         out[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms": r["launch_ms"],
                   "roofline": r["roofline"], "tile_waves": r["info"]["tile_waves"],
                   "substeps_per_launch": r["info"]["substeps"]}
+    return out
+
+
+def wall_costs(inp, precision):
+    """Algorithmic FLOP per element-step (a function of the node-wall contacts
+    per element, measured before and after the timed steps) and extra bytes per
+    element per launch of the boxed active filaments: the active step, every
+    node tested against every wall, the contact force of every node-wall pair
+    in contact (the mean of the two counts); bytes for the rod radii."""
+    ne, R = inp.n_elements, inp.n_rods
+    n_walls = len(inp.walls)
+    base = ALGO_FLOP_ACTIVE + WALL_TEST_FLOP * n_walls * (ne + R) / ne
+
+    def flop(before, after):
+        return base + CONTACT_FLOP * 0.5 * (before + after)
+
+    extra = MUSCLE_BYTES[precision] + 8 * R / ne
+    return flop, extra
+
+
+def contacts_per_element(inp):
+    """probe for time_gpu: node-wall pairs in contact per element."""
+    walls = np.asarray(inp.walls, dtype=np.float64)
+    rad = np.repeat(np.asarray(inp.radius, dtype=np.float64), np.asarray(inp.n_elems) + 1)
+
+    def probe(b, stream):
+        pos = b.get_state(stream=stream)[0]
+        delta = rad[:, None] - (pos @ walls[:, :3].T - walls[None, :, 3])
+        return float(np.count_nonzero(delta > 0)) / inp.n_elements
+
+    return probe
+
+
+def time_walls(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32")):
+    """Active filaments confined in a box: the active workload with six
+    planar walls (penalty contact, Coulomb friction), both precisions."""
+    from paper_2605_13766_amd import workloads as W
+    inp = W.active_filaments(box=True)
+    out = {"workload": f"active_box: 16,384 free rods x 50 elements in a 2 m box of {len(inp.walls)} walls "
+                       f"(k {inp.wall_k:g} N/m^2, c {inp.wall_c:g} N s/m^2, mu {inp.wall_mu:g}), gravity, travelling "
+                       f"muscle moments, dt 5e-5 s, {STEPS_PER_LAUNCH} steps per launch",
+           "unit": "element-steps/s"}
+    for p in precisions:
+        flop, extra = wall_costs(inp, p)
+        r = time_gpu(inp, p, steps, warmup, tile_waves, substeps, algo_flop=flop, extra_bytes=extra,
+                     traffic_tag=f"{p}_activebox16384", probe=contacts_per_element(inp))
+        out[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms": r["launch_ms"],
+                  "roofline": r["roofline"], "tile_waves": r["info"]["tile_waves"],
+                  "substeps_per_launch": r["info"]["substeps"], "algorithmic_flop_per_element_step": r["algo_flop"],
+                  "contacts_per_element": {"before": r["probe"][0], "after": r["probe"][1]}}
     return out
 
 
@@ -372,6 +435,7 @@ def main(argv=None):
     ap.add_argument("--no-magnetic", action="store_true")
     ap.add_argument("--no-active", action="store_true")
     ap.add_argument("--no-connected", action="store_true")
+    ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--connected-bots", default="224,4096", help="swarm sizes of the connected workload")
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the headline batch (profiling runs of the other workloads; value is then null)")
@@ -452,6 +516,10 @@ def main(argv=None):
         print("timing the active filaments", file=sys.stderr, flush=True)
         line["active"] = time_active(args.steps, args.warmup, args.tile_waves, args.substeps,
                                      precisions=args.precisions.split(","))
+    if not args.no_walls:
+        print("timing the active filaments in a box", file=sys.stderr, flush=True)
+        line["walls"] = time_walls(args.steps, args.warmup, args.tile_waves, args.substeps,
+                                   precisions=args.precisions.split(","))
     if not args.no_connected:
         print("timing the millipede swarm", file=sys.stderr, flush=True)
         line["connected"] = time_connected(args.steps, args.warmup, args.tile_waves, args.substeps,

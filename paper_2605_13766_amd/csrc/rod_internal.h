@@ -62,6 +62,8 @@ enum RodParam {
 
 enum RodFlags { FLAG_CLAMP0 = 1, FLAG_CLAMP1 = 2, FLAG_COUPLE = 4 };
 
+constexpr int DEV_MAX_WALLS = 8;   // planar walls a batch may hold
+
 template <typename T>
 struct DevBatch {
     T *state;              // [N_STATE][n_slots]
@@ -120,7 +122,7 @@ struct DevBatch {
     // planar walls: n.x = d with the solid on the side n.x < d (d in the lab
     // frame; the kernels use wall_off)
     int n_walls;
-    T wall[8][4];
+    T wall[DEV_MAX_WALLS][4];
     T wall_k, wall_c, wall_mu, wall_vslip;
 };
 

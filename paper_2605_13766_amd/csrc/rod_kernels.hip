@@ -256,26 +256,48 @@ __device__ inline void connection_force(const DevBatch<T> &B, const T *tab, int 
 // batch's planar walls: penalty normal force delta (k - c v_n) while it
 // penetrates by delta = rad - (n.x - d) and that force is positive, Coulomb
 // friction -mu f_n v_t / max(|v_t|, v_slip) against the tangential velocity.
+// wl: the walls as (n, d) quadruples in LDS, d in the tile's frame; unrolled
+// to the maximum count so that every wall's reads issue at once.
 template <typename T>
-__device__ inline void wall_force(const DevBatch<T> &B, const T *woff, T rad, T x0, T x1, T x2, T v0, T v1, T v2,
+__device__ inline void wall_force(const DevBatch<T> &B, const T *wl, T rad, T x0, T x1, T x2, T v0, T v1, T v2,
                                   T &f0, T &f1, T &f2)
 {
-    for (int w = 0; w < B.n_walls; ++w) {
-        const T n0 = B.wall[w][0], n1 = B.wall[w][1], n2 = B.wall[w][2];
-        const T delta = rad - ((n0 * x0 + n1 * x1 + n2 * x2) - woff[w]);
+#pragma unroll
+    for (int w = 0; w < DEV_MAX_WALLS; ++w) {
+        if (w >= B.n_walls) break;
+        const T n0 = wl[4 * w], n1 = wl[4 * w + 1], n2 = wl[4 * w + 2];
+        const T delta = rad - ((n0 * x0 + n1 * x1 + n2 * x2) - wl[4 * w + 3]);
         if (delta > T(0)) {
             const T vn = n0 * v0 + n1 * v1 + n2 * v2;
             const T fn = delta * (B.wall_k - B.wall_c * vn);
             if (fn > T(0)) {
                 const T t0 = v0 - vn * n0, t1 = v1 - vn * n1, t2 = v2 - vn * n2;
-                const T sp = dsqrt(t0 * t0 + t1 * t1 + t2 * t2);
-                const T g = B.wall_mu * fn / (sp > B.wall_vslip ? sp : B.wall_vslip);
+                // 1 / max(|v_t|, v_slip) as one reciprocal square root
+                const T s2 = t0 * t0 + t1 * t1 + t2 * t2, vs2 = B.wall_vslip * B.wall_vslip;
+                const T g = B.wall_mu * fn * rsqrt_t(s2 > vs2 ? s2 : vs2);
                 f0 += fn * n0 - g * t0;
                 f1 += fn * n1 - g * t1;
                 f2 += fn * n2 - g * t2;
             }
         }
     }
+}
+
+// Screen of the wall contacts of a lane: some wall within `reach` of x (the
+// largest rad + reach - (n.x - d) is positive).  Branch-free over the walls,
+// so that the contact forces run only in lanes near a wall.
+template <typename T>
+__device__ inline bool wall_reach(const DevBatch<T> &B, const T *wl, T reach, T x0, T x1, T x2)
+{
+    T m = T(-1);
+#pragma unroll
+    for (int w = 0; w < DEV_MAX_WALLS; ++w) {
+        if (w < B.n_walls) {
+            const T sw = reach - ((wl[4 * w] * x0 + wl[4 * w + 1] * x1 + wl[4 * w + 2] * x2) - wl[4 * w + 3]);
+            m = sw > m ? sw : m;
+        }
+    }
+    return m > T(0);
 }
 
 }  // namespace
@@ -362,6 +384,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         T lxb[NL * NB];
         double phs[2 * TL];        // couple phase increment: sin, cos
         double mph[EXT ? 2 * TL : 1];   // muscle phase increment: sin, cos (EXT only)
+        T wls[WALL ? 4 * DEV_MAX_WALLS : 1];   // walls (n, d), d in the tile's frame (KIND 3)
         T cst[N_C * TL];
     };
     __shared__ Shared sh;
@@ -546,6 +569,13 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             }
             // positions after the opening half drift
             if constexpr (WALL) {
+                if (lane < 4 * B.n_walls) {
+                    const int w = lane >> 2, a = lane & 3;
+                    sh.wls[lane] = a < 3 ? B.wall[w][a] : B.wall_off[8 * (int64_t)tile + w];
+                }
+                // every wave reads all walls (the previous tile's last reads
+                // are behind the barrier of its last exchange B)
+                __syncthreads();
                 T *cw = cst + lane;
                 cw[C_RAD * TL] = valid ? T(B.rod_rad[rr]) : T(0);
                 if constexpr (!POS) {
@@ -644,15 +674,19 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 if constexpr (WALL) {
                     // node i at x, node n (last lane) at x + the edge
                     const T rad = cl[C_RAD * TL];
-                    const T *woff = B.wall_off + 8 * (int64_t)tile;
                     T x0, x1, x2;
                     if constexpr (POS) {
                         x0 = t0; x1 = t1; x2 = t2;
                     } else {
                         x0 = cl[C_PX * TL]; x1 = cl[C_PY * TL]; x2 = cl[C_PZ * TL];
                     }
-                    wall_force(B, woff, rad, x0, x1, x2, v0, v1, v2, fc0, fc1, fc2);
-                    if (last) wall_force(B, woff, rad, x0 + d0, x1 + d1, x2 + d2, u0, u1, u2, gc0, gc1, gc2);
+                    // node n lies within |d| = l of node i: on a rod's last
+                    // lane one screen covers both (up to the rounding of the
+                    // positions)
+                    if (wall_reach(B, sh.wls, last ? rad + l : rad, x0, x1, x2)) {
+                        wall_force(B, sh.wls, rad, x0, x1, x2, v0, v1, v2, fc0, fc1, fc2);
+                        if (last) wall_force(B, sh.wls, rad, x0 + d0, x1 + d1, x2 + d2, u0, u1, u2, gc0, gc1, gc2);
+                    }
                 }
             }
 

@@ -131,7 +131,7 @@ struct rod_batch {
 
 namespace {
 
-static_assert(ROD_MAX_WALLS == 8, "DevBatch holds eight walls");
+static_assert(ROD_MAX_WALLS == rodk::DEV_MAX_WALLS, "the device batch holds ROD_MAX_WALLS walls");
 
 size_t elem_bytes(const rod_batch *b) { return b->precision == ROD_F32 ? 4 : 8; }
 
