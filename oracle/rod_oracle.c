@@ -69,8 +69,18 @@
  *     at contact onset), Coulomb friction mu f_n against the tangential velocity,
  *     regularised as viscous below a slip speed; the penalty potential
  *     1/2 k delta^2 joins W_ext.
- * Rods joined by connections are advanced together (one batch step), the
- * connection forces from the state of all rods at the kick time.
+ *   - rod-rod contact (Results, "Fibrous granular materials" and the
+ *     collision engine the paper names as future work; the contact law is in
+ *     the unavailable supplement): nodes are spheres of their rod's radius,
+ *     as for the walls; two nodes of different rods touch when their centres
+ *     are closer than the sum of the radii, and each feels the wall law with
+ *     the overlap of the two spheres, the normal from the other's centre and
+ *     their relative velocity (so the pair's forces are equal and opposite);
+ *     half of each pair's penalty potential goes to each rod's W_ext.  A rod
+ *     does not touch itself.  (Crossing rods whose elements are longer than
+ *     their diameters can pass between nodes.)
+ * Rods joined by connections or in contact are advanced together (one batch
+ * step), the coupling forces from the state of all rods at the kick time.
  */
 #include <math.h>
 #include <stdint.h>
@@ -119,6 +129,7 @@ typedef struct {
     int32_t n_walls;                 /* planar boundaries */
     const double *wall;              /* [n_walls][4]: unit normal nx ny nz, offset d (the wall is n.x = d) */
     double wall_k, wall_c, wall_mu, wall_vslip;   /* contact stiffness, damping, friction, slip speed */
+    int32_t rod_contact;             /* 1: contact between nodes of different rods (same law) */
 } orc_rods;
 
 /* ---------------------------------------------------------------- vectors */
@@ -595,7 +606,57 @@ static void conn_forces(const orc_rods *p, const double *pos, const double *vel,
     }
 }
 
-/* All rods together, one step at a time (rods joined by connections). */
+/* Contact force on node a (a sphere of radius ra at xa, velocity va) from
+ * node b of another rod: the wall law with the overlap of the two spheres,
+ * the normal from b to a and their relative velocity.  Adds to f; returns the
+ * overlap (<= 0 without contact). */
+static double sphere_force(const orc_rods *p, const double *xa, const double *va, double ra, const double *xb,
+                           const double *vb, double rb, double *f)
+{
+    const double d[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
+    const double dist = sqrt(dot3(d, d));
+    const double delta = ra + rb - dist;
+    if (!(delta > 0.0) || !(dist > 0.0)) return delta;   /* coincident centres: no direction */
+    const double n[3] = {d[0] / dist, d[1] / dist, d[2] / dist};
+    const double vr[3] = {va[0] - vb[0], va[1] - vb[1], va[2] - vb[2]};
+    const double vn = dot3(n, vr);
+    const double fn = delta * (p->wall_k - p->wall_c * vn);
+    if (!(fn > 0.0)) return delta;
+    const double vt[3] = {vr[0] - vn * n[0], vr[1] - vn * n[1], vr[2] - vn * n[2]};
+    const double speed = sqrt(dot3(vt, vt));
+    const double g = p->wall_mu * fn / (speed > p->wall_vslip ? speed : p->wall_vslip);
+    for (int k = 0; k < 3; ++k) f[k] += fn * n[k] - g * vt[k];
+    return delta;
+}
+
+/* Rod-rod contact forces at the current state, added to fc [N_n][3] (if
+ * non-NULL): every ordered pair of nodes of different rods, by brute force.
+ * With pot (non-NULL, [R]) adds a quarter of k delta^2 per ordered pair to
+ * the first node's rod (half of each pair's potential to each rod). */
+static void contact_forces(const orc_rods *p, const double *pos, const double *vel, double *fc,
+                           const int64_t *no, double *pot)
+{
+    const int R = p->n_rods;
+    for (int ra = 0; ra < R; ++ra)
+        for (int i = 0; i <= p->n_elems[ra]; ++i) {
+            const int64_t a = no[ra] + i;
+            double f[3] = {0.0, 0.0, 0.0};
+            for (int rb = 0; rb < R; ++rb) {
+                if (rb == ra) continue;
+                for (int j = 0; j <= p->n_elems[rb]; ++j) {
+                    const int64_t b = no[rb] + j;
+                    const double delta = sphere_force(p, &pos[3 * a], &vel[3 * a], p->radius[ra], &pos[3 * b],
+                                                      &vel[3 * b], p->radius[rb], f);
+                    if (pot && delta > 0.0) pot[ra] += 0.25 * p->wall_k * delta * delta;
+                }
+            }
+            if (fc)
+                for (int k = 0; k < 3; ++k) fc[3 * a + k] += f[k];
+        }
+}
+
+/* All rods together, one step at a time (rods joined by connections or in
+ * contact). */
 static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double *dir, double *omega,
                             int64_t step0, int64_t n_steps, const int64_t *eo, const int64_t *no,
                             const int64_t *vo)
@@ -620,6 +681,7 @@ static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double 
                 rod_constraints(&rv, x, v, Q, om);
             }
             conn_forces(p, pos, vel, fc, Nn);
+            if (p->rod_contact) contact_forces(p, pos, vel, fc, no, NULL);
             for (int r = 0; r < R; ++r) {
                 rod_view rv;
                 rod_consts c;
@@ -657,7 +719,7 @@ int orc_step(const orc_rods *p, double *pos, double *vel, double *dir, double *o
     if (!eo) return -2;
     int64_t *no = eo + R, *vo = eo + 2 * R;
     offsets(p, eo, no, vo);
-    if (p->n_conn > 0) {
+    if (p->n_conn > 0 || p->rod_contact) {
         const int rc = orc_step_coupled(p, pos, vel, dir, omega, step0, n_steps, eo, no, vo);
         free(eo);
         return rc;
@@ -817,6 +879,13 @@ int orc_energy(const orc_rods *p, const double *pos, const double *vel, const do
             while (r + 1 < R && no[r + 1] <= node) ++r;
             out[5 * r + 4] += half;
         }
+    }
+    if (p->rod_contact) {
+        double *pot = calloc((size_t)R, sizeof(double));
+        if (!pot) { work_free(&w); free(eo); return -2; }
+        contact_forces(p, pos, vel, NULL, no, pot);
+        for (int r = 0; r < R; ++r) out[5 * r + 4] += pot[r];
+        free(pot);
     }
     work_free(&w);
     free(eo);

@@ -39,6 +39,7 @@ class _OrcRods(C.Structure):
         ("n_conn", C.c_int32), ("conn_node", _ip), ("conn_k", _dp), ("conn_c", _dp), ("conn_rest", _dp),
         ("n_walls", C.c_int32), ("wall", _dp), ("wall_k", C.c_double), ("wall_c", C.c_double),
         ("wall_mu", C.c_double), ("wall_vslip", C.c_double),
+        ("rod_contact", C.c_int32),
     ]
 
 
@@ -155,6 +156,7 @@ class Oracle:
         wl = getattr(inp, "walls", None)
         self.walls = None if wl is None or len(wl) == 0 else _d(np.asarray(wl, float).reshape(-1, 4))
         self.wall_par = [float(getattr(inp, k, 0.0) or 0.0) for k in ("wall_k", "wall_c", "wall_mu", "wall_vslip")]
+        self.rod_contact = int(getattr(inp, "rod_contact", 0) or 0)
         self.mat = {k: _d(getattr(inp, k)) for k in
                     ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping")}
         self.bc_start = np.ascontiguousarray(inp.bc_start, dtype=np.int32)
@@ -194,7 +196,9 @@ class Oracle:
         if self.walls is not None:
             s.n_walls = int(self.walls.shape[0])
             s.wall = _ptr(self.walls)
+        if self.walls is not None or self.rod_contact:
             s.wall_k, s.wall_c, s.wall_mu, s.wall_vslip = self.wall_par
+        s.rod_contact = self.rod_contact
         if self.conn is not None:
             s.n_conn = int(self.conn[0].shape[0])
             s.conn_node = self.conn[0].ctypes.data_as(_ip)

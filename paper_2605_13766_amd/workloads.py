@@ -86,6 +86,7 @@ class RodInputs:
     wall_c: float = 0.0                         # N s/m^2 (damping per unit penetration)
     wall_mu: float = 0.0
     wall_vslip: float = 1e-4                    # m/s
+    rod_contact: int = 0                        # 1: nodes of different rods touch (spheres, the wall law)
     name: str = ""
 
     # ------------------------------------------------------------------ sizes
@@ -153,7 +154,7 @@ class RodInputs:
             **self._subset_connections(rods),
             walls=None if self.walls is None else np.array(self.walls, float).copy(),
             wall_k=self.wall_k, wall_c=self.wall_c, wall_mu=self.wall_mu, wall_vslip=self.wall_vslip,
-            name=self.name + "[subset]",
+            rod_contact=self.rod_contact, name=self.name + "[subset]",
         )
 
     def _subset_connections(self, rods):
