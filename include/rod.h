@@ -162,13 +162,29 @@ typedef struct {
      * damper of coefficient wall_mu f_n / wall_vslip: the explicit step needs
      * wall_mu f_n h / (m wall_vslip) well below 2 for node masses m (the
      * contact frequency sqrt(wall_k / m) enters the stability warning).
-     * Rod-rod contact is not modelled. */
+     * The same law, with the same four parameters, acts between the nodes of
+     * different rods when rod_contact is set (below). */
     int32_t n_walls;                 /* 0..ROD_MAX_WALLS */
     const double *walls;             /* [n_walls][4], host memory always */
     double wall_k;                   /* N/m >= 0 */
     double wall_c;                   /* N s/m^2 >= 0 */
     double wall_mu;                  /* >= 0 */
-    double wall_vslip;               /* m/s > 0 (with walls) */
+    double wall_vslip;               /* m/s > 0 (with walls or rod contact) */
+    /* Rod-rod contact (Results, "Fibrous granular materials"; the collision
+     * engine the paper names as future work).  With rod_contact = 1 every
+     * node is a sphere of its rod's radius, and two nodes of different rods
+     * whose centres are closer than the sum of their radii each receive the
+     * wall law above with the overlap delta = r_a + r_b - |x_a - x_b|, the
+     * normal (x_a - x_b)/|x_a - x_b| and the relative velocity v_a - v_b (so
+     * the pair's forces are equal and opposite); half of each pair's penalty
+     * potential 1/2 wall_k delta^2 joins each rod's W_ext.  A rod does not
+     * touch itself.  Pairs are found every step by a hashed uniform grid over
+     * the node positions (cells of twice the largest radius), so each step is
+     * one launch sequence: FP64 batches only (ROD_EUNSUPPORTED for FP32),
+     * substeps must be 0 or 1 (one step per launch), and forces are summed in
+     * the order the grid lists the pairs, which may differ between runs at
+     * round-off. */
+    int32_t rod_contact;             /* 0 or 1 */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -192,8 +208,9 @@ typedef struct {
  * node outside the batch, joining a node to itself, or with k, c or l0
  * negative or not finite; n_walls outside [0, ROD_MAX_WALLS], a wall normal
  * not of unit length within 1e-9, wall_k, wall_c or wall_mu negative,
- * wall_vslip <= 0), ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED
- * (tile_waves too small for the longest rod or connected group).
+ * wall_vslip <= 0, rod_contact not 0 or 1, rod_contact with substeps > 1),
+ * ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the
+ * longest rod or connected group, rod_contact in an FP32 batch).
  * A time step above the explicit stability estimate is reported through
  * rod_last_error with ROD_OK.
  */
@@ -202,7 +219,7 @@ int rod_batch_create(const rod_batch_desc *desc, void *stream, rod_batch **out);
 /*
  * The autotuner (desc->autotune = 1).  Candidates: tile_waves in {1, 2, 4, 8}
  * that hold the longest rod (when tile_waves = 0) times substeps in
- * {50, 200, 1000} (when substeps = 0).  Each tile width is packed into a
+ * {50, 200, 1000} (when substeps = 0; {1} with rod contact).  Each tile width is packed into a
  * scratch batch of the same rods; each candidate runs one warm-up launch and
  * then 1000 timed steps (HIP events on a private stream; the scratch state is
  * discarded), and the fastest per element-step is kept.  Tile width does not
@@ -234,7 +251,8 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream);
  *   W_ext   = -sum f . (r_last - r_last(0)) - sum_j m_j g . (r_j - r_j(0))
  *             + half of 1/2 k (l - l0)^2 of every connection at the rod
  *             + 1/2 wall_k delta^2 of every node in contact with a wall
- *                                  (the end force, gravity, connections, walls)
+ *             + half of 1/2 wall_k delta^2 of every node pair in rod contact
+ *                      (the end force, gravity, connections, walls, contacts)
  * The distributed, magnetic and muscle couples have no energy column.  Returns ROD_ENONFINITE if any rod is flagged non-finite.
  */
 int rod_energy(rod_batch *b, double *out, void *stream);

@@ -124,7 +124,40 @@ struct DevBatch {
     int n_walls;
     T wall[DEV_MAX_WALLS][4];
     T wall_k, wall_c, wall_mu, wall_vslip;
+    // rod-rod contact (FP64 batches, one step per launch): the contact force
+    // on every node for the coming kick, [3][n_slots + n_rods] by node id (the
+    // slot's node i, then each rod's node n), and each node's share of the
+    // pairs' penalty potential [n_slots + n_rods] (energy passes); NULL
+    // without contact
+    const double *cforce;
+    const double *cpot;
 };
+
+// The contact grid of a batch with rod-rod contact: nodes are binned by a
+// wrapped uniform grid of g^3 buckets (cell = twice the largest radius, so
+// every pair in contact lies in neighbouring cells; with g >= 3 the 27 cells
+// around a node are 27 different buckets), counted, prefix-summed and
+// scattered into bucket order; each node then sums its contacts over its 27
+// neighbouring buckets.
+struct ContactGrid {
+    int64_t nn;        // node ids: n_slots + n_rods
+    int g;             // cells per axis of the wrapped grid, 3..CONTACT_MAX_G
+    double inv_cell;   // 1 / cell size
+    int32_t *count;    // [g^3] nodes per bucket; zero between passes
+    int32_t *start;    // [g^3 + 1] first sorted position of each bucket
+    int32_t *chunk;    // [ceil(g^3 / 1024)] chunk totals of the prefix sum
+    int32_t *bucket;   // [nn] a node's bucket
+    int32_t *rank;     // [nn] its rank within the bucket, -1 for padding slots
+    double *sorted;    // [6][nn] positions and velocities in bucket order
+    int32_t *srod;     // [nn] rods in bucket order
+    double *force;     // [3][nn] contact force by node id
+    double *pot;       // [nn] potential share by node id
+};
+constexpr int CONTACT_MAX_G = 161;   // g^3 / 1024 chunk totals fit one workgroup's prefix sum
+
+// Fill g.force and g.pot for positions advanced by `drift` seconds from the
+// state (dt/2 before a step's kick, 0 for energies).
+hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, double drift, hipStream_t s);
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
 hipError_t launch_step(const DevBatch<double> &b, int waves, int n_sub, int grid, hipStream_t s);

@@ -112,6 +112,8 @@ struct rod_batch {
     double *d_rod_rad = nullptr;       // [R] rod radii (walls)
     void *d_wall_off = nullptr;        // [n_tiles][8] wall offsets in each tile's frame
     int n_walls = 0;
+    bool rod_contact = false;          // rod-rod contact: a grid pass before every step
+    rodk::ContactGrid cg{};
     double walls[ROD_MAX_WALLS][4] = {};
     double wall_k = 0, wall_c = 0, wall_mu = 0, wall_vslip = 0;
     int conn_max_nodes = 0;            // most connected nodes in one tile
@@ -226,8 +228,13 @@ int validate(const rod_batch_desc *d)
         return fail(ROD_EINVAL, "connections need conn_rod, conn_node, conn_k, conn_c and conn_rest");
     if (d->n_walls < 0 || d->n_walls > ROD_MAX_WALLS)
         return fail(ROD_EINVAL, "n_walls must be in [0, " + std::to_string(ROD_MAX_WALLS) + "]");
-    if (d->n_walls > 0) {
-        if (!d->walls) return fail(ROD_EINVAL, "walls is NULL");
+    if (d->rod_contact != 0 && d->rod_contact != 1) return fail(ROD_EINVAL, "rod_contact must be 0 or 1");
+    if (d->rod_contact && d->substeps > 1)
+        return fail(ROD_EINVAL, "rod contact runs one step per launch: substeps must be 0 or 1");
+    if (d->rod_contact && d->precision == ROD_F32)
+        return fail(ROD_EUNSUPPORTED, "rod contact runs in FP64 batches only");
+    if (d->n_walls > 0 || d->rod_contact) {
+        if (d->n_walls > 0 && !d->walls) return fail(ROD_EINVAL, "walls is NULL");
         for (int w = 0; w < d->n_walls; ++w) {
             const double *n = &d->walls[4 * w];
             for (int k = 0; k < 4; ++k)
@@ -390,7 +397,7 @@ int check_values(HostInputs &h)
 
 // Crude explicit stability bound: 2 / (largest natural frequency) over the
 // axial, shear, bending, twisting and rotational-shear modes of one element.
-double stability_dt(const HostInputs &h, const double *field, double wall_k = 0.0)
+double stability_dt(const HostInputs &h, const double *field, double wall_k = 0.0, double contact_k = 0.0)
 {
     double dt = 1e300;
     double bmax = 0;   // bound on |b(t)|
@@ -419,6 +426,7 @@ double stability_dt(const HostInputs &h, const double *field, double wall_k = 0.
         w = std::max(w, std::sqrt(2.0 * h.ac[r] * h.G[r] * A / (rho * I)));          // rotational shear
         w = std::max(w, std::sqrt(mmax * bmax / (rho * I)));                         // magnetic restoring couple
         w = std::max(w, std::sqrt(wall_k / (0.5 * rho * A * lmin)));                // wall contact of an end node
+        w = std::max(w, std::sqrt(2.0 * contact_k / (0.5 * rho * A * lmin)));       // two end nodes in contact
         dt = std::min(dt, 2.0 / w);
     }
     return dt;
@@ -466,6 +474,8 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.rod_org = (const T *)b->d_rod_org;
     d.rod_rad = b->d_rod_rad;
     d.wall_off = (const T *)b->d_wall_off;
+    d.cforce = sizeof(T) == 8 && b->rod_contact ? b->cg.force : nullptr;
+    d.cpot = sizeof(T) == 8 && b->rod_contact ? b->cg.pot : nullptr;
     d.n_walls = b->n_walls;
     for (int w = 0; w < 8; ++w)
         for (int k = 0; k < 4; ++k) d.wall[w][k] = T(w < b->n_walls ? b->walls[w][k] : 0.0);
@@ -734,7 +744,7 @@ int build_device(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMemcpy(b->d_conn_key, ckey.data(), ckey.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_par, par.data(), par.size() * es, hipMemcpyHostToDevice));
     }
-    if (!h.ck.empty() || b->n_walls > 0) {
+    if (!h.ck.empty() || b->n_walls > 0 || b->rod_contact) {
         // FP32 node interactions work in the frame of each tile's first rod
         // (small coordinates): rod origins relative to it, and the walls'
         // offsets d - n . (its origin) per tile. FP64 keeps lab-frame node
@@ -795,6 +805,35 @@ int build_device(rod_batch *b, const HostInputs &h)
     return ROD_OK;
 }
 
+// Device buffers of the contact grid: g^3 buckets, g = cbrt(2 x nodes) within
+// [3, CONTACT_MAX_G], cells of twice the largest radius.
+int build_contact_grid(rod_batch *b, const HostInputs &h)
+{
+    rodk::ContactGrid &g = b->cg;
+    g.nn = b->n_slots + b->R;
+    double rmax = 0;
+    for (double r : h.rad) rmax = std::max(rmax, r);
+    g.inv_cell = 1.0 / (2.0 * rmax);
+    g.g = (int)std::ceil(std::cbrt(2.0 * (double)g.nn));
+    g.g = std::min(std::max(g.g, 3), rodk::CONTACT_MAX_G);
+    const int64_t nb = (int64_t)g.g * g.g * g.g, nc = (nb + 1023) / 1024;
+    HIPCHK(hipMalloc((void **)&g.count, nb * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.start, (nb + 1) * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.chunk, nc * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.bucket, g.nn * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.rank, g.nn * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.sorted, 6 * g.nn * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&g.srod, g.nn * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.force, 3 * g.nn * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&g.pot, g.nn * sizeof(double)));
+    // counts start at zero; each pass clears them as it reads them
+    HIPCHK(hipMemset(g.count, 0, nb * sizeof(int32_t)));
+    HIPCHK(hipMemset(g.force, 0, 3 * g.nn * sizeof(double)));
+    HIPCHK(hipMemset(g.pot, 0, g.nn * sizeof(double)));
+    HIPCHK(hipDeviceSynchronize());
+    return ROD_OK;
+}
+
 void free_graphs(rod_batch *b)
 {
     for (auto &kv : b->graphs) {
@@ -809,6 +848,11 @@ int enqueue_steps(rod_batch *b, int64_t n_steps, hipStream_t s)
     const int64_t S = b->substeps > 0 ? b->substeps : n_steps;
     for (int64_t done = 0; done < n_steps; done += S) {
         const int n_sub = (int)std::min<int64_t>(S, n_steps - done);
+        if (b->rod_contact) {
+            // contact forces at the positions after the coming half drift
+            hipError_t e = rodk::launch_contact(b->b64, b->cg, 0.5 * b->dt, s);
+            if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
+        }
         hipError_t e = b->precision == ROD_F32 ? rodk::launch_step(b->b32, b->waves, n_sub, b->grid, s)
                                                : rodk::launch_step(b->b64, b->waves, n_sub, b->grid, s);
         if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -953,7 +997,9 @@ int autotune(const rod_batch_desc *d, std::vector<rod_tune_trial> &log, rod_batc
 {
     constexpr int TRIAL_STEPS = 1000;
     const std::vector<int> widths = d->tile_waves ? std::vector<int>{d->tile_waves} : std::vector<int>{1, 2, 4, 8};
-    const std::vector<int> subs = d->substeps ? std::vector<int>{d->substeps} : std::vector<int>{50, 200, 1000};
+    const std::vector<int> subs = d->substeps  ? std::vector<int>{d->substeps}
+                                : d->rod_contact ? std::vector<int>{1}
+                                                 : std::vector<int>{50, 200, 1000};
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto release = [&]() {
@@ -1118,8 +1164,10 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->wall_c = d->wall_c;
     b->wall_mu = d->wall_mu;
     b->wall_vslip = d->wall_vslip;
+    b->rod_contact = d->rod_contact != 0;
+    if (b->rod_contact) b->substeps = 1;   // a contact pass before every step
     b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0
-           || d->n_connections > 0 || d->n_walls > 0;
+           || d->n_connections > 0 || d->n_walls > 0 || b->rod_contact;
     b->clamp_r0.assign(3 * b->R, 0.0);
     b->clamp_rn.assign(3 * b->R, 0.0);
     b->clamp_q0.assign(9 * b->R, 0.0);
@@ -1142,6 +1190,7 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
         }
     }
     rc = b->precision == ROD_F32 ? build_device<float>(b, h) : build_device<double>(b, h);
+    if (!rc && b->rod_contact) rc = build_contact_grid(b, h);
     if (rc) {
         rod_batch_destroy(b);
         return rc;
@@ -1151,7 +1200,7 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->grid = b->n_tiles;
     {
         // the kernel this batch runs must fit the workgroup's LDS
-        const int kind = !b->ext ? 0 : b->n_walls > 0 ? 3 : b->n_conn > 0 ? 2 : 1;
+        const int kind = !b->ext ? 0 : (b->n_walls > 0 || b->rod_contact) ? 3 : b->n_conn > 0 ? 2 : 1;
         int dev = 0, limit = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) limit = 65536;
@@ -1168,7 +1217,7 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
         rod_batch_destroy(b);
         return fail(ROD_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
-    const double dts = stability_dt(h, d->field, d->n_walls > 0 ? d->wall_k : 0.0);
+    const double dts = stability_dt(h, d->field, d->n_walls > 0 ? d->wall_k : 0.0, b->rod_contact ? d->wall_k : 0.0);
     if (d->dt > dts) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "warning: dt %.3g exceeds the explicit stability estimate %.3g", d->dt, dts);
@@ -1219,6 +1268,11 @@ int rod_energy(rod_batch *b, double *out, void *stream)
 {
     if (!b || !out) return fail(ROD_EINVAL, "handle or out is NULL");
     hipStream_t s = (hipStream_t)stream;
+    if (b->rod_contact) {
+        // the pairs' potentials at the current positions
+        hipError_t e = rodk::launch_contact(b->b64, b->cg, 0.0, s);
+        if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
+    }
     hipError_t e = b->precision == ROD_F32 ? rodk::launch_energy(b->b32, b->d_energy, s)
                                            : rodk::launch_energy(b->b64, b->d_energy, s);
     if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("energy launch: ") + hipGetErrorString(e));
@@ -1297,6 +1351,15 @@ void rod_batch_destroy(rod_batch *b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     (void)hipFree(b->d_state);
     (void)hipFree(b->d_param);
+    (void)hipFree(b->cg.count);
+    (void)hipFree(b->cg.start);
+    (void)hipFree(b->cg.chunk);
+    (void)hipFree(b->cg.bucket);
+    (void)hipFree(b->cg.rank);
+    (void)hipFree(b->cg.sorted);
+    (void)hipFree(b->cg.srod);
+    (void)hipFree(b->cg.force);
+    (void)hipFree(b->cg.pot);
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);
     (void)hipFree(b->d_mag);

@@ -43,6 +43,7 @@ class RodBatchDesc(C.Structure):
         ("conn_rest", _dp),
         ("n_walls", C.c_int32), ("walls", _dp), ("wall_k", C.c_double), ("wall_c", C.c_double),
         ("wall_mu", C.c_double), ("wall_vslip", C.c_double),
+        ("rod_contact", C.c_int32),
     ]
 
 
@@ -228,6 +229,8 @@ class RodBatch:
             keep["walls"] = np.ascontiguousarray(np.asarray(wl, dtype=np.float64).reshape(-1, 4))   # host always
             d.n_walls = int(keep["walls"].shape[0])
             d.walls = keep["walls"].ctypes.data_as(_dp)
+        d.rod_contact = int(getattr(inp, "rod_contact", 0) or 0)
+        if d.n_walls > 0 or d.rod_contact:
             d.wall_k, d.wall_c = float(inp.wall_k), float(inp.wall_c)
             d.wall_mu, d.wall_vslip = float(inp.wall_mu), float(inp.wall_vslip)
         d.dt = float(inp.dt)

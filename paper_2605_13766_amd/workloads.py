@@ -516,6 +516,47 @@ def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period
     return inp
 
 
+def fibre_pile(n_rods=16384, n=50, L=0.5, radius=0.01, youngs=1e7, per_row=8, rows=100, overlap=1e-7,
+               g=9.81, damping=0.5, dt=1e-5, contact_k=1e5, contact_c=1e3, mu=0.3, vslip=1e-2, noise=1e-3,
+               seed=SEED_BASE + 9):
+    """Straight fibres in crossed layers on a floor, in rod-rod contact (the
+    paper's fibrous granular materials).
+
+    Layer q holds per_row x rows fibres of length L, along x in even layers and
+    along y in odd ones, rows 4 radii apart and fibres end to end with a gap of
+    4 radii; layers are 2 radii minus `overlap` apart, so every crossing starts
+    in light contact, and the lowest layer rests on a floor wall at z = 0.
+    Gravity, linear damping, the contact law with stiffness contact_k, damping
+    contact_c, friction mu below slip speed vslip; node velocities N(0, noise^2)
+    break the lattice's symmetry.  Defaults: 16,384 fibres of 50 elements in
+    21 layers of 800 (element length 1 cm = one radius, so a crossing meets
+    several nodes of each fibre).
+    """
+    rng = np.random.default_rng(seed)
+    sp = 4.0 * radius
+    per_layer = per_row * rows
+    nodes_list, Q_list = [], []
+    for r in range(n_rods):
+        q, k = divmod(r, per_layer)
+        j, i = divmod(k, per_row)
+        z = radius + q * (2.0 * radius - overlap)
+        along, across = i * (L + sp), (j + 0.5) * sp
+        if q % 2 == 0:
+            nodes, Q = straight_rod(n, L, direction=(1, 0, 0), d1=(0, 1, 0), origin=(along, across, z))
+        else:
+            nodes, Q = straight_rod(n, L, direction=(0, 1, 0), d1=(0, 0, 1), origin=(across, along, z))
+        nodes_list.append(nodes)
+        Q_list.append(Q)
+    vel = [rng.normal(0.0, noise, size=(n + 1, 3)) for _ in range(n_rods)]
+    inp = _assemble("fibre_pile", nodes_list, Q_list, dt, density=DENSITY, youngs=youngs, radius=radius,
+                    damping=damping, bc_start=0, bc_end=0, velocity_list=vel)
+    inp.gravity = np.array([0.0, 0.0, -g])
+    inp.walls = np.array([[0.0, 0.0, 1.0, 0.0]])
+    inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = contact_k, contact_c, mu, vslip
+    inp.rod_contact = 1
+    return inp
+
+
 def millipede_swarm(n_bots=224, legs_per_side=12, n_back=20, n_leg=8, back_length=0.02, leg_length=0.004,
                     back_radius=2.5e-4, leg_radius=2e-4, width=2e-3, youngs=1e6, k_lateral=1.0, k_leg=1.0,
                     c_conn=1e-5, m0=1e-4, b0=0.01, freq=5.0, spacing=0.03, dt=1e-6, seed=SEED_BASE + 8):

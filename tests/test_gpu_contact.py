@@ -1,0 +1,84 @@
+"""GPU parity of rod-rod contact (nodes as spheres of the rod radius, the
+walls' penalty law between nodes of different rods, pairs found by the
+hashed grid) against the FP64 oracle's brute force over all node pairs,
+through the C boundary.  Bars as in test_gpu_step: FP64 max(1e-10, 10 x the
+oracle's one-ulp sensitivity) per norm, energies (W_ext holding the contact
+potentials) included.
+"""
+import numpy as np
+import pytest
+
+from paper_2605_13766_amd import workloads as W
+from test_gpu_step import _rod, assert_norms, run_both
+import test_oracle_contact as OC
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_pile(seed=91):
+    """Three crossed layers of 8 fibres of 20 elements (1 cm elements, radius
+    1 cm) on the floor, under gravity, with friction."""
+    return W.fibre_pile(n_rods=24, n=20, L=0.2, per_row=2, rows=4, noise=1e-2, seed=seed)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+def test_fibre_pile_f64(waves):
+    print(f"case: fibre pile 24 rods x 20, tile_waves={waves}, FP64, 1000 steps", flush=True)
+    norms, info = run_both(_small_pile(), 1000, tile_waves=waves)
+    assert info["tile_waves"] == waves and info["substeps"] == 1
+    assert_norms(norms)
+
+
+def test_crossing_collision_f64():
+    print("case: two crossing rods colliding with friction, FP64, 4000 steps", flush=True)
+    inp = OC._crossing(gap=2e-4, vel_b=[0.03, 0.0, -0.05], mu=0.5, c=2.0)
+    norms, _ = run_both(inp, 4000)
+    assert_norms(norms)
+
+
+def test_pile_with_connections_f64():
+    """Contact together with connections and walls: pairs of fibres joined
+    end to end by springs."""
+    print("case: fibre pile with end-to-end springs, FP64, 1000 steps", flush=True)
+    inp = _small_pile(seed=93)
+    pairs = [(2 * k, 2 * k + 1) for k in range(12)]
+    inp.conn_rod = np.array(pairs, np.int32)
+    inp.conn_node = np.array([[20, 0]] * len(pairs), np.int32)
+    inp.conn_k = np.full(len(pairs), 50.0)
+    inp.conn_c = np.full(len(pairs), 0.01)
+    inp.conn_rest = np.array([np.linalg.norm(inp.position[inp.node_offset[b]] - inp.position[inp.node_offset[a] + 20])
+                              for a, b in pairs])
+    norms, _ = run_both(inp, 1000)
+    assert_norms(norms)
+
+
+def test_full_pile_conserves_momentum():
+    """The full 16,384-fibre pile without gravity, floor, damping or friction:
+    the contact forces come in equal and opposite pairs, so the total linear
+    momentum stays at its initial value to round-off; the autotuned launch
+    shape runs one step per launch."""
+    print("case: fibre pile 16384 x 50, no gravity/floor/damping/friction, FP64, 200 steps", flush=True)
+    R = _rod()
+    inp = W.fibre_pile(overlap=2e-4, damping=0.0, mu=0.0, contact_c=0.0)
+    inp.gravity = np.zeros(3)
+    inp.walls = None
+    A = np.pi * inp.radius ** 2
+    m = np.zeros(inp.position.shape[0])
+    for r, n in enumerate(inp.n_elems):
+        o = inp.node_offset[r]
+        m[o:o + n] += 0.5 * inp.density[r] * A[r] * (0.5 / n)
+        m[o + 1:o + n + 1] += 0.5 * inp.density[r] * A[r] * (0.5 / n)
+    p0 = (m[:, None] * inp.velocity).sum(0)
+    with R.RodBatch(inp, precision="f64", autotune=True) as b:
+        info = b.info()
+        b.step(200)
+        pos, vel, _, _, _ = b.get_state()
+        e = b.energy()
+    p1 = (m[:, None] * vel).sum(0)
+    scale = np.abs(m[:, None] * vel).sum()
+    moved = np.abs(vel - inp.velocity).max()
+    print("substeps", info["substeps"], "p0", p0, "p1", p1, "scale", scale, "max dv", moved, flush=True)
+    assert info["substeps"] == 1
+    assert np.isfinite(pos).all() and np.isfinite(e).all()
+    assert moved > 1e-3                      # the initial overlaps pushed the layers apart
+    assert np.abs(p1 - p0).max() < 1e-12 * scale
