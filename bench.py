@@ -8,7 +8,7 @@ substeps per launch S chosen by the library's autotuner).  The headline value is
 FP32 figure rides along in the same JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate] [--no-magnetic]
-                  [--no-active] [--no-walls] [--no-connected]
+                  [--no-active] [--no-walls] [--no-contact] [--no-connected]
 
 The magnetic carpet rides along as the "magnetic" object: 65,536 base-clamped
 rods x 50 elements (FP32) turned by a rotating homogeneous field through their
@@ -16,9 +16,11 @@ programmed magnetization, timed like the headline and next to the same carpet
 driven by its distributed couple.  The "active" object times 16,384 free
 filaments x 50 elements under gravity and travelling-wave muscle moments in
 both precisions, and the "walls" object the same filaments confined in a box
-of six planar walls (penalty contact with Coulomb friction); the "connected"
-object times millipede-like bots of rods joined by point-wise and lateral
-spring-dashpot connections (224 bots, and 4096 to fill the GPU).
+of six planar walls (penalty contact with Coulomb friction); the "contact"
+object times a pile of crossed fibres in rod-rod contact (hash-grid pairs
+every step, one step per launch); the "connected" object times millipede-like
+bots of rods joined by point-wise and lateral spring-dashpot connections (224
+bots, and 4096 to fill the GPU).
 
 The learned coarse step rides along as the "surrogate" object: the network is
 trained on 16,384 carpet rods (64 elements, 2.1e6 windows from plain
@@ -240,6 +242,34 @@ def time_walls(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32"
     return out
 
 
+CONTACT_NODE_BYTES = 72                          # a contact pass: node position and velocity in, force out
+
+
+def time_contact(steps, warmup, tile_waves=0):
+    """The fibre pile (16,384 fibres x 50 elements in 21 crossed layers on a
+    floor, rod-rod contact found by the hash grid every step, FP64).  One step
+    per launch, so the pass is HBM-bound: the roofline is bytes against the
+    HBM peak, algorithmic bytes per step = the step's 400 per element (state in
+    and out, constants) + 72 per node for the contact pass."""
+    from paper_2605_13766_amd import workloads as W
+    inp = W.fibre_pile()
+    r = time_gpu(inp, "f64", steps, warmup, tile_waves, 1, traffic_tag="none")
+    n_nodes = inp.n_elements + inp.n_rods
+    step_s = r["launch_ms"] * 1e-3 / STEPS_PER_LAUNCH
+    algo = ALGO_BYTES["f64"] * inp.n_elements + CONTACT_NODE_BYTES * n_nodes
+    achieved = algo / step_s / 1e9
+    return {
+        "workload": f"fibre_pile: {inp.n_rods:,} fibres x 50 elements (0.5 m, radius 1 cm) in 21 crossed layers on a "
+                    f"floor, rod-rod contact (k {inp.wall_k:g} N/m, mu {inp.wall_mu:g}), gravity, dt 1e-5 s, "
+                    "one step per launch, FP64",
+        "unit": "element-steps/s",
+        "value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms_per_1000_steps": r["launch_ms"],
+        "tile_waves": r["info"]["tile_waves"], "substeps_per_launch": r["info"]["substeps"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None, "algorithmic_bytes_per_step": algo},
+    }
+
+
 def connected_costs(inp, precision):
     """Algorithmic FLOP per element-step and extra bytes per element per launch of
     the millipede swarm: the plain step without the distributed couple, the
@@ -436,6 +466,7 @@ def main(argv=None):
     ap.add_argument("--no-active", action="store_true")
     ap.add_argument("--no-connected", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
+    ap.add_argument("--no-contact", action="store_true")
     ap.add_argument("--connected-bots", default="224,4096", help="swarm sizes of the connected workload")
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the headline batch (profiling runs of the other workloads; value is then null)")
@@ -520,6 +551,9 @@ def main(argv=None):
         print("timing the active filaments in a box", file=sys.stderr, flush=True)
         line["walls"] = time_walls(args.steps, args.warmup, args.tile_waves, args.substeps,
                                    precisions=args.precisions.split(","))
+    if not args.no_contact and "f64" in args.precisions.split(","):
+        print("timing the fibre pile (rod-rod contact)", file=sys.stderr, flush=True)
+        line["contact"] = time_contact(args.steps, args.warmup, args.tile_waves)
     if not args.no_connected:
         print("timing the millipede swarm", file=sys.stderr, flush=True)
         line["connected"] = time_connected(args.steps, args.warmup, args.tile_waves, args.substeps,

@@ -134,26 +134,28 @@ struct DevBatch {
 };
 
 // The contact grid of a batch with rod-rod contact: nodes are binned by a
-// wrapped uniform grid of g^3 buckets (cell = twice the largest radius, so
-// every pair in contact lies in neighbouring cells; with g >= 3 the 27 cells
-// around a node are 27 different buckets), counted, prefix-summed and
-// scattered into bucket order; each node then sums its contacts over its 27
-// neighbouring buckets.
+// wrapped uniform grid of gx x gy x gz buckets (cell = twice the largest
+// radius, so every pair in contact lies in neighbouring cells; with at least 3
+// cells per axis the 27 cells around a node are 27 different buckets; the
+// counts per axis cover the batch's initial extent, within a bucket budget),
+// counted, prefix-summed and scattered into bucket order; each node then sums
+// its contacts over its 27 neighbouring buckets.
 struct ContactGrid {
     int64_t nn;        // node ids: n_slots + n_rods
-    int g;             // cells per axis of the wrapped grid, 3..CONTACT_MAX_G
+    int gx, gy, gz;    // cells per axis of the wrapped grid, each >= 3
     double inv_cell;   // 1 / cell size
-    int32_t *count;    // [g^3] nodes per bucket; zero between passes
-    int32_t *start;    // [g^3 + 1] first sorted position of each bucket
-    int32_t *chunk;    // [ceil(g^3 / 1024)] chunk totals of the prefix sum
+    double org[3];     // grid origin (the initial extent's lower corner)
+    int32_t *count;    // [gx gy gz] nodes per bucket; zero between passes
+    int32_t *start;    // [gx gy gz + 1] first sorted position of each bucket
+    int32_t *chunk;    // [ceil(gx gy gz / 1024)] chunk totals of the prefix sum
     int32_t *bucket;   // [nn] a node's bucket
     int32_t *rank;     // [nn] its rank within the bucket, -1 for padding slots
-    double *sorted;    // [6][nn] positions and velocities in bucket order
-    int32_t *srod;     // [nn] rods in bucket order
+    double4 *spr;      // [nn] position and radius in bucket order
+    double4 *svr;      // [nn] velocity and rod (as a double) in bucket order
     double *force;     // [3][nn] contact force by node id
     double *pot;       // [nn] potential share by node id
 };
-constexpr int CONTACT_MAX_G = 161;   // g^3 / 1024 chunk totals fit one workgroup's prefix sum
+constexpr int64_t CONTACT_MAX_BUCKETS = 4096 * 1024;   // chunk totals fit one workgroup's prefix sum
 
 // Fill g.force and g.pot for positions advanced by `drift` seconds from the
 // state (dt/2 before a step's kick, 0 for energies).

@@ -1055,9 +1055,9 @@ __device__ inline int wrap_cell(int64_t c, int g)
     return (int)(m < 0 ? m + g : m);
 }
 
-__device__ inline int64_t cell_of(double x, double inv_cell)
+__device__ inline int64_t cell_of(double x, double org, double inv_cell)
 {
-    const double q = x * inv_cell;
+    const double q = (x - org) * inv_cell;
     return (int64_t)floor(q < -1e15 ? -1e15 : (q > 1e15 ? 1e15 : q));   // finite x; keeps the cast defined
 }
 
@@ -1071,9 +1071,9 @@ __global__ void contact_bin_kernel(const DevBatch<double> B, const ContactGrid G
         G.rank[id] = -1;
         return;
     }
-    const int g = G.g;
-    const int b = (wrap_cell(cell_of(x[2], G.inv_cell), g) * g + wrap_cell(cell_of(x[1], G.inv_cell), g)) * g
-                + wrap_cell(cell_of(x[0], G.inv_cell), g);
+    const int b = (wrap_cell(cell_of(x[2], G.org[2], G.inv_cell), G.gz) * G.gy
+                   + wrap_cell(cell_of(x[1], G.org[1], G.inv_cell), G.gy)) * G.gx
+                + wrap_cell(cell_of(x[0], G.org[0], G.inv_cell), G.gx);
     G.bucket[id] = b;
     G.rank[id] = atomicAdd(&G.count[b], 1);
 }
@@ -1154,16 +1154,14 @@ __global__ void contact_scatter_kernel(const DevBatch<double> B, const ContactGr
     int rod;
     double x[3], v[3];
     contact_node(B, id, drift, rod, x, v);
-    const int64_t p = G.start[G.bucket[id]] + r, nn = G.nn;
-    for (int a = 0; a < 3; ++a) {
-        G.sorted[a * nn + p] = x[a];
-        G.sorted[(3 + a) * nn + p] = v[a];
-    }
-    G.srod[p] = rod;
+    const int64_t p = G.start[G.bucket[id]] + r;
+    G.spr[p] = make_double4(x[0], x[1], x[2], B.rod_rad[rod]);
+    G.svr[p] = make_double4(v[0], v[1], v[2], (double)rod);
 }
 
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
-// around it: the walls' law between two spheres.
+// around it: the walls' law between two spheres.  A candidate costs one
+// 32-byte load (position, radius); velocity and rod only for overlaps.
 __global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid G, double drift)
 {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1176,26 +1174,28 @@ __global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid
         contact_node(B, id, drift, rod, x, v);
         const double ra = B.rod_rad[rod];
         const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
-        const int g = G.g;
-        const int64_t cx = cell_of(x[0], G.inv_cell), cy = cell_of(x[1], G.inv_cell), cz = cell_of(x[2], G.inv_cell);
+        const int64_t cx = cell_of(x[0], G.org[0], G.inv_cell), cy = cell_of(x[1], G.org[1], G.inv_cell),
+                      cz = cell_of(x[2], G.org[2], G.inv_cell);
         for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int row = (wrap_cell(cz + dz, G.gz) * G.gy + wrap_cell(cy + dy, G.gy)) * G.gx;
                 for (int dx = -1; dx <= 1; ++dx) {
-                    const int b = (wrap_cell(cz + dz, g) * g + wrap_cell(cy + dy, g)) * g + wrap_cell(cx + dx, g);
+                    const int b = row + wrap_cell(cx + dx, G.gx);
                     const int32_t p1 = G.start[b + 1];
                     for (int32_t p = G.start[b]; p < p1; ++p) {
-                        const int orod = G.srod[p];
-                        if (orod == rod) continue;
-                        const double e0 = x[0] - G.sorted[p], e1 = x[1] - G.sorted[nn + p],
-                                     e2 = x[2] - G.sorted[2 * nn + p];
-                        const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                        const double delta = ra + B.rod_rad[orod] - dist;
+                        const double4 q = G.spr[p];
+                        const double e0 = x[0] - q.x, e1 = x[1] - q.y, e2 = x[2] - q.z;
+                        const double d2 = e0 * e0 + e1 * e1 + e2 * e2, reach = ra + q.w;
+                        if (!(d2 < reach * reach)) continue;
+                        const double4 u = G.svr[p];
+                        if ((int)u.w == rod) continue;
+                        const double dist = sqrt(d2);
+                        const double delta = reach - dist;
                         if (!(delta > 0.0)) continue;
                         pot += 0.25 * k * delta * delta;
                         if (!(dist > 0.0)) continue;   // coincident centres: no direction
                         const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
-                        const double r0 = v[0] - G.sorted[3 * nn + p], r1 = v[1] - G.sorted[4 * nn + p],
-                                     r2 = v[2] - G.sorted[5 * nn + p];
+                        const double r0 = v[0] - u.x, r1 = v[1] - u.y, r2 = v[2] - u.z;
                         const double vn = n0 * r0 + n1 * r1 + n2 * r2;
                         const double fn = delta * (k - c * vn);
                         if (!(fn > 0.0)) continue;
@@ -1207,6 +1207,7 @@ __global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid
                         f2 += fn * n2 - gf * t2;
                     }
                 }
+            }
     }
     G.force[id] = f0;
     G.force[nn + id] = f1;
@@ -1219,10 +1220,11 @@ __global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid
 hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, double drift, hipStream_t s)
 {
     const int bs = 256;
-    const int nb = g.g * g.g * g.g;
-    const int n_chunks = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    const int64_t nb64 = (int64_t)g.gx * g.gy * g.gz;
     if (g.nn <= 0) return hipSuccess;
-    if (g.g < 3 || g.g > CONTACT_MAX_G || n_chunks > 4 * 1024) return hipErrorInvalidValue;
+    if (g.gx < 3 || g.gy < 3 || g.gz < 3 || nb64 > CONTACT_MAX_BUCKETS) return hipErrorInvalidValue;
+    const int nb = (int)nb64;
+    const int n_chunks = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
     const int gn = (int)((g.nn + bs - 1) / bs);
     hipLaunchKernelGGL(contact_bin_kernel, dim3(gn), dim3(bs), 0, s, b, g, drift);
     hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb);

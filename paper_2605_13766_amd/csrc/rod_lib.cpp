@@ -805,25 +805,48 @@ int build_device(rod_batch *b, const HostInputs &h)
     return ROD_OK;
 }
 
-// Device buffers of the contact grid: g^3 buckets, g = cbrt(2 x nodes) within
-// [3, CONTACT_MAX_G], cells of twice the largest radius.
+// Device buffers of the contact grid: cells of twice the largest radius; per
+// axis enough cells (at least 3) to cover the initial extent of the nodes,
+// shrunk along the longest axes while the grid holds more than 4 buckets per
+// node (or more than the prefix sum takes); the grid wraps beyond that.
 int build_contact_grid(rod_batch *b, const HostInputs &h)
 {
     rodk::ContactGrid &g = b->cg;
     g.nn = b->n_slots + b->R;
     double rmax = 0;
     for (double r : h.rad) rmax = std::max(rmax, r);
-    g.inv_cell = 1.0 / (2.0 * rmax);
-    g.g = (int)std::ceil(std::cbrt(2.0 * (double)g.nn));
-    g.g = std::min(std::max(g.g, 3), rodk::CONTACT_MAX_G);
-    const int64_t nb = (int64_t)g.g * g.g * g.g, nc = (nb + 1023) / 1024;
+    const double cell = 2.0 * rmax;
+    g.inv_cell = 1.0 / cell;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (size_t j = 0; j < h.pos.size() / 3; ++j)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], h.pos[3 * j + a]);
+            hi[a] = std::max(hi[a], h.pos[3 * j + a]);
+        }
+    int64_t n[3];
+    for (int a = 0; a < 3; ++a) {
+        g.org[a] = lo[a];
+        n[a] = std::max<int64_t>(3, (int64_t)std::ceil((hi[a] - lo[a]) / cell) + 1);
+        n[a] = std::min<int64_t>(n[a], rodk::CONTACT_MAX_BUCKETS / 9);
+    }
+    const int64_t budget = std::min<int64_t>(std::max<int64_t>(4 * g.nn, 27), rodk::CONTACT_MAX_BUCKETS);
+    while (n[0] * n[1] * n[2] > budget) {
+        const int a = n[0] >= n[1] && n[0] >= n[2] ? 0 : (n[1] >= n[2] ? 1 : 2);
+        if (n[a] <= 3) break;
+        n[a] = std::max<int64_t>(3, (n[a] * 7) / 8);
+    }
+    g.gx = (int)n[0];
+    g.gy = (int)n[1];
+    g.gz = (int)n[2];
+    const int64_t nb = n[0] * n[1] * n[2], nc = (nb + 1023) / 1024;
+    if (nb > rodk::CONTACT_MAX_BUCKETS) return fail(ROD_EUNSUPPORTED, "contact grid too large");
     HIPCHK(hipMalloc((void **)&g.count, nb * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.start, (nb + 1) * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.chunk, nc * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.bucket, g.nn * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.rank, g.nn * sizeof(int32_t)));
-    HIPCHK(hipMalloc((void **)&g.sorted, 6 * g.nn * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&g.srod, g.nn * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&g.spr, g.nn * sizeof(double4)));
+    HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
     HIPCHK(hipMalloc((void **)&g.force, 3 * g.nn * sizeof(double)));
     HIPCHK(hipMalloc((void **)&g.pot, g.nn * sizeof(double)));
     // counts start at zero; each pass clears them as it reads them
@@ -1356,8 +1379,8 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.chunk);
     (void)hipFree(b->cg.bucket);
     (void)hipFree(b->cg.rank);
-    (void)hipFree(b->cg.sorted);
-    (void)hipFree(b->cg.srod);
+    (void)hipFree(b->cg.spr);
+    (void)hipFree(b->cg.svr);
     (void)hipFree(b->cg.force);
     (void)hipFree(b->cg.pot);
     (void)hipFree(b->d_tail);
