@@ -83,7 +83,8 @@ def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source in the same launch shape (else None).
     tag: {f64,f32}_ragged4096, f32_magnetic65536, {f64,f32}_active16384,
-    {f64,f32}_activebox16384 or {f64,f32}_millipede{224,4096}."""
+    {f64,f32}_activebox16384, {f64,f32}_millipede{224,4096} or f64_fibrepile16384
+    (there: the whole step, contact pass included, per one-step launch)."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"rod_step_{tag}*_traffic.json"))):
         with open(path) as f:
@@ -95,7 +96,7 @@ def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
 
 
 def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=ALGO_FLOP, extra_bytes=0,
-             traffic_tag=None, probe=None):
+             traffic_tag=None, probe=None, n_steps=STEPS_PER_LAUNCH):
     """Times `steps` bench steps after `warmup`.  algo_flop: FLOP per
     element-step, or a function of (probe before, probe after) when probe(batch)
     measures state the work depends on (outside the timed region)."""
@@ -110,7 +111,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         info = b.info()
         info["tuning"] = b.tuning()
         for _ in range(warmup):
-            b.step(STEPS_PER_LAUNCH, stream=stream)
+            b.step(n_steps, stream=stream)
         torch.cuda.synchronize()
         before = probe(b, stream) if probe else None
         torch.cuda.synchronize()
@@ -119,7 +120,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         t0 = time.perf_counter()
         for k in range(steps):
             starts[k].record(stream)
-            b.step(STEPS_PER_LAUNCH, stream=stream)
+            b.step(n_steps, stream=stream)
             ends[k].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -129,7 +130,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         b.close()
     if flags.any():
         raise RuntimeError(f"{int(flags.sum())} rods became non-finite")
-    el_steps = inp.n_elements * STEPS_PER_LAUNCH
+    el_steps = inp.n_elements * n_steps
     value = el_steps * steps / wall
     if probe:
         algo_flop = algo_flop(before, after)
@@ -245,7 +246,7 @@ def time_walls(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32"
 CONTACT_NODE_BYTES = 72                          # a contact pass: node position and velocity in, force out
 
 
-def time_contact(steps, warmup, tile_waves=0):
+def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH):
     """The fibre pile (16,384 fibres x 50 elements in 21 crossed layers on a
     floor, rod-rod contact found by the hash grid every step, FP64).  One step
     per launch, so the pass is HBM-bound: the roofline is bytes against the
@@ -253,9 +254,9 @@ def time_contact(steps, warmup, tile_waves=0):
     and out, constants) + 72 per node for the contact pass."""
     from paper_2605_13766_amd import workloads as W
     inp = W.fibre_pile()
-    r = time_gpu(inp, "f64", steps, warmup, tile_waves, 1, traffic_tag="none")
+    r = time_gpu(inp, "f64", steps, warmup, tile_waves, 1, traffic_tag="none", n_steps=n_steps)
     n_nodes = inp.n_elements + inp.n_rods
-    step_s = r["launch_ms"] * 1e-3 / STEPS_PER_LAUNCH
+    step_s = r["launch_ms"] * 1e-3 / n_steps
     algo = ALGO_BYTES["f64"] * inp.n_elements + CONTACT_NODE_BYTES * n_nodes
     achieved = algo / step_s / 1e9
     return {
@@ -263,10 +264,13 @@ def time_contact(steps, warmup, tile_waves=0):
                     f"floor, rod-rod contact (k {inp.wall_k:g} N/m, mu {inp.wall_mu:g}), gravity, dt 1e-5 s, "
                     "one step per launch, FP64",
         "unit": "element-steps/s",
-        "value": r["value"], "ms_per_step": r["ms_per_step"], "launch_ms_per_1000_steps": r["launch_ms"],
+        "value": r["value"], "ms_per_step": r["ms_per_step"], "steps_per_bench_step": n_steps,
+        "ms_per_simulation_step": step_s * 1e3,
         "tile_waves": r["info"]["tile_waves"], "substeps_per_launch": r["info"]["substeps"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": None, "algorithmic_bytes_per_step": algo},
+                     "frac": achieved / 8000.0,
+                     "traffic": traffic_from_profile("f64_fibrepile16384", r["info"]["tile_waves"], 1),
+                     "algorithmic_bytes_per_step": algo},
     }
 
 
@@ -467,6 +471,8 @@ def main(argv=None):
     ap.add_argument("--no-connected", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-contact", action="store_true")
+    ap.add_argument("--contact-steps", type=int, default=STEPS_PER_LAUNCH,
+                    help="simulation steps per bench step of the contact workload (short runs for counters)")
     ap.add_argument("--connected-bots", default="224,4096", help="swarm sizes of the connected workload")
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the headline batch (profiling runs of the other workloads; value is then null)")
@@ -553,7 +559,7 @@ def main(argv=None):
                                    precisions=args.precisions.split(","))
     if not args.no_contact and "f64" in args.precisions.split(","):
         print("timing the fibre pile (rod-rod contact)", file=sys.stderr, flush=True)
-        line["contact"] = time_contact(args.steps, args.warmup, args.tile_waves)
+        line["contact"] = time_contact(args.steps, args.warmup, args.tile_waves, args.contact_steps)
     if not args.no_connected:
         print("timing the millipede swarm", file=sys.stderr, flush=True)
         line["connected"] = time_connected(args.steps, args.warmup, args.tile_waves, args.substeps,

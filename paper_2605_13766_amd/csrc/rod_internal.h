@@ -152,6 +152,7 @@ struct ContactGrid {
     int32_t *rank;     // [nn] its rank within the bucket, -1 for padding slots
     double4 *spr;      // [nn] position and radius in bucket order
     double4 *svr;      // [nn] velocity and rod (as a double) in bucket order
+    int32_t *sid;      // [nn] node ids in bucket order
     double *force;     // [3][nn] contact force by node id
     double *pot;       // [nn] potential share by node id
 };

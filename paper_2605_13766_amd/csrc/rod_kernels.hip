@@ -1157,22 +1157,28 @@ __global__ void contact_scatter_kernel(const DevBatch<double> B, const ContactGr
     const int64_t p = G.start[G.bucket[id]] + r;
     G.spr[p] = make_double4(x[0], x[1], x[2], B.rod_rad[rod]);
     G.svr[p] = make_double4(v[0], v[1], v[2], (double)rod);
+    G.sid[p] = (int32_t)id;
 }
 
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
-// around it: the walls' law between two spheres.  A candidate costs one
-// 32-byte load (position, radius); velocity and rod only for overlaps.
-__global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid G, double drift)
+// around it: the walls' law between two spheres.  Threads take the nodes in
+// bucket order, so neighbouring threads read the same buckets and the sweep
+// streams through the sorted records; a candidate costs one 32-byte load
+// (position, radius), velocity and rod only for overlaps.  Results go to the
+// node's id (padding ids keep the zeros set at creation).  (Renumbering the
+// workgroups so that each XCD sweeps a contiguous eighth halved this kernel's
+// HBM reads but made it slower on the fibre pile, so the plain order stays.)
+__global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid G, int nb)
 {
-    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (id >= G.nn) return;
+    const int64_t p0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p0 >= G.start[nb]) return;
     const int64_t nn = G.nn;
     double f0 = 0, f1 = 0, f2 = 0, pot = 0;
-    if (G.rank[id] >= 0) {
-        int rod;
-        double x[3], v[3];
-        contact_node(B, id, drift, rod, x, v);
-        const double ra = B.rod_rad[rod];
+    {
+        const double4 me = G.spr[p0], mv = G.svr[p0];
+        const int rod = (int)mv.w;
+        const double x[3] = {me.x, me.y, me.z}, v[3] = {mv.x, mv.y, mv.z};
+        const double ra = me.w;
         const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
         const int64_t cx = cell_of(x[0], G.org[0], G.inv_cell), cy = cell_of(x[1], G.org[1], G.inv_cell),
                       cz = cell_of(x[2], G.org[2], G.inv_cell);
@@ -1209,6 +1215,7 @@ __global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid
                 }
             }
     }
+    const int64_t id = G.sid[p0];
     G.force[id] = f0;
     G.force[nn + id] = f1;
     G.force[2 * nn + id] = f2;
@@ -1231,7 +1238,7 @@ hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, doubl
     hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb);
     hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb);
     hipLaunchKernelGGL(contact_scatter_kernel, dim3(gn), dim3(bs), 0, s, b, g, drift);
-    hipLaunchKernelGGL(contact_force_kernel, dim3(gn), dim3(bs), 0, s, b, g, drift);
+    hipLaunchKernelGGL(contact_force_kernel, dim3(gn), dim3(bs), 0, s, b, g, nb);
     return hipGetLastError();
 }
 

@@ -847,6 +847,7 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     HIPCHK(hipMalloc((void **)&g.rank, g.nn * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.spr, g.nn * sizeof(double4)));
     HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
+    HIPCHK(hipMalloc((void **)&g.sid, g.nn * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.force, 3 * g.nn * sizeof(double)));
     HIPCHK(hipMalloc((void **)&g.pot, g.nn * sizeof(double)));
     // counts start at zero; each pass clears them as it reads them
@@ -1381,6 +1382,7 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.rank);
     (void)hipFree(b->cg.spr);
     (void)hipFree(b->cg.svr);
+    (void)hipFree(b->cg.sid);
     (void)hipFree(b->cg.force);
     (void)hipFree(b->cg.pot);
     (void)hipFree(b->d_tail);
