@@ -72,14 +72,18 @@ SURR_COARSE = 16                                 # two judge windows
 MLP_FLOP = 2 * (96 * 256 + 256 * 256 * 2 + 256 * 12)   # per window
 BF16_PEAK = 2500.0                               # TFLOP/s, dense MFMA
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_13766_amd", "csrc", "rod_kernels.hip")
+CONTACT_SRC = os.path.join(ROOT, "paper_2605_13766_amd", "csrc", "contact_kernels.hip")
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_hash(paths=(KERNEL_SRC,)) -> str:
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
+def traffic_from_profile(tag: str, tile_waves: int, substeps: int, paths=(KERNEL_SRC,)):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source in the same launch shape (else None).
     tag: {f64,f32}_ragged4096, f32_magnetic65536, {f64,f32}_active16384,
@@ -89,7 +93,7 @@ def traffic_from_profile(tag: str, tile_waves: int, substeps: int):
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"rod_step_{tag}*_traffic.json"))):
         with open(path) as f:
             d = json.load(f)
-        if (d.get("kernel_sha256_16") == kernel_hash()
+        if (d.get("kernel_sha256_16") == kernel_hash(paths)
                 and (d.get("tile_waves"), d.get("substeps")) == (tile_waves, substeps)):
             return d.get("hbm_bytes_per_launch")
     return None
@@ -269,7 +273,8 @@ def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH):
         "tile_waves": r["info"]["tile_waves"], "substeps_per_launch": r["info"]["substeps"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                      "frac": achieved / 8000.0,
-                     "traffic": traffic_from_profile("f64_fibrepile16384", r["info"]["tile_waves"], 1),
+                     "traffic": traffic_from_profile("f64_fibrepile16384", r["info"]["tile_waves"], 1,
+                                                     (KERNEL_SRC, CONTACT_SRC)),
                      "algorithmic_bytes_per_step": algo},
     }
 
