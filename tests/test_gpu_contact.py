@@ -82,3 +82,20 @@ def test_full_pile_conserves_momentum():
     assert np.isfinite(pos).all() and np.isfinite(e).all()
     assert moved > 1e-3                      # the initial overlaps pushed the layers apart
     assert np.abs(p1 - p0).max() < 1e-12 * scale
+
+
+def test_wrapped_grid_f64():
+    """Two colliding pairs of crossing rods 20 m apart: the grid's cells per
+    axis are capped by the bucket budget (4 per node), so the grid wraps many
+    times over the batch's extent and far-apart nodes share buckets; the result
+    must still be the oracle's."""
+    print("case: two crossing pairs 20 m apart (wrapped grid), FP64, 3000 steps", flush=True)
+    a = OC._crossing(gap=2e-4, vel_b=[0.0, 0.0, -0.05], mu=0.3, c=1.0)
+    b = OC._crossing(gap=1e-4, vel_b=[0.02, 0.0, -0.04], mu=0.3, c=1.0)
+    inp = a.copy()
+    for f in ("n_elems", "velocity", "director", "omega", "density", "youngs", "shear_modulus", "radius",
+              "shear_coeff", "damping", "bc_start", "bc_end"):
+        setattr(inp, f, np.concatenate([getattr(a, f), getattr(b, f)]))
+    inp.position = np.concatenate([a.position, b.position + np.array([20.0, 3.0, -1.0])])
+    norms, _ = run_both(inp, 3000)
+    assert_norms(norms)
