@@ -180,10 +180,10 @@ typedef struct {
      * potential 1/2 wall_k delta^2 joins each rod's W_ext.  A rod does not
      * touch itself.  Pairs are found every step by a hashed uniform grid over
      * the node positions (cells of twice the largest radius), so each step is
-     * one launch sequence: FP64 batches only (ROD_EUNSUPPORTED for FP32),
-     * substeps must be 0 or 1 (one step per launch), and forces are summed in
-     * the order the grid lists the pairs, which may differ between runs at
-     * round-off. */
+     * one launch sequence: substeps must be 0 or 1 (one step per launch);
+     * FP32 batches sum their node positions along each rod in FP64 for the
+     * grid; forces are summed in the order the grid lists the pairs, which
+     * may differ between runs at round-off. */
     int32_t rod_contact;             /* 0 or 1 */
 } rod_batch_desc;
 
@@ -210,7 +210,7 @@ typedef struct {
  * not of unit length within 1e-9, wall_k, wall_c or wall_mu negative,
  * wall_vslip <= 0, rod_contact not 0 or 1, rod_contact with substeps > 1),
  * ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the
- * longest rod or connected group, rod_contact in an FP32 batch).
+ * longest rod or connected group).
  * A time step above the explicit stability estimate is reported through
  * rod_last_error with ROD_OK.
  */

@@ -1,4 +1,4 @@
-// contact_kernels.hip -- gfx950 kernels of rod-rod contact (FP64 batches).
+// contact_kernels.hip -- gfx950 kernels of rod-rod contact.
 //
 // Results, "Fibrous granular materials" (filaments in frictional contact;
 // the paper names a GPU collision engine as future work and leaves the
@@ -23,8 +23,8 @@ namespace {
 // Node id's rod, its position `drift` seconds ahead and its velocity (FP64
 // state: lane node i at the slot, node n in the tail); false for padding slots
 // and non-finite positions.
-__device__ inline bool contact_node(const DevBatch<double> &B, int64_t id, double drift, int &rod, double x[3],
-                                    double v[3])
+__device__ inline bool contact_node(const DevBatch<double> &B, const ContactGrid &, int64_t id, double drift,
+                                    int &rod, double x[3], double v[3])
 {
     const int64_t NS = B.n_slots;
     if (id < NS) {
@@ -44,6 +44,48 @@ __device__ inline bool contact_node(const DevBatch<double> &B, int64_t id, doubl
     return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
 }
 
+// FP32 batches hold edges and each rod's anchor: the positions come from
+// contact_positions_kernel (already advanced by the drift), velocities from
+// the state.
+__device__ inline bool contact_node(const DevBatch<float> &B, const ContactGrid &G, int64_t id, double, int &rod,
+                                    double x[3], double v[3])
+{
+    const int64_t NS = B.n_slots;
+    if (id < NS) {
+        rod = B.slot_rod[id];
+        if (rod < 0) return false;
+        for (int a = 0; a < 3; ++a) v[a] = (double)B.state[(VX + a) * NS + id];
+    } else {
+        rod = (int)(id - NS);
+        for (int a = 0; a < 3; ++a) v[a] = (double)B.tail[(TVX + a) * B.n_rods + rod];
+    }
+    for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nn + id];
+    return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+}
+
+// FP32 node positions for the grid: rod origin + anchor + the edges before
+// the node, summed in FP64 along each rod (one thread per rod), advanced by
+// the drift.
+__global__ void contact_positions_kernel(const DevBatch<float> B, const ContactGrid G, double drift)
+{
+    const int rod = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rod >= B.n_rods) return;
+    const int64_t NS = B.n_slots, nn = G.nn, R = B.n_rods;
+    const int n = B.rod_n[rod];
+    const int64_t s0 = B.rod_slot[rod];
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = G.origin[a * R + rod] + (double)B.tail[(TRX + a) * R + rod];
+    for (int j = 0; j <= n; ++j) {
+        const int64_t id = j < n ? s0 + j : NS + rod;
+        for (int a = 0; a < 3; ++a) {
+            const double v = j < n ? (double)B.state[(VX + a) * NS + s0 + j] : (double)B.tail[(TVX + a) * R + rod];
+            G.xabs[a * nn + id] = x[a] + drift * v;
+        }
+        if (j < n)
+            for (int a = 0; a < 3; ++a) x[a] += (double)B.state[(RX + a) * NS + s0 + j];
+    }
+}
+
 __device__ inline int wrap_cell(int64_t c, int g)
 {
     const int64_t m = c % g;
@@ -56,13 +98,14 @@ __device__ inline int64_t cell_of(double x, double org, double inv_cell)
     return (int64_t)floor(q < -1e15 ? -1e15 : (q > 1e15 ? 1e15 : q));   // finite x; keeps the cast defined
 }
 
-__global__ void contact_bin_kernel(const DevBatch<double> B, const ContactGrid G, double drift)
+template <typename T>
+__global__ void contact_bin_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
 {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn) return;
     int rod;
     double x[3], v[3];
-    if (!contact_node(B, id, drift, rod, x, v)) {
+    if (!contact_node(B, G, id, drift, rod, x, v)) {
         G.rank[id] = -1;
         return;
     }
@@ -140,7 +183,8 @@ __global__ __launch_bounds__(256) void contact_scan_add(const ContactGrid G, int
         if (base + k < nb) G.start[base + k] += off;
 }
 
-__global__ void contact_scatter_kernel(const DevBatch<double> B, const ContactGrid G, double drift)
+template <typename T>
+__global__ void contact_scatter_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
 {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn) return;
@@ -148,7 +192,7 @@ __global__ void contact_scatter_kernel(const DevBatch<double> B, const ContactGr
     if (r < 0) return;
     int rod;
     double x[3], v[3];
-    contact_node(B, id, drift, rod, x, v);
+    contact_node(B, G, id, drift, rod, x, v);
     const int64_t p = G.start[G.bucket[id]] + r;
     G.spr[p] = make_double4(x[0], x[1], x[2], B.rod_rad[rod]);
     G.svr[p] = make_double4(v[0], v[1], v[2], (double)rod);
@@ -163,7 +207,8 @@ __global__ void contact_scatter_kernel(const DevBatch<double> B, const ContactGr
 // node's id (padding ids keep the zeros set at creation).  (Renumbering the
 // workgroups so that each XCD sweeps a contiguous eighth halved this kernel's
 // HBM reads but made it slower on the fibre pile, so the plain order stays.)
-__global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid G, int nb)
+template <typename T>
+__global__ void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
 {
     const int64_t p0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p0 >= G.start[nb]) return;
@@ -217,9 +262,8 @@ __global__ void contact_force_kernel(const DevBatch<double> B, const ContactGrid
     G.pot[id] = pot;
 }
 
-}  // namespace
-
-hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, double drift, hipStream_t s)
+template <typename T>
+hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double drift, hipStream_t s)
 {
     const int bs = 256;
     const int64_t nb64 = (int64_t)g.gx * g.gy * g.gz;
@@ -228,13 +272,29 @@ hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, doubl
     const int nb = (int)nb64;
     const int n_chunks = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
     const int gn = (int)((g.nn + bs - 1) / bs);
-    hipLaunchKernelGGL(contact_bin_kernel, dim3(gn), dim3(bs), 0, s, b, g, drift);
+    if constexpr (sizeof(T) == 4) {
+        if (!g.xabs || !g.origin) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(contact_positions_kernel, dim3((b.n_rods + 63) / 64), dim3(64), 0, s, b, g, drift);
+    }
+    hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
     hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb);
     hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb);
     hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb);
-    hipLaunchKernelGGL(contact_scatter_kernel, dim3(gn), dim3(bs), 0, s, b, g, drift);
-    hipLaunchKernelGGL(contact_force_kernel, dim3(gn), dim3(bs), 0, s, b, g, nb);
+    hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+    hipLaunchKernelGGL((contact_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, double drift, hipStream_t s)
+{
+    return launch_contact_t<double>(b, g, drift, s);
+}
+
+hipError_t launch_contact(const DevBatch<float> &b, const ContactGrid &g, double drift, hipStream_t s)
+{
+    return launch_contact_t<float>(b, g, drift, s);
 }
 
 }  // namespace rodk

@@ -124,7 +124,7 @@ struct DevBatch {
     int n_walls;
     T wall[DEV_MAX_WALLS][4];
     T wall_k, wall_c, wall_mu, wall_vslip;
-    // rod-rod contact (FP64 batches, one step per launch): the contact force
+    // rod-rod contact (one step per launch): the contact force
     // on every node for the coming kick, [3][n_slots + n_rods] by node id (the
     // slot's node i, then each rod's node n), and each node's share of the
     // pairs' penalty potential [n_slots + n_rods] (energy passes); NULL
@@ -155,12 +155,15 @@ struct ContactGrid {
     int32_t *sid;      // [nn] node ids in bucket order
     double *force;     // [3][nn] contact force by node id
     double *pot;       // [nn] potential share by node id
+    const double *origin;   // FP32 batches: [3][n_rods] rod origins
+    double *xabs;      // FP32 batches: [3][nn] node positions (summed in FP64) after the drift
 };
 constexpr int64_t CONTACT_MAX_BUCKETS = 4096 * 1024;   // chunk totals fit one workgroup's prefix sum
 
 // Fill g.force and g.pot for positions advanced by `drift` seconds from the
 // state (dt/2 before a step's kick, 0 for energies).
 hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, double drift, hipStream_t s);
+hipError_t launch_contact(const DevBatch<float> &b, const ContactGrid &g, double drift, hipStream_t s);
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
 hipError_t launch_step(const DevBatch<double> &b, int waves, int n_sub, int grid, hipStream_t s);

@@ -687,17 +687,15 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                         wall_force(B, sh.wls, rad, x0, x1, x2, v0, v1, v2, fc0, fc1, fc2);
                         if (last) wall_force(B, sh.wls, rad, x0 + d0, x1 + d1, x2 + d2, u0, u1, u2, gc0, gc1, gc2);
                     }
-                    if constexpr (POS) {
-                        // rod-rod contact, from the contact pass before this
-                        // launch (one step per launch)
-                        if (B.cforce) {
-                            const int64_t NN = B.n_slots + B.n_rods;
-                            const int64_t sl = (int64_t)tile * TL + lane;
-                            fc0 += B.cforce[sl]; fc1 += B.cforce[NN + sl]; fc2 += B.cforce[2 * NN + sl];
-                            if (last) {
-                                const int64_t id = B.n_slots + B.slot_rod[sl];
-                                gc0 += B.cforce[id]; gc1 += B.cforce[NN + id]; gc2 += B.cforce[2 * NN + id];
-                            }
+                    // rod-rod contact, from the contact pass before this
+                    // launch (one step per launch)
+                    if (B.cforce) {
+                        const int64_t NN = B.n_slots + B.n_rods;
+                        const int64_t sl = (int64_t)tile * TL + lane;
+                        fc0 += T(B.cforce[sl]); fc1 += T(B.cforce[NN + sl]); fc2 += T(B.cforce[2 * NN + sl]);
+                        if (last) {
+                            const int64_t id = B.n_slots + B.slot_rod[sl];
+                            gc0 += T(B.cforce[id]); gc1 += T(B.cforce[NN + id]); gc2 += T(B.cforce[2 * NN + id]);
                         }
                     }
                 }

@@ -231,8 +231,6 @@ int validate(const rod_batch_desc *d)
     if (d->rod_contact != 0 && d->rod_contact != 1) return fail(ROD_EINVAL, "rod_contact must be 0 or 1");
     if (d->rod_contact && d->substeps > 1)
         return fail(ROD_EINVAL, "rod contact runs one step per launch: substeps must be 0 or 1");
-    if (d->rod_contact && d->precision == ROD_F32)
-        return fail(ROD_EUNSUPPORTED, "rod contact runs in FP64 batches only");
     if (d->n_walls > 0 || d->rod_contact) {
         if (d->n_walls > 0 && !d->walls) return fail(ROD_EINVAL, "walls is NULL");
         for (int w = 0; w < d->n_walls; ++w) {
@@ -474,8 +472,8 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.rod_org = (const T *)b->d_rod_org;
     d.rod_rad = b->d_rod_rad;
     d.wall_off = (const T *)b->d_wall_off;
-    d.cforce = sizeof(T) == 8 && b->rod_contact ? b->cg.force : nullptr;
-    d.cpot = sizeof(T) == 8 && b->rod_contact ? b->cg.pot : nullptr;
+    d.cforce = b->rod_contact ? b->cg.force : nullptr;
+    d.cpot = b->rod_contact ? b->cg.pot : nullptr;
     d.n_walls = b->n_walls;
     for (int w = 0; w < 8; ++w)
         for (int k = 0; k < 4; ++k) d.wall[w][k] = T(w < b->n_walls ? b->walls[w][k] : 0.0);
@@ -854,6 +852,17 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     HIPCHK(hipMemset(g.count, 0, nb * sizeof(int32_t)));
     HIPCHK(hipMemset(g.force, 0, 3 * g.nn * sizeof(double)));
     HIPCHK(hipMemset(g.pot, 0, g.nn * sizeof(double)));
+    if (b->precision == ROD_F32) {
+        // FP32 positions are summed from the rod origins, edges and anchors
+        std::vector<double> org((size_t)3 * b->R);
+        for (int r = 0; r < b->R; ++r)
+            for (int a = 0; a < 3; ++a) org[(size_t)a * b->R + r] = b->origin[3 * r + a];
+        double *d_org = nullptr;
+        HIPCHK(hipMalloc((void **)&d_org, org.size() * sizeof(double)));
+        g.origin = d_org;
+        HIPCHK(hipMemcpy(d_org, org.data(), org.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc((void **)&g.xabs, 3 * g.nn * sizeof(double)));
+    }
     HIPCHK(hipDeviceSynchronize());
     return ROD_OK;
 }
@@ -874,7 +883,8 @@ int enqueue_steps(rod_batch *b, int64_t n_steps, hipStream_t s)
         const int n_sub = (int)std::min<int64_t>(S, n_steps - done);
         if (b->rod_contact) {
             // contact forces at the positions after the coming half drift
-            hipError_t e = rodk::launch_contact(b->b64, b->cg, 0.5 * b->dt, s);
+            hipError_t e = b->precision == ROD_F32 ? rodk::launch_contact(b->b32, b->cg, 0.5 * b->dt, s)
+                                                   : rodk::launch_contact(b->b64, b->cg, 0.5 * b->dt, s);
             if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
         }
         hipError_t e = b->precision == ROD_F32 ? rodk::launch_step(b->b32, b->waves, n_sub, b->grid, s)
@@ -1294,7 +1304,8 @@ int rod_energy(rod_batch *b, double *out, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (b->rod_contact) {
         // the pairs' potentials at the current positions
-        hipError_t e = rodk::launch_contact(b->b64, b->cg, 0.0, s);
+        hipError_t e = b->precision == ROD_F32 ? rodk::launch_contact(b->b32, b->cg, 0.0, s)
+                                               : rodk::launch_contact(b->b64, b->cg, 0.0, s);
         if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
     }
     hipError_t e = b->precision == ROD_F32 ? rodk::launch_energy(b->b32, b->d_energy, s)
@@ -1383,6 +1394,8 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.spr);
     (void)hipFree(b->cg.svr);
     (void)hipFree(b->cg.sid);
+    (void)hipFree((void *)b->cg.origin);
+    (void)hipFree(b->cg.xabs);
     (void)hipFree(b->cg.force);
     (void)hipFree(b->cg.pot);
     (void)hipFree(b->d_tail);

@@ -99,3 +99,41 @@ def test_wrapped_grid_f64():
     inp.position = np.concatenate([a.position, b.position + np.array([20.0, 3.0, -1.0])])
     norms, _ = run_both(inp, 3000)
     assert_norms(norms)
+
+
+def test_contact_graph_replays():
+    """The same captured 100-step graph replayed five times (with eager work
+    and synchronisations between the replays) against the oracle's 500 steps:
+    every contact pass clears its bucket counts for the next, so replays after
+    the first see a clean grid."""
+    print("case: fibre pile 24 rods, 5 replays of a 100-step graph, FP64", flush=True)
+    import torch
+    R = _rod()
+    inp = _small_pile(seed=95)
+    from parity import oracle_pair, rod_norms, energy_norm, fp64_bars
+    o, p = oracle_pair(inp, 500)
+    with R.RodBatch(inp, precision="f64") as b:
+        for k in range(5):
+            b.step(100)
+            torch.cuda.synchronize()
+            _ = torch.ones(1024, device="cuda").sum().item()   # eager work between replays
+        pos, vel, dr, om, t = b.get_state()
+        e_gpu = b.energy()
+    norms = rod_norms(inp, o.state(), (pos, vel, dr, om), 500 * inp.dt)
+    norms["energy"] = energy_norm(o.energy(), e_gpu)
+    norms["bars"], _ = fp64_bars(inp, o, p, 500)
+    print("norms", {k: f"{v:.2e}" for k, v in norms.items() if k != "bars"}, flush=True)
+    assert_norms(norms)
+
+
+def test_contact_f32_parity():
+    """FP32 batches: node positions for the grid summed along each rod in FP64
+    from the FP32 edges; held to the FP32 bar (1e-4 on positions and
+    directors) against the FP64 oracle."""
+    cases = (("fibre pile 24 rods", _small_pile(seed=97), 1000),
+             ("crossing collision with friction", OC._crossing(gap=2e-4, vel_b=[0.03, 0.0, -0.05], mu=0.5, c=2.0), 2000))
+    for name, inp, steps in cases:
+        print(f"case: {name}, FP32, {steps} steps", flush=True)
+        norms, info = run_both(inp, steps, precision="f32")
+        assert info["substeps"] == 1
+        assert_norms(norms, 1e-4, keys=("pos", "dir"))
