@@ -250,30 +250,42 @@ def time_walls(steps, warmup, tile_waves=0, substeps=0, precisions=("f64", "f32"
 CONTACT_NODE_BYTES = 72                          # a contact pass: node position and velocity in, force out
 
 
-def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH):
+def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH, precisions=("f64", "f32")):
     """The fibre pile (16,384 fibres x 50 elements in 21 crossed layers on a
-    floor, rod-rod contact found by the hash grid every step, FP64).  One step
-    per launch, so the pass is HBM-bound: the roofline is bytes against the
-    HBM peak, algorithmic bytes per step = the step's 400 per element (state in
-    and out, constants) + 72 per node for the contact pass."""
+    floor, rod-rod contact found by the hash grid every step), FP64 (the
+    object's own figures) and FP32 (its "f32" member).  One step per launch, so
+    the pass is HBM-bound: the roofline is bytes against the HBM peak,
+    algorithmic bytes per step = the step's 400 (FP64) / 204 (FP32) per element
+    (state in and out, constants) + 72 per node for the contact pass."""
     from paper_2605_13766_amd import workloads as W
     inp = W.fibre_pile()
-    r = time_gpu(inp, "f64", steps, warmup, tile_waves, 1, traffic_tag="none", n_steps=n_steps)
+    out = None
+    for p in precisions:
+        row = _time_contact_one(inp, p, steps, warmup, tile_waves, n_steps)
+        if out is None:
+            out = row
+        else:
+            out[p] = {k: row[k] for k in ("value", "ms_per_step", "ms_per_simulation_step", "tile_waves", "roofline")}
+    return out
+
+
+def _time_contact_one(inp, precision, steps, warmup, tile_waves, n_steps):
+    r = time_gpu(inp, precision, steps, warmup, tile_waves, 1, traffic_tag="none", n_steps=n_steps)
     n_nodes = inp.n_elements + inp.n_rods
     step_s = r["launch_ms"] * 1e-3 / n_steps
-    algo = ALGO_BYTES["f64"] * inp.n_elements + CONTACT_NODE_BYTES * n_nodes
+    algo = ALGO_BYTES[precision] * inp.n_elements + CONTACT_NODE_BYTES * n_nodes
     achieved = algo / step_s / 1e9
     return {
         "workload": f"fibre_pile: {inp.n_rods:,} fibres x 50 elements (0.5 m, radius 1 cm) in 21 crossed layers on a "
                     f"floor, rod-rod contact (k {inp.wall_k:g} N/m, mu {inp.wall_mu:g}), gravity, dt 1e-5 s, "
-                    "one step per launch, FP64",
+                    f"one step per launch, {precision.upper()}",
         "unit": "element-steps/s",
         "value": r["value"], "ms_per_step": r["ms_per_step"], "steps_per_bench_step": n_steps,
         "ms_per_simulation_step": step_s * 1e3,
         "tile_waves": r["info"]["tile_waves"], "substeps_per_launch": r["info"]["substeps"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                      "frac": achieved / 8000.0,
-                     "traffic": traffic_from_profile("f64_fibrepile16384", r["info"]["tile_waves"], 1,
+                     "traffic": traffic_from_profile(f"{precision}_fibrepile16384", r["info"]["tile_waves"], 1,
                                                      (KERNEL_SRC, CONTACT_SRC)),
                      "algorithmic_bytes_per_step": algo},
     }
@@ -562,9 +574,10 @@ def main(argv=None):
         print("timing the active filaments in a box", file=sys.stderr, flush=True)
         line["walls"] = time_walls(args.steps, args.warmup, args.tile_waves, args.substeps,
                                    precisions=args.precisions.split(","))
-    if not args.no_contact and "f64" in args.precisions.split(","):
+    if not args.no_contact:
         print("timing the fibre pile (rod-rod contact)", file=sys.stderr, flush=True)
-        line["contact"] = time_contact(args.steps, args.warmup, args.tile_waves, args.contact_steps)
+        line["contact"] = time_contact(args.steps, args.warmup, args.tile_waves, args.contact_steps,
+                                       precisions=args.precisions.split(","))
     if not args.no_connected:
         print("timing the millipede swarm", file=sys.stderr, flush=True)
         line["connected"] = time_connected(args.steps, args.warmup, args.tile_waves, args.substeps,
