@@ -64,25 +64,43 @@ __device__ inline bool contact_node(const DevBatch<float> &B, const ContactGrid 
 }
 
 // FP32 node positions for the grid: rod origin + anchor + the edges before
-// the node, summed in FP64 along each rod (one thread per rod), advanced by
-// the drift.
-__global__ void contact_positions_kernel(const DevBatch<float> B, const ContactGrid G, double drift)
+// the node, summed in FP64 and advanced by the drift.  One wave per rod: the
+// lanes take 64 consecutive nodes at a time (coalesced loads and stores), an
+// exclusive prefix sum of the FP32 edges across the lanes places them, and
+// the chunk's total carries to the next 64.
+__global__ __launch_bounds__(256) void contact_positions_kernel(const DevBatch<float> B, const ContactGrid G,
+                                                                double drift)
 {
-    const int rod = blockIdx.x * blockDim.x + threadIdx.x;
-    if (rod >= B.n_rods) return;
+    const int rod = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (rod >= B.n_rods) return;   // whole waves leave together
     const int64_t NS = B.n_slots, nn = G.nn, R = B.n_rods;
     const int n = B.rod_n[rod];
     const int64_t s0 = B.rod_slot[rod];
-    double x[3];
-    for (int a = 0; a < 3; ++a) x[a] = G.origin[a * R + rod] + (double)B.tail[(TRX + a) * R + rod];
-    for (int j = 0; j <= n; ++j) {
-        const int64_t id = j < n ? s0 + j : NS + rod;
+    double carry[3];
+    for (int a = 0; a < 3; ++a) carry[a] = G.origin[a * R + rod] + (double)B.tail[(TRX + a) * R + rod];
+    for (int base = 0; base <= n; base += 64) {
+        const int j = base + lane;   // this lane's node; its edge j leads to node j + 1
+        double incl[3];
+        for (int a = 0; a < 3; ++a) incl[a] = j < n ? (double)B.state[(RX + a) * NS + s0 + j] : 0.0;
+        for (int d = 1; d < 64; d <<= 1)
+            for (int a = 0; a < 3; ++a) {
+                const double up = __shfl_up(incl[a], d, 64);
+                if (lane >= d) incl[a] += up;
+            }
+        double before[3];   // edges base .. j-1 (every lane takes part in the shuffle)
         for (int a = 0; a < 3; ++a) {
-            const double v = j < n ? (double)B.state[(VX + a) * NS + s0 + j] : (double)B.tail[(TVX + a) * R + rod];
-            G.xabs[a * nn + id] = x[a] + drift * v;
+            const double up = __shfl_up(incl[a], 1, 64);
+            before[a] = lane > 0 ? up : 0.0;
         }
-        if (j < n)
-            for (int a = 0; a < 3; ++a) x[a] += (double)B.state[(RX + a) * NS + s0 + j];
+        if (j <= n) {
+            const int64_t id = j < n ? s0 + j : NS + rod;
+            for (int a = 0; a < 3; ++a) {
+                const double v = j < n ? (double)B.state[(VX + a) * NS + s0 + j] : (double)B.tail[(TVX + a) * R + rod];
+                G.xabs[a * nn + id] = carry[a] + before[a] + drift * v;
+            }
+        }
+        for (int a = 0; a < 3; ++a) carry[a] += __shfl(incl[a], 63, 64);
     }
 }
 
@@ -274,7 +292,7 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
     const int gn = (int)((g.nn + bs - 1) / bs);
     if constexpr (sizeof(T) == 4) {
         if (!g.xabs || !g.origin) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(contact_positions_kernel, dim3((b.n_rods + 63) / 64), dim3(64), 0, s, b, g, drift);
+        hipLaunchKernelGGL(contact_positions_kernel, dim3((b.n_rods + 3) / 4), dim3(256), 0, s, b, g, drift);
     }
     hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
     hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb);
