@@ -347,13 +347,30 @@ def cpu_baseline(inp, target_s=10.0):
     t = time.perf_counter()
     o.step(STEPS_PER_LAUNCH)
     dt = time.perf_counter() - t
+    # the same oracle on one thread: 100 steps of a sample sized for about 1.5 s
+    k = int(np.clip(n_rods * 1.5 / max(dt * 0.1 * threads, 1e-9), 4, n_rods))
+    one = inp.subset(np.sort(rng.choice(inp.n_rods, size=k, replace=False)))
+    o1 = ro.Oracle(one)
+    t = time.perf_counter()
+    o1.step(100, n_threads=1)
+    dt1 = time.perf_counter() - t
+    o1.step(0, n_threads=threads)   # restores the thread count for later oracle calls
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": sample.n_elements * STEPS_PER_LAUNCH / dt,
         "unit": "element-steps/s",
         "cores": threads,
+        "cpu_model": model,
+        "one_thread_value": one.n_elements * 100 / dt1,
         "kind": "oracle",
         "sample": f"{n_rods} of the {inp.n_rods} rods ({sample.n_elements} elements), "
-                  f"{STEPS_PER_LAUNCH} steps, FP64, {threads} OpenMP threads, {dt:.1f} s",
+                  f"{STEPS_PER_LAUNCH} steps, FP64, {threads} OpenMP threads, {dt:.1f} s; one thread: {k} rods, "
+                  f"100 steps, {dt1:.1f} s",
     }
 
 
