@@ -15,6 +15,8 @@ split between the two rods):
 * a rod laid on another on the floor settles into the grooves between the
   lower rod's nodes, its weight carried by the node contacts (the vertical
   components of k delta sum to M g), and the floor carries both rods;
+* normal damping c takes energy out of a frictionless collision, more for a
+  larger c, none for c = 0;
 * contact off: far-apart rods, and a rod curled onto itself (no self-contact),
   step exactly as without contact.
 """
@@ -161,3 +163,20 @@ def test_no_contact_changes_nothing():
     a.step(300)
     b.step(300)
     assert np.array_equal(a.pos, b.pos) and np.array_equal(a.vel, b.vel)
+
+
+def test_contact_damping_dissipates_in_proportion():
+    """Head-on frictionless collisions with growing normal damping c: the energy
+    after the collision falls as c grows (the damping term delta c v_n opposes
+    the approach and the separation), and with c = 0 it is conserved; a damping
+    of the wrong sign would feed energy."""
+    lost = []
+    for c in (0.0, 1.0, 4.0):
+        inp = _crossing(gap=2e-4, vel_b=[0.0, 0.0, -0.05], c=c)
+        o = ro.Oracle(inp)
+        H0 = o.energy().sum()
+        o.step(4000)
+        lost.append((H0 - o.energy().sum()) / H0)
+    print("relative energy lost", lost)
+    assert abs(lost[0]) < 1e-3
+    assert 0 < lost[1] < lost[2]
