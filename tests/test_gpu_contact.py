@@ -137,3 +137,56 @@ def test_contact_f32_parity():
         norms, info = run_both(inp, steps, precision="f32")
         assert info["substeps"] == 1
         assert_norms(norms, 1e-4, keys=("pos", "dir"))
+
+
+def test_contact_edge_cases_f64():
+    """Contact with everything else at once: rods of 1 to 100 elements and of
+    different radii (the grid's cells follow the largest), some clamped at
+    their base (a clamped node keeps its place whatever presses on it),
+    magnetized elements in a rotating field, muscle moments, gravity and a
+    floor; rods cross one above the other so that many pairs touch."""
+    print("case: contact edge cases (lengths 1..100, radii, clamps, field, muscles, floor), FP64, 1000 steps",
+          flush=True)
+    rng = np.random.default_rng(99)
+    lengths = [1, 2, 3, 20, 63, 64, 65, 100, 5, 40]
+    nodes_list, Q_list = [], []
+    for k, n in enumerate(lengths):
+        ds = 0.004
+        direction = (1, 0, 0) if k % 2 == 0 else (0, 1, 0)
+        d1 = (0, 1, 0) if k % 2 == 0 else (0, 0, 1)
+        # every rod centred over (0.02, 0.02), alternately along x and y, 5 mm above the previous
+        L = n * ds
+        origin = (0.02 - L / 2, 0.02, 0.004 + 0.005 * k) if k % 2 == 0 else (0.02, 0.02 - L / 2, 0.004 + 0.005 * k)
+        nodes, Q = W.straight_rod(n, n * ds, direction=direction, d1=d1, origin=origin)
+        nodes_list.append(nodes)
+        Q_list.append(Q)
+    R = len(lengths)
+    radii = rng.uniform(0.002, 0.004, R)
+    vel = [rng.normal(0, 0.02, (n + 1, 3)) for n in lengths]
+    inp = W._assemble("contact_edges", nodes_list, Q_list, 2e-6, density=1000.0, youngs=1e6, radius=radii,
+                      damping=0.2, bc_start=np.array([k % 4 == 1 for k in range(R)], np.int32), bc_end=0,
+                      velocity_list=vel)
+    inp.gravity = np.array([0.0, 0.0, -9.81])
+    inp.walls = np.array([[0.0, 0.0, 1.0, 0.0]])
+    inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = 20.0, 10.0, 0.3, 0.02
+    inp.rod_contact = 1
+    ne = int(np.sum(lengths))
+    inp.magnetization = np.tile([0.0, 0.0, 1e-4], (ne, 1))
+    inp.field = np.array([0.0, 0.0, 0.0, 0.01, 0.0, 0.0, 0.0, 0.01, 0.0])
+    inp.field_freq = 5.0
+    nv = ne - R
+    inp.muscle_amp = np.full(nv, 1e-7)
+    inp.muscle_axis = np.tile([1.0, 0.0, 0.0], (R, 1))
+    inp.muscle_freq = np.full(R, 2.0)
+    inp.muscle_wavenumber = np.full(R, 10.0)
+    inp.muscle_phase = rng.uniform(0, 2 * np.pi, R)
+    from oracle import rodoracle as ro
+    o = ro.Oracle(inp)
+    d = o.pos[:, None, :] - o.pos[None, :, :]
+    rod = np.repeat(np.arange(R), np.asarray(lengths) + 1)
+    rr = radii[rod]
+    touching = (np.linalg.norm(d, axis=2) < rr[:, None] + rr[None, :]) & (rod[:, None] != rod[None, :])
+    print("pairs in contact at the start", int(touching.sum()) // 2, flush=True)
+    assert touching.sum() > 0
+    norms, _ = run_both(inp, 1000)
+    assert_norms(norms)
