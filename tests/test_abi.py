@@ -181,3 +181,17 @@ def test_rod_contact_descriptor_rejected_when_invalid():
     assert "substeps" in _expect(rod.ROD_EINVAL, base, substeps=2)
     bad = base.copy(); bad.walls = None; bad.wall_vslip = 0.0
     assert "wall_vslip" in _expect(rod.ROD_EINVAL, bad)
+
+
+def test_empty_batch_rejected():
+    """A batch with no rods is an error (ROD_EINVAL), not an empty launch."""
+    from paper_2605_13766_amd import rod
+    import dataclasses
+    one = W.ragged_batch(n_rods=1, n_min=16, n_max=16, seed=41)
+    empty = dataclasses.replace(
+        one, n_elems=np.zeros(0, np.int32), position=np.zeros((0, 3)), velocity=np.zeros((0, 3)),
+        director=np.zeros((0, 3, 3)), omega=np.zeros((0, 3)),
+        **{k: np.zeros(0, np.int32 if k.startswith("bc_") else np.float64)
+           for k in ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping", "bc_start", "bc_end")})
+    assert empty.n_rods == 0
+    assert "n_rods" in _expect(rod.ROD_EINVAL, empty)
