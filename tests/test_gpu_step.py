@@ -248,3 +248,23 @@ def test_device_inputs_give_the_same_batch():
             b.step(100)
             for x, y in zip(a.get_state()[:4], b.get_state()[:4]):
                 assert np.array_equal(x, y)
+
+
+def test_zero_and_negative_steps():
+    """rod_step(0) is a no-op (state and time bit for bit), a negative count is
+    ROD_EINVAL, and a contact batch behaves the same."""
+    print("case: zero and negative step counts, plain and contact batches", flush=True)
+    R = _rod()
+    for inp in (W.ragged_batch(n_rods=8, n_min=16, n_max=40, seed=3),
+                W.fibre_pile(n_rods=8, n=10, L=0.1, per_row=2, rows=2)):
+        with R.RodBatch(inp, precision="f64") as b:
+            b.step(3)
+            before = b.get_state()
+            b.step(0)
+            after = b.get_state()
+            for x, y in zip(before[:4], after[:4]):
+                assert np.array_equal(x, y)
+            assert before[4] == after[4]
+            with pytest.raises(R.RodError) as ei:
+                b.step(-1)
+            assert ei.value.code == R.ROD_EINVAL
