@@ -91,3 +91,22 @@ def test_active_box_full_f64_sampled():
           flush=True)
     bad = {k: (norms[k], bars[k]) for k in norms if not norms[k] <= bars[k]}
     assert not bad, bad
+
+
+def test_eight_walls_f64():
+    """The largest wall count (ROD_MAX_WALLS = 8): the box's six walls and two
+    slanted ones cutting its lower corners, so that every slot of the kernel's
+    wall table is in use and some rods touch a slanted wall."""
+    print("case: rods in a box with 8 walls (2 slanted), tile_waves=4, FP64, 1000 steps", flush=True)
+    inp = _boxed(4, seed=85)
+    s2 = np.sqrt(0.5)
+    rad = np.repeat(inp.radius, inp.n_elems + 1)
+    slanted = []
+    for n in ([s2, s2, 0.0], [-s2, s2, 0.0]):
+        # placed so that the nearest node starts 0.5 mm into it
+        gap = inp.position @ np.array(n) - rad
+        slanted.append(n + [gap.min() + 5e-4])
+    inp.walls = np.concatenate([inp.walls, np.array(slanted)])
+    assert len(inp.walls) == 8
+    norms, _ = run_both(inp, 1000, tile_waves=4)
+    assert_norms(norms)
