@@ -17,6 +17,8 @@ split between the two rods):
   components of k delta sum to M g), and the floor carries both rods;
 * normal damping c takes energy out of a frictionless collision, more for a
   larger c, none for c = 0;
+* a rod pressed by an end force F against the end of a clamped rod settles
+  with the two touching nodes 2 r - F / k apart;
 * contact off: far-apart rods, and a rod curled onto itself (no self-contact),
   step exactly as without contact.
 """
@@ -180,3 +182,25 @@ def test_contact_damping_dissipates_in_proportion():
     print("relative energy lost", lost)
     assert abs(lost[0]) < 1e-3
     assert 0 < lost[1] < lost[2]
+
+
+def test_static_load_on_a_clamped_rod():
+    """A clamped rod A and a free rod B on one line along x, B's first node
+    touching A's last; an end force F on B's last node presses B against A.
+    With damping B settles where the contact carries F: the two nodes sit
+    2 r - F / k apart (Hooke's law of the penalty), independent of B's own
+    compression."""
+    k, F = 40.0, 2e-3
+    na = nb = 5
+    a_nodes, a_Q = W.straight_rod(na, 0.05, direction=(1, 0, 0), d1=(0, 1, 0), origin=(-0.05, 0.0, 0.0))
+    b_nodes, b_Q = W.straight_rod(nb, 0.05, direction=(1, 0, 0), d1=(0, 1, 0), origin=(2 * RAD, 0.0, 0.0))
+    inp = W._assemble("press", [a_nodes, b_nodes], [a_Q, b_Q], 1e-5, density=1000.0, youngs=1e6, radius=RAD,
+                      damping=np.array([0.0, 30.0]), bc_start=np.array([1, 0]), bc_end=np.array([1, 0]),
+                      end_force=np.array([[0.0, 0.0, 0.0], [-F, 0.0, 0.0]]))
+    inp.rod_contact = 1
+    inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = k, 0.0, 0.0, 1e-4
+    o = ro.Oracle(inp)
+    o.step(100000)
+    gap = o.pos[na + 1, 0] - o.pos[na, 0]
+    print("gap", gap, "want", 2 * RAD - F / k, "residual speed", np.abs(o.vel).max())
+    assert abs(gap - (2 * RAD - F / k)) < 1e-8
