@@ -196,3 +196,11 @@ def test_contact_edge_cases_f64():
     assert touching.sum() > 0
     norms, _ = run_both(inp, 1000)
     assert_norms(norms)
+
+
+def test_press_against_clamped_rod_f64():
+    """A rod pushed by an end force against a rod clamped at both ends (the
+    oracle's static-load pin), 2000 steps of the approach to rest."""
+    print("case: rod pressed against a clamped rod, FP64, 2000 steps", flush=True)
+    norms, _ = run_both(OC._press(40.0, 2e-3), 2000)
+    assert_norms(norms)

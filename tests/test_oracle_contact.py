@@ -184,14 +184,9 @@ def test_contact_damping_dissipates_in_proportion():
     assert 0 < lost[1] < lost[2]
 
 
-def test_static_load_on_a_clamped_rod():
-    """A clamped rod A and a free rod B on one line along x, B's first node
-    touching A's last; an end force F on B's last node presses B against A.
-    With damping B settles where the contact carries F: the two nodes sit
-    2 r - F / k apart (Hooke's law of the penalty), independent of B's own
-    compression."""
-    k, F = 40.0, 2e-3
-    na = nb = 5
+def _press(k, F, na=5, nb=5):
+    """Rod A (clamped at both ends) and rod B on the x axis, B's first node
+    touching A's last; an end force -F x on B's last node."""
     a_nodes, a_Q = W.straight_rod(na, 0.05, direction=(1, 0, 0), d1=(0, 1, 0), origin=(-0.05, 0.0, 0.0))
     b_nodes, b_Q = W.straight_rod(nb, 0.05, direction=(1, 0, 0), d1=(0, 1, 0), origin=(2 * RAD, 0.0, 0.0))
     inp = W._assemble("press", [a_nodes, b_nodes], [a_Q, b_Q], 1e-5, density=1000.0, youngs=1e6, radius=RAD,
@@ -199,6 +194,18 @@ def test_static_load_on_a_clamped_rod():
                       end_force=np.array([[0.0, 0.0, 0.0], [-F, 0.0, 0.0]]))
     inp.rod_contact = 1
     inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = k, 0.0, 0.0, 1e-4
+    return inp
+
+
+def test_static_load_on_a_clamped_rod():
+    """A clamped rod A and a free rod B on one line along x, B's first node
+    touching A's last; an end force F on B's last node presses B against A.
+    With damping B settles where the contact carries F: the two nodes sit
+    2 r - F / k apart (Hooke's law of the penalty), independent of B's own
+    compression."""
+    k, F = 40.0, 2e-3
+    na = 5
+    inp = _press(k, F)
     o = ro.Oracle(inp)
     o.step(100000)
     gap = o.pos[na + 1, 0] - o.pos[na, 0]
