@@ -36,11 +36,8 @@ def test_crossing_collision_f64():
     assert_norms(norms)
 
 
-def test_pile_with_connections_f64():
-    """Contact together with connections and walls: pairs of fibres joined
-    end to end by springs."""
-    print("case: fibre pile with end-to-end springs, FP64, 1000 steps", flush=True)
-    inp = _small_pile(seed=93)
+def _linked_pile(seed=93):
+    inp = _small_pile(seed=seed)
     pairs = [(2 * k, 2 * k + 1) for k in range(12)]
     inp.conn_rod = np.array(pairs, np.int32)
     inp.conn_node = np.array([[20, 0]] * len(pairs), np.int32)
@@ -48,7 +45,14 @@ def test_pile_with_connections_f64():
     inp.conn_c = np.full(len(pairs), 0.01)
     inp.conn_rest = np.array([np.linalg.norm(inp.position[inp.node_offset[b]] - inp.position[inp.node_offset[a] + 20])
                               for a, b in pairs])
-    norms, _ = run_both(inp, 1000)
+    return inp
+
+
+def test_pile_with_connections_f64():
+    """Contact together with connections and walls: pairs of fibres joined
+    end to end by springs."""
+    print("case: fibre pile with end-to-end springs, FP64, 1000 steps", flush=True)
+    norms, _ = run_both(_linked_pile(), 1000)
     assert_norms(norms)
 
 
@@ -137,6 +141,7 @@ def test_contact_f32_parity():
     from the FP32 edges; held to the FP32 bar (1e-4 on positions and
     directors) against the FP64 oracle."""
     cases = (("fibre pile 24 rods", _small_pile(seed=97), 1000),
+             ("fibre pile with end-to-end springs", _linked_pile(seed=98), 1000),
              ("crossing collision with friction", OC._crossing(gap=2e-4, vel_b=[0.03, 0.0, -0.05], mu=0.5, c=2.0), 2000))
     for name, inp, steps in cases:
         print(f"case: {name}, FP32, {steps} steps", flush=True)
