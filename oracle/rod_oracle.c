@@ -81,6 +81,30 @@
  *     their diameters can pass between nodes.)
  * Rods joined by connections or in contact are advanced together (one batch
  * step), the coupling forces from the state of all rods at the kick time.
+ *
+ * FP32 mirror.  The same source compiled with -DORC_F32 (and
+ * -fsingle-precision-constant, so that literals do not lift expressions to
+ * FP64) carries out every operation of the rod step above in IEEE single
+ * precision: the reference for what FP32 arithmetic of this method gives,
+ * against which an FP32 implementation's discrepancy from the FP64 oracle is
+ * judged.  Its inputs (material constants, rest lengths and curvatures, loads,
+ * magnetization, muscle amplitudes, initial directors) are FP32 arrays, i.e.
+ * rounded once from FP64.  What stays FP64 in the mirror:
+ *   - time and the phases of the time-dependent loads (sin(2 pi f t + phi)
+ *     evaluated in FP64, then rounded);
+ *   - positions: a rod's nodes are held as an FP64 origin (its first node at
+ *     creation) plus, in FP32, the first node relative to it (the anchor) and
+ *     the element edge vectors r_{i+1} - r_i.  The half drift
+ *     r_j += h/2 v_j becomes anchor += h/2 v_0, edge_i += h/2 (v_{i+1} - v_i),
+ *     the same update in exact arithmetic; FP32 absolute positions would
+ *     round every drift increment against the rod's whole extent, which is
+ *     not a property of the method;
+ *   - the node-interaction laws (walls, connections, rod-rod contact), which
+ *     are evaluated in FP64 on node positions summed from the FP32 state,
+ *     their forces rounded to FP32.
+ * In the FP32 build the position array of a rod holds the anchor in row 0 and
+ * edge i in row i + 1, and a clamped far end is imposed by setting the last
+ * edge so that node n sits at its initial position.
  */
 #include <math.h>
 #include <stdint.h>
@@ -90,34 +114,53 @@
 #include <omp.h>
 #endif
 
+#ifdef ORC_F32
+typedef float real;
+#define SQRT sqrtf
+#define SIN sinf
+#define COS cosf
+#define ATAN2 atan2f
+#define POW powf
+#else
+typedef double real;
+#define SQRT sqrt
+#define SIN sin
+#define COS cos
+#define ATAN2 atan2
+#define POW pow
+#endif
+/* 2 pi in FP64 in both builds (a literal would be single precision in the
+ * FP32 build) */
+#define ORC_TWO_PI (8.0 * atan(1.0))
+
 typedef struct {
     int32_t n_rods;
     const int32_t *n_elems;          /* [R] */
-    const double *density;           /* [R] rho */
-    const double *youngs;            /* [R] E */
-    const double *shear_modulus;     /* [R] G */
-    const double *radius;            /* [R] */
-    const double *shear_coeff;       /* [R] alpha_c */
-    const double *damping;           /* [R] gamma, 1/s */
+    const real *density;             /* [R] rho */
+    const real *youngs;              /* [R] E */
+    const real *shear_modulus;       /* [R] G */
+    const real *radius;              /* [R] */
+    const real *shear_coeff;         /* [R] alpha_c */
+    const real *damping;             /* [R] gamma, 1/s */
     const int32_t *bc_start;         /* [R] 1: clamped at s = 0 */
     const int32_t *bc_end;           /* [R] 1: clamped at s = L */
-    const double *rest_length;       /* [N_e] */
-    const double *rest_kappa;        /* [N_v][3] or NULL */
-    const double *node_force;        /* [N_n][3] or NULL: constant external nodal force */
-    const double *couple_amp;        /* [N_e][3] or NULL: couple per unit length, material frame */
+    const real *rest_length;         /* [N_e] */
+    const real *rest_kappa;          /* [N_v][3] or NULL */
+    const real *node_force;          /* [N_n][3] or NULL: constant external nodal force */
+    const real *couple_amp;          /* [N_e][3] or NULL: couple per unit length, material frame */
     const double *couple_freq;       /* [R] Hz (used with couple_amp) */
     const double *couple_phase;      /* [R] rad */
     const double *pos0;              /* [N_n][3] initial positions (constraints, work of f) */
-    const double *dir0;              /* [N_e][9] initial directors (constraints) */
+    const real *dir0;                /* [N_e][9] initial directors (constraints) */
     double dt;
     double t0;                       /* time at step 0 */
     int32_t drop_term;               /* 0 in normal use; k > 0 removes term k (mutation tests) */
-    const double *magnetization;     /* [N_e][3] or NULL: magnetization per unit length, material frame */
+    const real *magnetization;       /* [N_e][3] or NULL: magnetization per unit length, material frame */
     double field[9];                 /* b(t) = field[0:3] + field[3:6] cos(2 pi f t) + field[6:9] sin(2 pi f t) */
     double field_freq;               /* f, Hz */
     double gravity[3];               /* g, m/s^2: nodal force m_j g */
-    const double *muscle_amp;        /* [N_v] or NULL: active moment amplitude beta_k */
-    const double *muscle_axis;       /* [R][3] material-frame axis */
+    const real *muscle_amp;          /* [N_v] or NULL: active moment amplitude beta_k */
+    const real *muscle_axis;         /* [R][3] material-frame axis */
     const double *muscle_freq;       /* [R] Hz */
     const double *muscle_wavenumber; /* [R] rad/m */
     const double *muscle_phase;      /* [R] rad */
@@ -130,38 +173,45 @@ typedef struct {
     const double *wall;              /* [n_walls][4]: unit normal nx ny nz, offset d (the wall is n.x = d) */
     double wall_k, wall_c, wall_mu, wall_vslip;   /* contact stiffness, damping, friction, slip speed */
     int32_t rod_contact;             /* 1: contact between nodes of different rods (same law) */
+    const double *origin;            /* FP32 build: [R][3] rod origins (first node at creation); else unused */
 } orc_rods;
 
 /* ---------------------------------------------------------------- vectors */
 
-static void cross3(const double *a, const double *b, double *c)
+static void cross3(const real *a, const real *b, real *c)
 {
     c[0] = a[1] * b[2] - a[2] * b[1];
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-static double dot3(const double *a, const double *b)
+static real dot3(const real *a, const real *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* FP64 dot product (node-interaction laws) */
+static double dot3d(const double *a, const double *b)
 {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
 /* y = Q x, Q row-major 3x3 */
-static void matvec(const double *Q, const double *x, double *y)
+static void matvec(const real *Q, const real *x, real *y)
 {
     for (int a = 0; a < 3; ++a)
         y[a] = Q[3 * a + 0] * x[0] + Q[3 * a + 1] * x[1] + Q[3 * a + 2] * x[2];
 }
 
 /* y = Q^T x */
-static void matTvec(const double *Q, const double *x, double *y)
+static void matTvec(const real *Q, const real *x, real *y)
 {
     for (int b = 0; b < 3; ++b)
         y[b] = Q[0 + b] * x[0] + Q[3 + b] * x[1] + Q[6 + b] * x[2];
 }
 
 /* C = A B^T */
-static void mat_abt(const double *A, const double *B, double *C)
+static void mat_abt(const real *A, const real *B, real *C)
 {
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
@@ -170,7 +220,7 @@ static void mat_abt(const double *A, const double *B, double *C)
 }
 
 /* C = A B */
-static void mat_ab(const double *A, const double *B, double *C)
+static void mat_ab(const real *A, const real *B, real *C)
 {
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
@@ -180,19 +230,19 @@ static void mat_ab(const double *A, const double *B, double *C)
 
 /* Rotation exp([u]x) by the Rodrigues formula:
  * I + sin(th) [k]x + (1 - cos(th)) [k]x^2 with th = |u|, k = u/th; exp(0) = I. */
-static void rodrigues(const double *u, double *E)
+static void rodrigues(const real *u, real *E)
 {
-    double th = sqrt(dot3(u, u));
+    real th = SQRT(dot3(u, u));
     for (int i = 0; i < 9; ++i) E[i] = 0.0;
     E[0] = E[4] = E[8] = 1.0;
     if (th == 0.0) return;
-    double k[3] = {u[0] / th, u[1] / th, u[2] / th};
-    double K[9] = {0.0, -k[2], k[1],
-                   k[2], 0.0, -k[0],
-                   -k[1], k[0], 0.0};
-    double K2[9];
+    real k[3] = {u[0] / th, u[1] / th, u[2] / th};
+    real K[9] = {0.0, -k[2], k[1],
+                 k[2], 0.0, -k[0],
+                 -k[1], k[0], 0.0};
+    real K2[9];
     mat_ab(K, K, K2);
-    double s = sin(th), c1 = 1.0 - cos(th);
+    real s = SIN(th), c1 = 1.0 - COS(th);
     for (int i = 0; i < 9; ++i) E[i] += s * K[i] + c1 * K2[i];
 }
 
@@ -200,16 +250,16 @@ static void rodrigues(const double *u, double *E)
  * w = ax(R) = (R32 - R23, R13 - R31, R21 - R12)/2 = sin(th) k,
  * c = (tr R - 1)/2 = cos(th), th = atan2(|w|, c), u = (th/|w|) w.
  * For |w| -> 0 the ratio th/|w| tends to 1 + |w|^2/6. */
-static void logmap(const double *R, double *u)
+static void logmap(const real *R, real *u)
 {
-    double w[3] = {0.5 * (R[7] - R[5]), 0.5 * (R[2] - R[6]), 0.5 * (R[3] - R[1])};
-    double sw = sqrt(dot3(w, w));
-    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
-    double f;
+    real w[3] = {0.5 * (R[7] - R[5]), 0.5 * (R[2] - R[6]), 0.5 * (R[3] - R[1])};
+    real sw = SQRT(dot3(w, w));
+    real c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    real f;
     if (sw < 1e-7 && c > 0.0)
         f = 1.0 + sw * sw / 6.0;   /* next term 3|w|^4/40 is below FP64 resolution */
     else
-        f = atan2(sw, c) / sw;     /* a half-turn (w = 0, c = -1) has no unique axis */
+        f = ATAN2(sw, c) / sw;     /* a half-turn (w = 0, c = -1) has no unique axis */
     u[0] = f * w[0];
     u[1] = f * w[1];
     u[2] = f * w[2];
@@ -219,15 +269,17 @@ static void logmap(const double *R, double *u)
 
 typedef struct {
     int n;                       /* elements */
-    double rho, E, G, rad, alpha_c, gamma, freq, phase;
+    real rho, E, G, rad, alpha_c, gamma;
+    double freq, phase;
     int clamp0, clamp1;
-    const double *lh;            /* [n] rest lengths */
-    const double *k0;            /* [n-1][3] or NULL */
-    const double *fext;          /* [n+1][3] or NULL */
-    const double *camp;          /* [n][3] or NULL */
+    const real *lh;              /* [n] rest lengths */
+    const real *k0;              /* [n-1][3] or NULL */
+    const real *fext;            /* [n+1][3] or NULL */
+    const real *camp;            /* [n][3] or NULL */
     const double *r0;            /* [n+1][3] */
-    const double *Q0;            /* [n][9] */
-    const double *mag;           /* [n][3] or NULL */
+    const double *org;           /* FP32 build: [3] the rod's origin */
+    const real *Q0;              /* [n][9] */
+    const real *mag;             /* [n][3] or NULL */
     const double *field;         /* [9] */
     double field_freq;
     const double *grav;          /* [3] */
@@ -235,8 +287,8 @@ typedef struct {
     int32_t n_walls;
     const double *wall;
     double wall_k, wall_c, wall_mu, wall_vslip;
-    const double *mamp;          /* [n-1] or NULL */
-    const double *maxis;         /* [3] */
+    const real *mamp;            /* [n-1] or NULL */
+    const real *maxis;           /* [3] */
     double mfreq, mwave, mphase;
     int drop;
 } rod_view;
@@ -259,6 +311,7 @@ static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int6
     v->fext = p->node_force ? p->node_force + 3 * no : NULL;
     v->camp = p->couple_amp ? p->couple_amp + 3 * eo : NULL;
     v->r0 = p->pos0 + 3 * no;
+    v->org = p->origin ? p->origin + 3 * r : NULL;
     v->Q0 = p->dir0 + 9 * eo;
     v->mag = p->magnetization ? p->magnetization + 3 * eo : NULL;
     v->field = p->field;
@@ -281,15 +334,15 @@ static void rod_view_make(const orc_rods *p, int r, int64_t eo, int64_t no, int6
 
 /* Section and constitutive constants of one rod. */
 typedef struct {
-    double A, I1, I2, I3;        /* area, second moments */
-    double S[3];                 /* shear/stretch stiffness diag */
-    double B[3];                 /* bend/twist stiffness diag */
+    real A, I1, I2, I3;          /* area, second moments */
+    real S[3];                   /* shear/stretch stiffness diag */
+    real B[3];                   /* bend/twist stiffness diag */
 } rod_consts;
 
 static void rod_consts_make(const rod_view *v, rod_consts *c)
 {
     c->A = M_PI * v->rad * v->rad;
-    c->I1 = M_PI * pow(v->rad, 4) / 4.0;
+    c->I1 = M_PI * POW(v->rad, 4) / 4.0;
     c->I2 = c->I1;
     c->I3 = c->I1 + c->I2;
     c->S[0] = v->alpha_c * v->G * c->A;
@@ -302,23 +355,23 @@ static void rod_consts_make(const rod_view *v, rod_consts *c)
 
 /* Workspace for one rod of up to nmax elements. */
 typedef struct {
-    double *l, *e, *t, *edot, *sig, *Ssig, *nint, *kap, *M, *y, *eps;
+    real *l, *e, *t, *edot, *sig, *Ssig, *nint, *kap, *M, *y, *eps;
 } rod_work;
 
 static int work_alloc(rod_work *w, int nmax)
 {
     size_t ne = (size_t)nmax;
-    w->l = malloc(ne * sizeof(double));
-    w->e = malloc(ne * sizeof(double));
-    w->t = malloc(3 * ne * sizeof(double));
-    w->edot = malloc(ne * sizeof(double));
-    w->sig = malloc(3 * ne * sizeof(double));
-    w->Ssig = malloc(3 * ne * sizeof(double));
-    w->nint = malloc(3 * ne * sizeof(double));
-    w->kap = malloc(3 * ne * sizeof(double));
-    w->M = malloc(3 * ne * sizeof(double));
-    w->y = malloc(3 * ne * sizeof(double));
-    w->eps = malloc(ne * sizeof(double));
+    w->l = malloc(ne * sizeof(real));
+    w->e = malloc(ne * sizeof(real));
+    w->t = malloc(3 * ne * sizeof(real));
+    w->edot = malloc(ne * sizeof(real));
+    w->sig = malloc(3 * ne * sizeof(real));
+    w->Ssig = malloc(3 * ne * sizeof(real));
+    w->nint = malloc(3 * ne * sizeof(real));
+    w->kap = malloc(3 * ne * sizeof(real));
+    w->M = malloc(3 * ne * sizeof(real));
+    w->y = malloc(3 * ne * sizeof(real));
+    w->eps = malloc(ne * sizeof(real));
     return (w->l && w->e && w->t && w->edot && w->sig && w->Ssig && w->nint && w->kap && w->M
             && w->y && w->eps) ? 0 : -1;
 }
@@ -332,37 +385,41 @@ static void work_free(rod_work *w)
 /* Kinematics and strains of one rod at positions r, velocities v, directors Q:
  * l, e, t, edot per element; sigma, S sigma, internal force n per element;
  * eps, kappa per Voronoi point.  Returns nothing; fills w. */
-static void rod_kinematics(const rod_view *rv, const rod_consts *c, const double *r,
-                           const double *v, const double *Q, rod_work *w)
+static void rod_kinematics(const rod_view *rv, const rod_consts *c, const real *r,
+                           const real *v, const real *Q, rod_work *w)
 {
     const int n = rv->n;
     for (int i = 0; i < n; ++i) {
-        double dr[3], dv[3];
+        real dr[3], dv[3];
         for (int a = 0; a < 3; ++a) {
+#ifdef ORC_F32
+            dr[a] = r[3 * (i + 1) + a];   /* the edge itself */
+#else
             dr[a] = r[3 * (i + 1) + a] - r[3 * i + a];
+#endif
             dv[a] = v ? v[3 * (i + 1) + a] - v[3 * i + a] : 0.0;
         }
-        double l = sqrt(dot3(dr, dr));
+        real l = SQRT(dot3(dr, dr));
         w->l[i] = l;
         w->e[i] = l / rv->lh[i];
         for (int a = 0; a < 3; ++a) w->t[3 * i + a] = dr[a] / l;
         w->edot[i] = dot3(&w->t[3 * i], dv) / rv->lh[i];
         /* sigma = Q dr / lh - e3 */
-        double qdr[3];
+        real qdr[3];
         matvec(&Q[9 * i], dr, qdr);
         w->sig[3 * i + 0] = qdr[0] / rv->lh[i];
         w->sig[3 * i + 1] = qdr[1] / rv->lh[i];
         w->sig[3 * i + 2] = qdr[2] / rv->lh[i] - 1.0;
         for (int a = 0; a < 3; ++a) w->Ssig[3 * i + a] = c->S[a] * w->sig[3 * i + a];
         /* n = Q^T S sigma / e (lab frame) */
-        double qs[3];
+        real qs[3];
         matTvec(&Q[9 * i], &w->Ssig[3 * i], qs);
         for (int a = 0; a < 3; ++a) w->nint[3 * i + a] = qs[a] / w->e[i];
     }
     for (int k = 0; k + 1 < n; ++k) {
-        double Dh = 0.5 * (rv->lh[k] + rv->lh[k + 1]);
+        real Dh = 0.5 * (rv->lh[k] + rv->lh[k + 1]);
         w->eps[k] = 0.5 * (w->l[k] + w->l[k + 1]) / Dh;
-        double R[9], u[3];
+        real R[9], u[3];
         mat_abt(&Q[9 * k], &Q[9 * (k + 1)], R);
         logmap(R, u);
         for (int a = 0; a < 3; ++a) w->kap[3 * k + a] = u[a] / Dh;
@@ -382,14 +439,14 @@ static double wall_force(const rod_view *rv, const double *x, const double *v, d
     double pot = 0.0;
     for (int w = 0; w < rv->n_walls; ++w) {
         const double *nw = &rv->wall[4 * w];
-        const double delta = rv->rad - (dot3(nw, x) - nw[3]);
+        const double delta = rv->rad - (dot3d(nw, x) - nw[3]);
         if (!(delta > 0.0)) continue;
         pot += 0.5 * rv->wall_k * delta * delta;
-        const double vn = dot3(nw, v);
+        const double vn = dot3d(nw, v);
         const double fn = delta * (rv->wall_k - rv->wall_c * vn);
         if (!(fn > 0.0)) continue;
         double vt[3] = {v[0] - vn * nw[0], v[1] - vn * nw[1], v[2] - vn * nw[2]};
-        const double speed = sqrt(dot3(vt, vt));
+        const double speed = sqrt(dot3d(vt, vt));
         const double g = rv->wall_mu * fn / (speed > rv->wall_vslip ? speed : rv->wall_vslip);
         for (int a = 0; a < 3; ++a) f[a] += fn * nw[a] - g * vt[a];
     }
@@ -398,21 +455,21 @@ static double wall_force(const rod_view *rv, const double *x, const double *v, d
 
 /* Linear accelerations a[n+1][3] and angular accelerations alpha[n][3] of one
  * rod (Eq. 1a and 1b) at state (r, v, Q, om) and time t. */
-static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, const double *v,
-                      const double *Q, const double *om, double t, rod_work *w,
-                      double *acc, double *alpha)
+static void rod_accel(const rod_view *rv, const rod_consts *c, const real *r, const real *v,
+                      const real *Q, const real *om, double t, rod_work *w,
+                      real *acc, real *alpha)
 {
     const int n = rv->n;
     rod_kinematics(rv, c, r, v, Q, w);
 
     /* bending/twisting moments at Voronoi points */
     for (int k = 0; k + 1 < n; ++k) {
-        double Dh = 0.5 * (rv->lh[k] + rv->lh[k + 1]);
-        double Bv[3];
+        real Dh = 0.5 * (rv->lh[k] + rv->lh[k + 1]);
+        real Bv[3];
         for (int a = 0; a < 3; ++a)
             Bv[a] = (c->B[a] * rv->lh[k] + c->B[a] * rv->lh[k + 1]) / (rv->lh[k] + rv->lh[k + 1]);
-        double e3 = w->eps[k] * w->eps[k] * w->eps[k];
-        double dk[3];
+        real e3 = w->eps[k] * w->eps[k] * w->eps[k];
+        real dk[3];
         for (int a = 0; a < 3; ++a)
             dk[a] = w->kap[3 * k + a] - (rv->k0 ? rv->k0[3 * k + a] : 0.0);
         for (int a = 0; a < 3; ++a) w->M[3 * k + a] = Bv[a] * dk[a] / e3;
@@ -421,48 +478,62 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
         if (rv->mamp) {
             double sk = 0.0;
             for (int i = 0; i <= k; ++i) sk += rv->lh[i];
-            const double act = rv->mamp[k] * sin(2.0 * M_PI * rv->mfreq * t - rv->mwave * sk + rv->mphase);
+            const real act = rv->mamp[k] * (real)sin(ORC_TWO_PI * rv->mfreq * t - rv->mwave * sk + rv->mphase);
             for (int a = 0; a < 3; ++a) w->M[3 * k + a] += act * rv->maxis[a];
         }
-        double kxM[3];
+        real kxM[3];
         cross3(&w->kap[3 * k], &w->M[3 * k], kxM);
         for (int a = 0; a < 3; ++a) w->y[3 * k + a] = kxM[a] * Dh;
     }
 
     /* nodes: Eq. 1a with the difference operator */
+#ifdef ORC_F32
+    /* node positions in FP64 for the wall law: origin + anchor + edges */
+    double xn[3] = {rv->org[0] + r[0], rv->org[1] + r[1], rv->org[2] + r[2]};
+#endif
     for (int j = 0; j <= n; ++j) {
-        double mass = 0.0;
+        real mass = 0.0;
         if (j > 0) mass += 0.5 * rv->rho * c->A * rv->lh[j - 1];
         if (j < n) mass += 0.5 * rv->rho * c->A * rv->lh[j];
         double fw[3] = {0.0, 0.0, 0.0};
+#ifdef ORC_F32
+        if (rv->n_walls) {
+            const double vd[3] = {v[3 * j], v[3 * j + 1], v[3 * j + 2]};
+            wall_force(rv, xn, vd, fw);
+        }
+        if (j < n)
+            for (int a = 0; a < 3; ++a) xn[a] += r[3 * (j + 1) + a];
+#else
         if (rv->n_walls) wall_force(rv, &r[3 * j], &v[3 * j], fw);
+#endif
         for (int a = 0; a < 3; ++a) {
-            double F = 0.0;
+            real F = 0.0;
             if (j < n) F += w->nint[3 * j + a];
             if (j > 0) F -= w->nint[3 * (j - 1) + a];
             if (rv->fext) F += rv->fext[3 * j + a];
-            if (rv->fconn) F += rv->fconn[3 * j + a];
-            F += fw[a];
-            F += mass * rv->grav[a];
+            if (rv->fconn) F += (real)rv->fconn[3 * j + a];
+            F += (real)fw[a];
+            F += mass * (real)rv->grav[a];
             acc[3 * j + a] = F / mass - rv->gamma * v[3 * j + a];
         }
     }
 
     /* elements: Eq. 1b */
-    double s_t = 0.0;
-    if (rv->camp) s_t = sin(2.0 * M_PI * rv->freq * t + rv->phase);
+    real s_t = 0.0;
+    if (rv->camp) s_t = (real)sin(ORC_TWO_PI * rv->freq * t + rv->phase);
     /* homogeneous lab field at time t (Methods, "Magnetized filaments") */
-    double bfield[3] = {0.0, 0.0, 0.0};
+    real bfield[3] = {0.0, 0.0, 0.0};
     if (rv->mag) {
-        const double cb = cos(2.0 * M_PI * rv->field_freq * t), sb = sin(2.0 * M_PI * rv->field_freq * t);
-        for (int a = 0; a < 3; ++a) bfield[a] = rv->field[a] + rv->field[3 + a] * cb + rv->field[6 + a] * sb;
+        const double cb = cos(ORC_TWO_PI * rv->field_freq * t), sb = sin(ORC_TWO_PI * rv->field_freq * t);
+        for (int a = 0; a < 3; ++a)
+            bfield[a] = (real)(rv->field[a] + rv->field[3 + a] * cb + rv->field[6 + a] * sb);
     }
     for (int i = 0; i < n; ++i) {
-        const double *Qi = &Q[9 * i];
-        const double *wi = &om[3 * i];
-        double lh = rv->lh[i], e = w->e[i];
-        double J[3] = {rv->rho * c->I1 * lh, rv->rho * c->I2 * lh, rv->rho * c->I3 * lh};
-        double tau[3] = {0.0, 0.0, 0.0};
+        const real *Qi = &Q[9 * i];
+        const real *wi = &om[3 * i];
+        real lh = rv->lh[i], e = w->e[i];
+        real J[3] = {rv->rho * c->I1 * lh, rv->rho * c->I2 * lh, rv->rho * c->I3 * lh};
+        real tau[3] = {0.0, 0.0, 0.0};
         /* d/ds(B kappa / e^3): difference of Voronoi moments */
         if (rv->drop != 1)
             for (int a = 0; a < 3; ++a) {
@@ -472,22 +543,22 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
         /* kappa x B kappa / e^3: average of the two adjacent Voronoi terms */
         if (rv->drop != 2)
             for (int a = 0; a < 3; ++a) {
-                double ysum = 0.0;
+                real ysum = 0.0;
                 if (i > 0) ysum += w->y[3 * (i - 1) + a];
                 if (i < n - 1) ysum += w->y[3 * i + a];
                 tau[a] += 0.5 * ysum;
             }
         /* Q t x S sigma, per element (times the rest length) */
         if (rv->drop != 3) {
-            double qt[3], sh[3];
+            real qt[3], sh[3];
             matvec(Qi, &w->t[3 * i], qt);
             cross3(qt, &w->Ssig[3 * i], sh);
             for (int a = 0; a < 3; ++a) tau[a] += sh[a] * lh;
         }
         /* (rho I omega / e) x omega */
-        double Jw_e[3] = {J[0] * wi[0] / e, J[1] * wi[1] / e, J[2] * wi[2] / e};
+        real Jw_e[3] = {J[0] * wi[0] / e, J[1] * wi[1] / e, J[2] * wi[2] / e};
         if (rv->drop != 4) {
-            double lt[3];
+            real lt[3];
             cross3(Jw_e, wi, lt);
             for (int a = 0; a < 3; ++a) tau[a] += lt[a];
         }
@@ -499,7 +570,7 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
             for (int a = 0; a < 3; ++a) tau[a] += rv->camp[3 * i + a] * s_t * lh;
         /* magnetic couple per unit length, m x (Q b(t)), in the material frame */
         if (rv->mag) {
-            double qb[3], cm[3];
+            real qb[3], cm[3];
             matvec(Qi, bfield, qb);
             cross3(&rv->mag[3 * i], qb, cm);
             for (int a = 0; a < 3; ++a) tau[a] += cm[a] * lh;
@@ -509,16 +580,30 @@ static void rod_accel(const rod_view *rv, const rod_consts *c, const double *r, 
     }
 }
 
-static void rod_constraints(const rod_view *rv, double *r, double *v, double *Q, double *om)
+static void rod_constraints(const rod_view *rv, real *r, real *v, real *Q, real *om)
 {
     const int n = rv->n;
     if (rv->clamp0) {
+#ifdef ORC_F32
+        /* the anchor: node 0 relative to the origin */
+        for (int a = 0; a < 3; ++a) { r[a] = (real)(rv->r0[a] - rv->org[a]); v[a] = 0.0; om[a] = 0.0; }
+#else
         for (int a = 0; a < 3; ++a) { r[a] = rv->r0[a]; v[a] = 0.0; om[a] = 0.0; }
+#endif
         for (int a = 0; a < 9; ++a) Q[a] = rv->Q0[a];
     }
     if (rv->clamp1) {
+#ifdef ORC_F32
+        /* the last edge puts node n at its initial position */
+        double x[3] = {rv->org[0] + r[0], rv->org[1] + r[1], rv->org[2] + r[2]};
+        for (int i = 0; i + 1 < n; ++i)
+            for (int a = 0; a < 3; ++a) x[a] += r[3 * (i + 1) + a];
+        for (int a = 0; a < 3; ++a) r[3 * n + a] = (real)(rv->r0[3 * n + a] - x[a]);
+#endif
         for (int a = 0; a < 3; ++a) {
+#ifndef ORC_F32
             r[3 * n + a] = rv->r0[3 * n + a];
+#endif
             v[3 * n + a] = 0.0;
             om[3 * (n - 1) + a] = 0.0;
         }
@@ -526,30 +611,38 @@ static void rod_constraints(const rod_view *rv, double *r, double *v, double *Q,
     }
 }
 
-static void rod_half_drift(const rod_view *rv, double h, double *r, const double *v, double *Q,
-                           const double *om)
+static void rod_half_drift(const rod_view *rv, real h, real *r, const real *v, real *Q,
+                           const real *om)
 {
     const int n = rv->n;
+#ifdef ORC_F32
+    /* edge form: anchor += h/2 v_0, edge i += h/2 (v_{i+1} - v_i) */
+    for (int a = 0; a < 3; ++a) r[a] += 0.5 * h * v[a];
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) r[3 * (i + 1) + a] += 0.5 * h * (v[3 * (i + 1) + a] - v[3 * i + a]);
+#else
     for (int j = 0; j <= n; ++j)
         for (int a = 0; a < 3; ++a) r[3 * j + a] += 0.5 * h * v[3 * j + a];
+#endif
     for (int i = 0; i < n; ++i) {
-        double u[3] = {-0.5 * h * om[3 * i + 0], -0.5 * h * om[3 * i + 1], -0.5 * h * om[3 * i + 2]};
-        double E[9], Qn[9];
+        real u[3] = {-0.5 * h * om[3 * i + 0], -0.5 * h * om[3 * i + 1], -0.5 * h * om[3 * i + 2]};
+        real E[9], Qn[9];
         rodrigues(u, E);
         mat_ab(E, &Q[9 * i], Qn);
         memcpy(&Q[9 * i], Qn, sizeof Qn);
     }
 }
 
-static void rod_steps(const rod_view *rv, double h, double t0, int64_t step0, int64_t nsteps,
-                      double *r, double *v, double *Q, double *om, rod_work *w, double *acc,
-                      double *alpha)
+static void rod_steps(const rod_view *rv, double dt, double t0, int64_t step0, int64_t nsteps,
+                      real *r, real *v, real *Q, real *om, rod_work *w, real *acc,
+                      real *alpha)
 {
     rod_consts c;
     rod_consts_make(rv, &c);
     const int n = rv->n;
+    const real h = (real)dt;
     for (int64_t s = 0; s < nsteps; ++s) {
-        double t_mid = t0 + ((double)(step0 + s) + 0.5) * h;
+        double t_mid = t0 + ((double)(step0 + s) + 0.5) * dt;
         rod_half_drift(rv, h, r, v, Q, om);
         rod_constraints(rv, r, v, Q, om);
         rod_accel(rv, &c, r, v, Q, om, t_mid, w, acc, alpha);
@@ -595,10 +688,10 @@ static void conn_forces(const orc_rods *p, const double *pos, const double *vel,
             d[k] = pos[3 * b + k] - pos[3 * a + k];
             dv[k] = vel[3 * b + k] - vel[3 * a + k];
         }
-        const double l = sqrt(dot3(d, d));
+        const double l = sqrt(dot3d(d, d));
         if (!(l > 0.0)) continue;   /* coincident nodes: no direction, no force */
         double e[3] = {d[0] / l, d[1] / l, d[2] / l};
-        const double mag = p->conn_k[c] * (l - p->conn_rest[c]) + p->conn_c[c] * dot3(e, dv);
+        const double mag = p->conn_k[c] * (l - p->conn_rest[c]) + p->conn_c[c] * dot3d(e, dv);
         for (int k = 0; k < 3; ++k) {
             fc[3 * a + k] += mag * e[k];
             fc[3 * b + k] -= mag * e[k];
@@ -614,16 +707,16 @@ static double sphere_force(const orc_rods *p, const double *xa, const double *va
                            const double *vb, double rb, double *f)
 {
     const double d[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
-    const double dist = sqrt(dot3(d, d));
+    const double dist = sqrt(dot3d(d, d));
     const double delta = ra + rb - dist;
     if (!(delta > 0.0) || !(dist > 0.0)) return delta;   /* coincident centres: no direction */
     const double n[3] = {d[0] / dist, d[1] / dist, d[2] / dist};
     const double vr[3] = {va[0] - vb[0], va[1] - vb[1], va[2] - vb[2]};
-    const double vn = dot3(n, vr);
+    const double vn = dot3d(n, vr);
     const double fn = delta * (p->wall_k - p->wall_c * vn);
     if (!(fn > 0.0)) return delta;
     const double vt[3] = {vr[0] - vn * n[0], vr[1] - vn * n[1], vr[2] - vn * n[2]};
-    const double speed = sqrt(dot3(vt, vt));
+    const double speed = sqrt(dot3d(vt, vt));
     const double g = p->wall_mu * fn / (speed > p->wall_vslip ? speed : p->wall_vslip);
     for (int k = 0; k < 3; ++k) f[k] += fn * n[k] - g * vt[k];
     return delta;
@@ -657,7 +750,7 @@ static void contact_forces(const orc_rods *p, const double *pos, const double *v
 
 /* All rods together, one step at a time (rods joined by connections or in
  * contact). */
-static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double *dir, double *omega,
+static int orc_step_coupled(const orc_rods *p, real *pos, real *vel, real *dir, real *omega,
                             int64_t step0, int64_t n_steps, const int64_t *eo, const int64_t *no,
                             const int64_t *vo)
 {
@@ -665,23 +758,50 @@ static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double 
     const int64_t Nn = no[R - 1] + p->n_elems[R - 1] + 1;
     const int nmax = max_elems(p);
     double *fc = malloc(3 * (size_t)Nn * sizeof(double));
-    double *acc = malloc(3 * (size_t)(nmax + 1) * sizeof(double));
-    double *alpha = malloc(3 * (size_t)nmax * sizeof(double));
+    real *acc = malloc(3 * (size_t)(nmax + 1) * sizeof(real));
+    real *alpha = malloc(3 * (size_t)nmax * sizeof(real));
+#ifdef ORC_F32
+    /* node positions (origin + anchor + edges) and velocities in FP64 for the
+     * interaction laws */
+    double *xabs = malloc(3 * (size_t)Nn * sizeof(double));
+    double *vabs = malloc(3 * (size_t)Nn * sizeof(double));
+    rod_work w;
+    int fail = (!fc || !acc || !alpha || !xabs || !vabs || work_alloc(&w, nmax) != 0);
+#else
     rod_work w;
     int fail = (!fc || !acc || !alpha || work_alloc(&w, nmax) != 0);
+#endif
     if (!fail) {
-        const double h = p->dt;
+        const double dt = p->dt;
+        const real h = (real)dt;
         for (int64_t s = 0; s < n_steps; ++s) {
-            const double t_mid = p->t0 + ((double)(step0 + s) + 0.5) * h;
+            const double t_mid = p->t0 + ((double)(step0 + s) + 0.5) * dt;
             for (int r = 0; r < R; ++r) {
                 rod_view rv;
                 rod_view_make(p, r, eo[r], no[r], vo[r], &rv);
-                double *x = pos + 3 * no[r], *v = vel + 3 * no[r], *Q = dir + 9 * eo[r], *om = omega + 3 * eo[r];
+                real *x = pos + 3 * no[r], *v = vel + 3 * no[r], *Q = dir + 9 * eo[r], *om = omega + 3 * eo[r];
                 rod_half_drift(&rv, h, x, v, Q, om);
                 rod_constraints(&rv, x, v, Q, om);
             }
+#ifdef ORC_F32
+            for (int r = 0; r < R; ++r) {
+                const real *x = pos + 3 * no[r];
+                double acc_x[3] = {p->origin[3 * r] + x[0], p->origin[3 * r + 1] + x[1], p->origin[3 * r + 2] + x[2]};
+                for (int j = 0; j <= p->n_elems[r]; ++j) {
+                    if (j > 0)
+                        for (int a = 0; a < 3; ++a) acc_x[a] += x[3 * j + a];
+                    for (int a = 0; a < 3; ++a) {
+                        xabs[3 * (no[r] + j) + a] = acc_x[a];
+                        vabs[3 * (no[r] + j) + a] = vel[3 * (no[r] + j) + a];
+                    }
+                }
+            }
+            conn_forces(p, xabs, vabs, fc, Nn);
+            if (p->rod_contact) contact_forces(p, xabs, vabs, fc, no, NULL);
+#else
             conn_forces(p, pos, vel, fc, Nn);
             if (p->rod_contact) contact_forces(p, pos, vel, fc, no, NULL);
+#endif
             for (int r = 0; r < R; ++r) {
                 rod_view rv;
                 rod_consts c;
@@ -689,7 +809,7 @@ static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double 
                 rod_consts_make(&rv, &c);
                 rv.fconn = fc + 3 * no[r];
                 const int n = rv.n;
-                double *x = pos + 3 * no[r], *v = vel + 3 * no[r], *Q = dir + 9 * eo[r], *om = omega + 3 * eo[r];
+                real *x = pos + 3 * no[r], *v = vel + 3 * no[r], *Q = dir + 9 * eo[r], *om = omega + 3 * eo[r];
                 rod_accel(&rv, &c, x, v, Q, om, t_mid, &w, acc, alpha);
                 for (int j = 0; j <= n; ++j)
                     for (int a = 0; a < 3; ++a) v[3 * j + a] += h * acc[3 * j + a];
@@ -701,7 +821,13 @@ static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double 
             }
         }
     }
-    if (fc && acc && alpha) work_free(&w);
+#ifdef ORC_F32
+    if (fc && acc && alpha && xabs && vabs) work_free(&w);   /* work_alloc ran */
+    free(xabs);
+    free(vabs);
+#else
+    if (fc && acc && alpha) work_free(&w);   /* work_alloc ran */
+#endif
     free(fc);
     free(acc);
     free(alpha);
@@ -711,10 +837,11 @@ static int orc_step_coupled(const orc_rods *p, double *pos, double *vel, double 
 /* Advance every rod by n_steps position-Verlet steps, starting at step index
  * step0 (time t0 + step0*dt).  pos/vel [N_n][3], dir [N_e][9], omega [N_e][3]
  * are updated in place.  n_threads <= 0 uses the OpenMP default. */
-int orc_step(const orc_rods *p, double *pos, double *vel, double *dir, double *omega,
+int orc_step(const orc_rods *p, real *pos, real *vel, real *dir, real *omega,
              int64_t step0, int64_t n_steps, int n_threads)
 {
     const int R = p->n_rods;
+    if (R <= 0) return 0;
     int64_t *eo = malloc(3 * (size_t)R * sizeof(int64_t));
     if (!eo) return -2;
     int64_t *no = eo + R, *vo = eo + 2 * R;
@@ -732,8 +859,8 @@ int orc_step(const orc_rods *p, double *pos, double *vel, double *dir, double *o
 #endif
     {
         rod_work w;
-        double *acc = malloc(3 * (size_t)(nmax + 1) * sizeof(double));
-        double *alpha = malloc(3 * (size_t)nmax * sizeof(double));
+        real *acc = malloc(3 * (size_t)(nmax + 1) * sizeof(real));
+        real *alpha = malloc(3 * (size_t)nmax * sizeof(real));
         if (work_alloc(&w, nmax) != 0 || !acc || !alpha) {
             fail = 1;
         } else {
@@ -755,6 +882,7 @@ int orc_step(const orc_rods *p, double *pos, double *vel, double *dir, double *o
     return fail ? -2 : 0;
 }
 
+#ifndef ORC_F32
 /* Strains at a state: sigma [N_e][3], kappa [N_v][3], dilatation e [N_e]. */
 int orc_strains(const orc_rods *p, const double *pos, const double *dir, double *sigma,
                 double *kappa, double *dil)
@@ -895,6 +1023,7 @@ int orc_energy(const orc_rods *p, const double *pos, const double *vel, const do
 /* The two rotation maps, exposed for direct checks. */
 void orc_rodrigues(const double *u, double *E) { rodrigues(u, E); }
 void orc_logmap(const double *R, double *u) { logmap(R, u); }
+#endif /* !ORC_F32: the FP32 build exports the step only */
 
 int orc_max_threads(void)
 {

@@ -1,4 +1,5 @@
-"""ctypes front end of the FP64 CPU oracle (``rod_oracle.c``).
+"""ctypes front end of the FP64 CPU oracle (``rod_oracle.c``) and of its FP32
+mirror (the same source built in single precision).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg use it; the GPU library never does.  It imports nothing from
@@ -18,42 +19,78 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rod_oracle.c")
 _LIB = os.path.join(_HERE, "librod_oracle.so")
+_LIB32 = os.path.join(_HERE, "librod_oracle32.so")
 
 _dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
 _ip = C.POINTER(C.c_int32)
 
 
-class _OrcRods(C.Structure):
-    _fields_ = [
+def _orc_fields(rp):
+    """Fields of the C struct orc_rods; `rp` is the pointer type of its `real`
+    arrays (double in the oracle, float in the FP32 mirror)."""
+    return [
         ("n_rods", C.c_int32),
         ("n_elems", _ip),
-        ("density", _dp), ("youngs", _dp), ("shear_modulus", _dp), ("radius", _dp),
-        ("shear_coeff", _dp), ("damping", _dp),
+        ("density", rp), ("youngs", rp), ("shear_modulus", rp), ("radius", rp),
+        ("shear_coeff", rp), ("damping", rp),
         ("bc_start", _ip), ("bc_end", _ip),
-        ("rest_length", _dp), ("rest_kappa", _dp), ("node_force", _dp), ("couple_amp", _dp),
-        ("couple_freq", _dp), ("couple_phase", _dp), ("pos0", _dp), ("dir0", _dp),
+        ("rest_length", rp), ("rest_kappa", rp), ("node_force", rp), ("couple_amp", rp),
+        ("couple_freq", _dp), ("couple_phase", _dp), ("pos0", _dp), ("dir0", rp),
         ("dt", C.c_double), ("t0", C.c_double), ("drop_term", C.c_int32),
-        ("magnetization", _dp), ("field", C.c_double * 9), ("field_freq", C.c_double),
-        ("gravity", C.c_double * 3), ("muscle_amp", _dp), ("muscle_axis", _dp), ("muscle_freq", _dp),
+        ("magnetization", rp), ("field", C.c_double * 9), ("field_freq", C.c_double),
+        ("gravity", C.c_double * 3), ("muscle_amp", rp), ("muscle_axis", rp), ("muscle_freq", _dp),
         ("muscle_wavenumber", _dp), ("muscle_phase", _dp),
         ("n_conn", C.c_int32), ("conn_node", _ip), ("conn_k", _dp), ("conn_c", _dp), ("conn_rest", _dp),
         ("n_walls", C.c_int32), ("wall", _dp), ("wall_k", C.c_double), ("wall_c", C.c_double),
         ("wall_mu", C.c_double), ("wall_vslip", C.c_double),
         ("rod_contact", C.c_int32),
+        ("origin", _dp),
     ]
 
 
+class _OrcRods(C.Structure):
+    _fields_ = _orc_fields(_dp)
+
+
+class _OrcRods32(C.Structure):
+    _fields_ = _orc_fields(_fp)
+
+
+# names of the orc_rods arrays of type `real` (FP32 in the mirror)
+_REAL_FIELDS = ("density", "youngs", "shear_modulus", "radius", "shear_coeff", "damping", "rest_length",
+                "rest_kappa", "node_force", "couple_amp", "dir0", "magnetization", "muscle_amp", "muscle_axis")
+
+_COMMON = ["-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-D_DEFAULT_SOURCE"]
+# the FP32 mirror: the same source in single precision (literals included)
+_F32_FLAGS = ["-DORC_F32", "-fsingle-precision-constant"]
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-D_DEFAULT_SOURCE", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle and its FP32 mirror with gcc (-O2, OpenMP, no
+    fast-math, no FMA contraction)."""
+    for out, extra in ((_LIB, []), (_LIB32, _F32_FLAGS)):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            cmd = ["gcc", *_COMMON, *extra, "-o", out + ".tmp", _SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
 _lib = None
+_lib32 = None
+
+
+def lib32():
+    """The FP32 mirror's library (orc_step on float state arrays)."""
+    global _lib32
+    if _lib32 is None:
+        build()
+        L = C.CDLL(_LIB32)
+        L.orc_step.argtypes = [C.POINTER(_OrcRods32), _fp, _fp, _fp, _fp, C.c_int64, C.c_int64, C.c_int]
+        L.orc_step.restype = C.c_int
+        _lib32 = L
+    return _lib32
 
 
 def lib():
@@ -259,3 +296,109 @@ def logmap(R):
 
 def max_threads():
     return int(lib().orc_max_threads())
+
+
+def _f(a):
+    """Round an FP64 array once to FP32 (round to nearest even)."""
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+class Oracle32:
+    """The FP32 mirror of the oracle: the same step carried out in single
+    precision (see the header of rod_oracle.c), with positions held as an FP64
+    origin per rod (its first node at creation) plus an FP32 anchor and FP32
+    edge vectors.  Inputs are rounded once from FP64.
+
+    ``state()`` returns FP64 arrays with node positions summed from origin,
+    anchor and edges in FP64.  ``energy()`` evaluates the FP64 oracle's
+    energies on that state with the rounded constants: the energies of the
+    mirror's own state and model.
+    """
+
+    def __init__(self, inp, t0=0.0):
+        o = Oracle(inp, t0=t0)
+        self._o64 = o
+        self.R = o.R
+        self.n_elems = o.n_elems
+        self.dt = o.dt
+        self.t0 = o.t0
+        self.step_index = 0
+        no = np.concatenate([[0], np.cumsum(o.n_elems + 1)[:-1]]).astype(np.int64)
+        self._no = no
+        self.origin = np.ascontiguousarray(o.pos0[no])
+        edges = np.diff(o.pos, axis=0)
+        # row 0 of each rod: the anchor (node 0 relative to the origin, 0 at
+        # creation); row j > 0: edge j - 1
+        x = np.empty_like(o.pos)
+        x[no] = 0.0
+        rest = np.ones(len(o.pos), bool)
+        rest[no] = False
+        x[rest] = edges[np.nonzero(rest)[0] - 1]
+        self.x = _f(x)
+        self.vel = _f(o.vel)
+        self.dir = _f(o.dir)
+        self.omega = _f(o.omega)
+        # the rounded constants, kept for the energies
+        self._round = {k: _f(getattr(o, a)) for k, a in (
+            ("rest_length", "rest_length"), ("rest_kappa", "rest_kappa"), ("node_force", "node_force"),
+            ("couple_amp", "elem_couple"), ("dir0", "dir0"), ("magnetization", "magnetization"))}
+        self._mat = {k: _f(v) for k, v in o.mat.items()}
+        self._muscle = None if o.muscle is None else [_f(o.muscle[0]), _f(o.muscle[1])]
+        s = _OrcRods32()
+        for name, _ in _OrcRods32._fields_:
+            if name in _REAL_FIELDS:
+                continue
+            setattr(s, name, getattr(o._s, name))
+        for k, v in self._mat.items():
+            setattr(s, k, _ptr(v, _fp))
+        for k, v in self._round.items():
+            setattr(s, k, _ptr(v, _fp))
+        if self._muscle is not None:
+            s.muscle_amp, s.muscle_axis = [_ptr(a, _fp) for a in self._muscle]
+        s.origin = _ptr(self.origin)
+        self._s = s
+
+    @property
+    def time(self):
+        return self.t0 + self.step_index * self.dt
+
+    def step(self, n_steps=1, n_threads=0):
+        rc = lib32().orc_step(C.byref(self._s), _ptr(self.x, _fp), _ptr(self.vel, _fp), _ptr(self.dir, _fp),
+                              _ptr(self.omega, _fp), self.step_index, int(n_steps), int(n_threads))
+        if rc != 0:
+            raise MemoryError("oracle step failed")
+        self.step_index += int(n_steps)
+
+    def positions(self):
+        """Node positions in FP64: origin + anchor + the edges before each node."""
+        x = self.x.astype(np.float64)
+        pos = np.empty_like(x)
+        for r, (a, n) in enumerate(zip(self._no, self.n_elems)):
+            pos[a:a + n + 1] = self.origin[r] + np.cumsum(x[a:a + n + 1], axis=0)
+        return pos
+
+    def state(self):
+        return (self.positions(), self.vel.astype(np.float64), self.dir.astype(np.float64),
+                self.omega.astype(np.float64))
+
+    def energy(self):
+        e = self._o64
+        saved = ({k: getattr(e, k) for k in ("rest_length", "rest_kappa", "node_force", "elem_couple")},
+                 dict(e.mat), e.muscle)
+        try:
+            e.rest_length = self._round["rest_length"].astype(np.float64)
+            for k, a in (("rest_kappa", "rest_kappa"), ("node_force", "node_force"), ("couple_amp", "elem_couple")):
+                r = self._round[k]
+                setattr(e, a, None if r is None else r.astype(np.float64))
+            e.mat = {k: v.astype(np.float64) for k, v in self._mat.items()}
+            e._mk()
+            out = np.empty((self.R, 5))
+            pos, vel, dr, om = self.state()
+            lib().orc_energy(C.byref(e._s), _ptr(np.ascontiguousarray(pos)), _ptr(np.ascontiguousarray(vel)),
+                             _ptr(np.ascontiguousarray(dr)), _ptr(np.ascontiguousarray(om)), _ptr(out))
+        finally:
+            for k, v in saved[0].items():
+                setattr(e, k, v)
+            e.mat = saved[1]
+            e._mk()
+        return out

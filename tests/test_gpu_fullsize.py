@@ -2,18 +2,19 @@
 times (autotuned tile width and substeps, one rod_step call per bench step):
 the GPU advances every rod, the FP64 oracle a seeded sample of them one by one.
 
-Bars: FP64 as in test_gpu_step (max(1e-10, 10 x the oracle's one-ulp
-sensitivity)); FP32 1e-4 in positions and directors after 1000 steps (the
-derivation in test_gpu_step.test_f32_parity) and, for the 20,000-step carpet,
-the same per-step round-off accumulated linearly: 20,000 x 6e-8 = 1.2e-3.
+Bars on all five norms, as in test_gpu_step: FP64 max(1e-10, 3 x the
+oracle's largest one-ulp divergence over three starts); FP32 max(2^-20, 4 x the
+discrepancy of the oracle's FP32 mirror over the same steps, 20,000 of them
+for the carpets).
 """
 import numpy as np
 import pytest
 
 from oracle import rodoracle as ro
 from paper_2605_13766_amd import workloads as W
-from parity import energy_norm, fp64_bars, oracle_pair, rod_norms
+from parity import check, energy_norm, fp32_bars, fp32_mirror, fp64_bars, oracle_pair, rod_norms
 import rodcases as RC
+from test_gpu_step import report
 
 pytestmark = pytest.mark.gpu
 
@@ -51,13 +52,12 @@ def test_ragged_4096_full_batch_sampled(precision):
     o, p = oracle_pair(sub, 1000)
     norms = rod_norms(sub, o.state(), got, 1000 * inp.dt)
     norms["energy"] = energy_norm(o.energy(), e_got)
-    print("norms", {k: f"{v:.2e}" for k, v in norms.items()}, flush=True)
     if precision == "f64":
-        bars, sens = fp64_bars(sub, o, p, 1000)
-        print("bars", {k: f"{v:.2e}" for k, v in bars.items()}, flush=True)
-        bad = {k: (norms[k], bars[k]) for k in norms if not norms[k] <= bars[k]}
+        bars, base = fp64_bars(sub, o, p, 1000)
     else:
-        bad = {k: norms[k] for k in ("pos", "dir") if not norms[k] <= 1e-4}
+        bars, base = fp32_bars(sub, o, fp32_mirror(sub, 1000), 1000)
+    report(norms, base, precision)
+    bad = check(norms, bars)
     assert not bad, bad
 
 
@@ -75,8 +75,8 @@ def test_cantilever_full_10000_steps():
     norms = rod_norms(inp, o.state(), (pos, vel, dr, om), t)
     norms["energy"] = energy_norm(o.energy(), e)
     bars, sens = fp64_bars(inp, o, p, 10000)
-    print("norms", {k: f"{v:.2e}" for k, v in norms.items()}, "bars", {k: f"{v:.2e}" for k, v in bars.items()})
-    bad = {k: (norms[k], bars[k]) for k in norms if not norms[k] <= bars[k]}
+    report(norms, sens, "f64")
+    bad = check(norms, bars)
     assert not bad, bad
     A, I = RC.section(0.01)
     ref = RC.cantilever_modal_tip(t, 1e-3, 1e6, I, 1000.0, A, 1.0)
@@ -85,15 +85,26 @@ def test_cantilever_full_10000_steps():
     assert abs(tip / ref - 1) < 0.01
 
 
+def full_f32_against_mirror(inp, steps, n_sample, seed):
+    """Full-size FP32 run; a seeded sample of rods against the FP64 oracle,
+    all five norms within the FP32 bars of the mirror's own discrepancy."""
+    got, e_got, sub, t = _full_run(inp, "f32", steps, n_sample, seed)
+    o = ro.Oracle(sub)
+    o.step(steps)
+    norms = rod_norms(sub, o.state(), got, steps * inp.dt)
+    norms["energy"] = energy_norm(o.energy(), e_got)
+    bars, base = fp32_bars(sub, o, fp32_mirror(sub, steps), steps)
+    report(norms, base, "f32")
+    bad = check(norms, bars)
+    assert not bad, bad
+
+
 def test_carpet_65536_full_f32_20000_steps():
     """The cilia carpet (65,536 rods x 50, FP32, autotuned) over its full
-    20,000 steps; 64 seeded rods against the FP64 oracle."""
+    20,000 steps; 64 seeded rods against the FP64 oracle.  The FP32 mirror
+    itself departs from the FP64 oracle by about 3e-2 in omega and 1e-3 in
+    velocity over these steps (the stiff shear modes carry FP32 round-off):
+    that is the scale the bar follows."""
     inp = W.cilia_carpet()
     print("case: carpet 65,536 rods, f32, 20,000 steps, 64-rod oracle sample", flush=True)
-    got, e_got, sub, t = _full_run(inp, "f32", 20000, 64, 103)
-    o = ro.Oracle(sub)
-    o.step(20000)
-    norms = rod_norms(sub, o.state(), got, 20000 * inp.dt)
-    print("norms", {k: f"{v:.2e}" for k, v in norms.items()}, flush=True)
-    bad = {k: norms[k] for k in ("pos", "dir") if not norms[k] <= 1.2e-3}
-    assert not bad, bad
+    full_f32_against_mirror(inp, 20000, 64, 103)

@@ -96,3 +96,20 @@ def test_flatten_roundtrip_and_count():
     q = M.unflatten(v)
     for (a, b), (c, d) in zip(p, q):
         assert np.array_equal(a, c) and np.array_equal(b, d)
+
+
+def test_silu_matches_torch_and_its_identities():
+    """The forward's activation against torch's SiLU (a library routine) in
+    FP64 over a wide range, and the identities that fix x * sigmoid(x): it
+    vanishes at 0, silu(x) - silu(-x) = x, it tends to x and to 0 in the two
+    tails; its derivative against torch's autograd of the same routine."""
+    rng = np.random.default_rng(3)
+    z = np.concatenate([rng.normal(0, 3, 5000), np.linspace(-40, 40, 801), [0.0, 1e-12, -1e-12, 700.0, -700.0]])
+    ref = torch.nn.functional.silu(torch.tensor(z, dtype=torch.float64)).numpy()
+    assert np.allclose(M.silu(z), ref, rtol=1e-14, atol=1e-300)
+    assert M.silu(0.0) == 0.0
+    assert np.allclose(M.silu(z) - M.silu(-z), z, rtol=1e-13, atol=1e-13)
+    assert abs(M.silu(50.0) - 50.0) < 1e-15 * 50 * 10 and abs(M.silu(-50.0)) < 1e-19
+    t = torch.tensor(z, dtype=torch.float64, requires_grad=True)
+    torch.nn.functional.silu(t).sum().backward()
+    assert np.allclose(M.dsilu(z), t.grad.numpy(), rtol=1e-13, atol=1e-300)

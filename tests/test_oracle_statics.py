@@ -138,3 +138,23 @@ def test_cantilever_static_euler_bernoulli():
         assert abs(tips[n] / ref - 1) < 0.01
     rich = 2 * tips[50] - tips[25]
     assert abs(rich / (F * L ** 3 / (3 * E * I) + F * L / (4 / 3 * G * A)) - 1) < 0.01
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("stretch", [1.0, 1.01])
+def test_rotational_kinetic_energy_closed_form(axis, stretch):
+    """T_rot of a straight rod whose elements all spin at w about one
+    material axis, in closed form: 1/2 rho I_a L w^2 / e with I_1 = I_2 =
+    pi r^4 / 4, I_3 = I_1 + I_2 (Eq. 1b's angular momentum density
+    rho I omega / e); the rod stretched uniformly to e = 1.01 divides it by e."""
+    n, L, r, rho, w = 20, 0.4, 0.01, 1000.0, 3.0
+    nodes, Q = RC.twisted_rod(n, L, 0.0)
+    om = np.zeros((n, 3))
+    om[:, axis] = w
+    inp = RC.single(nodes * stretch, Q, omega=om, radius=r, rho=rho, rest_length=np.full(n, L / n))
+    e = ro.Oracle(inp).energy()[0]
+    I1 = np.pi * r ** 4 / 4.0
+    Ia = (I1, I1, 2.0 * I1)[axis]
+    want = 0.5 * rho * Ia * L * w * w / stretch
+    assert abs(e[1] / want - 1.0) < 1e-13
+    assert e[0] == 0.0                      # nodes at rest

@@ -145,3 +145,32 @@ def test_perturbation_statistics_and_clamps():
         assert abs(x.mean()) < 0.02 and abs(x.std() - 1) < 0.02
     QQ = np.einsum("iab,icb->iac", p1[2], p1[2]) - np.eye(3)
     assert np.abs(QQ).max() < 1e-14
+
+
+def test_judge_errors_hand_built():
+    """The judge's two measures on states whose answers are known by
+    construction: a straight rod of length L with one node moved by
+    (3e-4, 4e-4, 0) m reports 5e-4 / L; frames scaled by (1 + eps) report
+    (1 + eps)^2 - 1 as the orthonormality error, exact rotations zero; the
+    length is the reference's."""
+    n, L = 10, 0.5
+    nodes = np.stack([np.linspace(0, L, n + 1), np.zeros(n + 1), np.zeros(n + 1)], axis=1)
+    rng = np.random.default_rng(5)
+    Q = np.stack([RC.random_rotation(rng) for _ in range(n)])
+    inp = RC.single(nodes, Q)
+    ref = (nodes, np.zeros_like(nodes), Q, np.zeros((n, 3)))
+    moved = nodes.copy()
+    moved[4] += [3e-4, 4e-4, 0.0]
+    eps = 1e-6
+    Qs = Q.copy()
+    Qs[7] *= 1.0 + eps
+    err = S.judge_errors(inp, ref, (moved, ref[1], Qs, ref[3]))
+    assert err.shape == (1, 2)
+    assert abs(err[0, 0] - 5e-4 / L) < 1e-15
+    assert abs(err[0, 1] - ((1 + eps) ** 2 - 1)) < 1e-15
+    err0 = S.judge_errors(inp, ref, ref)
+    assert err0[0, 0] == 0.0 and err0[0, 1] < 1e-15
+    # the length comes from the reference state: stretching the judged state
+    # by 10% along the rod moves node j by 0.1 x_j, the largest at the tip
+    err1 = S.judge_errors(inp, ref, (nodes * [1.1, 1, 1], ref[1], Q, ref[3]))
+    assert abs(err1[0, 0] - 0.1) < 1e-14
