@@ -113,8 +113,8 @@ struct DevBatch {
     const int32_t *conn_off;       // [total + 1] CSR offsets over global compact indices
     const int32_t *conn_partner;   // [2C] partner's compact index within the tile
     const int32_t *conn_key;       // [total] slot * 2 + (0: node i, 1: node n) of each compact index
-    const T *conn_par;             // [3][2C] k, c, rest
-    const T *rod_org;              // [3][n_rods] rod origin relative to its tile's first rod (connections or walls)
+    const double *conn_par;        // [3][2C] k, c, rest
+    const double *rod_org;         // [3][n_rods] rod origin relative to its tile's first rod (connections or walls)
     const double *rod_rad;         // [n_rods] rod radius (connections or walls)
     const T *wall_off;             // [n_tiles][8] wall offsets d in each tile's frame
     int conn_nodes;                // table rows per tile

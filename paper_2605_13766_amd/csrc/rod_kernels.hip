@@ -229,24 +229,26 @@ __device__ __forceinline__ void rod_prefix(T &p0, T &p1, T &p2, int idx, T *sc, 
 // from its connections: sum over them, in connection order, of
 // [k (l - l0) + c dl/dt] e, e the unit vector to the partner.  `tab` holds
 // rows x0 x1 x2 v0 v1 v2 of `rows` entries.  Coincident nodes exert nothing
-// (the direction is undefined there).
+// (the direction is undefined there).  FP64 in both precisions: the table's
+// positions are FP64, and in an FP32 step the spring's small extension
+// l - l0 would otherwise lose the digits of the rod-sized coordinates.
 template <typename T>
-__device__ inline void connection_force(const DevBatch<T> &B, const T *tab, int rows, int me, int g, T &f0, T &f1,
-                                        T &f2)
+__device__ inline void connection_force(const DevBatch<T> &B, const double *tab, int rows, int me, int g,
+                                        double &f0, double &f1, double &f2)
 {
     const int64_t E = B.conn_entries;
-    const T x0 = tab[me], x1 = tab[rows + me], x2 = tab[2 * rows + me];
-    const T u0 = tab[3 * rows + me], u1 = tab[4 * rows + me], u2 = tab[5 * rows + me];
+    const double x0 = tab[me], x1 = tab[rows + me], x2 = tab[2 * rows + me];
+    const double u0 = tab[3 * rows + me], u1 = tab[4 * rows + me], u2 = tab[5 * rows + me];
     for (int e = B.conn_off[g]; e < B.conn_off[g + 1]; ++e) {
         const int p = B.conn_partner[e];
-        const T dx = tab[p] - x0, dy = tab[rows + p] - x1, dz = tab[2 * rows + p] - x2;
-        const T l2 = dx * dx + dy * dy + dz * dz;
-        if (l2 > T(0)) {
-            const T il = rsqrt_t(l2);
-            const T l = l2 * il;
-            const T ex = dx * il, ey = dy * il, ez = dz * il;
-            const T ldot = ex * (tab[3 * rows + p] - u0) + ey * (tab[4 * rows + p] - u1) + ez * (tab[5 * rows + p] - u2);
-            const T mag = B.conn_par[e] * (l - B.conn_par[2 * E + e]) + B.conn_par[E + e] * ldot;
+        const double dx = tab[p] - x0, dy = tab[rows + p] - x1, dz = tab[2 * rows + p] - x2;
+        const double l2 = dx * dx + dy * dy + dz * dz;
+        if (l2 > 0.0) {
+            const double il = rsqrt_t(l2);
+            const double l = l2 * il;
+            const double ex = dx * il, ey = dy * il, ez = dz * il;
+            const double ldot = ex * (tab[3 * rows + p] - u0) + ey * (tab[4 * rows + p] - u1) + ez * (tab[5 * rows + p] - u2);
+            const double mag = B.conn_par[e] * (l - B.conn_par[2 * E + e]) + B.conn_par[E + e] * ldot;
             f0 += mag * ex; f1 += mag * ey; f2 += mag * ez;
         }
     }
@@ -388,10 +390,11 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         T cst[N_C * TL];
     };
     __shared__ Shared sh;
-    // connections: rows x0 x1 x2 v0 v1 v2 of the tile's connected nodes (and,
-    // for FP32, scratch of a prefix sum at the tile's start); sized at launch
+    // connections: rows x0 x1 x2 v0 v1 v2 (FP64) of the tile's connected
+    // nodes; for FP32, also the scratch of the prefix sum of node positions at
+    // the tile's start (FP64 with connections, else FP32); sized at launch
     extern __shared__ __align__(16) unsigned char conn_lds[];
-    T *const tab = reinterpret_cast<T *>(conn_lds);
+    double *const tab = reinterpret_cast<double *>(conn_lds);
     T *const lxa = sh.lxa, *const lxb = sh.lxb;
     T *const cst = sh.cst;
     double *const phs = sh.phs;
@@ -554,17 +557,29 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         int ci = -1, cn = -1, cbase = 0;
         if constexpr (NODE) {
             T x0, x1, x2;
+            double X0, X1, X2;   // the same in FP64, for the connection table
             if constexpr (POS) {
                 x0 = t0; x1 = t1; x2 = t2;   // node i's position
+                X0 = x0; X1 = x1; X2 = x2;
             } else {
-                // rod origin + anchor + the edges before node i (a prefix sum along the rod)
+                // rod origin + anchor + the edges before node i (a prefix sum
+                // along the rod; in FP64 when the tile has connections)
                 const T e3[3] = {d0, d1, d2};
                 T lf[3];
                 from_left<W>(e3, lf, lxa, wave, wl);
-                x0 = first ? B.rod_org[rr] + t0 : lf[0];
-                x1 = first ? B.rod_org[B.n_rods + rr] + t1 : lf[1];
-                x2 = first ? B.rod_org[2 * B.n_rods + rr] + t2 : lf[2];
-                rod_prefix<W>(x0, x1, x2, i, tab, lane);
+                if (B.conn_idx) {
+                    X0 = first ? B.rod_org[rr] + (double)t0 : (double)lf[0];
+                    X1 = first ? B.rod_org[B.n_rods + rr] + (double)t1 : (double)lf[1];
+                    X2 = first ? B.rod_org[2 * B.n_rods + rr] + (double)t2 : (double)lf[2];
+                    rod_prefix<W>(X0, X1, X2, i, tab, lane);
+                    x0 = T(X0); x1 = T(X1); x2 = T(X2);
+                } else {
+                    x0 = first ? T(B.rod_org[rr]) + t0 : lf[0];
+                    x1 = first ? T(B.rod_org[B.n_rods + rr]) + t1 : lf[1];
+                    x2 = first ? T(B.rod_org[2 * B.n_rods + rr]) + t2 : lf[2];
+                    rod_prefix<W>(x0, x1, x2, i, reinterpret_cast<T *>(conn_lds), lane);
+                    X0 = x0; X1 = x1; X2 = x2;
+                }
                 __syncthreads();
             }
             // positions after the opening half drift
@@ -587,9 +602,10 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 ci = B.conn_idx[s];
                 cn = last ? B.conn_idx[NS + s] : -1;
                 cbase = B.conn_tbase[tile];
-                if (ci >= 0) { tab[ci] = x0 + hh * v0; tab[rows + ci] = x1 + hh * v1; tab[2 * rows + ci] = x2 + hh * v2; }
+                const double H = hh;
+                if (ci >= 0) { tab[ci] = X0 + H * v0; tab[rows + ci] = X1 + H * v1; tab[2 * rows + ci] = X2 + H * v2; }
                 if (cn >= 0) {
-                    tab[cn] = x0 + d0 + hh * u0; tab[rows + cn] = x1 + d1 + hh * u1; tab[2 * rows + cn] = x2 + d2 + hh * u2;
+                    tab[cn] = X0 + d0 + H * u0; tab[rows + cn] = X1 + d1 + H * u1; tab[2 * rows + cn] = X2 + d2 + H * u2;
                 }
             }
         }
@@ -668,8 +684,11 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                     if (ci >= 0) { tab[3 * rows + ci] = v0; tab[4 * rows + ci] = v1; tab[5 * rows + ci] = v2; }
                     if (cn >= 0) { tab[3 * rows + cn] = u0; tab[4 * rows + cn] = u1; tab[5 * rows + cn] = u2; }
                     __syncthreads();
-                    if (ci >= 0) connection_force(B, tab, rows, ci, cbase + ci, fc0, fc1, fc2);
-                    if (cn >= 0) connection_force(B, tab, rows, cn, cbase + cn, gc0, gc1, gc2);
+                    double f0 = 0, f1 = 0, f2 = 0, g0 = 0, g1 = 0, g2 = 0;
+                    if (ci >= 0) connection_force(B, tab, rows, ci, cbase + ci, f0, f1, f2);
+                    if (cn >= 0) connection_force(B, tab, rows, cn, cbase + cn, g0, g1, g2);
+                    fc0 = T(f0); fc1 = T(f1); fc2 = T(f2);
+                    gc0 = T(g0); gc1 = T(g1); gc2 = T(g2);
                 }
                 if constexpr (WALL) {
                     // node i at x, node n (last lane) at x + the edge
@@ -776,8 +795,9 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 }
                 if (B.conn_idx) {
                     const int rows = B.conn_nodes;
-                    if (ci >= 0) { tab[ci] += dd * v0; tab[rows + ci] += dd * v1; tab[2 * rows + ci] += dd * v2; }
-                    if (cn >= 0) { tab[cn] += dd * u0; tab[rows + cn] += dd * u1; tab[2 * rows + cn] += dd * u2; }
+                    const double D = dd;
+                    if (ci >= 0) { tab[ci] += D * v0; tab[rows + ci] += D * v1; tab[2 * rows + ci] += D * v2; }
+                    if (cn >= 0) { tab[cn] += D * u0; tab[rows + cn] += D * u1; tab[2 * rows + cn] += D * u2; }
                 }
             }
             rotate_left(q, -dd * w0, -dd * w1, -dd * w2);
@@ -1021,15 +1041,26 @@ __global__ void rod_energy_kernel(const DevBatch<T> B, double *out, const int32_
 
 // ------------------------------------------------------------------ launchers
 
+// Dynamic LDS of the node-interaction kinds: the FP64 connection table of
+// `conn_nodes` rows (negative: the batch has no connections) and, for FP32,
+// the scratch of the starting prefix sum, 3 values per lane (FP64 with
+// connections).
+static size_t step_dyn_lds(bool f32, int waves, int conn_nodes)
+{
+    const size_t scan = (size_t)3 * 64 * waves;
+    if (conn_nodes < 0) return f32 ? sizeof(float) * scan : 0;
+    const size_t table = (size_t)6 * conn_nodes;
+    return sizeof(double) * (f32 ? std::max(table, scan) : table);
+}
+
 template <typename T, int W>
 static hipError_t launch_w(const DevBatch<T> &b, int n_sub, int grid, hipStream_t s)
 {
     if (grid <= 0) grid = b.n_tiles;
     if (b.ext && (b.conn_idx || b.n_walls || b.cforce)) {
-        // node interactions: the connection table (6 rows per connected node),
-        // and for FP32 the scratch of the starting prefix sum (3 per lane)
-        const size_t lds = sizeof(T) * (size_t)std::max(b.conn_idx ? 6 * b.conn_nodes : 0,
-                                                        sizeof(T) == 4 ? 3 * 64 * W : 0);
+        // node interactions: the FP64 connection table (6 rows per connected
+        // node), and for FP32 the scratch of the starting prefix sum (3 per lane)
+        const size_t lds = step_dyn_lds(sizeof(T) == 4, W, b.conn_idx ? b.conn_nodes : -1);
         if (b.n_walls || b.cforce)
             hipLaunchKernelGGL((rod_step_kernel<T, W, 3>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
         else
@@ -1154,11 +1185,11 @@ size_t step_lds_bytes(int precision_f32, int waves, int kind, int conn_nodes)
     if (precision_f32) {
         st = kind == 3 ? static_lds_t<float, 3>(waves) : kind == 2 ? static_lds_t<float, 2>(waves)
            : kind == 1 ? static_lds_t<float, 1>(waves) : static_lds_t<float, 0>(waves);
-        if (kind >= 2) dyn = sizeof(float) * (size_t)std::max(6 * conn_nodes, 3 * 64 * waves);
+        if (kind >= 2) dyn = step_dyn_lds(true, waves, kind == 2 || conn_nodes > 0 ? conn_nodes : -1);
     } else {
         st = kind == 3 ? static_lds_t<double, 3>(waves) : kind == 2 ? static_lds_t<double, 2>(waves)
            : kind == 1 ? static_lds_t<double, 1>(waves) : static_lds_t<double, 0>(waves);
-        if (kind >= 2) dyn = sizeof(double) * (size_t)(6 * conn_nodes);
+        if (kind >= 2) dyn = step_dyn_lds(false, waves, conn_nodes);
     }
     return st + dyn;
 }

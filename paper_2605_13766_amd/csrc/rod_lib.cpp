@@ -107,8 +107,8 @@ struct rod_batch {
     int32_t *d_conn_tbase = nullptr;   // [n_tiles] first compact index of each tile
     int32_t *d_conn_partner = nullptr; // [2C] partner's compact index within its tile
     int32_t *d_conn_key = nullptr;     // [total] slot * 2 + column of each compact index
-    void *d_conn_par = nullptr;        // [3][2C] k, c, rest (state precision)
-    void *d_rod_org = nullptr;         // [3][R] rod origins (connections or walls)
+    double *d_conn_par = nullptr;      // [3][2C] k, c, rest
+    double *d_rod_org = nullptr;       // [3][R] rod origins (connections or walls)
     double *d_rod_rad = nullptr;       // [R] rod radii (walls)
     void *d_wall_off = nullptr;        // [n_tiles][8] wall offsets in each tile's frame
     int n_walls = 0;
@@ -468,8 +468,8 @@ void fill_dev(rodk::DevBatch<T> &d, rod_batch *b)
     d.conn_off = b->d_conn_off;
     d.conn_partner = b->d_conn_partner;
     d.conn_key = b->d_conn_key;
-    d.conn_par = (const T *)b->d_conn_par;
-    d.rod_org = (const T *)b->d_rod_org;
+    d.conn_par = b->d_conn_par;
+    d.rod_org = b->d_rod_org;
     d.rod_rad = b->d_rod_rad;
     d.wall_off = (const T *)b->d_wall_off;
     d.cforce = b->rod_contact ? b->cg.force : nullptr;
@@ -709,7 +709,7 @@ int build_device(rod_batch *b, const HostInputs &h)
         std::vector<int32_t> ckey(total);
         for (int64_t key : ukeys) ckey[global_of(key)] = (int32_t)key;
         std::vector<int32_t> off(total + 1, 0), partner(2 * C);
-        std::vector<T> par((size_t)3 * 2 * C);
+        std::vector<double> par((size_t)3 * 2 * C);
         for (int c = 0; c < C; ++c) {
             ++off[global_of(keys[2 * c]) + 1];
             ++off[global_of(keys[2 * c + 1]) + 1];
@@ -723,9 +723,9 @@ int build_device(rod_batch *b, const HostInputs &h)
                     return fail(ROD_EDEVICE, "connection " + std::to_string(c) + " spans two tiles");
                 const int32_t e = fill[global_of(me)]++;
                 partner[e] = idx[(other % 2) * NS + other / 2];
-                par[e] = T(h.ck[c]);
-                par[2 * C + e] = T(h.cc[c]);
-                par[4 * C + e] = T(h.crest[c]);
+                par[e] = h.ck[c];
+                par[2 * C + e] = h.cc[c];
+                par[4 * C + e] = h.crest[c];
             }
         b->n_conn = C;
         HIPCHK(hipMalloc((void **)&b->d_conn_idx, idx.size() * sizeof(int32_t)));
@@ -733,14 +733,14 @@ int build_device(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc((void **)&b->d_conn_off, off.size() * sizeof(int32_t)));
         HIPCHK(hipMalloc((void **)&b->d_conn_partner, partner.size() * sizeof(int32_t)));
         HIPCHK(hipMalloc((void **)&b->d_conn_key, std::max<size_t>(ckey.size(), 1) * sizeof(int32_t)));
-        HIPCHK(hipMalloc(&b->d_conn_par, par.size() * es));
+        HIPCHK(hipMalloc((void **)&b->d_conn_par, par.size() * sizeof(double)));
 
         HIPCHK(hipMemcpy(b->d_conn_idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_tbase, tbase.data(), tbase.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_partner, partner.data(), partner.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_conn_key, ckey.data(), ckey.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->d_conn_par, par.data(), par.size() * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_conn_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     if (!h.ck.empty() || b->n_walls > 0 || b->rod_contact) {
         // FP32 node interactions work in the frame of each tile's first rod
@@ -754,11 +754,11 @@ int build_device(rod_batch *b, const HostInputs &h)
             const int tile = b->rod_slot[r] / TL;
             if (first_rod[tile] < 0 || b->rod_slot[r] < b->rod_slot[first_rod[tile]]) first_rod[tile] = r;
         }
-        std::vector<T> org((size_t)3 * R, T(0));
+        std::vector<double> org((size_t)3 * R, 0.0);
         for (int r = 0; r < R; ++r) {
             const int ref = first_rod[b->rod_slot[r] / TL];
             for (int a = 0; a < 3; ++a)
-                org[a * R + r] = rel ? T(b->origin[3 * r + a] - b->origin[3 * ref + a]) : T(0);
+                org[a * R + r] = rel ? b->origin[3 * r + a] - b->origin[3 * ref + a] : 0.0;
         }
         std::vector<T> woff((size_t)8 * b->n_tiles, T(0));
         for (int t = 0; t < b->n_tiles; ++t)
@@ -769,8 +769,8 @@ int build_device(rod_batch *b, const HostInputs &h)
             }
         HIPCHK(hipMalloc(&b->d_wall_off, woff.size() * es));
         HIPCHK(hipMemcpy(b->d_wall_off, woff.data(), woff.size() * es, hipMemcpyHostToDevice));
-        HIPCHK(hipMalloc(&b->d_rod_org, org.size() * es));
-        HIPCHK(hipMemcpy(b->d_rod_org, org.data(), org.size() * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc((void **)&b->d_rod_org, org.size() * sizeof(double)));
+        HIPCHK(hipMemcpy(b->d_rod_org, org.data(), org.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMalloc((void **)&b->d_rod_rad, (size_t)R * sizeof(double)));
         HIPCHK(hipMemcpy(b->d_rod_rad, h.rad.data(), (size_t)R * sizeof(double), hipMemcpyHostToDevice));
     }
