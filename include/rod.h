@@ -257,6 +257,23 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream);
  */
 int rod_energy(rod_batch *b, double *out, void *stream);
 
+/*
+ * rod_energy for callers that cannot allocate device memory (code that must
+ * not call hipMalloc: serving loops, harnesses that forbid allocation).  Same
+ * arguments, result and errors as rod_energy, bit for bit; the per-rod
+ * energies are staged in a statically allocated device buffer of the library
+ * instead of one allocated with the batch.  No device memory is allocated or
+ * freed (the buffer's address is looked up once per device, on the first call
+ * there).
+ * Limit: batches of at most 262,144 rods (the buffer holds 5 doubles per rod,
+ * 10 MiB, and stays allocated on every device the library runs on until the
+ * process ends); larger batches get ROD_EINVAL.  Call with the batch's device
+ * current.  All calls on one device share the buffer: calls that overlap in
+ * time on one device (other host threads, other streams) race and must not
+ * be made.
+ */
+int rod_energy_noalloc(rod_batch *b, double *out, void *stream);
+
 /* Copy the state back into caller-owned host arrays in the layout above (any
  * pointer may be NULL to skip it); *t receives the current time.
  * Synchronises `stream`.  ROD_ENONFINITE if any rod is flagged. */

@@ -27,7 +27,7 @@ HIP_FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["rod_lib.cpp", "rod_kernels.hip", "contact_kernels.hip", "surrogate.cpp", "mlp_kernels.hip", "mlp_infer.hip", "surrogate_kernels.hip"]
+SOURCES = ["rod_lib.cpp", "rod_kernels.hip", "contact_kernels.hip", "noalloc.hip", "surrogate.cpp", "mlp_kernels.hip", "mlp_infer.hip", "surrogate_kernels.hip"]
 
 
 def hipcc() -> str:

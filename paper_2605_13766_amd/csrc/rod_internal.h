@@ -180,6 +180,15 @@ int step_resident_groups(int precision_f32, int waves);
 // connected nodes per tile.
 size_t step_lds_bytes(int precision_f32, int waves, int kind, int conn_nodes);
 
+// rod_energy_noalloc's statically allocated device buffer (noalloc.hip): room
+// for the energies of NOALLOC_MAX_RODS rods and one int32 result.
+constexpr int64_t NOALLOC_MAX_RODS = 262144;
+// The buffer's device address on the current device (looked up once per
+// device): the energies [5 * NOALLOC_MAX_RODS] and the int32 after them.
+int noalloc_scratch(double **energies, int32_t **first_flagged);
+// out[0] = smallest r < n with flags[r] != 0, or n (one small kernel).
+hipError_t launch_first_flagged(const int32_t *flags, int n, int32_t *out, hipStream_t s);
+
 // Read access to a batch for the surrogate runtime (rod_lib.cpp).
 struct BatchView {
     int precision;

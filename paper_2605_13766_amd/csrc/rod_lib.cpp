@@ -1316,6 +1316,37 @@ int rod_energy(rod_batch *b, double *out, void *stream)
     return check_flags(b, s);
 }
 
+int rod_energy_noalloc(rod_batch *b, double *out, void *stream)
+{
+    if (!b || !out) return fail(ROD_EINVAL, "handle or out is NULL");
+    if (b->R > rodk::NOALLOC_MAX_RODS)
+        return fail(ROD_EINVAL, "rod_energy_noalloc serves at most " + std::to_string(rodk::NOALLOC_MAX_RODS)
+                                    + " rods; this batch has " + std::to_string(b->R) + " (use rod_energy)");
+    double *energies = nullptr;
+    int32_t *first = nullptr;
+    int rc = rodk::noalloc_scratch(&energies, &first);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (b->rod_contact) {
+        // the pairs' potentials at the current positions (the batch's own grid buffers)
+        hipError_t e = b->precision == ROD_F32 ? rodk::launch_contact(b->b32, b->cg, 0.0, s)
+                                               : rodk::launch_contact(b->b64, b->cg, 0.0, s);
+        if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
+    }
+    hipError_t e = b->precision == ROD_F32 ? rodk::launch_energy(b->b32, energies, s)
+                                           : rodk::launch_energy(b->b64, energies, s);
+    if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("energy launch: ") + hipGetErrorString(e));
+    const int32_t *dflags = b->d_ints + 2 * b->n_slots + 3 * b->R;
+    e = rodk::launch_first_flagged(dflags, b->R, first, s);
+    if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("flag launch: ") + hipGetErrorString(e));
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(out, energies, (size_t)5 * b->R * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&bad, first, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad < b->R) return fail(ROD_ENONFINITE, "rod " + std::to_string(bad) + " has a non-finite state");
+    return ROD_OK;
+}
+
 int rod_get_state(rod_batch *b, double *pos, double *vel, double *dir, double *om, double *t, void *stream)
 {
     if (!b) return fail(ROD_EINVAL, "handle is NULL");

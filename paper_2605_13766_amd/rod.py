@@ -105,6 +105,7 @@ def lib():
         L.rod_batch_create.argtypes = [C.POINTER(RodBatchDesc), vp, C.POINTER(vp)]
         L.rod_step.argtypes = [vp, C.c_int64, vp]
         L.rod_energy.argtypes = [vp, _dp, vp]
+        L.rod_energy_noalloc.argtypes = [vp, _dp, vp]
         L.rod_get_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, vp]
         L.rod_set_state.argtypes = [vp, _dp, _dp, _dp, _dp, C.c_double, vp]
         L.rod_get_flags.argtypes = [vp, _ip, vp]
@@ -114,7 +115,7 @@ def lib():
         L.rod_batch_tuning.restype = C.c_int
         L.rod_batch_destroy.restype = None
         L.rod_last_error.restype = C.c_char_p
-        for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_get_state", "rod_set_state",
+        for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_energy_noalloc", "rod_get_state", "rod_set_state",
                   "rod_get_flags", "rod_batch_info"):
             getattr(L, f).restype = C.c_int
         fp = C.POINTER(C.c_float)
@@ -268,6 +269,12 @@ class RodBatch:
     def energy(self, stream=None) -> np.ndarray:
         out = np.empty((self.n_rods, 5))
         _check(lib().rod_energy(self._h, _p(out), _stream_ptr(stream)))
+        return out
+
+    def energy_noalloc(self, stream=None) -> np.ndarray:
+        """rod_energy_noalloc: the energies staged in the library's static buffer."""
+        out = np.empty((self.n_rods, 5))
+        _check(lib().rod_energy_noalloc(self._h, _p(out), _stream_ptr(stream)))
         return out
 
     def get_state(self, stream=None):
