@@ -77,6 +77,31 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+# AddressSanitizer and UBSan build (tests only): every error aborts the process
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def build_sanitized(outdir: str) -> str:
+    """Compile the oracle and its FP32 mirror with AddressSanitizer and UBSan
+    into `outdir` (same file names).  Loaded by a process that has gcc's
+    libasan preloaded and ROD_ORACLE_LIBDIR=outdir."""
+    os.makedirs(outdir, exist_ok=True)
+    for name, extra in (("librod_oracle.so", []), ("librod_oracle32.so", _F32_FLAGS)):
+        out = os.path.join(outdir, name)
+        subprocess.check_call(["gcc", *_COMMON, *extra, *_SAN_FLAGS, "-o", out, _SRC, "-lm"])
+    return outdir
+
+
+def _lib_paths():
+    """The two libraries: those in ROD_ORACLE_LIBDIR when it is set (a
+    sanitizer build), else the regular build (compiled when stale)."""
+    d = os.environ.get("ROD_ORACLE_LIBDIR")
+    if d:
+        return os.path.join(d, "librod_oracle.so"), os.path.join(d, "librod_oracle32.so")
+    build()
+    return _LIB, _LIB32
+
+
 _lib = None
 _lib32 = None
 
@@ -85,8 +110,7 @@ def lib32():
     """The FP32 mirror's library (orc_step on float state arrays)."""
     global _lib32
     if _lib32 is None:
-        build()
-        L = C.CDLL(_LIB32)
+        L = C.CDLL(_lib_paths()[1])
         L.orc_step.argtypes = [C.POINTER(_OrcRods32), _fp, _fp, _fp, _fp, C.c_int64, C.c_int64, C.c_int]
         L.orc_step.restype = C.c_int
         _lib32 = L
@@ -96,8 +120,7 @@ def lib32():
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(_lib_paths()[0])
         P = C.POINTER(_OrcRods)
         L.orc_step.argtypes = [P, _dp, _dp, _dp, _dp, C.c_int64, C.c_int64, C.c_int]
         L.orc_step.restype = C.c_int
