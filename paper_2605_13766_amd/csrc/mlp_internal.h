@@ -20,21 +20,22 @@ struct GemmArgs {
     const float *zsave;     // [M][ldc] pre-activation for EPI_DSILU
     int kchunk = 0;         // split reduction: K per z-slice (0: one slice)
     int64_t zstride = 0;    // offset between the slices' outputs
+    int ones_row = -1;      // row of A (in [0, M)) that reads as all ones: with A^T dZ
+                            // it makes that row of C the column sums of dZ (a bias gradient)
 };
 
 hipError_t gemm_forward(const GemmArgs &g, int epi, hipStream_t s);
 hipError_t gemm_backward_data(const GemmArgs &g, int epi, hipStream_t s);
-// work: scratch of work_floats floats for the split reduction (NULL: no split)
+// work: scratch of work_floats floats for the split reduction (NULL: no split).
+// With g.ones_row = K_l and g.M = K_l + 1, row K_l of C is the bias gradient.
 hipError_t gemm_backward_weight(const GemmArgs &g, float *work, int64_t work_floats, hipStream_t s);
 hipError_t mse_grad(const float *Y, const float *T, const float *mask, float *dY, float *partial,
                     int64_t M, int n_out, int ld, hipStream_t s);
 int mse_partials(int64_t M, int ld);
 hipError_t sum_partials(const float *partial, int n, float scale, float *out, hipStream_t s);
-// db[n] = sum_m dZ[m][n]; N must divide 256; work: ceil(M / 64) * N floats of scratch
-hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, float *work, int64_t work_floats,
-                  hipStream_t s);
+// wb: BF16 copies of the updated weights (NULL: none)
 hipError_t adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                float eps, int64_t t, hipStream_t s);
+                float eps, int64_t t, __bf16 *wb, hipStream_t s);
 hipError_t to_bf16(const float *src, __bf16 *dst, int64_t n, hipStream_t s);
 
 // Fused inference (mlp_infer.hip).  Weights are first packed from the BF16

@@ -1,6 +1,7 @@
 // mlp_kernels.hip -- gfx950 kernels of the surrogate's per-element MLP:
 // a tiled BF16 MFMA GEMM (v_mfma_f32_16x16x32_bf16, FP32 accumulate) with
-// fused epilogues, the MSE gradient, bias-gradient column sums and Adam.
+// fused epilogues (the bias gradient rides in the weight-gradient GEMM), the
+// MSE gradient and Adam.
 //
 // Network: F_in -> 256 -> 256 -> 256 -> 12 (padded to 16 columns), SiLU after
 // the first three layers, BF16 weights and activations, FP32 bias, FP32
@@ -38,16 +39,18 @@ __device__ inline float dsilu_f(float z)
 // each thread moves one 16-element run with 16-byte loads (two for BF16, four
 // for FP32 sources), written to LDS as two 16-byte stores (k contiguous) or
 // sixteen 2-byte stores (transposing).  Rows >= nrows and k outside [k0, ke)
-// read as zero.
+// read as zero; row `ones` (if in [0, nrows)) reads as one for every k in
+// [k0, ke) and is not loaded.
 template <bool TRANS, typename TS, int LDK>
 __device__ inline void stage_tile(__bf16 (*S)[LDK], const TS *src, int64_t ld, int row0, int nrows, int k0, int ke,
-                                  int t)
+                                  int t, int ones)
 {
     __bf16 v[16];
     const int a = t >> 2, b = (t & 3) * 16;   // direct: a = row, b = k offset; transposed: a = k, b = row offset
     const int row = TRANS ? row0 + b : row0 + a;
     const int k = TRANS ? k0 + a : k0 + b;
-    const bool full = TRANS ? (k < ke && row + 16 <= nrows) : (row < nrows && k + 16 <= ke);
+    const bool full = TRANS ? (k < ke && row + 16 <= nrows && (ones < row || ones >= row + 16))
+                            : (row < nrows && row != ones && k + 16 <= ke);
     if (full) {
         const TS *p = TRANS ? src + (int64_t)k * ld + row : src + (int64_t)row * ld + k;
         if constexpr (sizeof(TS) == 2) {
@@ -72,8 +75,10 @@ __device__ inline void stage_tile(__bf16 (*S)[LDK], const TS *src, int64_t ld, i
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int rj = TRANS ? row + j : row, kj = TRANS ? k : k + j;
-            v[j] = (__bf16)(rj < nrows && kj >= k0 && kj < ke ? to_f(src[TRANS ? (int64_t)kj * ld + rj : (int64_t)rj * ld + kj])
-                                                              : 0.f);
+            const bool in_k = kj >= k0 && kj < ke;
+            v[j] = (__bf16)(rj == ones ? (in_k ? 1.f : 0.f)
+                            : rj < nrows && in_k ? to_f(src[TRANS ? (int64_t)kj * ld + rj : (int64_t)rj * ld + kj])
+                                                 : 0.f);
         }
     }
     if constexpr (TRANS) {
@@ -118,9 +123,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
     const int q = lane >> 4, c = lane & 15;
     for (int k0 = kb; k0 < ke; k0 += BK) {
         // A: rows m, stored [M][K] (k contiguous) or [K][M] (m contiguous)
-        stage_tile<AT, TA, LDK>(As, A, g.lda, m0, g.M, k0, ke, t);
+        stage_tile<AT, TA, LDK>(As, A, g.lda, m0, g.M, k0, ke, t, g.ones_row);
         // B: rows n, stored [N][K] (k contiguous) when BT, else [K][N] (n contiguous)
-        stage_tile<!BT, TB, LDK>(Bs, B, g.ldb, n0, g.N, k0, ke, t);
+        stage_tile<!BT, TB, LDK>(Bs, B, g.ldb, n0, g.N, k0, ke, t, -1);
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
@@ -209,51 +214,10 @@ __global__ void sum_kernel(const float *partial, int n, float scale, float *out)
     if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
-// db[n] = sum_m dZ[m][n], one block per column.
-// Column sums db[n] = sum_m dZ[m][n], first pass: workgroup b sums rows
-// [b * CS_ROWS, (b + 1) * CS_ROWS) of every column; its 256 threads are
-// 256 / N row groups of N consecutive columns (N divides 256), so every load
-// instruction reads consecutive columns.  Partials go to part[b][N].  Short
-// chunks give many workgroups (1024 for 65,536 rows).
-constexpr int CS_ROWS = 64;
-
-__global__ void colsum_partial_kernel(const float *dZ, int64_t M, int N, int ld, float *part)
-{
-    __shared__ float red[256];
-    const int groups = 256 / N;
-    const int n = threadIdx.x % N, grp = threadIdx.x / N;
-    const int64_t r0 = (int64_t)blockIdx.x * CS_ROWS;
-    const int64_t r1 = r0 + CS_ROWS < M ? r0 + CS_ROWS : M;
-    float s = 0.f;
-    for (int64_t m = r0 + grp; m < r1; m += groups) s += dZ[m * ld + n];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (grp == 0) {
-        for (int k = 1; k < groups; ++k) s += red[k * N + n];
-        part[(int64_t)blockIdx.x * N + n] = s;
-    }
-}
-
-// Second pass, one workgroup per column: thread t sums part[b][n] over
-// b = t, t + 256, ..., then a fixed-order tree over the 256 threads.
-__global__ void colsum_final_kernel(const float *part, int nb, int N, float *db)
-{
-    __shared__ float red[256];
-    const int n = blockIdx.x;
-    float s = 0.f;
-    for (int b = threadIdx.x; b < nb; b += 256) s += part[(int64_t)b * N + n];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[n] = red[0];
-}
-
-// Adam (Kingma & Ba): m, v, w in FP32; bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
+// Adam (Kingma & Ba): m, v, w in FP32; bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t;
+// wb (or NULL) receives the updated weight rounded to BF16.
 __global__ void adam_kernel(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1,
-                            float b2, float eps, float c1, float c2)
+                            float b2, float eps, float c1, float c2, __bf16 *wb)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -262,7 +226,9 @@ __global__ void adam_kernel(float *w, float *m, float *v, const float *g, int64_
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = (__bf16)wi;
 }
 
 // BF16 copies of the FP32 master weights.
@@ -282,13 +248,22 @@ static hipError_t launch_t(const GemmArgs &g, hipStream_t s, int splits = 1)
     return hipGetLastError();
 }
 
-// out[i] = sum over z of part[z * stride + i], z ascending (deterministic)
+// out[i] = sum over z of part[z * stride + i], z ascending (deterministic);
+// the loads of eight slices are issued before their additions
 __global__ void sum_splits_kernel(const float *part, int splits, int64_t stride, int64_t n, float *out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float acc = 0.f;
-    for (int z = 0; z < splits; ++z) acc += part[z * stride + i];
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * stride + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; z < splits; ++z) acc += part[(int64_t)z * stride + i];
     out[i] = acc;
 }
 
@@ -316,11 +291,11 @@ hipError_t gemm_backward_weight(const GemmArgs &g, float *work, int64_t work_flo
 {
     // C[K_l][N_l] = act^T * dZ: act bf16 stored [M][K_l] = [K_gemm][M_gemm], dZ f32 [M][N_l].
     // The output has few 64 x 64 tiles, so the long reduction (the minibatch) is split
-    // into z-slices of whole 32-row stages, about 512 workgroups in all; the slices'
-    // partial products go to `work` and are summed in slice order.
+    // into z-slices of at least 512 rows, at most about 512 workgroups in all; the
+    // slices' partial products go to `work` and are summed in slice order.
     const int64_t tiles = (int64_t)((g.N + 63) / 64) * ((g.M + 63) / 64);
     const int64_t out_floats = (int64_t)g.M * g.ldc;
-    int splits = (int)std::min<int64_t>({(512 + tiles - 1) / tiles, (g.K + 31) / 32,
+    int splits = (int)std::min<int64_t>({(512 + tiles - 1) / tiles, (g.K + 511) / 512,
                                          work ? work_floats / std::max<int64_t>(out_floats, 1) : 1});
     if (splits <= 1) return launch_t<true, false, __bf16, float, EPI_STORE>(g, s);
     GemmArgs a = g;
@@ -353,28 +328,12 @@ hipError_t sum_partials(const float *partial, int n, float scale, float *out, hi
     return hipGetLastError();
 }
 
-hipError_t colsum(const float *dZ, int64_t M, int N, int ld, float *db, float *work, int64_t work_floats,
-                  hipStream_t s)
-{
-    const int64_t nb = (M + CS_ROWS - 1) / CS_ROWS;
-    if (256 % N != 0 || nb * N > work_floats) return hipErrorInvalidValue;
-    if (nb == 0) {
-        hipLaunchKernelGGL(colsum_final_kernel, dim3(N), dim3(256), 0, s, work, 0, N, db);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, dZ, M, N, ld, work);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(N), dim3(256), 0, s, work, (int)nb, N, db);
-    return hipGetLastError();
-}
-
 hipError_t adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                float eps, int64_t t, hipStream_t s)
+                float eps, int64_t t, __bf16 *wb, hipStream_t s)
 {
     const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1,
-                       b2, eps, c1, c2);
+                       b2, eps, c1, c2, wb);
     return hipGetLastError();
 }
 

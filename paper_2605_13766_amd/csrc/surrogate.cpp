@@ -62,6 +62,7 @@ struct rod_surrogate {
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;   // FP32, internal layout
     __bf16 *wb = nullptr;                                           // BF16 weights (internal layout)
     __bf16 *frag = nullptr;                                         // BF16 weights as inference fragments
+    bool frag_stale = true;                                         // wb changed since frag was packed
     int64_t adam_t = 0;
     // workspace (max_rows rows)
     float *Z[3] = {nullptr, nullptr, nullptr};
@@ -101,23 +102,45 @@ struct rod_surrogate {
 
 namespace {
 
+// BF16 copies of the FP32 weights; the inference fragments are repacked
+// lazily, before the next inference (training steps never need them).
 int refresh_bf16(rod_surrogate *s, hipStream_t st)
 {
     hipError_t e = mlpk::to_bf16(s->w, s->wb, s->lay.total, st);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("to_bf16: ") + hipGetErrorString(e));
+    s->frag_stale = true;
+    return ROD_OK;
+}
+
+int pack_if_stale(rod_surrogate *s, hipStream_t st)
+{
+    if (!s->frag_stale) return ROD_OK;
     mlpk::PackArgs p{};
     for (int l = 0; l < NL; ++l) {
         p.w_offset[l] = s->lay.w[l];
         p.ld[l] = NPAD[l];
     }
-    e = mlpk::pack_fragments(s->wb, p, s->frag, st);
+    hipError_t e = mlpk::pack_fragments(s->wb, p, s->frag, st);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("pack: ") + hipGetErrorString(e));
+    s->frag_stale = false;
+    return ROD_OK;
+}
+
+// One Adam step of every parameter with the BF16 copies refreshed in the same pass.
+int adam_step(rod_surrogate *s, float lr, hipStream_t st)
+{
+    s->adam_t += 1;
+    hipError_t e = mlpk::adam(s->w, s->m, s->v, s->g, s->lay.total, lr, 0.9f, 0.999f, 1e-8f, s->adam_t, s->wb, st);
+    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("adam: ") + hipGetErrorString(e));
+    s->frag_stale = true;
     return ROD_OK;
 }
 
 // Fused inference over M rows of standardised BF16 inputs into y ([M][ldy], ldy 16 or 12).
 int infer(rod_surrogate *s, const __bf16 *x, int64_t M, float *y, int ldy, hipStream_t st)
 {
+    int rc = pack_if_stale(s, st);
+    if (rc) return rc;
     mlpk::InferArgs a{};
     a.x = x;
     a.M = M;
@@ -164,7 +187,7 @@ int forward_chunk(rod_surrogate *s, const __bf16 *x, int M, hipStream_t st, floa
 
 // Loss and gradients (internal layout, into s->g) for one chunk.
 int gradient_chunk(rod_surrogate *s, const __bf16 *x, const float *t, const float *mask, int M,
-                   hipStream_t st)
+                   hipStream_t st, float *loss_out = nullptr)
 {
     int rc = forward_chunk(s, x, M, st);
     if (rc) return rc;
@@ -172,27 +195,28 @@ int gradient_chunk(rod_surrogate *s, const __bf16 *x, const float *t, const floa
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("mse_grad: ") + hipGetErrorString(e));
     // loss = sum(mask * e^2) / (M * 12): masked entries still count in the mean
     e = mlpk::sum_partials(s->partial, mlpk::mse_partials(M, NOUT_LD), 1.0f / (float)(M * ROD_SURROGATE_OUTPUTS),
-                           s->loss, st);
+                           loss_out ? loss_out : s->loss, st);
     if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("loss: ") + hipGetErrorString(e));
     const float *dZ = s->dY;
     int ldz = NOUT_LD;
     float *bufs[2] = {s->dZa, s->dZb};
     for (int l = NL - 1; l >= 0; --l) {
-        // dW_l = A_{l-1}^T dZ_l ; db_l = colsum(dZ_l)
+        // [dW_l; db_l] = [A_{l-1}, 1]^T dZ_l: a row of ones appended to A^T gives the
+        // column sums of dZ_l, which land right after dW_l (the bias follows the
+        // weights in the internal layout)
         mlpk::GemmArgs a{};
         a.A = l > 0 ? (const void *)s->Ab[l - 1] : (const void *)x;
         a.lda = KDIM[l];
         a.B = dZ;
         a.ldb = ldz;
-        a.M = KDIM[l];
+        a.M = KDIM[l] + 1;
+        a.ones_row = KDIM[l];
         a.N = NPAD[l];
         a.K = M;
         a.C = s->g + s->lay.w[l];
         a.ldc = NPAD[l];
         e = mlpk::gemm_backward_weight(a, s->splitw, SPLIT_FLOATS, st);
         if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("dW gemm: ") + hipGetErrorString(e));
-        e = mlpk::colsum(dZ, M, NPAD[l], ldz, s->g + s->lay.b[l], s->splitw, SPLIT_FLOATS, st);
-        if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("db: ") + hipGetErrorString(e));
         if (l == 0) break;
         // dZ_{l-1} = (dZ_l W_l^T) * silu'(Z_{l-1})
         mlpk::GemmArgs b{};
@@ -693,10 +717,7 @@ int rod_surrogate_train_step(rod_surrogate *s, const void *x, const float *t, co
     hipStream_t st = (hipStream_t)stream;
     int rc = gradient_chunk(s, (const __bf16 *)x, t, mask, (int)M, st);
     if (rc) return rc;
-    s->adam_t += 1;
-    hipError_t e = mlpk::adam(s->w, s->m, s->v, s->g, s->lay.total, lr, 0.9f, 0.999f, 1e-8f, s->adam_t, st);
-    if (e != hipSuccess) return sfail(ROD_EDEVICE, std::string("adam: ") + hipGetErrorString(e));
-    rc = refresh_bf16(s, st);
+    rc = adam_step(s, lr, st);
     if (rc) return rc;
     if (loss) {
         SHIPCHK(hipMemcpyAsync(loss, s->loss, 4, hipMemcpyDeviceToHost, st));
@@ -889,13 +910,10 @@ int rod_surrogate_train(rod_surrogate *s, rod_batch *b, const rod_train_desc *d,
         TRYH(hipMemcpyAsync(idx, tr.data(), n_tr * 8, hipMemcpyHostToDevice, st));
         for (int64_t bi = 0; bi < steps_per_epoch; ++bi, ++step) {
             TRYH(surk::gather_rows(F, T, Mk, idx + bi * B, B, mux, isdx, mut, sdt, xb, tb, mb, st));
-            TRY(gradient_chunk(s, xb, tb, mb, B, st));
+            TRY(gradient_chunk(s, xb, tb, mb, B, st, lhist + step));
             const double ph = total_steps > 1 ? (double)step / (double)(total_steps - 1) : 1.0;
             const float lr = (float)(d->lr_min + 0.5 * (d->lr - d->lr_min) * (1.0 + std::cos(M_PI * ph)));
-            s->adam_t += 1;
-            TRYH(mlpk::adam(s->w, s->m, s->v, s->g, s->lay.total, lr, 0.9f, 0.999f, 1e-8f, s->adam_t, st));
-            TRY(refresh_bf16(s, st));
-            TRYH(hipMemcpyAsync(lhist + step, s->loss, 4, hipMemcpyDeviceToDevice, st));
+            TRY(adam_step(s, lr, st));
         }
         TRYH(hipStreamSynchronize(st));   // the host index buffer is reused next epoch
     }

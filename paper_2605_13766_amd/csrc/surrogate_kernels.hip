@@ -413,17 +413,37 @@ __global__ void apply_elems_kernel(const WinArgs A, const float *y, int ldy, con
 }
 
 // ---------------------------------------------------------------- training rows
+// Minibatch rows idx[i] of the raw tables, standardised: 16 threads per row,
+// thread c < 12 moves features 8c..8c+7 (two 16-byte loads, one 16-byte store
+// of eight BF16 values), threads 12-14 four targets and four mask entries each.
 __global__ void gather_rows_kernel(const float *fraw, const float *traw, const float *mraw, const int64_t *idx,
                                    int64_t rows, const float *mu_x, const float *isd_x, const float *mu_t,
                                    const float *sd_t, __bf16 *x, float *t, float *m)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
+    typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = g >> 4;
+    const int c = (int)(g & 15);
+    if (i >= rows || c == 15) return;
     const int64_t s = idx[i];
-    for (int k = 0; k < N_FEAT; ++k) x[i * N_FEAT + k] = (__bf16)((fraw[s * N_FEAT + k] - mu_x[k]) * isd_x[k]);
-    for (int k = 0; k < N_OUT; ++k) {
-        t[i * N_OUT + k] = (traw[s * N_OUT + k] - mu_t[k]) / sd_t[k];
-        m[i * N_OUT + k] = mraw[s * N_OUT + k];
+    if (c < 12) {
+        const float4 *src = reinterpret_cast<const float4 *>(fraw + s * N_FEAT + 8 * c);
+        const float4 a = src[0], b = src[1];
+        const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        bf16x8_t o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * c + j;
+            o[j] = (__bf16)((f[j] - mu_x[k]) * isd_x[k]);
+        }
+        *reinterpret_cast<bf16x8_t *>(x + i * N_FEAT + 8 * c) = o;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * (c - 12) + j;
+            t[i * N_OUT + k] = (traw[s * N_OUT + k] - mu_t[k]) / sd_t[k];
+            m[i * N_OUT + k] = mraw[s * N_OUT + k];
+        }
     }
 }
 
@@ -718,8 +738,8 @@ hipError_t gather_rows(const float *fraw, const float *traw, const float *mraw, 
                        const float *mu_x, const float *isd_x, const float *mu_t, const float *sd_t, __bf16 *x, float *t,
                        float *m, hipStream_t s)
 {
-    hipLaunchKernelGGL(gather_rows_kernel, blocks(rows), dim3(256), 0, s, fraw, traw, mraw, idx, rows, mu_x, isd_x, mu_t,
-                       sd_t, x, t, m);
+    hipLaunchKernelGGL(gather_rows_kernel, blocks(16 * rows), dim3(256), 0, s, fraw, traw, mraw, idx, rows, mu_x, isd_x,
+                       mu_t, sd_t, x, t, m);
     return hipGetLastError();
 }
 
