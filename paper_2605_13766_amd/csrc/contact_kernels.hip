@@ -8,7 +8,8 @@
 // friction).  One pass per step, before the step kernel's launch: bin the
 // nodes (positions after the coming half drift) into a wrapped uniform grid
 // with atomic counts, prefix-sum the counts, scatter the nodes into bucket
-// order, and let every node sum its contacts over the 27 buckets around it;
+// order (each bucket sorted by node id), and let every node sum its contacts
+// over the 27 buckets around it;
 // the step kernel adds the forces at its kick.
 #include "rod_internal.h"
 
@@ -217,6 +218,35 @@ __global__ void contact_scatter_kernel(const DevBatch<T> B, const ContactGrid G,
     G.sid[p] = (int32_t)id;
 }
 
+// The scatter leaves each bucket's nodes in the order their atomic ranks came
+// out, which can differ from run to run; sorting every bucket by node id makes
+// the order in which each node sums its contacts, and so the forces to the
+// last bit, independent of the run.  Buckets hold a few nodes: insertion sort
+// by the thread of the node that took rank 0 in the bucket (one per occupied
+// bucket; threads run over node ids, far fewer than buckets).
+__global__ void contact_sort_kernel(const ContactGrid G)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= G.nn || G.rank[id] != 0) return;
+    const int b = G.bucket[id];
+    const int32_t s = G.start[b], e = G.start[b + 1];
+    for (int32_t i = s + 1; i < e; ++i) {
+        const int32_t id = G.sid[i];
+        if (G.sid[i - 1] < id) continue;
+        const double4 a = G.spr[i], c = G.svr[i];
+        int32_t j = i - 1;
+        while (j >= s && G.sid[j] > id) {
+            G.sid[j + 1] = G.sid[j];
+            G.spr[j + 1] = G.spr[j];
+            G.svr[j + 1] = G.svr[j];
+            --j;
+        }
+        G.sid[j + 1] = id;
+        G.spr[j + 1] = a;
+        G.svr[j + 1] = c;
+    }
+}
+
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
 // around it: the walls' law between two spheres.  Threads take the nodes in
 // bucket order, so neighbouring threads read the same buckets and the sweep
@@ -299,6 +329,7 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
     hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb);
     hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb);
     hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+    hipLaunchKernelGGL(contact_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
     hipLaunchKernelGGL((contact_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
     return hipGetLastError();
 }
