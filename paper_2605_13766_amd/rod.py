@@ -277,14 +277,17 @@ class RodBatch:
         _check(lib().rod_energy_noalloc(self._h, _p(out), _stream_ptr(stream)))
         return out
 
-    def get_state(self, stream=None):
+    def get_state(self, stream=None, check=True):
+        """The state (host FP64 arrays) and time.  check=False returns it even
+        when a rod has been flagged non-finite (the arrays are filled first)."""
         pos = np.empty((self.n_nodes, 3))
         vel = np.empty((self.n_nodes, 3))
         dr = np.empty((self.n_elements, 3, 3))
         om = np.empty((self.n_elements, 3))
         t = C.c_double()
-        _check(lib().rod_get_state(self._h, _p(pos), _p(vel), _p(dr), _p(om), C.byref(t),
-                                   _stream_ptr(stream)))
+        rc = lib().rod_get_state(self._h, _p(pos), _p(vel), _p(dr), _p(om), C.byref(t), _stream_ptr(stream))
+        if check or rc != ROD_ENONFINITE:
+            _check(rc)
         return pos, vel, dr, om, t.value
 
     def set_state(self, pos=None, vel=None, director=None, omega=None, t=0.0, stream=None):

@@ -224,7 +224,11 @@ def test_trained_network_gains_over_free_flight():
     (the same step with zero departures) after one coarse step and at most
     0.85 after four, and its median shear-energy error (relative to the
     rod's mechanical energy) at most 0.05 of free flight's, which leaves
-    positions and frames inconsistent; with every rod judged every 8 steps at
+    positions and frames inconsistent.  Two more baselines: persistence (the
+    state left as it is: the trained step's median position error at most 0.1
+    of it) and the plain integrator taking the coarse step itself (dt = 32 h,
+    far beyond its stability limit: it must not come out better than the
+    trained step; it blows up).  With every rod judged every 8 steps at
     the 1e-3 / 1e-5 / 5e-2 thresholds, every rod ends within 1e-3 of the plain
     result after 16 coarse steps (512 plain steps) and not every rod needed
     the fallback."""
@@ -242,19 +246,32 @@ def test_trained_network_gains_over_free_flight():
     _, ref = _rods(256, seed_shift=17)
     s0 = rod.Surrogate(k_substeps=K, seed=0)
     zero = torch.zeros((s0.n_windows(ff), 12), dtype=torch.float32, device="cuda")
+    # persistence: the start state itself; the plain step at dt = 32 h from it
+    p0, v0, d0, w0, t0 = ref.get_state()
+    inp32 = inp.copy()
+    inp32.dt = inp.dt * K
+    big = rod.RodBatch(inp32, precision="f32")
+    big.set_state(p0, v0, d0, w0, t=t0)
     done = 0
-    res, shear = {}, {}
+    res, shear, persist, plain32 = {}, {}, {}, {}
     for H in (1, 4):
         s.step(net, H - done, **NO_JUDGE)
         for _ in range(H - done):
             s0.apply(ff, zero)
+        big.step(H - done)
         ref.step((H - done) * K)
         done = H
         res[H] = (np.median(_pos_err(ref, net)), np.median(_pos_err(ref, ff)))
+        pr = ref.get_state()[0].reshape(-1, N + 1, 3)
+        persist[H] = float(np.median(np.linalg.norm(pr - p0.reshape(-1, N + 1, 3), axis=2).max(axis=1) / L))
+        pb = big.get_state(check=False)[0].reshape(-1, N + 1, 3)
+        eb = np.linalg.norm(pb - pr, axis=2).max(axis=1) / L
+        plain32[H] = float(np.median(np.where(np.isfinite(eb), eb, np.inf)))
         Er, En, Ef = ref.energy(), net.energy(), ff.energy()
         mech = Er[:, :4].sum(axis=1)
         shear[H] = tuple(np.median(np.abs(E[:, 2] - Er[:, 2]) / mech) for E in (En, Ef))
         print("H", H, "position: trained", res[H][0], "free flight", res[H][1], "ratio", res[H][0] / res[H][1],
+              "persistence", persist[H], "plain at dt = 32 h", plain32[H],
               "| shear energy: trained", shear[H][0], "free flight", shear[H][1])
     _, j = _rods(256, seed_shift=17)
     _, jr = _rods(256, seed_shift=17)
@@ -265,10 +282,12 @@ def test_trained_network_gains_over_free_flight():
     print("judged run", st, "end-to-end max", e.max(), "median", np.median(e))
     assert res[1][0] <= 0.6 * res[1][1]
     assert res[4][0] <= 0.85 * res[4][1]
+    assert res[1][0] <= 0.1 * persist[1] and res[4][0] <= 0.1 * persist[4]
+    assert not plain32[4] < res[4][0]
     assert shear[4][0] <= 0.05 * shear[4][1]
     assert e.max() <= 1e-3
     assert st["judge_windows"] == 2 and st["rods_plain"] < 256
-    for h in (s, s0, net, ff, ref, j, jr):
+    for h in (s, s0, net, ff, ref, j, jr, big):
         h.close()
 
 

@@ -76,10 +76,20 @@ def test_collect_targets_parity():
     b.close()
 
 
-def test_apply_parity():
+@pytest.mark.parametrize("ends", ["clamped base", "mixed ends"])
+def test_apply_parity(ends):
+    """Random outputs applied on the GPU against the oracle's apply: carpet rods
+    (clamped base), and rods whose ends are free-free, base-clamped,
+    tip-clamped and clamped at both ends (every way the nodes are rebuilt
+    from the edges).  Positions are also held to 1e-6 of the rod length."""
     import torch
     from paper_2605_13766_amd import rod
-    inp, b, (s0, t0) = _batch(12, 64, 1000)
+    inp = W.surrogate_training(n_rods=12, n=64)
+    if ends == "mixed ends":
+        inp.bc_start = np.array([0, 1, 0, 1] * 3, np.int32)
+        inp.bc_end = np.array([0, 0, 1, 1] * 3, np.int32)
+    s0, t0 = oracle_run(inp, 1000)
+    b = gpu_batch(inp, s0, t0)
     s = rod.Surrogate(k_substeps=K, seed=0)
     Wn = s.n_windows(b)
     rng = np.random.default_rng(3)
@@ -91,6 +101,9 @@ def test_apply_parity():
     ref = S.apply_deltas(inp, s0, D.astype(np.float32).astype(np.float64), K)
     for a, r in zip(s1, ref):
         _close(a.reshape(len(a), -1), r.reshape(len(r), -1))
+    perr = np.abs(s1[0] - ref[0]).max() / 0.01
+    print(ends, "position error / L", perr)
+    assert perr < 1e-6
     s.close()
     b.close()
 
