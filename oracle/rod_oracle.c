@@ -79,6 +79,19 @@
  *     half of each pair's penalty potential goes to each rod's W_ext.  A rod
  *     does not touch itself.  (Crossing rods whose elements are longer than
  *     their diameters can pass between nodes.)
+ *   - segment contact (rod_contact = 2; the same sources): every element is a
+ *     capsule, the segment between its two nodes dilated by the rod's radius.
+ *     Two capsules touch when the distance between the closest points P (on
+ *     element a, parameter s) and Q (on element b, parameter t) of their
+ *     segments is below the sum of the radii; element a then feels the wall
+ *     law with that overlap, the normal from Q to P and the relative velocity
+ *     of the two points (node velocities interpolated with the same
+ *     parameters), and the force is shared by its two nodes as (1 - s) and s
+ *     (so its moment about any point is that of the force at P).  Elements of
+ *     different rods touch, and so do elements of one rod when the rest lengths
+ *     of the elements between them add up to at least the rod's diameter (in
+ *     the straight rest state such capsules do not overlap; closer ones always
+ *     would).  Half of each pair's penalty potential goes to each rod.
  * Rods joined by connections or in contact are advanced together (one batch
  * step), the coupling forces from the state of all rods at the kick time.
  *
@@ -172,7 +185,8 @@ typedef struct {
     int32_t n_walls;                 /* planar boundaries */
     const double *wall;              /* [n_walls][4]: unit normal nx ny nz, offset d (the wall is n.x = d) */
     double wall_k, wall_c, wall_mu, wall_vslip;   /* contact stiffness, damping, friction, slip speed */
-    int32_t rod_contact;             /* 1: contact between nodes of different rods (same law) */
+    int32_t rod_contact;             /* 1: contact between nodes of different rods (same law); 2: capsule
+                                        contact between elements, of different rods and of one rod */
     const double *origin;            /* FP32 build: [R][3] rod origins (first node at creation); else unused */
 } orc_rods;
 
@@ -722,13 +736,129 @@ static double sphere_force(const orc_rods *p, const double *xa, const double *va
     return delta;
 }
 
+/* Closest points of the segments p0 + s (p1 - p0) and q0 + t (q1 - q0),
+ * s, t in [0, 1] (both of positive length): the minimiser of the convex
+ * quadratic |p(s) - q(t)|^2 over the unit square.  The unconstrained
+ * stationary point's s is clamped to [0, 1], t is the best t for that s,
+ * clamped, and when that clamp acts s is re-solved for the clamped t; for
+ * parallel segments (no unique stationary point) s starts at 0. */
+static void segment_closest(const double *p0, const double *p1, const double *q0, const double *q1, double *s,
+                            double *t)
+{
+    const double d1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    const double d2[3] = {q1[0] - q0[0], q1[1] - q0[1], q1[2] - q0[2]};
+    const double r[3] = {p0[0] - q0[0], p0[1] - q0[1], p0[2] - q0[2]};
+    const double a = dot3d(d1, d1), e = dot3d(d2, d2), b = dot3d(d1, d2);
+    const double c = dot3d(d1, r), f = dot3d(d2, r);
+    const double den = a * e - b * b;   /* >= 0; 0 for parallel segments */
+    double ss = 0.0;
+    if (den > 1e-12 * a * e) {
+        ss = (b * f - c * e) / den;
+        ss = ss < 0.0 ? 0.0 : (ss > 1.0 ? 1.0 : ss);
+    }
+    double tt = (b * ss + f) / e;
+    if (tt < 0.0) {
+        tt = 0.0;
+        ss = -c / a;
+        ss = ss < 0.0 ? 0.0 : (ss > 1.0 ? 1.0 : ss);
+    } else if (tt > 1.0) {
+        tt = 1.0;
+        ss = (b - c) / a;
+        ss = ss < 0.0 ? 0.0 : (ss > 1.0 ? 1.0 : ss);
+    }
+    *s = ss;
+    *t = tt;
+}
+
+/* Exported for the tests: out[0] = s, out[1] = t of segment_closest. */
+void orc_segment_closest(const double *p0, const double *p1, const double *q0, const double *q1, double *out)
+{
+    segment_closest(p0, p1, q0, q1, &out[0], &out[1]);
+}
+
+/* Elements i < j of rod r touch each other only when the rest lengths of the
+ * elements strictly between them add up to at least the rod's diameter. */
+static int self_pair_allowed(const orc_rods *p, const int64_t *eo, int r, int i, int j)
+{
+    if (j < i) { const int k = i; i = j; j = k; }
+    if (j - i < 2) return 0;
+    double gap = 0.0;
+    for (int k = i + 1; k < j; ++k) gap += (double)p->rest_length[eo[r] + k];
+    return gap >= 2.0 * (double)p->radius[r];
+}
+
+/* Capsule contact (rod_contact = 2) at the current state, brute force over
+ * every ordered pair of elements (element a of rod ra against element b of
+ * rod rb): the force on element a goes to its nodes as (1 - s) and s; with pot
+ * a quarter of k delta^2 per ordered pair to rod ra.  Each pair's closest
+ * points and force are evaluated in one fixed order, the element first in
+ * (rod, element) order taking the part of a, and the other element receives
+ * the exact negative: the closest-point routine is not symmetric in rounding
+ * (nor in its choice for parallel segments), and the two elements of a pair
+ * must feel opposite forces for momentum to be conserved. */
+static void segment_contact_forces(const orc_rods *p, const double *pos, const double *vel, double *fc,
+                                   const int64_t *no, double *pot)
+{
+    const int R = p->n_rods;
+    int64_t *eo = malloc((size_t)R * sizeof(int64_t));
+    if (!eo) return;
+    int64_t e = 0;
+    for (int r = 0; r < R; ++r) {
+        eo[r] = e;
+        e += p->n_elems[r];
+    }
+    for (int ra = 0; ra < R; ++ra)
+        for (int i = 0; i < p->n_elems[ra]; ++i) {
+            const int64_t a0 = no[ra] + i, a1 = a0 + 1;
+            double f0[3] = {0.0, 0.0, 0.0}, f1[3] = {0.0, 0.0, 0.0};
+            for (int rb = 0; rb < R; ++rb)
+                for (int j = 0; j < p->n_elems[rb]; ++j) {
+                    if (rb == ra && !self_pair_allowed(p, eo, ra, i, j)) continue;
+                    const int64_t b0 = no[rb] + j, b1 = b0 + 1;
+                    /* u: the pair's first element in (rod, element) order, w the other */
+                    const int a_first = ra < rb || (ra == rb && i < j);
+                    const int64_t u0 = a_first ? a0 : b0, u1 = u0 + 1, w0 = a_first ? b0 : a0, w1 = w0 + 1;
+                    const double ru = p->radius[a_first ? ra : rb], rw = p->radius[a_first ? rb : ra];
+                    double su, sw;
+                    segment_closest(&pos[3 * u0], &pos[3 * u1], &pos[3 * w0], &pos[3 * w1], &su, &sw);
+                    double xu[3], xw[3], vu[3], vw[3], f[3] = {0.0, 0.0, 0.0};
+                    for (int k = 0; k < 3; ++k) {
+                        xu[k] = pos[3 * u0 + k] + su * (pos[3 * u1 + k] - pos[3 * u0 + k]);
+                        xw[k] = pos[3 * w0 + k] + sw * (pos[3 * w1 + k] - pos[3 * w0 + k]);
+                        vu[k] = (1.0 - su) * vel[3 * u0 + k] + su * vel[3 * u1 + k];
+                        vw[k] = (1.0 - sw) * vel[3 * w0 + k] + sw * vel[3 * w1 + k];
+                    }
+                    const double delta = sphere_force(p, xu, vu, ru, xw, vw, rw, f);   /* force on u */
+                    if (pot && delta > 0.0) pot[ra] += 0.25 * p->wall_k * delta * delta;
+                    const double s = a_first ? su : sw;
+                    if (!a_first)
+                        for (int k = 0; k < 3; ++k) f[k] = -f[k];
+                    for (int k = 0; k < 3; ++k) {
+                        f0[k] += (1.0 - s) * f[k];
+                        f1[k] += s * f[k];
+                    }
+                }
+            if (fc)
+                for (int k = 0; k < 3; ++k) {
+                    fc[3 * a0 + k] += f0[k];
+                    fc[3 * a1 + k] += f1[k];
+                }
+        }
+    free(eo);
+}
+
 /* Rod-rod contact forces at the current state, added to fc [N_n][3] (if
- * non-NULL): every ordered pair of nodes of different rods, by brute force.
- * With pot (non-NULL, [R]) adds a quarter of k delta^2 per ordered pair to
- * the first node's rod (half of each pair's potential to each rod). */
+ * non-NULL): every ordered pair of nodes of different rods, by brute force
+ * (capsule contact between elements when rod_contact = 2).  With pot
+ * (non-NULL, [R]) adds a quarter of k delta^2 per ordered pair to the first
+ * node's rod (half of each pair's potential to each rod). */
 static void contact_forces(const orc_rods *p, const double *pos, const double *vel, double *fc,
                            const int64_t *no, double *pot)
 {
+    if (p->rod_contact == 2) {
+        segment_contact_forces(p, pos, vel, fc, no, pot);
+        return;
+    }
     const int R = p->n_rods;
     for (int ra = 0; ra < R; ++ra)
         for (int i = 0; i <= p->n_elems[ra]; ++i) {

@@ -131,6 +131,7 @@ def lib():
         L.orc_energy.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
         L.orc_energy.restype = C.c_int
         L.orc_rodrigues.argtypes = [_dp, _dp]
+        L.orc_segment_closest.argtypes = [_dp, _dp, _dp, _dp, _dp]
         L.orc_logmap.argtypes = [_dp, _dp]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -315,6 +316,14 @@ def logmap(R):
     RR = _d(np.asarray(R, float).reshape(9))
     lib().orc_logmap(_ptr(RR), _ptr(u))
     return u
+
+
+def segment_closest(p0, p1, q0, q1):
+    """Parameters (s, t) of the closest points of two segments (the oracle's routine)."""
+    out = np.zeros(2)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (p0, p1, q0, q1)]
+    lib().orc_segment_closest(*[_ptr(x) for x in a], _ptr(out))
+    return float(out[0]), float(out[1])
 
 
 def max_threads():
