@@ -837,21 +837,31 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             // LDS, restarted at each rod's first lane; its additions depend only
             // on the element index, so every tile width gives the same bits).
             // Afterwards d holds node i's position and t node n's (last lane).
-            const T e3[3] = {d0, d1, d2};
-            T lf[3];
-            from_left<W>(e3, lf, lxa, wave, wl);
-            T p0 = first_o ? t0 : lf[0], p1 = first_o ? t1 : lf[1], p2 = first_o ? t2 : lf[2];
-            T *const sc = cst;   // the constant columns are not read any more
-            for (int k = 1; k < TL; k <<= 1) {
-                __syncthreads();
-                sc[lane] = p0; sc[TL + lane] = p1; sc[2 * TL + lane] = p2;
-                __syncthreads();
-                if (i_o >= k) {
-                    p0 += sc[lane - k]; p1 += sc[TL + lane - k]; p2 += sc[2 * TL + lane - k];
+            // Launches of a few substeps (contact batches take one) skip the sum:
+            // t, node i's position drifted with v_i, differs from the edges' sum
+            // by a few roundings only, and the sum's barriers cost about as much
+            // as the substep itself.  (n_sub is the same for the whole grid.)
+            if (n_sub <= 4) {
+                const T n0 = t0 + d0, n1 = t1 + d1, n2 = t2 + d2;
+                d0 = t0; d1 = t1; d2 = t2;
+                t0 = n0; t1 = n1; t2 = n2;
+            } else {
+                const T e3[3] = {d0, d1, d2};
+                T lf[3];
+                from_left<W>(e3, lf, lxa, wave, wl);
+                T p0 = first_o ? t0 : lf[0], p1 = first_o ? t1 : lf[1], p2 = first_o ? t2 : lf[2];
+                T *const sc = cst;   // the constant columns are not read any more
+                for (int k = 1; k < TL; k <<= 1) {
+                    __syncthreads();
+                    sc[lane] = p0; sc[TL + lane] = p1; sc[2 * TL + lane] = p2;
+                    __syncthreads();
+                    if (i_o >= k) {
+                        p0 += sc[lane - k]; p1 += sc[TL + lane - k]; p2 += sc[2 * TL + lane - k];
+                    }
                 }
+                t0 = p0 + d0; t1 = p1 + d1; t2 = p2 + d2;
+                d0 = p0; d1 = p1; d2 = p2;
             }
-            t0 = p0 + d0; t1 = p1 + d1; t2 = p2 + d2;
-            d0 = p0; d1 = p1; d2 = p2;
         }
 
         if (act_o) {
