@@ -179,12 +179,26 @@ typedef struct {
      * the pair's forces are equal and opposite); half of each pair's penalty
      * potential 1/2 wall_k delta^2 joins each rod's W_ext.  A rod does not
      * touch itself.  Pairs are found every step by a hashed uniform grid over
-     * the node positions (cells of twice the largest radius), so each step is
-     * one launch sequence: substeps must be 0 or 1 (one step per launch);
-     * FP32 batches sum their node positions along each rod in FP64 for the
-     * grid; forces are summed in the order the grid lists the pairs, which
-     * may differ between runs at round-off. */
-    int32_t rod_contact;             /* 0 or 1 */
+     * the node positions (cells of twice the largest radius).
+     * With rod_contact = 2 every element is a capsule, the segment between
+     * its two nodes dilated by its rod's radius: the same law acts between the
+     * closest points of two elements' segments (the point velocities
+     * interpolated along each element), and the force on an element goes to
+     * its nodes in the shares (1 - s) and s of the closest point's parameter s
+     * along it.  Each pair is evaluated once, in (rod, element) order, and the
+     * other element takes the exact negative, so the pair's forces cancel
+     * bit for bit.  Elements of one rod touch when the rest lengths of the
+     * elements between them add up to at least the diameter (self-contact of
+     * a folded rod).  The grid bins element midpoints in cells of 1.25 times
+     * the longest rest length plus twice the largest radius: contacts of
+     * elements stretched by more than a quarter of their rest length can be
+     * missed.
+     * Both modes: each step is one launch sequence, so substeps must be 0 or
+     * 1 (one step per launch); FP32 batches sum their node positions along
+     * each rod in FP64 for the grid; each grid cell's entries are sorted by
+     * node (element) before the forces are summed, so runs are bitwise
+     * repeatable and independent of tile_waves. */
+    int32_t rod_contact;             /* 0, 1 (node spheres) or 2 (element capsules) */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -208,7 +222,7 @@ typedef struct {
  * node outside the batch, joining a node to itself, or with k, c or l0
  * negative or not finite; n_walls outside [0, ROD_MAX_WALLS], a wall normal
  * not of unit length within 1e-9, wall_k, wall_c or wall_mu negative,
- * wall_vslip <= 0, rod_contact not 0 or 1, rod_contact with substeps > 1),
+ * wall_vslip <= 0, rod_contact not 0, 1 or 2, rod_contact with substeps > 1),
  * ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the
  * longest rod or connected group).
  * A time step above the explicit stability estimate is reported through

@@ -60,7 +60,7 @@ __device__ inline bool contact_node(const DevBatch<float> &B, const ContactGrid 
         rod = (int)(id - NS);
         for (int a = 0; a < 3; ++a) v[a] = (double)B.tail[(TVX + a) * B.n_rods + rod];
     }
-    for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nn + id];
+    for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nid + id];
     return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
 }
 
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void contact_positions_kernel(const DevBatch<f
     const int rod = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (rod >= B.n_rods) return;   // whole waves leave together
-    const int64_t NS = B.n_slots, nn = G.nn, R = B.n_rods;
+    const int64_t NS = B.n_slots, nn = G.nid, R = B.n_rods;
     const int n = B.rod_n[rod];
     const int64_t s0 = B.rod_slot[rod];
     double carry[3];
@@ -305,9 +305,248 @@ __global__ void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, i
     }
     const int64_t id = G.sid[p0];
     G.force[id] = f0;
-    G.force[nn + id] = f1;
-    G.force[2 * nn + id] = f2;
+    G.force[G.nid + id] = f1;
+    G.force[2 * G.nid + id] = f2;
     G.pot[id] = pot;
+}
+
+// ---------------------------------------------------------------- capsules
+// Mode 2: every element is a capsule, the segment between its nodes A (node
+// i) and B (node i + 1) dilated by the rod's radius.  Elements are binned by
+// their midpoints in cells of the longest element the grid allows for plus
+// twice the largest radius, so the midpoints of two touching elements are at
+// most one cell apart per axis.
+
+// Element (slot) s: endpoints and velocities `drift` seconds ahead; false for
+// padding slots and non-finite positions.
+template <typename T>
+__device__ inline bool contact_segment(const DevBatch<T> &B, const ContactGrid &G, int64_t s, double drift, int &rod,
+                                       int &elem, double a[3], double b[3], double va[3], double vb[3])
+{
+    rod = B.slot_rod[s];
+    if (rod < 0) return false;
+    elem = B.slot_idx[s];
+    const int64_t idb = elem + 1 < B.rod_n[rod] ? s + 1 : B.n_slots + rod;
+    int r2;
+    const bool oka = contact_node(B, G, s, drift, r2, a, va);
+    const bool okb = contact_node(B, G, idb, drift, r2, b, vb);
+    return oka && okb;
+}
+
+// Closest points p0 + s (p1 - p0), q0 + t (q1 - q0) of two segments of
+// positive length, s, t in [0, 1]: the convex quadratic's stationary s,
+// clamped; the best t for it, clamped; s again for a clamped t; s from 0 for
+// parallel segments.
+__device__ inline void closest_params(const double p0[3], const double p1[3], const double q0[3], const double q1[3],
+                                      double &s, double &t)
+{
+    const double d1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    const double d2[3] = {q1[0] - q0[0], q1[1] - q0[1], q1[2] - q0[2]};
+    const double r[3] = {p0[0] - q0[0], p0[1] - q0[1], p0[2] - q0[2]};
+    const double a = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+    const double e = d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2];
+    const double b = d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2];
+    const double c = d1[0] * r[0] + d1[1] * r[1] + d1[2] * r[2];
+    const double f = d2[0] * r[0] + d2[1] * r[1] + d2[2] * r[2];
+    const double den = a * e - b * b;
+    double ss = 0.0;
+    if (den > 1e-12 * a * e) ss = fmin(fmax((b * f - c * e) / den, 0.0), 1.0);
+    double tt = (b * ss + f) / e;
+    if (tt < 0.0) {
+        tt = 0.0;
+        ss = fmin(fmax(-c / a, 0.0), 1.0);
+    } else if (tt > 1.0) {
+        tt = 1.0;
+        ss = fmin(fmax((b - c) / a, 0.0), 1.0);
+    }
+    s = ss;
+    t = tt;
+}
+
+template <typename T>
+__global__ void seg_bin_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= G.nn) return;
+    int rod, elem;
+    double a[3], b[3], va[3], vb[3];
+    if (!contact_segment(B, G, s, drift, rod, elem, a, b, va, vb)) {
+        // out of the grid this pass: its nodes take no shares from it
+        G.rank[s] = -1;
+        for (int k = 0; k < 6; ++k) G.fseg[k * G.nn + s] = 0.0;
+        G.pot[s] = 0.0;
+        return;
+    }
+    const int bk = (wrap_cell(cell_of(0.5 * (a[2] + b[2]), G.org[2], G.inv_cell), G.gz) * G.gy
+                    + wrap_cell(cell_of(0.5 * (a[1] + b[1]), G.org[1], G.inv_cell), G.gy)) * G.gx
+                 + wrap_cell(cell_of(0.5 * (a[0] + b[0]), G.org[0], G.inv_cell), G.gx);
+    G.bucket[s] = bk;
+    G.rank[s] = atomicAdd(&G.count[bk], 1);
+}
+
+template <typename T>
+__global__ void seg_scatter_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= G.nn) return;
+    const int32_t r = G.rank[s];
+    if (r < 0) return;
+    int rod, elem;
+    double a[3], b[3], va[3], vb[3];
+    contact_segment(B, G, s, drift, rod, elem, a, b, va, vb);
+    const int64_t p = G.start[G.bucket[s]] + r;
+    G.sca[p] = make_double4(a[0], a[1], a[2], B.rod_rad[rod]);
+    G.scb[p] = make_double4(b[0], b[1], b[2], (double)rod);
+    G.sva[p] = make_double4(va[0], va[1], va[2], (double)elem);
+    G.svb[p] = make_double4(vb[0], vb[1], vb[2], (double)G.next_allowed[s]);
+    G.sid[p] = (int32_t)s;
+}
+
+// as contact_sort_kernel, for the four segment records
+__global__ void seg_sort_kernel(const ContactGrid G)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= G.nn || G.rank[id] != 0) return;
+    const int bk = G.bucket[id];
+    const int32_t s = G.start[bk], e = G.start[bk + 1];
+    for (int32_t i = s + 1; i < e; ++i) {
+        const int32_t key = G.sid[i];
+        if (G.sid[i - 1] < key) continue;
+        const double4 r0 = G.sca[i], r1 = G.scb[i], r2 = G.sva[i], r3 = G.svb[i];
+        int32_t j = i - 1;
+        while (j >= s && G.sid[j] > key) {
+            G.sid[j + 1] = G.sid[j];
+            G.sca[j + 1] = G.sca[j];
+            G.scb[j + 1] = G.scb[j];
+            G.sva[j + 1] = G.sva[j];
+            G.svb[j + 1] = G.svb[j];
+            --j;
+        }
+        G.sid[j + 1] = key;
+        G.sca[j + 1] = r0;
+        G.scb[j + 1] = r1;
+        G.sva[j + 1] = r2;
+        G.svb[j + 1] = r3;
+    }
+}
+
+// Each element sums its contacts over the 27 buckets around its midpoint.  A
+// pair's closest points and force are evaluated in one fixed order (the
+// element first in (rod, element) order takes the part of a), and the other
+// element takes the exact negative, so the two feel opposite forces to the
+// last bit.  Elements of one rod touch only from `next` on.  The force on the
+// element goes to its nodes as (1 - s) and s; a quarter of k delta^2 per
+// ordered pair is the element's potential share.
+template <typename T>
+__global__ void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
+{
+    const int64_t p0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p0 >= G.start[nb]) return;
+    const double4 ua = G.sca[p0], ub = G.scb[p0], uva = G.sva[p0], uvb = G.svb[p0];
+    const int rod = (int)ub.w, elem = (int)uva.w, next = (int)uvb.w;
+    const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
+    const double ra = ua.w;
+    const double mx = 0.5 * (ua.x + ub.x), my = 0.5 * (ua.y + ub.y), mz = 0.5 * (ua.z + ub.z);
+    const double hl = 0.5 * sqrt((ub.x - ua.x) * (ub.x - ua.x) + (ub.y - ua.y) * (ub.y - ua.y)
+                                 + (ub.z - ua.z) * (ub.z - ua.z));
+    double fa0 = 0, fa1 = 0, fa2 = 0, fb0 = 0, fb1 = 0, fb2 = 0, pot = 0;
+    const int64_t cx = cell_of(mx, G.org[0], G.inv_cell), cy = cell_of(my, G.org[1], G.inv_cell),
+                  cz = cell_of(mz, G.org[2], G.inv_cell);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int row = (wrap_cell(cz + dz, G.gz) * G.gy + wrap_cell(cy + dy, G.gy)) * G.gx;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int bk = row + wrap_cell(cx + dx, G.gx);
+                const int32_t p1 = G.start[bk + 1];
+                for (int32_t p = G.start[bk]; p < p1; ++p) {
+                    if (p == p0) continue;
+                    const double4 qa = G.sca[p], qb = G.scb[p];
+                    // bounding spheres of the two capsules
+                    const double nx = 0.5 * (qa.x + qb.x) - mx, ny = 0.5 * (qa.y + qb.y) - my,
+                                 nz = 0.5 * (qa.z + qb.z) - mz;
+                    const double ql = 0.5 * sqrt((qb.x - qa.x) * (qb.x - qa.x) + (qb.y - qa.y) * (qb.y - qa.y)
+                                                 + (qb.z - qa.z) * (qb.z - qa.z));
+                    const double reach = hl + ql + ra + qa.w;
+                    if (!(nx * nx + ny * ny + nz * nz < reach * reach)) continue;
+                    const int qrod = (int)qb.w;
+                    const double4 qva = G.sva[p], qvb = G.svb[p];
+                    const int qelem = (int)qva.w;
+                    if (qrod == rod) {
+                        const bool allowed = elem < qelem ? qelem >= next : elem >= (int)qvb.w;
+                        if (!allowed) continue;
+                    }
+                    const bool first = rod < qrod || (rod == qrod && elem < qelem);
+                    // u: the pair's first element, w: the other
+                    const double u0[3] = {first ? ua.x : qa.x, first ? ua.y : qa.y, first ? ua.z : qa.z};
+                    const double u1[3] = {first ? ub.x : qb.x, first ? ub.y : qb.y, first ? ub.z : qb.z};
+                    const double w0[3] = {first ? qa.x : ua.x, first ? qa.y : ua.y, first ? qa.z : ua.z};
+                    const double w1[3] = {first ? qb.x : ub.x, first ? qb.y : ub.y, first ? qb.z : ub.z};
+                    const double4 vu0 = first ? uva : qva, vu1 = first ? uvb : qvb;
+                    const double4 vw0 = first ? qva : uva, vw1 = first ? qvb : uvb;
+                    const double ru = first ? ra : qa.w, rw = first ? qa.w : ra;
+                    double su, sw;
+                    closest_params(u0, u1, w0, w1, su, sw);
+                    const double pu[3] = {u0[0] + su * (u1[0] - u0[0]), u0[1] + su * (u1[1] - u0[1]),
+                                          u0[2] + su * (u1[2] - u0[2])};
+                    const double pw[3] = {w0[0] + sw * (w1[0] - w0[0]), w0[1] + sw * (w1[1] - w0[1]),
+                                          w0[2] + sw * (w1[2] - w0[2])};
+                    const double e0 = pu[0] - pw[0], e1 = pu[1] - pw[1], e2 = pu[2] - pw[2];
+                    const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    const double delta = ru + rw - dist;
+                    if (!(delta > 0.0)) continue;
+                    pot += 0.25 * k * delta * delta;
+                    if (!(dist > 0.0)) continue;   // the segments cross: no direction
+                    const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
+                    const double r0 = ((1.0 - su) * vu0.x + su * vu1.x) - ((1.0 - sw) * vw0.x + sw * vw1.x);
+                    const double r1 = ((1.0 - su) * vu0.y + su * vu1.y) - ((1.0 - sw) * vw0.y + sw * vw1.y);
+                    const double r2 = ((1.0 - su) * vu0.z + su * vu1.z) - ((1.0 - sw) * vw0.z + sw * vw1.z);
+                    const double vn = n0 * r0 + n1 * r1 + n2 * r2;
+                    const double fn = delta * (k - c * vn);
+                    if (!(fn > 0.0)) continue;
+                    const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
+                    const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+                    const double gf = mu * fn / (sp > vs ? sp : vs);
+                    double f0 = fn * n0 - gf * t0, f1 = fn * n1 - gf * t1, f2 = fn * n2 - gf * t2;   // on u
+                    double sp_ = su;
+                    if (!first) {
+                        f0 = -f0; f1 = -f1; f2 = -f2;
+                        sp_ = sw;
+                    }
+                    fa0 += (1.0 - sp_) * f0; fa1 += (1.0 - sp_) * f1; fa2 += (1.0 - sp_) * f2;
+                    fb0 += sp_ * f0; fb1 += sp_ * f1; fb2 += sp_ * f2;
+                }
+            }
+        }
+    const int64_t s = G.sid[p0], nn = G.nn;
+    G.fseg[s] = fa0; G.fseg[nn + s] = fa1; G.fseg[2 * nn + s] = fa2;
+    G.fseg[3 * nn + s] = fb0; G.fseg[4 * nn + s] = fb1; G.fseg[5 * nn + s] = fb2;
+    G.pot[s] = pot;
+}
+
+// Node forces from the elements' shares: node i of a rod takes element i's
+// A share and element i - 1's B share (node n: element n - 1's B share).
+template <typename T>
+__global__ void seg_nodes_kernel(const DevBatch<T> B, const ContactGrid G)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= G.nid) return;
+    const int64_t NS = B.n_slots, nn = G.nn;
+    int64_t sa = -1, sb = -1;   // elements whose A / B share lands here
+    if (id < NS) {
+        const int rod = B.slot_rod[id];
+        if (rod < 0) return;
+        sa = id;
+        if (B.slot_idx[id] > 0) sb = id - 1;
+    } else {
+        const int rod = (int)(id - NS);
+        sb = B.rod_slot[rod] + B.rod_n[rod] - 1;
+    }
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        if (sa >= 0) f[a] += G.fseg[a * nn + sa];
+        if (sb >= 0) f[a] += G.fseg[(3 + a) * nn + sb];
+        G.force[a * G.nid + id] = f[a];
+    }
 }
 
 template <typename T>
@@ -324,13 +563,23 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
         if (!g.xabs || !g.origin) return hipErrorInvalidValue;
         hipLaunchKernelGGL(contact_positions_kernel, dim3((b.n_rods + 3) / 4), dim3(256), 0, s, b, g, drift);
     }
-    hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+    const bool seg = g.mode == 2;
+    if (seg && (!g.sca || !g.fseg || !g.next_allowed)) return hipErrorInvalidValue;
+    if (seg) hipLaunchKernelGGL((seg_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+    else hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
     hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb);
     hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb);
     hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb);
-    hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
-    hipLaunchKernelGGL(contact_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
-    hipLaunchKernelGGL((contact_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
+    if (seg) {
+        hipLaunchKernelGGL((seg_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+        hipLaunchKernelGGL(seg_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
+        hipLaunchKernelGGL((seg_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
+        hipLaunchKernelGGL((seg_nodes_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g);
+    } else {
+        hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+        hipLaunchKernelGGL(contact_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
+        hipLaunchKernelGGL((contact_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
+    }
     return hipGetLastError();
 }
 

@@ -141,7 +141,9 @@ struct DevBatch {
 // counted, prefix-summed and scattered into bucket order; each node then sums
 // its contacts over its 27 neighbouring buckets.
 struct ContactGrid {
-    int64_t nn;        // node ids: n_slots + n_rods
+    int mode;          // 1: nodes as spheres; 2: elements as capsules (segments), self-contact included
+    int64_t nn;        // items binned: node ids n_slots + n_rods (mode 1), element slots n_slots (mode 2)
+    int64_t nid;       // node ids: n_slots + n_rods (the stride of force, pot and xabs)
     int gx, gy, gz;    // cells per axis of the wrapped grid, each >= 3
     double inv_cell;   // 1 / cell size
     double org[3];     // grid origin (the initial extent's lower corner)
@@ -153,10 +155,17 @@ struct ContactGrid {
     double4 *spr;      // [nn] position and radius in bucket order
     double4 *svr;      // [nn] velocity and rod (as a double) in bucket order
     int32_t *sid;      // [nn] node ids in bucket order
-    double *force;     // [3][nn] contact force by node id
-    double *pot;       // [nn] potential share by node id
+    double *force;     // [3][nid] contact force by node id
+    double *pot;       // [nid] potential share by node id (mode 2: each element's share on its first node)
     const double *origin;   // FP32 batches: [3][n_rods] rod origins
-    double *xabs;      // FP32 batches: [3][nn] node positions (summed in FP64) after the drift
+    double *xabs;      // FP32 batches: [3][nid] node positions (summed in FP64) after the drift
+    // mode 2: segment records in bucket order, 128 bytes each: (A, radius), (B, rod),
+    // (v_A, element), (v_B, next); `next` of element i is the first element j > i of
+    // its rod that it may touch (the rest lengths between them add up to the diameter)
+    double4 *sca, *scb, *sva, *svb;
+    const int32_t *next_allowed;   // [n_slots]
+    double *fseg;      // [6][nn] each element's force shares of its nodes A and B
+    double cell_len;   // mode 2: the longest element the grid allows for (the cell holds it)
 };
 constexpr int64_t CONTACT_MAX_BUCKETS = 4096 * 1024;   // chunk totals fit one workgroup's prefix sum
 

@@ -113,6 +113,7 @@ struct rod_batch {
     void *d_wall_off = nullptr;        // [n_tiles][8] wall offsets in each tile's frame
     int n_walls = 0;
     bool rod_contact = false;          // rod-rod contact: a grid pass before every step
+    int contact_mode = 0;              // 1: node spheres, 2: element capsules
     rodk::ContactGrid cg{};
     double walls[ROD_MAX_WALLS][4] = {};
     double wall_k = 0, wall_c = 0, wall_mu = 0, wall_vslip = 0;
@@ -228,7 +229,7 @@ int validate(const rod_batch_desc *d)
         return fail(ROD_EINVAL, "connections need conn_rod, conn_node, conn_k, conn_c and conn_rest");
     if (d->n_walls < 0 || d->n_walls > ROD_MAX_WALLS)
         return fail(ROD_EINVAL, "n_walls must be in [0, " + std::to_string(ROD_MAX_WALLS) + "]");
-    if (d->rod_contact != 0 && d->rod_contact != 1) return fail(ROD_EINVAL, "rod_contact must be 0 or 1");
+    if (d->rod_contact < 0 || d->rod_contact > 2) return fail(ROD_EINVAL, "rod_contact must be 0, 1 or 2");
     if (d->rod_contact && d->substeps > 1)
         return fail(ROD_EINVAL, "rod contact runs one step per launch: substeps must be 0 or 1");
     if (d->n_walls > 0 || d->rod_contact) {
@@ -810,10 +811,17 @@ int build_device(rod_batch *b, const HostInputs &h)
 int build_contact_grid(rod_batch *b, const HostInputs &h)
 {
     rodk::ContactGrid &g = b->cg;
-    g.nn = b->n_slots + b->R;
-    double rmax = 0;
+    g.mode = b->contact_mode;
+    g.nid = b->n_slots + b->R;
+    g.nn = g.mode == 2 ? b->n_slots : g.nid;
+    double rmax = 0, lmax = 0;
     for (double r : h.rad) rmax = std::max(rmax, r);
-    const double cell = 2.0 * rmax;
+    for (double l : h.lh) lmax = std::max(lmax, l);
+    // mode 2: elements are binned by their midpoints; two touching elements'
+    // midpoints are at most (l_a + l_b) / 2 + r_a + r_b apart, so cells hold the
+    // longest element stretched by a quarter plus twice the largest radius
+    g.cell_len = 1.25 * lmax;
+    const double cell = g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax;
     g.inv_cell = 1.0 / cell;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (size_t j = 0; j < h.pos.size() / 3; ++j)
@@ -843,15 +851,44 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     HIPCHK(hipMalloc((void **)&g.chunk, nc * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.bucket, g.nn * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&g.rank, g.nn * sizeof(int32_t)));
-    HIPCHK(hipMalloc((void **)&g.spr, g.nn * sizeof(double4)));
-    HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
     HIPCHK(hipMalloc((void **)&g.sid, g.nn * sizeof(int32_t)));
-    HIPCHK(hipMalloc((void **)&g.force, 3 * g.nn * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&g.pot, g.nn * sizeof(double)));
+    if (g.mode == 2) {
+        HIPCHK(hipMalloc((void **)&g.sca, g.nn * sizeof(double4)));
+        HIPCHK(hipMalloc((void **)&g.scb, g.nn * sizeof(double4)));
+        HIPCHK(hipMalloc((void **)&g.sva, g.nn * sizeof(double4)));
+        HIPCHK(hipMalloc((void **)&g.svb, g.nn * sizeof(double4)));
+        HIPCHK(hipMalloc((void **)&g.fseg, 6 * g.nn * sizeof(double)));
+        // first element of the same rod each element may touch: the rest
+        // lengths strictly between them add up to at least the diameter
+        std::vector<int32_t> next((size_t)b->n_slots, 0);
+        int64_t e = 0;
+        for (int r = 0; r < b->R; ++r) {
+            const int n = h.n[r];
+            for (int i = 0; i < n; ++i) {
+                int j = i + 2;
+                double gap = j - 1 < n ? h.lh[e + i + 1] : 0.0;
+                while (j < n && !(gap >= 2.0 * h.rad[r])) {
+                    gap += h.lh[e + j];
+                    ++j;
+                }
+                next[b->rod_slot[r] + i] = std::min(j, n);
+            }
+            e += n;
+        }
+        int32_t *d_next = nullptr;
+        HIPCHK(hipMalloc((void **)&d_next, next.size() * sizeof(int32_t)));
+        g.next_allowed = d_next;
+        HIPCHK(hipMemcpy(d_next, next.data(), next.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    } else {
+        HIPCHK(hipMalloc((void **)&g.spr, g.nn * sizeof(double4)));
+        HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
+    }
+    HIPCHK(hipMalloc((void **)&g.force, 3 * g.nid * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&g.pot, g.nid * sizeof(double)));
     // counts start at zero; each pass clears them as it reads them
     HIPCHK(hipMemset(g.count, 0, nb * sizeof(int32_t)));
-    HIPCHK(hipMemset(g.force, 0, 3 * g.nn * sizeof(double)));
-    HIPCHK(hipMemset(g.pot, 0, g.nn * sizeof(double)));
+    HIPCHK(hipMemset(g.force, 0, 3 * g.nid * sizeof(double)));
+    HIPCHK(hipMemset(g.pot, 0, g.nid * sizeof(double)));
     if (b->precision == ROD_F32) {
         // FP32 positions are summed from the rod origins, edges and anchors
         std::vector<double> org((size_t)3 * b->R);
@@ -861,7 +898,7 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc((void **)&d_org, org.size() * sizeof(double)));
         g.origin = d_org;
         HIPCHK(hipMemcpy(d_org, org.data(), org.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMalloc((void **)&g.xabs, 3 * g.nn * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&g.xabs, 3 * g.nid * sizeof(double)));
     }
     HIPCHK(hipDeviceSynchronize());
     return ROD_OK;
@@ -1199,6 +1236,7 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->wall_mu = d->wall_mu;
     b->wall_vslip = d->wall_vslip;
     b->rod_contact = d->rod_contact != 0;
+    b->contact_mode = d->rod_contact;
     if (b->rod_contact) b->substeps = 1;   // a contact pass before every step
     b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0
            || d->n_connections > 0 || d->n_walls > 0 || b->rod_contact;
@@ -1424,6 +1462,12 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.rank);
     (void)hipFree(b->cg.spr);
     (void)hipFree(b->cg.svr);
+    (void)hipFree(b->cg.sca);
+    (void)hipFree(b->cg.scb);
+    (void)hipFree(b->cg.sva);
+    (void)hipFree(b->cg.svb);
+    (void)hipFree(b->cg.fseg);
+    (void)hipFree((void *)b->cg.next_allowed);
     (void)hipFree(b->cg.sid);
     (void)hipFree((void *)b->cg.origin);
     (void)hipFree(b->cg.xabs);

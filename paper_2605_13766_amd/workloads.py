@@ -86,7 +86,7 @@ class RodInputs:
     wall_c: float = 0.0                         # N s/m^2 (damping per unit penetration)
     wall_mu: float = 0.0
     wall_vslip: float = 1e-4                    # m/s
-    rod_contact: int = 0                        # 1: nodes of different rods touch (spheres, the wall law)
+    rod_contact: int = 0                        # 1: nodes of different rods touch (spheres, the wall law); 2: elements (capsules)
     name: str = ""
 
     # ------------------------------------------------------------------ sizes
@@ -518,7 +518,7 @@ def active_filaments(n_rods=16384, n=50, L=1.0, radius=0.025, youngs=1e7, period
 
 def fibre_pile(n_rods=16384, n=50, L=0.5, radius=0.01, youngs=1e7, per_row=8, rows=100, overlap=1e-7,
                g=9.81, damping=0.5, dt=1e-5, contact_k=1e5, contact_c=1e3, mu=0.3, vslip=1e-2, noise=1e-3,
-               seed=SEED_BASE + 9):
+               seed=SEED_BASE + 9, contact=1):
     """Straight fibres in crossed layers on a floor, in rod-rod contact (the
     paper's fibrous granular materials).
 
@@ -530,7 +530,8 @@ def fibre_pile(n_rods=16384, n=50, L=0.5, radius=0.01, youngs=1e7, per_row=8, ro
     contact_c, friction mu below slip speed vslip; node velocities N(0, noise^2)
     break the lattice's symmetry.  Defaults: 16,384 fibres of 50 elements in
     21 layers of 800 (element length 1 cm = one radius, so a crossing meets
-    several nodes of each fibre).
+    several nodes of each fibre).  contact=2 makes the elements capsules
+    (segment contact, self-contact included) instead of node spheres.
     """
     rng = np.random.default_rng(seed)
     sp = 4.0 * radius
@@ -553,8 +554,16 @@ def fibre_pile(n_rods=16384, n=50, L=0.5, radius=0.01, youngs=1e7, per_row=8, ro
     inp.gravity = np.array([0.0, 0.0, -g])
     inp.walls = np.array([[0.0, 0.0, 1.0, 0.0]])
     inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = contact_k, contact_c, mu, vslip
-    inp.rod_contact = 1
+    inp.rod_contact = contact
     return inp
+
+
+def capsule_pile(n_rods=16384, n=20, radius=0.01, **kw):
+    """The fibre pile with the paper's fibre aspect ratio (length 31 diameters,
+    0.62 m at a radius of 1 cm) in capsule contact: n = 20 elements of 3.1
+    radii, longer than the diameter, so crossing fibres meet between nodes and
+    only segment contact sees them."""
+    return fibre_pile(n_rods=n_rods, n=n, L=62.0 * radius, radius=radius, contact=2, seed=SEED_BASE + 10, **kw)
 
 
 def millipede_swarm(n_bots=224, legs_per_side=12, n_back=20, n_leg=8, back_length=0.02, leg_length=0.004,

@@ -176,7 +176,7 @@ def test_wall_descriptor_rejected_when_invalid():
 def test_rod_contact_descriptor_rejected_when_invalid():
     from paper_2605_13766_amd import rod
     base = W.fibre_pile(n_rods=4, n=8, L=0.08, per_row=1, rows=2)
-    bad = base.copy(); bad.rod_contact = 2
+    bad = base.copy(); bad.rod_contact = 3
     assert "rod_contact" in _expect(rod.ROD_EINVAL, bad)
     assert "substeps" in _expect(rod.ROD_EINVAL, base, substeps=2)
     bad = base.copy(); bad.walls = None; bad.wall_vslip = 0.0

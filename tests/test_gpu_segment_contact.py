@@ -1,0 +1,97 @@
+"""GPU parity of capsule (segment) contact, rod_contact = 2 (elements are
+capsules; elements of different rods and of one rod at least a diameter of
+rest length apart touch), against the FP64 oracle's brute force over element
+pairs, through the C boundary.  Bars on all five norms as in test_gpu_step;
+runs are bitwise repeatable and tile invariant.
+"""
+import numpy as np
+import pytest
+
+from paper_2605_13766_amd import workloads as W
+from test_gpu_step import _rod, assert_norms, run_both
+import test_oracle_segment_contact as OS
+
+pytestmark = pytest.mark.gpu
+
+
+def _pile(seed=61, n_rods=24):
+    """Crossed layers of 2 x 4 fibres of 8 elements (3.1 radii each: crossings
+    fall between nodes) on the floor, under gravity, with friction."""
+    return W.fibre_pile(n_rods=n_rods, n=8, L=0.248, per_row=2, rows=4, noise=1e-2, seed=seed, contact=2)
+
+
+def _hairpin_inp():
+    from rodcases import single
+    from oracle import rodoracle as ro
+    nodes = OS._hairpin(gap=-4e-4)
+    Q = W.frames_parallel_transport(nodes, d1_first=(0.0, 0.0, 1.0))
+    inp = single(nodes, Q, E=1e5, radius=OS.RAD, rest_length=np.linalg.norm(np.diff(nodes, axis=0), axis=1))
+    inp.rest_kappa = ro.Oracle(inp).strains()[1].copy()
+    inp.rod_contact = 2
+    inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = 20.0, 0.5, 0.3, 1e-3
+    return inp
+
+
+def test_long_elements_collide_f64():
+    print("case: two rods with elements of 5 radii crossing between nodes, capsules, FP64, 3000 steps", flush=True)
+    norms, info = run_both(OS._long_crossing(2), 3000)
+    assert info["substeps"] == 1
+    assert_norms(norms)
+
+
+def test_hairpin_self_contact_f64():
+    print("case: hairpin opening by self-contact (with damping and friction), FP64, 1000 steps", flush=True)
+    norms, _ = run_both(_hairpin_inp(), 1000)
+    assert_norms(norms)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+def test_capsule_pile_f64(waves):
+    print(f"case: capsule pile 24 fibres x 8, tile_waves={waves}, FP64, 800 steps", flush=True)
+    norms, info = run_both(_pile(), 800, tile_waves=waves)
+    assert info["tile_waves"] == waves
+    assert_norms(norms)
+
+
+def test_capsule_f32_parity():
+    for name, inp, steps in (("capsule pile 24 fibres", _pile(seed=62), 800),
+                             ("hairpin", _hairpin_inp(), 1000),
+                             ("long crossing", OS._long_crossing(2), 3000)):
+        print(f"case: {name}, FP32, {steps} steps", flush=True)
+        norms, _ = run_both(inp, steps, precision="f32")
+        assert_norms(norms)
+
+
+def test_capsule_runs_bitwise_repeatable_and_tile_invariant():
+    R = _rod()
+    inp = _pile(seed=63)
+    out = {}
+    for tag, waves in (("a", 2), ("b", 2), ("w1", 1), ("w4", 4)):
+        print(f"case: capsule pile, FP64, tile_waves={waves}, run {tag}", flush=True)
+        with R.RodBatch(inp, precision="f64", tile_waves=waves, substeps=1) as b:
+            b.step(400)
+            out[tag] = b.get_state()[:4] + (b.energy(),)
+    for tag in ("b", "w1", "w4"):
+        assert all(np.array_equal(x, y) for x, y in zip(out["a"], out[tag])), tag
+
+
+def test_capsule_pile_full_size_momentum():
+    """The 16,384-fibre capsule pile (aspect ratio 31, 20 elements each) without
+    gravity, floor, damping or friction: internal forces only, so the total
+    linear momentum stays at its start value (to the round-off of the
+    opposite pair forces, which cancel bit for bit, and of the kicks)."""
+    R = _rod()
+    inp = W.capsule_pile(g=0.0, damping=0.0, mu=0.0, contact_c=0.0)
+    inp.walls = None
+    print(f"case: capsule pile {inp.n_rods} fibres, {inp.n_elements} elements, FP64, 200 steps", flush=True)
+    m = OS._mass_vec(inp)
+    with R.RodBatch(inp, precision="f64") as b:
+        p0 = (m[:, None] * b.get_state()[1]).sum(0)
+        b.step(200)
+        v1 = b.get_state()[1]
+        e = b.energy()
+    p1 = (m[:, None] * v1).sum(0)
+    scale = (m[:, None] * np.abs(v1)).sum(0).max()
+    print("momentum change", np.abs(p1 - p0).max(), "scale", scale, "contact potential", e[:, 4].sum(), flush=True)
+    assert np.abs(p1 - p0).max() <= 1e-13 * scale
+    assert e[:, 4].sum() > 0.0
