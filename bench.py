@@ -8,7 +8,7 @@ substeps per launch S chosen by the library's autotuner).  The headline value is
 FP32 figure rides along in the same JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate] [--no-magnetic]
-                  [--no-active] [--no-walls] [--no-contact] [--no-connected]
+                  [--no-active] [--no-walls] [--no-contact] [--no-capsule] [--no-connected]
 
 The magnetic carpet rides along as the "magnetic" object: 65,536 base-clamped
 rods x 50 elements (FP32) turned by a rotating homogeneous field through their
@@ -18,7 +18,9 @@ filaments x 50 elements under gravity and travelling-wave muscle moments in
 both precisions, and the "walls" object the same filaments confined in a box
 of six planar walls (penalty contact with Coulomb friction); the "contact"
 object times a pile of crossed fibres in rod-rod contact (hash-grid pairs
-every step, one step per launch); the "connected" object times millipede-like
+every step, one step per launch), and the "capsule" object the same pile with
+fibres of aspect ratio 31 whose elements touch as capsules; the "connected"
+object times millipede-like
 bots of rods joined by point-wise and lateral spring-dashpot connections (224
 bots, and 4096 to fill the GPU).
 
@@ -269,7 +271,28 @@ def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH, precisio
     return out
 
 
-def _time_contact_one(inp, precision, steps, warmup, tile_waves, n_steps):
+def time_capsule(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH, precisions=("f64", "f32")):
+    """The capsule pile: 16,384 fibres of the paper's aspect ratio (31
+    diameters, 20 elements of 3.1 radii) in 21 crossed layers on a floor,
+    every element a capsule (segment contact, self-contact included), pairs
+    found by the hash grid over element midpoints every step.  Bytes as for
+    the fibre pile: the step's per element plus 72 per node for the pass."""
+    from paper_2605_13766_amd import workloads as W
+    inp = W.capsule_pile()
+    out = None
+    for p in precisions:
+        row = _time_contact_one(inp, p, steps, warmup, tile_waves, n_steps, tag="capsulepile16384")
+        row["workload"] = (f"capsule_pile: {inp.n_rods:,} fibres x 20 elements (0.62 m, radius 1 cm, aspect ratio 31) "
+                           f"in 21 crossed layers on a floor, capsule contact between elements (k {inp.wall_k:g} N/m, "
+                           f"mu {inp.wall_mu:g}), gravity, dt 1e-5 s, one step per launch, {p.upper()}")
+        if out is None:
+            out = row
+        else:
+            out[p] = {k: row[k] for k in ("value", "ms_per_step", "ms_per_simulation_step", "tile_waves", "roofline")}
+    return out
+
+
+def _time_contact_one(inp, precision, steps, warmup, tile_waves, n_steps, tag="fibrepile16384"):
     r = time_gpu(inp, precision, steps, warmup, tile_waves, 1, traffic_tag="none", n_steps=n_steps)
     n_nodes = inp.n_elements + inp.n_rods
     step_s = r["launch_ms"] * 1e-3 / n_steps
@@ -285,7 +308,7 @@ def _time_contact_one(inp, precision, steps, warmup, tile_waves, n_steps):
         "tile_waves": r["info"]["tile_waves"], "substeps_per_launch": r["info"]["substeps"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                      "frac": achieved / 8000.0,
-                     "traffic": traffic_from_profile(f"{precision}_fibrepile16384", r["info"]["tile_waves"], 1,
+                     "traffic": traffic_from_profile(f"{precision}_{tag}", r["info"]["tile_waves"], 1,
                                                      (KERNEL_SRC, CONTACT_SRC)),
                      "algorithmic_bytes_per_step": algo},
     }
@@ -505,6 +528,7 @@ def main(argv=None):
     ap.add_argument("--no-connected", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-contact", action="store_true")
+    ap.add_argument("--no-capsule", action="store_true")
     ap.add_argument("--contact-steps", type=int, default=STEPS_PER_LAUNCH,
                     help="simulation steps per bench step of the contact workload (short runs for counters)")
     ap.add_argument("--connected-bots", default="224,4096", help="swarm sizes of the connected workload")
@@ -594,6 +618,10 @@ def main(argv=None):
     if not args.no_contact:
         print("timing the fibre pile (rod-rod contact)", file=sys.stderr, flush=True)
         line["contact"] = time_contact(args.steps, args.warmup, args.tile_waves, args.contact_steps,
+                                       precisions=args.precisions.split(","))
+    if not args.no_capsule:
+        print("timing the capsule pile (segment contact)", file=sys.stderr, flush=True)
+        line["capsule"] = time_capsule(args.steps, args.warmup, args.tile_waves, args.contact_steps,
                                        precisions=args.precisions.split(","))
     if not args.no_connected:
         print("timing the millipede swarm", file=sys.stderr, flush=True)

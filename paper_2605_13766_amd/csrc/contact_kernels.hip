@@ -310,12 +310,72 @@ __global__ void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, i
     G.pot[id] = pot;
 }
 
+
 // ---------------------------------------------------------------- capsules
 // Mode 2: every element is a capsule, the segment between its nodes A (node
 // i) and B (node i + 1) dilated by the rod's radius.  Elements are binned by
 // their midpoints in cells of the longest element the grid allows for plus
 // twice the largest radius, so the midpoints of two touching elements are at
 // most one cell apart per axis.
+
+// Each binned item's id to its place: the bucket's start plus its rank.
+__global__ void contact_scatter_ids(const ContactGrid G)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= G.nn) return;
+    const int32_t r = G.rank[id];
+    if (r < 0) return;
+    G.sid[G.start[G.bucket[id]] + r] = (int32_t)id;
+}
+
+// As contact_sort_kernel, for the ids alone: the segment records (128 bytes
+// each) are written afterwards, in sorted order, by seg_fill_kernel.
+__global__ void sort_ids_kernel(const ContactGrid G)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= G.nn || G.rank[id] != 0) return;
+    const int b = G.bucket[id];
+    const int32_t s = G.start[b], e = G.start[b + 1];
+    for (int32_t i = s + 1; i < e; ++i) {
+        const int32_t key = G.sid[i];
+        int32_t j = i - 1;
+        while (j >= s && G.sid[j] > key) {
+            G.sid[j + 1] = G.sid[j];
+            --j;
+        }
+        G.sid[j + 1] = key;
+    }
+}
+
+// FP32 screening record of an element, two float4: the centre of its
+// capsule's axis-aligned bounding box relative to the grid origin and the half
+// extents, then its rod and element index (as bits).
+__device__ inline void cull_record(const double a[3], const double b[3], double r, int rod, int elem,
+                                   const ContactGrid &G, float4 &c0, float4 &c1)
+{
+    double c[3], e[3];
+    for (int k = 0; k < 3; ++k) {
+        const double lo = fmin(a[k], b[k]) - r, hi = fmax(a[k], b[k]) + r;
+        c[k] = 0.5 * (lo + hi) - G.org[k];
+        e[k] = 0.5 * (hi - lo);
+    }
+    c0 = make_float4((float)c[0], (float)c[1], (float)c[2], (float)e[0]);
+    c1 = make_float4((float)e[1], (float)e[2], __int_as_float(rod), __int_as_float(elem));
+}
+
+// Screening tolerance of a box test in FP32.  Two capsules in contact have
+// boxes that overlap in exact arithmetic: per axis, the centres are closer
+// than the sum of the half extents, itself at most a cell or so.  Rounding
+// each centre (relative to the origin) and half extent to FP32 moves the two
+// sides of the test by at most 2^-24 times the centres' magnitudes plus the
+// extents, below 2^-23 (|c|_1 + 2 cell) for the element's own centre c, and
+// the FP32 test itself adds a unit or two of 2^-24 of the same.  The margin
+// 1e-6 (|c|_1 + 4 cell) > 2^-20 (|c|_1 + 4 cell) covers this eight times
+// over, so the screen drops only pairs that cannot touch.
+__device__ inline float cull_margin(const float4 &c, float cell)
+{
+    return 1e-6f * (fabsf(c.x) + fabsf(c.y) + fabsf(c.z) + 4.0f * cell);
+}
 
 // Element (slot) s: endpoints and velocities `drift` seconds ahead; false for
 // padding slots and non-finite positions.
@@ -384,139 +444,169 @@ __global__ void seg_bin_kernel(const DevBatch<T> B, const ContactGrid G, double 
     G.rank[s] = atomicAdd(&G.count[bk], 1);
 }
 
+// Segment records in sorted order: (A, radius), (B, rod), (v_A, element),
+// v_B, and the screening record.
 template <typename T>
-__global__ void seg_scatter_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+__global__ void seg_fill_kernel(const DevBatch<T> B, const ContactGrid G, double drift, int nb)
 {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= G.nn) return;
-    const int32_t r = G.rank[s];
-    if (r < 0) return;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= G.start[nb]) return;
+    const int64_t s = G.sid[p];
     int rod, elem;
     double a[3], b[3], va[3], vb[3];
     contact_segment(B, G, s, drift, rod, elem, a, b, va, vb);
-    const int64_t p = G.start[G.bucket[s]] + r;
-    G.sca[p] = make_double4(a[0], a[1], a[2], B.rod_rad[rod]);
+    const double r = B.rod_rad[rod];
+    G.sca[p] = make_double4(a[0], a[1], a[2], r);
     G.scb[p] = make_double4(b[0], b[1], b[2], (double)rod);
     G.sva[p] = make_double4(va[0], va[1], va[2], (double)elem);
-    G.svb[p] = make_double4(vb[0], vb[1], vb[2], (double)G.next_allowed[s]);
-    G.sid[p] = (int32_t)s;
+    G.svb[p] = make_double4(vb[0], vb[1], vb[2], 0.0);
+    cull_record(a, b, r, rod, elem, G, G.cull[2 * p], G.cull[2 * p + 1]);
 }
 
-// as contact_sort_kernel, for the four segment records
-__global__ void seg_sort_kernel(const ContactGrid G)
-{
-    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (id >= G.nn || G.rank[id] != 0) return;
-    const int bk = G.bucket[id];
-    const int32_t s = G.start[bk], e = G.start[bk + 1];
-    for (int32_t i = s + 1; i < e; ++i) {
-        const int32_t key = G.sid[i];
-        if (G.sid[i - 1] < key) continue;
-        const double4 r0 = G.sca[i], r1 = G.scb[i], r2 = G.sva[i], r3 = G.svb[i];
-        int32_t j = i - 1;
-        while (j >= s && G.sid[j] > key) {
-            G.sid[j + 1] = G.sid[j];
-            G.sca[j + 1] = G.sca[j];
-            G.scb[j + 1] = G.scb[j];
-            G.sva[j + 1] = G.sva[j];
-            G.svb[j + 1] = G.svb[j];
-            --j;
-        }
-        G.sid[j + 1] = key;
-        G.sca[j + 1] = r0;
-        G.scb[j + 1] = r1;
-        G.sva[j + 1] = r2;
-        G.svb[j + 1] = r3;
-    }
-}
+// Each element sums its contacts over the 27 buckets around its midpoint, in
+// two phases so that the wave's lanes do the costly FP64 work together.  The
+// screen: every candidate's capsule bounding box against the element's in
+// FP32, four candidates' records loaded at a time and tested without
+// branches, and elements of the same rod closer than the self-contact rule
+// allows dropped; a survivor's sorted position goes to the lane's queue in
+// LDS.  A lane screens until its queue is nearly full or its sweep ends; then
+// the wave drains its queues, each lane taking its survivors in the order it
+// queued them (the order of the sweep, so the sums are those of a single
+// pass), and lanes with candidates left go on.
+//
+// Evaluation of a pair: its closest points and force in one fixed order (the
+// element first in (rod, element) order takes the part of a), the other
+// element taking the exact negative, so the two feel opposite forces to the
+// last bit.  The force on the element goes to its nodes as (1 - s) and s; a
+// quarter of k delta^2 per ordered pair is the element's potential share.
+constexpr int SEG_BLOCK = 256;
+constexpr int SEG_QUEUE = 32;   // survivors a lane holds (LDS: 32 KB per workgroup)
+constexpr int SEG_GROUP = 4;    // candidates screened together
+static_assert(SEG_GROUP <= SEG_CULL_PAD, "a group may read up to SEG_GROUP - 1 records past the last element");
 
-// Each element sums its contacts over the 27 buckets around its midpoint.  A
-// pair's closest points and force are evaluated in one fixed order (the
-// element first in (rod, element) order takes the part of a), and the other
-// element takes the exact negative, so the two feel opposite forces to the
-// last bit.  Elements of one rod touch only from `next` on.  The force on the
-// element goes to its nodes as (1 - s) and s; a quarter of k delta^2 per
-// ordered pair is the element's potential share.
 template <typename T>
-__global__ void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
+__global__ __launch_bounds__(SEG_BLOCK) void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
 {
-    const int64_t p0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p0 >= G.start[nb]) return;
-    const double4 ua = G.sca[p0], ub = G.scb[p0], uva = G.sva[p0], uvb = G.svb[p0];
-    const int rod = (int)ub.w, elem = (int)uva.w, next = (int)uvb.w;
+    __shared__ int32_t queue[SEG_QUEUE * SEG_BLOCK];
+    int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * SEG_BLOCK]
+    const int64_t p0 = blockIdx.x * (int64_t)SEG_BLOCK + threadIdx.x;
+    // no early exit: every lane reaches the wave-wide drains
+    const bool live = p0 < G.start[nb];
+    const int64_t pm = live ? p0 : 0;
+    const double4 ua = G.sca[pm], ub = G.scb[pm], uva = G.sva[pm], uvb = G.svb[pm];
+    const float4 mc = G.cull[2 * pm], me = G.cull[2 * pm + 1];
+    const float mg = cull_margin(mc, (float)(1.0 / G.inv_cell));
+    const float ex = mc.w + mg, ey = me.x + mg, ez = me.y + mg;   // own half extents plus the margin
+    const int rod = (int)ub.w, elem = (int)uva.w;
+    const int64_t sme = live ? G.sid[p0] : 0;
+    // elements of the own rod it may touch: up to `prev` and from `next` on
+    const int next = G.self_pairs[sme], prev = G.self_pairs[G.nn + sme];
     const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
     const double ra = ua.w;
-    const double mx = 0.5 * (ua.x + ub.x), my = 0.5 * (ua.y + ub.y), mz = 0.5 * (ua.z + ub.z);
-    const double hl = 0.5 * sqrt((ub.x - ua.x) * (ub.x - ua.x) + (ub.y - ua.y) * (ub.y - ua.y)
-                                 + (ub.z - ua.z) * (ub.z - ua.z));
     double fa0 = 0, fa1 = 0, fa2 = 0, fb0 = 0, fb1 = 0, fb2 = 0, pot = 0;
-    const int64_t cx = cell_of(mx, G.org[0], G.inv_cell), cy = cell_of(my, G.org[1], G.inv_cell),
-                  cz = cell_of(mz, G.org[2], G.inv_cell);
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int row = (wrap_cell(cz + dz, G.gz) * G.gy + wrap_cell(cy + dy, G.gy)) * G.gx;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int bk = row + wrap_cell(cx + dx, G.gx);
-                const int32_t p1 = G.start[bk + 1];
-                for (int32_t p = G.start[bk]; p < p1; ++p) {
-                    if (p == p0) continue;
-                    const double4 qa = G.sca[p], qb = G.scb[p];
-                    // bounding spheres of the two capsules
-                    const double nx = 0.5 * (qa.x + qb.x) - mx, ny = 0.5 * (qa.y + qb.y) - my,
-                                 nz = 0.5 * (qa.z + qb.z) - mz;
-                    const double ql = 0.5 * sqrt((qb.x - qa.x) * (qb.x - qa.x) + (qb.y - qa.y) * (qb.y - qa.y)
-                                                 + (qb.z - qa.z) * (qb.z - qa.z));
-                    const double reach = hl + ql + ra + qa.w;
-                    if (!(nx * nx + ny * ny + nz * nz < reach * reach)) continue;
-                    const int qrod = (int)qb.w;
-                    const double4 qva = G.sva[p], qvb = G.svb[p];
-                    const int qelem = (int)qva.w;
-                    if (qrod == rod) {
-                        const bool allowed = elem < qelem ? qelem >= next : elem >= (int)qvb.w;
-                        if (!allowed) continue;
-                    }
-                    const bool first = rod < qrod || (rod == qrod && elem < qelem);
-                    // u: the pair's first element, w: the other
-                    const double u0[3] = {first ? ua.x : qa.x, first ? ua.y : qa.y, first ? ua.z : qa.z};
-                    const double u1[3] = {first ? ub.x : qb.x, first ? ub.y : qb.y, first ? ub.z : qb.z};
-                    const double w0[3] = {first ? qa.x : ua.x, first ? qa.y : ua.y, first ? qa.z : ua.z};
-                    const double w1[3] = {first ? qb.x : ub.x, first ? qb.y : ub.y, first ? qb.z : ub.z};
-                    const double4 vu0 = first ? uva : qva, vu1 = first ? uvb : qvb;
-                    const double4 vw0 = first ? qva : uva, vw1 = first ? qvb : uvb;
-                    const double ru = first ? ra : qa.w, rw = first ? qa.w : ra;
-                    double su, sw;
-                    closest_params(u0, u1, w0, w1, su, sw);
-                    const double pu[3] = {u0[0] + su * (u1[0] - u0[0]), u0[1] + su * (u1[1] - u0[1]),
-                                          u0[2] + su * (u1[2] - u0[2])};
-                    const double pw[3] = {w0[0] + sw * (w1[0] - w0[0]), w0[1] + sw * (w1[1] - w0[1]),
-                                          w0[2] + sw * (w1[2] - w0[2])};
-                    const double e0 = pu[0] - pw[0], e1 = pu[1] - pw[1], e2 = pu[2] - pw[2];
-                    const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                    const double delta = ru + rw - dist;
-                    if (!(delta > 0.0)) continue;
-                    pot += 0.25 * k * delta * delta;
-                    if (!(dist > 0.0)) continue;   // the segments cross: no direction
-                    const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
-                    const double r0 = ((1.0 - su) * vu0.x + su * vu1.x) - ((1.0 - sw) * vw0.x + sw * vw1.x);
-                    const double r1 = ((1.0 - su) * vu0.y + su * vu1.y) - ((1.0 - sw) * vw0.y + sw * vw1.y);
-                    const double r2 = ((1.0 - su) * vu0.z + su * vu1.z) - ((1.0 - sw) * vw0.z + sw * vw1.z);
-                    const double vn = n0 * r0 + n1 * r1 + n2 * r2;
-                    const double fn = delta * (k - c * vn);
-                    if (!(fn > 0.0)) continue;
-                    const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
-                    const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-                    const double gf = mu * fn / (sp > vs ? sp : vs);
-                    double f0 = fn * n0 - gf * t0, f1 = fn * n1 - gf * t1, f2 = fn * n2 - gf * t2;   // on u
-                    double sp_ = su;
-                    if (!first) {
-                        f0 = -f0; f1 = -f1; f2 = -f2;
-                        sp_ = sw;
-                    }
-                    fa0 += (1.0 - sp_) * f0; fa1 += (1.0 - sp_) * f1; fa2 += (1.0 - sp_) * f2;
-                    fb0 += sp_ * f0; fb1 += sp_ * f1; fb2 += sp_ * f2;
-                }
-            }
+    int nq = 0;
+
+    auto evaluate = [&](int32_t p) {
+        const double4 qa = G.sca[p], qb = G.scb[p], qva = G.sva[p], qvb = G.svb[p];
+        const int qrod = (int)qb.w, qelem = (int)qva.w;
+        const bool first = rod < qrod || (rod == qrod && elem < qelem);
+        // u: the pair's first element, w: the other
+        const double u0[3] = {first ? ua.x : qa.x, first ? ua.y : qa.y, first ? ua.z : qa.z};
+        const double u1[3] = {first ? ub.x : qb.x, first ? ub.y : qb.y, first ? ub.z : qb.z};
+        const double w0[3] = {first ? qa.x : ua.x, first ? qa.y : ua.y, first ? qa.z : ua.z};
+        const double w1[3] = {first ? qb.x : ub.x, first ? qb.y : ub.y, first ? qb.z : ub.z};
+        const double4 vu0 = first ? uva : qva, vu1 = first ? uvb : qvb;
+        const double4 vw0 = first ? qva : uva, vw1 = first ? qvb : uvb;
+        const double ru = first ? ra : qa.w, rw = first ? qa.w : ra;
+        double su, sw;
+        closest_params(u0, u1, w0, w1, su, sw);
+        const double pu[3] = {u0[0] + su * (u1[0] - u0[0]), u0[1] + su * (u1[1] - u0[1]),
+                              u0[2] + su * (u1[2] - u0[2])};
+        const double pw[3] = {w0[0] + sw * (w1[0] - w0[0]), w0[1] + sw * (w1[1] - w0[1]),
+                              w0[2] + sw * (w1[2] - w0[2])};
+        const double e0 = pu[0] - pw[0], e1 = pu[1] - pw[1], e2 = pu[2] - pw[2];
+        const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        const double delta = ru + rw - dist;
+        if (!(delta > 0.0)) return;
+        pot += 0.25 * k * delta * delta;
+        if (!(dist > 0.0)) return;   // the segments cross: no direction
+        const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
+        const double r0 = ((1.0 - su) * vu0.x + su * vu1.x) - ((1.0 - sw) * vw0.x + sw * vw1.x);
+        const double r1 = ((1.0 - su) * vu0.y + su * vu1.y) - ((1.0 - sw) * vw0.y + sw * vw1.y);
+        const double r2 = ((1.0 - su) * vu0.z + su * vu1.z) - ((1.0 - sw) * vw0.z + sw * vw1.z);
+        const double vn = n0 * r0 + n1 * r1 + n2 * r2;
+        const double fn = delta * (k - c * vn);
+        if (!(fn > 0.0)) return;
+        const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
+        const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        const double gf = mu * fn / (sp > vs ? sp : vs);
+        double f0 = fn * n0 - gf * t0, f1 = fn * n1 - gf * t1, f2 = fn * n2 - gf * t2;   // on u
+        double sp_ = su;
+        if (!first) {
+            f0 = -f0; f1 = -f1; f2 = -f2;
+            sp_ = sw;
         }
+        fa0 += (1.0 - sp_) * f0; fa1 += (1.0 - sp_) * f1; fa2 += (1.0 - sp_) * f2;
+        fb0 += sp_ * f0; fb1 += sp_ * f1; fb2 += sp_ * f2;
+    };
+
+    // the sweep: ranges of sorted positions, 27 buckets (or 9 rows of three
+    // contiguous x buckets) in bucket order; p..pe is the current one
+    const int64_t cx = cell_of(0.5 * (ua.x + ub.x), G.org[0], G.inv_cell),
+                  cy = cell_of(0.5 * (ua.y + ub.y), G.org[1], G.inv_cell),
+                  cz = cell_of(0.5 * (ua.z + ub.z), G.org[2], G.inv_cell);
+    const int wx = wrap_cell(cx, G.gx);
+    const bool run = wx >= 1 && wx + 1 < G.gx;
+    int ri = 0;
+    int32_t p = 0, pe = 0;
+    auto next_range = [&]() -> bool {
+        while (ri < 27) {
+            const int r = ri / 3;
+            const int row = (wrap_cell(cz + r / 3 - 1, G.gz) * G.gy + wrap_cell(cy + r % 3 - 1, G.gy)) * G.gx;
+            if (run) {
+                p = G.start[row + wx - 1];
+                pe = G.start[row + wx + 2];
+                ri += 3;
+            } else {
+                const int b = row + wrap_cell(cx + ri % 3 - 1, G.gx);
+                p = G.start[b];
+                pe = G.start[b + 1];
+                ri += 1;
+            }
+            if (p < pe) return true;
+        }
+        return false;
+    };
+    bool done = !live || !next_range();
+    for (;;) {
+        while (!done && nq <= SEG_QUEUE - SEG_GROUP) {
+            // the records of p .. p + 3; those past pe (the array holds a group
+            // more than the elements) are read and masked
+            const float4 *const q = G.cull + 2 * (int64_t)p;
+            float4 q0[SEG_GROUP], q1[SEG_GROUP];
+#pragma unroll
+            for (int u = 0; u < SEG_GROUP; ++u) {
+                q0[u] = q[2 * u];
+                q1[u] = q[2 * u + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < SEG_GROUP; ++u) {
+                // half extents: x in the first record's w, y and z in the second's x and y
+                const bool box = (fabsf(mc.x - q0[u].x) < ex + q0[u].w) & (fabsf(mc.y - q0[u].y) < ey + q1[u].x)
+                               & (fabsf(mc.z - q0[u].z) < ez + q1[u].y);
+                const int qe = __float_as_int(q1[u].w);   // the element itself fails both bounds
+                const bool pair = (__float_as_int(q1[u].z) != rod) | (qe >= next) | (qe <= prev);
+                mine[nq * SEG_BLOCK] = p + u;   // nq < SEG_QUEUE: a free slot, kept only if it passed
+                nq += (int)((p + u < pe) & box & pair);
+            }
+            p += SEG_GROUP;
+            if (p >= pe) done = !next_range();
+        }
+        for (int j = 0; j < nq; ++j) evaluate(mine[j * SEG_BLOCK]);
+        nq = 0;
+        if (!__any(!done)) break;
+    }
+    if (!live) return;
     const int64_t s = G.sid[p0], nn = G.nn;
     G.fseg[s] = fa0; G.fseg[nn + s] = fa1; G.fseg[2 * nn + s] = fa2;
     G.fseg[3 * nn + s] = fb0; G.fseg[4 * nn + s] = fb1; G.fseg[5 * nn + s] = fb2;
@@ -564,16 +654,18 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
         hipLaunchKernelGGL(contact_positions_kernel, dim3((b.n_rods + 3) / 4), dim3(256), 0, s, b, g, drift);
     }
     const bool seg = g.mode == 2;
-    if (seg && (!g.sca || !g.fseg || !g.next_allowed)) return hipErrorInvalidValue;
+    if (seg ? (!g.sca || !g.fseg || !g.self_pairs || !g.cull) : !g.spr) return hipErrorInvalidValue;
     if (seg) hipLaunchKernelGGL((seg_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
     else hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
     hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb);
     hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb);
     hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb);
     if (seg) {
-        hipLaunchKernelGGL((seg_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
-        hipLaunchKernelGGL(seg_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
-        hipLaunchKernelGGL((seg_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
+        hipLaunchKernelGGL(contact_scatter_ids, dim3(gn), dim3(bs), 0, s, g);
+        hipLaunchKernelGGL(sort_ids_kernel, dim3(gn), dim3(bs), 0, s, g);
+        hipLaunchKernelGGL((seg_fill_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, nb);
+        hipLaunchKernelGGL((seg_force_kernel<T>), dim3((unsigned)((g.nn + SEG_BLOCK - 1) / SEG_BLOCK)),
+                           dim3(SEG_BLOCK), 0, s, b, g, nb);
         hipLaunchKernelGGL((seg_nodes_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g);
     } else {
         hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);

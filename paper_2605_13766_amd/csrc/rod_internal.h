@@ -155,18 +155,24 @@ struct ContactGrid {
     double4 *spr;      // [nn] position and radius in bucket order
     double4 *svr;      // [nn] velocity and rod (as a double) in bucket order
     int32_t *sid;      // [nn] node ids in bucket order
+    // mode 2: [2 (nn + SEG_CULL_PAD)] screening records in bucket order, two float4 per element:
+    // its capsule's bounding box (centre relative to org, half extents), rod, element
+    float4 *cull;
     double *force;     // [3][nid] contact force by node id
     double *pot;       // [nid] potential share by node id (mode 2: each element's share on its first node)
     const double *origin;   // FP32 batches: [3][n_rods] rod origins
     double *xabs;      // FP32 batches: [3][nid] node positions (summed in FP64) after the drift
     // mode 2: segment records in bucket order, 128 bytes each: (A, radius), (B, rod),
-    // (v_A, element), (v_B, next); `next` of element i is the first element j > i of
-    // its rod that it may touch (the rest lengths between them add up to the diameter)
+    // (v_A, element), (v_B, unused)
     double4 *sca, *scb, *sva, *svb;
-    const int32_t *next_allowed;   // [n_slots]
+    // [2][n_slots] the elements of its own rod each element may touch: from
+    // `next` on and up to `prev` (the rest lengths between them add up to the
+    // diameter; next = n and prev = -1 when there are none)
+    const int32_t *self_pairs;
     double *fseg;      // [6][nn] each element's force shares of its nodes A and B
     double cell_len;   // mode 2: the longest element the grid allows for (the cell holds it)
 };
+constexpr int64_t SEG_CULL_PAD = 4;   // screening records past the last element (one group)
 constexpr int64_t CONTACT_MAX_BUCKETS = 4096 * 1024;   // chunk totals fit one workgroup's prefix sum
 
 // Fill g.force and g.pot for positions advanced by `drift` seconds from the

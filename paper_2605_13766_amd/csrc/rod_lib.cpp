@@ -858,12 +858,17 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc((void **)&g.sva, g.nn * sizeof(double4)));
         HIPCHK(hipMalloc((void **)&g.svb, g.nn * sizeof(double4)));
         HIPCHK(hipMalloc((void **)&g.fseg, 6 * g.nn * sizeof(double)));
-        // first element of the same rod each element may touch: the rest
-        // lengths strictly between them add up to at least the diameter
-        std::vector<int32_t> next((size_t)b->n_slots, 0);
+        // the elements of its own rod each element may touch: j > i from
+        // next[i] on, where the rest lengths strictly between them, summed in
+        // increasing order, reach the diameter; j < i up to prev[i], the last
+        // j with next[j] <= i (the sums only grow as j moves down, even rounded:
+        // a rounded sum of positive terms is monotone in each term)
+        const size_t NS = (size_t)b->n_slots;
+        std::vector<int32_t> pairs(2 * NS, 0);
         int64_t e = 0;
         for (int r = 0; r < b->R; ++r) {
             const int n = h.n[r];
+            const int64_t s0 = b->rod_slot[r];
             for (int i = 0; i < n; ++i) {
                 int j = i + 2;
                 double gap = j - 1 < n ? h.lh[e + i + 1] : 0.0;
@@ -871,14 +876,23 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
                     gap += h.lh[e + j];
                     ++j;
                 }
-                next[b->rod_slot[r] + i] = std::min(j, n);
+                pairs[s0 + i] = std::min(j, n);
+            }
+            // next[] does not decrease along the rod, so prev[] follows it
+            int prev = -1;
+            for (int i = 0; i < n; ++i) {
+                while (prev + 1 < n && pairs[s0 + prev + 1] <= i) ++prev;
+                pairs[NS + s0 + i] = prev;
             }
             e += n;
         }
-        int32_t *d_next = nullptr;
-        HIPCHK(hipMalloc((void **)&d_next, next.size() * sizeof(int32_t)));
-        g.next_allowed = d_next;
-        HIPCHK(hipMemcpy(d_next, next.data(), next.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        int32_t *d_pairs = nullptr;
+        HIPCHK(hipMalloc((void **)&d_pairs, pairs.size() * sizeof(int32_t)));
+        g.self_pairs = d_pairs;
+        HIPCHK(hipMemcpy(d_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        // a group of screening records more than the elements: the force pass
+        // reads whole groups and masks the records past a range's end
+        HIPCHK(hipMalloc((void **)&g.cull, 2 * (g.nn + rodk::SEG_CULL_PAD) * sizeof(float4)));
     } else {
         HIPCHK(hipMalloc((void **)&g.spr, g.nn * sizeof(double4)));
         HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
@@ -1467,8 +1481,9 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.sva);
     (void)hipFree(b->cg.svb);
     (void)hipFree(b->cg.fseg);
-    (void)hipFree((void *)b->cg.next_allowed);
+    (void)hipFree((void *)b->cg.self_pairs);
     (void)hipFree(b->cg.sid);
+    (void)hipFree(b->cg.cull);
     (void)hipFree((void *)b->cg.origin);
     (void)hipFree(b->cg.xabs);
     (void)hipFree(b->cg.force);
