@@ -213,8 +213,8 @@ __global__ void contact_scatter_kernel(const DevBatch<T> B, const ContactGrid G,
     double x[3], v[3];
     contact_node(B, G, id, drift, rod, x, v);
     const int64_t p = G.start[G.bucket[id]] + r;
-    G.spr[p] = make_double4(x[0], x[1], x[2], B.rod_rad[rod]);
-    G.svr[p] = make_double4(v[0], v[1], v[2], (double)rod);
+    G.spr[p] = make_double4(x[0], x[1], x[2], (double)rod);
+    G.svr[p] = make_double4(v[0], v[1], v[2], B.rod_rad[rod]);
     G.sid[p] = (int32_t)id;
 }
 
@@ -247,69 +247,143 @@ __global__ void contact_sort_kernel(const ContactGrid G)
     }
 }
 
+// Force passes: workgroups of CF_BLOCK lanes, one item per lane; a lane
+// screens its candidates CF_GROUP at a time (their records loaded together,
+// the test without branches; the record arrays hold CONTACT_PAD entries past
+// the last item, so a group may read past a range's end and mask what it
+// read) and queues the survivors' sorted positions in LDS, CF_QUEUE at most.
+// A lane screens until its queue is nearly full or its sweep ends; then the
+// wave evaluates its queues together, each lane taking its survivors in the
+// order it queued them (the order of the sweep, so the sums are those of a
+// single pass), and lanes with candidates left go on.
+constexpr int CF_BLOCK = 256;
+constexpr int CF_QUEUE = 32;   // survivors a lane holds (LDS: 32 KB per workgroup)
+constexpr int CF_GROUP = 4;
+static_assert(CF_GROUP <= CONTACT_PAD, "a group may read up to CF_GROUP - 1 records past the last item");
+
+// A lane's sweep over the sorted positions of the 27 buckets around cell
+// (cx, cy, cz) in bucket order: 27 ranges, or 9 rows of three contiguous x
+// buckets where the row does not wrap there.  next() moves p..pe to the next
+// non-empty range and returns false at the end.  The bounds of the range
+// after the current one are loaded ahead (np, npe), so their latency overlaps
+// the screening of the current range.
+struct Sweep {
+    int64_t cx, cy, cz;
+    int wx, ri;
+    bool run;
+    int32_t p, pe, np, npe;   // np = -1: no range left
+    __device__ Sweep(const ContactGrid &G, int64_t x, int64_t y, int64_t z)
+        : cx(x), cy(y), cz(z), wx(wrap_cell(x, G.gx)), ri(0), run(false), p(0), pe(0), np(-1), npe(0)
+    {
+        run = wx >= 1 && wx + 1 < G.gx;
+        fetch(G);
+    }
+    // bounds of range ri into np, npe
+    __device__ void fetch(const ContactGrid &G)
+    {
+        if (ri >= 27) {
+            np = -1;
+            return;
+        }
+        const int r = ri / 3;
+        const int row = (wrap_cell(cz + r / 3 - 1, G.gz) * G.gy + wrap_cell(cy + r % 3 - 1, G.gy)) * G.gx;
+        const int b0 = run ? row + wx - 1 : row + wrap_cell(cx + ri % 3 - 1, G.gx);
+        const int b1 = run ? row + wx + 2 : b0 + 1;
+        np = G.start[b0];
+        npe = G.start[b1];
+        ri += run ? 3 : 1;
+    }
+    __device__ bool next(const ContactGrid &G)
+    {
+        for (;;) {
+            if (np < 0) return false;
+            p = np;
+            pe = npe;
+            fetch(G);
+            if (p < pe) return true;
+        }
+    }
+};
+
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
 // around it: the walls' law between two spheres.  Threads take the nodes in
-// bucket order, so neighbouring threads read the same buckets and the sweep
-// streams through the sorted records; a candidate costs one 32-byte load
-// (position, radius), velocity and rod only for overlaps.  Results go to the
-// node's id (padding ids keep the zeros set at creation).  (Renumbering the
-// workgroups so that each XCD sweeps a contiguous eighth halved this kernel's
-// HBM reads but made it slower on the fibre pile, so the plain order stays.)
+// bucket order, so neighbouring threads read the same buckets.  The screen
+// keeps candidates of other rods closer than the node's radius plus the
+// largest radius (a bound on the exact test, widened by 1e-9 relative so that
+// rounding cannot drop a pair the exact test takes); the evaluation repeats
+// the exact test with the partner's radius and applies the law.  Results go
+// to the node's id (padding ids keep the zeros set at creation).
 template <typename T>
-__global__ void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
+__global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
 {
-    const int64_t p0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p0 >= G.start[nb]) return;
-    const int64_t nn = G.nn;
+    __shared__ int32_t queue[CF_QUEUE * CF_BLOCK];
+    int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * CF_BLOCK]
+    const int64_t p0 = blockIdx.x * (int64_t)CF_BLOCK + threadIdx.x;
+    // no early exit: every lane reaches the wave-wide evaluations
+    const bool live = p0 < G.start[nb];
+    const int64_t pm = live ? p0 : 0;
+    const double4 me = G.spr[pm], mv = G.svr[pm];
+    const int rod = (int)me.w;
+    const double x[3] = {me.x, me.y, me.z}, v[3] = {mv.x, mv.y, mv.z};
+    const double ra = mv.w;
+    const double rs = ra + G.rmax, rs2 = rs * rs * (1.0 + 1e-9);
+    const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
     double f0 = 0, f1 = 0, f2 = 0, pot = 0;
-    {
-        const double4 me = G.spr[p0], mv = G.svr[p0];
-        const int rod = (int)mv.w;
-        const double x[3] = {me.x, me.y, me.z}, v[3] = {mv.x, mv.y, mv.z};
-        const double ra = me.w;
-        const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
-        const int64_t cx = cell_of(x[0], G.org[0], G.inv_cell), cy = cell_of(x[1], G.org[1], G.inv_cell),
-                      cz = cell_of(x[2], G.org[2], G.inv_cell);
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int row = (wrap_cell(cz + dz, G.gz) * G.gy + wrap_cell(cy + dy, G.gy)) * G.gx;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int b = row + wrap_cell(cx + dx, G.gx);
-                    const int32_t p1 = G.start[b + 1];
-                    for (int32_t p = G.start[b]; p < p1; ++p) {
-                        const double4 q = G.spr[p];
-                        const double e0 = x[0] - q.x, e1 = x[1] - q.y, e2 = x[2] - q.z;
-                        const double d2 = e0 * e0 + e1 * e1 + e2 * e2, reach = ra + q.w;
-                        if (!(d2 < reach * reach)) continue;
-                        const double4 u = G.svr[p];
-                        if ((int)u.w == rod) continue;
-                        const double dist = sqrt(d2);
-                        const double delta = reach - dist;
-                        if (!(delta > 0.0)) continue;
-                        pot += 0.25 * k * delta * delta;
-                        if (!(dist > 0.0)) continue;   // coincident centres: no direction
-                        const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
-                        const double r0 = v[0] - u.x, r1 = v[1] - u.y, r2 = v[2] - u.z;
-                        const double vn = n0 * r0 + n1 * r1 + n2 * r2;
-                        const double fn = delta * (k - c * vn);
-                        if (!(fn > 0.0)) continue;
-                        const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
-                        const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-                        const double gf = mu * fn / (sp > vs ? sp : vs);
-                        f0 += fn * n0 - gf * t0;
-                        f1 += fn * n1 - gf * t1;
-                        f2 += fn * n2 - gf * t2;
-                    }
-                }
+    int nq = 0;
+
+    auto evaluate = [&](int32_t p) {
+        const double4 q = G.spr[p], u = G.svr[p];
+        const double e0 = x[0] - q.x, e1 = x[1] - q.y, e2 = x[2] - q.z;
+        const double d2 = e0 * e0 + e1 * e1 + e2 * e2, reach = ra + u.w;
+        if (!(d2 < reach * reach)) return;
+        const double dist = sqrt(d2);
+        const double delta = reach - dist;
+        if (!(delta > 0.0)) return;
+        pot += 0.25 * k * delta * delta;
+        if (!(dist > 0.0)) return;   // coincident centres: no direction
+        const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
+        const double r0 = v[0] - u.x, r1 = v[1] - u.y, r2 = v[2] - u.z;
+        const double vn = n0 * r0 + n1 * r1 + n2 * r2;
+        const double fn = delta * (k - c * vn);
+        if (!(fn > 0.0)) return;
+        const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
+        const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        const double gf = mu * fn / (sp > vs ? sp : vs);
+        f0 += fn * n0 - gf * t0;
+        f1 += fn * n1 - gf * t1;
+        f2 += fn * n2 - gf * t2;
+    };
+
+    Sweep sw(G, cell_of(x[0], G.org[0], G.inv_cell), cell_of(x[1], G.org[1], G.inv_cell),
+             cell_of(x[2], G.org[2], G.inv_cell));
+    bool done = !live || !sw.next(G);
+    for (;;) {
+        while (!done && nq <= CF_QUEUE - CF_GROUP) {
+            const double4 *const q = G.spr + sw.p;
+            double4 r[CF_GROUP];
+#pragma unroll
+            for (int u = 0; u < CF_GROUP; ++u) r[u] = q[u];
+#pragma unroll
+            for (int u = 0; u < CF_GROUP; ++u) {
+                const double e0 = x[0] - r[u].x, e1 = x[1] - r[u].y, e2 = x[2] - r[u].z;
+                const bool ok = (sw.p + u < sw.pe) & (e0 * e0 + e1 * e1 + e2 * e2 < rs2) & ((int)r[u].w != rod);
+                mine[nq * CF_BLOCK] = sw.p + u;   // nq < CF_QUEUE: a free slot, kept only if it passed
+                nq += (int)ok;
             }
+            sw.p += CF_GROUP;
+            if (sw.p >= sw.pe) done = !sw.next(G);
+        }
+        for (int j = 0; j < nq; ++j) evaluate(mine[j * CF_BLOCK]);
+        nq = 0;
+        if (!__any(!done)) break;
     }
+    if (!live) return;
     const int64_t id = G.sid[p0];
     G.force[id] = f0;
     G.force[G.nid + id] = f1;
     G.force[2 * G.nid + id] = f2;
     G.pot[id] = pot;
 }
-
 
 // ---------------------------------------------------------------- capsules
 // Mode 2: every element is a capsule, the segment between its nodes A (node
@@ -479,17 +553,12 @@ __global__ void seg_fill_kernel(const DevBatch<T> B, const ContactGrid G, double
 // element taking the exact negative, so the two feel opposite forces to the
 // last bit.  The force on the element goes to its nodes as (1 - s) and s; a
 // quarter of k delta^2 per ordered pair is the element's potential share.
-constexpr int SEG_BLOCK = 256;
-constexpr int SEG_QUEUE = 32;   // survivors a lane holds (LDS: 32 KB per workgroup)
-constexpr int SEG_GROUP = 4;    // candidates screened together
-static_assert(SEG_GROUP <= SEG_CULL_PAD, "a group may read up to SEG_GROUP - 1 records past the last element");
-
 template <typename T>
-__global__ __launch_bounds__(SEG_BLOCK) void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
+__global__ __launch_bounds__(CF_BLOCK) void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
 {
-    __shared__ int32_t queue[SEG_QUEUE * SEG_BLOCK];
-    int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * SEG_BLOCK]
-    const int64_t p0 = blockIdx.x * (int64_t)SEG_BLOCK + threadIdx.x;
+    __shared__ int32_t queue[CF_QUEUE * CF_BLOCK];
+    int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * CF_BLOCK]
+    const int64_t p0 = blockIdx.x * (int64_t)CF_BLOCK + threadIdx.x;
     // no early exit: every lane reaches the wave-wide drains
     const bool live = p0 < G.start[nb];
     const int64_t pm = live ? p0 : 0;
@@ -550,59 +619,32 @@ __global__ __launch_bounds__(SEG_BLOCK) void seg_force_kernel(const DevBatch<T> 
         fb0 += sp_ * f0; fb1 += sp_ * f1; fb2 += sp_ * f2;
     };
 
-    // the sweep: ranges of sorted positions, 27 buckets (or 9 rows of three
-    // contiguous x buckets) in bucket order; p..pe is the current one
-    const int64_t cx = cell_of(0.5 * (ua.x + ub.x), G.org[0], G.inv_cell),
-                  cy = cell_of(0.5 * (ua.y + ub.y), G.org[1], G.inv_cell),
-                  cz = cell_of(0.5 * (ua.z + ub.z), G.org[2], G.inv_cell);
-    const int wx = wrap_cell(cx, G.gx);
-    const bool run = wx >= 1 && wx + 1 < G.gx;
-    int ri = 0;
-    int32_t p = 0, pe = 0;
-    auto next_range = [&]() -> bool {
-        while (ri < 27) {
-            const int r = ri / 3;
-            const int row = (wrap_cell(cz + r / 3 - 1, G.gz) * G.gy + wrap_cell(cy + r % 3 - 1, G.gy)) * G.gx;
-            if (run) {
-                p = G.start[row + wx - 1];
-                pe = G.start[row + wx + 2];
-                ri += 3;
-            } else {
-                const int b = row + wrap_cell(cx + ri % 3 - 1, G.gx);
-                p = G.start[b];
-                pe = G.start[b + 1];
-                ri += 1;
-            }
-            if (p < pe) return true;
-        }
-        return false;
-    };
-    bool done = !live || !next_range();
+    Sweep sw(G, cell_of(0.5 * (ua.x + ub.x), G.org[0], G.inv_cell), cell_of(0.5 * (ua.y + ub.y), G.org[1], G.inv_cell),
+             cell_of(0.5 * (ua.z + ub.z), G.org[2], G.inv_cell));
+    bool done = !live || !sw.next(G);
     for (;;) {
-        while (!done && nq <= SEG_QUEUE - SEG_GROUP) {
-            // the records of p .. p + 3; those past pe (the array holds a group
-            // more than the elements) are read and masked
-            const float4 *const q = G.cull + 2 * (int64_t)p;
-            float4 q0[SEG_GROUP], q1[SEG_GROUP];
+        while (!done && nq <= CF_QUEUE - CF_GROUP) {
+            const float4 *const q = G.cull + 2 * (int64_t)sw.p;
+            float4 q0[CF_GROUP], q1[CF_GROUP];
 #pragma unroll
-            for (int u = 0; u < SEG_GROUP; ++u) {
+            for (int u = 0; u < CF_GROUP; ++u) {
                 q0[u] = q[2 * u];
                 q1[u] = q[2 * u + 1];
             }
 #pragma unroll
-            for (int u = 0; u < SEG_GROUP; ++u) {
+            for (int u = 0; u < CF_GROUP; ++u) {
                 // half extents: x in the first record's w, y and z in the second's x and y
                 const bool box = (fabsf(mc.x - q0[u].x) < ex + q0[u].w) & (fabsf(mc.y - q0[u].y) < ey + q1[u].x)
                                & (fabsf(mc.z - q0[u].z) < ez + q1[u].y);
                 const int qe = __float_as_int(q1[u].w);   // the element itself fails both bounds
                 const bool pair = (__float_as_int(q1[u].z) != rod) | (qe >= next) | (qe <= prev);
-                mine[nq * SEG_BLOCK] = p + u;   // nq < SEG_QUEUE: a free slot, kept only if it passed
-                nq += (int)((p + u < pe) & box & pair);
+                mine[nq * CF_BLOCK] = sw.p + u;   // nq < CF_QUEUE: a free slot, kept only if it passed
+                nq += (int)((sw.p + u < sw.pe) & box & pair);
             }
-            p += SEG_GROUP;
-            if (p >= pe) done = !next_range();
+            sw.p += CF_GROUP;
+            if (sw.p >= sw.pe) done = !sw.next(G);
         }
-        for (int j = 0; j < nq; ++j) evaluate(mine[j * SEG_BLOCK]);
+        for (int j = 0; j < nq; ++j) evaluate(mine[j * CF_BLOCK]);
         nq = 0;
         if (!__any(!done)) break;
     }
@@ -664,13 +706,14 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
         hipLaunchKernelGGL(contact_scatter_ids, dim3(gn), dim3(bs), 0, s, g);
         hipLaunchKernelGGL(sort_ids_kernel, dim3(gn), dim3(bs), 0, s, g);
         hipLaunchKernelGGL((seg_fill_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, nb);
-        hipLaunchKernelGGL((seg_force_kernel<T>), dim3((unsigned)((g.nn + SEG_BLOCK - 1) / SEG_BLOCK)),
-                           dim3(SEG_BLOCK), 0, s, b, g, nb);
+        hipLaunchKernelGGL((seg_force_kernel<T>), dim3((unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK)),
+                           dim3(CF_BLOCK), 0, s, b, g, nb);
         hipLaunchKernelGGL((seg_nodes_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g);
     } else {
         hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
         hipLaunchKernelGGL(contact_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
-        hipLaunchKernelGGL((contact_force_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, nb);
+        hipLaunchKernelGGL((contact_force_kernel<T>), dim3((unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK)),
+                           dim3(CF_BLOCK), 0, s, b, g, nb);
     }
     return hipGetLastError();
 }

@@ -146,16 +146,17 @@ struct ContactGrid {
     int64_t nid;       // node ids: n_slots + n_rods (the stride of force, pot and xabs)
     int gx, gy, gz;    // cells per axis of the wrapped grid, each >= 3
     double inv_cell;   // 1 / cell size
+    double rmax;       // the largest rod radius
     double org[3];     // grid origin (the initial extent's lower corner)
     int32_t *count;    // [gx gy gz] nodes per bucket; zero between passes
     int32_t *start;    // [gx gy gz + 1] first sorted position of each bucket
     int32_t *chunk;    // [ceil(gx gy gz / 1024)] chunk totals of the prefix sum
     int32_t *bucket;   // [nn] a node's bucket
     int32_t *rank;     // [nn] its rank within the bucket, -1 for padding slots
-    double4 *spr;      // [nn] position and radius in bucket order
-    double4 *svr;      // [nn] velocity and rod (as a double) in bucket order
+    double4 *spr;      // mode 1: [nn + CONTACT_PAD] position and rod (as a double) in bucket order
+    double4 *svr;      // mode 1: [nn] velocity and radius in bucket order
     int32_t *sid;      // [nn] node ids in bucket order
-    // mode 2: [2 (nn + SEG_CULL_PAD)] screening records in bucket order, two float4 per element:
+    // mode 2: [2 (nn + CONTACT_PAD)] screening records in bucket order, two float4 per element:
     // its capsule's bounding box (centre relative to org, half extents), rod, element
     float4 *cull;
     double *force;     // [3][nid] contact force by node id
@@ -172,7 +173,7 @@ struct ContactGrid {
     double *fseg;      // [6][nn] each element's force shares of its nodes A and B
     double cell_len;   // mode 2: the longest element the grid allows for (the cell holds it)
 };
-constexpr int64_t SEG_CULL_PAD = 4;   // screening records past the last element (one group)
+constexpr int64_t CONTACT_PAD = 4;   // sorted records past the last item (a screening group reads past a range)
 constexpr int64_t CONTACT_MAX_BUCKETS = 4096 * 1024;   // chunk totals fit one workgroup's prefix sum
 
 // Fill g.force and g.pot for positions advanced by `drift` seconds from the

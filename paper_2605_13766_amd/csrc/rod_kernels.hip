@@ -342,8 +342,10 @@ __device__ inline bool wall_reach(const DevBatch<T> &B, const T *wl, T reach, T 
 // extended step with planar walls, with or without connections, which needs
 // every node's position in every substep (FP32: three more LDS columns).
 // Separate instantiations, so each kernel keeps the registers and LDS of what
-// it computes.  FP32 wall tiles run 3 waves per SIMD (2 at 8 waves a tile:
-// their LDS admits one workgroup per CU).  Each extension a batch lacks contributes an exact zero
+// it computes.  FP32 wall and connection tiles run 3 waves per SIMD (wall
+// tiles of 8 waves 2: their LDS admits one workgroup per CU); at 4 the FP32
+// connection step, whose connection laws work in FP64, spilled 44 VGPRs and
+// took 1.6 times as long on the 4096-bot swarm.  Each extension a batch lacks contributes an exact zero
 // (zero magnetization, amplitude or gravity), so the extended kernel reproduces
 // the plain one bit for bit on a plain batch.  Its multi-wave FP64 tiles and
 // all its FP32 tiles run one wave per SIMD fewer than the plain step's.
@@ -352,7 +354,8 @@ constexpr int step_waves_per_simd()
 {
     return sizeof(T) == 8 ? ((W == 8 || (KIND > 0 && W > 1)) ? 2 : ROD_F64_WAVES_PER_SIMD)
                           : (KIND == 3 ? (W == 8 ? 2 : ROD_F32_WAVES_PER_SIMD - 2)
-                                       : KIND > 0 ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
+                                       : KIND == 2 ? ROD_F32_WAVES_PER_SIMD - 2
+                                       : KIND == 1 ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
 }
 
 template <typename T, int W, int KIND>

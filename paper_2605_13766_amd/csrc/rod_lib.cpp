@@ -823,6 +823,7 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     g.cell_len = 1.25 * lmax;
     const double cell = g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax;
     g.inv_cell = 1.0 / cell;
+    g.rmax = rmax;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (size_t j = 0; j < h.pos.size() / 3; ++j)
         for (int a = 0; a < 3; ++a) {
@@ -892,9 +893,11 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMemcpy(d_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         // a group of screening records more than the elements: the force pass
         // reads whole groups and masks the records past a range's end
-        HIPCHK(hipMalloc((void **)&g.cull, 2 * (g.nn + rodk::SEG_CULL_PAD) * sizeof(float4)));
+        HIPCHK(hipMalloc((void **)&g.cull, 2 * (g.nn + rodk::CONTACT_PAD) * sizeof(float4)));
     } else {
-        HIPCHK(hipMalloc((void **)&g.spr, g.nn * sizeof(double4)));
+        // a group of records more than the nodes: the force pass reads whole
+        // groups and masks the records past a range's end
+        HIPCHK(hipMalloc((void **)&g.spr, (g.nn + rodk::CONTACT_PAD) * sizeof(double4)));
         HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
     }
     HIPCHK(hipMalloc((void **)&g.force, 3 * g.nid * sizeof(double)));

@@ -95,3 +95,28 @@ def test_capsule_pile_full_size_momentum():
     print("momentum change", np.abs(p1 - p0).max(), "scale", scale, "contact potential", e[:, 4].sum(), flush=True)
     assert np.abs(p1 - p0).max() <= 1e-13 * scale
     assert e[:, 4].sum() > 0.0
+
+
+def test_straight_rod_steps_as_without_contact():
+    """Elements 0.35 of a diameter long: the elements of one rod that overlap
+    as capsules in the straight state are excluded by the self-contact rule
+    (the next/prev bounds), so capsule contact adds no force: the rod steps bit
+    for bit as with node-sphere contact (same kernel, and a rod's nodes never
+    touch each other), in both precisions, with no contact potential."""
+    from rodcases import single
+    R = _rod()
+    nodes, Q = W.straight_rod(20, 0.07, direction=(1, 0, 0), d1=(0, 1, 0))
+    rng = np.random.default_rng(6)
+    inp = single(nodes, Q, radius=OS.RAD, vel=rng.normal(scale=1e-3, size=nodes.shape))
+    inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = 20.0, 1.0, 0.3, 1e-4
+    for prec in ("f64", "f32"):
+        out = []
+        for mode in (2, 1):
+            a = inp.copy()
+            a.rod_contact = mode
+            print(f"case: straight rod 20 elements, rod_contact={mode}, {prec}, 300 steps", flush=True)
+            with R.RodBatch(a, precision=prec, substeps=1) as b:
+                b.step(300)
+                out.append(b.get_state()[:4] + (b.energy(),))
+        assert all(np.array_equal(x, y) for x, y in zip(*out)), prec
+        assert out[0][4][0, 4] == 0.0
