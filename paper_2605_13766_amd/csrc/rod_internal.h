@@ -192,7 +192,8 @@ hipError_t launch_energy(const DevBatch<float> &b, double *out, hipStream_t s, c
 // Largest number of co-resident workgroups of the step kernel (occupancy x CUs).
 int step_resident_groups(int precision_f32, int waves);
 // LDS bytes per workgroup of the step kernel: static, plus the dynamic table of
-// the node-interaction kinds (2: connections, 3: walls) with conn_nodes
+// the node-interaction kinds (2: connections, 3: walls or contact with
+// connections, 4: walls or contact without) with conn_nodes
 // connected nodes per tile.
 size_t step_lds_bytes(int precision_f32, int waves, int kind, int conn_nodes);
 

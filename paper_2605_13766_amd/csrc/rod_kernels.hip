@@ -339,8 +339,10 @@ __device__ inline bool wall_reach(const DevBatch<T> &B, const T *wl, T reach, T 
 // KIND 0: the plain step.  KIND 1: the extended step, for batches with a
 // magnetic couple, gravity or muscle torques.  KIND 2: the extended step with
 // rod-rod connections (connected node positions in an LDS table).  KIND 3: the
-// extended step with planar walls, with or without connections, which needs
-// every node's position in every substep (FP32: three more LDS columns).
+// extended step with planar walls or rod contact and connections, which needs
+// every node's position in every substep (FP32: three more LDS columns).  KIND
+// 4: the same without connections, their code compiled out (it held registers
+// the wall and contact batches never use).
 // Separate instantiations, so each kernel keeps the registers and LDS of what
 // it computes.  FP32 wall and connection tiles run 3 waves per SIMD (wall
 // tiles of 8 waves 2: their LDS admits one workgroup per CU); at 4 the FP32
@@ -353,7 +355,7 @@ template <typename T, int W, int KIND>
 constexpr int step_waves_per_simd()
 {
     return sizeof(T) == 8 ? ((W == 8 || (KIND > 0 && W > 1)) ? 2 : ROD_F64_WAVES_PER_SIMD)
-                          : (KIND == 3 ? (W == 8 ? 2 : ROD_F32_WAVES_PER_SIMD - 2)
+                          : (KIND >= 3 ? (W == 8 ? 2 : ROD_F32_WAVES_PER_SIMD - 2)
                                        : KIND == 2 ? ROD_F32_WAVES_PER_SIMD - 2
                                        : KIND == 1 ? ROD_F32_WAVES_PER_SIMD - 1 : ROD_F32_WAVES_PER_SIMD);
 }
@@ -365,7 +367,8 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
 {
     constexpr bool EXT = KIND > 0;     // magnetic couple, gravity, muscle torques
     constexpr bool NODE = KIND >= 2;   // and node interactions (connections, walls)
-    constexpr bool WALL = KIND == 3;   // planar walls: every node's position
+    constexpr bool WALL = KIND >= 3;   // planar walls or rod contact: every node's position
+    constexpr bool CONN = KIND == 2 || KIND == 3;   // connections (compiled out of KIND 4)
     constexpr bool POS = sizeof(T) == 8;   // node positions in memory
     constexpr int TL = 64 * W;
     constexpr int NA = 13;     // from the left: frame (9), length, internal force (3)
@@ -378,8 +381,8 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
            C_INV_MT, C_FX, C_FY, C_FZ, C_CX, C_CY, C_CZ, C_INV_M, C_LH, C_INV_LH, C_S1, C_S3,
            C_MX, C_MY, C_MZ,     // magnetization times rest length (EXT only)
            C_AX, C_AY, C_AZ,     // muscle amplitude times axis (EXT only)
-           C_RAD,                // rod radius (KIND 3)
-           C_PX, C_PY, C_PZ };   // node i's position (KIND 3, FP32; FP64 has it in registers)
+           C_RAD,                // rod radius (KIND 3, 4)
+           C_PX, C_PY, C_PZ };   // node i's position (KIND 3, 4, FP32; FP64 has it in registers)
     constexpr int N_C = WALL ? (POS ? C_RAD + 1 : C_PZ + 1) : (EXT ? C_AZ + 1 : C_MX);
     // One LDS block in a fixed order: the small wave-edge exchange buffers first,
     // so their addresses fit the 8-bit offsets of ds_write2/ds_read2 and need no
@@ -389,7 +392,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
         T lxb[NL * NB];
         double phs[2 * TL];        // couple phase increment: sin, cos
         double mph[EXT ? 2 * TL : 1];   // muscle phase increment: sin, cos (EXT only)
-        T wls[WALL ? 4 * DEV_MAX_WALLS : 1];   // walls (n, d), d in the tile's frame (KIND 3)
+        T wls[WALL ? 4 * DEV_MAX_WALLS : 1];   // walls (n, d), d in the tile's frame (KIND 3, 4)
         T cst[N_C * TL];
     };
     __shared__ Shared sh;
@@ -570,7 +573,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 const T e3[3] = {d0, d1, d2};
                 T lf[3];
                 from_left<W>(e3, lf, lxa, wave, wl);
-                if (B.conn_idx) {
+                if (CONN && B.conn_idx) {
                     X0 = first ? B.rod_org[rr] + (double)t0 : (double)lf[0];
                     X1 = first ? B.rod_org[B.n_rods + rr] + (double)t1 : (double)lf[1];
                     X2 = first ? B.rod_org[2 * B.n_rods + rr] + (double)t2 : (double)lf[2];
@@ -600,7 +603,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                     cw[C_PX * TL] = x0 + hh * v0; cw[C_PY * TL] = x1 + hh * v1; cw[C_PZ * TL] = x2 + hh * v2;
                 }
             }
-            if (B.conn_idx) {
+            if (CONN && B.conn_idx) {
                 const int rows = B.conn_nodes;
                 ci = B.conn_idx[s];
                 cn = last ? B.conn_idx[NS + s] : -1;
@@ -682,7 +685,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
             // ---- connection forces on node i and node n (pre-kick velocities)
             T fc0 = 0, fc1 = 0, fc2 = 0, gc0 = 0, gc1 = 0, gc2 = 0;
             if constexpr (NODE) {
-                if (B.conn_idx) {
+                if (CONN && B.conn_idx) {
                     const int rows = B.conn_nodes;
                     if (ci >= 0) { tab[3 * rows + ci] = v0; tab[4 * rows + ci] = v1; tab[5 * rows + ci] = v2; }
                     if (cn >= 0) { tab[3 * rows + cn] = u0; tab[4 * rows + cn] = u1; tab[5 * rows + cn] = u2; }
@@ -796,7 +799,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                     T *cw = cst + cofs;
                     cw[C_PX * TL] += dd * v0; cw[C_PY * TL] += dd * v1; cw[C_PZ * TL] += dd * v2;
                 }
-                if (B.conn_idx) {
+                if (CONN && B.conn_idx) {
                     const int rows = B.conn_nodes;
                     const double D = dd;
                     if (ci >= 0) { tab[ci] += D * v0; tab[rows + ci] += D * v1; tab[2 * rows + ci] += D * v2; }
@@ -1074,8 +1077,10 @@ static hipError_t launch_w(const DevBatch<T> &b, int n_sub, int grid, hipStream_
         // node interactions: the FP64 connection table (6 rows per connected
         // node), and for FP32 the scratch of the starting prefix sum (3 per lane)
         const size_t lds = step_dyn_lds(sizeof(T) == 4, W, b.conn_idx ? b.conn_nodes : -1);
-        if (b.n_walls || b.cforce)
+        if ((b.n_walls || b.cforce) && b.conn_idx)
             hipLaunchKernelGGL((rod_step_kernel<T, W, 3>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
+        else if (b.n_walls || b.cforce)
+            hipLaunchKernelGGL((rod_step_kernel<T, W, 4>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
         else
             hipLaunchKernelGGL((rod_step_kernel<T, W, 2>), dim3(grid), dim3(64 * W), lds, s, b, n_sub);
     } else if (b.ext) {
@@ -1196,11 +1201,13 @@ size_t step_lds_bytes(int precision_f32, int waves, int kind, int conn_nodes)
 {
     size_t st = 0, dyn = 0;
     if (precision_f32) {
-        st = kind == 3 ? static_lds_t<float, 3>(waves) : kind == 2 ? static_lds_t<float, 2>(waves)
+        st = kind == 4 ? static_lds_t<float, 4>(waves) : kind == 3 ? static_lds_t<float, 3>(waves)
+           : kind == 2 ? static_lds_t<float, 2>(waves)
            : kind == 1 ? static_lds_t<float, 1>(waves) : static_lds_t<float, 0>(waves);
         if (kind >= 2) dyn = step_dyn_lds(true, waves, kind == 2 || conn_nodes > 0 ? conn_nodes : -1);
     } else {
-        st = kind == 3 ? static_lds_t<double, 3>(waves) : kind == 2 ? static_lds_t<double, 2>(waves)
+        st = kind == 4 ? static_lds_t<double, 4>(waves) : kind == 3 ? static_lds_t<double, 3>(waves)
+           : kind == 2 ? static_lds_t<double, 2>(waves)
            : kind == 1 ? static_lds_t<double, 1>(waves) : static_lds_t<double, 0>(waves);
         if (kind >= 2) dyn = step_dyn_lds(false, waves, conn_nodes);
     }

@@ -1289,7 +1289,8 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->grid = b->n_tiles;
     {
         // the kernel this batch runs must fit the workgroup's LDS
-        const int kind = !b->ext ? 0 : (b->n_walls > 0 || b->rod_contact) ? 3 : b->n_conn > 0 ? 2 : 1;
+        const int kind = !b->ext ? 0
+                       : (b->n_walls > 0 || b->rod_contact) ? (b->n_conn > 0 ? 3 : 4) : b->n_conn > 0 ? 2 : 1;
         int dev = 0, limit = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) limit = 65536;
