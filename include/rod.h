@@ -192,7 +192,7 @@ typedef struct {
      * a folded rod).  The grid bins element midpoints in cells of 1.25 times
      * the longest rest length plus twice the largest radius: contacts of
      * elements stretched by more than a quarter of their rest length can be
-     * missed.
+     * missed, and such a rod is flagged (ROD_FLAG_STRETCHED, rod_get_flags).
      * Both modes: each step is one launch sequence, so substeps must be 0 or
      * 1 (one step per launch); FP32 batches sum their node positions along
      * each rod in FP64 for the grid; each grid cell's entries are sorted by
@@ -301,8 +301,14 @@ int rod_get_state(rod_batch *b, double *position, double *velocity, double *dire
 int rod_set_state(rod_batch *b, const double *position, const double *velocity,
                   const double *director, const double *omega, double t, void *stream);
 
-/* Per-rod non-finite flags (host int32 [R]: 1 = NaN/Inf seen at the end of a
- * launch).  Synchronises `stream`. */
+/* Per-rod flags (host int32 [R], bits): ROD_FLAG_NONFINITE = NaN/Inf seen at
+ * the end of a launch (the synchronising calls then return ROD_ENONFINITE);
+ * ROD_FLAG_STRETCHED = with capsule contact (rod_contact = 2), an element of
+ * the rod was longer than 1.25 times the longest rest length when the contact
+ * grid binned it, so contacts of that element may have been missed (the state
+ * stays valid; no call fails for it).  Synchronises `stream`.  rod_set_state
+ * clears both. */
+enum { ROD_FLAG_NONFINITE = 1, ROD_FLAG_STRETCHED = 2 };
 int rod_get_flags(rod_batch *b, int32_t *nonfinite, void *stream);
 
 /* Sizes and the chosen launch shape: info[0] rods, [1] elements, [2] tiles,

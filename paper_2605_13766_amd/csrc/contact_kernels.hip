@@ -11,6 +11,7 @@
 // order (each bucket sorted by node id), and let every node sum its contacts
 // over the 27 buckets around it;
 // the step kernel adds the forces at its kick.
+#include "rod.h"
 #include "rod_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -511,6 +512,9 @@ __global__ void seg_bin_kernel(const DevBatch<T> B, const ContactGrid G, double 
         G.pot[s] = 0.0;
         return;
     }
+    // longer than the grid's cells allow for: contacts of this element may be missed
+    const double l2 = (b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]);
+    if (l2 > G.cell_len * G.cell_len) atomicOr(&B.nonfinite[rod], ROD_FLAG_STRETCHED);
     const int bk = (wrap_cell(cell_of(0.5 * (a[2] + b[2]), G.org[2], G.inv_cell), G.gz) * G.gy
                     + wrap_cell(cell_of(0.5 * (a[1] + b[1]), G.org[1], G.inv_cell), G.gy)) * G.gx
                  + wrap_cell(cell_of(0.5 * (a[0] + b[0]), G.org[0], G.inv_cell), G.gx);

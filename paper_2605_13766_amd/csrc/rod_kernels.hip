@@ -16,6 +16,7 @@
 // elements and Voronoi points; time stepping per Results,
 // "Performance-oriented software design" (position Verlet with the
 // kinematic constraints imposed after every stage).
+#include "rod.h"
 #include "rod_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -887,7 +888,7 @@ void rod_step_kernel(const DevBatch<T> B, int n_sub)
                 B.tail[TVX * B.n_rods + rr_o] = u0; B.tail[TVY * B.n_rods + rr_o] = u1; B.tail[TVZ * B.n_rods + rr_o] = u2;
                 ok = ok && finite3(u0, u1, u2);
             }
-            if (!ok) B.nonfinite[rr_o] = 1;
+            if (!ok) atomicOr(&B.nonfinite[rr_o], ROD_FLAG_NONFINITE);   // keeps the other flag bits
         }
         if constexpr (W > 1) __syncthreads();   // LDS reuse by the next tile
     }

@@ -958,7 +958,7 @@ int check_flags(rod_batch *b, hipStream_t s, std::vector<int32_t> *out = nullptr
     HIPCHK(hipStreamSynchronize(s));
     if (out) *out = f;
     for (int r = 0; r < b->R; ++r)
-        if (f[r]) return fail(ROD_ENONFINITE, "rod " + std::to_string(r) + " has a non-finite state");
+        if (f[r] & ROD_FLAG_NONFINITE) return fail(ROD_ENONFINITE, "rod " + std::to_string(r) + " has a non-finite state");
     return ROD_OK;
 }
 

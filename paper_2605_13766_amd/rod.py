@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("ROD_LIBRARY") or os.path.join(HERE, "librod.so")
 ROD_OK, ROD_EINVAL, ROD_ENOMEM, ROD_EDEVICE, ROD_ENONFINITE, ROD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ROD_F64, ROD_F32 = 0, 1
 ROD_MAX_ELEMS = 512
+ROD_FLAG_NONFINITE, ROD_FLAG_STRETCHED = 1, 2   # bits of flags()
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

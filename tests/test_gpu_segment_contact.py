@@ -120,3 +120,33 @@ def test_straight_rod_steps_as_without_contact():
                 out.append(b.get_state()[:4] + (b.energy(),))
         assert all(np.array_equal(x, y) for x, y in zip(*out)), prec
         assert out[0][4][0, 4] == 0.0
+
+
+def test_stretched_element_is_flagged():
+    """An element longer than the capsule grid allows for (1.25 x the longest
+    rest length) sets ROD_FLAG_STRETCHED on its rod at the next contact pass;
+    no call fails for it, other rods stay unflagged, rod_set_state clears it."""
+    R = _rod()
+    inp = _pile(seed=64)
+    for prec in ("f64", "f32"):
+        print(f"case: capsule pile with one element stretched by 40%, {prec}", flush=True)
+        with R.RodBatch(inp, precision=prec, substeps=1) as b:
+            b.step(2)
+            assert not np.any(b.flags() & R.ROD_FLAG_STRETCHED)
+            pos, vel, dr, om, t = b.get_state()
+            r = 5
+            a = inp.node_offset[r]
+            n = inp.n_elems[r]
+            edge = pos[a + n] - pos[a + n - 1]
+            pos[a + n] = pos[a + n - 1] + 1.4 * edge            # the rod's last element 40% longer
+            b.set_state(pos, vel, dr, om, t)
+            b.step(1)
+            f = b.flags()
+            assert f[r] & R.ROD_FLAG_STRETCHED
+            assert not np.any(np.delete(f, r))
+            assert not np.any(f & R.ROD_FLAG_NONFINITE)
+            b.get_state()                                      # no error: the state is valid
+            b.energy()
+            pos[a + n] = pos[a + n - 1] + edge
+            b.set_state(pos, vel, dr, om, t)
+            assert not np.any(b.flags())
