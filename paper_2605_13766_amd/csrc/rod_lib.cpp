@@ -1329,27 +1329,48 @@ int rod_step(rod_batch *b, int64_t n_steps, void *stream)
         b->steps += n_steps;
         return ROD_OK;
     }
-    auto it = b->graphs.find(n_steps);
-    if (it == b->graphs.end()) {
-        if (b->graphs.size() >= 16) free_graphs(b);
-        HIPCHK(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_steps(b, n_steps, b->capture_stream);
-        hipGraph_t g = nullptr;
-        hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+    // A graph holds at most 64 step launches (a multiple of the substeps per
+    // launch, so the launches split the steps exactly as one long sequence
+    // would): rod_step(n) replays it as often as it fits, then a graph of the
+    // rest.  One-step launches (rod contact) would otherwise put some ten
+    // kernel nodes per step into one graph.
+    const int64_t chunk = b->substeps > 0 ? std::min<int64_t>(n_steps, 64 * (int64_t)b->substeps) : n_steps;
+    auto graph_of = [&](int64_t steps, hipGraphExec_t &x) -> int {
+        auto it = b->graphs.find(steps);
+        if (it == b->graphs.end()) {
+            if (b->graphs.size() >= 16) free_graphs(b);
+            HIPCHK(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_steps(b, steps, b->capture_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(ROD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+            hipGraphExec_t e = nullptr;
+            ec = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+            if (ec != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(ROD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+            }
+            it = b->graphs.emplace(steps, std::make_pair(g, e)).first;
         }
-        if (ec != hipSuccess) return fail(ROD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
-        hipGraphExec_t x = nullptr;
-        ec = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        if (ec != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return fail(ROD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
-        }
-        it = b->graphs.emplace(n_steps, std::make_pair(g, x)).first;
+        x = it->second.second;
+        return ROD_OK;
+    };
+    const int64_t reps = n_steps / chunk, rest = n_steps % chunk;
+    hipGraphExec_t xc = nullptr, xr = nullptr;
+    int rc = graph_of(chunk, xc);
+    if (!rc && rest) rc = graph_of(rest, xr);
+    if (rc) return rc;
+    if (rest && !b->graphs.count(chunk)) {
+        // capturing the rest evicted the chunk's graph (cache full): capture it again
+        rc = graph_of(chunk, xc);
+        if (rc) return rc;
     }
-    HIPCHK(hipGraphLaunch(it->second.second, s));
+    for (int64_t k = 0; k < reps; ++k) HIPCHK(hipGraphLaunch(xc, s));
+    if (rest) HIPCHK(hipGraphLaunch(xr, s));
     b->steps += n_steps;
     return ROD_OK;
 }

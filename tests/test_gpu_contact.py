@@ -112,11 +112,12 @@ def test_wrapped_grid_f64():
 
 
 def test_contact_graph_replays():
-    """The same captured 100-step graph replayed five times (with eager work
-    and synchronisations between the replays) against the oracle's 500 steps:
-    every contact pass clears its bucket counts for the next, so replays after
-    the first see a clean grid."""
-    print("case: fibre pile 24 rods, 5 replays of a 100-step graph, FP64", flush=True)
+    """rod_step(100) five times (each a replay of the captured 64-step graph
+    and of the 36-step graph of the rest, with eager work and synchronisations
+    between the calls) against the oracle's 500 steps: every contact pass
+    clears its bucket counts for the next, so replays after the first see a
+    clean grid."""
+    print("case: fibre pile 24 rods, 5 x rod_step(100) by captured graphs, FP64", flush=True)
     import torch
     R = _rod()
     inp = _small_pile(seed=95)
@@ -234,3 +235,27 @@ def test_contact_is_bitwise_repeatable_and_tile_invariant():
             b.step(300)
             f32.append(b.get_state()[:4])
     assert all(np.array_equal(x, y) for x, y in zip(*f32))
+
+
+def test_chunked_graphs_match_direct_launches():
+    """rod_step(n) on a contact batch replays a graph of 64 one-step launches
+    as often as it fits and a graph of the rest (150 = 2 x 64 + 22), bit for
+    bit as the same launches made directly, and again on a second call that
+    reuses both graphs."""
+    import os
+    R = _rod()
+    inp = _small_pile(seed=99)
+    out = []
+    for direct in (False, True):
+        if direct:
+            os.environ["ROD_NO_GRAPH"] = "1"
+        try:
+            print(f"case: fibre pile 24 rods, 2 x 150 steps, {'direct launches' if direct else 'chunked graphs'}", flush=True)
+            with R.RodBatch(inp, precision="f64") as b:
+                b.step(150)
+                b.step(150)
+                out.append(b.get_state()[:4])
+        finally:
+            if direct:
+                del os.environ["ROD_NO_GRAPH"]
+    assert all(np.array_equal(x, y) for x, y in zip(*out))
