@@ -151,14 +151,12 @@ def test_contact_f32_parity():
         assert_norms(norms)
 
 
-def test_contact_edge_cases_f64():
+def _edge_case_input(mode=1):
     """Contact with everything else at once: rods of 1 to 100 elements and of
     different radii (the grid's cells follow the largest), some clamped at
     their base (a clamped node keeps its place whatever presses on it),
     magnetized elements in a rotating field, muscle moments, gravity and a
     floor; rods cross one above the other so that many pairs touch."""
-    print("case: contact edge cases (lengths 1..100, radii, clamps, field, muscles, floor), FP64, 1000 steps",
-          flush=True)
     rng = np.random.default_rng(99)
     lengths = [1, 2, 3, 20, 63, 64, 65, 100, 5, 40]
     nodes_list, Q_list = [], []
@@ -181,7 +179,7 @@ def test_contact_edge_cases_f64():
     inp.gravity = np.array([0.0, 0.0, -9.81])
     inp.walls = np.array([[0.0, 0.0, 1.0, 0.0]])
     inp.wall_k, inp.wall_c, inp.wall_mu, inp.wall_vslip = 20.0, 10.0, 0.3, 0.02
-    inp.rod_contact = 1
+    inp.rod_contact = mode
     ne = int(np.sum(lengths))
     inp.magnetization = np.tile([0.0, 0.0, 1e-4], (ne, 1))
     inp.field = np.array([0.0, 0.0, 0.0, 0.01, 0.0, 0.0, 0.0, 0.01, 0.0])
@@ -192,11 +190,18 @@ def test_contact_edge_cases_f64():
     inp.muscle_freq = np.full(R, 2.0)
     inp.muscle_wavenumber = np.full(R, 10.0)
     inp.muscle_phase = rng.uniform(0, 2 * np.pi, R)
+    return inp
+
+
+def test_contact_edge_cases_f64():
+    print("case: contact edge cases (lengths 1..100, radii, clamps, field, muscles, floor), FP64, 1000 steps",
+          flush=True)
+    inp = _edge_case_input()
     from oracle import rodoracle as ro
     o = ro.Oracle(inp)
     d = o.pos[:, None, :] - o.pos[None, :, :]
-    rod = np.repeat(np.arange(R), np.asarray(lengths) + 1)
-    rr = radii[rod]
+    rod = np.repeat(np.arange(inp.n_rods), np.asarray(inp.n_elems) + 1)
+    rr = inp.radius[rod]
     touching = (np.linalg.norm(d, axis=2) < rr[:, None] + rr[None, :]) & (rod[:, None] != rod[None, :])
     print("pairs in contact at the start", int(touching.sum()) // 2, flush=True)
     assert touching.sum() > 0

@@ -150,3 +150,55 @@ def test_stretched_element_is_flagged():
             pos[a + n] = pos[a + n - 1] + edge
             b.set_state(pos, vel, dr, om, t)
             assert not np.any(b.flags())
+
+
+def test_capsule_edge_cases_f64():
+    """Capsule contact with everything else at once (the node-sphere edge
+    case's rods of 1 to 100 elements, uneven radii, clamps, field, muscles,
+    gravity and a floor), elements 4 mm long against diameters of 4 to 8 mm,
+    so the self-contact rule excludes one to two neighbours on each side."""
+    import test_gpu_contact as GC
+    print("case: capsule edge cases (lengths 1..100, radii, clamps, field, muscles, floor), FP64, 600 steps", flush=True)
+    norms, _ = run_both(GC._edge_case_input(mode=2), 600)
+    assert_norms(norms)
+
+
+def test_capsules_with_connections_and_walls():
+    """Capsule contact together with connections and a floor (the step kernel
+    with connection code): pairs of fibres joined end to end by springs, in
+    both precisions."""
+    import test_gpu_contact as GC
+    inp = GC._linked_pile(seed=67)
+    inp.rod_contact = 2
+    for prec in ("f64", "f32"):
+        print(f"case: capsule pile with end-to-end springs, {prec}, 800 steps", flush=True)
+        norms, _ = run_both(inp, 800, precision=prec)
+        assert_norms(norms)
+
+
+def test_capsules_on_a_wrapped_grid_f64():
+    """Two colliding pairs of long-element rods 2 m apart: the grid's cells
+    per axis are capped by the bucket budget (about 50 cells of extent along x
+    against about 20 buckets), so the grid wraps and far-apart elements share
+    buckets.  (At 20 m the FP64 rounding of the coordinates, 3.5e-15 m, is
+    3.5e-11 of the contact overlap at every step, which the one-ulp bar, taken
+    from a perturbation of the start alone, does not cover.)"""
+    print("case: two capsule crossings 2 m apart (wrapped grid), FP64, 3000 steps", flush=True)
+    a = OS._long_crossing(2)
+    b = OS._long_crossing(2, gap=1e-4, vz=-0.3)
+    inp = a.copy()
+    for f in ("n_elems", "velocity", "director", "omega", "density", "youngs", "shear_modulus", "radius",
+              "shear_coeff", "damping", "bc_start", "bc_end"):
+        setattr(inp, f, np.concatenate([getattr(a, f), getattr(b, f)]))
+    inp.position = np.concatenate([a.position, b.position + np.array([2.0, 0.3, -0.1])])
+    if getattr(a, "rest_length", None) is not None:
+        inp.rest_length = np.concatenate([a.rest_length, b.rest_length])
+    norms, _ = run_both(inp, 3000)
+    assert_norms(norms)
+
+
+def test_capsule_edge_cases_f32():
+    import test_gpu_contact as GC
+    print("case: capsule edge cases, FP32, 600 steps", flush=True)
+    norms, _ = run_both(GC._edge_case_input(mode=2), 600, precision="f32")
+    assert_norms(norms)
