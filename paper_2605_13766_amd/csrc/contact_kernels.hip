@@ -306,6 +306,16 @@ struct Sweep {
     }
 };
 
+// Workgroup index in a renumbering that gives each XCD a contiguous run of
+// workgroups (the hardware deals them out to the 8 XCDs in turn), so each
+// XCD's L2 holds the records of one region of the sorted order.
+__device__ inline int64_t xcd_contiguous_block()
+{
+    const int nb = gridDim.x, x = blockIdx.x % 8, i = blockIdx.x / 8;
+    const int q = nb / 8, r = nb % 8;
+    return (int64_t)x * q + (x < r ? x : r) + i;
+}
+
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
 // around it: the walls' law between two spheres.  Threads take the nodes in
 // bucket order, so neighbouring threads read the same buckets.  The screen
@@ -319,7 +329,7 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
 {
     __shared__ int32_t queue[CF_QUEUE * CF_BLOCK];
     int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * CF_BLOCK]
-    const int64_t p0 = blockIdx.x * (int64_t)CF_BLOCK + threadIdx.x;
+    const int64_t p0 = xcd_contiguous_block() * CF_BLOCK + threadIdx.x;
     // no early exit: every lane reaches the wave-wide evaluations
     const bool live = p0 < G.start[nb];
     const int64_t pm = live ? p0 : 0;
