@@ -2,15 +2,18 @@
 //
 // Results, "Fibrous granular materials" (filaments in frictional contact;
 // the paper names a GPU collision engine as future work and leaves the
-// contact law to its supplement): every node is a sphere of its rod's
-// radius; nodes of different rods that overlap push each other with the
+// contact law to its supplement).  Mode 1: every node is a sphere of its
+// rod's radius; nodes of different rods that overlap push each other with the
 // walls' penalty law (normal force delta (k - c v_n), regularised Coulomb
-// friction).  One pass per step, before the step kernel's launch: bin the
-// nodes (positions after the coming half drift) into a wrapped uniform grid
-// with atomic counts, prefix-sum the counts, scatter the nodes into bucket
-// order (each bucket sorted by node id), and let every node sum its contacts
-// over the 27 buckets around it;
-// the step kernel adds the forces at its kick.
+// friction).  Mode 2: every element is a capsule (its segment dilated by the
+// radius); the same law acts between the closest points of two elements, of
+// different rods or of one rod far enough apart along it, and each element's
+// force goes to its two nodes.  One pass per step, before the step kernel's
+// launch: bin the nodes or element midpoints (positions after the coming half
+// drift) into a wrapped uniform grid with atomic counts, prefix-sum the
+// counts, put the items into bucket order (each bucket sorted by id), and let
+// every item sum its contacts over the 27 buckets around it; the step kernel
+// adds the node forces at its kick.
 #include "rod.h"
 #include "rod_internal.h"
 
@@ -232,17 +235,17 @@ __global__ void contact_sort_kernel(const ContactGrid G)
     const int b = G.bucket[id];
     const int32_t s = G.start[b], e = G.start[b + 1];
     for (int32_t i = s + 1; i < e; ++i) {
-        const int32_t id = G.sid[i];
-        if (G.sid[i - 1] < id) continue;
+        const int32_t key = G.sid[i];
+        if (G.sid[i - 1] < key) continue;
         const double4 a = G.spr[i], c = G.svr[i];
         int32_t j = i - 1;
-        while (j >= s && G.sid[j] > id) {
+        while (j >= s && G.sid[j] > key) {
             G.sid[j + 1] = G.sid[j];
             G.spr[j + 1] = G.spr[j];
             G.svr[j + 1] = G.svr[j];
             --j;
         }
-        G.sid[j + 1] = id;
+        G.sid[j + 1] = key;
         G.spr[j + 1] = a;
         G.svr[j + 1] = c;
     }

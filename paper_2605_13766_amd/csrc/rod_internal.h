@@ -133,13 +133,14 @@ struct DevBatch {
     const double *cpot;
 };
 
-// The contact grid of a batch with rod-rod contact: nodes are binned by a
-// wrapped uniform grid of gx x gy x gz buckets (cell = twice the largest
-// radius, so every pair in contact lies in neighbouring cells; with at least 3
-// cells per axis the 27 cells around a node are 27 different buckets; the
-// counts per axis cover the batch's initial extent, within a bucket budget),
-// counted, prefix-summed and scattered into bucket order; each node then sums
-// its contacts over its 27 neighbouring buckets.
+// The contact grid of a batch with rod-rod contact: nodes (mode 1) or element
+// midpoints (mode 2) are binned by a wrapped uniform grid of gx x gy x gz
+// buckets (cell = twice the largest radius, or 1.25 x the longest rest length
+// plus twice the largest radius, so every pair in contact lies in neighbouring
+// cells; with at least 3 cells per axis the 27 cells around an item are 27
+// different buckets; the counts per axis cover the batch's initial extent,
+// within a bucket budget), counted, prefix-summed and put into bucket order;
+// each item then sums its contacts over its 27 neighbouring buckets.
 struct ContactGrid {
     int mode;          // 1: nodes as spheres; 2: elements as capsules (segments), self-contact included
     int64_t nn;        // items binned: node ids n_slots + n_rods (mode 1), element slots n_slots (mode 2)
@@ -148,19 +149,19 @@ struct ContactGrid {
     double inv_cell;   // 1 / cell size
     double rmax;       // the largest rod radius
     double org[3];     // grid origin (the initial extent's lower corner)
-    int32_t *count;    // [gx gy gz] nodes per bucket; zero between passes
+    int32_t *count;    // [gx gy gz] items per bucket; zero between passes
     int32_t *start;    // [gx gy gz + 1] first sorted position of each bucket
     int32_t *chunk;    // [ceil(gx gy gz / 1024)] chunk totals of the prefix sum
-    int32_t *bucket;   // [nn] a node's bucket
+    int32_t *bucket;   // [nn] an item's bucket
     int32_t *rank;     // [nn] its rank within the bucket, -1 for padding slots
     double4 *spr;      // mode 1: [nn + CONTACT_PAD] position and rod (as a double) in bucket order
     double4 *svr;      // mode 1: [nn] velocity and radius in bucket order
-    int32_t *sid;      // [nn] node ids in bucket order
+    int32_t *sid;      // [nn] item ids (node ids, or element slots) in bucket order
     // mode 2: [2 (nn + CONTACT_PAD)] screening records in bucket order, two float4 per element:
     // its capsule's bounding box (centre relative to org, half extents), rod, element
     float4 *cull;
     double *force;     // [3][nid] contact force by node id
-    double *pot;       // [nid] potential share by node id (mode 2: each element's share on its first node)
+    double *pot;       // [nid] potential share by node id (mode 2: each element's share at its slot)
     const double *origin;   // FP32 batches: [3][n_rods] rod origins
     double *xabs;      // FP32 batches: [3][nid] node positions (summed in FP64) after the drift
     // mode 2: segment records in bucket order, 128 bytes each: (A, radius), (B, rod),
