@@ -8,6 +8,7 @@
 //   per-rod error measures.
 // One thread per window, element or rod; neighbours are read from the slot
 // arrays (adjacent slots of the same tile).
+#include "rod.h"
 #include "surrogate_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -360,15 +361,19 @@ __global__ void apply_nodes_kernel(const WinArgs A, const float *y, int ldy, con
     const float s = L / A.tau;
     float *st = A.B.state;
     const int64_t NS = A.B.n_slots;
+    float *v0, *v1, *v2;
     if (p < n) {
-        st[rodk::VX * NS + R.s0 + p] += dv.x * s;
-        st[rodk::VY * NS + R.s0 + p] += dv.y * s;
-        st[rodk::VZ * NS + R.s0 + p] += dv.z * s;
+        v0 = &st[rodk::VX * NS + R.s0 + p]; v1 = &st[rodk::VY * NS + R.s0 + p]; v2 = &st[rodk::VZ * NS + R.s0 + p];
     } else {
-        A.B.tail[rodk::TVX * A.B.n_rods + r] += dv.x * s;
-        A.B.tail[rodk::TVY * A.B.n_rods + r] += dv.y * s;
-        A.B.tail[rodk::TVZ * A.B.n_rods + r] += dv.z * s;
+        v0 = &A.B.tail[rodk::TVX * A.B.n_rods + r]; v1 = &A.B.tail[rodk::TVY * A.B.n_rods + r];
+        v2 = &A.B.tail[rodk::TVZ * A.B.n_rods + r];
     }
+    *v0 += dv.x * s;
+    *v1 += dv.y * s;
+    *v2 += dv.z * s;
+    // displacements and velocities; the edges are checked by phase 2
+    if (!(isfinite(*v0) && isfinite(*v1) && isfinite(*v2) && isfinite(dr.x) && isfinite(dr.y) && isfinite(dr.z)))
+        atomicOr(&A.B.nonfinite[r], ROD_FLAG_NONFINITE);
 }
 
 // Phase 2 (one thread per element): edge, anchor, director and omega.
@@ -395,21 +400,28 @@ __global__ void apply_elems_kernel(const WinArgs A, const float *y, int ldy, con
         A.B.tail[rodk::TRY * A.B.n_rods + r] += disp[g * 3 + 1];
         A.B.tail[rodk::TRZ * A.B.n_rods + r] += disp[g * 3 + 2];
     }
+    bool ok = isfinite(st[rodk::RX * NS + sl]) && isfinite(st[rodk::RY * NS + sl]) && isfinite(st[rodk::RZ * NS + sl]);
     const int flags = A.B.rod_flags[r];
     const bool fixed = (c == 0 && (flags & rodk::FLAG_CLAMP0)) || (c == n - 1 && (flags & rodk::FLAG_CLAMP1));
-    if (fixed) return;
-    float d[6];
-    for (int k = 0; k < 6; ++k) d[k] = sd ? y[g * ldy + 6 + k] * sd[6 + k] + mu[6 + k] : y[g * ldy + 6 + k];
-    float q[9];
-    R.dirs(c, q);
-    const V3 w0 = R.omega(c);
-    rotate_left(q, V3{-(d[0] + w0.x * A.tau), -(d[1] + w0.y * A.tau), -(d[2] + w0.z * A.tau)});
-    polar_step(q);
-    for (int k = 0; k < 9; ++k) st[(rodk::Q00 + k) * NS + sl] = q[k];
-    const float it = 1.f / A.tau;
-    st[rodk::WX * NS + sl] += d[3] * it;
-    st[rodk::WY * NS + sl] += d[4] * it;
-    st[rodk::WZ * NS + sl] += d[5] * it;
+    if (!fixed) {
+        float d[6];
+        for (int k = 0; k < 6; ++k) d[k] = sd ? y[g * ldy + 6 + k] * sd[6 + k] + mu[6 + k] : y[g * ldy + 6 + k];
+        float q[9];
+        R.dirs(c, q);
+        const V3 w0 = R.omega(c);
+        rotate_left(q, V3{-(d[0] + w0.x * A.tau), -(d[1] + w0.y * A.tau), -(d[2] + w0.z * A.tau)});
+        polar_step(q);
+        for (int k = 0; k < 9; ++k) {
+            st[(rodk::Q00 + k) * NS + sl] = q[k];
+            ok = ok && isfinite(q[k]);
+        }
+        const float it = 1.f / A.tau;
+        st[rodk::WX * NS + sl] += d[3] * it;
+        st[rodk::WY * NS + sl] += d[4] * it;
+        st[rodk::WZ * NS + sl] += d[5] * it;
+        ok = ok && isfinite(st[rodk::WX * NS + sl]) && isfinite(st[rodk::WY * NS + sl]) && isfinite(st[rodk::WZ * NS + sl]);
+    }
+    if (!ok) atomicOr(&A.B.nonfinite[r], ROD_FLAG_NONFINITE);
 }
 
 // ---------------------------------------------------------------- training rows
@@ -526,34 +538,46 @@ __global__ __launch_bounds__(APPLY_MAX_THREADS) void apply_rod_kernel(const WinA
     const int64_t NS = A.B.n_slots;
     const int64_t sl = R.s0 + c;
     const V3 d0 = sdisp[c], d1 = sdisp[c + 1];
-    st[rodk::RX * NS + sl] += d1.x - d0.x;
-    st[rodk::RY * NS + sl] += d1.y - d0.y;
-    st[rodk::RZ * NS + sl] += d1.z - d0.z;
+    bool ok = true;   // every value this thread writes is finite
+    auto add = [&](float *a, float dlt) {
+        const float v = *a + dlt;
+        *a = v;
+        ok = ok && isfinite(v);
+    };
+    add(&st[rodk::RX * NS + sl], d1.x - d0.x);
+    add(&st[rodk::RY * NS + sl], d1.y - d0.y);
+    add(&st[rodk::RZ * NS + sl], d1.z - d0.z);
     if (c == 0) {
-        A.B.tail[rodk::TRX * A.B.n_rods + r] += d0.x;
-        A.B.tail[rodk::TRY * A.B.n_rods + r] += d0.y;
-        A.B.tail[rodk::TRZ * A.B.n_rods + r] += d0.z;
+        add(&A.B.tail[rodk::TRX * A.B.n_rods + r], d0.x);
+        add(&A.B.tail[rodk::TRY * A.B.n_rods + r], d0.y);
+        add(&A.B.tail[rodk::TRZ * A.B.n_rods + r], d0.z);
     }
-    st[rodk::VX * NS + sl] += dv.x;
-    st[rodk::VY * NS + sl] += dv.y;
-    st[rodk::VZ * NS + sl] += dv.z;
+    add(&st[rodk::VX * NS + sl], dv.x);
+    add(&st[rodk::VY * NS + sl], dv.y);
+    add(&st[rodk::VZ * NS + sl], dv.z);
     if (c == n - 1) {
-        A.B.tail[rodk::TVX * A.B.n_rods + r] += dvn.x;
-        A.B.tail[rodk::TVY * A.B.n_rods + r] += dvn.y;
-        A.B.tail[rodk::TVZ * A.B.n_rods + r] += dvn.z;
+        add(&A.B.tail[rodk::TVX * A.B.n_rods + r], dvn.x);
+        add(&A.B.tail[rodk::TVY * A.B.n_rods + r], dvn.y);
+        add(&A.B.tail[rodk::TVZ * A.B.n_rods + r], dvn.z);
     }
     const bool fixed_e = (c == 0 && (flags & rodk::FLAG_CLAMP0)) || (c == n - 1 && (flags & rodk::FLAG_CLAMP1));
-    if (fixed_e) return;
-    float d[6];
-    for (int k = 0; k < 6; ++k) d[k] = out(g, 6 + k);
-    const V3 w0 = R.omega(c);
-    rotate_left(qc, V3{-(d[0] + w0.x * A.tau), -(d[1] + w0.y * A.tau), -(d[2] + w0.z * A.tau)});
-    polar_step(qc);
-    for (int k = 0; k < 9; ++k) st[(rodk::Q00 + k) * NS + sl] = qc[k];
-    const float it = 1.f / A.tau;
-    st[rodk::WX * NS + sl] += d[3] * it;
-    st[rodk::WY * NS + sl] += d[4] * it;
-    st[rodk::WZ * NS + sl] += d[5] * it;
+    if (!fixed_e) {
+        float d[6];
+        for (int k = 0; k < 6; ++k) d[k] = out(g, 6 + k);
+        const V3 w0 = R.omega(c);
+        rotate_left(qc, V3{-(d[0] + w0.x * A.tau), -(d[1] + w0.y * A.tau), -(d[2] + w0.z * A.tau)});
+        polar_step(qc);
+        for (int k = 0; k < 9; ++k) {
+            st[(rodk::Q00 + k) * NS + sl] = qc[k];
+            ok = ok && isfinite(qc[k]);
+        }
+        const float it = 1.f / A.tau;
+        add(&st[rodk::WX * NS + sl], d[3] * it);
+        add(&st[rodk::WY * NS + sl], d[4] * it);
+        add(&st[rodk::WZ * NS + sl], d[5] * it);
+    }
+    // a rod the learned step drives to NaN/Inf is flagged like one the plain step does
+    if (!ok) atomicOr(&A.B.nonfinite[r], ROD_FLAG_NONFINITE);
 }
 
 // Copy rods between two FP32 batches of equal per-rod layout: dst rod k <- src rod map[k]
@@ -584,7 +608,7 @@ __global__ void copy_rods_kernel(DevBatch<float> dst, DevBatch<float> src, const
             to.rod_phase[rt] = from.rod_phase[rf];
             to.rod_flags[rt] = from.rod_flags[rf];
         }
-        to.nonfinite[rt] = 0;
+        to.nonfinite[rt] = from.nonfinite[rf];   // the flags travel with the state they describe
     }
 }
 

@@ -123,3 +123,28 @@ def test_training_learns_the_coarse_step():
     assert val < 0.35
     s.close()
     b.close()
+
+
+def test_apply_flags_rods_driven_non_finite():
+    """A rod that the learned step drives to NaN/Inf is flagged like one the
+    plain step drives there: a NaN delta in one window of rod 3 flags rod 3
+    alone, and the synchronising calls report ROD_ENONFINITE."""
+    import torch
+    from paper_2605_13766_amd import rod
+    inp = W.surrogate_training(n_rods=12, n=64)
+    s0, t0 = oracle_run(inp, 200)
+    b = gpu_batch(inp, s0, t0)
+    s = rod.Surrogate(k_substeps=K, seed=0)
+    Wn = s.n_windows(b)
+    D = np.zeros((Wn, 12))
+    D[3 * 65 + 10, 0] = np.nan          # rod 3, window of node 10 (65 windows per rod)
+    s.apply(b, torch.tensor(D, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    f = b.flags()
+    assert f[3] & rod.ROD_FLAG_NONFINITE
+    assert not np.any(np.delete(f, 3))
+    with pytest.raises(rod.RodError) as ei:
+        b.get_state()
+    assert ei.value.code == rod.ROD_ENONFINITE
+    s.close()
+    b.close()
