@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void first_flagged_kernel(const int32_t *flags
     __shared__ int32_t red[256];
     int m = n;
     for (int r = threadIdx.x; r < n; r += 256)
-        if (flags[r] != 0) {
+        if (flags[r] & ROD_FLAG_NONFINITE) {   // other flag bits do not fail the call
             m = r;
             break;
         }

@@ -84,3 +84,23 @@ def test_noalloc_energy_rejects_batches_beyond_its_buffer():
     assert np.abs(a).max() > 0
     assert np.array_equal(a, c)
     ok.close()
+
+
+def test_noalloc_energy_on_a_capsule_pile_with_a_stretched_rod():
+    """Contact batches run a contact pass before the energies (the pairs'
+    potentials) in both entry points; a rod flagged only as stretched
+    (ROD_FLAG_STRETCHED) fails neither, and the two agree bit for bit."""
+    from paper_2605_13766_amd import rod
+    inp = W.fibre_pile(n_rods=24, n=8, L=0.248, per_row=2, rows=4, noise=1e-2, seed=68, contact=2)
+    with rod.RodBatch(inp, precision="f64", substeps=1) as b:
+        b.step(5)
+        pos, vel, dr, om, t = b.get_state()
+        a0 = inp.node_offset[2]
+        n = inp.n_elems[2]
+        pos[a0 + n] = pos[a0 + n - 1] + 1.4 * (pos[a0 + n] - pos[a0 + n - 1])
+        b.set_state(pos, vel, dr, om, t)
+        b.step(1)
+        assert b.flags()[2] & rod.ROD_FLAG_STRETCHED
+        a, c = _both(b)
+        assert np.array_equal(a, c)
+        assert a[:, 4].sum() > 0.0      # the contact potentials are in W_ext
