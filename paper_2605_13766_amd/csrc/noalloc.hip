@@ -28,7 +28,7 @@ constexpr int MAX_DEVICES = 64;
 std::mutex g_mu;
 double *g_ptr[MAX_DEVICES] = {};
 
-// out[0] = the smallest r < n with flags[r] != 0, or n when there is none.
+// out[0] = the smallest r < n whose flags have the non-finite bit, or n when there is none.
 // One workgroup; every lane's slot of the LDS reduction is written before it
 // is read, so nothing needs clearing beforehand.
 __global__ __launch_bounds__(256) void first_flagged_kernel(const int32_t *flags, int n, int32_t *out)
