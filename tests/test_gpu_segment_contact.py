@@ -79,13 +79,16 @@ def test_capsule_pile_full_size_momentum():
     """The 16,384-fibre capsule pile (aspect ratio 31, 20 elements each) without
     gravity, floor, damping or friction: internal forces only, so the total
     linear momentum stays at its start value (to the round-off of the
-    opposite pair forces, which cancel bit for bit, and of the kicks)."""
+    opposite pair forces, which cancel bit for bit, and of the kicks).  The
+    batch is autotuned (one step per launch, every tile width tried)."""
     R = _rod()
     inp = W.capsule_pile(g=0.0, damping=0.0, mu=0.0, contact_c=0.0)
     inp.walls = None
     print(f"case: capsule pile {inp.n_rods} fibres, {inp.n_elements} elements, FP64, 200 steps", flush=True)
     m = OS._mass_vec(inp)
-    with R.RodBatch(inp, precision="f64") as b:
+    with R.RodBatch(inp, precision="f64", autotune=True) as b:   # the tuner's trial batches build their own grids
+        info = b.info()
+        assert info["substeps"] == 1
         p0 = (m[:, None] * b.get_state()[1]).sum(0)
         b.step(200)
         v1 = b.get_state()[1]
