@@ -199,6 +199,18 @@ typedef struct {
      * node (element) before the forces are summed, so runs are bitwise
      * repeatable and independent of tile_waves. */
     int32_t rod_contact;             /* 0, 1 (node spheres) or 2 (element capsules) */
+    /* Verlet lists for rod_contact = 1 (ignored otherwise).  With a skin s > 0
+     * the grid (cells of twice the largest radius plus s) lists, for every
+     * node, the nodes of other rods closer than its radius plus the largest
+     * radius plus s, and the grid pass runs again only in a step where some
+     * node has moved more than s/2 since (or a list would have held more
+     * than 32 partners: that node's contacts are summed in grid order and the
+     * next step builds again).  Every step sums each node's contacts over its
+     * list in increasing node order, so the results do not depend on s or on
+     * when the lists were built (bit for bit, while no list overflows).
+     * 0: s = half the largest radius; < 0: no lists (the grid pass every
+     * step, contacts summed in grid order).  Not finite: ROD_EINVAL. */
+    double contact_skin;             /* m */
 } rod_batch_desc;
 
 /* One timed candidate of the autotuner. */
@@ -222,7 +234,8 @@ typedef struct {
  * node outside the batch, joining a node to itself, or with k, c or l0
  * negative or not finite; n_walls outside [0, ROD_MAX_WALLS], a wall normal
  * not of unit length within 1e-9, wall_k, wall_c or wall_mu negative,
- * wall_vslip <= 0, rod_contact not 0, 1 or 2, rod_contact with substeps > 1),
+ * wall_vslip <= 0, rod_contact not 0, 1 or 2, rod_contact with substeps > 1,
+ * contact_skin not finite),
  * ROD_ENOMEM, ROD_EDEVICE, ROD_EUNSUPPORTED (tile_waves too small for the
  * longest rod or connected group).
  * A time step above the explicit stability estimate is reported through
@@ -315,6 +328,14 @@ int rod_get_flags(rod_batch *b, int32_t *nonfinite, void *stream);
  * [3] tile_waves, [4] substeps per launch (0 = whole call), [5] precision,
  * [6] slots (tiles * 64 * tile_waves), [7] steps taken so far. */
 int rod_batch_info(const rod_batch *b, int64_t *info);
+
+/* Verlet-list counters of a batch with rod_contact = 1 and a skin > 0 (all
+ * zero otherwise): out[0] contact passes (one per step, one per energy call),
+ * [1] passes that rebuilt the lists, [2] builds at which a list overflowed
+ * (its node's contacts were summed in grid order, and the next pass built
+ * again), [3] the most partners one node had at a build, [4] the list
+ * capacity (32).  Counters wrap at 2^32.  Synchronises `stream`. */
+int rod_contact_stats(rod_batch *b, int64_t *out, void *stream);
 
 void rod_batch_destroy(rod_batch *b);
 

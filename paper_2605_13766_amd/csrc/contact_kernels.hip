@@ -13,7 +13,15 @@
 // drift) into a wrapped uniform grid with atomic counts, prefix-sum the
 // counts, put the items into bucket order (each bucket sorted by id), and let
 // every item sum its contacts over the 27 buckets around it; the step kernel
-// adds the node forces at its kick.
+// adds the node forces at its kick.  Mode 1 can keep Verlet lists instead
+// (a skin > 0): every node's list of partners (nodes of other rods within
+// its radius plus the largest radius plus the skin at the build), by
+// increasing id.  A pass first sums each node's contacts over its list and
+// checks how far the node has moved since the build; only when one has moved
+// more than half the skin does the grid pass run, rebuilding the lists and
+// summing every node's contacts again over its new list.  Both sums run over
+// the same pairs (every pair that touches is listed) in the same order, so
+// the forces depend neither on when the lists were built nor on the skin.
 #include "rod.h"
 #include "rod_internal.h"
 
@@ -24,6 +32,10 @@
 namespace rodk {
 
 namespace {
+
+// A position `drift` seconds ahead (one expression, so every caller rounds it
+// alike).
+__device__ inline double ahead(double r, double drift, double v) { return r + drift * v; }
 
 // Node id's rod, its position `drift` seconds ahead and its velocity (FP64
 // state: lane node i at the slot, node n in the tail); false for padding slots
@@ -37,13 +49,13 @@ __device__ inline bool contact_node(const DevBatch<double> &B, const ContactGrid
         if (rod < 0) return false;
         for (int a = 0; a < 3; ++a) {
             v[a] = B.state[(VX + a) * NS + id];
-            x[a] = B.state[(RX + a) * NS + id] + drift * v[a];
+            x[a] = ahead(B.state[(RX + a) * NS + id], drift, v[a]);
         }
     } else {
         rod = (int)(id - NS);
         for (int a = 0; a < 3; ++a) {
             v[a] = B.tail[(TVX + a) * B.n_rods + rod];
-            x[a] = B.tail[(TRX + a) * B.n_rods + rod] + drift * v[a];
+            x[a] = ahead(B.tail[(TRX + a) * B.n_rods + rod], drift, v[a]);
         }
     }
     return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
@@ -121,15 +133,26 @@ __device__ inline int64_t cell_of(double x, double org, double inv_cell)
     return (int64_t)floor(q < -1e15 ? -1e15 : (q > 1e15 ? 1e15 : q));   // finite x; keeps the cast defined
 }
 
+// With Verlet lists a kernel of the pass runs only when a flag set by the
+// check before it says so (the flag's value, set or clear, is the same for
+// every thread of the launch); without (p NULL) it always runs.
+struct Gate {
+    const int32_t *p = nullptr;
+    int want = 1;
+    __device__ bool skip() const { return p && ((*p != 0) != (want != 0)); }
+};
+
 template <typename T>
-__global__ void contact_bin_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+__global__ void contact_bin_kernel(const DevBatch<T> B, const ContactGrid G, double drift, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn) return;
     int rod;
     double x[3], v[3];
     if (!contact_node(B, G, id, drift, rod, x, v)) {
         G.rank[id] = -1;
+        if (G.lcount) G.lcount[id] = 0;   // not binned: no partners until the next build
         return;
     }
     const int b = (wrap_cell(cell_of(x[2], G.org[2], G.inv_cell), G.gz) * G.gy
@@ -159,8 +182,9 @@ __device__ inline int32_t block_exclusive(int32_t mine, int32_t *part, int n_thr
     return part[t] - mine;
 }
 
-__global__ __launch_bounds__(256) void contact_scan_chunks(const ContactGrid G, int nb)
+__global__ __launch_bounds__(256) void contact_scan_chunks(const ContactGrid G, int nb, Gate gate)
 {
+    if (gate.skip()) return;
     __shared__ int32_t part[256];
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 4;
     int32_t c[4], sum = 0;
@@ -180,8 +204,9 @@ __global__ __launch_bounds__(256) void contact_scan_chunks(const ContactGrid G, 
     if (threadIdx.x == 0) G.chunk[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(1024) void contact_scan_top(const ContactGrid G, int n_chunks, int nb)
+__global__ __launch_bounds__(1024) void contact_scan_top(const ContactGrid G, int n_chunks, int nb, Gate gate)
 {
+    if (gate.skip()) return;
     __shared__ int32_t part[1024];
     const int base = threadIdx.x * 4;
     int32_t c[4], sum = 0;
@@ -198,8 +223,9 @@ __global__ __launch_bounds__(1024) void contact_scan_top(const ContactGrid G, in
     if (threadIdx.x == 0) G.start[nb] = total;
 }
 
-__global__ __launch_bounds__(256) void contact_scan_add(const ContactGrid G, int nb)
+__global__ __launch_bounds__(256) void contact_scan_add(const ContactGrid G, int nb, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 4;
     const int32_t off = G.chunk[blockIdx.x];
     for (int k = 0; k < 4; ++k)
@@ -207,8 +233,9 @@ __global__ __launch_bounds__(256) void contact_scan_add(const ContactGrid G, int
 }
 
 template <typename T>
-__global__ void contact_scatter_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+__global__ void contact_scatter_kernel(const DevBatch<T> B, const ContactGrid G, double drift, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn) return;
     const int32_t r = G.rank[id];
@@ -228,8 +255,9 @@ __global__ void contact_scatter_kernel(const DevBatch<T> B, const ContactGrid G,
 // last bit, independent of the run.  Buckets hold a few nodes: insertion sort
 // by the thread of the node that took rank 0 in the bucket (one per occupied
 // bucket; threads run over node ids, far fewer than buckets).
-__global__ void contact_sort_kernel(const ContactGrid G)
+__global__ void contact_sort_kernel(const ContactGrid G, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn || G.rank[id] != 0) return;
     const int b = G.bucket[id];
@@ -319,6 +347,99 @@ __device__ inline int64_t xcd_contiguous_block()
     return (int64_t)x * q + (x < r ? x : r) + i;
 }
 
+// The walls' law between two spheres: node a at x (velocity v, radius ra)
+// against a partner at q (velocity u, radius rb); adds a's force to f and
+// a's share of the pair's potential (half) to pot.
+__device__ inline void sphere_pair(const double x[3], const double v[3], double ra, const double4 &q, const double4 &u,
+                                   double rb, double k, double c, double mu, double vs, double f[3], double &pot)
+{
+    const double e0 = x[0] - q.x, e1 = x[1] - q.y, e2 = x[2] - q.z;
+    const double d2 = e0 * e0 + e1 * e1 + e2 * e2, reach = ra + rb;
+    if (!(d2 < reach * reach)) return;
+    const double dist = sqrt(d2);
+    const double delta = reach - dist;
+    if (!(delta > 0.0)) return;
+    pot += 0.25 * k * delta * delta;
+    if (!(dist > 0.0)) return;   // coincident centres: no direction
+    const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
+    const double r0 = v[0] - u.x, r1 = v[1] - u.y, r2 = v[2] - u.z;
+    const double vn = n0 * r0 + n1 * r1 + n2 * r2;
+    const double fn = delta * (k - c * vn);
+    if (!(fn > 0.0)) return;
+    const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
+    const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    const double gf = mu * fn / (sp > vs ? sp : vs);
+    f[0] += fn * n0 - gf * t0;
+    f[1] += fn * n1 - gf * t1;
+    f[2] += fn * n2 - gf * t2;
+}
+
+// A listed partner's position `drift` ahead and velocity, as contact_node
+// gives them, without its branches: slot and tail arrays keep position and
+// velocity at the same field offsets.  A partner that is not finite fails
+// the pair's distance test.
+static_assert((int)RX == (int)TRX && (int)VX == (int)TVX, "slot and tail fields share offsets");
+
+__device__ inline void listed_partner(const DevBatch<double> &B, const ContactGrid &, int64_t p, double drift,
+                                      double4 &y, double4 &u)
+{
+    const int64_t NS = B.n_slots;
+    const bool slot = p < NS;
+    const double *const src = slot ? B.state + p : B.tail + (p - NS);
+    const int64_t st = slot ? NS : B.n_rods;
+    u = make_double4(src[(VX + 0) * st], src[(VX + 1) * st], src[(VX + 2) * st], 0.0);
+    y = make_double4(ahead(src[(RX + 0) * st], drift, u.x), ahead(src[(RX + 1) * st], drift, u.y),
+                     ahead(src[(RX + 2) * st], drift, u.z), 0.0);
+}
+
+__device__ inline void listed_partner(const DevBatch<float> &B, const ContactGrid &G, int64_t p, double, double4 &y,
+                                      double4 &u)
+{
+    const int64_t NS = B.n_slots;
+    const bool slot = p < NS;
+    const float *const src = slot ? B.state + p : B.tail + (p - NS);
+    const int64_t st = slot ? NS : B.n_rods;
+    u = make_double4((double)src[(VX + 0) * st], (double)src[(VX + 1) * st], (double)src[(VX + 2) * st], 0.0);
+    y = make_double4(G.xabs[p], G.xabs[G.nid + p], G.xabs[2 * G.nid + p], 0.0);
+}
+
+// Up to four listed pairs of a node (entries e[0..m-1]; the rest are ignored
+// but must name valid nodes): the partners' loads all go out before the
+// pairs are evaluated, in entry order.
+template <typename T>
+__device__ inline void listed_pairs4(const DevBatch<T> &B, const ContactGrid &G, const int2 e[4], int m,
+                                     double drift, const double x[3], const double v[3], double ra, double f[3],
+                                     double &pot)
+{
+    const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
+    double4 y[4], u[4];
+    double rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        listed_partner(B, G, e[q].x, drift, y[q], u[q]);
+        rb[q] = B.rod_rad[e[q].y];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < m) sphere_pair(x, v, ra, y[q], u[q], rb[q], k, c, mu, vs, f, pot);
+}
+
+// A node's contacts over its Verlet list entries j0 .. n-1 (partner id and
+// rod), in list (increasing id) order, four entries at a time (entries past
+// the end repeat the last one and are not evaluated).
+template <typename T>
+__device__ inline void list_contacts(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int j0, int n,
+                                     double drift, const double x[3], const double v[3], double ra, double f[3],
+                                     double &pot)
+{
+    for (; j0 < n; j0 += 4) {
+        int2 e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = G.lid[min(j0 + q, n - 1) * G.nid + id];
+        listed_pairs4(B, G, e, n - j0, drift, x, v, ra, f, pot);
+    }
+}
+
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
 // around it: the walls' law between two spheres.  Threads take the nodes in
 // bucket order, so neighbouring threads read the same buckets.  The screen
@@ -327,9 +448,16 @@ __device__ inline int64_t xcd_contiguous_block()
 // rounding cannot drop a pair the exact test takes); the evaluation repeats
 // the exact test with the partner's radius and applies the law.  Results go
 // to the node's id (padding ids keep the zeros set at creation).
-template <typename T>
-__global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
+// LIST (the pass that rebuilds the Verlet lists): the screen's bound grows by
+// the skin and every survivor's id joins the node's list, which is then
+// sorted by id; the node's contacts are summed over the new list, or, when
+// it overflowed, in the sweep's order (the evaluation above, run on the same
+// survivors), and the next pass is asked to build again.
+template <typename T, bool LIST>
+__global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb,
+                                                                 double drift, Gate gate)
 {
+    if (gate.skip()) return;
     __shared__ int32_t queue[CF_QUEUE * CF_BLOCK];
     int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * CF_BLOCK]
     const int64_t p0 = xcd_contiguous_block() * CF_BLOCK + threadIdx.x;
@@ -340,33 +468,12 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
     const int rod = (int)me.w;
     const double x[3] = {me.x, me.y, me.z}, v[3] = {mv.x, mv.y, mv.z};
     const double ra = mv.w;
-    const double rs = ra + G.rmax, rs2 = rs * rs * (1.0 + 1e-9);
+    const double rs = LIST ? ra + G.rmax + G.skin : ra + G.rmax, rs2 = rs * rs * (1.0 + 1e-9);
     const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
-    double f0 = 0, f1 = 0, f2 = 0, pot = 0;
+    double f[3] = {0.0, 0.0, 0.0}, pot = 0;
     int nq = 0;
-
-    auto evaluate = [&](int32_t p) {
-        const double4 q = G.spr[p], u = G.svr[p];
-        const double e0 = x[0] - q.x, e1 = x[1] - q.y, e2 = x[2] - q.z;
-        const double d2 = e0 * e0 + e1 * e1 + e2 * e2, reach = ra + u.w;
-        if (!(d2 < reach * reach)) return;
-        const double dist = sqrt(d2);
-        const double delta = reach - dist;
-        if (!(delta > 0.0)) return;
-        pot += 0.25 * k * delta * delta;
-        if (!(dist > 0.0)) return;   // coincident centres: no direction
-        const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
-        const double r0 = v[0] - u.x, r1 = v[1] - u.y, r2 = v[2] - u.z;
-        const double vn = n0 * r0 + n1 * r1 + n2 * r2;
-        const double fn = delta * (k - c * vn);
-        if (!(fn > 0.0)) return;
-        const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
-        const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-        const double gf = mu * fn / (sp > vs ? sp : vs);
-        f0 += fn * n0 - gf * t0;
-        f1 += fn * n1 - gf * t1;
-        f2 += fn * n2 - gf * t2;
-    };
+    const int64_t id = live ? G.sid[p0] : 0, NI = G.nid;
+    int n_list = 0;
 
     Sweep sw(G, cell_of(x[0], G.org[0], G.inv_cell), cell_of(x[1], G.org[1], G.inv_cell),
              cell_of(x[2], G.org[2], G.inv_cell));
@@ -387,16 +494,110 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
             sw.p += CF_GROUP;
             if (sw.p >= sw.pe) done = !sw.next(G);
         }
-        for (int j = 0; j < nq; ++j) evaluate(mine[j * CF_BLOCK]);
+        for (int j = 0; j < nq; ++j) {
+            const int32_t p = mine[j * CF_BLOCK];
+            const double4 u = G.svr[p];
+            sphere_pair(x, v, ra, G.spr[p], u, u.w, k, c, mu, vs, f, pot);
+            if constexpr (LIST) {
+                if (n_list < CONTACT_LIST_CAP) G.lid[n_list * NI + id] = make_int2(G.sid[p], (int)G.spr[p].w);
+                ++n_list;
+            }
+        }
         nq = 0;
         if (!__any(!done)) break;
     }
+    if constexpr (LIST) {
+        int most = n_list;   // the wave's longest list, one atomic per wave
+        for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o, 64));
+        if ((threadIdx.x & 63) == 0 && most > 0) atomicMax(&G.vflag[VF_MOST], most);
+        if (!live) return;
+        for (int a = 0; a < 3; ++a) G.xb[a * NI + id] = x[a];
+        G.lcount[id] = n_list;
+        if (n_list > CONTACT_LIST_CAP) {
+            atomicOr(&G.vflag[VF_OVERFLOW], 1);   // forces of the sweep's order; the next pass builds again
+        } else {
+            int2 *const L = G.lid + id;   // insertion sort by id (the sweep left it sorted within buckets)
+            for (int i = 1; i < n_list; ++i) {
+                const int2 key = L[i * NI];
+                int j = i - 1;
+                while (j >= 0 && L[j * NI].x > key.x) {
+                    L[(j + 1) * NI] = L[j * NI];
+                    --j;
+                }
+                L[(j + 1) * NI] = key;
+            }
+            f[0] = f[1] = f[2] = pot = 0.0;
+            list_contacts(B, G, id, 0, n_list, drift, x, v, ra, f, pot);
+        }
+    }
     if (!live) return;
-    const int64_t id = G.sid[p0];
-    G.force[id] = f0;
-    G.force[G.nid + id] = f1;
-    G.force[2 * G.nid + id] = f2;
+    G.force[id] = f[0];
+    G.force[NI + id] = f[1];
+    G.force[2 * NI + id] = f[2];
     G.pot[id] = pot;
+}
+
+// Verlet lists, first kernel of every pass: each node sums its contacts over
+// its list, and asks for a build when it has moved more than half the skin
+// from its position at the last one (a NaN position there counts as moved).
+// Without a build no pair missing from the lists can touch: the pair was at
+// least its radii plus the skin apart at the build (up to the 1e-9 widening)
+// and each node has moved at most half the skin since.  With a build the
+// forces computed here are replaced.  The node's own loads and its first 8
+// list entries go out together (padding slots and ids past the end read
+// valid addresses and do nothing; entries past the node's count name valid
+// nodes, and are replaced by the node itself before its partners are read);
+// padding ids keep the zeros set at creation.
+template <typename T>
+__global__ __launch_bounds__(256) void verlet_force_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, NI = G.nid, NS = B.n_slots;
+    const int64_t ic = id < NI ? id : NI - 1;
+    const int rod = ic < NS ? B.slot_rod[ic] : (int)(ic - NS);
+    double4 y, u;
+    listed_partner(B, G, ic, drift, y, u);
+    const double b0 = G.xb[ic], b1 = G.xb[NI + ic], b2 = G.xb[2 * NI + ic];
+    const int n = min(G.lcount[ic], CONTACT_LIST_CAP);   // larger only after an overflow, when a build follows
+    int2 e[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = G.lid[q * NI + ic];
+    const bool live = id < NI && rod >= 0;
+    const bool ok = live && isfinite(y.x) && isfinite(y.y) && isfinite(y.z);
+    const double h = 0.5 * G.skin, e0 = y.x - b0, e1 = y.y - b1, e2 = y.z - b2;
+    const int moved = ok && !(e0 * e0 + e1 * e1 + e2 * e2 <= h * h);
+    if (live && !ok) G.xb[id] = NAN;   // a node that turns finite again (a new state) forces a build
+    if (__any(moved) && (threadIdx.x & 63) == 0) atomicOr(&G.vflag[VF_REQUEST], 1);
+    if (!live) return;
+    double f[3] = {0.0, 0.0, 0.0}, pot = 0;
+    const double x[3] = {y.x, y.y, y.z}, v[3] = {u.x, u.y, u.z};
+    if (ok && n > 0) {
+        const int2 self = make_int2((int)ic, rod);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = q < n ? e[q] : self;
+        const double ra = B.rod_rad[rod];
+        listed_pairs4(B, G, e, n, drift, x, v, ra, f, pot);
+        if (n > 4) listed_pairs4(B, G, e + 4, n - 4, drift, x, v, ra, f, pot);
+        if (n > 8) list_contacts(B, G, id, 8, n, drift, x, v, ra, f, pot);
+    }
+    G.force[id] = f[0];
+    G.force[NI + id] = f[1];
+    G.force[2 * NI + id] = f[2];
+    G.pot[id] = pot;
+}
+
+// Verlet lists, the end of a pass (after the step kernel, in place of its
+// step-counter advance): counts the pass and its build, carries an overflow
+// of this pass's build into the next pass's request, and clears the flags.
+__global__ void verlet_finish_kernel(int32_t *vflag, int64_t *step, int64_t n)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (step) *step += n;
+    const int req = vflag[VF_REQUEST], ovf = vflag[VF_OVERFLOW];
+    vflag[VF_PASSES] += 1;
+    vflag[VF_BUILDS] += req != 0;
+    vflag[VF_FALLBACKS] += ovf != 0;
+    vflag[VF_REQUEST] = ovf;
+    vflag[VF_OVERFLOW] = 0;
 }
 
 // ---------------------------------------------------------------- capsules
@@ -714,23 +915,35 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
     }
     const bool seg = g.mode == 2;
     if (seg ? (!g.sca || !g.fseg || !g.self_pairs || !g.cull) : !g.spr) return hipErrorInvalidValue;
+    const bool lists = !seg && g.skin > 0.0;
+    if (lists && (!g.lcount || !g.lid || !g.xb || !g.vflag)) return hipErrorInvalidValue;
+    const unsigned gf = (unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK);
+    Gate build;   // with lists the grid pass runs only in passes that rebuild them
+    if (lists) {
+        build.p = g.vflag + VF_REQUEST;
+        hipLaunchKernelGGL((verlet_force_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g,
+                           drift);
+    }
     if (seg) hipLaunchKernelGGL((seg_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
-    else hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
-    hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb);
-    hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb);
-    hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb);
+    else hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, build);
+    hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb, build);
+    hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb, build);
+    hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb, build);
     if (seg) {
         hipLaunchKernelGGL(contact_scatter_ids, dim3(gn), dim3(bs), 0, s, g);
         hipLaunchKernelGGL(sort_ids_kernel, dim3(gn), dim3(bs), 0, s, g);
         hipLaunchKernelGGL((seg_fill_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, nb);
-        hipLaunchKernelGGL((seg_force_kernel<T>), dim3((unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK)),
-                           dim3(CF_BLOCK), 0, s, b, g, nb);
+        hipLaunchKernelGGL((seg_force_kernel<T>), dim3(gf), dim3(CF_BLOCK), 0, s, b, g, nb);
         hipLaunchKernelGGL((seg_nodes_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g);
     } else {
-        hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
-        hipLaunchKernelGGL(contact_sort_kernel, dim3(gn), dim3(bs), 0, s, g);
-        hipLaunchKernelGGL((contact_force_kernel<T>), dim3((unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK)),
-                           dim3(CF_BLOCK), 0, s, b, g, nb);
+        hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, build);
+        hipLaunchKernelGGL(contact_sort_kernel, dim3(gn), dim3(bs), 0, s, g, build);
+        if (lists)
+            hipLaunchKernelGGL((contact_force_kernel<T, true>), dim3(gf), dim3(CF_BLOCK), 0, s, b, g, nb, drift,
+                               build);
+        else
+            hipLaunchKernelGGL((contact_force_kernel<T, false>), dim3(gf), dim3(CF_BLOCK), 0, s, b, g, nb, drift,
+                               build);
     }
     return hipGetLastError();
 }
@@ -745,6 +958,12 @@ hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, doubl
 hipError_t launch_contact(const DevBatch<float> &b, const ContactGrid &g, double drift, hipStream_t s)
 {
     return launch_contact_t<float>(b, g, drift, s);
+}
+
+hipError_t launch_contact_finish(const ContactGrid &g, int64_t *step, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(verlet_finish_kernel, dim3(1), dim3(64), 0, s, g.vflag, step, n);
+    return hipGetLastError();
 }
 
 }  // namespace rodk

@@ -173,14 +173,32 @@ struct ContactGrid {
     const int32_t *self_pairs;
     double *fseg;      // [6][nn] each element's force shares of its nodes A and B
     double cell_len;   // mode 2: the longest element the grid allows for (the cell holds it)
+    // mode 1 with Verlet lists (skin > 0; cells of 2 rmax + skin): each node's
+    // partners, the nodes of other rods within its radius + rmax + skin when
+    // the lists were built, by increasing id; rebuilt when a node has moved
+    // more than skin / 2 since
+    double skin;       // 0: no lists (the grid pass every step)
+    int32_t *lcount;   // [nid] partners listed (more than CONTACT_LIST_CAP: the build overflowed)
+    int2 *lid;         // [CONTACT_LIST_CAP][nid] partner id and its rod
+    double *xb;        // [3][nid] positions at the last build (NaN: none yet, or the node was not finite)
+    // [CONTACT_VFLAGS]: this pass builds, this pass's build overflowed; then
+    // counters (passes, builds, builds that overflowed, most partners of one
+    // node at a build)
+    int32_t *vflag;
 };
 constexpr int64_t CONTACT_PAD = 4;   // sorted records past the last item (a screening group reads past a range)
+constexpr int CONTACT_LIST_CAP = 32; // partners a node's Verlet list holds
+constexpr int CONTACT_VFLAGS = 8;
+enum { VF_REQUEST = 0, VF_OVERFLOW, VF_PASSES, VF_BUILDS, VF_FALLBACKS, VF_MOST };
 constexpr int64_t CONTACT_MAX_BUCKETS = 4096 * 1024;   // chunk totals fit one workgroup's prefix sum
 
 // Fill g.force and g.pot for positions advanced by `drift` seconds from the
 // state (dt/2 before a step's kick, 0 for energies).
 hipError_t launch_contact(const DevBatch<double> &b, const ContactGrid &g, double drift, hipStream_t s);
 hipError_t launch_contact(const DevBatch<float> &b, const ContactGrid &g, double drift, hipStream_t s);
+// With Verlet lists (g.skin > 0), after every pass and the step kernel that
+// follows it: advance *step by n (step may be NULL) and settle the pass's flags.
+hipError_t launch_contact_finish(const ContactGrid &g, int64_t *step, int64_t n, hipStream_t s);
 
 // Kernel launchers (rod_kernels.hip).  `waves` is the tile width in wave64s.
 hipError_t launch_step(const DevBatch<double> &b, int waves, int n_sub, int grid, hipStream_t s);

@@ -114,6 +114,7 @@ struct rod_batch {
     int n_walls = 0;
     bool rod_contact = false;          // rod-rod contact: a grid pass before every step
     int contact_mode = 0;              // 1: node spheres, 2: element capsules
+    double contact_skin = 0;           // as given (mode 1: < 0 no Verlet lists, 0 half the largest radius)
     rodk::ContactGrid cg{};
     double walls[ROD_MAX_WALLS][4] = {};
     double wall_k = 0, wall_c = 0, wall_mu = 0, wall_vslip = 0;
@@ -232,6 +233,7 @@ int validate(const rod_batch_desc *d)
     if (d->rod_contact < 0 || d->rod_contact > 2) return fail(ROD_EINVAL, "rod_contact must be 0, 1 or 2");
     if (d->rod_contact && d->substeps > 1)
         return fail(ROD_EINVAL, "rod contact runs one step per launch: substeps must be 0 or 1");
+    if (!std::isfinite(d->contact_skin)) return fail(ROD_EINVAL, "contact_skin must be finite");
     if (d->n_walls > 0 || d->rod_contact) {
         if (d->n_walls > 0 && !d->walls) return fail(ROD_EINVAL, "walls is NULL");
         for (int w = 0; w < d->n_walls; ++w) {
@@ -804,7 +806,8 @@ int build_device(rod_batch *b, const HostInputs &h)
     return ROD_OK;
 }
 
-// Device buffers of the contact grid: cells of twice the largest radius; per
+// Device buffers of the contact grid: cells of twice the largest radius (plus
+// the Verlet skin); per
 // axis enough cells (at least 3) to cover the initial extent of the nodes,
 // shrunk along the longest axes while the grid holds more than 4 buckets per
 // node (or more than the prefix sum takes); the grid wraps beyond that.
@@ -821,7 +824,10 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     // midpoints are at most (l_a + l_b) / 2 + r_a + r_b apart, so cells hold the
     // longest element stretched by a quarter plus twice the largest radius
     g.cell_len = 1.25 * lmax;
-    const double cell = g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax;
+    // mode 1: Verlet lists unless the skin is negative; 0 picks half the
+    // largest radius (a node may then move a quarter radius between builds)
+    g.skin = g.mode == 1 && b->contact_skin >= 0 ? (b->contact_skin > 0 ? b->contact_skin : 0.5 * rmax) : 0.0;
+    const double cell = g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax + g.skin;
     g.inv_cell = 1.0 / cell;
     g.rmax = rmax;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -899,6 +905,19 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         // groups and masks the records past a range's end
         HIPCHK(hipMalloc((void **)&g.spr, (g.nn + rodk::CONTACT_PAD) * sizeof(double4)));
         HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
+        if (g.skin > 0) {
+            HIPCHK(hipMalloc((void **)&g.lcount, g.nid * sizeof(int32_t)));
+            HIPCHK(hipMalloc((void **)&g.lid, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int2)));
+            HIPCHK(hipMalloc((void **)&g.xb, 3 * g.nid * sizeof(double)));
+            HIPCHK(hipMalloc((void **)&g.vflag, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
+            // no build yet (NaN positions: the first pass builds)
+            const std::vector<double> nan3(3 * g.nid, std::nan(""));
+            HIPCHK(hipMemcpy(g.xb, nan3.data(), nan3.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemset(g.lcount, 0, g.nid * sizeof(int32_t)));
+            // every entry names a valid node (the list pass reads entries past a count)
+            HIPCHK(hipMemset(g.lid, 0, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int2)));
+            HIPCHK(hipMemset(g.vflag, 0, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
+        }
     }
     HIPCHK(hipMalloc((void **)&g.force, 3 * g.nid * sizeof(double)));
     HIPCHK(hipMalloc((void **)&g.pot, g.nid * sizeof(double)));
@@ -944,7 +963,9 @@ int enqueue_steps(rod_batch *b, int64_t n_steps, hipStream_t s)
         hipError_t e = b->precision == ROD_F32 ? rodk::launch_step(b->b32, b->waves, n_sub, b->grid, s)
                                                : rodk::launch_step(b->b64, b->waves, n_sub, b->grid, s);
         if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
-        e = rodk::launch_advance(b->d_step, n_sub, s);
+        // with Verlet lists the pass's closing kernel advances the step counter
+        e = b->cg.vflag ? rodk::launch_contact_finish(b->cg, b->d_step, n_sub, s)
+                        : rodk::launch_advance(b->d_step, n_sub, s);
         if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("advance launch: ") + hipGetErrorString(e));
     }
     return ROD_OK;
@@ -1254,6 +1275,7 @@ int rod_batch_create(const rod_batch_desc *d, void *stream, rod_batch **out)
     b->wall_vslip = d->wall_vslip;
     b->rod_contact = d->rod_contact != 0;
     b->contact_mode = d->rod_contact;
+    b->contact_skin = d->contact_skin;
     if (b->rod_contact) b->substeps = 1;   // a contact pass before every step
     b->ext = b->magnetic || b->muscle || d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0
            || d->n_connections > 0 || d->n_walls > 0 || b->rod_contact;
@@ -1383,6 +1405,7 @@ int rod_energy(rod_batch *b, double *out, void *stream)
         // the pairs' potentials at the current positions
         hipError_t e = b->precision == ROD_F32 ? rodk::launch_contact(b->b32, b->cg, 0.0, s)
                                                : rodk::launch_contact(b->b64, b->cg, 0.0, s);
+        if (e == hipSuccess && b->cg.vflag) e = rodk::launch_contact_finish(b->cg, nullptr, 0, s);
         if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
     }
     hipError_t e = b->precision == ROD_F32 ? rodk::launch_energy(b->b32, b->d_energy, s)
@@ -1408,6 +1431,7 @@ int rod_energy_noalloc(rod_batch *b, double *out, void *stream)
         // the pairs' potentials at the current positions (the batch's own grid buffers)
         hipError_t e = b->precision == ROD_F32 ? rodk::launch_contact(b->b32, b->cg, 0.0, s)
                                                : rodk::launch_contact(b->b64, b->cg, 0.0, s);
+        if (e == hipSuccess && b->cg.vflag) e = rodk::launch_contact_finish(b->cg, nullptr, 0, s);
         if (e != hipSuccess) return fail(ROD_EDEVICE, std::string("contact launch: ") + hipGetErrorString(e));
     }
     hipError_t e = b->precision == ROD_F32 ? rodk::launch_energy(b->b32, energies, s)
@@ -1487,6 +1511,23 @@ int rod_batch_info(const rod_batch *b, int64_t *info)
     return ROD_OK;
 }
 
+int rod_contact_stats(rod_batch *b, int64_t *out, void *stream)
+{
+    if (!b || !out) return fail(ROD_EINVAL, "handle or out is NULL");
+    for (int k = 0; k < 5; ++k) out[k] = 0;
+    if (!b->cg.vflag) return ROD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t f[rodk::CONTACT_VFLAGS];
+    HIPCHK(hipMemcpyAsync(f, b->cg.vflag, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out[0] = (uint32_t)f[rodk::VF_PASSES];
+    out[1] = (uint32_t)f[rodk::VF_BUILDS];
+    out[2] = (uint32_t)f[rodk::VF_FALLBACKS];
+    out[3] = f[rodk::VF_MOST];
+    out[4] = rodk::CONTACT_LIST_CAP;
+    return ROD_OK;
+}
+
 void rod_batch_destroy(rod_batch *b)
 {
     if (!b) return;
@@ -1513,6 +1554,10 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.xabs);
     (void)hipFree(b->cg.force);
     (void)hipFree(b->cg.pot);
+    (void)hipFree(b->cg.lcount);
+    (void)hipFree(b->cg.lid);
+    (void)hipFree(b->cg.xb);
+    (void)hipFree(b->cg.vflag);
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);
     (void)hipFree(b->d_mag);

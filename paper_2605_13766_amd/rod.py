@@ -45,6 +45,7 @@ class RodBatchDesc(C.Structure):
         ("n_walls", C.c_int32), ("walls", _dp), ("wall_k", C.c_double), ("wall_c", C.c_double),
         ("wall_mu", C.c_double), ("wall_vslip", C.c_double),
         ("rod_contact", C.c_int32),
+        ("contact_skin", C.c_double),
     ]
 
 
@@ -111,13 +112,14 @@ def lib():
         L.rod_set_state.argtypes = [vp, _dp, _dp, _dp, _dp, C.c_double, vp]
         L.rod_get_flags.argtypes = [vp, _ip, vp]
         L.rod_batch_info.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.rod_contact_stats.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.rod_batch_destroy.argtypes = [vp]
         L.rod_batch_tuning.argtypes = [vp, C.POINTER(TuneTrial), C.c_int32, C.POINTER(C.c_int32)]
         L.rod_batch_tuning.restype = C.c_int
         L.rod_batch_destroy.restype = None
         L.rod_last_error.restype = C.c_char_p
         for f in ("rod_batch_create", "rod_step", "rod_energy", "rod_energy_noalloc", "rod_get_state", "rod_set_state",
-                  "rod_get_flags", "rod_batch_info"):
+                  "rod_get_flags", "rod_batch_info", "rod_contact_stats"):
             getattr(L, f).restype = C.c_int
         fp = C.POINTER(C.c_float)
         L.rod_surrogate_create.argtypes = [C.POINTER(SurrogateDesc), C.POINTER(vp)]
@@ -183,9 +185,12 @@ class RodBatch:
     """A batch of rods resident on the GPU (owned by librod.so)."""
 
     def __init__(self, inp, precision: str = "f64", substeps: int = 0, tile_waves: int = 0,
-                 t0: float = 0.0, stream=None, autotune: bool = False, device_inputs: bool = False):
+                 t0: float = 0.0, stream=None, autotune: bool = False, device_inputs: bool = False,
+                 contact_skin: float = 0.0):
         """device_inputs: hand the library device copies (torch tensors) of every
-        input array instead of host arrays (inputs_on_device = 1)."""
+        input array instead of host arrays (inputs_on_device = 1).  contact_skin:
+        the Verlet-list skin of node-sphere contact (m; 0: half the largest
+        radius; negative: no lists)."""
         self._h = None
         prec = {"f64": ROD_F64, "f32": ROD_F32}[precision]
         keep = {}
@@ -232,6 +237,7 @@ class RodBatch:
             d.n_walls = int(keep["walls"].shape[0])
             d.walls = keep["walls"].ctypes.data_as(_dp)
         d.rod_contact = int(getattr(inp, "rod_contact", 0) or 0)
+        d.contact_skin = float(contact_skin)
         if d.n_walls > 0 or d.rod_contact:
             d.wall_k, d.wall_c = float(inp.wall_k), float(inp.wall_c)
             d.wall_mu, d.wall_vslip = float(inp.wall_mu), float(inp.wall_vslip)
@@ -313,6 +319,13 @@ class RodBatch:
         _check(lib().rod_batch_info(self._h, a))
         keys = ("n_rods", "n_elements", "n_tiles", "tile_waves", "substeps", "precision", "n_slots",
                 "steps")
+        return dict(zip(keys, [int(x) for x in a]))
+
+    def contact_stats(self, stream=None) -> dict:
+        """rod_contact_stats: the Verlet-list counters (zeros without lists)."""
+        a = (C.c_int64 * 5)()
+        _check(lib().rod_contact_stats(self._h, a, _stream_ptr(stream)))
+        keys = ("passes", "builds", "fallbacks", "most_partners", "capacity")
         return dict(zip(keys, [int(x) for x in a]))
 
     def close(self):

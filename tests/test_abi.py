@@ -179,6 +179,8 @@ def test_rod_contact_descriptor_rejected_when_invalid():
     bad = base.copy(); bad.rod_contact = 3
     assert "rod_contact" in _expect(rod.ROD_EINVAL, bad)
     assert "substeps" in _expect(rod.ROD_EINVAL, base, substeps=2)
+    assert "contact_skin" in _expect(rod.ROD_EINVAL, base, contact_skin=float("nan"))
+    assert "contact_skin" in _expect(rod.ROD_EINVAL, base, contact_skin=float("inf"))
     bad = base.copy(); bad.walls = None; bad.wall_vslip = 0.0
     assert "wall_vslip" in _expect(rod.ROD_EINVAL, bad)
 
