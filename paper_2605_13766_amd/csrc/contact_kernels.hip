@@ -62,8 +62,8 @@ __device__ inline bool contact_node(const DevBatch<double> &B, const ContactGrid
 }
 
 // FP32 batches hold edges and each rod's anchor: the positions come from
-// contact_positions_kernel (already advanced by the drift), velocities from
-// the state.
+// contact_positions_kernel (already advanced by the drift; in the Verlet
+// records when the batch keeps lists), velocities from the state.
 __device__ inline bool contact_node(const DevBatch<float> &B, const ContactGrid &G, int64_t id, double, int &rod,
                                     double x[3], double v[3])
 {
@@ -76,7 +76,14 @@ __device__ inline bool contact_node(const DevBatch<float> &B, const ContactGrid 
         rod = (int)(id - NS);
         for (int a = 0; a < 3; ++a) v[a] = (double)B.tail[(TVX + a) * B.n_rods + rod];
     }
-    for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nid + id];
+    if (G.rec) {
+        const double4 r = G.rec[2 * id];
+        x[0] = r.x;
+        x[1] = r.y;
+        x[2] = r.z;
+    } else {
+        for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nid + id];
+    }
     return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
 }
 
@@ -84,7 +91,9 @@ __device__ inline bool contact_node(const DevBatch<float> &B, const ContactGrid 
 // the node, summed in FP64 and advanced by the drift.  One wave per rod: the
 // lanes take 64 consecutive nodes at a time (coalesced loads and stores), an
 // exclusive prefix sum of the FP32 edges across the lanes places them, and
-// the chunk's total carries to the next 64.
+// the chunk's total carries to the next 64.  With Verlet lists the positions
+// go into the nodes' records instead, with the move check of the pack kernel
+// below.
 __global__ __launch_bounds__(256) void contact_positions_kernel(const DevBatch<float> B, const ContactGrid G,
                                                                 double drift)
 {
@@ -110,13 +119,29 @@ __global__ __launch_bounds__(256) void contact_positions_kernel(const DevBatch<f
             const double up = __shfl_up(incl[a], 1, 64);
             before[a] = lane > 0 ? up : 0.0;
         }
+        int moved = 0;
         if (j <= n) {
             const int64_t id = j < n ? s0 + j : NS + rod;
+            double x[3], v[3];
             for (int a = 0; a < 3; ++a) {
-                const double v = j < n ? (double)B.state[(VX + a) * NS + s0 + j] : (double)B.tail[(TVX + a) * R + rod];
-                G.xabs[a * nn + id] = carry[a] + before[a] + drift * v;
+                v[a] = j < n ? (double)B.state[(VX + a) * NS + s0 + j] : (double)B.tail[(TVX + a) * R + rod];
+                x[a] = carry[a] + before[a] + drift * v[a];
+            }
+            if (G.rec) {
+                G.rec[2 * id] = make_double4(x[0], x[1], x[2], B.rod_rad[rod]);
+                G.rec[2 * id + 1] = make_double4(v[0], v[1], v[2], (double)rod);
+                if (isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2])) {
+                    const double h = 0.5 * G.skin;
+                    const double e0 = x[0] - G.xb[id], e1 = x[1] - G.xb[nn + id], e2 = x[2] - G.xb[2 * nn + id];
+                    moved = !(e0 * e0 + e1 * e1 + e2 * e2 <= h * h);
+                } else {
+                    G.xb[id] = NAN;   // a node that turns finite again (a new state) forces a build
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) G.xabs[a * nn + id] = x[a];
             }
         }
+        if (__any(moved) && lane == 0) atomicOr(&G.vflag[VF_REQUEST], 1);
         for (int a = 0; a < 3; ++a) carry[a] += __shfl(incl[a], 63, 64);
     }
 }
@@ -374,69 +399,43 @@ __device__ inline void sphere_pair(const double x[3], const double v[3], double 
     f[2] += fn * n2 - gf * t2;
 }
 
-// A listed partner's position `drift` ahead and velocity, as contact_node
-// gives them, without its branches: slot and tail arrays keep position and
-// velocity at the same field offsets.  A partner that is not finite fails
-// the pair's distance test.
-static_assert((int)RX == (int)TRX && (int)VX == (int)TVX, "slot and tail fields share offsets");
-
-__device__ inline void listed_partner(const DevBatch<double> &B, const ContactGrid &, int64_t p, double drift,
-                                      double4 &y, double4 &u)
+// Verlet lists: every node's record for the pass, two double4 per id:
+// (position after the drift, radius) and (velocity, rod; -1 for padding).
+// A node that is not finite fails every pair's distance test.
+__device__ inline void node_record(const ContactGrid &G, int64_t p, double4 &y, double4 &u)
 {
-    const int64_t NS = B.n_slots;
-    const bool slot = p < NS;
-    const double *const src = slot ? B.state + p : B.tail + (p - NS);
-    const int64_t st = slot ? NS : B.n_rods;
-    u = make_double4(src[(VX + 0) * st], src[(VX + 1) * st], src[(VX + 2) * st], 0.0);
-    y = make_double4(ahead(src[(RX + 0) * st], drift, u.x), ahead(src[(RX + 1) * st], drift, u.y),
-                     ahead(src[(RX + 2) * st], drift, u.z), 0.0);
-}
-
-__device__ inline void listed_partner(const DevBatch<float> &B, const ContactGrid &G, int64_t p, double, double4 &y,
-                                      double4 &u)
-{
-    const int64_t NS = B.n_slots;
-    const bool slot = p < NS;
-    const float *const src = slot ? B.state + p : B.tail + (p - NS);
-    const int64_t st = slot ? NS : B.n_rods;
-    u = make_double4((double)src[(VX + 0) * st], (double)src[(VX + 1) * st], (double)src[(VX + 2) * st], 0.0);
-    y = make_double4(G.xabs[p], G.xabs[G.nid + p], G.xabs[2 * G.nid + p], 0.0);
+    y = G.rec[2 * p];
+    u = G.rec[2 * p + 1];
 }
 
 // Up to four listed pairs of a node (entries e[0..m-1]; the rest are ignored
-// but must name valid nodes): the partners' loads all go out before the
+// but must name valid nodes): the partners' records all load before the
 // pairs are evaluated, in entry order.
 template <typename T>
-__device__ inline void listed_pairs4(const DevBatch<T> &B, const ContactGrid &G, const int2 e[4], int m,
-                                     double drift, const double x[3], const double v[3], double ra, double f[3],
-                                     double &pot)
+__device__ inline void listed_pairs4(const DevBatch<T> &B, const ContactGrid &G, const int32_t e[4], int m,
+                                     const double x[3], const double v[3], double ra, double f[3], double &pot)
 {
     const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
     double4 y[4], u[4];
-    double rb[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        listed_partner(B, G, e[q].x, drift, y[q], u[q]);
-        rb[q] = B.rod_rad[e[q].y];
-    }
+    for (int q = 0; q < 4; ++q) node_record(G, e[q], y[q], u[q]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        if (q < m) sphere_pair(x, v, ra, y[q], u[q], rb[q], k, c, mu, vs, f, pot);
+        if (q < m) sphere_pair(x, v, ra, y[q], u[q], y[q].w, k, c, mu, vs, f, pot);
 }
 
-// A node's contacts over its Verlet list entries j0 .. n-1 (partner id and
-// rod), in list (increasing id) order, four entries at a time (entries past
-// the end repeat the last one and are not evaluated).
+// A node's contacts over its Verlet list entries j0 .. n-1, in list
+// (increasing id) order, four entries at a time (entries past the end repeat
+// the last one and are not evaluated).
 template <typename T>
 __device__ inline void list_contacts(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int j0, int n,
-                                     double drift, const double x[3], const double v[3], double ra, double f[3],
-                                     double &pot)
+                                     const double x[3], const double v[3], double ra, double f[3], double &pot)
 {
     for (; j0 < n; j0 += 4) {
-        int2 e[4];
+        int32_t e[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) e[q] = G.lid[min(j0 + q, n - 1) * G.nid + id];
-        listed_pairs4(B, G, e, n - j0, drift, x, v, ra, f, pot);
+        listed_pairs4(B, G, e, n - j0, x, v, ra, f, pot);
     }
 }
 
@@ -499,7 +498,7 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
             const double4 u = G.svr[p];
             sphere_pair(x, v, ra, G.spr[p], u, u.w, k, c, mu, vs, f, pot);
             if constexpr (LIST) {
-                if (n_list < CONTACT_LIST_CAP) G.lid[n_list * NI + id] = make_int2(G.sid[p], (int)G.spr[p].w);
+                if (n_list < CONTACT_LIST_CAP) G.lid[n_list * NI + id] = G.sid[p];
                 ++n_list;
             }
         }
@@ -516,18 +515,18 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
         if (n_list > CONTACT_LIST_CAP) {
             atomicOr(&G.vflag[VF_OVERFLOW], 1);   // forces of the sweep's order; the next pass builds again
         } else {
-            int2 *const L = G.lid + id;   // insertion sort by id (the sweep left it sorted within buckets)
+            int32_t *const L = G.lid + id;   // insertion sort by id (the sweep left it sorted within buckets)
             for (int i = 1; i < n_list; ++i) {
-                const int2 key = L[i * NI];
+                const int32_t key = L[i * NI];
                 int j = i - 1;
-                while (j >= 0 && L[j * NI].x > key.x) {
+                while (j >= 0 && L[j * NI] > key) {
                     L[(j + 1) * NI] = L[j * NI];
                     --j;
                 }
                 L[(j + 1) * NI] = key;
             }
             f[0] = f[1] = f[2] = pot = 0.0;
-            list_contacts(B, G, id, 0, n_list, drift, x, v, ra, f, pot);
+            list_contacts(B, G, id, 0, n_list, x, v, ra, f, pot);
         }
     }
     if (!live) return;
@@ -537,47 +536,87 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
     G.pot[id] = pot;
 }
 
-// Verlet lists, first kernel of every pass: each node sums its contacts over
-// its list, and asks for a build when it has moved more than half the skin
+// Verlet lists, first kernel of every pass: every node's record (above),
+// and a request for a build when a node has moved more than half the skin
 // from its position at the last one (a NaN position there counts as moved).
 // Without a build no pair missing from the lists can touch: the pair was at
 // least its radii plus the skin apart at the build (up to the 1e-9 widening)
-// and each node has moved at most half the skin since.  With a build the
-// forces computed here are replaced.  The node's own loads and its first 8
-// list entries go out together (padding slots and ids past the end read
-// valid addresses and do nothing; entries past the node's count name valid
-// nodes, and are replaced by the node itself before its partners are read);
-// padding ids keep the zeros set at creation.
+// and each node has moved at most half the skin since.
+// A node's position `drift` ahead and velocity, as contact_node gives them,
+// without its branches: slot and tail arrays keep position and velocity at
+// the same field offsets.
+static_assert((int)RX == (int)TRX && (int)VX == (int)TVX, "slot and tail fields share offsets");
+
+__device__ inline void node_state(const DevBatch<double> &B, const ContactGrid &, int64_t p, double drift,
+                                  double x[3], double v[3])
+{
+    const int64_t NS = B.n_slots;
+    const bool slot = p < NS;
+    const double *const src = slot ? B.state + p : B.tail + (p - NS);
+    const int64_t st = slot ? NS : B.n_rods;
+    for (int a = 0; a < 3; ++a) v[a] = src[(VX + a) * st];
+    for (int a = 0; a < 3; ++a) x[a] = ahead(src[(RX + a) * st], drift, v[a]);
+}
+
+__device__ inline void node_state(const DevBatch<float> &B, const ContactGrid &G, int64_t p, double, double x[3],
+                                  double v[3])
+{
+    const int64_t NS = B.n_slots;
+    const bool slot = p < NS;
+    const float *const src = slot ? B.state + p : B.tail + (p - NS);
+    const int64_t st = slot ? NS : B.n_rods;
+    for (int a = 0; a < 3; ++a) v[a] = (double)src[(VX + a) * st];
+    for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nid + p];
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void verlet_force_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+__global__ __launch_bounds__(256) void verlet_pack_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
 {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, NI = G.nid, NS = B.n_slots;
+    // every load goes out at once (ids past the end read the last id's)
     const int64_t ic = id < NI ? id : NI - 1;
     const int rod = ic < NS ? B.slot_rod[ic] : (int)(ic - NS);
-    double4 y, u;
-    listed_partner(B, G, ic, drift, y, u);
+    double x[3], v[3];
+    node_state(B, G, ic, drift, x, v);
     const double b0 = G.xb[ic], b1 = G.xb[NI + ic], b2 = G.xb[2 * NI + ic];
-    const int n = min(G.lcount[ic], CONTACT_LIST_CAP);   // larger only after an overflow, when a build follows
-    int2 e[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) e[q] = G.lid[q * NI + ic];
+    const double rad = B.rod_rad[rod < 0 ? 0 : rod];
     const bool live = id < NI && rod >= 0;
-    const bool ok = live && isfinite(y.x) && isfinite(y.y) && isfinite(y.z);
-    const double h = 0.5 * G.skin, e0 = y.x - b0, e1 = y.y - b1, e2 = y.z - b2;
+    const bool ok = live && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+    const double h = 0.5 * G.skin, e0 = x[0] - b0, e1 = x[1] - b1, e2 = x[2] - b2;
     const int moved = ok && !(e0 * e0 + e1 * e1 + e2 * e2 <= h * h);
-    if (live && !ok) G.xb[id] = NAN;   // a node that turns finite again (a new state) forces a build
     if (__any(moved) && (threadIdx.x & 63) == 0) atomicOr(&G.vflag[VF_REQUEST], 1);
     if (!live) return;
+    G.rec[2 * id] = make_double4(x[0], x[1], x[2], rad);
+    G.rec[2 * id + 1] = make_double4(v[0], v[1], v[2], (double)rod);
+    if (!ok) G.xb[id] = NAN;   // a node that turns finite again (a new state) forces a build
+}
+
+// Verlet lists, every pass: each node sums its contacts over its list from
+// the records.  The node's record, count and first 8 entries load together
+// (entries past the count name valid nodes, and are replaced by the node
+// itself before the partners' records are read).  With a build in this pass
+// the forces computed here are replaced.  Padding ids keep the zeros set at
+// creation.
+template <typename T>
+__global__ __launch_bounds__(256) void verlet_force_kernel(const DevBatch<T> B, const ContactGrid G)
+{
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, NI = G.nid;
+    if (id >= NI) return;
+    double4 y, u;
+    node_record(G, id, y, u);
+    const int n = min(G.lcount[id], CONTACT_LIST_CAP);   // larger only after an overflow, when a build follows
+    int32_t e[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = G.lid[q * NI + id];
+    if (u.w < 0.0) return;   // padding
     double f[3] = {0.0, 0.0, 0.0}, pot = 0;
     const double x[3] = {y.x, y.y, y.z}, v[3] = {u.x, u.y, u.z};
-    if (ok && n > 0) {
-        const int2 self = make_int2((int)ic, rod);
+    if (n > 0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) e[q] = q < n ? e[q] : self;
-        const double ra = B.rod_rad[rod];
-        listed_pairs4(B, G, e, n, drift, x, v, ra, f, pot);
-        if (n > 4) listed_pairs4(B, G, e + 4, n - 4, drift, x, v, ra, f, pot);
-        if (n > 8) list_contacts(B, G, id, 8, n, drift, x, v, ra, f, pot);
+        for (int q = 0; q < 8; ++q) e[q] = q < n ? e[q] : (int32_t)id;
+        listed_pairs4(B, G, e, n, x, v, y.w, f, pot);
+        if (n > 4) listed_pairs4(B, G, e + 4, n - 4, x, v, y.w, f, pot);
+        if (n > 8) list_contacts(B, G, id, 8, n, x, v, y.w, f, pot);
     }
     G.force[id] = f[0];
     G.force[NI + id] = f[1];
@@ -910,19 +949,21 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
     const int n_chunks = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
     const int gn = (int)((g.nn + bs - 1) / bs);
     if constexpr (sizeof(T) == 4) {
-        if (!g.xabs || !g.origin) return hipErrorInvalidValue;
+        if ((!g.xabs && !g.rec) || !g.origin) return hipErrorInvalidValue;
         hipLaunchKernelGGL(contact_positions_kernel, dim3((b.n_rods + 3) / 4), dim3(256), 0, s, b, g, drift);
     }
     const bool seg = g.mode == 2;
     if (seg ? (!g.sca || !g.fseg || !g.self_pairs || !g.cull) : !g.spr) return hipErrorInvalidValue;
     const bool lists = !seg && g.skin > 0.0;
-    if (lists && (!g.lcount || !g.lid || !g.xb || !g.vflag)) return hipErrorInvalidValue;
+    if (lists && (!g.lcount || !g.lid || !g.xb || !g.rec || !g.vflag)) return hipErrorInvalidValue;
     const unsigned gf = (unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK);
     Gate build;   // with lists the grid pass runs only in passes that rebuild them
     if (lists) {
         build.p = g.vflag + VF_REQUEST;
-        hipLaunchKernelGGL((verlet_force_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g,
-                           drift);
+        const dim3 gi((unsigned)((g.nid + bs - 1) / bs));
+        // FP32 batches: the positions kernel above wrote the records
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((verlet_pack_kernel<T>), gi, dim3(bs), 0, s, b, g, drift);
+        hipLaunchKernelGGL((verlet_force_kernel<T>), gi, dim3(bs), 0, s, b, g);
     }
     if (seg) hipLaunchKernelGGL((seg_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
     else hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, build);

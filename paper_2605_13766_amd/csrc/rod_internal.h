@@ -179,8 +179,9 @@ struct ContactGrid {
     // more than skin / 2 since
     double skin;       // 0: no lists (the grid pass every step)
     int32_t *lcount;   // [nid] partners listed (more than CONTACT_LIST_CAP: the build overflowed)
-    int2 *lid;         // [CONTACT_LIST_CAP][nid] partner id and its rod
+    int32_t *lid;      // [CONTACT_LIST_CAP][nid] partner ids
     double *xb;        // [3][nid] positions at the last build (NaN: none yet, or the node was not finite)
+    double4 *rec;      // [2 nid] per pass: (position after the drift, radius), (velocity, rod) of each id
     // [CONTACT_VFLAGS]: this pass builds, this pass's build overflowed; then
     // counters (passes, builds, builds that overflowed, most partners of one
     // node at a build)

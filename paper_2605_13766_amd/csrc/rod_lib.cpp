@@ -907,7 +907,8 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
         if (g.skin > 0) {
             HIPCHK(hipMalloc((void **)&g.lcount, g.nid * sizeof(int32_t)));
-            HIPCHK(hipMalloc((void **)&g.lid, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int2)));
+            HIPCHK(hipMalloc((void **)&g.lid, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int32_t)));
+            HIPCHK(hipMalloc((void **)&g.rec, 2 * g.nid * sizeof(double4)));
             HIPCHK(hipMalloc((void **)&g.xb, 3 * g.nid * sizeof(double)));
             HIPCHK(hipMalloc((void **)&g.vflag, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
             // no build yet (NaN positions: the first pass builds)
@@ -915,7 +916,10 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
             HIPCHK(hipMemcpy(g.xb, nan3.data(), nan3.size() * sizeof(double), hipMemcpyHostToDevice));
             HIPCHK(hipMemset(g.lcount, 0, g.nid * sizeof(int32_t)));
             // every entry names a valid node (the list pass reads entries past a count)
-            HIPCHK(hipMemset(g.lid, 0, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int2)));
+            HIPCHK(hipMemset(g.lid, 0, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int32_t)));
+            // padding ids keep rod -1 (the pack kernel writes real nodes only)
+            const std::vector<double4> pad(2 * g.nid, make_double4(0.0, 0.0, 0.0, -1.0));
+            HIPCHK(hipMemcpy(g.rec, pad.data(), pad.size() * sizeof(double4), hipMemcpyHostToDevice));
             HIPCHK(hipMemset(g.vflag, 0, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
         }
     }
@@ -934,7 +938,7 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         HIPCHK(hipMalloc((void **)&d_org, org.size() * sizeof(double)));
         g.origin = d_org;
         HIPCHK(hipMemcpy(d_org, org.data(), org.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMalloc((void **)&g.xabs, 3 * g.nid * sizeof(double)));
+        if (!g.rec) HIPCHK(hipMalloc((void **)&g.xabs, 3 * g.nid * sizeof(double)));   // else in the records
     }
     HIPCHK(hipDeviceSynchronize());
     return ROD_OK;
@@ -1557,6 +1561,7 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.lcount);
     (void)hipFree(b->cg.lid);
     (void)hipFree(b->cg.xb);
+    (void)hipFree(b->cg.rec);
     (void)hipFree(b->cg.vflag);
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);
