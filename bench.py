@@ -137,6 +137,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         launch_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
         after = probe(b, stream) if probe else None
         flags = b.flags(stream=stream)
+        cstats = b.contact_stats(stream=stream) if getattr(inp, "rod_contact", 0) == 1 else None
         b.close()
     if flags.any():
         raise RuntimeError(f"{int(flags.sum())} rods became non-finite")
@@ -153,6 +154,7 @@ def time_gpu(inp, precision, steps, warmup, tile_waves=0, substeps=0, algo_flop=
         "info": info,
         "algo_flop": algo_flop,
         "probe": (before, after) if probe else None,
+        "contact_stats": cstats,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
@@ -258,7 +260,8 @@ CONTACT_NODE_BYTES = 72                          # a contact pass: node position
 
 def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH, precisions=("f64", "f32")):
     """The fibre pile (16,384 fibres x 50 elements in 21 crossed layers on a
-    floor, rod-rod contact found by the hash grid every step), FP64 (the
+    floor, rod-rod contact over Verlet lists that the hash grid rebuilds when
+    a node has moved more than half the skin), FP64 (the
     object's own figures) and FP32 (its "f32" member).  One step per launch, so
     the pass is HBM-bound: the roofline is bytes against the HBM peak,
     algorithmic bytes per step = the step's 400 (FP64) / 204 (FP32) per element
@@ -271,7 +274,8 @@ def time_contact(steps, warmup, tile_waves=0, n_steps=STEPS_PER_LAUNCH, precisio
         if out is None:
             out = row
         else:
-            out[p] = {k: row[k] for k in ("value", "ms_per_step", "ms_per_simulation_step", "tile_waves", "roofline")}
+            out[p] = {k: row[k] for k in ("value", "ms_per_step", "ms_per_simulation_step", "tile_waves",
+                                          "verlet_lists", "roofline")}
     return out
 
 
@@ -304,12 +308,13 @@ def _time_contact_one(inp, precision, steps, warmup, tile_waves, n_steps, tag="f
     achieved = algo / step_s / 1e9
     return {
         "workload": f"fibre_pile: {inp.n_rods:,} fibres x 50 elements (0.5 m, radius 1 cm) in 21 crossed layers on a "
-                    f"floor, rod-rod contact (k {inp.wall_k:g} N/m, mu {inp.wall_mu:g}), gravity, dt 1e-5 s, "
-                    f"one step per launch, {precision.upper()}",
+                    f"floor, rod-rod contact (k {inp.wall_k:g} N/m, mu {inp.wall_mu:g}) over Verlet lists (skin 2 mm), "
+                    f"gravity, dt 1e-5 s, one step per launch, {precision.upper()}",
         "unit": "element-steps/s",
         "value": r["value"], "ms_per_step": r["ms_per_step"], "steps_per_bench_step": n_steps,
         "ms_per_simulation_step": step_s * 1e3,
         "tile_waves": r["info"]["tile_waves"], "substeps_per_launch": r["info"]["substeps"],
+        **({"verlet_lists": r["contact_stats"]} if r["contact_stats"] else {}),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                      "frac": achieved / 8000.0,
                      "traffic": traffic_from_profile(f"{precision}_{tag}", r["info"]["tile_waves"], 1,

@@ -208,7 +208,7 @@ typedef struct {
      * next step builds again).  Every step sums each node's contacts over its
      * list in increasing node order, so the results do not depend on s or on
      * when the lists were built (bit for bit, while no list overflows).
-     * 0: s = half the largest radius; < 0: no lists (the grid pass every
+     * 0: s = a fifth of the largest radius; < 0: no lists (the grid pass every
      * step, contacts summed in grid order).  Not finite: ROD_EINVAL. */
     double contact_skin;             /* m */
 } rod_batch_desc;

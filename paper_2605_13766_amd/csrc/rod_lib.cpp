@@ -114,7 +114,7 @@ struct rod_batch {
     int n_walls = 0;
     bool rod_contact = false;          // rod-rod contact: a grid pass before every step
     int contact_mode = 0;              // 1: node spheres, 2: element capsules
-    double contact_skin = 0;           // as given (mode 1: < 0 no Verlet lists, 0 half the largest radius)
+    double contact_skin = 0;           // as given (mode 1: < 0 no Verlet lists, 0 a fifth of the largest radius)
     rodk::ContactGrid cg{};
     double walls[ROD_MAX_WALLS][4] = {};
     double wall_k = 0, wall_c = 0, wall_mu = 0, wall_vslip = 0;
@@ -824,9 +824,9 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     // midpoints are at most (l_a + l_b) / 2 + r_a + r_b apart, so cells hold the
     // longest element stretched by a quarter plus twice the largest radius
     g.cell_len = 1.25 * lmax;
-    // mode 1: Verlet lists unless the skin is negative; 0 picks half the
-    // largest radius (a node may then move a quarter radius between builds)
-    g.skin = g.mode == 1 && b->contact_skin >= 0 ? (b->contact_skin > 0 ? b->contact_skin : 0.5 * rmax) : 0.0;
+    // mode 1: Verlet lists unless the skin is negative; 0 picks a fifth of
+    // the largest radius (a node may then move a tenth of it between builds)
+    g.skin = g.mode == 1 && b->contact_skin >= 0 ? (b->contact_skin > 0 ? b->contact_skin : 0.2 * rmax) : 0.0;
     const double cell = g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax + g.skin;
     g.inv_cell = 1.0 / cell;
     g.rmax = rmax;

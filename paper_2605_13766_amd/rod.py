@@ -189,8 +189,8 @@ class RodBatch:
                  contact_skin: float = 0.0):
         """device_inputs: hand the library device copies (torch tensors) of every
         input array instead of host arrays (inputs_on_device = 1).  contact_skin:
-        the Verlet-list skin of node-sphere contact (m; 0: half the largest
-        radius; negative: no lists)."""
+        the Verlet-list skin of node-sphere contact (m; 0: a fifth of the
+        largest radius; negative: no lists)."""
         self._h = None
         prec = {"f64": ROD_F64, "f32": ROD_F32}[precision]
         keep = {}

@@ -57,8 +57,8 @@ def _same(a, b):
 
 
 def test_skin_does_not_change_results():
-    """A skin of 1e-9 m (a build almost every step), the default (half the
-    radius) and two radii: the same bits after 1000 FP64 steps (energies
+    """A skin of 1e-9 m (a build almost every step), the default (a fifth of
+    the radius) and two radii: the same bits after 1000 FP64 steps (energies
     included) and 400 FP32 steps; the smallest skin rebuilds far more often."""
     inp = _small_pile(seed=93)
     out = {}
@@ -105,8 +105,8 @@ def test_overflowing_lists_fall_back_to_grid_order():
     """With a skin of two radii the middle rod's nodes of the bundle have 42
     partners: every pass rebuilds, finds the overflow, sums those nodes'
     contacts in grid order and asks the next pass to build again; against the
-    oracle as every contact test.  With the default skin (18 partners) the
-    lists hold."""
+    oracle as every contact test.  With the default skin (a fifth of the
+    radius: 6 partners) the lists hold."""
     R = _rod()
     inp = _bundle()
     print("case: 7-rod bundle, FP64, 1000 steps, contact_skin=0.02 (overflowing lists)", flush=True)
