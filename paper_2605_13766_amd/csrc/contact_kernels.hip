@@ -173,6 +173,7 @@ __global__ void contact_bin_kernel(const DevBatch<T> B, const ContactGrid G, dou
     if (gate.skip()) return;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn) return;
+    if (G.need) G.need[id] = 0;   // the build marks the records its lists use
     int rod;
     double x[3], v[3];
     if (!contact_node(B, G, id, drift, rod, x, v)) {
@@ -439,6 +440,25 @@ __device__ inline void list_contacts(const DevBatch<T> &B, const ContactGrid &G,
     }
 }
 
+// The same sum, each partner read as contact_node gives it (the values the
+// records hold), for the pass that builds the lists: records are written
+// only for the nodes the previous lists used.  A partner that is not finite
+// adds nothing, as its record's failed distance test does.
+template <typename T>
+__device__ inline void list_contacts_state(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int n,
+                                           double drift, const double x[3], const double v[3], double ra,
+                                           double f[3], double &pot)
+{
+    const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
+    for (int j = 0; j < n; ++j) {
+        int rb;
+        double y[3], u[3];
+        if (!contact_node(B, G, G.lid[j * G.nid + id], drift, rb, y, u)) continue;
+        sphere_pair(x, v, ra, make_double4(y[0], y[1], y[2], 0.0), make_double4(u[0], u[1], u[2], 0.0),
+                    B.rod_rad[rb], k, c, mu, vs, f, pot);
+    }
+}
+
 // Each node sums its contacts with the nodes of other rods in the 27 buckets
 // around it: the walls' law between two spheres.  Threads take the nodes in
 // bucket order, so neighbouring threads read the same buckets.  The screen
@@ -526,7 +546,11 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
                 L[(j + 1) * NI] = key;
             }
             f[0] = f[1] = f[2] = pot = 0.0;
-            list_contacts(B, G, id, 0, n_list, x, v, ra, f, pot);
+            list_contacts_state(B, G, id, n_list, drift, x, v, ra, f, pot);
+            if (G.need && n_list > 0) {   // the records the list pass will read
+                G.need[id] = 1;
+                for (int j = 0; j < n_list; ++j) G.need[L[j * NI]] = 1;
+            }
         }
     }
     if (!live) return;
@@ -580,44 +604,37 @@ __global__ __launch_bounds__(256) void verlet_pack_kernel(const DevBatch<T> B, c
     node_state(B, G, ic, drift, x, v);
     const double b0 = G.xb[ic], b1 = G.xb[NI + ic], b2 = G.xb[2 * NI + ic];
     const double rad = B.rod_rad[rod < 0 ? 0 : rod];
+    const bool need = G.need[ic] != 0;
     const bool live = id < NI && rod >= 0;
     const bool ok = live && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
     const double h = 0.5 * G.skin, e0 = x[0] - b0, e1 = x[1] - b1, e2 = x[2] - b2;
     const int moved = ok && !(e0 * e0 + e1 * e1 + e2 * e2 <= h * h);
     if (__any(moved) && (threadIdx.x & 63) == 0) atomicOr(&G.vflag[VF_REQUEST], 1);
     if (!live) return;
-    G.rec[2 * id] = make_double4(x[0], x[1], x[2], rad);
-    G.rec[2 * id + 1] = make_double4(v[0], v[1], v[2], (double)rod);
+    if (need) {   // a node with partners, or some node's partner, at the last build
+        G.rec[2 * id] = make_double4(x[0], x[1], x[2], rad);
+        G.rec[2 * id + 1] = make_double4(v[0], v[1], v[2], (double)rod);
+    }
     if (!ok) G.xb[id] = NAN;   // a node that turns finite again (a new state) forces a build
 }
 
-// Verlet lists, every pass: each node sums its contacts over its list from
-// the records.  The node's record, count and first 8 entries load together
-// (entries past the count name valid nodes, and are replaced by the node
-// itself before the partners' records are read).  With a build in this pass
-// the forces computed here are replaced.  Padding ids keep the zeros set at
-// creation.
+// Verlet lists, every pass: each node with partners sums its contacts over
+// its list from the records.  A node without partners (padding ids too)
+// reads and writes nothing: its force and potential are the zeros the last
+// build wrote (or creation's).  With a build in this pass the forces
+// computed here are replaced.
 template <typename T>
 __global__ __launch_bounds__(256) void verlet_force_kernel(const DevBatch<T> B, const ContactGrid G)
 {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, NI = G.nid;
     if (id >= NI) return;
+    const int n = min(G.lcount[id], CONTACT_LIST_CAP);   // larger only after an overflow, when a build follows
+    if (n == 0) return;
     double4 y, u;
     node_record(G, id, y, u);
-    const int n = min(G.lcount[id], CONTACT_LIST_CAP);   // larger only after an overflow, when a build follows
-    int32_t e[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) e[q] = G.lid[q * NI + id];
-    if (u.w < 0.0) return;   // padding
     double f[3] = {0.0, 0.0, 0.0}, pot = 0;
     const double x[3] = {y.x, y.y, y.z}, v[3] = {u.x, u.y, u.z};
-    if (n > 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) e[q] = q < n ? e[q] : (int32_t)id;
-        listed_pairs4(B, G, e, n, x, v, y.w, f, pot);
-        if (n > 4) listed_pairs4(B, G, e + 4, n - 4, x, v, y.w, f, pot);
-        if (n > 8) list_contacts(B, G, id, 8, n, x, v, y.w, f, pot);
-    }
+    list_contacts(B, G, id, 0, n, x, v, y.w, f, pot);
     G.force[id] = f[0];
     G.force[NI + id] = f[1];
     G.force[2 * NI + id] = f[2];

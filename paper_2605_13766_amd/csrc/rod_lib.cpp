@@ -909,6 +909,10 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
             HIPCHK(hipMalloc((void **)&g.lcount, g.nid * sizeof(int32_t)));
             HIPCHK(hipMalloc((void **)&g.lid, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int32_t)));
             HIPCHK(hipMalloc((void **)&g.rec, 2 * g.nid * sizeof(double4)));
+            if (b->precision == ROD_F64) {   // FP32 records come from the positions kernel, all of them
+                HIPCHK(hipMalloc((void **)&g.need, g.nid));
+                HIPCHK(hipMemset(g.need, 0, g.nid));
+            }
             HIPCHK(hipMalloc((void **)&g.xb, 3 * g.nid * sizeof(double)));
             HIPCHK(hipMalloc((void **)&g.vflag, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
             // no build yet (NaN positions: the first pass builds)
@@ -1562,6 +1566,7 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.lid);
     (void)hipFree(b->cg.xb);
     (void)hipFree(b->cg.rec);
+    (void)hipFree(b->cg.need);
     (void)hipFree(b->cg.vflag);
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);
