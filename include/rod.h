@@ -199,17 +199,21 @@ typedef struct {
      * node (element) before the forces are summed, so runs are bitwise
      * repeatable and independent of tile_waves. */
     int32_t rod_contact;             /* 0, 1 (node spheres) or 2 (element capsules) */
-    /* Verlet lists for rod_contact = 1 (ignored otherwise).  With a skin s > 0
-     * the grid (cells of twice the largest radius plus s) lists, for every
-     * node, the nodes of other rods closer than its radius plus the largest
-     * radius plus s, and the grid pass runs again only in a step where some
-     * node has moved more than s/2 since (or a list would have held more
-     * than 32 partners: that node's contacts are summed in grid order and the
-     * next step builds again).  Every step sums each node's contacts over its
-     * list in increasing node order, so the results do not depend on s or on
-     * when the lists were built (bit for bit, while no list overflows).
-     * 0: s = a fifth of the largest radius; < 0: no lists (the grid pass every
-     * step, contacts summed in grid order).  Not finite: ROD_EINVAL. */
+    /* Verlet lists.  With a skin s > 0 the grid (cells grown by s) lists,
+     * for every node (rod_contact = 1), the nodes of other rods closer than
+     * its radius plus the largest radius plus s, or, for every element
+     * (rod_contact = 2), the elements it may touch whose segments are closer
+     * than the two radii plus s; the grid pass then runs again only in a
+     * step where some node has moved more than s/2 since (the distance
+     * between two nodes or two segments changes by at most the sum of their
+     * moves), or where a list would have held more than 32 partners (that
+     * item's contacts are summed in grid order and the next step builds
+     * again).  Every step sums each item's contacts over its list in
+     * increasing node (element slot) order, so the results do not depend on
+     * s or on when the lists were built (bit for bit, while no list
+     * overflows).  0: s = a fifth of the largest radius; < 0: no lists (the
+     * grid pass every step, contacts summed in grid order).  Not finite:
+     * ROD_EINVAL. */
     double contact_skin;             /* m */
 } rod_batch_desc;
 
@@ -329,12 +333,12 @@ int rod_get_flags(rod_batch *b, int32_t *nonfinite, void *stream);
  * [6] slots (tiles * 64 * tile_waves), [7] steps taken so far. */
 int rod_batch_info(const rod_batch *b, int64_t *info);
 
-/* Verlet-list counters of a batch with rod_contact = 1 and a skin > 0 (all
+/* Verlet-list counters of a batch with rod contact and a skin > 0 (all
  * zero otherwise): out[0] contact passes (one per step, one per energy call),
  * [1] passes that rebuilt the lists, [2] builds at which a list overflowed
- * (its node's contacts were summed in grid order, and the next pass built
- * again), [3] the most partners one node had at a build, [4] the list
- * capacity (32).  Counters wrap at 2^32.  Synchronises `stream`. */
+ * (its item's contacts were summed in grid order, and the next pass built
+ * again), [3] the most partners one node or element had at a build, [4] the
+ * list capacity (32).  Counters wrap at 2^32.  Synchronises `stream`. */
 int rod_contact_stats(rod_batch *b, int64_t *out, void *stream);
 
 void rod_batch_destroy(rod_batch *b);

@@ -376,7 +376,7 @@ __device__ inline int64_t xcd_contiguous_block()
 // The walls' law between two spheres: node a at x (velocity v, radius ra)
 // against a partner at q (velocity u, radius rb); adds a's force to f and
 // a's share of the pair's potential (half) to pot.
-__device__ inline void sphere_pair(const double x[3], const double v[3], double ra, const double4 &q, const double4 &u,
+__device__ __attribute__((always_inline)) inline void sphere_pair(const double x[3], const double v[3], double ra, const double4 &q, const double4 &u,
                                    double rb, double k, double c, double mu, double vs, double f[3], double &pot)
 {
     const double e0 = x[0] - q.x, e1 = x[1] - q.y, e2 = x[2] - q.z;
@@ -403,7 +403,7 @@ __device__ inline void sphere_pair(const double x[3], const double v[3], double 
 // Verlet lists: every node's record for the pass, two double4 per id:
 // (position after the drift, radius) and (velocity, rod; -1 for padding).
 // A node that is not finite fails every pair's distance test.
-__device__ inline void node_record(const ContactGrid &G, int64_t p, double4 &y, double4 &u)
+__device__ __attribute__((always_inline)) inline void node_record(const ContactGrid &G, int64_t p, double4 &y, double4 &u)
 {
     y = G.rec[2 * p];
     u = G.rec[2 * p + 1];
@@ -413,7 +413,7 @@ __device__ inline void node_record(const ContactGrid &G, int64_t p, double4 &y, 
 // but must name valid nodes): the partners' records all load before the
 // pairs are evaluated, in entry order.
 template <typename T>
-__device__ inline void listed_pairs4(const DevBatch<T> &B, const ContactGrid &G, const int32_t e[4], int m,
+__device__ __attribute__((always_inline)) inline void listed_pairs4(const DevBatch<T> &B, const ContactGrid &G, const int32_t e[4], int m,
                                      const double x[3], const double v[3], double ra, double f[3], double &pot)
 {
     const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
@@ -429,7 +429,7 @@ __device__ inline void listed_pairs4(const DevBatch<T> &B, const ContactGrid &G,
 // (increasing id) order, four entries at a time (entries past the end repeat
 // the last one and are not evaluated).
 template <typename T>
-__device__ inline void list_contacts(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int j0, int n,
+__device__ __attribute__((always_inline)) inline void list_contacts(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int j0, int n,
                                      const double x[3], const double v[3], double ra, double f[3], double &pot)
 {
     for (; j0 < n; j0 += 4) {
@@ -445,7 +445,7 @@ __device__ inline void list_contacts(const DevBatch<T> &B, const ContactGrid &G,
 // only for the nodes the previous lists used.  A partner that is not finite
 // adds nothing, as its record's failed distance test does.
 template <typename T>
-__device__ inline void list_contacts_state(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int n,
+__device__ __attribute__((always_inline)) inline void list_contacts_state(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int n,
                                            double drift, const double x[3], const double v[3], double ra,
                                            double f[3], double &pot)
 {
@@ -664,8 +664,9 @@ __global__ void verlet_finish_kernel(int32_t *vflag, int64_t *step, int64_t n)
 // most one cell apart per axis.
 
 // Each binned item's id to its place: the bucket's start plus its rank.
-__global__ void contact_scatter_ids(const ContactGrid G)
+__global__ void contact_scatter_ids(const ContactGrid G, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn) return;
     const int32_t r = G.rank[id];
@@ -675,8 +676,9 @@ __global__ void contact_scatter_ids(const ContactGrid G)
 
 // As contact_sort_kernel, for the ids alone: the segment records (128 bytes
 // each) are written afterwards, in sorted order, by seg_fill_kernel.
-__global__ void sort_ids_kernel(const ContactGrid G)
+__global__ void sort_ids_kernel(const ContactGrid G, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= G.nn || G.rank[id] != 0) return;
     const int b = G.bucket[id];
@@ -742,7 +744,7 @@ __device__ inline bool contact_segment(const DevBatch<T> &B, const ContactGrid &
 // positive length, s, t in [0, 1]: the convex quadratic's stationary s,
 // clamped; the best t for it, clamped; s again for a clamped t; s from 0 for
 // parallel segments.
-__device__ inline void closest_params(const double p0[3], const double p1[3], const double q0[3], const double q1[3],
+__device__ __attribute__((always_inline)) inline void closest_params(const double p0[3], const double p1[3], const double q0[3], const double q1[3],
                                       double &s, double &t)
 {
     const double d1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
@@ -769,13 +771,24 @@ __device__ inline void closest_params(const double p0[3], const double p1[3], co
 }
 
 template <typename T>
-__global__ void seg_bin_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+__global__ void seg_bin_kernel(const DevBatch<T> B, const ContactGrid G, double drift, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= G.nn) return;
     int rod, elem;
     double a[3], b[3], va[3], vb[3];
-    if (!contact_segment(B, G, s, drift, rod, elem, a, b, va, vb)) {
+    const bool ok = contact_segment(B, G, s, drift, rod, elem, a, b, va, vb);
+    if (G.lcount && rod >= 0) {
+        // Verlet lists: the build's positions of the element's node A, and of
+        // the rod's last node after its last element (NaN where not finite)
+        const int64_t NI = G.nid;
+        for (int k = 0; k < 3; ++k) G.xb[k * NI + s] = a[k];
+        if (elem + 1 == B.rod_n[rod])
+            for (int k = 0; k < 3; ++k) G.xb[k * NI + B.n_slots + rod] = b[k];
+        if (!ok) G.lcount[s] = 0;   // not binned: no partners until the next build
+    }
+    if (!ok) {
         // out of the grid this pass: its nodes take no shares from it
         G.rank[s] = -1;
         for (int k = 0; k < 6; ++k) G.fseg[k * G.nn + s] = 0.0;
@@ -795,8 +808,9 @@ __global__ void seg_bin_kernel(const DevBatch<T> B, const ContactGrid G, double 
 // Segment records in sorted order: (A, radius), (B, rod), (v_A, element),
 // v_B, and the screening record.
 template <typename T>
-__global__ void seg_fill_kernel(const DevBatch<T> B, const ContactGrid G, double drift, int nb)
+__global__ void seg_fill_kernel(const DevBatch<T> B, const ContactGrid G, double drift, int nb, Gate gate)
 {
+    if (gate.skip()) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= G.start[nb]) return;
     const int64_t s = G.sid[p];
@@ -811,6 +825,90 @@ __global__ void seg_fill_kernel(const DevBatch<T> B, const ContactGrid G, double
     cull_record(a, b, r, rod, elem, G, G.cull[2 * p], G.cull[2 * p + 1]);
 }
 
+// One capsule pair, seen from element e (records ua = (A, radius), ub = (B,
+// rod), uva = (v_A, element), uvb = v_B) against element q (qa, qb, qva, qvb):
+// the closest points and the force in one fixed order (the element first in
+// (rod, element) order takes the part of u), e taking the exact negative when
+// it is the second, so the two feel opposite forces to the last bit.  The
+// force goes to e's nodes as (1 - s) and s; a quarter of k delta^2 per
+// ordered pair is e's potential share.  Returns the closest points' distance.
+__device__ __attribute__((always_inline)) inline double capsule_pair(const double4 &ua, const double4 &ub, const double4 &uva, const double4 &uvb,
+                                      const double4 &qa, const double4 &qb, const double4 &qva, const double4 &qvb,
+                                      double k, double c, double mu, double vs, double fa[3], double fb[3],
+                                      double &pot)
+{
+    const int rod = (int)ub.w, elem = (int)uva.w;
+    const int qrod = (int)qb.w, qelem = (int)qva.w;
+    const double ra = ua.w;
+    const bool first = rod < qrod || (rod == qrod && elem < qelem);
+    // u: the pair's first element, w: the other
+    const double u0[3] = {first ? ua.x : qa.x, first ? ua.y : qa.y, first ? ua.z : qa.z};
+    const double u1[3] = {first ? ub.x : qb.x, first ? ub.y : qb.y, first ? ub.z : qb.z};
+    const double w0[3] = {first ? qa.x : ua.x, first ? qa.y : ua.y, first ? qa.z : ua.z};
+    const double w1[3] = {first ? qb.x : ub.x, first ? qb.y : ub.y, first ? qb.z : ub.z};
+    // the velocities picked component by component (a select of whole
+    // records would go through memory)
+    const double vu0[3] = {first ? uva.x : qva.x, first ? uva.y : qva.y, first ? uva.z : qva.z};
+    const double vu1[3] = {first ? uvb.x : qvb.x, first ? uvb.y : qvb.y, first ? uvb.z : qvb.z};
+    const double vw0[3] = {first ? qva.x : uva.x, first ? qva.y : uva.y, first ? qva.z : uva.z};
+    const double vw1[3] = {first ? qvb.x : uvb.x, first ? qvb.y : uvb.y, first ? qvb.z : uvb.z};
+    const double ru = first ? ra : qa.w, rw = first ? qa.w : ra;
+    double su, sw;
+    closest_params(u0, u1, w0, w1, su, sw);
+    const double pu[3] = {u0[0] + su * (u1[0] - u0[0]), u0[1] + su * (u1[1] - u0[1]), u0[2] + su * (u1[2] - u0[2])};
+    const double pw[3] = {w0[0] + sw * (w1[0] - w0[0]), w0[1] + sw * (w1[1] - w0[1]), w0[2] + sw * (w1[2] - w0[2])};
+    const double e0 = pu[0] - pw[0], e1 = pu[1] - pw[1], e2 = pu[2] - pw[2];
+    const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    const double delta = ru + rw - dist;
+    if (!(delta > 0.0)) return dist;
+    pot += 0.25 * k * delta * delta;
+    if (!(dist > 0.0)) return dist;   // the segments cross: no direction
+    const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
+    const double r0 = ((1.0 - su) * vu0[0] + su * vu1[0]) - ((1.0 - sw) * vw0[0] + sw * vw1[0]);
+    const double r1 = ((1.0 - su) * vu0[1] + su * vu1[1]) - ((1.0 - sw) * vw0[1] + sw * vw1[1]);
+    const double r2 = ((1.0 - su) * vu0[2] + su * vu1[2]) - ((1.0 - sw) * vw0[2] + sw * vw1[2]);
+    const double vn = n0 * r0 + n1 * r1 + n2 * r2;
+    const double fn = delta * (k - c * vn);
+    if (!(fn > 0.0)) return dist;
+    const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
+    const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    const double gf = mu * fn / (sp > vs ? sp : vs);
+    double f0 = fn * n0 - gf * t0, f1 = fn * n1 - gf * t1, f2 = fn * n2 - gf * t2;   // on u
+    double sp_ = su;
+    if (!first) {
+        f0 = -f0; f1 = -f1; f2 = -f2;
+        sp_ = sw;
+    }
+    fa[0] += (1.0 - sp_) * f0; fa[1] += (1.0 - sp_) * f1; fa[2] += (1.0 - sp_) * f2;
+    fb[0] += sp_ * f0; fb[1] += sp_ * f1; fb[2] += sp_ * f2;
+    return dist;
+}
+
+// Verlet lists of capsules: element s's record for the pass, four double4 by
+// slot: (A, radius), (B, rod), (v_A, element), (v_B, 0).
+__device__ __attribute__((always_inline)) inline void element_record(const ContactGrid &G, int64_t s, double4 r[4])
+{
+    for (int k = 0; k < 4; ++k) r[k] = G.srec[4 * s + k];
+}
+
+// Element s's contacts over its list entries 0 .. n-1 (element slots), in
+// list (increasing slot) order, two partners' records loaded at a time
+// (entries past the end repeat the last one and are not evaluated).
+__device__ __attribute__((always_inline)) inline void capsule_list(const ContactGrid &G, int64_t s, int n, const double4 me[4], double k, double c,
+                                    double mu, double vs, double fa[3], double fb[3], double &pot)
+{
+    for (int j0 = 0; j0 < n; j0 += 2) {
+        double4 q[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) element_record(G, G.lid[min(j0 + u, n - 1) * G.nn + s], q[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (j0 + u < n)
+                capsule_pair(me[0], me[1], me[2], me[3], q[u][0], q[u][1], q[u][2], q[u][3], k, c, mu, vs, fa, fb,
+                             pot);
+    }
+}
+
 // Each element sums its contacts over the 27 buckets around its midpoint, in
 // two phases so that the wave's lanes do the costly FP64 work together.  The
 // screen: every candidate's capsule bounding box against the element's in
@@ -820,16 +918,12 @@ __global__ void seg_fill_kernel(const DevBatch<T> B, const ContactGrid G, double
 // LDS.  A lane screens until its queue is nearly full or its sweep ends; then
 // the wave drains its queues, each lane taking its survivors in the order it
 // queued them (the order of the sweep, so the sums are those of a single
-// pass), and lanes with candidates left go on.
-//
-// Evaluation of a pair: its closest points and force in one fixed order (the
-// element first in (rod, element) order takes the part of a), the other
-// element taking the exact negative, so the two feel opposite forces to the
-// last bit.  The force on the element goes to its nodes as (1 - s) and s; a
-// quarter of k delta^2 per ordered pair is the element's potential share.
-template <typename T>
-__global__ __launch_bounds__(CF_BLOCK) void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb)
+// pass; each pair by capsule_pair), and lanes with candidates left go on.
+template <typename T, bool LIST>
+__global__ __launch_bounds__(CF_BLOCK) void seg_force_kernel(const DevBatch<T> B, const ContactGrid G, int nb,
+                                                             Gate gate)
 {
+    if (gate.skip()) return;
     __shared__ int32_t queue[CF_QUEUE * CF_BLOCK];
     int32_t *const mine = queue + threadIdx.x;   // entry j at mine[j * CF_BLOCK]
     const int64_t p0 = blockIdx.x * (int64_t)CF_BLOCK + threadIdx.x;
@@ -839,59 +933,26 @@ __global__ __launch_bounds__(CF_BLOCK) void seg_force_kernel(const DevBatch<T> B
     const double4 ua = G.sca[pm], ub = G.scb[pm], uva = G.sva[pm], uvb = G.svb[pm];
     const float4 mc = G.cull[2 * pm], me = G.cull[2 * pm + 1];
     const float mg = cull_margin(mc, (float)(1.0 / G.inv_cell));
-    const float ex = mc.w + mg, ey = me.x + mg, ez = me.y + mg;   // own half extents plus the margin
+    // own half extents plus the margin (building lists: plus the skin, so
+    // boxes closer than the skin per axis pass)
+    const float sk = LIST ? (float)G.skin : 0.0f;
+    const float ex = mc.w + mg + sk, ey = me.x + mg + sk, ez = me.y + mg + sk;
     const int rod = (int)ub.w, elem = (int)uva.w;
     const int64_t sme = live ? G.sid[p0] : 0;
     // elements of the own rod it may touch: up to `prev` and from `next` on
     const int next = G.self_pairs[sme], prev = G.self_pairs[G.nn + sme];
     const double k = B.wall_k, c = B.wall_c, mu = B.wall_mu, vs = B.wall_vslip;
-    const double ra = ua.w;
-    double fa0 = 0, fa1 = 0, fa2 = 0, fb0 = 0, fb1 = 0, fb2 = 0, pot = 0;
+    double fa[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0}, pot = 0;
     int nq = 0;
 
     auto evaluate = [&](int32_t p) {
-        const double4 qa = G.sca[p], qb = G.scb[p], qva = G.sva[p], qvb = G.svb[p];
-        const int qrod = (int)qb.w, qelem = (int)qva.w;
-        const bool first = rod < qrod || (rod == qrod && elem < qelem);
-        // u: the pair's first element, w: the other
-        const double u0[3] = {first ? ua.x : qa.x, first ? ua.y : qa.y, first ? ua.z : qa.z};
-        const double u1[3] = {first ? ub.x : qb.x, first ? ub.y : qb.y, first ? ub.z : qb.z};
-        const double w0[3] = {first ? qa.x : ua.x, first ? qa.y : ua.y, first ? qa.z : ua.z};
-        const double w1[3] = {first ? qb.x : ub.x, first ? qb.y : ub.y, first ? qb.z : ub.z};
-        const double4 vu0 = first ? uva : qva, vu1 = first ? uvb : qvb;
-        const double4 vw0 = first ? qva : uva, vw1 = first ? qvb : uvb;
-        const double ru = first ? ra : qa.w, rw = first ? qa.w : ra;
-        double su, sw;
-        closest_params(u0, u1, w0, w1, su, sw);
-        const double pu[3] = {u0[0] + su * (u1[0] - u0[0]), u0[1] + su * (u1[1] - u0[1]),
-                              u0[2] + su * (u1[2] - u0[2])};
-        const double pw[3] = {w0[0] + sw * (w1[0] - w0[0]), w0[1] + sw * (w1[1] - w0[1]),
-                              w0[2] + sw * (w1[2] - w0[2])};
-        const double e0 = pu[0] - pw[0], e1 = pu[1] - pw[1], e2 = pu[2] - pw[2];
-        const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-        const double delta = ru + rw - dist;
-        if (!(delta > 0.0)) return;
-        pot += 0.25 * k * delta * delta;
-        if (!(dist > 0.0)) return;   // the segments cross: no direction
-        const double n0 = e0 / dist, n1 = e1 / dist, n2 = e2 / dist;
-        const double r0 = ((1.0 - su) * vu0.x + su * vu1.x) - ((1.0 - sw) * vw0.x + sw * vw1.x);
-        const double r1 = ((1.0 - su) * vu0.y + su * vu1.y) - ((1.0 - sw) * vw0.y + sw * vw1.y);
-        const double r2 = ((1.0 - su) * vu0.z + su * vu1.z) - ((1.0 - sw) * vw0.z + sw * vw1.z);
-        const double vn = n0 * r0 + n1 * r1 + n2 * r2;
-        const double fn = delta * (k - c * vn);
-        if (!(fn > 0.0)) return;
-        const double t0 = r0 - vn * n0, t1 = r1 - vn * n1, t2 = r2 - vn * n2;
-        const double sp = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-        const double gf = mu * fn / (sp > vs ? sp : vs);
-        double f0 = fn * n0 - gf * t0, f1 = fn * n1 - gf * t1, f2 = fn * n2 - gf * t2;   // on u
-        double sp_ = su;
-        if (!first) {
-            f0 = -f0; f1 = -f1; f2 = -f2;
-            sp_ = sw;
-        }
-        fa0 += (1.0 - sp_) * f0; fa1 += (1.0 - sp_) * f1; fa2 += (1.0 - sp_) * f2;
-        fb0 += sp_ * f0; fb1 += sp_ * f1; fb2 += sp_ * f2;
+        return capsule_pair(ua, ub, uva, uvb, G.sca[p], G.scb[p], G.sva[p], G.svb[p], k, c, mu, vs, fa, fb, pot);
     };
+    // building lists: a pair joins when its segments are closer than the radii
+    // plus the skin (and a slack far above the distance's rounding)
+    const double reach = G.skin * (1.0 + 1e-3) + 1e-9 / G.inv_cell;
+    int n_list = 0;
+    const int64_t NN = G.nn;
 
     Sweep sw(G, cell_of(0.5 * (ua.x + ub.x), G.org[0], G.inv_cell), cell_of(0.5 * (ua.y + ub.y), G.org[1], G.inv_cell),
              cell_of(0.5 * (ua.z + ub.z), G.org[2], G.inv_cell));
@@ -918,14 +979,107 @@ __global__ __launch_bounds__(CF_BLOCK) void seg_force_kernel(const DevBatch<T> B
             sw.p += CF_GROUP;
             if (sw.p >= sw.pe) done = !sw.next(G);
         }
-        for (int j = 0; j < nq; ++j) evaluate(mine[j * CF_BLOCK]);
+        for (int j = 0; j < nq; ++j) {
+            const int32_t p = mine[j * CF_BLOCK];
+            const double dist = evaluate(p);
+            if constexpr (LIST) {
+                if (dist < ua.w + G.sca[p].w + reach) {
+                    if (n_list < CONTACT_LIST_CAP) G.lid[n_list * NN + sme] = G.sid[p];
+                    ++n_list;
+                }
+            }
+        }
         nq = 0;
         if (!__any(!done)) break;
     }
+    if constexpr (LIST) {
+        int most = n_list;   // the wave's longest list, one atomic per wave
+        for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o, 64));
+        if ((threadIdx.x & 63) == 0 && most > 0) atomicMax(&G.vflag[VF_MOST], most);
+        if (live) {
+            G.lcount[sme] = n_list;
+            if (n_list > CONTACT_LIST_CAP) {
+                atomicOr(&G.vflag[VF_OVERFLOW], 1);   // forces of the sweep's order; the next pass builds again
+            } else {
+                int32_t *const L = G.lid + sme;   // insertion sort by slot
+                for (int i = 1; i < n_list; ++i) {
+                    const int32_t key = L[i * NN];
+                    int j = i - 1;
+                    while (j >= 0 && L[j * NN] > key) {
+                        L[(j + 1) * NN] = L[j * NN];
+                        --j;
+                    }
+                    L[(j + 1) * NN] = key;
+                }
+                double4 mr[4];
+                element_record(G, sme, mr);
+                for (int a = 0; a < 3; ++a) fa[a] = fb[a] = 0.0;
+                pot = 0.0;
+                capsule_list(G, sme, n_list, mr, k, c, mu, vs, fa, fb, pot);
+            }
+        }
+    }
     if (!live) return;
     const int64_t s = G.sid[p0], nn = G.nn;
-    G.fseg[s] = fa0; G.fseg[nn + s] = fa1; G.fseg[2 * nn + s] = fa2;
-    G.fseg[3 * nn + s] = fb0; G.fseg[4 * nn + s] = fb1; G.fseg[5 * nn + s] = fb2;
+    for (int a = 0; a < 3; ++a) {
+        G.fseg[a * nn + s] = fa[a];
+        G.fseg[(3 + a) * nn + s] = fb[a];
+    }
+    G.pot[s] = pot;
+}
+
+// Verlet lists of capsules, first kernel of every pass: every element's
+// record (above) and the move check of its node A, and of the rod's last node
+// after its last element, so every node is checked once (as for node
+// spheres: a node that moved more than half the skin asks for a build; the
+// distance between two segments changes by at most the largest move of
+// either's points, so no pair missing from the lists can touch).
+template <typename T>
+__global__ __launch_bounds__(256) void seg_pack_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, NI = G.nid;
+    int moved = 0;
+    if (s < G.nn) {
+        int rod, elem;
+        double a[3], b[3], va[3], vb[3];
+        contact_segment(B, G, s, drift, rod, elem, a, b, va, vb);
+        if (rod >= 0) {
+            G.srec[4 * s] = make_double4(a[0], a[1], a[2], B.rod_rad[rod]);
+            G.srec[4 * s + 1] = make_double4(b[0], b[1], b[2], (double)rod);
+            G.srec[4 * s + 2] = make_double4(va[0], va[1], va[2], (double)elem);
+            G.srec[4 * s + 3] = make_double4(vb[0], vb[1], vb[2], 0.0);
+            const double h = 0.5 * G.skin;
+            auto check = [&](const double x[3], int64_t id) {
+                if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) return;   // a build records NaN there
+                const double e0 = x[0] - G.xb[id], e1 = x[1] - G.xb[NI + id], e2 = x[2] - G.xb[2 * NI + id];
+                moved |= !(e0 * e0 + e1 * e1 + e2 * e2 <= h * h);
+            };
+            check(a, s);
+            if (elem + 1 == B.rod_n[rod]) check(b, B.n_slots + rod);
+        }
+    }
+    if (__any(moved) && (threadIdx.x & 63) == 0) atomicOr(&G.vflag[VF_REQUEST], 1);
+}
+
+// Verlet lists of capsules, every pass: each element with partners sums its
+// contacts over its list from the records; one without reads and writes
+// nothing (its shares are the zeros the last build wrote).  With a build in
+// this pass the shares computed here are replaced.
+template <typename T>
+__global__ __launch_bounds__(256) void seg_list_kernel(const DevBatch<T> B, const ContactGrid G)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nn = G.nn;
+    if (s >= nn) return;
+    const int n = min(G.lcount[s], CONTACT_LIST_CAP);   // larger only after an overflow, when a build follows
+    if (n == 0) return;
+    double4 me[4];
+    element_record(G, s, me);
+    double fa[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0}, pot = 0.0;
+    capsule_list(G, s, n, me, B.wall_k, B.wall_c, B.wall_mu, B.wall_vslip, fa, fb, pot);
+    for (int a = 0; a < 3; ++a) {
+        G.fseg[a * nn + s] = fa[a];
+        G.fseg[(3 + a) * nn + s] = fb[a];
+    }
     G.pot[s] = pot;
 }
 
@@ -971,27 +1125,35 @@ hipError_t launch_contact_t(const DevBatch<T> &b, const ContactGrid &g, double d
     }
     const bool seg = g.mode == 2;
     if (seg ? (!g.sca || !g.fseg || !g.self_pairs || !g.cull) : !g.spr) return hipErrorInvalidValue;
-    const bool lists = !seg && g.skin > 0.0;
-    if (lists && (!g.lcount || !g.lid || !g.xb || !g.rec || !g.vflag)) return hipErrorInvalidValue;
+    const bool lists = g.skin > 0.0;
+    if (lists && (!g.lcount || !g.lid || !g.xb || !g.vflag || (seg ? !g.srec : !g.rec))) return hipErrorInvalidValue;
     const unsigned gf = (unsigned)((g.nn + CF_BLOCK - 1) / CF_BLOCK);
     Gate build;   // with lists the grid pass runs only in passes that rebuild them
     if (lists) {
         build.p = g.vflag + VF_REQUEST;
-        const dim3 gi((unsigned)((g.nid + bs - 1) / bs));
-        // FP32 batches: the positions kernel above wrote the records
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((verlet_pack_kernel<T>), gi, dim3(bs), 0, s, b, g, drift);
-        hipLaunchKernelGGL((verlet_force_kernel<T>), gi, dim3(bs), 0, s, b, g);
+        if (seg) {
+            hipLaunchKernelGGL((seg_pack_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+            hipLaunchKernelGGL((seg_list_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g);
+        } else {
+            const dim3 gi((unsigned)((g.nid + bs - 1) / bs));
+            // FP32 batches: the positions kernel above wrote the records
+            if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((verlet_pack_kernel<T>), gi, dim3(bs), 0, s, b, g, drift);
+            hipLaunchKernelGGL((verlet_force_kernel<T>), gi, dim3(bs), 0, s, b, g);
+        }
     }
-    if (seg) hipLaunchKernelGGL((seg_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift);
+    if (seg) hipLaunchKernelGGL((seg_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, build);
     else hipLaunchKernelGGL((contact_bin_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, build);
     hipLaunchKernelGGL(contact_scan_chunks, dim3(n_chunks), dim3(256), 0, s, g, nb, build);
     hipLaunchKernelGGL(contact_scan_top, dim3(1), dim3(1024), 0, s, g, n_chunks, nb, build);
     hipLaunchKernelGGL(contact_scan_add, dim3(n_chunks), dim3(256), 0, s, g, nb, build);
     if (seg) {
-        hipLaunchKernelGGL(contact_scatter_ids, dim3(gn), dim3(bs), 0, s, g);
-        hipLaunchKernelGGL(sort_ids_kernel, dim3(gn), dim3(bs), 0, s, g);
-        hipLaunchKernelGGL((seg_fill_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, nb);
-        hipLaunchKernelGGL((seg_force_kernel<T>), dim3(gf), dim3(CF_BLOCK), 0, s, b, g, nb);
+        hipLaunchKernelGGL(contact_scatter_ids, dim3(gn), dim3(bs), 0, s, g, build);
+        hipLaunchKernelGGL(sort_ids_kernel, dim3(gn), dim3(bs), 0, s, g, build);
+        hipLaunchKernelGGL((seg_fill_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, nb, build);
+        if (lists)
+            hipLaunchKernelGGL((seg_force_kernel<T, true>), dim3(gf), dim3(CF_BLOCK), 0, s, b, g, nb, build);
+        else
+            hipLaunchKernelGGL((seg_force_kernel<T, false>), dim3(gf), dim3(CF_BLOCK), 0, s, b, g, nb, build);
         hipLaunchKernelGGL((seg_nodes_kernel<T>), dim3((unsigned)((g.nid + bs - 1) / bs)), dim3(bs), 0, s, b, g);
     } else {
         hipLaunchKernelGGL((contact_scatter_kernel<T>), dim3(gn), dim3(bs), 0, s, b, g, drift, build);

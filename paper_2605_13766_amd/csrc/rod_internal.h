@@ -183,6 +183,7 @@ struct ContactGrid {
     double *xb;        // [3][nid] positions at the last build (NaN: none yet, or the node was not finite)
     double4 *rec;      // [2 nid] per pass: (position after the drift, radius), (velocity, rod) of each id
     uint8_t *need;     // [nid] FP64: 1 for the nodes whose records the lists use (the pack writes only those)
+    double4 *srec;     // mode 2: [4 nn] per pass: (A, radius), (B, rod), (v_A, element), (v_B, 0) of each element slot
     // [CONTACT_VFLAGS]: this pass builds, this pass's build overflowed; then
     // counters (passes, builds, builds that overflowed, most partners of one
     // node at a build)

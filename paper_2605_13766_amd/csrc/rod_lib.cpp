@@ -824,10 +824,10 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
     // midpoints are at most (l_a + l_b) / 2 + r_a + r_b apart, so cells hold the
     // longest element stretched by a quarter plus twice the largest radius
     g.cell_len = 1.25 * lmax;
-    // mode 1: Verlet lists unless the skin is negative; 0 picks a fifth of
-    // the largest radius (a node may then move a tenth of it between builds)
-    g.skin = g.mode == 1 && b->contact_skin >= 0 ? (b->contact_skin > 0 ? b->contact_skin : 0.2 * rmax) : 0.0;
-    const double cell = g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax + g.skin;
+    // Verlet lists unless the skin is negative; 0 picks a fifth of the
+    // largest radius (a node may then move a tenth of it between builds)
+    g.skin = b->contact_skin >= 0 ? (b->contact_skin > 0 ? b->contact_skin : 0.2 * rmax) : 0.0;
+    const double cell = (g.mode == 2 ? g.cell_len + 2.0 * rmax : 2.0 * rmax) + g.skin;
     g.inv_cell = 1.0 / cell;
     g.rmax = rmax;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -905,26 +905,32 @@ int build_contact_grid(rod_batch *b, const HostInputs &h)
         // groups and masks the records past a range's end
         HIPCHK(hipMalloc((void **)&g.spr, (g.nn + rodk::CONTACT_PAD) * sizeof(double4)));
         HIPCHK(hipMalloc((void **)&g.svr, g.nn * sizeof(double4)));
-        if (g.skin > 0) {
-            HIPCHK(hipMalloc((void **)&g.lcount, g.nid * sizeof(int32_t)));
-            HIPCHK(hipMalloc((void **)&g.lid, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int32_t)));
+    }
+    if (g.skin > 0) {
+        // Verlet lists: per item (node, or element slot) its count and entries
+        HIPCHK(hipMalloc((void **)&g.lcount, g.nn * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&g.lid, (size_t)rodk::CONTACT_LIST_CAP * g.nn * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&g.xb, 3 * g.nid * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&g.vflag, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
+        // no build yet (NaN positions: the first pass builds)
+        const std::vector<double> nan3(3 * g.nid, std::nan(""));
+        HIPCHK(hipMemcpy(g.xb, nan3.data(), nan3.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemset(g.lcount, 0, g.nn * sizeof(int32_t)));
+        // every entry names a valid item (the list pass reads entries past a count)
+        HIPCHK(hipMemset(g.lid, 0, (size_t)rodk::CONTACT_LIST_CAP * g.nn * sizeof(int32_t)));
+        HIPCHK(hipMemset(g.vflag, 0, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
+        if (g.mode == 2) {
+            HIPCHK(hipMalloc((void **)&g.srec, 4 * g.nn * sizeof(double4)));
+            HIPCHK(hipMemset(g.srec, 0, 4 * g.nn * sizeof(double4)));
+        } else {
             HIPCHK(hipMalloc((void **)&g.rec, 2 * g.nid * sizeof(double4)));
+            // padding ids keep rod -1 (the pack kernel writes real nodes only)
+            const std::vector<double4> pad(2 * g.nid, make_double4(0.0, 0.0, 0.0, -1.0));
+            HIPCHK(hipMemcpy(g.rec, pad.data(), pad.size() * sizeof(double4), hipMemcpyHostToDevice));
             if (b->precision == ROD_F64) {   // FP32 records come from the positions kernel, all of them
                 HIPCHK(hipMalloc((void **)&g.need, g.nid));
                 HIPCHK(hipMemset(g.need, 0, g.nid));
             }
-            HIPCHK(hipMalloc((void **)&g.xb, 3 * g.nid * sizeof(double)));
-            HIPCHK(hipMalloc((void **)&g.vflag, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
-            // no build yet (NaN positions: the first pass builds)
-            const std::vector<double> nan3(3 * g.nid, std::nan(""));
-            HIPCHK(hipMemcpy(g.xb, nan3.data(), nan3.size() * sizeof(double), hipMemcpyHostToDevice));
-            HIPCHK(hipMemset(g.lcount, 0, g.nid * sizeof(int32_t)));
-            // every entry names a valid node (the list pass reads entries past a count)
-            HIPCHK(hipMemset(g.lid, 0, (size_t)rodk::CONTACT_LIST_CAP * g.nid * sizeof(int32_t)));
-            // padding ids keep rod -1 (the pack kernel writes real nodes only)
-            const std::vector<double4> pad(2 * g.nid, make_double4(0.0, 0.0, 0.0, -1.0));
-            HIPCHK(hipMemcpy(g.rec, pad.data(), pad.size() * sizeof(double4), hipMemcpyHostToDevice));
-            HIPCHK(hipMemset(g.vflag, 0, rodk::CONTACT_VFLAGS * sizeof(int32_t)));
         }
     }
     HIPCHK(hipMalloc((void **)&g.force, 3 * g.nid * sizeof(double)));
@@ -1567,6 +1573,7 @@ void rod_batch_destroy(rod_batch *b)
     (void)hipFree(b->cg.xb);
     (void)hipFree(b->cg.rec);
     (void)hipFree(b->cg.need);
+    (void)hipFree(b->cg.srec);
     (void)hipFree(b->cg.vflag);
     (void)hipFree(b->d_tail);
     (void)hipFree(b->d_rodp);

@@ -1,4 +1,4 @@
-"""Verlet lists of node-sphere contact (rod_contact = 1, contact_skin).
+"""Verlet lists of rod-rod contact (node spheres and capsules, contact_skin).
 
 Every node sums its contacts over its list in increasing node order, and a
 pair missing from the lists cannot touch, so a run's results do not depend on
@@ -137,6 +137,100 @@ def test_full_pile_lists_against_grid_pass():
     runs = {}
     for skin in (1e-6, 0.0, -1.0):
         print(f"case: fibre pile 16384 x 50, FP64, 200 steps, contact_skin={skin}", flush=True)
+        runs[skin] = _run(inp, 200, contact_skin=skin, tile_waves=4)
+        print("stats", runs[skin][1], flush=True)
+    assert _same(runs[1e-6][0], runs[0.0][0])
+    assert runs[1e-6][1]["builds"] > 5 and runs[1e-6][1]["fallbacks"] == 0
+    dpos = np.abs(runs[0.0][0][0] - runs[-1.0][0][0]).max()
+    dvel = np.abs(runs[0.0][0][1] - runs[-1.0][0][1]).max()
+    print(f"lists against grid pass: max |dpos| {dpos:.2e} m, max |dvel| {dvel:.2e} m/s", flush=True)
+    assert dpos < 1e-12 and dvel < 1e-8
+
+
+# ------------------------------------------------------------------ capsules
+def _capsule_pile(seed=61):
+    """Crossed layers of 2 x 4 fibres of 8 elements (3.1 radii each) on the
+    floor in capsule contact, under gravity, with friction."""
+    return W.fibre_pile(n_rods=24, n=8, L=0.248, per_row=2, rows=4, noise=1e-2, seed=seed, contact=2)
+
+
+def test_capsule_skin_does_not_change_results():
+    """Capsule lists: a skin of 1e-9 m, the default and two radii give the
+    same bits after 1000 FP64 steps (energies included) and 400 FP32 steps;
+    the smallest skin rebuilds far more often."""
+    inp = _capsule_pile(seed=63)
+    out = {}
+    for skin in (1e-9, 0.0, 0.02):
+        print(f"case: capsule pile 24 rods, FP64, 1000 steps, contact_skin={skin}", flush=True)
+        out[skin] = _run(inp, 1000, contact_skin=skin)
+        print("stats", out[skin][1], flush=True)
+    for skin in (0.0, 0.02):
+        assert _same(out[1e-9][0], out[skin][0]), skin
+    tiny, dflt = out[1e-9][1], out[0.0][1]
+    assert tiny["passes"] == dflt["passes"] == 1001
+    assert tiny["builds"] > 10 * dflt["builds"] and dflt["builds"] >= 1
+    assert tiny["fallbacks"] == dflt["fallbacks"] == 0 and dflt["most_partners"] > 0
+    print("case: the same capsule pile, FP32, 400 steps, two skins", flush=True)
+    f32 = [_run(inp, 400, "f32", contact_skin=skin)[0] for skin in (1e-9, 0.0)]
+    assert _same(*f32)
+
+
+def test_capsule_resume_with_lists_is_bitwise():
+    R = _rod()
+    inp = _capsule_pile(seed=67)
+    print("case: capsule pile 24 rods, FP64, 600 steps against 300 + resume + 300", flush=True)
+    with R.RodBatch(inp, precision="f64") as b:
+        b.step(300)
+        mid = b.get_state()
+        b.step(300)
+        whole = b.get_state()[:4]
+    with R.RodBatch(inp, precision="f64") as b:
+        b.set_state(*mid[:4], t=mid[4])
+        b.step(300)
+        resumed = b.get_state()[:4]
+    assert _same(whole, resumed)
+
+
+def test_capsule_no_lists_matches_oracle():
+    print("case: capsule pile 24 rods, FP64, 1000 steps, contact_skin=-1 (no lists)", flush=True)
+    norms, _ = run_both(_capsule_pile(seed=61), 1000, contact_skin=-1.0)
+    assert_norms(norms)
+
+
+def test_capsule_overflowing_lists_fall_back_to_grid_order():
+    """The bundle's elements as capsules with a skin of four radii: more than
+    32 elements within reach of the middle rod's elements, so every pass
+    rebuilds and sums those elements' contacts in grid order; against the
+    oracle, and with the default skin the lists hold."""
+    R = _rod()
+    inp = _bundle()
+    inp.rod_contact = 2
+    print("case: 7-rod bundle as capsules, FP64, 1000 steps, contact_skin=0.04 (overflowing lists)", flush=True)
+    norms, _ = run_both(inp, 1000, contact_skin=0.04)
+    assert_norms(norms)
+    with R.RodBatch(inp, precision="f64", contact_skin=0.04) as b:
+        b.step(50)
+        s = b.contact_stats()
+    print("stats", s, flush=True)
+    assert s["passes"] == s["builds"] == s["fallbacks"] == 50 and s["most_partners"] > s["capacity"]
+    print("case: 7-rod bundle as capsules, FP64, 1000 steps, default skin", flush=True)
+    norms, _ = run_both(inp, 1000)
+    assert_norms(norms)
+    with R.RodBatch(inp, precision="f64") as b:
+        b.step(50)
+        s = b.contact_stats()
+    print("stats", s, flush=True)
+    assert s["fallbacks"] == 0 and 0 < s["most_partners"] <= s["capacity"]
+
+
+def test_full_capsule_pile_lists_against_grid_pass():
+    """16,384 fibres x 20 capsules, 200 FP64 steps: a skin of 1e-6 m gives
+    the default skin's bits; the grid pass of every step sums in grid order,
+    so positions differ by rounding only (below 1e-12 m)."""
+    inp = W.capsule_pile()
+    runs = {}
+    for skin in (1e-6, 0.0, -1.0):
+        print(f"case: capsule pile 16384 x 20, FP64, 200 steps, contact_skin={skin}", flush=True)
         runs[skin] = _run(inp, 200, contact_skin=skin, tile_waves=4)
         print("stats", runs[skin][1], flush=True)
     assert _same(runs[1e-6][0], runs[0.0][0])
