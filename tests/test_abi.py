@@ -93,6 +93,7 @@ def test_null_handle_calls():
     L = rod.lib()
     assert L.rod_step(None, 10, None) == rod.ROD_EINVAL
     assert L.rod_batch_info(None, None) == rod.ROD_EINVAL
+    assert L.rod_contact_stats(None, None, None) == rod.ROD_EINVAL
     L.rod_batch_destroy(None)
 
 
