@@ -17,8 +17,8 @@ driven by its distributed couple.  The "active" object times 16,384 free
 filaments x 50 elements under gravity and travelling-wave muscle moments in
 both precisions, and the "walls" object the same filaments confined in a box
 of six planar walls (penalty contact with Coulomb friction); the "contact"
-object times a pile of crossed fibres in rod-rod contact (hash-grid pairs
-every step, one step per launch), and the "capsule" object the same pile with
+object times a pile of crossed fibres in rod-rod contact (pairs in Verlet
+lists rebuilt by a hash grid, one step per launch), and the "capsule" object the same pile with
 fibres of aspect ratio 31 whose elements touch as capsules; the "connected"
 object times millipede-like
 bots of rods joined by point-wise and lateral spring-dashpot connections (224

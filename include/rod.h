@@ -178,8 +178,9 @@ typedef struct {
      * normal (x_a - x_b)/|x_a - x_b| and the relative velocity v_a - v_b (so
      * the pair's forces are equal and opposite); half of each pair's penalty
      * potential 1/2 wall_k delta^2 joins each rod's W_ext.  A rod does not
-     * touch itself.  Pairs are found every step by a hashed uniform grid over
-     * the node positions (cells of twice the largest radius).
+     * touch itself.  Pairs are found by a hashed uniform grid over the node
+     * positions (cells of twice the largest radius), every step or, with
+     * Verlet lists (contact_skin, below), when the lists need a rebuild.
      * With rod_contact = 2 every element is a capsule, the segment between
      * its two nodes dilated by its rod's radius: the same law acts between the
      * closest points of two elements' segments (the point velocities
