@@ -949,8 +949,10 @@ __global__ __launch_bounds__(CF_BLOCK) void seg_force_kernel(const DevBatch<T> B
         return capsule_pair(ua, ub, uva, uvb, G.sca[p], G.scb[p], G.sva[p], G.svb[p], k, c, mu, vs, fa, fb, pot);
     };
     // building lists: a pair joins when its segments are closer than the radii
-    // plus the skin (and a slack far above the distance's rounding)
-    const double reach = G.skin * (1.0 + 1e-3) + 1e-9 / G.inv_cell;
+    // plus the skin, plus a slack (0.1% of the skin and a millionth of a cell)
+    // far above the computed distance's rounding, near-parallel segments'
+    // included, whatever the skin
+    const double reach = G.skin * (1.0 + 1e-3) + 1e-6 / G.inv_cell;
     int n_list = 0;
     const int64_t NN = G.nn;
 
