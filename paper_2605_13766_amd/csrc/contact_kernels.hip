@@ -13,15 +13,17 @@
 // drift) into a wrapped uniform grid with atomic counts, prefix-sum the
 // counts, put the items into bucket order (each bucket sorted by id), and let
 // every item sum its contacts over the 27 buckets around it; the step kernel
-// adds the node forces at its kick.  Mode 1 can keep Verlet lists instead
-// (a skin > 0): every node's list of partners (nodes of other rods within
-// its radius plus the largest radius plus the skin at the build), by
-// increasing id.  A pass first sums each node's contacts over its list and
-// checks how far the node has moved since the build; only when one has moved
-// more than half the skin does the grid pass run, rebuilding the lists and
-// summing every node's contacts again over its new list.  Both sums run over
-// the same pairs (every pair that touches is listed) in the same order, so
-// the forces depend neither on when the lists were built nor on the skin.
+// adds the node forces at its kick.  Both modes can keep Verlet lists
+// instead (a skin > 0): every node's list of partners (nodes of other rods
+// within its radius plus the largest radius plus the skin at the build), or
+// every element's (elements whose segments were within the two radii plus
+// the skin), by increasing id.  A pass first sums each item's contacts over
+// its list and checks how far every node has moved since the build; only when
+// one has moved more than half the skin does the grid pass run, rebuilding
+// the lists and summing every item's contacts again over its new list.  Both
+// sums run over the same pairs (every pair that touches is listed) in the
+// same order, so the forces depend neither on when the lists were built nor
+// on the skin.
 #include "rod.h"
 #include "rod_internal.h"
 
@@ -441,8 +443,8 @@ __device__ __attribute__((always_inline)) inline void list_contacts(const DevBat
 }
 
 // The same sum, each partner read as contact_node gives it (the values the
-// records hold), for the pass that builds the lists: records are written
-// only for the nodes the previous lists used.  A partner that is not finite
+// records hold), for the pass that builds the lists: in FP64 batches records
+// are written only for the nodes the previous lists used.  A partner that is not finite
 // adds nothing, as its record's failed distance test does.
 template <typename T>
 __device__ __attribute__((always_inline)) inline void list_contacts_state(const DevBatch<T> &B, const ContactGrid &G, int64_t id, int n,
@@ -560,12 +562,6 @@ __global__ __launch_bounds__(CF_BLOCK) void contact_force_kernel(const DevBatch<
     G.pot[id] = pot;
 }
 
-// Verlet lists, first kernel of every pass: every node's record (above),
-// and a request for a build when a node has moved more than half the skin
-// from its position at the last one (a NaN position there counts as moved).
-// Without a build no pair missing from the lists can touch: the pair was at
-// least its radii plus the skin apart at the build (up to the 1e-9 widening)
-// and each node has moved at most half the skin since.
 // A node's position `drift` ahead and velocity, as contact_node gives them,
 // without its branches: slot and tail arrays keep position and velocity at
 // the same field offsets.
@@ -593,6 +589,13 @@ __device__ inline void node_state(const DevBatch<float> &B, const ContactGrid &G
     for (int a = 0; a < 3; ++a) x[a] = G.xabs[a * G.nid + p];
 }
 
+// Verlet lists, first kernel of every pass (FP64 batches; FP32 batches do
+// this in the positions kernel): the record (above) of every node the last
+// build's lists use, and a request for a build when any node has moved more
+// than half the skin from its position at the build (a NaN position there
+// counts as moved).  Without a build no pair missing from the lists can
+// touch: the pair was at least its radii plus the skin apart at the build (up
+// to the 1e-9 widening) and each node has moved at most half the skin since.
 template <typename T>
 __global__ __launch_bounds__(256) void verlet_pack_kernel(const DevBatch<T> B, const ContactGrid G, double drift)
 {

@@ -173,20 +173,21 @@ struct ContactGrid {
     const int32_t *self_pairs;
     double *fseg;      // [6][nn] each element's force shares of its nodes A and B
     double cell_len;   // mode 2: the longest element the grid allows for (the cell holds it)
-    // mode 1 with Verlet lists (skin > 0; cells of 2 rmax + skin): each node's
-    // partners, the nodes of other rods within its radius + rmax + skin when
-    // the lists were built, by increasing id; rebuilt when a node has moved
-    // more than skin / 2 since
+    // Verlet lists (skin > 0; cells grow by the skin): each item's partners
+    // when the lists were built, by increasing id - mode 1: the nodes of other
+    // rods within its radius + rmax + skin; mode 2: the elements it may touch
+    // whose segments were within the two radii + skin - rebuilt when a node
+    // has moved more than skin / 2 since
     double skin;       // 0: no lists (the grid pass every step)
-    int32_t *lcount;   // [nid] partners listed (more than CONTACT_LIST_CAP: the build overflowed)
-    int32_t *lid;      // [CONTACT_LIST_CAP][nid] partner ids
-    double *xb;        // [3][nid] positions at the last build (NaN: none yet, or the node was not finite)
-    double4 *rec;      // [2 nid] per pass: (position after the drift, radius), (velocity, rod) of each id
-    uint8_t *need;     // [nid] FP64: 1 for the nodes whose records the lists use (the pack writes only those)
+    int32_t *lcount;   // [nn] partners listed (more than CONTACT_LIST_CAP: the build overflowed)
+    int32_t *lid;      // [CONTACT_LIST_CAP][nn] partner ids (every entry a valid item)
+    double *xb;        // [3][nid] node positions at the last build (NaN: none yet, or the node was not finite)
+    double4 *rec;      // mode 1: [2 nid] per pass: (position after the drift, radius), (velocity, rod) of each id
+    uint8_t *need;     // mode 1, FP64: [nid] 1 for the nodes whose records the lists use (the pack writes only those)
     double4 *srec;     // mode 2: [4 nn] per pass: (A, radius), (B, rod), (v_A, element), (v_B, 0) of each element slot
     // [CONTACT_VFLAGS]: this pass builds, this pass's build overflowed; then
     // counters (passes, builds, builds that overflowed, most partners of one
-    // node at a build)
+    // item at a build)
     int32_t *vflag;
 };
 constexpr int64_t CONTACT_PAD = 4;   // sorted records past the last item (a screening group reads past a range)
