@@ -61,6 +61,31 @@ def test_segment_closest_points():
     assert ro.segment_closest(z, ex, 2 * ex, 3 * ex) == (1.0, 0.0)   # collinear, gap 1
 
 
+def test_segment_distance_moves_no_more_than_the_end_points():
+    """The property capsule Verlet lists rest on: when each end point of two
+    segments moves by at most e, every point of either moves by at most e (a
+    convex combination), so their closest distance changes by at most 2 e.
+    Random pairs (near-parallel and end-sharing ones included) and random
+    moves of every end point, the distances from the oracle's routine."""
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for k in range(400):
+        p0, p1, q0, q1 = rng.normal(size=(4, 3))
+        if k % 8 == 0:
+            q1 = q0 + 0.7 * (p1 - p0) + 1e-7 * rng.normal(size=3)   # near-parallel
+        if k % 8 == 1:
+            q0 = p1.copy()
+        d = _dist(p0, p1, q0, q1, *ro.segment_closest(p0, p1, q0, q1))
+        e = 10.0 ** rng.uniform(-6, -1)
+        mv = rng.normal(size=(4, 3))
+        mv *= (e * rng.uniform(0.0, 1.0, size=(4, 1))) / np.linalg.norm(mv, axis=1, keepdims=True)
+        a0, a1, b0, b1 = p0 + mv[0], p1 + mv[1], q0 + mv[2], q1 + mv[3]
+        d2 = _dist(a0, a1, b0, b1, *ro.segment_closest(a0, a1, b0, b1))
+        assert abs(d2 - d) <= 2 * e + 1e-12, (k, d, d2, e)
+        worst = max(worst, abs(d2 - d) / (2 * e))
+    assert worst > 0.5   # the bound is approached, so the test can see a violation
+
+
 def _long_crossing(mode, gap=2e-4, vz=-0.5, n=4, L=0.1):
     """Rod A along x and rod B along y (above A by 2 RAD + gap, moving with
     vz), elements L / n = 5 RAD long, the crossing at the middle of element 1 of
