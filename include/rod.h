@@ -320,7 +320,10 @@ int rod_set_state(rod_batch *b, const double *position, const double *velocity,
                   const double *director, const double *omega, double t, void *stream);
 
 /* Per-rod flags (host int32 [R], bits): ROD_FLAG_NONFINITE = NaN/Inf seen at
- * the end of a launch (the synchronising calls then return ROD_ENONFINITE);
+ * the end of a launch (the synchronising calls then return ROD_ENONFINITE; a
+ * non-finite rod can make the next rods of its workgroup tile non-finite in
+ * later steps, and flagged, since a rod's first Voronoi point takes the
+ * previous rod's values times zero stiffness; contact carries no NaN);
  * ROD_FLAG_STRETCHED = with capsule contact (rod_contact = 2), an element of
  * the rod was longer than 1.25 times the longest rest length when the contact
  * grid binned it, so contacts of that element may have been missed (the state

@@ -239,3 +239,37 @@ def test_full_capsule_pile_lists_against_grid_pass():
     dvel = np.abs(runs[0.0][0][1] - runs[-1.0][0][1]).max()
     print(f"lists against grid pass: max |dpos| {dpos:.2e} m, max |dvel| {dvel:.2e} m/s", flush=True)
     assert dpos < 1e-12 and dvel < 1e-8
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_lists_after_a_non_finite_rod(mode):
+    """A node of rod 0 set to NaN: rod 0 is flagged (a non-finite node or
+    element fails every distance test and is not binned, so contact carries
+    no NaN; the step's exchange between neighbouring rods of a tile can, and
+    those rods are flagged too).  With the state set back the lists are valid
+    again (rebuilt where a build position went NaN), and the next 200 steps
+    give the bits of a fresh batch given the same state."""
+    R = _rod()
+    inp = _small_pile(seed=101) if mode == 1 else _capsule_pile(seed=103)
+    print(f"case: {'fibre' if mode == 1 else 'capsule'} pile 24 rods, FP64, NaN node in rod 0, then restored",
+          flush=True)
+    with R.RodBatch(inp, precision="f64") as b:
+        b.step(100)
+        pos, vel, dr, om, t = b.get_state()
+        bad = pos.copy()
+        bad[3] = np.nan   # a node of rod 0
+        b.set_state(bad, vel, dr, om, t=t)
+        b.step(50)
+        flags = b.flags()
+        assert flags[0] & R.ROD_FLAG_NONFINITE
+        print("rods flagged", int((flags & R.ROD_FLAG_NONFINITE).astype(bool).sum()), "of", len(flags), flush=True)
+        b.set_state(pos, vel, dr, om, t=t)
+        assert not b.flags().any()
+        b.step(200)
+        after = b.get_state()[:4]
+        print("stats", b.contact_stats(), flush=True)
+    with R.RodBatch(inp, precision="f64") as c:
+        c.set_state(pos, vel, dr, om, t=t)
+        c.step(200)
+        fresh = c.get_state()[:4]
+    assert _same(after, fresh)
